@@ -1,0 +1,88 @@
+"""User-facing ordering of unknowns and boundary data, written independently
+from the C header's definition.  Test infrastructure only.
+
+Definition (as documented for fds_plan_create):
+* Rectangles are closed node boxes (i0, j0, i1, j1).  The coupled subdomain
+  (the "centre") is the rectangle that shares an edge with the largest number
+  of other rectangles; ties go to the first listed.
+* A rectangle owns its interior nodes.  A rectangle other than the centre also
+  owns the nodes strictly inside the edge it shares with the centre.
+* The unknown vector lists, rectangle by rectangle in the given order, the
+  owned nodes in row-major order (j ascending outer, i ascending inner).
+* The Dirichlet data vector lists, rectangle by rectangle, the values on the
+  rectangle's whole closed box in row-major order; only entries at Dirichlet
+  nodes are read.
+"""
+
+from __future__ import annotations
+
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+Rect = Tuple[int, int, int, int]
+
+
+def _share_edge(a: Rect, b: Rect) -> bool:
+    ai0, aj0, ai1, aj1 = a
+    bi0, bj0, bi1, bj1 = b
+    if ai1 == bi0 or ai0 == bi1:
+        return min(aj1, bj1) - max(aj0, bj0) > 0
+    if aj1 == bj0 or aj0 == bj1:
+        return min(ai1, bi1) - max(ai0, bi0) > 0
+    return False
+
+
+def centre_index(rects: Sequence[Rect]) -> int:
+    counts = [sum(_share_edge(a, b) for b in rects if b is not a) for a in rects]
+    best = max(counts)
+    return counts.index(best)
+
+
+def owned_nodes(rects: Sequence[Rect]) -> List[Tuple[np.ndarray, np.ndarray]]:
+    """For each rectangle, (j, i) index arrays of its owned nodes in order."""
+    c = centre_index(rects)
+    out = []
+    for r, (i0, j0, i1, j1) in enumerate(rects):
+        ilo, ihi, jlo, jhi = i0 + 1, i1 - 1, j0 + 1, j1 - 1   # inclusive interior
+        if r != c:
+            ci0, cj0, ci1, cj1 = rects[c]
+            if i0 == ci1:
+                ilo = i0        # east arm owns its west edge
+            elif i1 == ci0:
+                ihi = i1        # west arm owns its east edge
+            elif j0 == cj1:
+                jlo = j0        # north arm owns its south edge
+            elif j1 == cj0:
+                jhi = j1        # south arm owns its north edge
+        jj, ii = np.meshgrid(np.arange(jlo, jhi + 1), np.arange(ilo, ihi + 1), indexing="ij")
+        out.append((jj.ravel(), ii.ravel()))
+    return out
+
+
+def block_shapes(rects: Sequence[Rect]) -> List[Tuple[int, int]]:
+    """(rows, cols) of each rectangle's owned block."""
+    shapes = []
+    for jj, ii in owned_nodes(rects):
+        shapes.append((len(np.unique(jj)), len(np.unique(ii))))
+    return shapes
+
+
+def to_user(rects: Sequence[Rect], grid_values: np.ndarray) -> np.ndarray:
+    parts = [np.asarray(grid_values)[jj, ii] for jj, ii in owned_nodes(rects)]
+    return np.concatenate(parts).astype(np.float64)
+
+
+def from_user(rects: Sequence[Rect], vec: np.ndarray, shape: Tuple[int, int],
+              fill=np.nan) -> np.ndarray:
+    out = np.full(shape, fill, dtype=np.float64)
+    k = 0
+    for jj, ii in owned_nodes(rects):
+        out[jj, ii] = vec[k:k + len(jj)]
+        k += len(jj)
+    return out
+
+
+def bc_boxes(rects: Sequence[Rect], g_grid: np.ndarray) -> np.ndarray:
+    parts = [np.asarray(g_grid)[j0:j1 + 1, i0:i1 + 1].ravel() for (i0, j0, i1, j1) in rects]
+    return np.concatenate(parts).astype(np.float64)

@@ -1,0 +1,149 @@
+"""Pins of the global composite oracle against hand-derived fixtures, exact
+polynomial solutions, closed-form counts and the discretisation order."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import composite, layout, rect
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _const_grid(n, value):
+    N = n + 1
+    return np.full((3 * N + 1, 3 * N + 1), float(value))
+
+
+@pytest.mark.parametrize("fname", ["cross_n1.json", "L_n1.json"])
+def test_golden_hand_derived(fname):
+    with open(os.path.join(GOLDEN, fname)) as fh:
+        gd = json.load(fh)
+    n = gd["n"]
+    rects = workloads.shape_rects(gd["shape"], n)
+    h = 1.0 / (n + 1)
+    sol = composite.solve(rects, h, gd["kappa"], _const_grid(n, gd["f"]), _const_grid(n, gd["g"]),
+                          method="dense")
+    P = sol.on_grid()
+    vals = gd["values"]
+    i, j = vals["centre"]["node"]
+    assert P[j, i] == pytest.approx(vals["centre"]["num"] / vals["centre"]["den"], rel=1e-14)
+    for key in ("interface", "arm"):
+        for i, j in vals[key]["nodes"]:
+            assert P[j, i] == pytest.approx(vals[key]["num"] / vals[key]["den"], rel=1e-14)
+    assert sol.grid.n_unknowns == 1 + 2 * len(vals["interface"]["nodes"])
+
+
+@pytest.mark.parametrize("shape,count", [("cross", lambda n: 5 * n * n + 4 * n),
+                                         ("L", lambda n: 3 * n * n + 2 * n),
+                                         ("T", lambda n: 4 * n * n + 3 * n)])
+@pytest.mark.parametrize("n", [1, 2, 5, 32])
+def test_unknown_counts(shape, count, n):
+    g = composite.classify(workloads.shape_rects(shape, n))
+    assert g.n_unknowns == count(n)
+
+
+def _cubic(x, y):
+    return x ** 3 + 2.0 * y ** 3 - x * y * y + 3.0 * x - 1.0 + 0.5 * x * x * y
+
+
+def _cubic_lap(x, y):
+    # d2/dx2: 6x + y ; d2/dy2: 12y - 2x
+    return 6.0 * x + y + 12.0 * y - 2.0 * x
+
+
+@pytest.mark.parametrize("shape", ["cross", "L", "T", "square", "pair"])
+@pytest.mark.parametrize("kappa", [0.0, -50.0, 7.5])
+def test_cubic_polynomials_are_exact(shape, kappa):
+    """The five-point Laplacian is exact on polynomials of degree <= 3, so the
+    discrete solution with f = lap(p) + kappa p and Dirichlet data p equals p at
+    every unknown (exercises delta, signs, kappa, the boundary lift, interface
+    ownership and reentrant corners)."""
+    n = 6
+    X, Y, h = workloads.frame_nodes(n)
+    p = _cubic(X, Y)
+    f = _cubic_lap(X, Y) + kappa * p
+    rects = workloads.shape_rects(shape, n)
+    sol = composite.solve(rects, h, kappa, f, p, method="band_lu")
+    P = sol.on_grid()
+    m = sol.grid.unknown
+    p = p[:P.shape[0], :P.shape[1]]
+    assert np.max(np.abs(P[m] - p[m])) <= 1e-11 * np.max(np.abs(p[m]))
+
+
+@pytest.mark.parametrize("shape", ["cross", "L", "T"])
+def test_band_solvers_agree_with_dense(shape):
+    n = 7
+    prob = workloads.gaussian_problem(shape, n, -13.0, 99, 0, 0)
+    ref = composite.solve(prob.rects, prob.h, prob.kappa, prob.f_grid, prob.g_grid, method="dense")
+    for meth in ("band", "band_lu", "splu"):
+        s = composite.solve(prob.rects, prob.h, prob.kappa, prob.f_grid, prob.g_grid, method=meth)
+        assert np.max(np.abs(s.p - ref.p)) <= 1e-13 * np.max(np.abs(ref.p))
+        assert s.relres < 1e-13
+
+
+def test_matrix_symmetric():
+    """R_ij = R_ji^T for the self-adjoint operator (Section 2.3)."""
+    prob = workloads.manufactured_problem("T", 9, -3.0)
+    A, _, _ = composite.assemble(prob.rects, prob.h, prob.kappa, prob.f_grid, prob.g_grid)
+    assert abs(A - A.T).max() == 0.0
+
+
+def test_second_order_convergence():
+    """Manufactured solution on the cross: max error falls 4x per halving of h
+    (Section 3.1 reports second order)."""
+    errs = []
+    for N in (16, 32, 64, 128):
+        prob = workloads.manufactured_problem("cross", N - 1, 0.0, shifted=True)
+        sol = composite.solve(prob.rects, prob.h, 0.0, prob.f_grid, prob.g_grid)
+        P = sol.on_grid()
+        m = sol.grid.unknown
+        errs.append(np.max(np.abs(P[m] - prob.p_exact[m])))
+    ratios = [errs[k] / errs[k + 1] for k in range(3)]
+    for r in ratios:
+        assert 3.7 < r < 4.3, ratios
+
+
+def test_coupling_matters():
+    """Solving the five squares separately (interfaces forced to the exact
+    boundary value zero) differs from the coupled solve; a dropped coupling in
+    the assembly would make them equal."""
+    n = 32
+    prob = workloads.gaussian_problem("cross", n, 0.0, 1, 0, 0)
+    sol = composite.solve(prob.rects, prob.h, 0.0, prob.f_grid, prob.g_grid)
+    P = sol.on_grid()
+    # decoupled: every square on its own with zero data on its whole boundary
+    D = np.zeros_like(P)
+    for (i0, j0, i1, j1) in prob.rects:
+        F = prob.f_grid[j0 + 1:j1, i0 + 1:i1]
+        D[j0 + 1:j1, i0 + 1:i1] = rect.rect_solve(F, prob.h, 0.0)
+    m = sol.grid.unknown
+    diff = np.max(np.abs(P[m] - D[m])) / np.max(np.abs(P[m]))
+    assert diff > 1e-3
+
+
+def test_layout_roundtrip_and_sizes():
+    for shape in ("cross", "L", "T"):
+        n = 5
+        rects = workloads.shape_rects(shape, n)
+        g = composite.classify(rects)
+        own = layout.owned_nodes(rects)
+        total = sum(len(jj) for jj, _ in own)
+        assert total == g.n_unknowns
+        seen = np.zeros_like(g.unknown)
+        for jj, ii in own:
+            assert g.unknown[jj, ii].all()
+            assert not seen[jj, ii].any()
+            seen[jj, ii] = True
+        assert (seen == g.unknown).all()
+        shapes = layout.block_shapes(rects)
+        assert shapes[0] == (n, n)
+        assert sorted(shapes[1:]) == sorted([(n, n + 1) if (r[2] - r[0]) == (n + 1) and
+                                             (r[0] == rects[0][2] or r[2] == rects[0][0])
+                                             else (n + 1, n) for r in rects[1:]])
+        vals = np.random.default_rng(0).normal(size=g.unknown.shape)
+        back = layout.from_user(rects, layout.to_user(rects, vals), vals.shape)
+        assert np.array_equal(back[g.unknown], vals[g.unknown])
