@@ -23,9 +23,15 @@ import scipy.sparse as sp
 # --------------------------------------------------------------------------- DST-I
 
 def dst1_matrix(n: int) -> np.ndarray:
-    """S[j-1, k-1] = sin(pi j k / (n+1)), j, k = 1..n (unnormalised DST-I)."""
-    j = np.arange(1, n + 1, dtype=np.float64)
-    return np.sin(np.pi * np.outer(j, j) / (n + 1))
+    """S[j-1, k-1] = sin(pi j k / (n+1)), j, k = 1..n (unnormalised DST-I).
+
+    sin(pi t/(n+1)) has period 2(n+1) in the integer t = j k, so t is reduced
+    modulo 2(n+1) in exact integer arithmetic before the angle is formed;
+    otherwise the rounding of pi*t/(n+1) (t up to n^2) would perturb entries
+    by about 1e-12 at n = 2048."""
+    j = np.arange(1, n + 1, dtype=np.int64)
+    t = np.outer(j, j) % (2 * (n + 1))
+    return np.sin(np.pi * t.astype(np.float64) / (n + 1))
 
 
 def dst1_rows(x: np.ndarray) -> np.ndarray:

@@ -97,3 +97,16 @@ def test_rect_matrix_matches_composite_single_square():
                                  np.zeros((N + 1, N + 1)))
     B = rect.rect_matrix(n, n, h, -4.0)
     assert abs(A - B).max() == 0.0
+
+
+def test_dst_matrix_entries_exact_for_large_n():
+    """Entries of the sine matrix agree with 50-digit arithmetic even where
+    j*k is large (checks the exact reduction of the angle)."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 50
+    n = 2047
+    S = rect.dst1_matrix(n)
+    rng = np.random.default_rng(0)
+    for j, k in rng.integers(1, n + 1, size=(300, 2)):
+        ref = float(mpmath.sin(mpmath.pi * int(j) * int(k) / (n + 1)))
+        assert abs(S[j - 1, k - 1] - ref) <= 1e-15
