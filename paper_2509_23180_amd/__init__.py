@@ -1,0 +1,321 @@
+"""Python binding of the MI355X FFT-preconditioned domain-decomposition solver.
+
+Argument marshalling only: every step of the solve runs in the HIP library
+`libfds.so` built from `csrc/` (see `build.py`).  PyTorch supplies device
+memory and streams.  Importing this module does not load the library; the
+first call does, and it raises if the library is missing or no GPU is present.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfds.so")
+
+FDS_OK = 0
+FDS_PENDING = 1
+STATUS = {0: "ok", 1: "pending", -1: "invalid argument", -2: "unsupported geometry",
+          -3: "unsupported", -4: "singular", -5: "out of memory", -6: "not converged",
+          -7: "non-finite input", -8: "device error"}
+FP64 = 0
+FP32_PRECOND = 1
+STOP = {0: "none", 1: "tol", 2: "at_floor", 3: "max_cycles", 4: "stagnation"}
+
+TIMING_CLASSES = {"dst": 0, "tridiag": 1, "operator": 2, "mgs": 3, "lines": 4, "other": 5}
+
+
+class FdsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Rect(ctypes.Structure):
+    _fields_ = [("i0", ctypes.c_int32), ("j0", ctypes.c_int32), ("i1", ctypes.c_int32),
+                ("j1", ctypes.c_int32)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("restart_m", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("cycles", ctypes.c_int32), ("stop_reason", ctypes.c_int32),
+                ("relres_schur", ctypes.c_double), ("relres_global", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+@dataclass
+class Result:
+    status: int
+    iterations: int
+    cycles: int
+    stop_reason: str
+    relres_schur: float
+    relres_global: float
+    seconds: float
+
+    @staticmethod
+    def from_c(r: _Result) -> "Result":
+        return Result(r.status, r.iterations, r.cycles, STOP.get(r.stop_reason, str(r.stop_reason)),
+                      r.relres_schur, r.relres_global, r.seconds)
+
+
+_lib = None
+
+# exported symbols declared in include/fds.h
+SYMBOLS = (
+    "fds_plan_create", "fds_plan_destroy", "fds_plan_layout", "fds_plan_footprint", "fds_solve",
+    "fds_solve_batch", "fds_server_create", "fds_server_destroy", "fds_batch_submit",
+    "fds_batch_poll", "fds_k_dst_rows", "fds_k_dst_rows_f32", "fds_k_tridiag_modes",
+    "fds_k_tridiag_modes_f32", "fds_k_rect_solve", "fds_k_centre_operator", "fds_k_arnoldi_mgs",
+    "fds_status_str", "fds_last_error", "fds_timing_enable", "fds_timing_read", "fds_timing_reset",
+)
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libfds.so (no GPU needed to load).  Raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FdsError(-8, f"{path} is missing: run __graft_entry__.build() (or python "
+                           f"paper_2509_23180_amd/build.py) first")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    I32, I64, D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "fds_plan_create": ([ctypes.POINTER(_Rect), I32, D, D, ctypes.POINTER(_Options),
+                             ctypes.POINTER(P)], I32),
+        "fds_plan_destroy": ([P], None),
+        "fds_plan_layout": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
+        "fds_plan_footprint": ([P, ctypes.POINTER(ctypes.c_size_t)], I32),
+        "fds_solve": ([P, P, P, P, D, P, ctypes.POINTER(_Result)], I32),
+        "fds_solve_batch": ([ctypes.POINTER(P), I32, ctypes.POINTER(P), ctypes.POINTER(P),
+                             ctypes.POINTER(P), ctypes.POINTER(D), P, ctypes.POINTER(_Result)], I32),
+        "fds_server_create": ([ctypes.c_size_t, I32, ctypes.POINTER(P)], I32),
+        "fds_server_destroy": ([P], None),
+        "fds_batch_submit": ([P, P, P, P, P, D, ctypes.POINTER(ctypes.c_uint64)], I32),
+        "fds_batch_poll": ([P, ctypes.c_uint64, ctypes.POINTER(_Result)], I32),
+        "fds_k_dst_rows": ([P, P, I32, I32, D, P], I32),
+        "fds_k_dst_rows_f32": ([P, P, I32, I32, ctypes.c_float, P], I32),
+        "fds_k_tridiag_modes": ([P, I32, I32, D, D, D, P], I32),
+        "fds_k_tridiag_modes_f32": ([P, I32, I32, D, D, D, P], I32),
+        "fds_k_rect_solve": ([P, P, I32, I32, D, D, I32, P], I32),
+        "fds_k_centre_operator": ([P, P, P, P], I32),
+        "fds_k_arnoldi_mgs": ([P, I32, I64, P, P], I32),
+        "fds_status_str": ([I32], ctypes.c_char_p),
+        "fds_last_error": ([], ctypes.c_char_p),
+        "fds_timing_enable": ([I32], I32),
+        "fds_timing_read": ([I32, ctypes.POINTER(I64), ctypes.POINTER(D)], I32),
+        "fds_timing_reset": ([], I32),
+    }
+    for name, (args, ret) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ret
+    _lib = lib
+    return lib
+
+
+def _check(status: int, allow=(FDS_OK,)) -> int:
+    if status not in allow:
+        msg = load_library().fds_last_error().decode()
+        raise FdsError(status, msg)
+    return status
+
+
+def _require_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        raise FdsError(-8, "no HIP device available")
+    load_library()
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+# --------------------------------------------------------------------------- plans
+
+class Plan:
+    """fds_plan_create wrapper.  rects: closed node boxes (i0, j0, i1, j1)."""
+
+    def __init__(self, rects: Sequence[Tuple[int, int, int, int]], h: float, kappa: float,
+                 restart_m: int = 30, max_cycles: int = 200, precision: int = FP64):
+        _require_gpu()
+        lib = load_library()
+        arr = (_Rect * len(rects))(*[_Rect(*map(int, r)) for r in rects])
+        opt = _Options(restart_m, max_cycles, precision, 0)
+        out = ctypes.c_void_p()
+        _check(lib.fds_plan_create(arr, len(rects), float(h), float(kappa), ctypes.byref(opt),
+                                   ctypes.byref(out)))
+        self._h = out
+        self.rects = [tuple(map(int, r)) for r in rects]
+        self.h = float(h)
+        self.kappa = float(kappa)
+        self.restart_m = restart_m
+        self.precision = precision
+        n = len(rects)
+        uo = (ctypes.c_int64 * (n + 1))()
+        bo = (ctypes.c_int64 * (n + 1))()
+        _check(lib.fds_plan_layout(self._h, uo, bo))
+        self.unknown_offsets = list(uo)
+        self.bc_offsets = list(bo)
+        fp = ctypes.c_size_t()
+        _check(lib.fds_plan_footprint(self._h, ctypes.byref(fp)))
+        self.footprint = fp.value
+
+    @property
+    def n_unknowns(self) -> int:
+        return self.unknown_offsets[-1]
+
+    @property
+    def n_bc(self) -> int:
+        return self.bc_offsets[-1]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().fds_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(plan: Plan, rhs, x, tol: float, bc=None, stream=None) -> Result:
+    """Blocking solve; returns the Result (raises on argument/device errors,
+    not on FDS_E_NOT_CONVERGED / FDS_E_NONFINITE, which are in Result.status)."""
+    lib = load_library()
+    res = _Result()
+    st = lib.fds_solve(plan._h, _ptr(rhs), _ptr(bc), _ptr(x), float(tol), _stream(stream),
+                       ctypes.byref(res))
+    _check(st, allow=(FDS_OK, -6, -7))
+    return Result.from_c(res)
+
+
+def solve_batch(plans: Sequence[Plan], rhs: Sequence, xs: Sequence, tols: Sequence[float],
+                bcs: Optional[Sequence] = None, stream=None) -> List[Result]:
+    lib = load_library()
+    n = len(plans)
+    P = ctypes.c_void_p
+    ph = (P * n)(*[p._h for p in plans])
+    rh = (P * n)(*[_ptr(r) for r in rhs])
+    xh = (P * n)(*[_ptr(x) for x in xs])
+    bh = (P * n)(*[_ptr(b) for b in bcs]) if bcs is not None else None
+    th = (ctypes.c_double * n)(*map(float, tols))
+    res = (_Result * n)()
+    st = lib.fds_solve_batch(ph, n, rh, bh, xh, th, _stream(stream), res)
+    _check(st, allow=(FDS_OK, -6, -7))
+    return [Result.from_c(r) for r in res]
+
+
+class Server:
+    """Continuous-batching request server (fds_server_*)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int):
+        _require_gpu()
+        lib = load_library()
+        out = ctypes.c_void_p()
+        _check(lib.fds_server_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(out)))
+        self._h = out
+
+    def submit(self, plan: Plan, rhs, x, tol: float, bc=None) -> int:
+        t = ctypes.c_uint64()
+        _check(load_library().fds_batch_submit(self._h, plan._h, _ptr(rhs), _ptr(bc), _ptr(x),
+                                               float(tol), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> Optional[Result]:
+        res = _Result()
+        st = load_library().fds_batch_poll(self._h, int(ticket), ctypes.byref(res))
+        if st == FDS_PENDING:
+            return None
+        _check(st, allow=(FDS_OK, -6, -7))
+        return Result.from_c(res)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().fds_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------------------- kernel-level calls
+
+def dst_rows(inp, out, scale: float = 1.0, stream=None):
+    import torch
+    rows, n = inp.shape
+    lib = load_library()
+    if inp.dtype == torch.float64:
+        _check(lib.fds_k_dst_rows(_ptr(inp), _ptr(out), rows, n, float(scale), _stream(stream)))
+    else:
+        _check(lib.fds_k_dst_rows_f32(_ptr(inp), _ptr(out), rows, n, float(scale), _stream(stream)))
+
+
+def tridiag_modes(data, h: float, kappa: float, scale: float = 1.0, stream=None):
+    import torch
+    rows, modes = data.shape
+    lib = load_library()
+    fn = lib.fds_k_tridiag_modes if data.dtype == torch.float64 else lib.fds_k_tridiag_modes_f32
+    _check(fn(_ptr(data), rows, modes, float(h), float(kappa), float(scale), _stream(stream)))
+
+
+def rect_solve(f, z, h: float, kappa: float, precision: int = FP64, stream=None):
+    rows, cols = f.shape
+    _check(load_library().fds_k_rect_solve(_ptr(f), _ptr(z), rows, cols, float(h), float(kappa),
+                                           int(precision), _stream(stream)))
+
+
+def centre_operator(plan: Plan, z, w, stream=None):
+    _check(load_library().fds_k_centre_operator(plan._h, _ptr(z), _ptr(w), _stream(stream)))
+
+
+def arnoldi_mgs(V, k: int, h, stream=None):
+    _check(load_library().fds_k_arnoldi_mgs(_ptr(V), int(k), int(V.shape[1]), _ptr(h),
+                                            _stream(stream)))
+
+
+def timing_enable(on: bool = True):
+    _check(load_library().fds_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    _check(load_library().fds_timing_reset())
+
+
+def timing_read(cls: str) -> Tuple[int, float]:
+    c = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(load_library().fds_timing_read(TIMING_CLASSES[cls], ctypes.byref(c), ctypes.byref(ms)))
+    return c.value, ms.value

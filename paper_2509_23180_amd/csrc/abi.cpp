@@ -1,0 +1,434 @@
+// C ABI of the library (include/fds.h).  Converts exceptions into status
+// codes and keeps a thread-local message for fds_last_error().
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "runtime.h"
+#include "server.h"
+
+using namespace fds;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fds_status fail(fds_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+template <typename F>
+fds_status guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const Error& e) {
+    return fail(e.status, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(FDS_E_NOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(FDS_E_DEVICE, e.what());
+  }
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------- timing
+struct TimingState {
+  std::mutex mu;
+  bool on = false;
+  struct Pending { int cls; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t open[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  long long calls[6] = {0, 0, 0, 0, 0, 0};
+  double ms[6] = {0, 0, 0, 0, 0, 0};
+
+  hipEvent_t take() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e;
+    FDS_HIP(hipEventCreate(&e));
+    return e;
+  }
+  void flush() {
+    for (const Pending& p : pending) {
+      FDS_HIP(hipEventSynchronize(p.b));
+      float t = 0;
+      FDS_HIP(hipEventElapsedTime(&t, p.a, p.b));
+      calls[p.cls] += 1;
+      ms[p.cls] += t;
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+};
+
+TimingState& timing() {
+  static TimingState t;
+  return t;
+}
+
+}  // namespace
+
+namespace fds {
+
+void Timing::enable(bool on) {
+  std::lock_guard<std::mutex> lk(timing().mu);
+  timing().on = on;
+}
+bool Timing::on() { return timing().on; }
+void Timing::begin(int cls, hipStream_t s) {
+  TimingState& t = timing();
+  if (!t.on) return;
+  std::lock_guard<std::mutex> lk(t.mu);
+  hipEvent_t e = t.take();
+  FDS_HIP(hipEventRecord(e, s));
+  t.open[cls] = e;
+}
+void Timing::end(int cls, hipStream_t s) {
+  TimingState& t = timing();
+  if (!t.on) return;
+  std::lock_guard<std::mutex> lk(t.mu);
+  if (!t.open[cls]) return;
+  hipEvent_t e = t.take();
+  FDS_HIP(hipEventRecord(e, s));
+  t.pending.push_back({cls, t.open[cls], e});
+  t.open[cls] = nullptr;
+  if (t.pending.size() > 8192) t.flush();
+}
+void Timing::read(int cls, long long* calls, double* ms) {
+  TimingState& t = timing();
+  std::lock_guard<std::mutex> lk(t.mu);
+  t.flush();
+  *calls = t.calls[cls];
+  *ms = t.ms[cls];
+}
+void Timing::reset() {
+  TimingState& t = timing();
+  std::lock_guard<std::mutex> lk(t.mu);
+  t.flush();
+  for (int i = 0; i < 6; ++i) { t.calls[i] = 0; t.ms[i] = 0; }
+}
+
+}  // namespace fds
+
+extern "C" {
+
+const char* fds_status_str(fds_status s) {
+  switch (s) {
+    case FDS_OK: return "ok";
+    case FDS_PENDING: return "pending";
+    case FDS_E_INVALID_ARG: return "invalid argument";
+    case FDS_E_GEOMETRY: return "unsupported geometry";
+    case FDS_E_UNSUPPORTED: return "unsupported";
+    case FDS_E_SINGULAR: return "singular subdomain operator";
+    case FDS_E_NOMEM: return "out of memory";
+    case FDS_E_NOT_CONVERGED: return "not converged";
+    case FDS_E_NONFINITE: return "non-finite input";
+    case FDS_E_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+const char* fds_last_error(void) { return g_last_error.c_str(); }
+
+fds_status fds_plan_create(const fds_rect* rects, int32_t nrect, double h, double kappa,
+                           const fds_options* opt, fds_plan** out) {
+  return guarded([&] {
+    if (!out) throw Error(FDS_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    *out = create_plan(rects, nrect, h, kappa, opt);
+    return FDS_OK;
+  });
+}
+
+void fds_plan_destroy(fds_plan* plan) { delete plan; }
+
+fds_status fds_plan_layout(const fds_plan* plan, int64_t* unknown_offsets, int64_t* bc_offsets) {
+  return guarded([&] {
+    if (!plan) throw Error(FDS_E_INVALID_ARG, "plan is NULL");
+    const size_t n = plan->rects.size();
+    for (size_t i = 0; i <= n; ++i) {
+      if (unknown_offsets) unknown_offsets[i] = plan->user_off[i];
+      if (bc_offsets) bc_offsets[i] = plan->bc_off[i];
+    }
+    return FDS_OK;
+  });
+}
+
+fds_status fds_plan_footprint(const fds_plan* plan, size_t* bytes) {
+  return guarded([&] {
+    if (!plan || !bytes) throw Error(FDS_E_INVALID_ARG, "NULL argument");
+    *bytes = plan->footprint(plan->opt.restart_m, plan->opt.precision);
+    return FDS_OK;
+  });
+}
+
+fds_status fds_solve_batch(fds_plan* const* plans, int32_t count, const double* const* rhs,
+                           const double* const* bc, double* const* x, const double* tol,
+                           void* stream, fds_result* res) {
+  return guarded([&] {
+    if (count < 1 || !plans || !rhs || !x || !tol) throw Error(FDS_E_INVALID_ARG, "bad batch arguments");
+    std::vector<SolveRequest> reqs(count);
+    const int m = plans[0] ? plans[0]->opt.restart_m : 0;
+    const int prec = plans[0] ? plans[0]->opt.precision : 0;
+    int max_cycles = 1;
+    for (int i = 0; i < count; ++i) {
+      if (!plans[i] || !rhs[i] || !x[i]) throw Error(FDS_E_INVALID_ARG, "NULL plan/rhs/x in batch");
+      if (plans[i]->opt.restart_m != m || plans[i]->opt.precision != prec)
+        throw Error(FDS_E_INVALID_ARG, "batched plans must share restart_m and precision");
+      if (!(tol[i] >= 0.0)) throw Error(FDS_E_INVALID_ARG, "tol must be >= 0");
+      max_cycles = std::max(max_cycles, plans[i]->opt.max_cycles);
+      reqs[i] = SolveRequest{plans[i], rhs[i], bc ? bc[i] : nullptr, x[i], tol[i]};
+    }
+    Engine eng(reqs, m, prec, max_cycles, as_stream(stream));
+    std::vector<SolveOutcome> out = eng.run();
+    fds_status first = FDS_OK;
+    for (int i = 0; i < count; ++i) {
+      if (res) res[i] = out[i].res;
+      if (first == FDS_OK && out[i].status != FDS_OK) first = out[i].status;
+    }
+    if (first != FDS_OK) g_last_error = fds_status_str(first);
+    return first;
+  });
+}
+
+fds_status fds_solve(fds_plan* plan, const double* rhs, const double* bc, double* x, double tol,
+                     void* stream, fds_result* res) {
+  fds_plan* plans[1] = {plan};
+  const double* r[1] = {rhs};
+  const double* b[1] = {bc};
+  double* xx[1] = {x};
+  double t[1] = {tol};
+  return fds_solve_batch(plans, 1, r, b, xx, t, stream, res);
+}
+
+// ---------------------------------------------------------------- kernel-level entry points
+
+static fds_status dst_rows_impl(const void* in, void* out, int rows, int n, double scale,
+                                bool fp32, hipStream_t s) {
+  if (!in || !out || rows < 0 || n < 1) throw Error(FDS_E_INVALID_ARG, "bad DST arguments");
+  if (rows == 0) return FDS_OK;
+  auto fft = TableCache::get().fft(n);
+  const int rpb = kBlock / dst_threads_per_row(n);
+  DstTask t{};
+  t.in = in; t.out = out; t.in_rs = n; t.out_rs = n; t.in_cs = 1; t.out_cs = 1;
+  t.rows = rows; t.n = n; t.rpb = rpb; t.scale = scale; t.fft = fft->dev; t.block_begin = 0;
+  DevBuf d(sizeof(DstTask));
+  FDS_HIP(hipMemcpyAsync(d.get(), &t, sizeof(t), hipMemcpyHostToDevice, s));
+  const int nb = (rows + rpb - 1) / rpb;
+  Timing::begin(0, s);
+  launch_dst(fp32 ? DstKind::F_F : DstKind::D_D, d.as<DstTask>(), 1, nb, dst_smem_bytes(n, fp32), 0, s);
+  Timing::end(0, s);
+  FDS_HIP(hipGetLastError());
+  FDS_HIP(hipStreamSynchronize(s));
+  return FDS_OK;
+}
+
+fds_status fds_k_dst_rows(const double* in, double* out, int32_t rows, int32_t n, double scale,
+                          void* stream) {
+  return guarded([&] { return dst_rows_impl(in, out, rows, n, scale, false, as_stream(stream)); });
+}
+
+fds_status fds_k_dst_rows_f32(const float* in, float* out, int32_t rows, int32_t n, float scale,
+                              void* stream) {
+  return guarded([&] { return dst_rows_impl(in, out, rows, n, scale, true, as_stream(stream)); });
+}
+
+static fds_status tridiag_impl(void* data, int rows, int modes, double h, double kappa,
+                               double scale, bool fp32, hipStream_t s) {
+  if (!data || rows < 1 || modes < 1 || !(h > 0)) throw Error(FDS_E_INVALID_ARG, "bad tridiag arguments");
+  std::vector<ModeCoef<double>> c64;
+  std::vector<ModeCoef<float>> c32;
+  mode_coefs_host(modes, rows, h, kappa, scale, c64, c32);
+  auto tab = upload_modes(c64, c32);
+  TriTask t{};
+  t.data = data; t.rs = modes; t.rows = rows; t.modes = modes;
+  t.coef = fp32 ? (const void*)tab->c32 : (const void*)tab->c64;
+  DevBuf d(sizeof(TriTask));
+  FDS_HIP(hipMemcpyAsync(d.get(), &t, sizeof(t), hipMemcpyHostToDevice, s));
+  Timing::begin(1, s);
+  launch_tridiag(fp32, d.as<TriTask>(), 1, (modes + kBlock - 1) / kBlock, 0, s);
+  Timing::end(1, s);
+  FDS_HIP(hipGetLastError());
+  FDS_HIP(hipStreamSynchronize(s));
+  return FDS_OK;
+}
+
+fds_status fds_k_tridiag_modes(double* data, int32_t rows, int32_t modes, double h, double kappa,
+                               double scale, void* stream) {
+  return guarded([&] { return tridiag_impl(data, rows, modes, h, kappa, scale, false, as_stream(stream)); });
+}
+
+fds_status fds_k_tridiag_modes_f32(float* data, int32_t rows, int32_t modes, double h,
+                                   double kappa, double scale, void* stream) {
+  return guarded([&] { return tridiag_impl(data, rows, modes, h, kappa, scale, true, as_stream(stream)); });
+}
+
+fds_status fds_k_rect_solve(const double* f, double* z, int32_t rows, int32_t cols, double h,
+                            double kappa, int32_t precision, void* stream) {
+  return guarded([&] {
+    hipStream_t s = as_stream(stream);
+    if (!f || !z || rows < 1 || cols < 1 || !(h > 0)) throw Error(FDS_E_INVALID_ARG, "bad rect solve arguments");
+    const bool fp32 = precision == FDS_FP32_PRECOND;
+    auto fft = TableCache::get().fft(cols);
+    auto modes = TableCache::get().modes(cols, rows, h, kappa);
+    DevBuf tmp((size_t)rows * cols * (fp32 ? 4 : 8));
+    const int rpb = kBlock / dst_threads_per_row(cols);
+    DstTask t{};
+    t.in = f; t.out = tmp.get(); t.in_rs = cols; t.out_rs = cols; t.in_cs = 1; t.out_cs = 1;
+    t.rows = rows; t.n = cols; t.rpb = rpb; t.scale = 1.0; t.fft = fft->dev;
+    DstTask v = t;
+    v.in = tmp.get(); v.out = z;
+    TriTask tt{};
+    tt.data = tmp.get(); tt.rs = cols; tt.rows = rows; tt.modes = cols;
+    tt.coef = fp32 ? (const void*)modes->c32 : (const void*)modes->c64;
+    DevBuf d(sizeof(DstTask) * 2 + sizeof(TriTask));
+    FDS_HIP(hipMemcpyAsync(d.as<char>(0), &t, sizeof(t), hipMemcpyHostToDevice, s));
+    FDS_HIP(hipMemcpyAsync(d.as<char>(sizeof(DstTask)), &v, sizeof(v), hipMemcpyHostToDevice, s));
+    FDS_HIP(hipMemcpyAsync(d.as<char>(2 * sizeof(DstTask)), &tt, sizeof(tt), hipMemcpyHostToDevice, s));
+    const int nb = (rows + rpb - 1) / rpb;
+    const size_t sm = dst_smem_bytes(cols, fp32);
+    launch_dst(fp32 ? DstKind::D_F : DstKind::D_D, d.as<DstTask>(0), 1, nb, sm, 0, s);
+    launch_tridiag(fp32, reinterpret_cast<const TriTask*>(d.as<char>(2 * sizeof(DstTask))), 1,
+                   (cols + kBlock - 1) / kBlock, 0, s);
+    launch_dst(fp32 ? DstKind::F_D : DstKind::D_D,
+               reinterpret_cast<const DstTask*>(d.as<char>(sizeof(DstTask))), 1, nb, sm, 0, s);
+    FDS_HIP(hipGetLastError());
+    FDS_HIP(hipStreamSynchronize(s));
+    return FDS_OK;
+  });
+}
+
+fds_status fds_k_centre_operator(const fds_plan* plan, const double* z, double* w, void* stream) {
+  return guarded([&] {
+    hipStream_t s = as_stream(stream);
+    if (!plan || !z || !w) throw Error(FDS_E_INVALID_ARG, "NULL argument");
+    const int nx = plan->nx, ny = plan->ny;
+    const int Lmax = std::max(nx, ny);
+    DevBuf lines(sizeof(double) * 4 * Lmax);
+    std::vector<LineTask> lt;
+    OpTask ot{};
+    ot.z = z; ot.nx = nx; ot.ny = ny; ot.delta = plan->delta; ot.kappa = plan->kappa; ot.out = w;
+    ot.nblocks = std::max(1, (int)(((long long)nx * ny + kVecPerBlock - 1) / kVecPerBlock));
+    size_t sm = 0;
+    for (const ArmInfo& a : plan->arms) {
+      LineTask t{};
+      t.z = z; t.L = a.L; t.fft = a.fft->dev; t.gs = a.gs->gs;
+      t.out = lines.as<double>() + (size_t)a.line * Lmax;
+      switch (a.line) {
+        case 0: t.start = 0; t.stride = 1; break;
+        case 1: t.start = (long long)(ny - 1) * nx; t.stride = 1; break;
+        case 2: t.start = 0; t.stride = nx; break;
+        case 3: t.start = nx - 1; t.stride = nx; break;
+      }
+      ot.line[a.line] = t.out;
+      sm = std::max(sm, sizeof(double2) * 2 * (a.L + 1) + sizeof(double) * (a.L + 1));
+      lt.push_back(t);
+    }
+    DevBuf d(sizeof(OpTask) + sizeof(LineTask) * std::max<size_t>(1, lt.size()));
+    FDS_HIP(hipMemcpyAsync(d.get(), &ot, sizeof(ot), hipMemcpyHostToDevice, s));
+    if (!lt.empty())
+      FDS_HIP(hipMemcpyAsync(d.as<char>(sizeof(OpTask)), lt.data(), sizeof(LineTask) * lt.size(),
+                             hipMemcpyHostToDevice, s));
+    if (!lt.empty()) {
+      Timing::begin(4, s);
+      launch_lines(reinterpret_cast<const LineTask*>(d.as<char>(sizeof(OpTask))), (int)lt.size(), sm, 0, s);
+      Timing::end(4, s);
+    }
+    Timing::begin(2, s);
+    launch_operator(0, d.as<OpTask>(), 1, ot.nblocks, 0, s);
+    Timing::end(2, s);
+    FDS_HIP(hipGetLastError());
+    FDS_HIP(hipStreamSynchronize(s));
+    return FDS_OK;
+  });
+}
+
+fds_status fds_k_arnoldi_mgs(double* V, int32_t k, int64_t len, double* h, void* stream) {
+  return guarded([&] {
+    hipStream_t s = as_stream(stream);
+    if (!V || !h || k < 1 || len < 1 || k > 120) throw Error(FDS_E_INVALID_ARG, "bad Arnoldi arguments");
+    const int m = k;
+    const int j = k - 1;
+    const int P = (int)((len + kVecPerBlock - 1) / kVecPerBlock);
+    const size_t small = (size_t)(m + 1) * m + 4 * (size_t)m + 2;
+    DevBuf mem(8 * (small + 4 * (size_t)P) + sizeof(ProbState) + sizeof(KryTask) + 512);
+    FDS_HIP(hipMemsetAsync(mem.get(), 0, mem.size(), s));
+    double* H = mem.as<double>(0);
+    double* partials = H + small;
+    auto* st = reinterpret_cast<ProbState*>(partials + 4 * (size_t)P);
+    ProbState hs{};
+    hs.beta = 1.0;
+    hs.fnorm = 1.0;
+    hs.tol_eff = 0.0;
+    FDS_HIP(hipMemcpyAsync(st, &hs, sizeof(hs), hipMemcpyHostToDevice, s));
+    KryTask t{};
+    t.V = V; t.H = H; t.cs = H + (size_t)(m + 1) * m; t.sn = t.cs + m; t.g = t.sn + m; t.y = t.g + m + 1;
+    t.partials = partials; t.st = st; t.Nc = len; t.P = P; t.m = m;
+    auto* dt = reinterpret_cast<KryTask*>(reinterpret_cast<char*>(st) + 256);
+    FDS_HIP(hipMemcpyAsync(dt, &t, sizeof(t), hipMemcpyHostToDevice, s));
+    for (int i = 0; i <= j + 1; ++i) {
+      Timing::begin(3, s);
+      launch_mgs_pass(dt, 1, P, i, j, s);
+      Timing::end(3, s);
+    }
+    // H column j holds h_{0..j, j} before the Givens rotations of the finish step
+    FDS_HIP(hipMemcpyAsync(h, H + (size_t)j * (m + 1), 8 * (size_t)k, hipMemcpyDeviceToDevice, s));
+    launch_mgs_finish(dt, 1, P, j, s);
+    FDS_HIP(hipMemcpyAsync(h + k, &st->last_hn, 8, hipMemcpyDeviceToDevice, s));
+    FDS_HIP(hipGetLastError());
+    FDS_HIP(hipStreamSynchronize(s));
+    return FDS_OK;
+  });
+}
+
+fds_status fds_timing_enable(int32_t enable) {
+  return guarded([&] { Timing::enable(enable != 0); return FDS_OK; });
+}
+
+fds_status fds_timing_read(int32_t cls, int64_t* calls, double* total_ms) {
+  return guarded([&] {
+    if (cls < 0 || cls > 5 || !calls || !total_ms) throw Error(FDS_E_INVALID_ARG, "bad timing arguments");
+    long long c = 0;
+    double ms = 0;
+    Timing::read(cls, &c, &ms);
+    *calls = c;
+    *total_ms = ms;
+    return FDS_OK;
+  });
+}
+
+fds_status fds_timing_reset(void) {
+  return guarded([&] { Timing::reset(); return FDS_OK; });
+}
+
+}  // extern "C"
+
+extern "C" {
+
+fds_status fds_server_create(size_t hbm_budget_bytes, int32_t max_slots, fds_server** out) {
+  return guarded([&] {
+    if (!out) throw Error(FDS_E_INVALID_ARG, "out is NULL");
+    *out = server_create(hbm_budget_bytes, max_slots);
+    return FDS_OK;
+  });
+}
+
+void fds_server_destroy(fds_server* server) { server_destroy(server); }
+
+fds_status fds_batch_submit(fds_server* server, fds_plan* plan, const double* rhs,
+                            const double* bc, double* x, double tol, uint64_t* ticket) {
+  return guarded([&] { return server_submit(server, plan, rhs, bc, x, tol, ticket); });
+}
+
+fds_status fds_batch_poll(fds_server* server, uint64_t ticket, fds_result* res) {
+  return guarded([&] { return server_poll(server, ticket, res); });
+}
+
+}  // extern "C"

@@ -1,0 +1,572 @@
+// Batched GMRES engine (paper Section 2.4 and Algorithm 1).
+//
+// Per problem:  lift the Dirichlet data into the right-hand side; solve every
+// arm A_a q_a = b_a with the fast solver; f'_c = b_c - sum_a R_ca q_a; solve
+// L_c x_c = f'_c with restarted right-preconditioned GMRES(m) (plain FP64) or
+// flexible GMRES(m) with an FP32 preconditioner; back-substitute the arms
+// A_a p_a = b_a - R_ac x_c.  Every kernel launch serves all problems of the
+// batch; problems that finished (or whose cycle ended) skip their work.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "runtime.h"
+
+namespace fds {
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+template <typename T>
+struct TaskList {
+  std::vector<T> h;
+  DevBuf d;
+  int nblocks = 0;
+  size_t smem = 0;
+  const T* dev() const { return d.as<T>(); }
+  int n() const { return (int)h.size(); }
+  void upload() {
+    if (h.empty()) return;
+    d.alloc(sizeof(T) * h.size());
+    FDS_HIP(hipMemcpy(d.get(), h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+  }
+};
+
+template <typename T>
+void add_block_task(TaskList<T>& tl, T t, int nblocks) {
+  t.block_begin = tl.nblocks;
+  tl.h.push_back(t);
+  tl.nblocks += nblocks;
+}
+
+int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+struct Slot {
+  SolveRequest req;
+  fds_plan* plan = nullptr;
+  DevBuf mem;
+  double *b_int = nullptr, *x_int = nullptr, *tmpd = nullptr, *fp = nullptr, *V = nullptr,
+         *u = nullptr, *zbuf = nullptr, *lines = nullptr, *H = nullptr, *cs = nullptr,
+         *sn = nullptr, *g = nullptr, *y = nullptr, *partials = nullptr, *respart = nullptr;
+  float *Z = nullptr, *tmpf = nullptr;
+  ProbState* st = nullptr;
+  long long Nc = 0, Nint = 0;
+  int P = 0, Lmax = 0, res_blocks = 0;
+};
+
+// Buffer layout of one problem, shared by allocation and footprint queries.
+struct SlotLayout {
+  size_t b_int, x_int, tmpd, fp, V, u, zbuf, lines, small, partials, respart, Z, tmpf, total;
+};
+
+int res_blocks_of(const fds_plan* p) {
+  int nb = 0;
+  for (const RectDev& d : p->rd) nb += std::max(1, div_up((long long)d.rows * d.cols, (long long)kBlock * 8));
+  return nb;
+}
+
+SlotLayout layout_of(const fds_plan* p, int m, int precision) {
+  const long long Nc = (long long)p->nx * p->ny;
+  const long long Nint = p->n_internal;
+  const int P = std::max(1, div_up(Nc, kVecPerBlock));
+  const int Lmax = std::max(p->nx, p->ny);
+  const bool flex = precision == FDS_FP32_PRECOND;
+  SlotLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
+  L.b_int = take(8 * Nint);
+  L.x_int = take(8 * Nint);
+  L.tmpd = take(8 * Nint);
+  L.fp = take(8 * Nc);
+  L.V = take(8 * (size_t)(m + 1) * Nc);
+  L.u = take(8 * Nc);
+  L.zbuf = flex ? 0 : take(8 * Nc);
+  L.lines = take(8 * 4 * (size_t)Lmax);
+  L.small = take(8 * ((size_t)(m + 1) * m + 4 * (size_t)m + 2));
+  L.partials = take(8 * 4 * (size_t)P);
+  L.respart = take(8 * 2 * (size_t)res_blocks_of(p));
+  L.Z = flex ? take(4 * (size_t)m * Nc) : 0;
+  L.tmpf = flex ? take(4 * Nc) : 0;
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct Engine::Impl {
+  std::vector<Slot> slots;
+  int m, precision, max_cycles;
+  bool flex;
+  hipStream_t s;
+  DevBuf states;
+  std::vector<ProbState> host_states;
+  TaskList<DstTask> it_fwd, it_inv, cyc_fwd, cyc_inv, arm_fwd, arm_inv, bs_fwd;
+  TaskList<TriTask> it_tri, cyc_tri, arm_tri;
+  TaskList<LineTask> it_lines, x_lines;
+  TaskList<OpTask> it_op, res_op;
+  TaskList<KryTask> kry;
+  TaskList<LiftTask> lift, gather;
+  TaskList<IfaceTask> iface_fp, iface_bs;
+  TaskList<ResTask> resid;
+  size_t smem_lines = 0;
+  DevBuf active_dev;
+  int* active_host = nullptr;
+  std::vector<hipEvent_t> events;
+  bool set_up = false;
+
+  ~Impl() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    if (active_host) (void)hipHostFree(active_host);
+  }
+
+  void build();
+  void iteration(int j);
+  void end_of_cycle();
+  void read_states();
+};
+
+void Engine::Impl::build() {
+  const int n = (int)slots.size();
+  states.alloc(sizeof(ProbState) * n);
+  host_states.assign(n, ProbState{});
+  for (int i = 0; i < n; ++i) {
+    Slot& sl = slots[i];
+    fds_plan* p = sl.plan;
+    const SlotLayout L = layout_of(p, m, precision);
+    sl.mem.alloc(L.total);
+    sl.Nc = (long long)p->nx * p->ny;
+    sl.Nint = p->n_internal;
+    sl.P = std::max(1, div_up(sl.Nc, kVecPerBlock));
+    sl.Lmax = std::max(p->nx, p->ny);
+    sl.b_int = sl.mem.as<double>(L.b_int);
+    sl.x_int = sl.mem.as<double>(L.x_int);
+    sl.tmpd = sl.mem.as<double>(L.tmpd);
+    sl.fp = sl.mem.as<double>(L.fp);
+    sl.V = sl.mem.as<double>(L.V);
+    sl.u = sl.mem.as<double>(L.u);
+    sl.zbuf = flex ? nullptr : sl.mem.as<double>(L.zbuf);
+    sl.lines = sl.mem.as<double>(L.lines);
+    double* small = sl.mem.as<double>(L.small);
+    sl.H = small;
+    sl.cs = sl.H + (size_t)(m + 1) * m;
+    sl.sn = sl.cs + m;
+    sl.g = sl.sn + m;
+    sl.y = sl.g + (m + 1);
+    sl.partials = sl.mem.as<double>(L.partials);
+    sl.respart = sl.mem.as<double>(L.respart);
+    sl.Z = flex ? sl.mem.as<float>(L.Z) : nullptr;
+    sl.tmpf = flex ? sl.mem.as<float>(L.tmpf) : nullptr;
+    sl.st = states.as<ProbState>() + i;
+    ProbState& hs = host_states[i];
+    hs = ProbState{};
+    hs.tol = sl.req.tol;
+    hs.tol_eff = sl.req.tol;
+    hs.floor_coef = p->floor_coef;
+
+    const RectDev& cd = p->rd[p->centre];
+    const int nx = p->nx, ny = p->ny;
+    const long long Nc = sl.Nc;
+    const int* skip_it = &sl.st->cycle_done;
+    const int* skip_fin = &sl.st->finished;
+    const FftDesc* fftc = p->fft_c->dev;
+    const int rpb_c = kBlock / dst_threads_per_row(nx);
+    const size_t smem_c64 = dst_smem_bytes(nx, false), smem_c32 = dst_smem_bytes(nx, true);
+
+    // ---- per-iteration transforms of the centre
+    {
+      DstTask t{};
+      t.in = sl.V; t.in_js = Nc; t.in_rs = nx; t.in_cs = 1;
+      t.out = flex ? (void*)sl.tmpf : (void*)sl.tmpd; t.out_js = 0; t.out_rs = nx; t.out_cs = 1;
+      t.rows = ny; t.n = nx; t.rpb = rpb_c; t.scale = 1.0; t.fft = fftc; t.skip = skip_it;
+      add_block_task(it_fwd, t, div_up(ny, rpb_c));
+      it_fwd.smem = std::max(it_fwd.smem, flex ? smem_c32 : smem_c64);
+
+      TriTask tt{};
+      tt.data = t.out; tt.rs = nx; tt.js = 0; tt.rows = ny; tt.modes = nx;
+      tt.coef = flex ? (const void*)p->modes_c->c32 : (const void*)p->modes_c->c64;
+      tt.skip = skip_it;
+      add_block_task(it_tri, tt, div_up(nx, kBlock));
+
+      DstTask v{};
+      v.in = t.out; v.in_js = 0; v.in_rs = nx; v.in_cs = 1;
+      if (flex) { v.out = sl.Z; v.out_js = Nc; }
+      else { v.out = sl.zbuf; v.out_js = 0; }
+      v.out_rs = nx; v.out_cs = 1;
+      v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = 1.0; v.fft = fftc; v.skip = skip_it;
+      add_block_task(it_inv, v, div_up(ny, rpb_c));
+      it_inv.smem = std::max(it_inv.smem, flex ? smem_c32 : smem_c64);
+    }
+    // ---- end-of-cycle preconditioner apply (plain variant): u -> x_c += A_c^{-1} u
+    if (!flex) {
+      DstTask t{};
+      t.in = sl.u; t.in_rs = nx; t.in_cs = 1; t.out = sl.tmpd; t.out_rs = nx; t.out_cs = 1;
+      t.rows = ny; t.n = nx; t.rpb = rpb_c; t.scale = 1.0; t.fft = fftc; t.skip = skip_fin;
+      add_block_task(cyc_fwd, t, div_up(ny, rpb_c));
+      cyc_fwd.smem = std::max(cyc_fwd.smem, smem_c64);
+      TriTask tt{};
+      tt.data = sl.tmpd; tt.rs = nx; tt.rows = ny; tt.modes = nx; tt.coef = p->modes_c->c64;
+      tt.skip = skip_fin;
+      add_block_task(cyc_tri, tt, div_up(nx, kBlock));
+      DstTask v{};
+      v.in = sl.tmpd; v.in_rs = nx; v.in_cs = 1; v.out = sl.x_int + cd.off; v.out_rs = nx;
+      v.out_cs = 1; v.accumulate = 1;
+      v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = 1.0; v.fft = fftc; v.skip = skip_fin;
+      add_block_task(cyc_inv, v, div_up(ny, rpb_c));
+      cyc_inv.smem = std::max(cyc_inv.smem, smem_c64);
+    }
+    // ---- Schur lines and operators
+    OpTask ot{};
+    ot.nx = nx; ot.ny = ny; ot.nblocks = sl.P; ot.delta = p->delta; ot.kappa = p->kappa;
+    for (int q = 0; q < 4; ++q) ot.line[q] = nullptr;
+    IfaceTask fi{}, bi{};
+    fi.delta = bi.delta = p->delta;
+    for (const ArmInfo& a : p->arms) {
+      LineTask lt{};
+      lt.L = a.L;
+      lt.fft = a.fft->dev;
+      lt.gs = a.gs->gs;
+      lt.out = sl.lines + (size_t)a.line * sl.Lmax;
+      switch (a.line) {
+        case 0: lt.start = 0; lt.stride = 1; break;
+        case 1: lt.start = (long long)(ny - 1) * nx; lt.stride = 1; break;
+        case 2: lt.start = 0; lt.stride = nx; break;
+        case 3: lt.start = nx - 1; lt.stride = nx; break;
+      }
+      ot.line[a.line] = lt.out;
+      const size_t sm = sizeof(double2) * 2 * (a.L + 1) + sizeof(double) * (a.L + 1);
+      smem_lines = std::max(smem_lines, sm);
+      LineTask li = lt;
+      if (flex) { li.z = sl.Z; li.z_js = Nc; li.z_f32 = 1; }
+      else { li.z = sl.zbuf; li.z_js = 0; li.z_f32 = 0; }
+      li.skip = skip_it;
+      it_lines.h.push_back(li);
+      LineTask lx = lt;
+      lx.z = sl.x_int + cd.off; lx.z_js = 0; lx.z_f32 = 0; lx.skip = skip_fin;
+      x_lines.h.push_back(lx);
+
+      // f'_c formation and back substitution
+      const RectDev& ad = p->rd[a.rect];
+      const int q = fi.nlines++;
+      fi.dst[q] = sl.fp; fi.dst_start[q] = lt.start; fi.dst_stride[q] = lt.stride;
+      fi.src[q] = sl.x_int; fi.src_start[q] = ad.off; fi.src_stride[q] = 1; fi.L[q] = a.L;
+      bi.dst[q] = sl.x_int; bi.dst_start[q] = ad.off; bi.dst_stride[q] = 1;
+      bi.src[q] = sl.x_int; bi.src_start[q] = cd.off + lt.start; bi.src_stride[q] = lt.stride;
+      bi.L[q] = a.L;
+      bi.nlines = fi.nlines;
+
+      // arm solves (FP64): b_int -> tmpd -> x_int, and x_int -> tmpd -> x_int
+      const int rpb = kBlock / dst_threads_per_row(a.L);
+      DstTask f{};
+      f.in = sl.b_int + ad.off; f.in_rs = a.L; f.in_cs = 1;
+      f.out = sl.tmpd + ad.off; f.out_rs = a.L; f.out_cs = 1;
+      f.rows = a.rows; f.n = a.L; f.rpb = rpb; f.scale = 1.0; f.fft = a.fft->dev; f.skip = nullptr;
+      add_block_task(arm_fwd, f, div_up(a.rows, rpb));
+      arm_fwd.smem = std::max(arm_fwd.smem, dst_smem_bytes(a.L, false));
+      DstTask fb = f;
+      fb.in = sl.x_int + ad.off;
+      add_block_task(bs_fwd, fb, div_up(a.rows, rpb));
+      bs_fwd.smem = arm_fwd.smem;
+      TriTask at{};
+      at.data = sl.tmpd + ad.off; at.rs = a.L; at.rows = a.rows; at.modes = a.L;
+      at.coef = a.modes->c64; at.skip = nullptr;
+      add_block_task(arm_tri, at, div_up(a.L, kBlock));
+      DstTask iv = f;
+      iv.in = sl.tmpd + ad.off; iv.out = sl.x_int + ad.off;
+      add_block_task(arm_inv, iv, div_up(a.rows, rpb));
+      arm_inv.smem = arm_fwd.smem;
+    }
+    iface_fp.h.push_back(fi);
+    iface_bs.h.push_back(bi);
+    {
+      OpTask o = ot;
+      if (flex) { o.z = sl.Z; o.z_js = Nc; o.z_f32 = 1; }
+      else { o.z = sl.zbuf; o.z_js = 0; o.z_f32 = 0; }
+      o.out = sl.V + Nc; o.out_js = Nc; o.skip = skip_it;
+      add_block_task(it_op, o, sl.P);
+      OpTask r = ot;
+      r.z = sl.x_int + cd.off; r.z_js = 0; r.z_f32 = 0;
+      r.out = sl.V; r.out_js = 0; r.fp = sl.fp; r.partials = sl.partials + 2 * sl.P;
+      r.skip = skip_fin;
+      add_block_task(res_op, r, sl.P);
+    }
+    {
+      KryTask k{};
+      k.V = sl.V; k.Z = sl.Z; k.x = sl.x_int + cd.off; k.u = sl.u; k.H = sl.H; k.cs = sl.cs;
+      k.sn = sl.sn; k.g = sl.g; k.y = sl.y; k.partials = sl.partials; k.st = sl.st; k.Nc = Nc;
+      k.P = sl.P; k.m = m;
+      add_block_task(kry, k, sl.P);
+    }
+    // ---- layout conversion and composite residual
+    for (size_t r = 0; r < p->rd.size(); ++r) {
+      const RectDev& d = p->rd[r];
+      const long long tot = (long long)d.rows * d.cols;
+      LiftTask lt{};
+      lt.rd = d; lt.rhs = sl.req.rhs; lt.bc = sl.req.bc; lt.out = sl.b_int; lt.xuser = sl.req.x;
+      lt.xint = sl.x_int; lt.delta = p->delta; lt.kappa = p->kappa;
+      const int nb = std::max(1, div_up(tot, (long long)kBlock * 4));
+      lt.nblocks = nb;
+      add_block_task(lift, lt, nb);
+      add_block_task(gather, lt, nb);
+    }
+    {
+      int off = 0;
+      for (size_t r = 0; r < p->rd.size(); ++r) {
+        const RectDev& d = p->rd[r];
+        ResTask rt{};
+        rt.rd = d; rt.p = sl.x_int; rt.b = sl.b_int; rt.delta = p->delta; rt.kappa = p->kappa;
+        const int nb = std::max(1, div_up((long long)d.rows * d.cols, (long long)kBlock * 8));
+        rt.nblocks = nb;
+        rt.partials = sl.respart + 2 * off;
+        off += nb;
+        add_block_task(resid, rt, nb);
+      }
+      sl.res_blocks = off;
+    }
+  }
+  for (auto* tl : {&it_fwd, &it_inv, &cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd}) tl->upload();
+  for (auto* tl : {&it_tri, &cyc_tri, &arm_tri}) tl->upload();
+  it_lines.upload();
+  x_lines.upload();
+  it_op.upload();
+  res_op.upload();
+  kry.upload();
+  lift.upload();
+  gather.upload();
+  iface_fp.upload();
+  iface_bs.upload();
+  resid.upload();
+  active_dev.alloc(sizeof(int) * (m + 1));
+  FDS_HIP(hipHostMalloc((void**)&active_host, sizeof(int) * (m + 1), hipHostMallocDefault));
+  events.resize(m);
+  for (int j = 0; j < m; ++j) FDS_HIP(hipEventCreateWithFlags(&events[j], hipEventDisableTiming));
+}
+
+// One Arnoldi step j of every unfinished problem.
+void Engine::Impl::iteration(int j) {
+  const DstKind fk = flex ? DstKind::D_F : DstKind::D_D;
+  const DstKind ik = flex ? DstKind::F_F : DstKind::D_D;
+  Timing::begin(0, s);
+  launch_dst(fk, it_fwd.dev(), it_fwd.n(), it_fwd.nblocks, it_fwd.smem, j, s);
+  Timing::end(0, s);
+  Timing::begin(1, s);
+  launch_tridiag(flex, it_tri.dev(), it_tri.n(), it_tri.nblocks, 0, s);
+  Timing::end(1, s);
+  Timing::begin(0, s);
+  launch_dst(ik, it_inv.dev(), it_inv.n(), it_inv.nblocks, it_inv.smem, j, s);
+  Timing::end(0, s);
+  if (it_lines.n()) {
+    Timing::begin(4, s);
+    launch_lines(it_lines.dev(), it_lines.n(), smem_lines, j, s);
+    Timing::end(4, s);
+  }
+  Timing::begin(2, s);
+  launch_operator(0, it_op.dev(), it_op.n(), it_op.nblocks, j, s);
+  Timing::end(2, s);
+  for (int i = 0; i <= j + 1; ++i) {
+    Timing::begin(3, s);
+    launch_mgs_pass(kry.dev(), kry.n(), kry.nblocks, i, j, s);
+    Timing::end(3, s);
+  }
+  Timing::begin(5, s);
+  launch_mgs_finish(kry.dev(), kry.n(), kry.nblocks, j, s);
+  Timing::end(5, s);
+  FDS_HIP(hipGetLastError());
+}
+
+void Engine::Impl::end_of_cycle() {
+  Timing::begin(5, s);
+  launch_ls_solve(kry.dev(), kry.n(), s);
+  launch_combine(flex, kry.dev(), kry.n(), kry.nblocks, s);
+  Timing::end(5, s);
+  if (!flex) {
+    Timing::begin(0, s);
+    launch_dst(DstKind::D_D, cyc_fwd.dev(), cyc_fwd.n(), cyc_fwd.nblocks, cyc_fwd.smem, 0, s);
+    Timing::end(0, s);
+    Timing::begin(1, s);
+    launch_tridiag(false, cyc_tri.dev(), cyc_tri.n(), cyc_tri.nblocks, 0, s);
+    Timing::end(1, s);
+    Timing::begin(0, s);
+    launch_dst(DstKind::D_D, cyc_inv.dev(), cyc_inv.n(), cyc_inv.nblocks, cyc_inv.smem, 0, s);
+    Timing::end(0, s);
+  }
+  if (x_lines.n()) {
+    Timing::begin(4, s);
+    launch_lines(x_lines.dev(), x_lines.n(), smem_lines, 0, s);
+    Timing::end(4, s);
+  }
+  Timing::begin(2, s);
+  launch_operator(1, res_op.dev(), res_op.n(), res_op.nblocks, 0, s);
+  Timing::end(2, s);
+  Timing::begin(5, s);
+  launch_restart(kry.dev(), kry.n(), kry.nblocks, 0, max_cycles, s);
+  Timing::end(5, s);
+  FDS_HIP(hipGetLastError());
+}
+
+void Engine::Impl::read_states() {
+  FDS_HIP(hipMemcpyAsync(host_states.data(), states.get(), sizeof(ProbState) * slots.size(),
+                         hipMemcpyDeviceToHost, s));
+  FDS_HIP(hipStreamSynchronize(s));
+}
+
+Engine::Engine(const std::vector<SolveRequest>& reqs, int m, int precision, int max_cycles,
+               hipStream_t stream)
+    : impl_(new Impl()) {
+  Impl& I = *impl_;
+  I.m = m;
+  I.precision = precision;
+  I.flex = precision == FDS_FP32_PRECOND;
+  I.max_cycles = max_cycles;
+  I.s = stream;
+  I.slots.resize(reqs.size());
+  for (size_t i = 0; i < reqs.size(); ++i) {
+    I.slots[i].req = reqs[i];
+    I.slots[i].plan = reqs[i].plan;
+  }
+  I.build();
+}
+
+Engine::~Engine() = default;
+
+size_t Engine::bytes_per_problem(const fds_plan* p, int m, int precision) {
+  return layout_of(p, m, precision).total + sizeof(ProbState);
+}
+
+void Engine::setup() {
+  Impl& I = *impl_;
+  hipStream_t s = I.s;
+  FDS_HIP(hipMemcpyAsync(I.states.get(), I.host_states.data(), sizeof(ProbState) * I.slots.size(),
+                         hipMemcpyHostToDevice, s));
+  Timing::begin(5, s);
+  launch_lift(0, I.lift.dev(), I.lift.n(), I.lift.nblocks, s);
+  Timing::end(5, s);
+  if (I.arm_fwd.n()) {
+    Timing::begin(0, s);
+    launch_dst(DstKind::D_D, I.arm_fwd.dev(), I.arm_fwd.n(), I.arm_fwd.nblocks, I.arm_fwd.smem, 0, s);
+    Timing::end(0, s);
+    Timing::begin(1, s);
+    launch_tridiag(false, I.arm_tri.dev(), I.arm_tri.n(), I.arm_tri.nblocks, 0, s);
+    Timing::end(1, s);
+    Timing::begin(0, s);
+    launch_dst(DstKind::D_D, I.arm_inv.dev(), I.arm_inv.n(), I.arm_inv.nblocks, I.arm_inv.smem, 0, s);
+    Timing::end(0, s);
+  }
+  for (Slot& sl : I.slots) {
+    const long long coff = sl.plan->rd[sl.plan->centre].off;
+    FDS_HIP(hipMemcpyAsync(sl.fp, sl.b_int + coff, 8 * sl.Nc, hipMemcpyDeviceToDevice, s));
+  }
+  launch_iface(I.iface_fp.dev(), I.iface_fp.n(), s);
+  for (Slot& sl : I.slots) {
+    const long long coff = sl.plan->rd[sl.plan->centre].off;
+    FDS_HIP(hipMemsetAsync(sl.x_int + coff, 0, 8 * sl.Nc, s));
+  }
+  if (I.x_lines.n()) launch_lines(I.x_lines.dev(), I.x_lines.n(), I.smem_lines, 0, s);
+  launch_operator(1, I.res_op.dev(), I.res_op.n(), I.res_op.nblocks, 0, s);
+  launch_restart(I.kry.dev(), I.kry.n(), I.kry.nblocks, 1, I.max_cycles, s);
+  FDS_HIP(hipGetLastError());
+  I.read_states();
+  I.set_up = true;
+}
+
+bool Engine::step_cycle() {
+  Impl& I = *impl_;
+  bool any = false;
+  for (const ProbState& st : I.host_states) any |= !st.finished;
+  if (!any) return false;
+  hipStream_t s = I.s;
+  for (int j = 0; j < I.m; ++j) {
+    if (j >= 2) {
+      if (hipEventQuery(I.events[j - 2]) == hipSuccess && I.active_host[j - 2] == 0) break;
+    }
+    I.iteration(j);
+    launch_count_active(I.states.as<ProbState>(), (int)I.slots.size(), I.active_dev.as<int>() + j, s);
+    FDS_HIP(hipMemcpyAsync(I.active_host + j, I.active_dev.as<int>() + j, sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+    FDS_HIP(hipEventRecord(I.events[j], s));
+  }
+  I.end_of_cycle();
+  I.read_states();
+  for (const ProbState& st : I.host_states) if (!st.finished) return true;
+  return false;
+}
+
+std::vector<SolveOutcome> Engine::finalize() {
+  Impl& I = *impl_;
+  hipStream_t s = I.s;
+  for (Slot& sl : I.slots) {
+    const long long coff = sl.plan->rd[sl.plan->centre].off;
+    const long long rest = sl.Nint - sl.Nc;
+    if (rest > 0) {
+      // arms follow the centre in the internal layout
+      FDS_HIP(hipMemcpyAsync(sl.x_int + coff + sl.Nc, sl.b_int + coff + sl.Nc, 8 * rest,
+                             hipMemcpyDeviceToDevice, s));
+    }
+  }
+  launch_iface(I.iface_bs.dev(), I.iface_bs.n(), s);
+  if (I.bs_fwd.n()) {
+    Timing::begin(0, s);
+    launch_dst(DstKind::D_D, I.bs_fwd.dev(), I.bs_fwd.n(), I.bs_fwd.nblocks, I.bs_fwd.smem, 0, s);
+    Timing::end(0, s);
+    Timing::begin(1, s);
+    launch_tridiag(false, I.arm_tri.dev(), I.arm_tri.n(), I.arm_tri.nblocks, 0, s);
+    Timing::end(1, s);
+    Timing::begin(0, s);
+    launch_dst(DstKind::D_D, I.arm_inv.dev(), I.arm_inv.n(), I.arm_inv.nblocks, I.arm_inv.smem, 0, s);
+    Timing::end(0, s);
+  }
+  launch_lift(1, I.gather.dev(), I.gather.n(), I.gather.nblocks, s);
+  launch_residual(I.resid.dev(), I.resid.n(), I.resid.nblocks, s);
+  FDS_HIP(hipGetLastError());
+  std::vector<std::vector<double>> parts(I.slots.size());
+  for (size_t i = 0; i < I.slots.size(); ++i) {
+    parts[i].resize(2 * I.slots[i].res_blocks);
+    FDS_HIP(hipMemcpyAsync(parts[i].data(), I.slots[i].respart, 8 * parts[i].size(),
+                           hipMemcpyDeviceToHost, s));
+  }
+  I.read_states();
+  std::vector<SolveOutcome> out(I.slots.size());
+  for (size_t i = 0; i < I.slots.size(); ++i) {
+    const ProbState& st = I.host_states[i];
+    const Slot& sl = I.slots[i];
+    double rr = 0, bb = 0;
+    int off = 0;
+    // partials are laid out rectangle by rectangle: [r^2 (nb) | b^2 (nb)]
+    for (size_t r = 0; r < sl.plan->rd.size(); ++r) {
+      const RectDev& d = sl.plan->rd[r];
+      const int nb = std::max(1, div_up((long long)d.rows * d.cols, (long long)kBlock * 8));
+      for (int b = 0; b < nb; ++b) rr += parts[i][2 * off + b];
+      for (int b = 0; b < nb; ++b) bb += parts[i][2 * off + nb + b];
+      off += nb;
+    }
+    SolveOutcome& o = out[i];
+    o.res.iterations = st.iterations;
+    o.res.cycles = st.cycles;
+    o.res.stop_reason = st.stop_reason;
+    o.res.relres_schur = st.fnorm > 0 ? st.beta / st.fnorm : 0.0;
+    o.res.relres_global = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+    o.res.seconds = 0;
+    if (st.nonfinite) o.status = FDS_E_NONFINITE;
+    else if (!st.finished) { o.status = FDS_E_NOT_CONVERGED; o.res.stop_reason = FDS_STOP_MAX_CYCLES; }
+    else if (st.stop_reason == FDS_STOP_TOL || st.stop_reason == FDS_STOP_AT_FLOOR) o.status = FDS_OK;
+    else o.status = FDS_E_NOT_CONVERGED;
+    o.res.status = o.status;
+  }
+  return out;
+}
+
+std::vector<SolveOutcome> Engine::run() {
+  auto t0 = std::chrono::steady_clock::now();
+  setup();
+  int cyc = 0;
+  while (step_cycle()) {
+    if (++cyc > impl_->max_cycles + 2) break;
+  }
+  std::vector<SolveOutcome> out = finalize();
+  const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (auto& o : out) o.res.seconds = sec;
+  return out;
+}
+
+}  // namespace fds

@@ -1,0 +1,221 @@
+// Internal types shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/fds.h"
+
+namespace fds {
+
+constexpr int kMaxPass = 24;     // radix passes of one FFT plan
+constexpr int kBlock = 256;      // threads per block for most kernels
+constexpr int kMaxArms = 4;
+constexpr int kVecEPT = 8;       // centre-vector elements per thread in reduction kernels
+constexpr int kVecPerBlock = kBlock * kVecEPT;
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  fds_status status;
+  Error(fds_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define FDS_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::fds::Error(e_ == hipErrorOutOfMemory ? FDS_E_NOMEM : FDS_E_DEVICE,       \
+                         std::string(#call) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+// ---------------------------------------------------------------- FFT plan
+// Complex FFT of length N = n + 1 used to evaluate the DST-I of length n.
+struct FftDesc {
+  int N;
+  int npass;
+  int radix[kMaxPass];
+  const double2* tw64;    // N entries  exp(-2 pi i t / N)
+  const float2* tw32;
+  const double2* post64;  // N+1 entries (cos(pi k / N), sin(pi k / N))
+  const float2* post32;
+};
+
+// Per-mode coefficients of the constant-coefficient tridiagonal solve
+//   delta y[i-1] + a y[i] + delta y[i+1] = s r[i],  a = -delta (q + 1/q),
+// written as -(delta/q) (L U + q^2 e1 e1^T) y = s r with L = I - qZ,
+// U = I - qZ^T (Sherman-Morrison correction of the first row).
+template <typename T>
+struct ModeCoef {
+  T q;      // exp(-theta), cosh(theta) = -a/(2 delta)
+  T qinv;   // 1/q
+  T sc;     // -(q/delta) * s   (s = the DST normalisation 2/(n+1))
+  T beta;   // q^2 / (1 + q^2 (1 - q^{2m})/(1 - q^2))
+  T qK;     // q^K
+  int K;    // largest exponent kept before q^K would underflow (<= m-1)
+};
+
+// ---------------------------------------------------------------- problem state
+struct ProbState {
+  int cycle_done;   // remaining Arnoldi steps of this cycle are skipped
+  int finished;     // everything is skipped
+  int j_done;       // Arnoldi steps completed in the current cycle
+  int stop_reason;  // fds_stop_reason
+  int iterations;
+  int cycles;
+  int nonfinite;
+  int pad;
+  double beta;      // true residual norm at the start of the current cycle
+  double fnorm;     // ||f'_c||_2
+  double tol;
+  double tol_eff;
+  double prev_rel;
+  double xnorm;
+  double floor_coef;   // unit roundoff times a bound of ||L_c||_inf
+  double last_hn;      // h_{j+1,j} of the latest Arnoldi step
+};
+
+// ---------------------------------------------------------------- task records
+// One record per independent piece of work; blocks map to records through
+// block_begin (sorted ascending).
+struct DstTask {
+  const void* in;
+  void* out;
+  long long in_rs, out_rs;    // row strides (elements)
+  long long in_js, out_js;    // added once per Krylov index j
+  long long in_cs, out_cs;    // element stride along a row
+  int rows, n;
+  int rpb;                    // rows per block
+  int accumulate;             // out += result
+  double scale;
+  const FftDesc* fft;
+  const int* skip;            // skip when *skip != 0
+  int block_begin;
+  int pad;
+};
+
+struct TriTask {
+  void* data;
+  long long rs, js;
+  int rows, modes;
+  const void* coef;           // ModeCoef<T>[modes]
+  const int* skip;
+  int block_begin;
+  int pad;
+};
+
+// Schur line term: out[k] = sum_l Sline(k,l) z_line[l] with
+// Sline = delta^2 (2/N) S diag(g) S on one boundary line of the centre.
+struct LineTask {
+  const void* z;              // centre vector (FP64, or FP32 if z_f32)
+  long long z_js;
+  long long start;            // first element of the line
+  long long stride;           // element stride along the line
+  int L;
+  int z_f32;
+  const FftDesc* fft;
+  const double* gs;           // delta^2 (2/N) g_k, k = 1..L
+  double* out;                // L doubles
+  const int* skip;
+};
+
+// Centre operator w = A_c z - sum_a S_ca z  (mode 0), or the residual
+// r = f' - L_c z with partial sums of r^2 and z^2 (mode 1).
+struct OpTask {
+  const void* z;
+  long long z_js;
+  int z_f32;
+  int nx, ny;
+  int nblocks;
+  double* out;
+  long long out_js;
+  const double* fp;
+  const double* line[4];      // S (row 0), N (row ny-1), W (col 0), E (col nx-1); NULL if none
+  double delta, kappa;
+  double* partials;           // mode 1: [2 * nblocks]
+  const int* skip;
+  int block_begin;
+  int pad;
+};
+
+// Krylov bookkeeping of one problem.
+struct KryTask {
+  double* V;                  // (m+1) x Nc
+  float* Z;                   // m x Nc (flexible variant) or NULL
+  double* x;                  // centre solution (Nc)
+  double* u;                  // scratch centre vector (Nc)
+  double* H;                  // (m+1) x m, column-major (H[i + j (m+1)])
+  double* cs;
+  double* sn;
+  double* g;                  // m+1
+  double* y;                  // m
+  double* partials;           // 4 x P: MGS ping-pong (2P), residual r^2 and x^2 (2P)
+  ProbState* st;
+  long long Nc;
+  int P;                      // blocks covering Nc
+  int m;
+  int block_begin;
+  int pad;
+};
+
+// Rectangle of a problem in the library's internal layout: rows x cols with
+// the sine-transform axis (cols) contiguous.  Global node of element (r, c):
+//   i = ai + ar r + ac c,  j = aj + br r + bc c.
+struct RectDev {
+  int rows, cols;
+  long long off;              // into the internal vectors
+  long long user_off;         // into the user unknown vector
+  long long bc_off;           // into the user Dirichlet-data vector
+  int ai, ar, ac, aj, br, bcc;
+  int ilo, jlo, uwidth;       // user block origin (global node) and width
+  int bi0, bj0, bi1, bj1;     // closed box
+  int iface_mask;             // box sides whose interior nodes are unknowns:
+                              // 1: i=bi0, 2: i=bi1, 4: j=bj0, 8: j=bj1
+  // neighbour lines across internal sides: 0: r=-1, 1: r=rows, 2: c=-1, 3: c=cols
+  long long halo_off[4];      // -1 if Dirichlet
+  long long halo_stride[4];
+};
+
+struct LiftTask {
+  RectDev rd;
+  const double* rhs;          // user unknown vector
+  const double* bc;           // user Dirichlet data (NULL = zero)
+  double* out;                // internal vector base
+  double* xuser;              // gather-out target
+  const double* xint;         // gather-out source base
+  double delta, kappa;
+  int block_begin;
+  int nblocks;
+};
+
+// Composite residual b - A p over one rectangle (internal layout); halo
+// lines read neighbouring rectangles of the same internal vector.
+struct ResTask {
+  RectDev rd;
+  const double* p;            // internal vector base
+  const double* b;
+  double delta, kappa;
+  double* partials;           // [2 * nblocks]: sum r^2, sum b^2
+  int block_begin;
+  int nblocks;
+};
+
+// Interface right-hand side updates between the centre and its arms of one
+// problem, applied line after line by one block (lines of two arms share the
+// centre's corner node):
+//   f'_c formation:     fp[line_a] -= delta * q_a[row 0]
+//   back substitution:  b_a[row 0] -= delta * x_c[line_a]
+struct IfaceTask {
+  double* dst[kMaxArms];
+  const double* src[kMaxArms];
+  long long dst_start[kMaxArms], dst_stride[kMaxArms];
+  long long src_start[kMaxArms], src_stride[kMaxArms];
+  int L[kMaxArms];
+  int nlines;
+  int pad;
+  double delta;
+};
+
+}  // namespace fds

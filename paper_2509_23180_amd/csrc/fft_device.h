@@ -1,0 +1,248 @@
+// Device-side sine transform (DST-I) built on an LDS-resident mixed-radix
+// Stockham FFT.  Shared by the row-transform kernel and the Schur line kernel.
+//
+// DST-I of length n (paper Section 2.1: the sine eigenvectors of the
+// Dirichlet line matrix; the transform is evaluated through an FFT):
+//   X_k = sum_{j=1..n} x_j sin(pi j k / N),  N = n + 1,  k = 1..n.
+// With z the odd extension of x to length 2N (z_0 = z_N = 0, z_j = x_j,
+// z_{2N-j} = -x_j) the length-2N DFT satisfies Z_k = -2i X_k.  The real
+// length-2N DFT is obtained from one complex FFT of length N of
+// c_t = z_{2t} + i z_{2t+1}:  Z_k = (A + B)/2 - (i/2) W^k (A - B),
+// A = C_k, B = conj(C_{N-k}), W = exp(-i pi/N).  Hence
+//   X_k = -(1/4) [ Im(A + B) - (cos(pi k/N) Re(A-B) + sin(pi k/N) Im(A-B)) ].
+#pragma once
+
+#include "fds_internal.h"
+
+namespace fds {
+
+template <typename T> struct cx;
+template <> struct cx<double> { using t = double2; };
+template <> struct cx<float> { using t = float2; };
+template <typename T> using C2 = typename cx<T>::t;
+
+template <typename T> __device__ __forceinline__ const C2<T>* fft_tw(const FftDesc& f);
+template <> __device__ __forceinline__ const double2* fft_tw<double>(const FftDesc& f) { return f.tw64; }
+template <> __device__ __forceinline__ const float2* fft_tw<float>(const FftDesc& f) { return f.tw32; }
+template <typename T> __device__ __forceinline__ const C2<T>* fft_post(const FftDesc& f);
+template <> __device__ __forceinline__ const double2* fft_post<double>(const FftDesc& f) { return f.post64; }
+template <> __device__ __forceinline__ const float2* fft_post<float>(const FftDesc& f) { return f.post32; }
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C, typename T> __device__ __forceinline__ C cscale(C a, T s) { return C{a.x * s, a.y * s}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// multiply by -i and +i
+template <typename C> __device__ __forceinline__ C cmi(C a) { return C{a.y, -a.x}; }
+template <typename C> __device__ __forceinline__ C cpi(C a) { return C{-a.y, a.x}; }
+
+// ---------------------------------------------------------------- small DFTs
+// Forward DFTs (kernel exp(-2 pi i jk/R)) of fixed small sizes.
+template <typename T, typename C> __device__ __forceinline__ void dft2(C* v) {
+  C a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <typename T, typename C> __device__ __forceinline__ void dft3(C* v) {
+  const T s = T(0.866025403784438646763723170752936183);  // sin(2 pi/3)
+  C t1 = cadd(v[1], v[2]);
+  C t2 = csub(v[0], cscale(t1, T(0.5)));
+  C d = cscale(csub(v[1], v[2]), s);
+  v[0] = cadd(v[0], t1);
+  v[1] = cadd(t2, cmi(d));
+  v[2] = cadd(t2, cpi(d));
+}
+
+template <typename T, typename C> __device__ __forceinline__ void dft4(C* v) {
+  C a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+  C c = cadd(v[1], v[3]), d = csub(v[1], v[3]);
+  v[0] = cadd(a, c);
+  v[2] = csub(a, c);
+  v[1] = cadd(b, cmi(d));
+  v[3] = cadd(b, cpi(d));
+}
+
+template <typename T, typename C> __device__ __forceinline__ void dft5(C* v) {
+  const T c1 = T(0.309016994374947424102293417182819059);   // cos(2 pi/5)
+  const T c2 = T(-0.809016994374947424102293417182819059);  // cos(4 pi/5)
+  const T s1 = T(0.951056516295153572116439333379382143);   // sin(2 pi/5)
+  const T s2 = T(0.587785252292473129168705954639072769);   // sin(4 pi/5)
+  C a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+  C a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+  C x0 = v[0];
+  C r1 = cadd(x0, cadd(cscale(a1, c1), cscale(a2, c2)));
+  C r2 = cadd(x0, cadd(cscale(a1, c2), cscale(a2, c1)));
+  C i1 = cadd(cscale(b1, s1), cscale(b2, s2));
+  C i2 = csub(cscale(b1, s2), cscale(b2, s1));
+  v[0] = cadd(x0, cadd(a1, a2));
+  v[1] = cadd(r1, cmi(i1));
+  v[4] = cadd(r1, cpi(i1));
+  v[2] = cadd(r2, cmi(i2));
+  v[3] = cadd(r2, cpi(i2));
+}
+
+template <int R, typename T, typename C> __device__ __forceinline__ void dftR(C* v) {
+  if constexpr (R == 2) dft2<T>(v);
+  else if constexpr (R == 3) dft3<T>(v);
+  else if constexpr (R == 4) dft4<T>(v);
+  else dft5<T>(v);
+}
+
+// One Stockham pass of fixed radix R over a row group of G threads.
+//   Ns: product of the radices already applied; stw = N/(Ns R).
+template <int R, typename T>
+__device__ __forceinline__ void stockham_pass(const C2<T>* __restrict__ src, C2<T>* __restrict__ dst,
+                                              const C2<T>* __restrict__ tw, int N, int Ns, int g,
+                                              int G) {
+  using C = C2<T>;
+  const int NR = N / R;
+  const int stw = N / (Ns * R);
+  for (int j = g; j < NR; j += G) {
+    const int k = j % Ns;
+    C v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[j + r * NR];
+    if (k != 0) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * k * stw]);
+    }
+    dftR<R, T>(v);
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+  }
+}
+
+// Generic radix (any R dividing N): every output is a length-R sum whose
+// combined twiddle index is r (k stw + q N/R) mod N.
+template <typename T>
+__device__ __forceinline__ void generic_pass(const C2<T>* __restrict__ src, C2<T>* __restrict__ dst,
+                                             const C2<T>* __restrict__ tw, int N, int Ns, int R,
+                                             int g, int G) {
+  using C = C2<T>;
+  const int NR = N / R;
+  const int stw = N / (Ns * R);
+  for (int o = g; o < N; o += G) {
+    const int k = o % Ns;
+    const int q = (o / Ns) % R;
+    const int jb = o / (Ns * R);
+    const int j = jb * Ns + k;
+    const int step = (k * stw + q * NR) % N;
+    int idx = 0;
+    C acc = C{T(0), T(0)};
+    for (int r = 0; r < R; ++r) {
+      const C a = src[j + r * NR];
+      const C w = tw[idx];
+      acc.x += a.x * w.x - a.y * w.y;
+      acc.y += a.x * w.y + a.y * w.x;
+      idx += step;
+      if (idx >= N) idx -= N;
+    }
+    dst[o] = acc;
+  }
+}
+
+// Full complex FFT of length f.N held in LDS buffer `a` (scratch `b`), row
+// group of G threads, g = rank in the group.  Every group of the block must
+// call this with the same plan (block-wide barriers).  Returns the buffer
+// holding the result.
+template <typename T>
+__device__ C2<T>* fft_lds(C2<T>* a, C2<T>* b, const FftDesc& f, int g, int G) {
+  const C2<T>* tw = fft_tw<T>(f);
+  const int N = f.N;
+  int Ns = 1;
+  C2<T>* src = a;
+  C2<T>* dst = b;
+  for (int p = 0; p < f.npass; ++p) {
+    const int R = f.radix[p];
+    switch (R) {
+      case 2: stockham_pass<2, T>(src, dst, tw, N, Ns, g, G); break;
+      case 3: stockham_pass<3, T>(src, dst, tw, N, Ns, g, G); break;
+      case 4: stockham_pass<4, T>(src, dst, tw, N, Ns, g, G); break;
+      case 5: stockham_pass<5, T>(src, dst, tw, N, Ns, g, G); break;
+      default: generic_pass<T>(src, dst, tw, N, Ns, R, g, G); break;
+    }
+    __syncthreads();
+    C2<T>* t = src;
+    src = dst;
+    dst = t;
+    Ns *= R;
+  }
+  return src;
+}
+
+// Pack the odd extension of a real row into c_t = z_{2t} + i z_{2t+1}.
+// `load(j)` returns x_j for 1 <= j <= n.
+template <typename T, typename Load>
+__device__ __forceinline__ void dst_pack(C2<T>* a, int N, int g, int G, Load load) {
+  for (int t = g; t < N; t += G) {
+    T v[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = 2 * t + h;
+      T z = T(0);
+      if (j > 0 && j < N) z = load(j);
+      else if (j > N) z = -load(2 * N - j);
+      v[h] = z;
+    }
+    a[t] = C2<T>{v[0], v[1]};
+  }
+}
+
+// X_k from the complex FFT result C (k = 1..N-1).
+template <typename T>
+__device__ __forceinline__ T dst_post(const C2<T>* C, const C2<T>* post, int N, int k) {
+  const C2<T> A = C[k];
+  const C2<T> Bc = C[N - k];
+  const C2<T> w = post[k];
+  const T imsum = A.y - Bc.y;
+  const T dre = A.x - Bc.x;
+  const T dim = A.y + Bc.y;
+  return T(-0.25) * (imsum - (w.x * dre + w.y * dim));
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over a block of kBlock threads; every thread receives the same bits.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  const double r = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return r;
+}
+
+// Fixed-order sum of P partials (identical result in every block).
+__device__ __forceinline__ double sum_partials(const double* p, int P, double* red) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < P; i += kBlock) acc += p[i];
+  return block_sum(acc, red);
+}
+
+template <typename Task>
+__device__ __forceinline__ int find_task(const Task* tasks, int ntasks, int* slot) {
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = ntasks - 1;
+    const int b = blockIdx.x;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tasks[mid].block_begin <= b) lo = mid;
+      else hi = mid - 1;
+    }
+    *slot = lo;
+  }
+  __syncthreads();
+  return *slot;
+}
+
+}  // namespace fds

@@ -1,0 +1,31 @@
+// Launch wrappers of the HIP kernels (defined in kernels.hip).
+#pragma once
+
+#include "fds_internal.h"
+
+namespace fds {
+
+// Arithmetic / storage combination of a row sine transform:
+// D_D: FP64 in, FP64 math, FP64 out;  D_F: FP64 in, FP32 math/out;
+// F_F: FP32 throughout;               F_D: FP32 in/math, FP64 out.
+enum class DstKind { D_D, D_F, F_F, F_D };
+
+void launch_dst(DstKind kind, const DstTask* tasks, int ntasks, int nblocks, size_t smem, int jidx,
+                hipStream_t s);
+void launch_tridiag(bool fp32, const TriTask* tasks, int ntasks, int nblocks, int jidx,
+                    hipStream_t s);
+void launch_lines(const LineTask* tasks, int ntasks, size_t smem, int jidx, hipStream_t s);
+void launch_operator(int mode, const OpTask* tasks, int ntasks, int nblocks, int jidx,
+                     hipStream_t s);
+void launch_mgs_pass(const KryTask* tasks, int ntasks, int nblocks, int i, int j, hipStream_t s);
+void launch_mgs_finish(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s);
+void launch_ls_solve(const KryTask* tasks, int ntasks, hipStream_t s);
+void launch_combine(bool flex, const KryTask* tasks, int ntasks, int nblocks, hipStream_t s);
+void launch_restart(const KryTask* tasks, int ntasks, int nblocks, int initial, int max_cycles,
+                    hipStream_t s);
+void launch_lift(int mode, const LiftTask* tasks, int ntasks, int nblocks, hipStream_t s);
+void launch_iface(const IfaceTask* tasks, int ntasks, hipStream_t s);
+void launch_residual(const ResTask* tasks, int ntasks, int nblocks, hipStream_t s);
+void launch_count_active(const ProbState* st, int n, int* out, hipStream_t s);
+
+}  // namespace fds

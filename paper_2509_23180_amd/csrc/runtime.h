@@ -1,0 +1,184 @@
+// Host runtime: device buffers, shared tables, plans and the batched engine.
+#pragma once
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "fds_internal.h"
+#include "kernels.h"
+
+namespace fds {
+
+// ---------------------------------------------------------------- device buffer
+class DevBuf {
+ public:
+  DevBuf() = default;
+  explicit DevBuf(size_t bytes) { alloc(bytes); }
+  ~DevBuf() { release(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p_ = o.p_; n_ = o.n_; o.p_ = nullptr; o.n_ = 0; }
+    return *this;
+  }
+  void alloc(size_t bytes) {
+    release();
+    if (bytes) FDS_HIP(hipMalloc(&p_, bytes));
+    n_ = bytes;
+  }
+  void release() {
+    if (p_) (void)hipFree(p_);
+    p_ = nullptr;
+    n_ = 0;
+  }
+  template <typename T> T* as(size_t byte_off = 0) const {
+    return reinterpret_cast<T*>(static_cast<char*>(p_) + byte_off);
+  }
+  void* get() const { return p_; }
+  size_t size() const { return n_; }
+
+ private:
+  void* p_ = nullptr;
+  size_t n_ = 0;
+};
+
+// ---------------------------------------------------------------- shared tables
+struct FftTable {           // one transform length
+  DevBuf mem;
+  FftDesc host;             // with device pointers filled in
+  const FftDesc* dev;       // device copy of `host`
+};
+
+struct ModeTable {          // per-mode tridiagonal coefficients, FP64 and FP32
+  DevBuf mem;
+  const ModeCoef<double>* c64;
+  const ModeCoef<float>* c32;
+};
+
+struct GsTable {            // Schur line coefficients delta^2 (2/N) g_k
+  DevBuf mem;
+  const double* gs;
+};
+
+// Process-wide cache of device tables (per device), keyed by length and by
+// (length, rows, h, kappa).  Entries live until process exit.
+class TableCache {
+ public:
+  static TableCache& get();
+  std::shared_ptr<FftTable> fft(int n);
+  std::shared_ptr<ModeTable> modes(int n, int m, double h, double kappa);
+  std::shared_ptr<GsTable> gs(int n, int m, double h, double kappa);
+
+ private:
+  std::mutex mu_;
+  std::map<std::pair<int, int>, std::shared_ptr<FftTable>> fft_;
+  std::map<std::tuple<int, int, int, double, double>, std::shared_ptr<ModeTable>> modes_;
+  std::map<std::tuple<int, int, int, double, double>, std::shared_ptr<GsTable>> gs_;
+};
+
+// Per-mode coefficients for `n` modes of an m-row tridiagonal system whose
+// right-hand side is multiplied by `scale`.
+void mode_coefs_host(int n, int m, double h, double kappa, double scale,
+                     std::vector<ModeCoef<double>>& c64, std::vector<ModeCoef<float>>& c32);
+std::shared_ptr<ModeTable> upload_modes(const std::vector<ModeCoef<double>>& c64,
+                                        const std::vector<ModeCoef<float>>& c32);
+
+// Radix schedule of a complex FFT of length N (4s, 2s, 3s, 5s, then other
+// primes ascending).
+std::vector<int> fft_radices(int N);
+// Threads per row for a transform of length n (power of two, 32..256).
+int dst_threads_per_row(int n);
+size_t dst_smem_bytes(int n, bool fp32);
+
+// ---------------------------------------------------------------- plan
+enum RectKind { RK_CENTRE = 0, RK_N = 1, RK_S = 2, RK_E = 3, RK_W = 4 };
+// centre boundary line fed by an arm: 0 S (row 0), 1 N (row ny-1), 2 W (col 0), 3 E (col nx-1)
+int line_of_kind(int kind);
+
+struct ArmInfo {
+  int rect;                  // index in plan order
+  int kind;
+  int line;                  // centre line id
+  int L;                     // line length (= arm cols)
+  int rows;                  // arm rows (Thomas length, interface row first)
+  std::shared_ptr<FftTable> fft;
+  std::shared_ptr<ModeTable> modes;
+  std::shared_ptr<GsTable> gs;
+};
+
+}  // namespace fds
+
+struct fds_plan {
+  int device = 0;
+  std::vector<fds_rect> rects;
+  std::vector<fds::RectDev> rd;      // per rect (user order); off relative to a problem
+  std::vector<int> kind;
+  int centre = 0;
+  std::vector<fds::ArmInfo> arms;
+  double h = 0, delta = 0, kappa = 0;
+  fds_options opt{};
+  int nx = 0, ny = 0;
+  long long n_unknowns = 0, bc_total = 0, n_internal = 0;
+  std::vector<long long> user_off, bc_off;
+  std::shared_ptr<fds::FftTable> fft_c;
+  std::shared_ptr<fds::ModeTable> modes_c;
+  double floor_coef = 0;
+  size_t footprint(int m, int precision) const;
+};
+
+namespace fds {
+
+fds_plan* create_plan(const fds_rect* rects, int nrect, double h, double kappa,
+                      const fds_options* opt);
+
+// ---------------------------------------------------------------- engine
+struct SolveRequest {
+  fds_plan* plan;
+  const double* rhs;
+  const double* bc;
+  double* x;
+  double tol;
+};
+
+struct SolveOutcome {
+  fds_status status;
+  fds_result res;
+};
+
+// Batched right-preconditioned GMRES(m) / FGMRES(m): every kernel of an
+// Arnoldi step serves all unfinished problems of the batch in one launch.
+class Engine {
+ public:
+  Engine(const std::vector<SolveRequest>& reqs, int m, int precision, int max_cycles,
+         hipStream_t stream);
+  ~Engine();
+  // Runs setup, cycles and finalisation; blocks until done.
+  std::vector<SolveOutcome> run();
+
+  // Incremental interface used by the server: setup() then step_cycle()
+  // until done(), then finalize().
+  void setup();
+  bool step_cycle();                 // false once every problem finished
+  std::vector<SolveOutcome> finalize();
+  static size_t bytes_per_problem(const fds_plan* p, int m, int precision);
+
+ private:
+  struct Impl;
+  std::unique_ptr<Impl> impl_;
+};
+
+// Thread-local timing by kernel class (see fds_timing_*).
+struct Timing {
+  static void enable(bool on);
+  static bool on();
+  static void begin(int cls, hipStream_t s);
+  static void end(int cls, hipStream_t s);
+  static void read(int cls, long long* calls, double* ms);
+  static void reset();
+};
+
+}  // namespace fds

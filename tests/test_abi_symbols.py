@@ -1,0 +1,62 @@
+"""The C-ABI library loads without a GPU and exports every entry point that
+include/fds.h declares (no compute calls)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fds.h")
+LIB = os.path.join(ROOT, "paper_2509_23180_amd", "libfds.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(fds_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("fds_plan_create", "fds_solve", "fds_solve_batch", "fds_batch_submit",
+                     "fds_batch_poll", "fds_k_dst_rows", "fds_k_tridiag_modes",
+                     "fds_k_centre_operator", "fds_k_arnoldi_mgs"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_symbol_table_matches_header():
+    import paper_2509_23180_amd as fds
+    assert sorted(fds.SYMBOLS) == declared_functions()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_status_strings_without_gpu():
+    import paper_2509_23180_amd as fds
+    lib = fds.load_library()
+    assert lib.fds_status_str(0) == b"ok"
+    assert lib.fds_status_str(-6) == b"not converged"
+
+
+def test_host_layout_packing_matches_oracle_layout():
+    """The package's packer and the oracle's independently written layout
+    agree (host logic only)."""
+    import numpy as np
+    import workloads
+    from oracle import layout as olayout
+    from paper_2509_23180_amd import layout as playout
+    for shape in ("cross", "L", "T", "pair", "square"):
+        rects = workloads.shape_rects(shape, 5)
+        g = np.random.default_rng(1).normal(size=(19, 19))
+        assert np.array_equal(playout.pack_unknowns(rects, g), olayout.to_user(rects, g))
+        assert np.array_equal(playout.pack_boxes(rects, g), olayout.bc_boxes(rects, g))

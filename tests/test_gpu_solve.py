@@ -1,0 +1,193 @@
+"""Whole-solve parity with the FP64 oracle (global composite direct solve),
+error paths, batching and serving."""
+
+import numpy as np
+import pytest
+
+import workloads
+from tests.gpu_util import compare, device_problem, log, oracle_solution
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _fds():
+    import paper_2509_23180_amd as fds
+    return fds
+
+
+CASES_SMALL = [
+    ("cross", 32, 0.0, "manufactured"),
+    ("cross", 32, 0.0, "shifted"),
+    ("cross", 32, -50.0, "gauss"),
+    ("L", 32, 0.0, "shifted"),
+    ("T", 33, -50.0, "gauss"),
+    ("pair", 20, -3.0, "shifted"),
+    ("square", 17, 0.0, "shifted"),
+    ("cross", 1, 0.0, "shifted"),
+    ("cross", 2, -1.0, "gauss"),
+    ("T", 7, 0.0, "gauss"),
+    ("cross", 31, -100.0, "gauss"),
+]
+
+
+def _problem(shape, n, kappa, kind, seed=0):
+    if kind == "manufactured":
+        return workloads.manufactured_problem(shape, n, kappa)
+    if kind == "shifted":
+        return workloads.manufactured_problem(shape, n, kappa, shifted=True)
+    return workloads.gaussian_problem(shape, n, kappa, 1, seed, 0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("shape,n,kappa,kind", CASES_SMALL)
+def test_small_parity(shape, n, kappa, kind, precision):
+    fds = _fds()
+    log(f"solve {shape} n={n} kappa={kappa} {kind} prec={precision}")
+    prob = _problem(shape, n, kappa, kind)
+    ref = oracle_solution(prob)
+    plan, rhs, bc, x = device_problem(prob, restart_m=30, precision=precision)
+    res = fds.solve(plan, rhs, x, 1e-12, bc=bc)
+    assert res.status == 0, res
+    err = compare(prob, x, ref)
+    log(f"  its={res.iterations} cycles={res.cycles} err={err:.3e} relres={res.relres_schur:.2e} "
+        f"global={res.relres_global:.2e}")
+    assert err <= 1e-10
+    assert res.relres_schur <= 1e-12
+    assert res.relres_global <= 1e-11
+
+
+@pytest.mark.parametrize("kappa,kind", [(0.0, "manufactured"), (-50.0, "gauss")])
+def test_full_size_plain_fp64(kappa, kind):
+    """The plain method at its full size: cross, 256x256 per square."""
+    fds = _fds()
+    log(f"full-size n=256 kappa={kappa} {kind}")
+    prob = _problem("cross", 256, kappa, kind, seed=3)
+    ref = oracle_solution(prob, method="band")
+    plan, rhs, bc, x = device_problem(prob, restart_m=30)
+    res = fds.solve(plan, rhs, x, 1e-12, bc=bc)
+    err = compare(prob, x, ref)
+    log(f"  its={res.iterations} err={err:.3e} relres={res.relres_schur:.2e}")
+    assert res.status == 0
+    assert err <= 1e-10
+
+
+def test_solution_is_second_order():
+    """Manufactured solution through the whole GPU path: error falls 4x per
+    halving of h."""
+    fds = _fds()
+    errs = []
+    for N in (16, 32, 64):
+        prob = workloads.manufactured_problem("cross", N - 1, 0.0, shifted=True)
+        plan, rhs, bc, x = device_problem(prob)
+        res = fds.solve(plan, rhs, x, 1e-12, bc=bc)
+        assert res.status == 0
+        from oracle import layout as olayout, composite
+        g = composite.classify(prob.rects)
+        G = olayout.from_user(prob.rects, x.cpu().numpy(), (g.height, g.width))
+        m = g.unknown
+        errs.append(np.max(np.abs(G[m] - prob.p_exact[:g.height, :g.width][m])))
+    for a, b in zip(errs, errs[1:]):
+        assert 3.6 < a / b < 4.4, errs
+
+
+def test_geometry_errors():
+    fds = _fds()
+    N = 9
+    bad = [
+        [(0, 0, N, N), (N - 2, 0, 2 * N, N)],                       # overlap
+        [(N, N, 2 * N, 2 * N), (2 * N, N, 3 * N, 2 * N - 1)],        # partial side
+        # two coupled subdomains: the north-east square touches both arms
+        [(N, N, 2 * N, 2 * N), (N, 2 * N, 2 * N, 3 * N), (2 * N, N, 3 * N, 2 * N),
+         (2 * N, 2 * N, 3 * N, 3 * N)],
+        [(N, N, 2 * N, 2 * N), (2 * N, N, 3 * N, 2 * N), (2 * N, N - 1, 3 * N, N)],  # arm on arm
+        [(0, 0, 1, 5)],                                            # no interior node
+    ]
+    for rects in bad:
+        with pytest.raises(fds.FdsError) as ei:
+            fds.Plan(rects, 1.0 / N, 0.0)
+            assert ei.value.status == -2, rects
+
+
+def test_kappa_positive_paths():
+    fds = _fds()
+    n = 8
+    rects = workloads.shape_rects("cross", n)
+    h = 1.0 / (n + 1)
+    # small positive kappa keeps every mode diagonally dominant: accepted
+    fds.Plan(rects, h, 1.0)
+    # kappa equal to minus the smallest eigenvalue of a square: singular
+    lam = (2 * np.cos(np.pi * h) - 2) / h ** 2 * 2
+    with pytest.raises(fds.FdsError) as ei:
+        fds.Plan(rects, h, -lam)
+    assert ei.value.status == -4
+    # a larger kappa makes the lowest sine mode oscillatory
+    with pytest.raises(fds.FdsError) as ei:
+        fds.Plan(rects, h, -0.8 * lam)
+    assert ei.value.status == -3
+
+
+def test_nonfinite_and_not_converged():
+    fds = _fds()
+    prob = workloads.gaussian_problem("cross", 16, 0.0, 2, 0, 0)
+    plan, rhs, bc, x = device_problem(prob)
+    rhs[5] = float("nan")
+    res = fds.solve(plan, rhs, x, 1e-12, bc=bc)
+    assert res.status == -7
+    plan, rhs, bc, x = device_problem(prob, restart_m=2, max_cycles=1)
+    res = fds.solve(plan, rhs, x, 1e-12, bc=bc)
+    assert res.status == -6
+    assert res.cycles == 1 and res.iterations <= 2
+    assert np.all(np.isfinite(x.cpu().numpy()))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_matches_standalone(precision):
+    """Each problem of a mixed batch (shapes, sizes, kappa) gives the same
+    result as when solved alone."""
+    fds = _fds()
+    specs = [("cross", 24, 0.0, "gauss", 0), ("L", 40, -70.0, "gauss", 1), ("T", 9, -5.0, "shifted", 0),
+             ("cross", 64, -20.0, "gauss", 2), ("square", 30, 0.0, "gauss", 3)]
+    probs = [_problem(s, n, k, kind, seed) for (s, n, k, kind, seed) in specs]
+    alone = []
+    for p in probs:
+        plan, rhs, bc, x = device_problem(p, precision=precision)
+        r = fds.solve(plan, rhs, x, 1e-11, bc=bc)
+        assert r.status == 0
+        alone.append((x.clone(), r))
+    items = [device_problem(p, precision=precision) for p in probs]
+    res = fds.solve_batch([it[0] for it in items], [it[1] for it in items], [it[3] for it in items],
+                          [1e-11] * len(items), bcs=[it[2] for it in items])
+    for (x_alone, r_alone), it, r in zip(alone, items, res):
+        assert r.status == 0
+        assert r.iterations == r_alone.iterations
+        assert torch.equal(it[3], x_alone)
+    for p, it in zip(probs, items):
+        assert compare(p, it[3], oracle_solution(p)) <= 1e-9
+
+
+def test_server_results_match_direct():
+    fds = _fds()
+    probs = [_problem("cross", 20, 0.0, "gauss", s) for s in range(3)] + \
+            [_problem("L", 33, -10.0, "gauss", 5), _problem("T", 12, 0.0, "shifted", 0)]
+    srv = fds.Server(hbm_budget_bytes=1 << 30, max_slots=3)
+    items = [device_problem(p) for p in probs]
+    tickets = [srv.submit(it[0], it[1], it[3], 1e-11, bc=it[2]) for it in items]
+    import time
+    results = {}
+    t0 = time.time()
+    while len(results) < len(tickets) and time.time() - t0 < 60:
+        for t in tickets:
+            if t not in results:
+                r = srv.poll(t)
+                if r is not None:
+                    results[t] = r
+        time.sleep(0.002)
+    srv.close()
+    assert len(results) == len(tickets)
+    for p, it, t in zip(probs, items, tickets):
+        assert results[t].status == 0
+        plan, rhs, bc, x = device_problem(p)
+        fds.solve(plan, rhs, x, 1e-11, bc=bc)
+        assert torch.equal(x, it[3])
