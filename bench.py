@@ -1,0 +1,292 @@
+#!/usr/bin/env python3
+"""Benchmark of the FFT-preconditioned interface GMRES on one MI355X.
+
+Default workload (one "step" = one batched solve of all of it):
+  cross of five unit squares, 256x256 interior nodes per square
+  (328,704 unknowns per solve), plain method in FP64, GMRES(30),
+  relative residual 1e-10, kappa in {0, -50} x right-hand sides
+  {manufactured, 8 seeded sums of 16 Gaussians}: 18 solves per step.
+
+Prints ONE JSON line (solves/s, latency percentiles, roofline of the dominant
+kernel class, CPU oracle baseline).  Diagnostics go to stderr.
+
+Other workloads (--workload): "precision" (cross 1024x1024 per square,
+FGMRES(40) with an FP32 preconditioner), "batching" (64 composite problems x
+8 right-hand sides, sizes 64..512, FGMRES(40)).
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2509_23180_amd/csrc/kernels.hip", "paper_2509_23180_amd/csrc/fft_device.h",
+                  "paper_2509_23180_amd/csrc/fds_internal.h")
+# kernel class -> name of the HIP kernel that implements it (rocprofv3 summaries)
+CLASS_KERNEL = {"dst": "k_dst_rows", "tridiag": "k_tridiag", "operator": "k_operator",
+                "mgs": "k_mgs_pass", "lines": "k_schur_lines"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _r(v, d=3):
+    return None if v is None else round(v, d)
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[k]
+
+
+# --------------------------------------------------------------------------- workloads
+
+def build_workload(name, device):
+    """Returns (description dict, list of (plan_key, Problem)), plan kwargs."""
+    import workloads
+    items = []
+    if name == "plain":
+        for kappa in (0.0, -50.0):
+            items.append(workloads.manufactured_problem("cross", 256, kappa))
+            for seed in range(8):
+                items.append(workloads.gaussian_problem("cross", 256, kappa, 1, seed, 0))
+        desc = {"workload": "cross, 256x256 interior nodes per square (328,704 unknowns per solve), "
+                            "plain FP64 GMRES(30), rel-res 1e-10, kappa in {0,-50} x "
+                            "{manufactured, 8 seeded Gaussian} right-hand sides",
+                "solves_per_step": len(items), "n": 256, "restart_m": 30, "tol": 1e-10,
+                "precision": "fp64"}
+        opts = dict(restart_m=30, precision=0)
+    elif name == "precision":
+        items.append(workloads.manufactured_problem("cross", 1024, 0.0))
+        items.append(workloads.gaussian_problem("cross", 1024, 0.0, 2, 0, 0))
+        desc = {"workload": "cross, 1024x1024 interior nodes per square (5,246,976 unknowns per solve), "
+                            "FGMRES(40) with FP32 DST+tridiagonal preconditioner, FP64 Krylov, "
+                            "rel-res 1e-10, manufactured and seeded Gaussian right-hand sides",
+                "solves_per_step": len(items), "n": 1024, "restart_m": 40, "tol": 1e-10,
+                "precision": "fp32-preconditioned"}
+        opts = dict(restart_m=40, precision=1)
+    elif name == "batching":
+        specs = workloads.batch_workload()
+        items = [s.build() for s in specs]
+        desc = {"workload": "64 composite problems (cross/L/T, n in {64,128,256,512}, kappa in "
+                            "[-100,0]) x 8 seeded Gaussian right-hand sides = 512 solves, "
+                            "FGMRES(40) FP32 preconditioner, rel-res 1e-10",
+                "solves_per_step": len(items), "restart_m": 40, "tol": 1e-10,
+                "precision": "fp32-preconditioned"}
+        opts = dict(restart_m=40, precision=1)
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return desc, items, opts
+
+
+def to_device(items, opts, device):
+    import torch
+    import paper_2509_23180_amd as fds
+    from paper_2509_23180_amd import layout as playout
+    plans = {}
+    out = []
+    for prob in items:
+        key = (tuple(prob.rects), prob.h, prob.kappa)
+        if key not in plans:
+            plans[key] = fds.Plan(prob.rects, prob.h, prob.kappa, **opts)
+        plan = plans[key]
+        rhs = torch.tensor(playout.pack_unknowns(prob.rects, prob.f_grid), device=device)
+        bc = torch.tensor(playout.pack_boxes(prob.rects, prob.g_grid), device=device)
+        x = torch.zeros(plan.n_unknowns, dtype=torch.float64, device=device)
+        out.append((plan, rhs, bc, x))
+    return plans, out
+
+
+# --------------------------------------------------------------------------- CPU baseline
+
+def cpu_baseline(items, sample):
+    """The FP64 oracle (banded direct solve of the global system) timed on the
+    host cores on a bounded sample of the same workload."""
+    from oracle import composite
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in info] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    picks = items[:1] + items[len(items) // 2:len(items) // 2 + 1] if len(items) > 1 else items
+    picks = picks[:sample]
+    t0 = time.perf_counter()
+    for prob in picks:
+        composite.solve(prob.rects, prob.h, prob.kappa, prob.f_grid, prob.g_grid)
+    dt = time.perf_counter() - t0
+    return {"value": round(len(picks) / dt, 6), "unit": "solves/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"{len(picks)} of the {len(items)} solves of one step "
+                      f"({', '.join(p.label + ' kappa=' + str(p.kappa) for p in picks)}); "
+                      f"global composite system, LAPACK banded Cholesky; {dt:.1f} s"}
+
+
+# --------------------------------------------------------------------------- main
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="plain", choices=["plain", "precision", "batching"])
+    ap.add_argument("--cpu-sample", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-solves", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB (HBM counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: every solve of this method fits one MI355X, and "
+              "multi-GPU runs are outside this build (see DESIGN.md for how the path would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2509_23180_amd as fds
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    device = "cuda:0"
+    torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        n = (1 << 30) // 8
+        a = torch.ones(n, dtype=torch.float64, device=device)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 20
+        for _ in range(reps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"copy_bytes_per_launch": 2 * n * 8, "GB/s": 2 * n * 8 * reps / dt / 1e9}))
+        return
+
+    desc, items, opts = build_workload(args.workload, device)
+    log(f"building {len(items)} problems on {device}")
+    plans, dev = to_device(items, opts, device)
+    P = [d[0] for d in dev]
+    R = [d[1] for d in dev]
+    B = [d[2] for d in dev]
+    X = [d[3] for d in dev]
+    tol = desc["tol"]
+    T = [tol] * len(dev)
+
+    def step():
+        return fds.solve_batch(P, R, X, T, bcs=B)
+
+    for w in range(args.warmup):
+        res = step()
+        log(f"warmup {w}: iterations {[r.iterations for r in res][:6]}...")
+
+    # per-class totals of one step with every class timed -> dominant class
+    fds.timing_reset()
+    fds.timing_enable(None)
+    step()
+    fds.timing_enable([])
+    classes = {}
+    for name in ("dst", "tridiag", "operator", "mgs", "lines", "other"):
+        c, ms, by = fds.timing_read(name)
+        classes[name] = {"calls": c, "ms": round(ms, 4),
+                         "GB/s": round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 and by > 0 else None}
+    dominant = max((k for k in classes if k != "other"), key=lambda k: classes[k]["ms"])
+    log(f"per-class (one step, all classes timed): {classes}; dominant: {dominant}")
+
+    # timed region: only the dominant class carries HIP events
+    fds.timing_reset()
+    fds.timing_enable([dominant])
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    step_ms = []
+    results = None
+    for k in range(args.steps):
+        t0 = time.perf_counter()
+        results = step()
+        step_ms.append((time.perf_counter() - t0) * 1e3)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    fds.timing_enable([])
+    calls, ms, algo_bytes = fds.timing_read(dominant)
+    solves = len(dev) * args.steps
+    value = solves / total
+    ok = all(r.status == 0 and r.relres_schur <= tol for r in results)
+    its = [r.iterations for r in results]
+    log(f"timed: {args.steps} steps in {total:.3f} s -> {value:.2f} solves/s; iterations {its}")
+
+    # single-solve latency (outside the timed region)
+    lat = []
+    for _ in range(args.latency_solves):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fds.solve(P[0], R[0], X[0], tol, bc=B[0])
+        lat.append((time.perf_counter() - t0) * 1e3)
+
+    achieved = (algo_bytes / calls) / ((ms / calls) * 1e-3) / 1e9 if calls and ms > 0 else None
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{CLASS_KERNEL.get(dominant, dominant)}_{args.workload}.json")
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_source_hash") == kernel_source_hash():
+            traffic = tr.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                "traffic": traffic,
+                "kernel": CLASS_KERNEL.get(dominant, dominant),
+                "launches": calls, "avg_launch_us": round(ms / calls * 1e3, 3) if calls else None,
+                "algorithmic_bytes_per_launch": round(algo_bytes / calls, 1) if calls else None}
+
+    cpu = None
+    if not args.no_cpu_baseline and args.cpu_sample > 0:
+        log("timing the CPU oracle on a bounded sample ...")
+        cpu = cpu_baseline(items, args.cpu_sample)
+
+    line = {
+        "metric": "solves/s & p50/p99 latency at rel-res 1e-10; DST/Thomas GB/s vs HBM peak",
+        "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(total / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic", "config": desc,
+        "converged": ok, "iterations": its,
+        "latency_ms": {"step_p50": _r(pct(step_ms, 50)), "step_p99": _r(pct(step_ms, 99)),
+                       "single_solve_p50": _r(pct(lat, 50)), "single_solve_p99": _r(pct(lat, 99))},
+        "kernels": classes,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    if args.workload != "plain":
+        line["dtype"] = "f64+f32"
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

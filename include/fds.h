@@ -211,12 +211,17 @@ fds_status fds_k_arnoldi_mgs(double* V, int32_t k, int64_t len, double* h, void*
 /* ---------------------------------------------------------------- misc */
 const char* fds_status_str(fds_status s);
 const char* fds_last_error(void);
-/* Per-kernel-class timing with HIP events (off by default).  enable != 0
- * turns it on for subsequent calls on this thread; fds_timing_read copies
- * {calls, total_ms} for class `cls` (0 dst, 1 tridiag, 2 operator, 3 mgs,
- * 4 schur lines, 5 other) accumulated since the last reset. */
-fds_status fds_timing_enable(int32_t enable);
+/* Per-kernel-class timing with HIP events recorded on the launching stream
+ * (off by default).  Classes: 0 sine transforms, 1 tridiagonal solves,
+ * 2 centre operator, 3 Gram-Schmidt passes, 4 Schur line terms, 5 other.
+ * `mask` selects the classes to time (bit c = class c; 0 = off).
+ * fds_timing_read returns, per class, the launches timed, their summed
+ * duration and the algorithmic bytes (minimal HBM traffic: every operand
+ * read once and every result written once) the solver's work in those
+ * launches required, all since the last reset. */
+fds_status fds_timing_enable(int32_t mask);
 fds_status fds_timing_read(int32_t cls, int64_t* calls, double* total_ms);
+fds_status fds_timing_bytes(int32_t cls, double* algorithmic_bytes);
 fds_status fds_timing_reset(void);
 
 #ifdef __cplusplus

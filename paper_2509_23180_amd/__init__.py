@@ -75,7 +75,8 @@ SYMBOLS = (
     "fds_solve_batch", "fds_server_create", "fds_server_destroy", "fds_batch_submit",
     "fds_batch_poll", "fds_k_dst_rows", "fds_k_dst_rows_f32", "fds_k_tridiag_modes",
     "fds_k_tridiag_modes_f32", "fds_k_rect_solve", "fds_k_centre_operator", "fds_k_arnoldi_mgs",
-    "fds_status_str", "fds_last_error", "fds_timing_enable", "fds_timing_read", "fds_timing_reset",
+    "fds_status_str", "fds_last_error", "fds_timing_enable", "fds_timing_read", "fds_timing_bytes",
+    "fds_timing_reset",
 )
 
 
@@ -114,6 +115,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "fds_last_error": ([], ctypes.c_char_p),
         "fds_timing_enable": ([I32], I32),
         "fds_timing_read": ([I32, ctypes.POINTER(I64), ctypes.POINTER(D)], I32),
+        "fds_timing_bytes": ([I32, ctypes.POINTER(D)], I32),
         "fds_timing_reset": ([], I32),
     }
     for name, (args, ret) in sig.items():
@@ -306,16 +308,28 @@ def arnoldi_mgs(V, k: int, h, stream=None):
                                             _stream(stream)))
 
 
-def timing_enable(on: bool = True):
-    _check(load_library().fds_timing_enable(1 if on else 0))
+def timing_enable(classes=None):
+    """Time the given kernel classes (names of TIMING_CLASSES; None = all,
+    [] = off)."""
+    if classes is None:
+        mask = 0x3F
+    else:
+        mask = 0
+        for c in classes:
+            mask |= 1 << TIMING_CLASSES[c]
+    _check(load_library().fds_timing_enable(mask))
 
 
 def timing_reset():
     _check(load_library().fds_timing_reset())
 
 
-def timing_read(cls: str) -> Tuple[int, float]:
+def timing_read(cls: str) -> Tuple[int, float, float]:
+    """(launches, total milliseconds, algorithmic bytes) of a kernel class."""
     c = ctypes.c_int64()
     ms = ctypes.c_double()
-    _check(load_library().fds_timing_read(TIMING_CLASSES[cls], ctypes.byref(c), ctypes.byref(ms)))
-    return c.value, ms.value
+    b = ctypes.c_double()
+    lib = load_library()
+    _check(lib.fds_timing_read(TIMING_CLASSES[cls], ctypes.byref(c), ctypes.byref(ms)))
+    _check(lib.fds_timing_bytes(TIMING_CLASSES[cls], ctypes.byref(b)))
+    return c.value, ms.value, b.value

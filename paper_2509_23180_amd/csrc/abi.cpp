@@ -40,7 +40,8 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 // ---------------------------------------------------------------- timing
 struct TimingState {
   std::mutex mu;
-  bool on = false;
+  int mask = 0;
+  double bytes[6] = {0, 0, 0, 0, 0, 0};
   struct Pending { int cls; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
@@ -77,14 +78,25 @@ TimingState& timing() {
 
 namespace fds {
 
-void Timing::enable(bool on) {
+void Timing::enable(int mask) {
   std::lock_guard<std::mutex> lk(timing().mu);
-  timing().on = on;
+  timing().mask = mask;
 }
-bool Timing::on() { return timing().on; }
+bool Timing::on() { return timing().mask != 0; }
+bool Timing::on(int cls) { return (timing().mask >> cls) & 1; }
+void Timing::add_bytes(int cls, double b) {
+  TimingState& t = timing();
+  std::lock_guard<std::mutex> lk(t.mu);
+  t.bytes[cls] += b;
+}
+double Timing::bytes(int cls) {
+  TimingState& t = timing();
+  std::lock_guard<std::mutex> lk(t.mu);
+  return t.bytes[cls];
+}
 void Timing::begin(int cls, hipStream_t s) {
   TimingState& t = timing();
-  if (!t.on) return;
+  if (!((t.mask >> cls) & 1)) return;
   std::lock_guard<std::mutex> lk(t.mu);
   hipEvent_t e = t.take();
   FDS_HIP(hipEventRecord(e, s));
@@ -92,7 +104,7 @@ void Timing::begin(int cls, hipStream_t s) {
 }
 void Timing::end(int cls, hipStream_t s) {
   TimingState& t = timing();
-  if (!t.on) return;
+  if (!((t.mask >> cls) & 1)) return;
   std::lock_guard<std::mutex> lk(t.mu);
   if (!t.open[cls]) return;
   hipEvent_t e = t.take();
@@ -112,7 +124,7 @@ void Timing::reset() {
   TimingState& t = timing();
   std::lock_guard<std::mutex> lk(t.mu);
   t.flush();
-  for (int i = 0; i < 6; ++i) { t.calls[i] = 0; t.ms[i] = 0; }
+  for (int i = 0; i < 6; ++i) { t.calls[i] = 0; t.ms[i] = 0; t.bytes[i] = 0; }
 }
 
 }  // namespace fds
@@ -328,7 +340,7 @@ fds_status fds_k_centre_operator(const fds_plan* plan, const double* z, double* 
         case 3: t.start = nx - 1; t.stride = nx; break;
       }
       ot.line[a.line] = t.out;
-      sm = std::max(sm, sizeof(double2) * 2 * (a.L + 1) + sizeof(double) * (a.L + 1));
+      sm = std::max(sm, line_smem_bytes(a.L));
       lt.push_back(t);
     }
     DevBuf d(sizeof(OpTask) + sizeof(LineTask) * std::max<size_t>(1, lt.size()));
@@ -388,8 +400,16 @@ fds_status fds_k_arnoldi_mgs(double* V, int32_t k, int64_t len, double* h, void*
   });
 }
 
-fds_status fds_timing_enable(int32_t enable) {
-  return guarded([&] { Timing::enable(enable != 0); return FDS_OK; });
+fds_status fds_timing_enable(int32_t mask) {
+  return guarded([&] { Timing::enable(mask); return FDS_OK; });
+}
+
+fds_status fds_timing_bytes(int32_t cls, double* algorithmic_bytes) {
+  return guarded([&] {
+    if (cls < 0 || cls > 5 || !algorithmic_bytes) throw Error(FDS_E_INVALID_ARG, "bad timing arguments");
+    *algorithmic_bytes = Timing::bytes(cls);
+    return FDS_OK;
+  });
 }
 
 fds_status fds_timing_read(int32_t cls, int64_t* calls, double* total_ms) {

@@ -115,6 +115,12 @@ struct Engine::Impl {
   int* active_host = nullptr;
   std::vector<hipEvent_t> events;
   bool set_up = false;
+  std::vector<int> prev_its;
+
+  // Algorithmic bytes (each operand read once, each result written once) of
+  // the work every problem did in the cycle that just ended, by kernel class.
+  void account_cycle(const std::vector<ProbState>& before);
+  void account_arms(bool setup_phase);
 
   ~Impl() {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -235,8 +241,7 @@ void Engine::Impl::build() {
         case 3: lt.start = nx - 1; lt.stride = nx; break;
       }
       ot.line[a.line] = lt.out;
-      const size_t sm = sizeof(double2) * 2 * (a.L + 1) + sizeof(double) * (a.L + 1);
-      smem_lines = std::max(smem_lines, sm);
+      smem_lines = std::max(smem_lines, line_smem_bytes(a.L));
       LineTask li = lt;
       if (flex) { li.z = sl.Z; li.z_js = Nc; li.z_f32 = 1; }
       else { li.z = sl.zbuf; li.z_js = 0; li.z_f32 = 0; }
@@ -468,6 +473,56 @@ void Engine::setup() {
   FDS_HIP(hipGetLastError());
   I.read_states();
   I.set_up = true;
+  if (Timing::on()) I.account_arms(true);
+}
+
+void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
+  const double wz = flex ? 4.0 : 8.0;     // storage of z and of the transform scratch
+  for (size_t i = 0; i < slots.size(); ++i) {
+    if (before[i].finished) continue;
+    const Slot& sl = slots[i];
+    const double Nc = (double)sl.Nc;
+    const int its = host_states[i].iterations - before[i].iterations;
+    double lines = 0;
+    for (const ArmInfo& a : sl.plan->arms) lines += 16.0 * a.L;
+    // per Arnoldi step: forward transform reads v (8) writes scratch; tridiagonal
+    // solve reads and writes scratch; inverse transform reads scratch, writes z;
+    // operator reads z, writes w; MGS pass i reads w and v_i (and v_{i-1},
+    // writes w when i > 0)
+    Timing::add_bytes(0, its * Nc * ((8.0 + wz) + (wz + wz)));
+    Timing::add_bytes(1, its * Nc * 2.0 * wz);
+    Timing::add_bytes(2, its * Nc * (wz + 8.0));
+    Timing::add_bytes(4, its * lines);
+    double mgs = 0;
+    for (int j = 0; j < its; ++j) mgs += 40.0 + 32.0 * j;
+    Timing::add_bytes(3, mgs * Nc);
+    // end of cycle: plain variant applies A_c^{-1} to V y (transforms and
+    // tridiagonal solve in FP64, accumulate into x); residual operator reads
+    // x and f', writes r; line terms of x
+    if (!flex) {
+      Timing::add_bytes(0, Nc * (16.0 + 24.0));
+      Timing::add_bytes(1, Nc * 16.0);
+    }
+    Timing::add_bytes(2, Nc * 24.0);
+    Timing::add_bytes(4, lines);
+  }
+}
+
+void Engine::Impl::account_arms(bool setup_phase) {
+  for (const Slot& sl : slots) {
+    for (const ArmInfo& a : sl.plan->arms) {
+      const double na = (double)a.L * a.rows;
+      Timing::add_bytes(0, 2.0 * 16.0 * na);
+      Timing::add_bytes(1, 16.0 * na);
+    }
+    const double Nc = (double)sl.Nc;
+    if (setup_phase) {
+      double lines = 0;
+      for (const ArmInfo& a : sl.plan->arms) lines += 16.0 * a.L;
+      Timing::add_bytes(2, Nc * 24.0);
+      Timing::add_bytes(4, lines);
+    }
+  }
 }
 
 bool Engine::step_cycle() {
@@ -475,6 +530,7 @@ bool Engine::step_cycle() {
   bool any = false;
   for (const ProbState& st : I.host_states) any |= !st.finished;
   if (!any) return false;
+  const std::vector<ProbState> before = I.host_states;
   hipStream_t s = I.s;
   for (int j = 0; j < I.m; ++j) {
     if (j >= 2) {
@@ -488,6 +544,7 @@ bool Engine::step_cycle() {
   }
   I.end_of_cycle();
   I.read_states();
+  if (Timing::on()) I.account_cycle(before);
   for (const ProbState& st : I.host_states) if (!st.finished) return true;
   return false;
 }
@@ -526,6 +583,7 @@ std::vector<SolveOutcome> Engine::finalize() {
                            hipMemcpyDeviceToHost, s));
   }
   I.read_states();
+  if (Timing::on()) I.account_arms(false);
   std::vector<SolveOutcome> out(I.slots.size());
   for (size_t i = 0; i < I.slots.size(); ++i) {
     const ProbState& st = I.host_states[i];

@@ -33,14 +33,31 @@ struct Error : std::runtime_error {
 
 // ---------------------------------------------------------------- FFT plan
 // Complex FFT of length N = n + 1 used to evaluate the DST-I of length n.
+//   kind 0 (mixed radix): Stockham passes over N.
+//   kind 1 (Rader, N prime): the N-1 outputs k != 0 form a cyclic
+//          convolution of length L = N-1 evaluated with two inner FFTs.
+//   kind 2 (Bluestein): chirp-z, a cyclic convolution of power-of-two
+//          length L >= 2N-1 evaluated with two inner FFTs.
+// `radix`, `tw*` describe the inner (kind 1, 2) or the full (kind 0) FFT.
+enum FftKind { FFT_MIXED = 0, FFT_RADER = 1, FFT_BLUESTEIN = 2 };
+
 struct FftDesc {
   int N;
+  int kind;
+  int L;                  // length of the Stockham FFT actually run
+  int W;                  // LDS entries per buffer: max(N, L)
   int npass;
   int radix[kMaxPass];
-  const double2* tw64;    // N entries  exp(-2 pi i t / N)
+  const double2* tw64;    // L entries  exp(-2 pi i t / L)
   const float2* tw32;
   const double2* post64;  // N+1 entries (cos(pi k / N), sin(pi k / N))
   const float2* post32;
+  const int* perm_in;     // Rader: g^{-q} mod N, q < L
+  const int* perm_out;    // Rader: g^{q} mod N, q < L
+  const double2* kern64;  // Rader / Bluestein: FFT_L(kernel) / L
+  const float2* kern32;
+  const double2* chirp64; // Bluestein: exp(-i pi t^2 / N), t < N
+  const float2* chirp32;
 };
 
 // Per-mode coefficients of the constant-coefficient tridiagonal solve

@@ -27,6 +27,12 @@ template <> __device__ __forceinline__ const float2* fft_tw<float>(const FftDesc
 template <typename T> __device__ __forceinline__ const C2<T>* fft_post(const FftDesc& f);
 template <> __device__ __forceinline__ const double2* fft_post<double>(const FftDesc& f) { return f.post64; }
 template <> __device__ __forceinline__ const float2* fft_post<float>(const FftDesc& f) { return f.post32; }
+template <typename T> __device__ __forceinline__ const C2<T>* fft_kern(const FftDesc& f);
+template <> __device__ __forceinline__ const double2* fft_kern<double>(const FftDesc& f) { return f.kern64; }
+template <> __device__ __forceinline__ const float2* fft_kern<float>(const FftDesc& f) { return f.kern32; }
+template <typename T> __device__ __forceinline__ const C2<T>* fft_chirp(const FftDesc& f);
+template <> __device__ __forceinline__ const double2* fft_chirp<double>(const FftDesc& f) { return f.chirp64; }
+template <> __device__ __forceinline__ const float2* fft_chirp<float>(const FftDesc& f) { return f.chirp32; }
 
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
 template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
@@ -145,25 +151,23 @@ __device__ __forceinline__ void generic_pass(const C2<T>* __restrict__ src, C2<T
   }
 }
 
-// Full complex FFT of length f.N held in LDS buffer `a` (scratch `b`), row
-// group of G threads, g = rank in the group.  Every group of the block must
-// call this with the same plan (block-wide barriers).  Returns the buffer
-// holding the result.
+// Stockham FFT of length L (radix schedule `radix`) in LDS buffer `a`
+// (scratch `b`).  Every group of the block must run the same schedule
+// (block-wide barriers).  Returns the buffer holding the result.
 template <typename T>
-__device__ C2<T>* fft_lds(C2<T>* a, C2<T>* b, const FftDesc& f, int g, int G) {
-  const C2<T>* tw = fft_tw<T>(f);
-  const int N = f.N;
+__device__ C2<T>* stockham_lds(C2<T>* a, C2<T>* b, int L, int npass, const int* radix,
+                               const C2<T>* tw, int g, int G) {
   int Ns = 1;
   C2<T>* src = a;
   C2<T>* dst = b;
-  for (int p = 0; p < f.npass; ++p) {
-    const int R = f.radix[p];
+  for (int p = 0; p < npass; ++p) {
+    const int R = radix[p];
     switch (R) {
-      case 2: stockham_pass<2, T>(src, dst, tw, N, Ns, g, G); break;
-      case 3: stockham_pass<3, T>(src, dst, tw, N, Ns, g, G); break;
-      case 4: stockham_pass<4, T>(src, dst, tw, N, Ns, g, G); break;
-      case 5: stockham_pass<5, T>(src, dst, tw, N, Ns, g, G); break;
-      default: generic_pass<T>(src, dst, tw, N, Ns, R, g, G); break;
+      case 2: stockham_pass<2, T>(src, dst, tw, L, Ns, g, G); break;
+      case 3: stockham_pass<3, T>(src, dst, tw, L, Ns, g, G); break;
+      case 4: stockham_pass<4, T>(src, dst, tw, L, Ns, g, G); break;
+      case 5: stockham_pass<5, T>(src, dst, tw, L, Ns, g, G); break;
+      default: generic_pass<T>(src, dst, tw, L, Ns, R, g, G); break;
     }
     __syncthreads();
     C2<T>* t = src;
@@ -172,6 +176,59 @@ __device__ C2<T>* fft_lds(C2<T>* a, C2<T>* b, const FftDesc& f, int g, int G) {
     Ns *= R;
   }
   return src;
+}
+
+// Complex FFT of length f.N of the data in LDS buffer `a` (scratch `b`; both
+// hold max(N, L) entries).  Returns the buffer holding the N outputs.
+template <typename T>
+__device__ C2<T>* fft_lds(C2<T>* a, C2<T>* b, const FftDesc& f, int g, int G) {
+  using C = C2<T>;
+  const C* tw = fft_tw<T>(f);
+  if (f.kind == FFT_MIXED) return stockham_lds<T>(a, b, f.N, f.npass, f.radix, tw, g, G);
+  const int N = f.N, L = f.L;
+  const C* K = fft_kern<T>(f);
+  if (f.kind == FFT_RADER) {
+    // X_0 = x_0 + sum_{j>0} x_j;  X_{g^m} = x_0 + (a~ * b)_m with a~_q = x_{g^{-q}}
+    const C x0 = a[0];
+    for (int q = g; q < L; q += G) b[q] = a[f.perm_in[q]];
+    __syncthreads();
+    C* r = stockham_lds<T>(b, a, L, f.npass, f.radix, tw, g, G);
+    const C X0 = C{x0.x + r[0].x, x0.y + r[0].y};
+    C* o = (r == a) ? b : a;
+    for (int t = g; t < L; t += G) {
+      const C v = cmul(r[t], K[t]);
+      o[t] = C{v.x, -v.y};
+    }
+    __syncthreads();
+    C* r2 = stockham_lds<T>(o, r, L, f.npass, f.radix, tw, g, G);
+    C* fin = (r2 == a) ? b : a;
+    for (int m = g; m < L; m += G) {
+      const C v = r2[m];
+      fin[f.perm_out[m]] = C{x0.x + v.x, x0.y - v.y};
+    }
+    if (g == 0) fin[0] = X0;
+    __syncthreads();
+    return fin;
+  }
+  // Bluestein: X_k = c_k sum_j (x_j c_j) conj(c_{k-j}),  c_t = exp(-i pi t^2/N)
+  const C* ch = fft_chirp<T>(f);
+  for (int j = g; j < L; j += G) a[j] = (j < N) ? cmul(a[j], ch[j]) : C{T(0), T(0)};
+  __syncthreads();
+  C* r = stockham_lds<T>(a, b, L, f.npass, f.radix, tw, g, G);
+  C* o = (r == a) ? b : a;
+  for (int t = g; t < L; t += G) {
+    const C v = cmul(r[t], K[t]);
+    o[t] = C{v.x, -v.y};
+  }
+  __syncthreads();
+  C* r2 = stockham_lds<T>(o, r, L, f.npass, f.radix, tw, g, G);
+  C* fin = (r2 == a) ? b : a;
+  for (int k = g; k < N; k += G) {
+    const C v = r2[k];
+    fin[k] = cmul(ch[k], C{v.x, -v.y});
+  }
+  __syncthreads();
+  return fin;
 }
 
 // Pack the odd extension of a real row into c_t = z_{2t} + i z_{2t+1}.

@@ -25,8 +25,8 @@ __global__ void __launch_bounds__(kBlock) k_dst_rows(const DstTask* __restrict__
   const int g = threadIdx.x - grp * G;
   const int row = (blockIdx.x - tk.block_begin) * tk.rpb + grp;
   const bool valid = row < tk.rows;
-  C2<T>* A = reinterpret_cast<C2<T>*>(smem_raw) + (size_t)grp * 2 * N;
-  C2<T>* B = A + N;
+  C2<T>* A = reinterpret_cast<C2<T>*>(smem_raw) + (size_t)grp * 2 * f.W;
+  C2<T>* B = A + f.W;
   const TIn* in = static_cast<const TIn*>(tk.in) + (long long)jidx * tk.in_js +
                   (long long)(valid ? row : 0) * tk.in_rs;
   const long long ics = tk.in_cs;
@@ -96,8 +96,8 @@ __global__ void __launch_bounds__(kBlock) k_schur_lines(const LineTask* __restri
   const int N = f.N;
   const int L = tk.L;
   double2* A = reinterpret_cast<double2*>(smem_raw);
-  double2* B = A + N;
-  double* mid = reinterpret_cast<double*>(B + N);
+  double2* B = A + f.W;
+  double* mid = reinterpret_cast<double*>(B + f.W);
   const int g = threadIdx.x;
   const long long st = tk.stride;
   if (tk.z_f32) {

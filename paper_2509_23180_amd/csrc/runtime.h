@@ -90,9 +90,14 @@ std::shared_ptr<ModeTable> upload_modes(const std::vector<ModeCoef<double>>& c64
 // Radix schedule of a complex FFT of length N (4s, 2s, 3s, 5s, then other
 // primes ascending).
 std::vector<int> fft_radices(int N);
+// Algorithm for the length-(n+1) FFT behind a DST-I of length n: kind, the
+// Stockham length L it runs, and the LDS entries per buffer.
+struct FftShape { int kind; int L; int lds_len; };
+FftShape fft_shape(int n);
 // Threads per row for a transform of length n (power of two, 32..256).
 int dst_threads_per_row(int n);
 size_t dst_smem_bytes(int n, bool fp32);
+size_t line_smem_bytes(int n);
 
 // ---------------------------------------------------------------- plan
 enum RectKind { RK_CENTRE = 0, RK_N = 1, RK_S = 2, RK_E = 3, RK_W = 4 };
@@ -171,10 +176,13 @@ class Engine {
   std::unique_ptr<Impl> impl_;
 };
 
-// Thread-local timing by kernel class (see fds_timing_*).
+// Process-wide timing by kernel class (see fds_timing_*).
 struct Timing {
-  static void enable(bool on);
+  static void enable(int mask);
   static bool on();
+  static bool on(int cls);
+  static void add_bytes(int cls, double bytes);
+  static double bytes(int cls);
   static void begin(int cls, hipStream_t s);
   static void end(int cls, hipStream_t s);
   static void read(int cls, long long* calls, double* ms);

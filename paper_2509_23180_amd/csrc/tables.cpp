@@ -2,6 +2,7 @@
 // line coefficients.  All values are computed on the host in FP64 (long
 // double where the angle reduction benefits) and uploaded once.
 #include <cmath>
+#include <complex>
 #include <cstring>
 
 #include "runtime.h"
@@ -23,18 +24,69 @@ std::vector<int> fft_radices(int N) {
   return r;
 }
 
-int dst_threads_per_row(int n) {
+// Relative cost of one Stockham FFT of length L (per output, summed over
+// passes): fixed butterflies 2/3/4/5, direct sums for other primes.
+static double stockham_cost(int L) {
+  double c = 0;
+  for (int R : fft_radices(L)) {
+    switch (R) {
+      case 2: c += 1.0; break;
+      case 3: c += 2.0; break;
+      case 4: c += 1.5; break;
+      case 5: c += 3.0; break;
+      default: c += 1.5 * R; break;
+    }
+  }
+  return c * L;
+}
+
+static bool is_prime(int p) {
+  if (p < 2) return false;
+  for (int d = 2; (long long)d * d <= p; ++d)
+    if (p % d == 0) return false;
+  return true;
+}
+
+FftShape fft_shape(int n) {
   const int N = n + 1;
-  if (N <= 64) return 32;
-  if (N <= 160) return 64;
-  if (N <= 640) return 128;
+  FftShape s{FFT_MIXED, N, N};
+  double best = stockham_cost(N);
+  if (N > 7 && is_prime(N)) {
+    const double c = 2.0 * stockham_cost(N - 1) + 3.0 * N;
+    if (c < best) { best = c; s = FftShape{FFT_RADER, N - 1, N}; }
+  }
+  // smallest 5-smooth length >= 2N-1 (fixed butterflies only)
+  int M = 2 * N - 1;
+  auto smooth = [](int v) {
+    for (int p : {2, 3, 5}) while (v % p == 0) v /= p;
+    return v == 1;
+  };
+  while (!smooth(M)) ++M;
+  // both LDS buffers of an FP64 row (plus the line-kernel scratch) must fit
+  const bool fits = (size_t)M * 2 * sizeof(double2) + sizeof(double) * (N + 1) <= 160u * 1024u;
+  if (N > 8 && fits) {
+    const double c = 2.0 * stockham_cost(M) + 4.0 * M;
+    if (c < best) { best = c; s = FftShape{FFT_BLUESTEIN, M, M}; }
+  }
+  return s;
+}
+
+int dst_threads_per_row(int n) {
+  const int W = fft_shape(n).lds_len;
+  if (W <= 64) return 32;
+  if (W <= 160) return 64;
+  if (W <= 640) return 128;
   return 256;
 }
 
 size_t dst_smem_bytes(int n, bool fp32) {
   const int G = dst_threads_per_row(n);
   const int rpb = kBlock / G;
-  return (size_t)rpb * 2 * (n + 1) * (fp32 ? sizeof(float2) : sizeof(double2));
+  return (size_t)rpb * 2 * fft_shape(n).lds_len * (fp32 ? sizeof(float2) : sizeof(double2));
+}
+
+size_t line_smem_bytes(int n) {
+  return sizeof(double2) * 2 * fft_shape(n).lds_len + sizeof(double) * (n + 1);
 }
 
 TableCache& TableCache::get() {
@@ -50,6 +102,69 @@ static int current_device() {
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+using cld = std::complex<long double>;
+static const long double kPi = 3.141592653589793238462643383279502884L;
+
+// exp(-2 pi i t / N) with the integer t reduced modulo N first
+static cld unit_root(long long t, long long N) {
+  t %= N;
+  if (t < 0) t += N;
+  const long double a = 2.0L * kPi * (long double)t / (long double)N;
+  return cld(cosl(a), -sinl(a));
+}
+
+// Forward DFT on the host (plan construction only), recursive mixed radix.
+static std::vector<cld> host_dft(const std::vector<cld>& x) {
+  const int N = (int)x.size();
+  if (N == 1) return x;
+  int p = 2;
+  while (N % p) ++p;
+  if (p == N) {
+    std::vector<cld> X(N);
+    for (int k = 0; k < N; ++k) {
+      cld s = 0;
+      for (int j = 0; j < N; ++j) s += x[j] * unit_root((long long)j * k, N);
+      X[k] = s;
+    }
+    return X;
+  }
+  const int M = N / p;
+  std::vector<std::vector<cld>> sub(p);
+  for (int r = 0; r < p; ++r) {
+    std::vector<cld> xr(M);
+    for (int j = 0; j < M; ++j) xr[j] = x[j * p + r];
+    sub[r] = host_dft(xr);
+  }
+  std::vector<cld> X(N);
+  for (int k = 0; k < N; ++k) {
+    cld s = 0;
+    for (int r = 0; r < p; ++r) s += unit_root((long long)r * k, N) * sub[r][k % M];
+    X[k] = s;
+  }
+  return X;
+}
+
+static int primitive_root(int p) {
+  const int phi = p - 1;
+  std::vector<int> fs;
+  int m = phi;
+  for (int d = 2; (long long)d * d <= m; ++d)
+    if (m % d == 0) { fs.push_back(d); while (m % d == 0) m /= d; }
+  if (m > 1) fs.push_back(m);
+  auto powmod = [](long long b, long long e, long long mod) {
+    long long r = 1;
+    b %= mod;
+    while (e) { if (e & 1) r = r * b % mod; b = b * b % mod; e >>= 1; }
+    return r;
+  };
+  for (int g = 2; g < p; ++g) {
+    bool ok = true;
+    for (int q : fs) if (powmod(g, phi / q, p) == 1) { ok = false; break; }
+    if (ok) return g;
+  }
+  throw Error(FDS_E_UNSUPPORTED, "no primitive root");
+}
+
 std::shared_ptr<FftTable> TableCache::fft(int n) {
   const int dev = current_device();
   std::lock_guard<std::mutex> lk(mu_);
@@ -57,46 +172,99 @@ std::shared_ptr<FftTable> TableCache::fft(int n) {
   auto it = fft_.find(key);
   if (it != fft_.end()) return it->second;
   const int N = n + 1;
+  const FftShape shp = fft_shape(n);
+  const int L = shp.L;
   auto t = std::make_shared<FftTable>();
-  std::vector<int> rad = fft_radices(N);
-  // layout: [FftDesc][tw64 N][tw32 N][post64 N+1][post32 N+1]
-  size_t o_desc = 0;
-  size_t o_tw64 = align_up(sizeof(FftDesc), 256);
-  size_t o_tw32 = align_up(o_tw64 + sizeof(double2) * N, 256);
-  size_t o_p64 = align_up(o_tw32 + sizeof(float2) * N, 256);
-  size_t o_p32 = align_up(o_p64 + sizeof(double2) * (N + 1), 256);
-  size_t total = align_up(o_p32 + sizeof(float2) * (N + 1), 256);
+  std::vector<int> rad = fft_radices(L);
+  const bool rader = shp.kind == FFT_RADER, blue = shp.kind == FFT_BLUESTEIN;
+  const int nk = (rader || blue) ? L : 0;
+  const int nch = blue ? N : 0;
+  size_t o = align_up(sizeof(FftDesc), 256);
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
+  const size_t o_tw64 = take(sizeof(double2) * L), o_tw32 = take(sizeof(float2) * L);
+  const size_t o_p64 = take(sizeof(double2) * (N + 1)), o_p32 = take(sizeof(float2) * (N + 1));
+  const size_t o_pin = take(sizeof(int) * (rader ? L : 1)), o_pout = take(sizeof(int) * (rader ? L : 1));
+  const size_t o_k64 = take(sizeof(double2) * std::max(nk, 1)), o_k32 = take(sizeof(float2) * std::max(nk, 1));
+  const size_t o_c64 = take(sizeof(double2) * std::max(nch, 1)), o_c32 = take(sizeof(float2) * std::max(nch, 1));
+  const size_t total = o;
   std::vector<unsigned char> host(total, 0);
   auto* tw64 = reinterpret_cast<double2*>(host.data() + o_tw64);
   auto* tw32 = reinterpret_cast<float2*>(host.data() + o_tw32);
+  for (int t0 = 0; t0 < L; ++t0) {
+    const cld w = unit_root(t0, L);
+    tw64[t0] = double2{(double)w.real(), (double)w.imag()};
+    tw32[t0] = float2{(float)w.real(), (float)w.imag()};
+  }
   auto* p64 = reinterpret_cast<double2*>(host.data() + o_p64);
   auto* p32 = reinterpret_cast<float2*>(host.data() + o_p32);
-  const long double pi = 3.141592653589793238462643383279502884L;
-  for (int t0 = 0; t0 < N; ++t0) {
-    const long double a = 2.0L * pi * (long double)t0 / (long double)N;
-    const double c = (double)cosl(a), s = (double)-sinl(a);
-    tw64[t0] = double2{c, s};
-    tw32[t0] = float2{(float)c, (float)s};
-  }
   for (int k = 0; k <= N; ++k) {
-    const long double a = pi * (long double)k / (long double)N;
+    const long double a = kPi * (long double)k / (long double)N;
     const double c = (double)cosl(a), s = (double)sinl(a);
     p64[k] = double2{c, s};
     p32[k] = float2{(float)c, (float)s};
   }
+  std::vector<cld> kern;
+  if (rader) {
+    const int g = primitive_root(N);
+    long long gp = 1, gi = 1;
+    long long ginv = 1;
+    for (int e = 0; e < N - 2; ++e) ginv = ginv * g % N;  // g^{N-2} = g^{-1}
+    auto* pin = reinterpret_cast<int*>(host.data() + o_pin);
+    auto* pout = reinterpret_cast<int*>(host.data() + o_pout);
+    std::vector<cld> b(L);
+    for (int q = 0; q < L; ++q) {
+      pin[q] = (int)gi;
+      pout[q] = (int)gp;
+      b[q] = unit_root(gp, N);
+      gi = gi * ginv % N;
+      gp = gp * g % N;
+    }
+    kern = host_dft(b);
+  } else if (blue) {
+    auto* c64 = reinterpret_cast<double2*>(host.data() + o_c64);
+    auto* c32 = reinterpret_cast<float2*>(host.data() + o_c32);
+    std::vector<cld> h(L, cld(0, 0));
+    for (int j = 0; j < N; ++j) {
+      // exp(-i pi j^2/N) = exp(-2 pi i (j^2 mod 2N) / (2N))
+      const cld c = unit_root((long long)j * j % (2LL * N), 2LL * N);
+      c64[j] = double2{(double)c.real(), (double)c.imag()};
+      c32[j] = float2{(float)c.real(), (float)c.imag()};
+      h[j] = std::conj(c);
+      if (j > 0) h[L - j] = std::conj(c);
+    }
+    kern = host_dft(h);
+  }
+  if (!kern.empty()) {
+    auto* k64 = reinterpret_cast<double2*>(host.data() + o_k64);
+    auto* k32 = reinterpret_cast<float2*>(host.data() + o_k32);
+    for (int q = 0; q < L; ++q) {
+      const cld v = kern[q] / (long double)L;
+      k64[q] = double2{(double)v.real(), (double)v.imag()};
+      k32[q] = float2{(float)v.real(), (float)v.imag()};
+    }
+  }
   t->mem.alloc(total);
   FftDesc d{};
   d.N = N;
+  d.kind = shp.kind;
+  d.L = L;
+  d.W = shp.lds_len;
   d.npass = (int)rad.size();
   for (size_t i = 0; i < rad.size(); ++i) d.radix[i] = rad[i];
   d.tw64 = t->mem.as<double2>(o_tw64);
   d.tw32 = t->mem.as<float2>(o_tw32);
   d.post64 = t->mem.as<double2>(o_p64);
   d.post32 = t->mem.as<float2>(o_p32);
-  std::memcpy(host.data() + o_desc, &d, sizeof(d));
+  d.perm_in = rader ? t->mem.as<int>(o_pin) : nullptr;
+  d.perm_out = rader ? t->mem.as<int>(o_pout) : nullptr;
+  d.kern64 = nk ? t->mem.as<double2>(o_k64) : nullptr;
+  d.kern32 = nk ? t->mem.as<float2>(o_k32) : nullptr;
+  d.chirp64 = blue ? t->mem.as<double2>(o_c64) : nullptr;
+  d.chirp32 = blue ? t->mem.as<float2>(o_c32) : nullptr;
+  std::memcpy(host.data(), &d, sizeof(d));
   FDS_HIP(hipMemcpy(t->mem.get(), host.data(), total, hipMemcpyHostToDevice));
   t->host = d;
-  t->dev = t->mem.as<FftDesc>(o_desc);
+  t->dev = t->mem.as<FftDesc>(0);
   fft_[key] = t;
   return t;
 }

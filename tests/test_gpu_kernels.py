@@ -32,8 +32,10 @@ def _tol64(n):
     return 1e-13 * (1 + _maxprime(n + 1) / 32) * max(1.0, np.log2(n + 1) / 8)
 
 
-DST_SIZES = [1, 2, 3, 4, 5, 7, 10, 16, 31, 32, 33, 63, 64, 65, 100, 127, 128, 129, 255, 256, 257,
-             511, 512, 1000, 1023, 1024, 1025, 2047, 2048]
+# covers mixed radix (e.g. 33 = 3*11), Rader (prime n+1: 17, 97, 101, 257, 1201) and
+# Bluestein (n+1 = 301, 1501, 2049) schedules
+DST_SIZES = [1, 2, 3, 4, 5, 7, 10, 16, 31, 32, 33, 63, 64, 65, 96, 100, 127, 128, 129, 255, 256, 257,
+             300, 511, 512, 1000, 1023, 1024, 1025, 1200, 1500, 2047, 2048]
 
 
 @pytest.mark.parametrize("n", DST_SIZES)
@@ -54,7 +56,8 @@ def test_dst_rows_fp64(n):
     assert np.abs(back - x).max() <= 10 * _tol64(n) * np.abs(x).max()
 
 
-@pytest.mark.parametrize("n", [1, 7, 32, 33, 64, 255, 256, 257, 1023, 1024, 2047, 2048])
+@pytest.mark.parametrize("n", [1, 7, 16, 32, 33, 64, 100, 255, 256, 257, 300, 1023, 1024, 1200, 2047,
+                               2048])
 def test_dst_rows_fp32(n):
     fds = _fds()
     log(f"dst fp32 n={n}")
