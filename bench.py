@@ -32,8 +32,9 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2509_23180_amd/csrc/kernels.hip", "paper_2509_23180_amd/csrc/fft_device.h",
                   "paper_2509_23180_amd/csrc/fds_internal.h")
 # kernel class -> name of the HIP kernel that implements it (rocprofv3 summaries)
-CLASS_KERNEL = {"dst": "k_dst_rows", "tridiag": "k_tridiag", "operator": "k_operator",
-                "mgs": "k_mgs_pass", "lines": "k_schur_lines"}
+CLASS_KERNEL = {"dst": "k_dst_rows", "tridiag": "k_tridiag_seg", "operator": "k_operator",
+                "gram_dots": "k_gram_dots", "gram_update": "k_gram_update", "lines": "k_schur_lines",
+                "cols": "k_idst_cols"}
 
 
 def log(*a):
@@ -212,7 +213,7 @@ def main():
     step()
     fds.timing_enable([])
     classes = {}
-    for name in ("dst", "tridiag", "operator", "mgs", "lines", "other"):
+    for name in ("dst", "tridiag", "operator", "gram_dots", "gram_update", "lines", "cols", "other"):
         c, ms, by = fds.timing_read(name)
         classes[name] = {"calls": c, "ms": round(ms, 4),
                          "GB/s": round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 and by > 0 else None}

@@ -25,7 +25,8 @@ FP64 = 0
 FP32_PRECOND = 1
 STOP = {0: "none", 1: "tol", 2: "at_floor", 3: "max_cycles", 4: "stagnation"}
 
-TIMING_CLASSES = {"dst": 0, "tridiag": 1, "operator": 2, "mgs": 3, "lines": 4, "other": 5}
+TIMING_CLASSES = {"dst": 0, "tridiag": 1, "operator": 2, "gram_dots": 3, "lines": 4, "other": 5,
+                  "gram_update": 6, "cols": 7}
 
 
 class FdsError(RuntimeError):
@@ -312,7 +313,7 @@ def timing_enable(classes=None):
     """Time the given kernel classes (names of TIMING_CLASSES; None = all,
     [] = off)."""
     if classes is None:
-        mask = 0x3F
+        mask = 0xFF
     else:
         mask = 0
         for c in classes:

@@ -41,13 +41,14 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 struct TimingState {
   std::mutex mu;
   int mask = 0;
-  double bytes[6] = {0, 0, 0, 0, 0, 0};
+  static constexpr int kClasses = 8;
+  double bytes[kClasses] = {};
   struct Pending { int cls; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
-  hipEvent_t open[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  long long calls[6] = {0, 0, 0, 0, 0, 0};
-  double ms[6] = {0, 0, 0, 0, 0, 0};
+  hipEvent_t open[kClasses] = {};
+  long long calls[kClasses] = {};
+  double ms[kClasses] = {};
 
   hipEvent_t take() {
     if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
@@ -124,7 +125,7 @@ void Timing::reset() {
   TimingState& t = timing();
   std::lock_guard<std::mutex> lk(t.mu);
   t.flush();
-  for (int i = 0; i < 6; ++i) { t.calls[i] = 0; t.ms[i] = 0; t.bytes[i] = 0; }
+  for (int i = 0; i < TimingState::kClasses; ++i) { t.calls[i] = 0; t.ms[i] = 0; t.bytes[i] = 0; }
 }
 
 }  // namespace fds
@@ -231,6 +232,7 @@ static fds_status dst_rows_impl(const void* in, void* out, int rows, int n, doub
   DstTask t{};
   t.in = in; t.out = out; t.in_rs = n; t.out_rs = n; t.in_cs = 1; t.out_cs = 1;
   t.rows = rows; t.n = n; t.rpb = rpb; t.scale = scale; t.fft = fft->dev; t.block_begin = 0;
+  t.tw_lds = dst_twiddles_in_lds(n, fp32);
   DevBuf d(sizeof(DstTask));
   FDS_HIP(hipMemcpyAsync(d.get(), &t, sizeof(t), hipMemcpyHostToDevice, s));
   const int nb = (rows + rpb - 1) / rpb;
@@ -262,10 +264,11 @@ static fds_status tridiag_impl(void* data, int rows, int modes, double h, double
   TriTask t{};
   t.data = data; t.rs = modes; t.rows = rows; t.modes = modes;
   t.coef = fp32 ? (const void*)tab->c32 : (const void*)tab->c64;
+  const TriConfig tc = tri_config(fp32, rows);
   DevBuf d(sizeof(TriTask));
   FDS_HIP(hipMemcpyAsync(d.get(), &t, sizeof(t), hipMemcpyHostToDevice, s));
   Timing::begin(1, s);
-  launch_tridiag(fp32, d.as<TriTask>(), 1, (modes + kBlock - 1) / kBlock, 0, s);
+  launch_tri(tc, fp32, d.as<TriTask>(), 1, tri_blocks(tc, modes), 0, s);
   Timing::end(1, s);
   FDS_HIP(hipGetLastError());
   FDS_HIP(hipStreamSynchronize(s));
@@ -295,6 +298,7 @@ fds_status fds_k_rect_solve(const double* f, double* z, int32_t rows, int32_t co
     DstTask t{};
     t.in = f; t.out = tmp.get(); t.in_rs = cols; t.out_rs = cols; t.in_cs = 1; t.out_cs = 1;
     t.rows = rows; t.n = cols; t.rpb = rpb; t.scale = 1.0; t.fft = fft->dev;
+    t.tw_lds = dst_twiddles_in_lds(cols, fp32);
     DstTask v = t;
     v.in = tmp.get(); v.out = z;
     TriTask tt{};
@@ -307,8 +311,9 @@ fds_status fds_k_rect_solve(const double* f, double* z, int32_t rows, int32_t co
     const int nb = (rows + rpb - 1) / rpb;
     const size_t sm = dst_smem_bytes(cols, fp32);
     launch_dst(fp32 ? DstKind::D_F : DstKind::D_D, d.as<DstTask>(0), 1, nb, sm, 0, s);
-    launch_tridiag(fp32, reinterpret_cast<const TriTask*>(d.as<char>(2 * sizeof(DstTask))), 1,
-                   (cols + kBlock - 1) / kBlock, 0, s);
+    const TriConfig tc = tri_config(fp32, rows);
+    launch_tri(tc, fp32, reinterpret_cast<const TriTask*>(d.as<char>(2 * sizeof(DstTask))), 1,
+               tri_blocks(tc, cols), 0, s);
     launch_dst(fp32 ? DstKind::F_D : DstKind::D_D,
                reinterpret_cast<const DstTask*>(d.as<char>(sizeof(DstTask))), 1, nb, sm, 0, s);
     FDS_HIP(hipGetLastError());
@@ -370,29 +375,45 @@ fds_status fds_k_arnoldi_mgs(double* V, int32_t k, int64_t len, double* h, void*
     const int j = k - 1;
     const int P = (int)((len + kVecPerBlock - 1) / kVecPerBlock);
     const size_t small = (size_t)(m + 1) * m + 4 * (size_t)m + 2;
-    DevBuf mem(8 * (small + 4 * (size_t)P) + sizeof(ProbState) + sizeof(KryTask) + 512);
+    const size_t gram = (size_t)(m + 1) * (m + 1) + (m + 1);
+    const size_t parts = (size_t)(2 * (m + 1) + 4) * P;
+    DevBuf mem(8 * (small + gram + parts) + 1024 + 2 * sizeof(KryTask));
     FDS_HIP(hipMemsetAsync(mem.get(), 0, mem.size(), s));
     double* H = mem.as<double>(0);
-    double* partials = H + small;
-    auto* st = reinterpret_cast<ProbState*>(partials + 4 * (size_t)P);
+    double* G = H + small;
+    double* partials = G + gram;
+    auto* st = reinterpret_cast<ProbState*>(partials + parts);
     ProbState hs{};
     hs.beta = 1.0;
     hs.fnorm = 1.0;
     hs.tol_eff = 0.0;
+    hs.vscale = 1.0;
     FDS_HIP(hipMemcpyAsync(st, &hs, sizeof(hs), hipMemcpyHostToDevice, s));
     KryTask t{};
     t.V = V; t.H = H; t.cs = H + (size_t)(m + 1) * m; t.sn = t.cs + m; t.g = t.sn + m; t.y = t.g + m + 1;
-    t.partials = partials; t.st = st; t.Nc = len; t.P = P; t.m = m;
-    auto* dt = reinterpret_cast<KryTask*>(reinterpret_cast<char*>(st) + 256);
+    t.partials = partials; t.st = st; t.Nc = len; t.P = P; t.m = m; t.G = G; t.hv = G + (size_t)(m + 1) * (m + 1);
+    t.nx = (int)std::min<int64_t>(len, 1 << 30); t.ny = 1;
+    KryTask gt = t;   // Gram columns of the existing basis (w implicit, no line terms)
+    gt.implicit_w = 1;
+    t.implicit_w = 0;
+    auto* dt = reinterpret_cast<KryTask*>(reinterpret_cast<char*>(st) + 512);
     FDS_HIP(hipMemcpyAsync(dt, &t, sizeof(t), hipMemcpyHostToDevice, s));
-    for (int i = 0; i <= j + 1; ++i) {
-      Timing::begin(3, s);
-      launch_mgs_pass(dt, 1, P, i, j, s);
-      Timing::end(3, s);
+    FDS_HIP(hipMemcpyAsync(dt + 1, &gt, sizeof(gt), hipMemcpyHostToDevice, s));
+    for (int c = 0; c < j; ++c) {
+      launch_gram_dots(dt + 1, 1, P, c, s);
+      launch_gram_solve(dt + 1, 1, c, s);
     }
+    Timing::begin(3, s);
+    launch_gram_dots(dt, 1, P, j, s);
+    Timing::end(3, s);
+    launch_gram_solve(dt, 1, j, s);
+    Timing::begin(6, s);
+    launch_gram_update(dt, 1, P, j, s);
+    Timing::end(6, s);
     // H column j holds h_{0..j, j} before the Givens rotations of the finish step
     FDS_HIP(hipMemcpyAsync(h, H + (size_t)j * (m + 1), 8 * (size_t)k, hipMemcpyDeviceToDevice, s));
-    launch_mgs_finish(dt, 1, P, j, s);
+    launch_mgs_finish(dt, 1, j, nullptr, 0, s);
+    launch_scale_newest(dt, j, std::max(1, std::min(P * kVecEPT, 1024)), s);
     FDS_HIP(hipMemcpyAsync(h + k, &st->last_hn, 8, hipMemcpyDeviceToDevice, s));
     FDS_HIP(hipGetLastError());
     FDS_HIP(hipStreamSynchronize(s));
@@ -406,7 +427,7 @@ fds_status fds_timing_enable(int32_t mask) {
 
 fds_status fds_timing_bytes(int32_t cls, double* algorithmic_bytes) {
   return guarded([&] {
-    if (cls < 0 || cls > 5 || !algorithmic_bytes) throw Error(FDS_E_INVALID_ARG, "bad timing arguments");
+    if (cls < 0 || cls >= TimingState::kClasses || !algorithmic_bytes) throw Error(FDS_E_INVALID_ARG, "bad timing arguments");
     *algorithmic_bytes = Timing::bytes(cls);
     return FDS_OK;
   });
@@ -414,7 +435,7 @@ fds_status fds_timing_bytes(int32_t cls, double* algorithmic_bytes) {
 
 fds_status fds_timing_read(int32_t cls, int64_t* calls, double* total_ms) {
   return guarded([&] {
-    if (cls < 0 || cls > 5 || !calls || !total_ms) throw Error(FDS_E_INVALID_ARG, "bad timing arguments");
+    if (cls < 0 || cls >= TimingState::kClasses || !calls || !total_ms) throw Error(FDS_E_INVALID_ARG, "bad timing arguments");
     long long c = 0;
     double ms = 0;
     Timing::read(cls, &c, &ms);

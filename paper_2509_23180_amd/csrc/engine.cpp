@@ -49,7 +49,8 @@ struct Slot {
   DevBuf mem;
   double *b_int = nullptr, *x_int = nullptr, *tmpd = nullptr, *fp = nullptr, *V = nullptr,
          *u = nullptr, *zbuf = nullptr, *lines = nullptr, *H = nullptr, *cs = nullptr,
-         *sn = nullptr, *g = nullptr, *y = nullptr, *partials = nullptr, *respart = nullptr;
+         *sn = nullptr, *g = nullptr, *y = nullptr, *partials = nullptr, *respart = nullptr,
+         *G = nullptr, *hv = nullptr, *zcols = nullptr;
   float *Z = nullptr, *tmpf = nullptr;
   ProbState* st = nullptr;
   long long Nc = 0, Nint = 0;
@@ -58,7 +59,8 @@ struct Slot {
 
 // Buffer layout of one problem, shared by allocation and footprint queries.
 struct SlotLayout {
-  size_t b_int, x_int, tmpd, fp, V, u, zbuf, lines, small, partials, respart, Z, tmpf, total;
+  size_t b_int, x_int, tmpd, fp, V, u, zbuf, lines, small, partials, respart, Z, tmpf, gram, zcols,
+      total;
 };
 
 int res_blocks_of(const fds_plan* p) {
@@ -85,7 +87,9 @@ SlotLayout layout_of(const fds_plan* p, int m, int precision) {
   L.zbuf = flex ? 0 : take(8 * Nc);
   L.lines = take(8 * 4 * (size_t)Lmax);
   L.small = take(8 * ((size_t)(m + 1) * m + 4 * (size_t)m + 2));
-  L.partials = take(8 * 4 * (size_t)P);
+  L.partials = take(8 * (size_t)(2 * (m + 1) + 4) * P);
+  L.gram = take(8 * ((size_t)(m + 1) * (m + 1) + (m + 1)));
+  L.zcols = take(8 * 2 * (size_t)p->ny);
   L.respart = take(8 * 2 * (size_t)res_blocks_of(p));
   L.Z = flex ? take(4 * (size_t)m * Nc) : 0;
   L.tmpf = flex ? take(4 * Nc) : 0;
@@ -104,16 +108,18 @@ struct Engine::Impl {
   std::vector<ProbState> host_states;
   TaskList<DstTask> it_fwd, it_inv, cyc_fwd, cyc_inv, arm_fwd, arm_inv, bs_fwd;
   TaskList<TriTask> it_tri, cyc_tri, arm_tri;
+  TriConfig it_tc{}, cyc_tc{}, arm_tc{};
   TaskList<LineTask> it_lines, x_lines;
+  TaskList<ColTask> it_cols;
   TaskList<OpTask> it_op, res_op;
   TaskList<KryTask> kry;
   TaskList<LiftTask> lift, gather;
   TaskList<IfaceTask> iface_fp, iface_bs;
   TaskList<ResTask> resid;
   size_t smem_lines = 0;
-  DevBuf active_dev;
-  int* active_host = nullptr;
-  std::vector<hipEvent_t> events;
+  int* flags_host = nullptr;      // per problem: serial of the last cycle that ended (mapped)
+  int* flags_dev = nullptr;
+  int cycle_serial = 0;
   bool set_up = false;
   std::vector<int> prev_its;
 
@@ -123,12 +129,11 @@ struct Engine::Impl {
   void account_arms(bool setup_phase);
 
   ~Impl() {
-    for (hipEvent_t e : events) (void)hipEventDestroy(e);
-    if (active_host) (void)hipHostFree(active_host);
+    if (flags_host) (void)hipHostFree(flags_host);
   }
 
   void build();
-  void iteration(int j);
+  void iteration(int j, int tag);
   void end_of_cycle();
   void read_states();
 };
@@ -162,6 +167,9 @@ void Engine::Impl::build() {
     sl.y = sl.g + (m + 1);
     sl.partials = sl.mem.as<double>(L.partials);
     sl.respart = sl.mem.as<double>(L.respart);
+    sl.G = sl.mem.as<double>(L.gram);
+    sl.hv = sl.G + (size_t)(m + 1) * (m + 1);
+    sl.zcols = sl.mem.as<double>(L.zcols);
     sl.Z = flex ? sl.mem.as<float>(L.Z) : nullptr;
     sl.tmpf = flex ? sl.mem.as<float>(L.tmpf) : nullptr;
     sl.st = states.as<ProbState>() + i;
@@ -170,6 +178,7 @@ void Engine::Impl::build() {
     hs.tol = sl.req.tol;
     hs.tol_eff = sl.req.tol;
     hs.floor_coef = p->floor_coef;
+    hs.vscale = 1.0;
 
     const RectDev& cd = p->rd[p->centre];
     const int nx = p->nx, ny = p->ny;
@@ -180,12 +189,18 @@ void Engine::Impl::build() {
     const int rpb_c = kBlock / dst_threads_per_row(nx);
     const size_t smem_c64 = dst_smem_bytes(nx, false), smem_c32 = dst_smem_bytes(nx, true);
 
-    // ---- per-iteration transforms of the centre
+    // ---- per-iteration transforms of the centre.  The forward transform
+    // also normalises v_j (ProbState::vscale).  Plain variant: the Schur
+    // lines need z = A_c^{-1} v_j only on the centre's boundary lines, taken
+    // from the sine coefficients (rows 0 / ny-1 by a line transform, columns
+    // 0 / nx-1 by row sums).  Flexible variant: z_j = M^{-1} v_j is stored in
+    // FP32 (Z) and the operator is applied to it in full.
     {
       DstTask t{};
-      t.in = sl.V; t.in_js = Nc; t.in_rs = nx; t.in_cs = 1;
+      t.in = sl.V; t.in_js = Nc; t.in_rs = nx; t.in_cs = 1; t.in_scale = &sl.st->vscale;
       t.out = flex ? (void*)sl.tmpf : (void*)sl.tmpd; t.out_js = 0; t.out_rs = nx; t.out_cs = 1;
       t.rows = ny; t.n = nx; t.rpb = rpb_c; t.scale = 1.0; t.fft = fftc; t.skip = skip_it;
+      t.tw_lds = dst_twiddles_in_lds(nx, flex);
       add_block_task(it_fwd, t, div_up(ny, rpb_c));
       it_fwd.smem = std::max(it_fwd.smem, flex ? smem_c32 : smem_c64);
 
@@ -195,20 +210,32 @@ void Engine::Impl::build() {
       tt.skip = skip_it;
       add_block_task(it_tri, tt, div_up(nx, kBlock));
 
-      DstTask v{};
-      v.in = t.out; v.in_js = 0; v.in_rs = nx; v.in_cs = 1;
-      if (flex) { v.out = sl.Z; v.out_js = Nc; }
-      else { v.out = sl.zbuf; v.out_js = 0; }
-      v.out_rs = nx; v.out_cs = 1;
-      v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = 1.0; v.fft = fftc; v.skip = skip_it;
-      add_block_task(it_inv, v, div_up(ny, rpb_c));
-      it_inv.smem = std::max(it_inv.smem, flex ? smem_c32 : smem_c64);
+      if (flex) {
+        DstTask v{};
+        v.in = t.out; v.in_js = 0; v.in_rs = nx; v.in_cs = 1;
+        v.out = sl.Z; v.out_js = Nc;
+        v.out_rs = nx; v.out_cs = 1;
+        v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = 1.0; v.fft = fftc; v.skip = skip_it;
+        v.tw_lds = dst_twiddles_in_lds(nx, true);
+        add_block_task(it_inv, v, div_up(ny, rpb_c));
+        it_inv.smem = std::max(it_inv.smem, smem_c32);
+      } else {
+        bool west = false, east = false;
+        for (const ArmInfo& a : p->arms) { west |= a.line == 2; east |= a.line == 3; }
+        if (west || east) {
+          ColTask ct{};
+          ct.y = sl.tmpd; ct.zw = west ? sl.zcols : nullptr; ct.ze = east ? sl.zcols + ny : nullptr;
+          ct.fft = fftc; ct.nx = nx; ct.ny = ny; ct.skip = skip_it;
+          add_block_task(it_cols, ct, div_up(ny, kBlock / 64));
+        }
+      }
     }
     // ---- end-of-cycle preconditioner apply (plain variant): u -> x_c += A_c^{-1} u
     if (!flex) {
       DstTask t{};
       t.in = sl.u; t.in_rs = nx; t.in_cs = 1; t.out = sl.tmpd; t.out_rs = nx; t.out_cs = 1;
       t.rows = ny; t.n = nx; t.rpb = rpb_c; t.scale = 1.0; t.fft = fftc; t.skip = skip_fin;
+      t.tw_lds = dst_twiddles_in_lds(nx, false);
       add_block_task(cyc_fwd, t, div_up(ny, rpb_c));
       cyc_fwd.smem = std::max(cyc_fwd.smem, smem_c64);
       TriTask tt{};
@@ -219,6 +246,7 @@ void Engine::Impl::build() {
       v.in = sl.tmpd; v.in_rs = nx; v.in_cs = 1; v.out = sl.x_int + cd.off; v.out_rs = nx;
       v.out_cs = 1; v.accumulate = 1;
       v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = 1.0; v.fft = fftc; v.skip = skip_fin;
+      v.tw_lds = dst_twiddles_in_lds(nx, false);
       add_block_task(cyc_inv, v, div_up(ny, rpb_c));
       cyc_inv.smem = std::max(cyc_inv.smem, smem_c64);
     }
@@ -243,9 +271,15 @@ void Engine::Impl::build() {
       ot.line[a.line] = lt.out;
       smem_lines = std::max(smem_lines, line_smem_bytes(a.L));
       LineTask li = lt;
-      if (flex) { li.z = sl.Z; li.z_js = Nc; li.z_f32 = 1; }
-      else { li.z = sl.zbuf; li.z_js = 0; li.z_f32 = 0; }
       li.skip = skip_it;
+      if (flex) {
+        li.z = sl.Z; li.z_js = Nc; li.z_f32 = 1;
+      } else if (a.line < 2) {
+        li.z = sl.tmpd; li.z_js = 0; li.z_f32 = 0; li.pre_dst = 1;   // sine coefficients of row 0 / ny-1
+      } else {
+        li.z = sl.zcols + (a.line == 3 ? ny : 0); li.z_js = 0; li.z_f32 = 0;
+        li.start = 0; li.stride = 1;
+      }
       it_lines.h.push_back(li);
       LineTask lx = lt;
       lx.z = sl.x_int + cd.off; lx.z_js = 0; lx.z_f32 = 0; lx.skip = skip_fin;
@@ -267,6 +301,7 @@ void Engine::Impl::build() {
       f.in = sl.b_int + ad.off; f.in_rs = a.L; f.in_cs = 1;
       f.out = sl.tmpd + ad.off; f.out_rs = a.L; f.out_cs = 1;
       f.rows = a.rows; f.n = a.L; f.rpb = rpb; f.scale = 1.0; f.fft = a.fft->dev; f.skip = nullptr;
+      f.tw_lds = dst_twiddles_in_lds(a.L, false);
       add_block_task(arm_fwd, f, div_up(a.rows, rpb));
       arm_fwd.smem = std::max(arm_fwd.smem, dst_smem_bytes(a.L, false));
       DstTask fb = f;
@@ -284,15 +319,16 @@ void Engine::Impl::build() {
     }
     iface_fp.h.push_back(fi);
     iface_bs.h.push_back(bi);
-    {
+    if (flex) {
       OpTask o = ot;
-      if (flex) { o.z = sl.Z; o.z_js = Nc; o.z_f32 = 1; }
-      else { o.z = sl.zbuf; o.z_js = 0; o.z_f32 = 0; }
+      o.z = sl.Z; o.z_js = Nc; o.z_f32 = 1;
       o.out = sl.V + Nc; o.out_js = Nc; o.skip = skip_it;
       add_block_task(it_op, o, sl.P);
+    }
+    {
       OpTask r = ot;
       r.z = sl.x_int + cd.off; r.z_js = 0; r.z_f32 = 0;
-      r.out = sl.V; r.out_js = 0; r.fp = sl.fp; r.partials = sl.partials + 2 * sl.P;
+      r.out = sl.V; r.out_js = 0; r.fp = sl.fp; r.partials = sl.partials + (size_t)kPartRes * sl.P;
       r.skip = skip_fin;
       add_block_task(res_op, r, sl.P);
     }
@@ -300,7 +336,9 @@ void Engine::Impl::build() {
       KryTask k{};
       k.V = sl.V; k.Z = sl.Z; k.x = sl.x_int + cd.off; k.u = sl.u; k.H = sl.H; k.cs = sl.cs;
       k.sn = sl.sn; k.g = sl.g; k.y = sl.y; k.partials = sl.partials; k.st = sl.st; k.Nc = Nc;
-      k.P = sl.P; k.m = m;
+      k.P = sl.P; k.m = m; k.G = sl.G; k.hv = sl.hv; k.nx = nx; k.ny = ny;
+      k.implicit_w = flex ? 0 : 1;
+      for (int q = 0; q < 4; ++q) k.line[q] = ot.line[q];
       add_block_task(kry, k, sl.P);
     }
     // ---- layout conversion and composite residual
@@ -331,9 +369,25 @@ void Engine::Impl::build() {
     }
   }
   for (auto* tl : {&it_fwd, &it_inv, &cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd}) tl->upload();
+  auto config_tri = [](TaskList<TriTask>& tl, bool fp32) {
+    int mmax = 1;
+    for (const TriTask& t : tl.h) mmax = std::max(mmax, t.rows);
+    const TriConfig c = tri_config(fp32, mmax);
+    int nb = 0;
+    for (TriTask& t : tl.h) {
+      t.block_begin = nb;
+      nb += tri_blocks(c, t.modes);
+    }
+    tl.nblocks = nb;
+    return c;
+  };
+  it_tc = config_tri(it_tri, flex);
+  cyc_tc = config_tri(cyc_tri, false);
+  arm_tc = config_tri(arm_tri, false);
   for (auto* tl : {&it_tri, &cyc_tri, &arm_tri}) tl->upload();
   it_lines.upload();
   x_lines.upload();
+  it_cols.upload();
   it_op.upload();
   res_op.upload();
   kry.upload();
@@ -342,40 +396,50 @@ void Engine::Impl::build() {
   iface_fp.upload();
   iface_bs.upload();
   resid.upload();
-  active_dev.alloc(sizeof(int) * (m + 1));
-  FDS_HIP(hipHostMalloc((void**)&active_host, sizeof(int) * (m + 1), hipHostMallocDefault));
-  events.resize(m);
-  for (int j = 0; j < m; ++j) FDS_HIP(hipEventCreateWithFlags(&events[j], hipEventDisableTiming));
+  FDS_HIP(hipHostMalloc((void**)&flags_host, sizeof(int) * n, hipHostMallocMapped | hipHostMallocCoherent));
+  std::memset(flags_host, 0, sizeof(int) * n);
+  FDS_HIP(hipHostGetDevicePointer((void**)&flags_dev, flags_host, 0));
 }
 
 // One Arnoldi step j of every unfinished problem.
-void Engine::Impl::iteration(int j) {
+void Engine::Impl::iteration(int j, int tag) {
   const DstKind fk = flex ? DstKind::D_F : DstKind::D_D;
-  const DstKind ik = flex ? DstKind::F_F : DstKind::D_D;
   Timing::begin(0, s);
   launch_dst(fk, it_fwd.dev(), it_fwd.n(), it_fwd.nblocks, it_fwd.smem, j, s);
   Timing::end(0, s);
   Timing::begin(1, s);
-  launch_tridiag(flex, it_tri.dev(), it_tri.n(), it_tri.nblocks, 0, s);
+  launch_tri(it_tc, flex, it_tri.dev(), it_tri.n(), it_tri.nblocks, 0, s);
   Timing::end(1, s);
-  Timing::begin(0, s);
-  launch_dst(ik, it_inv.dev(), it_inv.n(), it_inv.nblocks, it_inv.smem, j, s);
-  Timing::end(0, s);
+  if (flex) {
+    Timing::begin(0, s);
+    launch_dst(DstKind::F_F, it_inv.dev(), it_inv.n(), it_inv.nblocks, it_inv.smem, j, s);
+    Timing::end(0, s);
+  } else if (it_cols.n()) {
+    Timing::begin(7, s);
+    launch_idst_cols(it_cols.dev(), it_cols.n(), it_cols.nblocks, s);
+    Timing::end(7, s);
+  }
   if (it_lines.n()) {
     Timing::begin(4, s);
     launch_lines(it_lines.dev(), it_lines.n(), smem_lines, j, s);
     Timing::end(4, s);
   }
-  Timing::begin(2, s);
-  launch_operator(0, it_op.dev(), it_op.n(), it_op.nblocks, j, s);
-  Timing::end(2, s);
-  for (int i = 0; i <= j + 1; ++i) {
-    Timing::begin(3, s);
-    launch_mgs_pass(kry.dev(), kry.n(), kry.nblocks, i, j, s);
-    Timing::end(3, s);
+  if (flex) {
+    Timing::begin(2, s);
+    launch_operator(0, it_op.dev(), it_op.n(), it_op.nblocks, j, s);
+    Timing::end(2, s);
   }
+  Timing::begin(3, s);
+  launch_gram_dots(kry.dev(), kry.n(), kry.nblocks, j, s);
+  Timing::end(3, s);
   Timing::begin(5, s);
-  launch_mgs_finish(kry.dev(), kry.n(), kry.nblocks, j, s);
+  launch_gram_solve(kry.dev(), kry.n(), j, s);
+  Timing::end(5, s);
+  Timing::begin(6, s);
+  launch_gram_update(kry.dev(), kry.n(), kry.nblocks, j, s);
+  Timing::end(6, s);
+  Timing::begin(5, s);
+  launch_mgs_finish(kry.dev(), kry.n(), j, flags_dev, tag, s);
   Timing::end(5, s);
   FDS_HIP(hipGetLastError());
 }
@@ -390,7 +454,7 @@ void Engine::Impl::end_of_cycle() {
     launch_dst(DstKind::D_D, cyc_fwd.dev(), cyc_fwd.n(), cyc_fwd.nblocks, cyc_fwd.smem, 0, s);
     Timing::end(0, s);
     Timing::begin(1, s);
-    launch_tridiag(false, cyc_tri.dev(), cyc_tri.n(), cyc_tri.nblocks, 0, s);
+    launch_tri(cyc_tc, false, cyc_tri.dev(), cyc_tri.n(), cyc_tri.nblocks, 0, s);
     Timing::end(1, s);
     Timing::begin(0, s);
     launch_dst(DstKind::D_D, cyc_inv.dev(), cyc_inv.n(), cyc_inv.nblocks, cyc_inv.smem, 0, s);
@@ -452,7 +516,7 @@ void Engine::setup() {
     launch_dst(DstKind::D_D, I.arm_fwd.dev(), I.arm_fwd.n(), I.arm_fwd.nblocks, I.arm_fwd.smem, 0, s);
     Timing::end(0, s);
     Timing::begin(1, s);
-    launch_tridiag(false, I.arm_tri.dev(), I.arm_tri.n(), I.arm_tri.nblocks, 0, s);
+    launch_tri(I.arm_tc, false, I.arm_tri.dev(), I.arm_tri.n(), I.arm_tri.nblocks, 0, s);
     Timing::end(1, s);
     Timing::begin(0, s);
     launch_dst(DstKind::D_D, I.arm_inv.dev(), I.arm_inv.n(), I.arm_inv.nblocks, I.arm_inv.smem, 0, s);
@@ -485,17 +549,28 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
     const int its = host_states[i].iterations - before[i].iterations;
     double lines = 0;
     for (const ArmInfo& a : sl.plan->arms) lines += 16.0 * a.L;
-    // per Arnoldi step: forward transform reads v (8) writes scratch; tridiagonal
-    // solve reads and writes scratch; inverse transform reads scratch, writes z;
-    // operator reads z, writes w; MGS pass i reads w and v_i (and v_{i-1},
-    // writes w when i > 0)
-    Timing::add_bytes(0, its * Nc * ((8.0 + wz) + (wz + wz)));
+    // per Arnoldi step: the forward transform reads v_j, writes it back
+    // normalised and writes the scratch; the tridiagonal solve reads and
+    // writes the scratch.  Flexible: the inverse transform writes z_j and
+    // the operator reads z_j and writes w.  Plain: the boundary columns read
+    // the scratch once.  Gram dots read v_0..v_j (and w if stored), the
+    // update reads v_0..v_j (and w if stored) and writes w.
+    Timing::add_bytes(0, its * Nc * (8.0 + 8.0 + wz));
     Timing::add_bytes(1, its * Nc * 2.0 * wz);
-    Timing::add_bytes(2, its * Nc * (wz + 8.0));
+    if (flex) {
+      Timing::add_bytes(0, its * Nc * (wz + wz));
+      Timing::add_bytes(2, its * Nc * (wz + 8.0));
+    } else {
+      Timing::add_bytes(7, its * Nc * 8.0);
+    }
     Timing::add_bytes(4, its * lines);
-    double mgs = 0;
-    for (int j = 0; j < its; ++j) mgs += 40.0 + 32.0 * j;
-    Timing::add_bytes(3, mgs * Nc);
+    double dots = 0, upd = 0;
+    for (int j = 0; j < its; ++j) {
+      dots += 8.0 * (j + 1) + (flex ? 8.0 : 0.0);
+      upd += 8.0 * (j + 1) + 8.0 + (flex ? 8.0 : 0.0);
+    }
+    Timing::add_bytes(3, dots * Nc);
+    Timing::add_bytes(6, upd * Nc);
     // end of cycle: plain variant applies A_c^{-1} to V y (transforms and
     // tridiagonal solve in FP64, accumulate into x); residual operator reads
     // x and f', writes r; line terms of x
@@ -531,16 +606,18 @@ bool Engine::step_cycle() {
   for (const ProbState& st : I.host_states) any |= !st.finished;
   if (!any) return false;
   const std::vector<ProbState> before = I.host_states;
-  hipStream_t s = I.s;
+  const int tag = ++I.cycle_serial;
   for (int j = 0; j < I.m; ++j) {
     if (j >= 2) {
-      if (hipEventQuery(I.events[j - 2]) == hipSuccess && I.active_host[j - 2] == 0) break;
+      // stop launching once every running problem reported the end of this
+      // cycle (the finish kernel writes the tag to mapped host memory)
+      bool all = true;
+      const volatile int* fl = I.flags_host;
+      for (size_t p = 0; p < I.slots.size() && all; ++p)
+        if (!before[p].finished && fl[p] != tag) all = false;
+      if (all) break;
     }
-    I.iteration(j);
-    launch_count_active(I.states.as<ProbState>(), (int)I.slots.size(), I.active_dev.as<int>() + j, s);
-    FDS_HIP(hipMemcpyAsync(I.active_host + j, I.active_dev.as<int>() + j, sizeof(int),
-                           hipMemcpyDeviceToHost, s));
-    FDS_HIP(hipEventRecord(I.events[j], s));
+    I.iteration(j, tag);
   }
   I.end_of_cycle();
   I.read_states();
@@ -567,7 +644,7 @@ std::vector<SolveOutcome> Engine::finalize() {
     launch_dst(DstKind::D_D, I.bs_fwd.dev(), I.bs_fwd.n(), I.bs_fwd.nblocks, I.bs_fwd.smem, 0, s);
     Timing::end(0, s);
     Timing::begin(1, s);
-    launch_tridiag(false, I.arm_tri.dev(), I.arm_tri.n(), I.arm_tri.nblocks, 0, s);
+    launch_tri(I.arm_tc, false, I.arm_tri.dev(), I.arm_tri.n(), I.arm_tri.nblocks, 0, s);
     Timing::end(1, s);
     Timing::begin(0, s);
     launch_dst(DstKind::D_D, I.arm_inv.dev(), I.arm_inv.n(), I.arm_inv.nblocks, I.arm_inv.smem, 0, s);

@@ -92,6 +92,8 @@ struct ProbState {
   double xnorm;
   double floor_coef;   // unit roundoff times a bound of ||L_c||_inf
   double last_hn;      // h_{j+1,j} of the latest Arnoldi step
+  double vscale;       // factor that normalises the newest basis vector V[j]
+  double pad3;
 };
 
 // ---------------------------------------------------------------- task records
@@ -106,9 +108,12 @@ struct DstTask {
   int rows, n;
   int rpb;                    // rows per block
   int accumulate;             // out += result
+  int tw_lds;                 // 1: stage the twiddles in LDS ahead of the row buffers
+  int pad0;
   double scale;
   const FftDesc* fft;
   const int* skip;            // skip when *skip != 0
+  const double* in_scale;     // if set: input *= *in_scale, written back in place
   int block_begin;
   int pad;
 };
@@ -132,6 +137,8 @@ struct LineTask {
   long long stride;           // element stride along the line
   int L;
   int z_f32;
+  int pre_dst;                // 1: the line holds sine coefficients; transform them first
+  int pad;
   const FftDesc* fft;
   const double* gs;           // delta^2 (2/N) g_k, k = 1..L
   double* out;                // L doubles
@@ -168,14 +175,23 @@ struct KryTask {
   double* sn;
   double* g;                  // m+1
   double* y;                  // m
-  double* partials;           // 4 x P: MGS ping-pong (2P), residual r^2 and x^2 (2P)
+  double* partials;           // (2(m+1) + 4) x P block partials, see kPart*
+  double* G;                  // (m+1) x (m+1) Gram matrix <v_i, v_j>, column-major
+  double* hv;                 // m+1 Gram-Schmidt coefficients of the current step
   ProbState* st;
   long long Nc;
   int P;                      // blocks covering Nc
   int m;
+  int nx, ny;
+  int implicit_w;             // 1: w = v_j - s (exact preconditioner), 0: w stored in V[j+1]
   int block_begin;
-  int pad;
+  const double* line[4];      // Schur line terms s on the centre's boundary lines (or NULL)
 };
+
+// partial-sum slots (each P wide) inside KryTask::partials
+constexpr int kPartRes = 0;   // residual r^2 (P) and x^2 (P)
+constexpr int kPartNorm = 2;  // ||w||^2
+constexpr int kPartDots = 3;  // 2(m+1) dot products
 
 // Rectangle of a problem in the library's internal layout: rows x cols with
 // the sine-transform axis (cols) contiguous.  Global node of element (r, c):
@@ -193,6 +209,19 @@ struct RectDev {
   // neighbour lines across internal sides: 0: r=-1, 1: r=rows, 2: c=-1, 3: c=cols
   long long halo_off[4];      // -1 if Dirichlet
   long long halo_stride[4];
+};
+
+// Boundary columns of z = S y for every row of the sine coefficients y:
+// z[r][0] = sum_k y[r][k] sin(pi k/N), z[r][nx-1] = sum_k y[r][k] (-1)^{k+1} sin(pi k/N).
+struct ColTask {
+  const double* y;
+  double* zw;                 // column 0 (ny values) or NULL
+  double* ze;                 // column nx-1 or NULL
+  const FftDesc* fft;
+  int nx, ny;
+  const int* skip;
+  int block_begin;
+  int pad;
 };
 
 struct LiftTask {

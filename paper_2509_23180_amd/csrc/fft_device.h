@@ -181,9 +181,8 @@ __device__ C2<T>* stockham_lds(C2<T>* a, C2<T>* b, int L, int npass, const int* 
 // Complex FFT of length f.N of the data in LDS buffer `a` (scratch `b`; both
 // hold max(N, L) entries).  Returns the buffer holding the N outputs.
 template <typename T>
-__device__ C2<T>* fft_lds(C2<T>* a, C2<T>* b, const FftDesc& f, int g, int G) {
+__device__ C2<T>* fft_lds(C2<T>* a, C2<T>* b, const FftDesc& f, const C2<T>* tw, int g, int G) {
   using C = C2<T>;
-  const C* tw = fft_tw<T>(f);
   if (f.kind == FFT_MIXED) return stockham_lds<T>(a, b, f.N, f.npass, f.radix, tw, g, G);
   const int N = f.N, L = f.L;
   const C* K = fft_kern<T>(f);
@@ -259,6 +258,15 @@ __device__ __forceinline__ T dst_post(const C2<T>* C, const C2<T>* post, int N, 
   const T dre = A.x - Bc.x;
   const T dim = A.y + Bc.y;
   return T(-0.25) * (imsum - (w.x * dre + w.y * dim));
+}
+
+// Copy the twiddle table of the Stockham FFT into LDS (whole block).
+template <typename T>
+__device__ __forceinline__ const C2<T>* stage_twiddles(const FftDesc& f, C2<T>* lds, bool use) {
+  const C2<T>* tw = fft_tw<T>(f);
+  if (!use) return tw;
+  for (int t = threadIdx.x; t < f.L; t += blockDim.x) lds[t] = tw[t];
+  return lds;
 }
 
 // ---------------------------------------------------------------- reductions

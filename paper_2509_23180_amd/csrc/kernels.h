@@ -14,11 +14,24 @@ void launch_dst(DstKind kind, const DstTask* tasks, int ntasks, int nblocks, siz
                 hipStream_t s);
 void launch_tridiag(bool fp32, const TriTask* tasks, int ntasks, int nblocks, int jidx,
                     hipStream_t s);
+// Choice of tridiagonal kernel for a launch whose longest system has
+// max_rows rows: the segmented kernel (register segments of `ls` rows, `mpb`
+// modes per block, `threads` per block) when the rows fit, else one lane per
+// mode sweeping the rows.
+struct TriConfig { bool seg; int ls; int mpb; int threads; };
+TriConfig tri_config(bool fp32, int max_rows);
+int tri_blocks(const TriConfig& c, int modes);
+void launch_tri(const TriConfig& c, bool fp32, const TriTask* tasks, int ntasks, int nblocks,
+                int jidx, hipStream_t s);
 void launch_lines(const LineTask* tasks, int ntasks, size_t smem, int jidx, hipStream_t s);
 void launch_operator(int mode, const OpTask* tasks, int ntasks, int nblocks, int jidx,
                      hipStream_t s);
-void launch_mgs_pass(const KryTask* tasks, int ntasks, int nblocks, int i, int j, hipStream_t s);
-void launch_mgs_finish(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s);
+void launch_gram_dots(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s);
+void launch_gram_solve(const KryTask* tasks, int ntasks, int j, hipStream_t s);
+void launch_gram_update(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s);
+void launch_mgs_finish(const KryTask* tasks, int ntasks, int j, int* flags, int tag, hipStream_t s);
+void launch_scale_newest(const KryTask* tasks, int j, int nblocks, hipStream_t s);
+void launch_idst_cols(const ColTask* tasks, int ntasks, int nblocks, hipStream_t s);
 void launch_ls_solve(const KryTask* tasks, int ntasks, hipStream_t s);
 void launch_combine(bool flex, const KryTask* tasks, int ntasks, int nblocks, hipStream_t s);
 void launch_restart(const KryTask* tasks, int ntasks, int nblocks, int initial, int max_cycles,

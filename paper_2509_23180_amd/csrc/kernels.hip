@@ -25,16 +25,30 @@ __global__ void __launch_bounds__(kBlock) k_dst_rows(const DstTask* __restrict__
   const int g = threadIdx.x - grp * G;
   const int row = (blockIdx.x - tk.block_begin) * tk.rpb + grp;
   const bool valid = row < tk.rows;
-  C2<T>* A = reinterpret_cast<C2<T>*>(smem_raw) + (size_t)grp * 2 * f.W;
+  C2<T>* twl = reinterpret_cast<C2<T>*>(smem_raw);
+  C2<T>* A = twl + (tk.tw_lds ? f.L : 0) + (size_t)grp * 2 * f.W;
   C2<T>* B = A + f.W;
+  const C2<T>* tw = stage_twiddles<T>(f, twl, tk.tw_lds != 0);
   const TIn* in = static_cast<const TIn*>(tk.in) + (long long)jidx * tk.in_js +
                   (long long)(valid ? row : 0) * tk.in_rs;
   const long long ics = tk.in_cs;
-  if (valid) {
+  if (tk.in_scale) {
+    // normalise the basis vector while reading it and write it back once
+    const double sc = *tk.in_scale;
+    if (valid) dst_pack<T>(A, N, g, G, [&](int j) { return T(double(in[(long long)(j - 1) * ics]) * sc); });
+    __syncthreads();
+    if (valid) {
+      TIn* inw = const_cast<TIn*>(in);
+      for (int j = 1 + g; j <= n; j += G) {
+        const double v = double(in[(long long)(j - 1) * ics]) * sc;
+        inw[(long long)(j - 1) * ics] = TIn(v);
+      }
+    }
+  } else if (valid) {
     dst_pack<T>(A, N, g, G, [&](int j) { return T(in[(long long)(j - 1) * ics]); });
   }
   __syncthreads();
-  const C2<T>* Cr = fft_lds<T>(A, B, f, g, G);
+  const C2<T>* Cr = fft_lds<T>(A, B, f, tw, g, G);
   if (valid) {
     TOut* out = static_cast<TOut*>(tk.out) + (long long)jidx * tk.out_js + (long long)row * tk.out_rs;
     const C2<T>* post = fft_post<T>(f);
@@ -84,6 +98,139 @@ __global__ void __launch_bounds__(kBlock) k_tridiag(const TriTask* __restrict__ 
   }
 }
 
+
+// Segmented variant: a block serves MPB consecutive modes and splits the rows
+// into segments of LS rows held in registers, one segment per thread
+// (thread t: mode t % MPB, segment t / MPB).  Both first-order recurrences
+// are solved per segment with a zero carry; the carries follow in closed form
+// (constant coefficient q):
+//   forward  w_{i0+t} = w_loc_t + q^{t+1} c,        c = w_{i0-1}
+//            sum_i q^i w_i = sum_s q^{i0}(A_s + c_s q (1-q^{2L})/(1-q^2))
+//   backward y_{i0+t} = y_loc_t + q^{L-t} d,        d = y_{i0+L}
+// so the data is read once and written once.
+template <typename T, int LS, int MPB>
+__global__ void __launch_bounds__(1024) k_tridiag_seg(const TriTask* __restrict__ tasks, int ntasks,
+                                                       int jidx) {
+  constexpr int SEGMAX = 1024 / MPB;
+  __shared__ int slot;
+  __shared__ T sa[SEGMAX][MPB];
+  __shared__ T sb[SEGMAX][MPB];
+  __shared__ T sg[MPB];
+  const TriTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  if (tk.skip && *tk.skip) return;
+  const int lane = threadIdx.x % MPB;
+  const int s = threadIdx.x / MPB;
+  const int m = tk.rows;
+  const int S = (m + LS - 1) / LS;
+  const int k = (blockIdx.x - tk.block_begin) * MPB + lane;
+  const bool act = k < tk.modes && s < S;
+  const int i0 = s * LS;
+  const int L = act ? min(LS, m - i0) : 0;
+  ModeCoef<T> c{};
+  if (k < tk.modes) c = static_cast<const ModeCoef<T>*>(tk.coef)[k];
+  const int rs = (int)tk.rs;
+  T* d = static_cast<T*>(tk.data) + (long long)jidx * tk.js + (long long)i0 * rs + (k < tk.modes ? k : 0);
+  T x[LS];
+#pragma unroll
+  for (int t = 0; t < LS; ++t) x[t] = (t < L) ? d[t * rs] : T(0);
+  // local forward sweep
+  T w = T(0), A = T(0), p = T(1);
+#pragma unroll
+  for (int t = 0; t < LS; ++t) {
+    if (t < L) {
+      w = c.sc * x[t] + c.q * w;
+      x[t] = w;
+      A += p * w;
+      p *= c.q;
+    }
+  }
+  if (act) {
+    sa[s][lane] = w;
+    sb[s][lane] = A;
+  }
+  __syncthreads();
+  if (s == 0 && k < tk.modes) {
+    // forward carries, the first-row weight sum and gamma
+    T carry = T(0), qi0 = T(1), stot = T(0);
+    T qLf = T(1), Bf = T(0), q2 = c.q;
+    for (int t = 0; t < LS; ++t) { Bf += q2; q2 *= c.q * c.q; qLf *= c.q; }
+    for (int ss = 0; ss < S; ++ss) {
+      const int Ls = min(LS, m - ss * LS);
+      T qL = qLf, B = Bf;
+      if (Ls != LS) {
+        qL = T(1); B = T(0); q2 = c.q;
+        for (int t = 0; t < Ls; ++t) { B += q2; q2 *= c.q * c.q; qL *= c.q; }
+      }
+      const T E = sa[ss][lane], As = sb[ss][lane];
+      stot += qi0 * (As + carry * B);
+      sa[ss][lane] = carry;
+      sb[ss][lane] = qi0;
+      carry = E + qL * carry;
+      qi0 *= qL;
+    }
+    sg[lane] = c.beta * stot;
+  }
+  __syncthreads();
+  T y = T(0);
+  if (act) {
+    const T cin = sa[s][lane], qi0 = sb[s][lane], gam = sg[lane];
+    T pc = c.q, pg = qi0;
+#pragma unroll
+    for (int t = 0; t < LS; ++t) {
+      if (t < L) {
+        x[t] = x[t] + pc * cin - gam * pg;
+        pc *= c.q;
+        pg *= c.q;
+      }
+    }
+#pragma unroll
+    for (int t = LS - 1; t >= 0; --t) {
+      if (t < L) {
+        y = x[t] + c.q * y;
+        x[t] = y;
+      }
+    }
+    sa[s][lane] = y;
+  }
+  __syncthreads();
+  if (s == 0 && k < tk.modes) {
+    T qLf = T(1);
+    for (int t = 0; t < LS; ++t) qLf *= c.q;
+    T dc = T(0);
+    for (int ss = S - 1; ss >= 0; --ss) {
+      const int Ls = min(LS, m - ss * LS);
+      T qL = qLf;
+      if (Ls != LS) {
+        qL = T(1);
+        for (int t = 0; t < Ls; ++t) qL *= c.q;
+      }
+      const T D = sa[ss][lane];
+      sb[ss][lane] = dc;
+      dc = D + qL * dc;
+    }
+  }
+  __syncthreads();
+  if (act) {
+    const T din = sb[s][lane];
+    T pw = c.q;
+#pragma unroll
+    for (int t = LS - 1; t >= 0; --t) {
+      if (t < L) {
+        x[t] += pw * din;
+        pw *= c.q;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < LS; ++t)
+      if (t < L) d[t * rs] = x[t];
+  }
+}
+
+__device__ __forceinline__ double A_line(const LineTask& tk, int jidx, int k) {
+  const double* z = static_cast<const double*>(tk.z) + (long long)jidx * tk.z_js + tk.start;
+  return z[(long long)(k - 1) * tk.stride];
+}
+
 // =====================================================================
 // Schur line terms: out = delta^2 (2/N) S diag(g) S z_line (FP64).
 // One block per line; two sine transforms in LDS.
@@ -95,12 +242,16 @@ __global__ void __launch_bounds__(kBlock) k_schur_lines(const LineTask* __restri
   const FftDesc& f = *tk.fft;
   const int N = f.N;
   const int L = tk.L;
-  double2* A = reinterpret_cast<double2*>(smem_raw);
+  double2* twl = reinterpret_cast<double2*>(smem_raw);
+  double2* A = twl + f.L;
   double2* B = A + f.W;
   double* mid = reinterpret_cast<double*>(B + f.W);
+  const double2* tw = stage_twiddles<double>(f, twl, true);
   const int g = threadIdx.x;
   const long long st = tk.stride;
-  if (tk.z_f32) {
+  if (tk.pre_dst) {
+    // nothing to transform before the diagonal scaling
+  } else if (tk.z_f32) {
     const float* z = static_cast<const float*>(tk.z) + (long long)jidx * tk.z_js + tk.start;
     dst_pack<double>(A, N, g, kBlock, [&](int j) { return double(z[(long long)(j - 1) * st]); });
   } else {
@@ -108,13 +259,44 @@ __global__ void __launch_bounds__(kBlock) k_schur_lines(const LineTask* __restri
     dst_pack<double>(A, N, g, kBlock, [&](int j) { return z[(long long)(j - 1) * st]; });
   }
   __syncthreads();
-  const double2* C = fft_lds<double>(A, B, f, g, kBlock);
-  for (int k = 1 + g; k <= L; k += kBlock) mid[k - 1] = tk.gs[k - 1] * dst_post<double>(C, f.post64, N, k);
+  const double2* C = tk.pre_dst ? A : fft_lds<double>(A, B, f, tw, g, kBlock);
+  if (tk.pre_dst) {
+    // the line holds the sine coefficients y of z (z = S y); since
+    // S S = (N/2) I the term is delta^2 (2/N) S diag(g) S S y = (N/2) S (gs o y)
+    const double half = 0.5 * N;
+    for (int k = 1 + g; k <= L; k += kBlock) mid[k - 1] = half * tk.gs[k - 1] * A_line(tk, jidx, k);
+  } else {
+    for (int k = 1 + g; k <= L; k += kBlock) mid[k - 1] = tk.gs[k - 1] * dst_post<double>(C, f.post64, N, k);
+  }
   __syncthreads();
   dst_pack<double>(A, N, g, kBlock, [&](int j) { return mid[j - 1]; });
   __syncthreads();
-  C = fft_lds<double>(A, B, f, g, kBlock);
+  C = fft_lds<double>(A, B, f, tw, g, kBlock);
   for (int k = 1 + g; k <= L; k += kBlock) tk.out[k - 1] = dst_post<double>(C, f.post64, N, k);
+}
+
+// Boundary columns of z = S y (see ColTask): one wave per row.
+__global__ void __launch_bounds__(kBlock) k_idst_cols(const ColTask* __restrict__ tasks, int ntasks) {
+  __shared__ int slot;
+  const ColTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  if (tk.skip && *tk.skip) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = (blockIdx.x - tk.block_begin) * (kBlock / 64) + wave;
+  if (r >= tk.ny) return;
+  const double* y = tk.y + (long long)r * tk.nx;
+  const double2* post = tk.fft->post64;
+  double odd = 0.0, even = 0.0;   // k odd / k even (k = 1..nx)
+  for (int k = 1 + lane; k <= tk.nx; k += 64) {
+    const double v = y[k - 1] * post[k].y;
+    if (k & 1) odd += v;
+    else even += v;
+  }
+  odd = wave_sum(odd);
+  even = wave_sum(even);
+  if (lane == 0) {
+    if (tk.zw) tk.zw[r] = odd + even;
+    if (tk.ze) tk.ze[r] = odd - even;
+  }
 }
 
 // =====================================================================
@@ -177,100 +359,238 @@ __global__ void __launch_bounds__(kBlock) k_operator(const OpTask* __restrict__ 
 }
 
 // =====================================================================
-// Arnoldi, modified Gram-Schmidt.  Pass i (0 <= i <= j+1) of step j:
-//   i > 0:   h_{i-1,j} = sum of the previous pass's partials;
-//            w -= h_{i-1,j} v_{i-1}
-//   i <= j:  partials of <w, v_i>;  i == j+1: partials of <w, w>
-// w lives in V[j+1].
+// Arnoldi step j with modified Gram-Schmidt in compact (one-reduction) form
+// (Swirydowicz, Langou, Ananthan, Yang, Thomas, "Low synchronization
+// Gram-Schmidt and GMRES algorithms", 2021).  MGS takes
+//   h_i = <w - sum_{l<i} h_l v_l, v_i> = <w, v_i> - sum_{l<i} h_l <v_l, v_i>,
+// so one pass computing the Gram column <v_i, v_j> and the projections
+// <w, v_i>, a triangular recurrence and one update pass give the same
+// coefficients as the i-by-i passes.
+// w is either stored in V[j+1] (flexible variant: w = L_c z_j) or implicit,
+// w = v_j - s with s the Schur line terms on the boundary lines (plain
+// variant: L_c A_c^{-1} v = v - S A_c^{-1} v).
 // =====================================================================
-__global__ void __launch_bounds__(kBlock) k_mgs_pass(const KryTask* __restrict__ tasks, int ntasks,
-                                                      int i, int j) {
+__device__ __forceinline__ double line_term(const KryTask& tk, long long idx) {
+  const int r = (int)(idx / tk.nx);
+  const int c = (int)(idx - (long long)r * tk.nx);
+  double s = 0.0;
+  if (r == 0 && tk.line[0]) s += tk.line[0][c];
+  if (r == tk.ny - 1 && tk.line[1]) s += tk.line[1][c];
+  if (c == 0 && tk.line[2]) s += tk.line[2][r];
+  if (c == tk.nx - 1 && tk.line[3]) s += tk.line[3][r];
+  return s;
+}
+
+// Block partials of <v_i, v_j> (i <= j) and of <v_i, u> with u = w when w is
+// stored, u = s (the Schur line terms, zero off the boundary) otherwise.
+__global__ void __launch_bounds__(kBlock) k_gram_dots(const KryTask* __restrict__ tasks, int ntasks,
+                                                       int j) {
   __shared__ int slot;
-  __shared__ double red[4];
+  __shared__ double red[2 * 121][4];
   const KryTask& tk = tasks[find_task(tasks, ntasks, &slot)];
   if (tk.st->cycle_done) return;
   const int b = blockIdx.x - tk.block_begin;
   const long long Nc = tk.Nc;
-  const int P = tk.P;
-  double* w = tk.V + (long long)(j + 1) * Nc;
-  double hprev = 0.0;
-  if (i > 0) {
-    hprev = sum_partials(tk.partials + ((i - 1) & 1) * P, P, red);
-    if (b == 0 && threadIdx.x == 0) tk.H[(i - 1) + j * (tk.m + 1)] = hprev;
-  }
-  const double* vprev = tk.V + (long long)(i > 0 ? i - 1 : 0) * Nc;
-  const double* vi = tk.V + (long long)(i <= j ? i : 0) * Nc;
-  double acc = 0.0;
   const long long base = (long long)b * kVecPerBlock;
+  const bool stored = !tk.implicit_w;
+  double xj[kVecEPT], uv[kVecEPT];
+  const double* vj = tk.V + (long long)j * Nc;
+  const double* w = tk.V + (long long)(j + 1) * Nc;
+#pragma unroll
+  for (int e = 0; e < kVecEPT; ++e) {
+    const long long idx = base + (long long)e * kBlock + threadIdx.x;
+    const bool ok = idx < Nc;
+    xj[e] = ok ? vj[idx] : 0.0;
+    uv[e] = !ok ? 0.0 : (stored ? w[idx] : line_term(tk, idx));
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = 0; i <= j; ++i) {
+    const double* vi = tk.V + (long long)i * Nc;
+    double a = 0.0, c = 0.0;
+#pragma unroll
+    for (int e = 0; e < kVecEPT; ++e) {
+      const long long idx = base + (long long)e * kBlock + threadIdx.x;
+      const double v = (i == j) ? xj[e] : ((idx < Nc) ? vi[idx] : 0.0);
+      a += v * xj[e];
+      c += v * uv[e];
+    }
+    a = wave_sum(a);
+    c = wave_sum(c);
+    if (lane == 0) {
+      red[i][wave] = a;
+      red[121 + i][wave] = c;
+    }
+  }
+  __syncthreads();
+  const int nd = j + 1;
+  for (int t = threadIdx.x; t < 2 * nd; t += kBlock) {
+    const int row = t < nd ? t : 121 + (t - nd);
+    const double s = (red[row][0] + red[row][1]) + (red[row][2] + red[row][3]);
+    tk.partials[(size_t)(kPartDots + t) * tk.P + b] = s;
+  }
+}
+
+// One block per problem: reduce the dot partials, store the Gram column,
+// form <w, v_i>, run the MGS recurrence for h and store column j of H.
+// The recurrence h_i = a_i - sum_{l<i} h_l G_li runs in LDS: after h_l is
+// final every i > l subtracts h_l G_li in parallel.
+__global__ void __launch_bounds__(kBlock) k_gram_solve(const KryTask* __restrict__ tasks, int ntasks,
+                                                        int j) {
+  __shared__ double dots[2 * 121];
+  __shared__ double a[121];
+  __shared__ double Gt[121 * 121 / 2 + 121];
+  const KryTask& tk = tasks[blockIdx.x];
+  if (tk.st->cycle_done) return;
+  const int nd = j + 1;
+  const int P = tk.P;
+  const int m1 = tk.m + 1;
+  for (int t = threadIdx.x; t < 2 * nd; t += kBlock) {
+    const double* p = tk.partials + (size_t)(kPartDots + t) * P;
+    double s = 0.0;
+    for (int q = 0; q < P; ++q) s += p[q];
+    dots[t] = s;
+  }
+  // strictly upper triangle G_li (l < i <= j), column i at offset i(i-1)/2;
+  // column j is this step's dots
+  const int ntri = nd * (nd - 1) / 2;
+  for (int e = threadIdx.x; e < ntri; e += kBlock) {
+    int i = (int)((1.0 + sqrt(1.0 + 8.0 * e)) * 0.5);
+    while (i * (i - 1) / 2 > e) --i;
+    while ((i + 1) * i / 2 <= e) ++i;
+    const int l = e - i * (i - 1) / 2;
+    Gt[e] = (i < j) ? tk.G[l + i * m1] : -1.0;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nd; t += kBlock) {
+    tk.G[t + j * m1] = dots[t];
+    a[t] = tk.implicit_w ? dots[t] - dots[nd + t] : dots[nd + t];
+  }
+  for (int l = threadIdx.x; l < j; l += kBlock) Gt[j * (j - 1) / 2 + l] = dots[l];
+  __syncthreads();
+  for (int l = 0; l < nd; ++l) {
+    const double hl = a[l];
+    __syncthreads();
+    for (int i = l + 1 + threadIdx.x; i < nd; i += kBlock) a[i] -= hl * Gt[i * (i - 1) / 2 + l];
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < nd; i += kBlock) {
+    tk.hv[i] = a[i];
+    tk.H[i + j * m1] = a[i];
+  }
+}
+
+// w_new = w - sum_i h_i v_i  -> V[j+1], with block partials of ||w_new||^2.
+__global__ void __launch_bounds__(kBlock) k_gram_update(const KryTask* __restrict__ tasks, int ntasks,
+                                                         int j) {
+  __shared__ int slot;
+  __shared__ double red[4];
+  __shared__ double hs[121];
+  const KryTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  if (tk.st->cycle_done) return;
+  for (int i = threadIdx.x; i <= j; i += kBlock) hs[i] = tk.hv[i];
+  __syncthreads();
+  const int b = blockIdx.x - tk.block_begin;
+  const long long Nc = tk.Nc;
+  const long long base = (long long)b * kVecPerBlock;
+  double* w = tk.V + (long long)(j + 1) * Nc;
+  const double* vj = tk.V + (long long)j * Nc;
+  double acc[kVecEPT], xj[kVecEPT];
+#pragma unroll
+  for (int e = 0; e < kVecEPT; ++e) {
+    const long long idx = base + (long long)e * kBlock + threadIdx.x;
+    const bool ok = idx < Nc;
+    xj[e] = ok ? vj[idx] : 0.0;
+    acc[e] = !ok ? 0.0 : (tk.implicit_w ? xj[e] - line_term(tk, idx) : w[idx]);
+  }
+  for (int i = 0; i < j; ++i) {
+    const double* vi = tk.V + (long long)i * Nc;
+    const double h = hs[i];
+#pragma unroll
+    for (int e = 0; e < kVecEPT; ++e) {
+      const long long idx = base + (long long)e * kBlock + threadIdx.x;
+      if (idx < Nc) acc[e] -= h * vi[idx];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kVecEPT; ++e) acc[e] -= hs[j] * xj[e];
+  double nrm = 0.0;
 #pragma unroll
   for (int e = 0; e < kVecEPT; ++e) {
     const long long idx = base + (long long)e * kBlock + threadIdx.x;
     if (idx < Nc) {
-      double wv = w[idx];
-      if (i > 0) {
-        wv -= hprev * vprev[idx];
-        w[idx] = wv;
-      }
-      acc += (i <= j) ? wv * vi[idx] : wv * wv;
+      w[idx] = acc[e];
+      nrm += acc[e] * acc[e];
     }
   }
-  const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) tk.partials[(i & 1) * P + b] = s;
+  const double s = block_sum(nrm, red);
+  if (threadIdx.x == 0) tk.partials[(size_t)kPartNorm * tk.P + b] = s;
 }
 
-// Norm, normalisation of v_{j+1}, Givens update of column j and the
-// convergence test on |g_{j+1}| (block 0, thread 0).
+// One block per problem: h_{j+1,j} = ||w||, Givens update of column j and
+// the convergence test on |g_{j+1}|.  V[j+1] is normalised by the next
+// step's sine transform (ProbState::vscale).  When the problem's cycle ends,
+// `flag` (host-visible) receives `tag`.
 __global__ void __launch_bounds__(kBlock) k_mgs_finish(const KryTask* __restrict__ tasks, int ntasks,
-                                                        int j) {
-  __shared__ int slot;
+                                                        int j, int* flags, int tag) {
   __shared__ double red[4];
-  const KryTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  __shared__ double col[122];
+  __shared__ double cs[121], sn[121];
+  const KryTask& tk = tasks[blockIdx.x];
   ProbState* st = tk.st;
   if (st->cycle_done) return;
-  const int b = blockIdx.x - tk.block_begin;
-  const long long Nc = tk.Nc;
-  const double nrm2 = sum_partials(tk.partials + ((j + 1) & 1) * tk.P, tk.P, red);
+  const int m1 = tk.m + 1;
+  for (int i = threadIdx.x; i <= j; i += kBlock) col[i] = tk.H[i + j * m1];
+  for (int i = threadIdx.x; i < j; i += kBlock) {
+    cs[i] = tk.cs[i];
+    sn[i] = tk.sn[i];
+  }
+  const double nrm2 = sum_partials(tk.partials + (size_t)kPartNorm * tk.P, tk.P, red);
+  if (threadIdx.x != 0) return;
   const double hn = sqrt(nrm2);
   const bool breakdown = !(hn > 1e-14 * st->beta);
-  if (!breakdown) {
-    const double inv = 1.0 / hn;
-    double* w = tk.V + (long long)(j + 1) * Nc;
-    const long long base = (long long)b * kVecPerBlock;
-#pragma unroll
-    for (int e = 0; e < kVecEPT; ++e) {
-      const long long idx = base + (long long)e * kBlock + threadIdx.x;
-      if (idx < Nc) w[idx] *= inv;
+  col[j + 1] = hn;
+  st->last_hn = hn;
+  st->vscale = breakdown ? 1.0 : 1.0 / hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = col[i], c2 = col[i + 1];
+    col[i] = cs[i] * a + sn[i] * c2;
+    col[i + 1] = -sn[i] * a + cs[i] * c2;
+  }
+  const double a = col[j];
+  const double rho = hypot(a, hn);
+  double c = 1.0, s = 0.0;
+  if (rho > 0.0) {
+    c = a / rho;
+    s = hn / rho;
+  }
+  tk.cs[j] = c;
+  tk.sn[j] = s;
+  col[j] = rho;
+  col[j + 1] = 0.0;
+  for (int i = 0; i <= j + 1; ++i) tk.H[i + j * m1] = col[i];
+  const double gj = tk.g[j];
+  tk.g[j + 1] = -s * gj;
+  tk.g[j] = c * gj;
+  st->j_done = j + 1;
+  st->iterations += 1;
+  const double est = fabs(tk.g[j + 1]);
+  if (!(est > st->tol_eff * st->fnorm) || breakdown || j + 1 == tk.m) {
+    st->cycle_done = 1;
+    if (flags) {
+      flags[blockIdx.x] = tag;
+      __threadfence_system();
     }
   }
-  if (b == 0 && threadIdx.x == 0) {
-    const int m1 = tk.m + 1;
-    double* H = tk.H;
-    H[(j + 1) + j * m1] = hn;
-    st->last_hn = hn;
-    for (int i = 0; i < j; ++i) {
-      const double a = H[i + j * m1], c2 = H[(i + 1) + j * m1];
-      H[i + j * m1] = tk.cs[i] * a + tk.sn[i] * c2;
-      H[(i + 1) + j * m1] = -tk.sn[i] * a + tk.cs[i] * c2;
-    }
-    const double a = H[j + j * m1];
-    const double rho = hypot(a, hn);
-    double c = 1.0, s = 0.0;
-    if (rho > 0.0) {
-      c = a / rho;
-      s = hn / rho;
-    }
-    tk.cs[j] = c;
-    tk.sn[j] = s;
-    H[j + j * m1] = rho;
-    H[(j + 1) + j * m1] = 0.0;
-    const double gj = tk.g[j];
-    tk.g[j + 1] = -s * gj;
-    tk.g[j] = c * gj;
-    st->j_done = j + 1;
-    st->iterations += 1;
-    const double est = fabs(tk.g[j + 1]);
-    if (!(est > st->tol_eff * st->fnorm) || breakdown || j + 1 == tk.m) st->cycle_done = 1;
-  }
+}
+
+// v *= 1 / h_{j+1,j} for the kernel-level Arnoldi entry point.
+__global__ void k_scale_newest(const KryTask* __restrict__ tasks, int j) {
+  const KryTask& tk = tasks[0];
+  const double s = tk.st->vscale;
+  double* w = tk.V + (long long)(j + 1) * tk.Nc;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < tk.Nc;
+       i += (long long)gridDim.x * blockDim.x)
+    w[i] *= s;
 }
 
 // Back substitution R y = g over the j_done columns (one thread per problem).
@@ -328,8 +648,8 @@ __global__ void __launch_bounds__(kBlock) k_restart(const KryTask* __restrict__ 
   ProbState* st = tk.st;
   if (st->finished) return;
   const int b = blockIdx.x - tk.block_begin;
-  const double r2 = sum_partials(tk.partials + 2 * tk.P, tk.P, red);
-  const double x2 = sum_partials(tk.partials + 3 * tk.P, tk.P, red);
+  const double r2 = sum_partials(tk.partials + (size_t)kPartRes * tk.P, tk.P, red);
+  const double x2 = sum_partials(tk.partials + (size_t)(kPartRes + 1) * tk.P, tk.P, red);
   const double beta = sqrt(r2);
   const double fnorm = initial ? beta : st->fnorm;
   bool done = false;
@@ -375,6 +695,7 @@ __global__ void __launch_bounds__(kBlock) k_restart(const KryTask* __restrict__ 
     } else {
       st->cycle_done = 0;
       st->j_done = 0;
+      st->vscale = 1.0;
       tk.g[0] = beta;
     }
   }
@@ -539,6 +860,64 @@ void launch_tridiag(bool fp32, const TriTask* tasks, int ntasks, int nblocks, in
     hipLaunchKernelGGL(k_tridiag<double>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
 }
 
+TriConfig tri_config(bool fp32, int max_rows) {
+  // register segments of at most 16 (FP64) or 32 (FP32) rows; up to 1024
+  // threads per block: 64 modes x 16 segments, 32 x 32 or 16 x 64
+  TriConfig c{false, 0, 0, 0};
+  const int lsmax = fp32 ? 32 : 16;
+  for (int mpb : {64, 32, 16}) {
+    const int segmax = 1024 / mpb;
+    for (int ls = 8; ls <= lsmax; ls *= 2) {
+      const int S = (max_rows + ls - 1) / ls;
+      if (S <= segmax) {
+        c.seg = true;
+        c.ls = ls;
+        c.mpb = mpb;
+        c.threads = mpb * (S < 1 ? 1 : S);
+        if (c.threads < 64) c.threads = 64;
+        return c;
+      }
+    }
+  }
+  return c;
+}
+
+int tri_blocks(const TriConfig& c, int modes) {
+  return c.seg ? (modes + c.mpb - 1) / c.mpb : (modes + kBlock - 1) / kBlock;
+}
+
+void launch_tri(const TriConfig& c, bool fp32, const TriTask* tasks, int ntasks, int nblocks,
+                int jidx, hipStream_t s) {
+  if (nblocks <= 0) return;
+  if (!c.seg) {
+    launch_tridiag(fp32, tasks, ntasks, nblocks, jidx, s);
+    return;
+  }
+  const dim3 blk(c.threads);
+#define FDS_SEG(T, L, M) \
+  hipLaunchKernelGGL((k_tridiag_seg<T, L, M>), dim3(nblocks), blk, 0, s, tasks, ntasks, jidx)
+#define FDS_SEG_MPB(T, L)                      \
+  switch (c.mpb) {                             \
+    case 64: FDS_SEG(T, L, 64); break;         \
+    case 32: FDS_SEG(T, L, 32); break;         \
+    default: FDS_SEG(T, L, 16); break;         \
+  }
+  if (fp32) {
+    switch (c.ls) {
+      case 8: FDS_SEG_MPB(float, 8); break;
+      case 16: FDS_SEG_MPB(float, 16); break;
+      default: FDS_SEG_MPB(float, 32); break;
+    }
+  } else {
+    switch (c.ls) {
+      case 8: FDS_SEG_MPB(double, 8); break;
+      default: FDS_SEG_MPB(double, 16); break;
+    }
+  }
+#undef FDS_SEG_MPB
+#undef FDS_SEG
+}
+
 void launch_lines(const LineTask* tasks, int ntasks, size_t smem, int jidx, hipStream_t s) {
   if (ntasks <= 0) return;
   static size_t granted = 0;
@@ -555,12 +934,29 @@ void launch_operator(int mode, const OpTask* tasks, int ntasks, int nblocks, int
     hipLaunchKernelGGL(k_operator<1>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
 }
 
-void launch_mgs_pass(const KryTask* tasks, int ntasks, int nblocks, int i, int j, hipStream_t s) {
-  hipLaunchKernelGGL(k_mgs_pass, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, i, j);
+void launch_gram_dots(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_dots, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j);
 }
 
-void launch_mgs_finish(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s) {
-  hipLaunchKernelGGL(k_mgs_finish, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j);
+void launch_gram_solve(const KryTask* tasks, int ntasks, int j, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_solve, dim3(ntasks), dim3(kBlock), 0, s, tasks, ntasks, j);
+}
+
+void launch_gram_update(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_update, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j);
+}
+
+void launch_mgs_finish(const KryTask* tasks, int ntasks, int j, int* flags, int tag, hipStream_t s) {
+  hipLaunchKernelGGL(k_mgs_finish, dim3(ntasks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
+}
+
+void launch_scale_newest(const KryTask* tasks, int j, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_newest, dim3(nblocks), dim3(kBlock), 0, s, tasks, j);
+}
+
+void launch_idst_cols(const ColTask* tasks, int ntasks, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return;
+  hipLaunchKernelGGL(k_idst_cols, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
 }
 
 void launch_ls_solve(const KryTask* tasks, int ntasks, hipStream_t s) {

@@ -97,6 +97,7 @@ FftShape fft_shape(int n);
 // Threads per row for a transform of length n (power of two, 32..256).
 int dst_threads_per_row(int n);
 size_t dst_smem_bytes(int n, bool fp32);
+bool dst_twiddles_in_lds(int n, bool fp32);
 size_t line_smem_bytes(int n);
 
 // ---------------------------------------------------------------- plan

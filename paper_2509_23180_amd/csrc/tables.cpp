@@ -63,7 +63,7 @@ FftShape fft_shape(int n) {
   };
   while (!smooth(M)) ++M;
   // both LDS buffers of an FP64 row (plus the line-kernel scratch) must fit
-  const bool fits = (size_t)M * 2 * sizeof(double2) + sizeof(double) * (N + 1) <= 160u * 1024u;
+  const bool fits = (size_t)M * 3 * sizeof(double2) + sizeof(double) * (N + 1) <= 160u * 1024u;
   if (N > 8 && fits) {
     const double c = 2.0 * stockham_cost(M) + 4.0 * M;
     if (c < best) { best = c; s = FftShape{FFT_BLUESTEIN, M, M}; }
@@ -72,21 +72,32 @@ FftShape fft_shape(int n) {
 }
 
 int dst_threads_per_row(int n) {
+  // about one radix-4 butterfly per thread and pass
   const int W = fft_shape(n).lds_len;
-  if (W <= 64) return 32;
-  if (W <= 160) return 64;
-  if (W <= 640) return 128;
-  return 256;
+  int G = 32;
+  while (G < 256 && 2 * G <= W / 4) G *= 2;
+  return G;
 }
 
-size_t dst_smem_bytes(int n, bool fp32) {
-  const int G = dst_threads_per_row(n);
-  const int rpb = kBlock / G;
+static size_t row_buffers(int n, bool fp32) {
+  const int rpb = kBlock / dst_threads_per_row(n);
   return (size_t)rpb * 2 * fft_shape(n).lds_len * (fp32 ? sizeof(float2) : sizeof(double2));
 }
 
+bool dst_twiddles_in_lds(int n, bool fp32) {
+  const size_t tw = (size_t)fft_shape(n).L * (fp32 ? sizeof(float2) : sizeof(double2));
+  return row_buffers(n, fp32) + tw <= 96u * 1024u;
+}
+
+size_t dst_smem_bytes(int n, bool fp32) {
+  const size_t tw = dst_twiddles_in_lds(n, fp32)
+                        ? (size_t)fft_shape(n).L * (fp32 ? sizeof(float2) : sizeof(double2)) : 0;
+  return row_buffers(n, fp32) + tw;
+}
+
 size_t line_smem_bytes(int n) {
-  return sizeof(double2) * 2 * fft_shape(n).lds_len + sizeof(double) * (n + 1);
+  const FftShape s = fft_shape(n);
+  return sizeof(double2) * ((size_t)2 * s.lds_len + s.L) + sizeof(double) * (n + 1);
 }
 
 TableCache& TableCache::get() {
