@@ -223,22 +223,32 @@ fds_status fds_solve(fds_plan* plan, const double* rhs, const double* bc, double
 
 // ---------------------------------------------------------------- kernel-level entry points
 
+static void launch_one_dst(DstKind kind, const DstTask& t0, hipStream_t s, DevBuf& keep) {
+  const bool fp32 = kind != DstKind::D_D;
+  const DstChoice ch = dst_choice(t0.n, fp32);
+  DstTask t = t0;
+  t.rpb = ch.gemm ? 1 : ch.rows_per_block;
+  t.tw_lds = ch.gemm ? 0 : (dst_twiddles_in_lds(t.n, fp32) ? 1 : 0);
+  t.block_begin = 0;
+  keep.alloc(sizeof(DstTask));
+  FDS_HIP(hipMemcpyAsync(keep.get(), &t, sizeof(t), hipMemcpyHostToDevice, s));
+  const int nb = (t.rows + ch.rows_per_block - 1) / ch.rows_per_block;
+  Timing::begin(0, s);
+  if (ch.gemm) launch_dst_gemm(kind, ch.rt, ch.ct, keep.as<DstTask>(), 1, nb, ch.smem, 0, s);
+  else launch_dst(kind, keep.as<DstTask>(), 1, nb, ch.smem, 0, s);
+  Timing::end(0, s);
+}
+
 static fds_status dst_rows_impl(const void* in, void* out, int rows, int n, double scale,
                                 bool fp32, hipStream_t s) {
   if (!in || !out || rows < 0 || n < 1) throw Error(FDS_E_INVALID_ARG, "bad DST arguments");
   if (rows == 0) return FDS_OK;
   auto fft = TableCache::get().fft(n);
-  const int rpb = kBlock / dst_threads_per_row(n);
   DstTask t{};
   t.in = in; t.out = out; t.in_rs = n; t.out_rs = n; t.in_cs = 1; t.out_cs = 1;
-  t.rows = rows; t.n = n; t.rpb = rpb; t.scale = scale; t.fft = fft->dev; t.block_begin = 0;
-  t.tw_lds = dst_twiddles_in_lds(n, fp32);
-  DevBuf d(sizeof(DstTask));
-  FDS_HIP(hipMemcpyAsync(d.get(), &t, sizeof(t), hipMemcpyHostToDevice, s));
-  const int nb = (rows + rpb - 1) / rpb;
-  Timing::begin(0, s);
-  launch_dst(fp32 ? DstKind::F_F : DstKind::D_D, d.as<DstTask>(), 1, nb, dst_smem_bytes(n, fp32), 0, s);
-  Timing::end(0, s);
+  t.rows = rows; t.n = n; t.scale = scale; t.fft = fft->dev;
+  DevBuf keep;
+  launch_one_dst(fp32 ? DstKind::F_F : DstKind::D_D, t, s, keep);
   FDS_HIP(hipGetLastError());
   FDS_HIP(hipStreamSynchronize(s));
   return FDS_OK;
@@ -294,28 +304,20 @@ fds_status fds_k_rect_solve(const double* f, double* z, int32_t rows, int32_t co
     auto fft = TableCache::get().fft(cols);
     auto modes = TableCache::get().modes(cols, rows, h, kappa);
     DevBuf tmp((size_t)rows * cols * (fp32 ? 4 : 8));
-    const int rpb = kBlock / dst_threads_per_row(cols);
     DstTask t{};
     t.in = f; t.out = tmp.get(); t.in_rs = cols; t.out_rs = cols; t.in_cs = 1; t.out_cs = 1;
-    t.rows = rows; t.n = cols; t.rpb = rpb; t.scale = 1.0; t.fft = fft->dev;
-    t.tw_lds = dst_twiddles_in_lds(cols, fp32);
+    t.rows = rows; t.n = cols; t.scale = 1.0; t.fft = fft->dev;
     DstTask v = t;
     v.in = tmp.get(); v.out = z;
     TriTask tt{};
     tt.data = tmp.get(); tt.rs = cols; tt.rows = rows; tt.modes = cols;
     tt.coef = fp32 ? (const void*)modes->c32 : (const void*)modes->c64;
-    DevBuf d(sizeof(DstTask) * 2 + sizeof(TriTask));
-    FDS_HIP(hipMemcpyAsync(d.as<char>(0), &t, sizeof(t), hipMemcpyHostToDevice, s));
-    FDS_HIP(hipMemcpyAsync(d.as<char>(sizeof(DstTask)), &v, sizeof(v), hipMemcpyHostToDevice, s));
-    FDS_HIP(hipMemcpyAsync(d.as<char>(2 * sizeof(DstTask)), &tt, sizeof(tt), hipMemcpyHostToDevice, s));
-    const int nb = (rows + rpb - 1) / rpb;
-    const size_t sm = dst_smem_bytes(cols, fp32);
-    launch_dst(fp32 ? DstKind::D_F : DstKind::D_D, d.as<DstTask>(0), 1, nb, sm, 0, s);
+    DevBuf keep1, keep2, keep3(sizeof(TriTask));
+    launch_one_dst(fp32 ? DstKind::D_F : DstKind::D_D, t, s, keep1);
+    FDS_HIP(hipMemcpyAsync(keep3.get(), &tt, sizeof(tt), hipMemcpyHostToDevice, s));
     const TriConfig tc = tri_config(fp32, rows);
-    launch_tri(tc, fp32, reinterpret_cast<const TriTask*>(d.as<char>(2 * sizeof(DstTask))), 1,
-               tri_blocks(tc, cols), 0, s);
-    launch_dst(fp32 ? DstKind::F_D : DstKind::D_D,
-               reinterpret_cast<const DstTask*>(d.as<char>(sizeof(DstTask))), 1, nb, sm, 0, s);
+    launch_tri(tc, fp32, keep3.as<TriTask>(), 1, tri_blocks(tc, cols), 0, s);
+    launch_one_dst(fp32 ? DstKind::F_D : DstKind::D_D, v, s, keep2);
     FDS_HIP(hipGetLastError());
     FDS_HIP(hipStreamSynchronize(s));
     return FDS_OK;

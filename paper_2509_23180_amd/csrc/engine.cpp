@@ -43,6 +43,50 @@ void add_block_task(TaskList<T>& tl, T t, int nblocks) {
 
 int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// Row sine transforms of one stage, grouped by kernel configuration (LDS FFT,
+// or matrix-core product with a given tile shape) so every launch runs one
+// instantiation.
+struct DstStage {
+  DstKind kind = DstKind::D_D;
+  struct Sub {
+    DstChoice ch;
+    TaskList<DstTask> tl;
+  };
+  std::vector<Sub> subs;
+  explicit DstStage(DstKind k = DstKind::D_D) : kind(k) {}
+  bool fp32() const { return kind != DstKind::D_D; }
+  void add(DstTask t) {
+    const DstChoice ch = dst_choice(t.n, fp32());
+    Sub* sub = nullptr;
+    for (Sub& s : subs)
+      if (s.ch.gemm == ch.gemm && s.ch.rt == ch.rt && s.ch.ct == ch.ct) sub = &s;
+    if (!sub) {
+      subs.push_back(Sub{ch, TaskList<DstTask>{}});
+      sub = &subs.back();
+    }
+    t.rpb = ch.gemm ? 1 : ch.rows_per_block;
+    t.tw_lds = ch.gemm ? 0 : (dst_twiddles_in_lds(t.n, fp32()) ? 1 : 0);
+    add_block_task(sub->tl, t, div_up(t.rows, ch.rows_per_block));
+    sub->tl.smem = std::max(sub->tl.smem, ch.smem);
+  }
+  int n() const {
+    int c = 0;
+    for (const Sub& s : subs) c += s.tl.n();
+    return c;
+  }
+  void upload() {
+    for (Sub& s : subs) s.tl.upload();
+  }
+  void launch(int jidx, hipStream_t st) const {
+    for (const Sub& s : subs) {
+      if (s.ch.gemm)
+        launch_dst_gemm(kind, s.ch.rt, s.ch.ct, s.tl.dev(), s.tl.n(), s.tl.nblocks, s.tl.smem, jidx, st);
+      else
+        launch_dst(kind, s.tl.dev(), s.tl.n(), s.tl.nblocks, s.tl.smem, jidx, st);
+    }
+  }
+};
+
 struct Slot {
   SolveRequest req;
   fds_plan* plan = nullptr;
@@ -106,7 +150,7 @@ struct Engine::Impl {
   hipStream_t s;
   DevBuf states;
   std::vector<ProbState> host_states;
-  TaskList<DstTask> it_fwd, it_inv, cyc_fwd, cyc_inv, arm_fwd, arm_inv, bs_fwd;
+  DstStage it_fwd, it_inv{DstKind::F_F}, cyc_fwd, cyc_inv, arm_fwd, arm_inv, bs_fwd;
   TaskList<TriTask> it_tri, cyc_tri, arm_tri;
   TriConfig it_tc{}, cyc_tc{}, arm_tc{};
   TaskList<LineTask> it_lines, x_lines;
@@ -187,7 +231,6 @@ void Engine::Impl::build() {
     const int* skip_fin = &sl.st->finished;
     const FftDesc* fftc = p->fft_c->dev;
     const int rpb_c = kBlock / dst_threads_per_row(nx);
-    const size_t smem_c64 = dst_smem_bytes(nx, false), smem_c32 = dst_smem_bytes(nx, true);
 
     // ---- per-iteration transforms of the centre.  The forward transform
     // also normalises v_j (ProbState::vscale).  Plain variant: the Schur
@@ -201,8 +244,7 @@ void Engine::Impl::build() {
       t.out = flex ? (void*)sl.tmpf : (void*)sl.tmpd; t.out_js = 0; t.out_rs = nx; t.out_cs = 1;
       t.rows = ny; t.n = nx; t.rpb = rpb_c; t.scale = 1.0; t.fft = fftc; t.skip = skip_it;
       t.tw_lds = dst_twiddles_in_lds(nx, flex);
-      add_block_task(it_fwd, t, div_up(ny, rpb_c));
-      it_fwd.smem = std::max(it_fwd.smem, flex ? smem_c32 : smem_c64);
+      it_fwd.add(t);
 
       TriTask tt{};
       tt.data = t.out; tt.rs = nx; tt.js = 0; tt.rows = ny; tt.modes = nx;
@@ -217,8 +259,7 @@ void Engine::Impl::build() {
         v.out_rs = nx; v.out_cs = 1;
         v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = 1.0; v.fft = fftc; v.skip = skip_it;
         v.tw_lds = dst_twiddles_in_lds(nx, true);
-        add_block_task(it_inv, v, div_up(ny, rpb_c));
-        it_inv.smem = std::max(it_inv.smem, smem_c32);
+        it_inv.add(v);
       } else {
         bool west = false, east = false;
         for (const ArmInfo& a : p->arms) { west |= a.line == 2; east |= a.line == 3; }
@@ -236,8 +277,7 @@ void Engine::Impl::build() {
       t.in = sl.u; t.in_rs = nx; t.in_cs = 1; t.out = sl.tmpd; t.out_rs = nx; t.out_cs = 1;
       t.rows = ny; t.n = nx; t.rpb = rpb_c; t.scale = 1.0; t.fft = fftc; t.skip = skip_fin;
       t.tw_lds = dst_twiddles_in_lds(nx, false);
-      add_block_task(cyc_fwd, t, div_up(ny, rpb_c));
-      cyc_fwd.smem = std::max(cyc_fwd.smem, smem_c64);
+      cyc_fwd.add(t);
       TriTask tt{};
       tt.data = sl.tmpd; tt.rs = nx; tt.rows = ny; tt.modes = nx; tt.coef = p->modes_c->c64;
       tt.skip = skip_fin;
@@ -247,8 +287,7 @@ void Engine::Impl::build() {
       v.out_cs = 1; v.accumulate = 1;
       v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = 1.0; v.fft = fftc; v.skip = skip_fin;
       v.tw_lds = dst_twiddles_in_lds(nx, false);
-      add_block_task(cyc_inv, v, div_up(ny, rpb_c));
-      cyc_inv.smem = std::max(cyc_inv.smem, smem_c64);
+      cyc_inv.add(v);
     }
     // ---- Schur lines and operators
     OpTask ot{};
@@ -302,20 +341,17 @@ void Engine::Impl::build() {
       f.out = sl.tmpd + ad.off; f.out_rs = a.L; f.out_cs = 1;
       f.rows = a.rows; f.n = a.L; f.rpb = rpb; f.scale = 1.0; f.fft = a.fft->dev; f.skip = nullptr;
       f.tw_lds = dst_twiddles_in_lds(a.L, false);
-      add_block_task(arm_fwd, f, div_up(a.rows, rpb));
-      arm_fwd.smem = std::max(arm_fwd.smem, dst_smem_bytes(a.L, false));
+      arm_fwd.add(f);
       DstTask fb = f;
       fb.in = sl.x_int + ad.off;
-      add_block_task(bs_fwd, fb, div_up(a.rows, rpb));
-      bs_fwd.smem = arm_fwd.smem;
+      bs_fwd.add(fb);
       TriTask at{};
       at.data = sl.tmpd + ad.off; at.rs = a.L; at.rows = a.rows; at.modes = a.L;
       at.coef = a.modes->c64; at.skip = nullptr;
       add_block_task(arm_tri, at, div_up(a.L, kBlock));
       DstTask iv = f;
       iv.in = sl.tmpd + ad.off; iv.out = sl.x_int + ad.off;
-      add_block_task(arm_inv, iv, div_up(a.rows, rpb));
-      arm_inv.smem = arm_fwd.smem;
+      arm_inv.add(iv);
     }
     iface_fp.h.push_back(fi);
     iface_bs.h.push_back(bi);
@@ -403,16 +439,15 @@ void Engine::Impl::build() {
 
 // One Arnoldi step j of every unfinished problem.
 void Engine::Impl::iteration(int j, int tag) {
-  const DstKind fk = flex ? DstKind::D_F : DstKind::D_D;
   Timing::begin(0, s);
-  launch_dst(fk, it_fwd.dev(), it_fwd.n(), it_fwd.nblocks, it_fwd.smem, j, s);
+  it_fwd.launch(j, s);
   Timing::end(0, s);
   Timing::begin(1, s);
   launch_tri(it_tc, flex, it_tri.dev(), it_tri.n(), it_tri.nblocks, 0, s);
   Timing::end(1, s);
   if (flex) {
     Timing::begin(0, s);
-    launch_dst(DstKind::F_F, it_inv.dev(), it_inv.n(), it_inv.nblocks, it_inv.smem, j, s);
+    it_inv.launch(j, s);
     Timing::end(0, s);
   } else if (it_cols.n()) {
     Timing::begin(7, s);
@@ -451,13 +486,13 @@ void Engine::Impl::end_of_cycle() {
   Timing::end(5, s);
   if (!flex) {
     Timing::begin(0, s);
-    launch_dst(DstKind::D_D, cyc_fwd.dev(), cyc_fwd.n(), cyc_fwd.nblocks, cyc_fwd.smem, 0, s);
+    cyc_fwd.launch(0, s);
     Timing::end(0, s);
     Timing::begin(1, s);
     launch_tri(cyc_tc, false, cyc_tri.dev(), cyc_tri.n(), cyc_tri.nblocks, 0, s);
     Timing::end(1, s);
     Timing::begin(0, s);
-    launch_dst(DstKind::D_D, cyc_inv.dev(), cyc_inv.n(), cyc_inv.nblocks, cyc_inv.smem, 0, s);
+    cyc_inv.launch(0, s);
     Timing::end(0, s);
   }
   if (x_lines.n()) {
@@ -489,6 +524,7 @@ Engine::Engine(const std::vector<SolveRequest>& reqs, int m, int precision, int 
   I.flex = precision == FDS_FP32_PRECOND;
   I.max_cycles = max_cycles;
   I.s = stream;
+  I.it_fwd.kind = I.flex ? DstKind::D_F : DstKind::D_D;
   I.slots.resize(reqs.size());
   for (size_t i = 0; i < reqs.size(); ++i) {
     I.slots[i].req = reqs[i];
@@ -513,13 +549,13 @@ void Engine::setup() {
   Timing::end(5, s);
   if (I.arm_fwd.n()) {
     Timing::begin(0, s);
-    launch_dst(DstKind::D_D, I.arm_fwd.dev(), I.arm_fwd.n(), I.arm_fwd.nblocks, I.arm_fwd.smem, 0, s);
+    I.arm_fwd.launch(0, s);
     Timing::end(0, s);
     Timing::begin(1, s);
     launch_tri(I.arm_tc, false, I.arm_tri.dev(), I.arm_tri.n(), I.arm_tri.nblocks, 0, s);
     Timing::end(1, s);
     Timing::begin(0, s);
-    launch_dst(DstKind::D_D, I.arm_inv.dev(), I.arm_inv.n(), I.arm_inv.nblocks, I.arm_inv.smem, 0, s);
+    I.arm_inv.launch(0, s);
     Timing::end(0, s);
   }
   for (Slot& sl : I.slots) {
@@ -641,13 +677,13 @@ std::vector<SolveOutcome> Engine::finalize() {
   launch_iface(I.iface_bs.dev(), I.iface_bs.n(), s);
   if (I.bs_fwd.n()) {
     Timing::begin(0, s);
-    launch_dst(DstKind::D_D, I.bs_fwd.dev(), I.bs_fwd.n(), I.bs_fwd.nblocks, I.bs_fwd.smem, 0, s);
+    I.bs_fwd.launch(0, s);
     Timing::end(0, s);
     Timing::begin(1, s);
     launch_tri(I.arm_tc, false, I.arm_tri.dev(), I.arm_tri.n(), I.arm_tri.nblocks, 0, s);
     Timing::end(1, s);
     Timing::begin(0, s);
-    launch_dst(DstKind::D_D, I.arm_inv.dev(), I.arm_inv.n(), I.arm_inv.nblocks, I.arm_inv.smem, 0, s);
+    I.arm_inv.launch(0, s);
     Timing::end(0, s);
   }
   launch_lift(1, I.gather.dev(), I.gather.n(), I.gather.nblocks, s);

@@ -58,7 +58,15 @@ struct FftDesc {
   const float2* kern32;
   const double2* chirp64; // Bluestein: exp(-i pi t^2 / N), t < N
   const float2* chirp32;
+  // dense sine matrix for the matrix-core variant (n <= kGemmMaxN), padded
+  // with zeros to np x np, np a multiple of 64; NULL when not built
+  int np;
+  int pad1;
+  const double* smat64;
+  const float* smat32;
 };
+
+constexpr int kGemmMaxN = 1024;
 
 // Per-mode coefficients of the constant-coefficient tridiagonal solve
 //   delta y[i-1] + a y[i] + delta y[i+1] = s r[i],  a = -delta (q + 1/q),

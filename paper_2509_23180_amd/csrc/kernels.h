@@ -12,6 +12,11 @@ enum class DstKind { D_D, D_F, F_F, F_D };
 
 void launch_dst(DstKind kind, const DstTask* tasks, int ntasks, int nblocks, size_t smem, int jidx,
                 hipStream_t s);
+// Matrix-core variant of the row sine transform: RT*16 rows per block, each
+// of the 4 waves covers CT*16 columns (4*CT*16 >= n).
+size_t gemm_smem_bytes(int n, bool fp32, int rt);
+void launch_dst_gemm(DstKind kind, int rt, int ct, const DstTask* tasks, int ntasks, int nblocks,
+                     size_t smem, int jidx, hipStream_t s);
 void launch_tridiag(bool fp32, const TriTask* tasks, int ntasks, int nblocks, int jidx,
                     hipStream_t s);
 // Choice of tridiagonal kernel for a launch whose longest system has

@@ -62,6 +62,110 @@ __global__ void __launch_bounds__(kBlock) k_dst_rows(const DstTask* __restrict__
   }
 }
 
+
+// =====================================================================
+// Sine transform of rows as a product with the dense sine matrix on the
+// matrix cores: out[r][c] = scale * sum_j x[r][j] S[j][c],
+// S[j][c] = sin(pi (j+1)(c+1)/(n+1)).  A block takes RT*16 rows of x into
+// LDS; wave w accumulates the 16x16 tiles of columns [w*CT*16, (w+1)*CT*16)
+// with v_mfma_*_16x16x4 (A lane l: A[l%16][l/16], B lane l: B[l/16][l%16]).
+// =====================================================================
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MfmaAcc;
+template <> struct MfmaAcc<double> { using t = v4d_t; };
+template <> struct MfmaAcc<float> { using t = v4f_t; };
+
+__device__ __forceinline__ v4d_t mfma16x16x4(double a, double b, v4d_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f_t mfma16x16x4(float a, float b, v4f_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// row of register v of lane l in the 16x16 result tile
+template <typename T> __device__ __forceinline__ int mfma_row(int l, int v);
+template <> __device__ __forceinline__ int mfma_row<double>(int l, int v) { return 4 * v + (l >> 4); }
+template <> __device__ __forceinline__ int mfma_row<float>(int l, int v) { return 4 * (l >> 4) + v; }
+
+template <typename T> __device__ __forceinline__ const T* fft_smat(const FftDesc& f);
+template <> __device__ __forceinline__ const double* fft_smat<double>(const FftDesc& f) { return f.smat64; }
+template <> __device__ __forceinline__ const float* fft_smat<float>(const FftDesc& f) { return f.smat32; }
+
+template <typename T, typename TIn, typename TOut, int RT, int CT>
+__global__ void __launch_bounds__(kBlock) k_dst_gemm(const DstTask* __restrict__ tasks, int ntasks,
+                                                      int jidx) {
+  using Acc = typename MfmaAcc<T>::t;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int slot;
+  const DstTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  if (tk.skip && *tk.skip) return;
+  const FftDesc& f = *tk.fft;
+  const int n = tk.n;
+  const int np = f.np;
+  const int ld = np + 1;                      // padded LDS row stride
+  constexpr int RB = RT * 16;
+  T* xs = reinterpret_cast<T*>(smem_raw);     // RB x ld
+  const int r0 = (blockIdx.x - tk.block_begin) * RB;
+  const TIn* in = static_cast<const TIn*>(tk.in) + (long long)jidx * tk.in_js;
+  const double sc_in = tk.in_scale ? *tk.in_scale : 1.0;
+  TIn* inw = const_cast<TIn*>(in);
+  for (int e = threadIdx.x; e < RB * np; e += kBlock) {
+    const int r = e / np, j = e - (e / np) * np;
+    const int row = r0 + r;
+    T v = T(0);
+    if (row < tk.rows && j < n) {
+      const long long a = (long long)row * tk.in_rs + (long long)j * tk.in_cs;
+      const double x = double(in[a]) * sc_in;
+      if (tk.in_scale) inw[a] = TIn(x);
+      v = T(x);
+    }
+    xs[r * ld + j] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const T* S = fft_smat<T>(f);
+  const int ar = lane & 15, ak = lane >> 4;
+  TOut* out = static_cast<TOut*>(tk.out) + (long long)jidx * tk.out_js;
+  const T scale = T(tk.scale);
+  for (int cbase = 0; cbase < np; cbase += 4 * CT * 16) {
+    const int c0 = cbase + wave * CT * 16;
+    if (c0 >= np) break;
+    Acc acc[RT][CT];
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int b = 0; b < CT; ++b) acc[a][b] = Acc{T(0), T(0), T(0), T(0)};
+    const T* Sl = S + (long long)ak * np + c0 + ar;
+    for (int k0 = 0; k0 < np; k0 += 4) {
+      T bv[CT];
+#pragma unroll
+      for (int b = 0; b < CT; ++b) bv[b] = (c0 + b * 16 < np) ? Sl[(long long)k0 * np + b * 16] : T(0);
+#pragma unroll
+      for (int a = 0; a < RT; ++a) {
+        const T av = xs[(a * 16 + ar) * ld + k0 + ak];
+#pragma unroll
+        for (int b = 0; b < CT; ++b) acc[a][b] = mfma16x16x4(av, bv[b], acc[a][b]);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int b = 0; b < CT; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = r0 + a * 16 + mfma_row<T>(lane, v);
+          const int col = c0 + b * 16 + ar;
+          if (row < tk.rows && col < n) {
+            TOut* o = out + (long long)row * tk.out_rs + (long long)col * tk.out_cs;
+            const T X = scale * acc[a][b][v];
+            if (tk.accumulate) *o = TOut(T(*o) + X);
+            else *o = TOut(X);
+          }
+        }
+  }
+}
+
 // =====================================================================
 // Per-mode tridiagonal solves, one lane per mode, in place.
 //   forward:  w_i = sc r_i + q w_{i-1},   s = sum q^{i-1} w_i
@@ -849,6 +953,41 @@ void launch_dst(DstKind kind, const DstTask* tasks, int ntasks, int nblocks, siz
                          tasks, ntasks, jidx);
       break;
   }
+}
+
+size_t gemm_smem_bytes(int n, bool fp32, int rt) {
+  const int np = (n + 63) / 64 * 64;
+  return (size_t)rt * 16 * (np + 1) * (fp32 ? sizeof(float) : sizeof(double));
+}
+
+void launch_dst_gemm(DstKind kind, int rt, int ct, const DstTask* tasks, int ntasks, int nblocks,
+                     size_t smem, int jidx, hipStream_t s) {
+  if (nblocks <= 0) return;
+#define FDS_G(T, TI, TO, R, C)                                                                    \
+  do {                                                                                           \
+    static size_t granted = 0;                                                                   \
+    ensure_smem(k_dst_gemm<T, TI, TO, R, C>, smem, &granted);                                    \
+    hipLaunchKernelGGL((k_dst_gemm<T, TI, TO, R, C>), dim3(nblocks), dim3(kBlock), smem, s, tasks, \
+                       ntasks, jidx);                                                            \
+  } while (0)
+#define FDS_G_CT(T, TI, TO, R)                      \
+  switch (ct) {                                     \
+    case 1: FDS_G(T, TI, TO, R, 1); break;          \
+    case 2: FDS_G(T, TI, TO, R, 2); break;          \
+    case 3: FDS_G(T, TI, TO, R, 3); break;          \
+    default: FDS_G(T, TI, TO, R, 4); break;         \
+  }
+#define FDS_G_RT(T, TI, TO)                         \
+  if (rt == 1) { FDS_G_CT(T, TI, TO, 1) } else { FDS_G_CT(T, TI, TO, 2) }
+  switch (kind) {
+    case DstKind::D_D: FDS_G_RT(double, double, double); break;
+    case DstKind::D_F: FDS_G_RT(float, double, float); break;
+    case DstKind::F_F: FDS_G_RT(float, float, float); break;
+    case DstKind::F_D: FDS_G_RT(float, float, double); break;
+  }
+#undef FDS_G_RT
+#undef FDS_G_CT
+#undef FDS_G
 }
 
 void launch_tridiag(bool fp32, const TriTask* tasks, int ntasks, int nblocks, int jidx,

@@ -99,6 +99,11 @@ int dst_threads_per_row(int n);
 size_t dst_smem_bytes(int n, bool fp32);
 bool dst_twiddles_in_lds(int n, bool fp32);
 size_t line_smem_bytes(int n);
+// Row sine transform algorithm for length n: the LDS FFT (default) or the
+// dense sine matrix on the matrix cores (n <= 1024; FDS_DST_ALGO=gemm).
+// FDS_DST_ALGO=fft|gemm|auto selects it for measurements.
+struct DstChoice { bool gemm; int rt; int ct; int rows_per_block; size_t smem; };
+DstChoice dst_choice(int n, bool fp32);
 
 // ---------------------------------------------------------------- plan
 enum RectKind { RK_CENTRE = 0, RK_N = 1, RK_S = 2, RK_E = 3, RK_W = 4 };

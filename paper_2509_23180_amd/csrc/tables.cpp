@@ -3,7 +3,9 @@
 // double where the angle reduction benefits) and uploaded once.
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 
 #include "runtime.h"
 
@@ -72,7 +74,12 @@ FftShape fft_shape(int n) {
 }
 
 int dst_threads_per_row(int n) {
-  // about one radix-4 butterfly per thread and pass
+  // about one radix-4 butterfly per thread and pass; FDS_DST_TPR overrides
+  // (32..256, power of two) for tuning measurements
+  if (const char* e = std::getenv("FDS_DST_TPR")) {
+    const int v = std::atoi(e);
+    if (v == 32 || v == 64 || v == 128 || v == 256) return v;
+  }
   const int W = fft_shape(n).lds_len;
   int G = 32;
   while (G < 256 && 2 * G <= W / 4) G *= 2;
@@ -85,6 +92,7 @@ static size_t row_buffers(int n, bool fp32) {
 }
 
 bool dst_twiddles_in_lds(int n, bool fp32) {
+  if (const char* e = std::getenv("FDS_DST_TWLDS")) return std::atoi(e) != 0;
   const size_t tw = (size_t)fft_shape(n).L * (fp32 ? sizeof(float2) : sizeof(double2));
   return row_buffers(n, fp32) + tw <= 96u * 1024u;
 }
@@ -93,6 +101,30 @@ size_t dst_smem_bytes(int n, bool fp32) {
   const size_t tw = dst_twiddles_in_lds(n, fp32)
                         ? (size_t)fft_shape(n).L * (fp32 ? sizeof(float2) : sizeof(double2)) : 0;
   return row_buffers(n, fp32) + tw;
+}
+
+DstChoice dst_choice(int n, bool fp32) {
+  DstChoice c{false, 1, 4, 0, 0};
+  const char* env = std::getenv("FDS_DST_ALGO");
+  const std::string mode = env ? env : "auto";
+  bool gemm = false;
+  if (n <= kGemmMaxN) {
+    if (mode == "gemm") gemm = true;
+    else if (mode == "fft") gemm = false;
+    else gemm = false;   // measured slower than the LDS FFT at n = 256 and 1024
+  }
+  if (gemm) {
+    const int np = (n + 63) / 64 * 64;
+    c.gemm = true;
+    c.rt = np <= 256 ? 2 : 1;
+    c.ct = 4;
+    c.rows_per_block = c.rt * 16;
+    c.smem = gemm_smem_bytes(n, fp32, c.rt);
+  } else {
+    c.rows_per_block = kBlock / dst_threads_per_row(n);
+    c.smem = dst_smem_bytes(n, fp32);
+  }
+  return c;
 }
 
 size_t line_smem_bytes(int n) {
@@ -197,6 +229,9 @@ std::shared_ptr<FftTable> TableCache::fft(int n) {
   const size_t o_pin = take(sizeof(int) * (rader ? L : 1)), o_pout = take(sizeof(int) * (rader ? L : 1));
   const size_t o_k64 = take(sizeof(double2) * std::max(nk, 1)), o_k32 = take(sizeof(float2) * std::max(nk, 1));
   const size_t o_c64 = take(sizeof(double2) * std::max(nch, 1)), o_c32 = take(sizeof(float2) * std::max(nch, 1));
+  const int np = n <= kGemmMaxN ? (n + 63) / 64 * 64 : 0;
+  const size_t o_s64 = take(sizeof(double) * std::max((size_t)np * np, (size_t)1));
+  const size_t o_s32 = take(sizeof(float) * std::max((size_t)np * np, (size_t)1));
   const size_t total = o;
   std::vector<unsigned char> host(total, 0);
   auto* tw64 = reinterpret_cast<double2*>(host.data() + o_tw64);
@@ -254,9 +289,24 @@ std::shared_ptr<FftTable> TableCache::fft(int n) {
       k32[q] = float2{(float)v.real(), (float)v.imag()};
     }
   }
+  if (np) {
+    auto* s64 = reinterpret_cast<double*>(host.data() + o_s64);
+    auto* s32 = reinterpret_cast<float*>(host.data() + o_s32);
+    for (int j = 0; j < n; ++j)
+      for (int c = 0; c < n; ++c) {
+        // sin(pi (j+1)(c+1) / N) with the integer reduced modulo 2N
+        const long long tt = (long long)(j + 1) * (c + 1) % (2LL * N);
+        const long double v = sinl(kPi * (long double)tt / (long double)N);
+        s64[(size_t)j * np + c] = (double)v;
+        s32[(size_t)j * np + c] = (float)v;
+      }
+  }
   t->mem.alloc(total);
   FftDesc d{};
   d.N = N;
+  d.np = np;
+  d.smat64 = np ? t->mem.as<double>(o_s64) : nullptr;
+  d.smat32 = np ? t->mem.as<float>(o_s32) : nullptr;
   d.kind = shp.kind;
   d.L = L;
   d.W = shp.lds_len;

@@ -38,8 +38,15 @@ DST_SIZES = [1, 2, 3, 4, 5, 7, 10, 16, 31, 32, 33, 63, 64, 65, 96, 100, 127, 128
              300, 511, 512, 1000, 1023, 1024, 1025, 1200, 1500, 2047, 2048]
 
 
+@pytest.fixture(params=["fft", "gemm"])
+def dst_algo(request, monkeypatch):
+    """Both row-transform algorithms (the matrix-core one exists for n <= 1024)."""
+    monkeypatch.setenv("FDS_DST_ALGO", request.param)
+    return request.param
+
+
 @pytest.mark.parametrize("n", DST_SIZES)
-def test_dst_rows_fp64(n):
+def test_dst_rows_fp64(n, dst_algo):
     fds = _fds()
     rows = 17 if n < 1024 else 5
     log(f"dst fp64 n={n} rows={rows}")
@@ -58,7 +65,7 @@ def test_dst_rows_fp64(n):
 
 @pytest.mark.parametrize("n", [1, 7, 16, 32, 33, 64, 100, 255, 256, 257, 300, 1023, 1024, 1200, 2047,
                                2048])
-def test_dst_rows_fp32(n):
+def test_dst_rows_fp32(n, dst_algo):
     fds = _fds()
     log(f"dst fp32 n={n}")
     x = np.random.default_rng(n + 5).normal(size=(9, n)).astype(np.float32)
@@ -93,7 +100,7 @@ def test_tridiag_modes(rows, modes, kappa):
 @pytest.mark.parametrize("rows,cols", [(1, 1), (2, 3), (5, 7), (32, 32), (33, 32), (256, 256),
                                        (257, 256), (100, 1024)])
 @pytest.mark.parametrize("kappa", [0.0, -37.5])
-def test_rect_solve(rows, cols, kappa):
+def test_rect_solve(rows, cols, kappa, dst_algo):
     fds = _fds()
     log(f"rect_solve {rows}x{cols} kappa={kappa}")
     h = 1.0 / (max(rows, cols) + 1)

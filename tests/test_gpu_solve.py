@@ -40,9 +40,15 @@ def _problem(shape, n, kappa, kind, seed=0):
     return workloads.gaussian_problem(shape, n, kappa, 1, seed, 0)
 
 
+@pytest.fixture(params=["fft", "auto"])
+def dst_algo(request, monkeypatch):
+    monkeypatch.setenv("FDS_DST_ALGO", request.param)
+    return request.param
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("shape,n,kappa,kind", CASES_SMALL)
-def test_small_parity(shape, n, kappa, kind, precision):
+def test_small_parity(shape, n, kappa, kind, precision, dst_algo):
     fds = _fds()
     log(f"solve {shape} n={n} kappa={kappa} {kind} prec={precision}")
     prob = _problem(shape, n, kappa, kind)
