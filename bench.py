@@ -29,10 +29,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("paper_2509_23180_amd/csrc/kernels.hip", "paper_2509_23180_amd/csrc/fft_device.h",
+KERNEL_SOURCES = ("paper_2509_23180_amd/csrc/kernels.hip", "paper_2509_23180_amd/csrc/dst_wave.hip",
+                  "paper_2509_23180_amd/csrc/fft_device.h", "paper_2509_23180_amd/csrc/fft_wave.h",
                   "paper_2509_23180_amd/csrc/fds_internal.h")
 # kernel class -> name of the HIP kernel that implements it (rocprofv3 summaries)
-CLASS_KERNEL = {"dst": "k_dst_rows", "tridiag": "k_tridiag_seg", "operator": "k_operator",
+CLASS_KERNEL = {"dst": "k_dst_wave", "tridiag": "k_tridiag_seg", "operator": "k_operator",
                 "gram_dots": "k_gram_dots", "gram_update": "k_gram_update", "lines": "k_schur_lines",
                 "cols": "k_idst_cols"}
 

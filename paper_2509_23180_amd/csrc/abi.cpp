@@ -47,6 +47,7 @@ struct TimingState {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   hipEvent_t open[kClasses] = {};
+  int armed = -1;
   long long calls[kClasses] = {};
   double ms[kClasses] = {};
 
@@ -95,24 +96,28 @@ double Timing::bytes(int cls) {
   std::lock_guard<std::mutex> lk(t.mu);
   return t.bytes[cls];
 }
-void Timing::begin(int cls, hipStream_t s) {
+void Timing::begin(int cls, hipStream_t) {
   TimingState& t = timing();
   if (!((t.mask >> cls) & 1)) return;
   std::lock_guard<std::mutex> lk(t.mu);
-  hipEvent_t e = t.take();
-  FDS_HIP(hipEventRecord(e, s));
-  t.open[cls] = e;
+  t.armed = cls;
 }
-void Timing::end(int cls, hipStream_t s) {
+void Timing::end(int cls, hipStream_t) {
   TimingState& t = timing();
   if (!((t.mask >> cls) & 1)) return;
   std::lock_guard<std::mutex> lk(t.mu);
-  if (!t.open[cls]) return;
-  hipEvent_t e = t.take();
-  FDS_HIP(hipEventRecord(e, s));
-  t.pending.push_back({cls, t.open[cls], e});
-  t.open[cls] = nullptr;
-  if (t.pending.size() > 8192) t.flush();
+  if (t.armed == cls) t.armed = -1;
+}
+bool Timing::take_pair(hipEvent_t* a, hipEvent_t* b) {
+  TimingState& t = timing();
+  if (t.armed < 0) return false;
+  std::lock_guard<std::mutex> lk(t.mu);
+  if (t.armed < 0) return false;
+  if (t.pending.size() >= 8192) t.flush();  // every pending pair was recorded
+  *a = t.take();
+  *b = t.take();
+  t.pending.push_back({t.armed, *a, *b});
+  return true;
 }
 void Timing::read(int cls, long long* calls, double* ms) {
   TimingState& t = timing();
@@ -228,13 +233,19 @@ static void launch_one_dst(DstKind kind, const DstTask& t0, hipStream_t s, DevBu
   const DstChoice ch = dst_choice(t0.n, fp32);
   DstTask t = t0;
   t.rpb = ch.gemm ? 1 : ch.rows_per_block;
-  t.tw_lds = ch.gemm ? 0 : (dst_twiddles_in_lds(t.n, fp32) ? 1 : 0);
+  t.tw_lds = (ch.gemm || ch.wave_e) ? 0 : (dst_twiddles_in_lds(t.n, fp32) ? 1 : 0);
+  if (ch.wave_e) {
+    t.wd = TableCache::get().wave_desc(t.fft, fp32);
+    t.io_f32 = dst_io_flags(kind);
+  }
   t.block_begin = 0;
   keep.alloc(sizeof(DstTask));
   FDS_HIP(hipMemcpyAsync(keep.get(), &t, sizeof(t), hipMemcpyHostToDevice, s));
   const int nb = (t.rows + ch.rows_per_block - 1) / ch.rows_per_block;
   Timing::begin(0, s);
   if (ch.gemm) launch_dst_gemm(kind, ch.rt, ch.ct, keep.as<DstTask>(), 1, nb, ch.smem, 0, s);
+  else if (ch.wave_e)
+    launch_dst_wave(kind, ch.wave_e, keep.as<DstTask>(), 1, nb, ch.threads, ch.smem, 0, s);
   else launch_dst(kind, keep.as<DstTask>(), 1, nb, ch.smem, 0, s);
   Timing::end(0, s);
 }

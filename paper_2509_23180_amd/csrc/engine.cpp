@@ -59,13 +59,19 @@ struct DstStage {
     const DstChoice ch = dst_choice(t.n, fp32());
     Sub* sub = nullptr;
     for (Sub& s : subs)
-      if (s.ch.gemm == ch.gemm && s.ch.rt == ch.rt && s.ch.ct == ch.ct) sub = &s;
+      if (s.ch.gemm == ch.gemm && s.ch.rt == ch.rt && s.ch.ct == ch.ct &&
+          s.ch.wave_e == ch.wave_e && s.ch.threads == ch.threads)
+        sub = &s;
     if (!sub) {
       subs.push_back(Sub{ch, TaskList<DstTask>{}});
       sub = &subs.back();
     }
     t.rpb = ch.gemm ? 1 : ch.rows_per_block;
-    t.tw_lds = ch.gemm ? 0 : (dst_twiddles_in_lds(t.n, fp32()) ? 1 : 0);
+    t.tw_lds = (ch.gemm || ch.wave_e) ? 0 : (dst_twiddles_in_lds(t.n, fp32()) ? 1 : 0);
+    if (ch.wave_e) {
+      t.wd = TableCache::get().wave_desc(t.fft, fp32());
+      t.io_f32 = dst_io_flags(kind);
+    }
     add_block_task(sub->tl, t, div_up(t.rows, ch.rows_per_block));
     sub->tl.smem = std::max(sub->tl.smem, ch.smem);
   }
@@ -81,6 +87,9 @@ struct DstStage {
     for (const Sub& s : subs) {
       if (s.ch.gemm)
         launch_dst_gemm(kind, s.ch.rt, s.ch.ct, s.tl.dev(), s.tl.n(), s.tl.nblocks, s.tl.smem, jidx, st);
+      else if (s.ch.wave_e)
+        launch_dst_wave(kind, s.ch.wave_e, s.tl.dev(), s.tl.n(), s.tl.nblocks, s.ch.threads,
+                        s.tl.smem, jidx, st);
       else
         launch_dst(kind, s.tl.dev(), s.tl.n(), s.tl.nblocks, s.tl.smem, jidx, st);
     }
@@ -153,7 +162,9 @@ struct Engine::Impl {
   DstStage it_fwd, it_inv{DstKind::F_F}, cyc_fwd, cyc_inv, arm_fwd, arm_inv, bs_fwd;
   TaskList<TriTask> it_tri, cyc_tri, arm_tri;
   TriConfig it_tc{}, cyc_tc{}, arm_tc{};
-  TaskList<LineTask> it_lines, x_lines;
+  TaskList<LineTask> it_lines, x_lines;      // FFT line kernel (one block per line)
+  TaskList<LineTask> it_lines_d, x_lines_d;  // dense line operators
+  int lmax_dense = 0;
   TaskList<ColTask> it_cols;
   TaskList<OpTask> it_op, res_op;
   TaskList<KryTask> kry;
@@ -319,10 +330,18 @@ void Engine::Impl::build() {
         li.z = sl.zcols + (a.line == 3 ? ny : 0); li.z_js = 0; li.z_f32 = 0;
         li.start = 0; li.stride = 1;
       }
-      it_lines.h.push_back(li);
       LineTask lx = lt;
       lx.z = sl.x_int + cd.off; lx.z_js = 0; lx.z_f32 = 0; lx.skip = skip_fin;
-      x_lines.h.push_back(lx);
+      if (dense_lines(a.L) && a.gs->mfull) {
+        li.mat = li.pre_dst ? a.gs->mpre_t : a.gs->mfull;
+        lx.mat = a.gs->mfull;
+        add_block_task(it_lines_d, li, div_up(a.L, 64));
+        add_block_task(x_lines_d, lx, div_up(a.L, 64));
+        lmax_dense = std::max(lmax_dense, a.L);
+      } else {
+        it_lines.h.push_back(li);
+        x_lines.h.push_back(lx);
+      }
 
       // f'_c formation and back substitution
       const RectDev& ad = p->rd[a.rect];
@@ -423,6 +442,8 @@ void Engine::Impl::build() {
   for (auto* tl : {&it_tri, &cyc_tri, &arm_tri}) tl->upload();
   it_lines.upload();
   x_lines.upload();
+  it_lines_d.upload();
+  x_lines_d.upload();
   it_cols.upload();
   it_op.upload();
   res_op.upload();
@@ -454,8 +475,9 @@ void Engine::Impl::iteration(int j, int tag) {
     launch_idst_cols(it_cols.dev(), it_cols.n(), it_cols.nblocks, s);
     Timing::end(7, s);
   }
-  if (it_lines.n()) {
+  if (it_lines.n() || it_lines_d.n()) {
     Timing::begin(4, s);
+    launch_lines_dense(it_lines_d.dev(), it_lines_d.n(), it_lines_d.nblocks, lmax_dense, j, s);
     launch_lines(it_lines.dev(), it_lines.n(), smem_lines, j, s);
     Timing::end(4, s);
   }
@@ -495,8 +517,9 @@ void Engine::Impl::end_of_cycle() {
     cyc_inv.launch(0, s);
     Timing::end(0, s);
   }
-  if (x_lines.n()) {
+  if (x_lines.n() || x_lines_d.n()) {
     Timing::begin(4, s);
+    launch_lines_dense(x_lines_d.dev(), x_lines_d.n(), x_lines_d.nblocks, lmax_dense, 0, s);
     launch_lines(x_lines.dev(), x_lines.n(), smem_lines, 0, s);
     Timing::end(4, s);
   }
@@ -567,6 +590,7 @@ void Engine::setup() {
     const long long coff = sl.plan->rd[sl.plan->centre].off;
     FDS_HIP(hipMemsetAsync(sl.x_int + coff, 0, 8 * sl.Nc, s));
   }
+  launch_lines_dense(I.x_lines_d.dev(), I.x_lines_d.n(), I.x_lines_d.nblocks, I.lmax_dense, 0, s);
   if (I.x_lines.n()) launch_lines(I.x_lines.dev(), I.x_lines.n(), I.smem_lines, 0, s);
   launch_operator(1, I.res_op.dev(), I.res_op.n(), I.res_op.nblocks, 0, s);
   launch_restart(I.kry.dev(), I.kry.n(), I.kry.nblocks, 1, I.max_cycles, s);
@@ -574,6 +598,13 @@ void Engine::setup() {
   I.read_states();
   I.set_up = true;
   if (Timing::on()) I.account_arms(true);
+}
+
+// Line term of one arm: the line in and out, plus the dense operator when
+// the term is a dense product.
+static double line_bytes(const ArmInfo& a) {
+  const double mat = (dense_lines(a.L) && a.gs->mfull) ? 8.0 * a.L * a.L : 0.0;
+  return 16.0 * a.L + mat;
 }
 
 void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
@@ -584,7 +615,7 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
     const double Nc = (double)sl.Nc;
     const int its = host_states[i].iterations - before[i].iterations;
     double lines = 0;
-    for (const ArmInfo& a : sl.plan->arms) lines += 16.0 * a.L;
+    for (const ArmInfo& a : sl.plan->arms) lines += line_bytes(a);
     // per Arnoldi step: the forward transform reads v_j, writes it back
     // normalised and writes the scratch; the tridiagonal solve reads and
     // writes the scratch.  Flexible: the inverse transform writes z_j and
@@ -629,7 +660,7 @@ void Engine::Impl::account_arms(bool setup_phase) {
     const double Nc = (double)sl.Nc;
     if (setup_phase) {
       double lines = 0;
-      for (const ArmInfo& a : sl.plan->arms) lines += 16.0 * a.L;
+      for (const ArmInfo& a : sl.plan->arms) lines += line_bytes(a);
       Timing::add_bytes(2, Nc * 24.0);
       Timing::add_bytes(4, lines);
     }

@@ -31,6 +31,24 @@ struct Error : std::runtime_error {
                          std::string(#call) + ": " + hipGetErrorString(e_));           \
   } while (0)
 
+// ---------------------------------------------------------------- timing
+// Per-class kernel timing.  Between begin(cls) and end(cls) every kernel
+// launch records its own start/stop events through the dispatch packet
+// (hipExtLaunchKernel), so timing adds no packets to the stream.
+struct Timing {
+  static void enable(int mask);
+  static bool on();
+  static bool on(int cls);
+  static void add_bytes(int cls, double bytes);
+  static double bytes(int cls);
+  static void begin(int cls, hipStream_t s);
+  static void end(int cls, hipStream_t s);
+  // events for the next launch when a class is being timed
+  static bool take_pair(hipEvent_t* start, hipEvent_t* stop);
+  static void read(int cls, long long* calls, double* ms);
+  static void reset();
+};
+
 // ---------------------------------------------------------------- FFT plan
 // Complex FFT of length N = n + 1 used to evaluate the DST-I of length n.
 //   kind 0 (mixed radix): Stockham passes over N.
@@ -67,6 +85,50 @@ struct FftDesc {
 };
 
 constexpr int kGemmMaxN = 1024;
+
+// ---------------------------------------------------------------- wave DST
+// LDS layout of the wave-parallel row transform: the workgroup's copy of the
+// tables (twiddles, post-processing, convolution kernel, chirp, Rader
+// permutations) followed by one padded buffer per row.  The same layout is
+// used for the table image in device memory, so staging is one plain copy.
+// Padded LDS index: one spare entry per 256 bytes keeps the strided accesses
+// of the early passes spread over the banks.
+template <typename T> __host__ __device__ __forceinline__ int wpad(int i) {
+  return i + (i >> (sizeof(T) == 8 ? 4 : 5));
+}
+
+// Byte offsets of the per-workgroup tables and of the row buffers.  The
+// twiddles are stored per pass: pass p (radix R, Ns = product of the earlier
+// radices) holds w^{r k L/(Ns R)} at (r-1) Ns + k, k < Ns, 1 <= r < R, so
+// the lanes of a pass read consecutive entries.
+struct WaveLayout {
+  int tw, post, kern, chirp, pin, pout, rows, row_bytes;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ WaveLayout wave_layout(int kind, int N, int L, int W, int twlen) {
+  const int cb = (int)sizeof(T) * 2;
+  WaveLayout w;
+  w.tw = 0;
+  w.post = w.tw + twlen * cb;
+  w.kern = w.post + (N + 1) * cb;
+  w.chirp = w.kern + (kind != FFT_MIXED ? L : 0) * cb;
+  w.pin = w.chirp + (kind == FFT_BLUESTEIN ? N : 0) * cb;
+  w.pout = w.pin + (kind == FFT_RADER ? L : 0) * 4;
+  w.rows = (w.pout + (kind == FFT_RADER ? L : 0) * 4 + 15) / 16 * 16;
+  w.row_bytes = ((wpad<T>(W - 1) + 1) * cb + 15) / 16 * 16;
+  return w;
+}
+
+// Everything the wave-parallel transform needs about its length, carried in
+// the task record itself (no dependent load through FftDesc).
+struct WaveDesc {
+  int N, L, W, kind, npass, twlen;
+  int img_chunks;           // 16-byte chunks of `img`
+  int pad;
+  const uint4* img;         // table image in the LDS layout, task precision
+  unsigned long long radices;  // radix of pass p in bits [5p, 5p+5) (at most 12 passes)
+};
 
 // Per-mode coefficients of the constant-coefficient tridiagonal solve
 //   delta y[i-1] + a y[i] + delta y[i+1] = s r[i],  a = -delta (q + 1/q),
@@ -117,13 +179,14 @@ struct DstTask {
   int rpb;                    // rows per block
   int accumulate;             // out += result
   int tw_lds;                 // 1: stage the twiddles in LDS ahead of the row buffers
-  int pad0;
+  int io_f32;                 // wave kernel: bit 0 input FP32, bit 1 output FP32
   double scale;
   const FftDesc* fft;
   const int* skip;            // skip when *skip != 0
   const double* in_scale;     // if set: input *= *in_scale, written back in place
   int block_begin;
   int pad;
+  WaveDesc wd;                // wave-parallel kernel only
 };
 
 struct TriTask {
@@ -151,6 +214,9 @@ struct LineTask {
   const double* gs;           // delta^2 (2/N) g_k, k = 1..L
   double* out;                // L doubles
   const int* skip;
+  const double* mat;          // dense operator (element (k, i) at k L + i), or null
+  int block_begin;
+  int pad2;
 };
 
 // Centre operator w = A_c z - sum_a S_ca z  (mode 0), or the residual

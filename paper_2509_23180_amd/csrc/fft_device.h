@@ -90,11 +90,67 @@ template <typename T, typename C> __device__ __forceinline__ void dft5(C* v) {
   v[3] = cadd(r2, cpi(i2));
 }
 
+// Length 8: outputs 2m from the length-4 DFT of v_r + v_{r+4}, outputs
+// 2m+1 from the length-4 DFT of (v_r - v_{r+4}) w8^r, w8 = exp(-i pi/4).
+template <typename T, typename C> __device__ __forceinline__ void dft8(C* v) {
+  const T h = T(0.707106781186547524400844362104849039);  // 1/sqrt(2)
+  C a[4], b[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    a[r] = cadd(v[r], v[r + 4]);
+    b[r] = csub(v[r], v[r + 4]);
+  }
+  b[1] = C{(b[1].x + b[1].y) * h, (b[1].y - b[1].x) * h};
+  b[2] = cmi(b[2]);
+  b[3] = C{(b[3].y - b[3].x) * h, -(b[3].x + b[3].y) * h};
+  dft4<T>(a);
+  dft4<T>(b);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    v[2 * m] = a[m];
+    v[2 * m + 1] = b[m];
+  }
+}
+
+// Length 16 as 4 x 4: with n = r1 + 4 r2 and k = m2 + 4 m1,
+// X_k = sum_{r1} w4^{r1 m1} w16^{r1 m2} sum_{r2} w4^{r2 m2} v_{r1 + 4 r2}.
+template <typename T, typename C> __device__ __forceinline__ void dft16(C* v) {
+  const T c1 = T(0.923879532511286756128183189396788933);  // cos(pi/8)
+  const T s1 = T(0.382683432365089771728459984030398867);  // sin(pi/8)
+  const T h = T(0.707106781186547524400844362104849039);
+  C y[4][4];
+#pragma unroll
+  for (int r1 = 0; r1 < 4; ++r1) {
+#pragma unroll
+    for (int r2 = 0; r2 < 4; ++r2) y[r1][r2] = v[r1 + 4 * r2];
+    dft4<T>(y[r1]);
+  }
+  // y[r1][m2] *= w16^{r1 m2}; w16^e = (cos(pi e/8), -sin(pi e/8))
+  y[1][1] = cmul(y[1][1], C{c1, -s1});
+  y[1][2] = cmul(y[1][2], C{h, -h});
+  y[1][3] = cmul(y[1][3], C{s1, -c1});
+  y[2][1] = cmul(y[2][1], C{h, -h});
+  y[2][2] = cmi(y[2][2]);
+  y[2][3] = cmul(y[2][3], C{-h, -h});
+  y[3][1] = cmul(y[3][1], C{s1, -c1});
+  y[3][2] = cmul(y[3][2], C{-h, -h});
+  y[3][3] = cmul(y[3][3], C{-c1, s1});
+#pragma unroll
+  for (int m2 = 0; m2 < 4; ++m2) {
+    C z[4] = {y[0][m2], y[1][m2], y[2][m2], y[3][m2]};
+    dft4<T>(z);
+#pragma unroll
+    for (int m1 = 0; m1 < 4; ++m1) v[m2 + 4 * m1] = z[m1];
+  }
+}
+
 template <int R, typename T, typename C> __device__ __forceinline__ void dftR(C* v) {
   if constexpr (R == 2) dft2<T>(v);
   else if constexpr (R == 3) dft3<T>(v);
   else if constexpr (R == 4) dft4<T>(v);
-  else dft5<T>(v);
+  else if constexpr (R == 5) dft5<T>(v);
+  else if constexpr (R == 8) dft8<T>(v);
+  else dft16<T>(v);
 }
 
 // One Stockham pass of fixed radix R over a row group of G threads.
@@ -167,6 +223,8 @@ __device__ C2<T>* stockham_lds(C2<T>* a, C2<T>* b, int L, int npass, const int* 
       case 3: stockham_pass<3, T>(src, dst, tw, L, Ns, g, G); break;
       case 4: stockham_pass<4, T>(src, dst, tw, L, Ns, g, G); break;
       case 5: stockham_pass<5, T>(src, dst, tw, L, Ns, g, G); break;
+      case 8: stockham_pass<8, T>(src, dst, tw, L, Ns, g, G); break;
+      case 16: stockham_pass<16, T>(src, dst, tw, L, Ns, g, G); break;
       default: generic_pass<T>(src, dst, tw, L, Ns, R, g, G); break;
     }
     __syncthreads();
@@ -294,20 +352,27 @@ __device__ __forceinline__ double sum_partials(const double* p, int P, double* r
   return block_sum(acc, red);
 }
 
+// Task of this block: the last record with block_begin <= blockIdx.x
+// (records are sorted by block_begin).  The first wave compares 64 records
+// per load round and counts with a ballot, so the search costs one dependent
+// load per 64 records; the result is made wave-uniform so that the record's
+// fields are read with scalar loads.
 template <typename Task>
 __device__ __forceinline__ int find_task(const Task* tasks, int ntasks, int* slot) {
-  if (threadIdx.x == 0) {
-    int lo = 0, hi = ntasks - 1;
+  if (threadIdx.x < 64) {
     const int b = blockIdx.x;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (tasks[mid].block_begin <= b) lo = mid;
-      else hi = mid - 1;
+    int cnt = 0;
+    for (int t0 = 0; t0 < ntasks; t0 += 64) {
+      const int t = t0 + (int)threadIdx.x;
+      const bool le = t < ntasks && tasks[t].block_begin <= b;
+      const unsigned long long m = __ballot(le);
+      cnt += __popcll(m);
+      if (m != ~0ull) break;
     }
-    *slot = lo;
+    if (threadIdx.x == 0) *slot = cnt - 1;
   }
   __syncthreads();
-  return *slot;
+  return __builtin_amdgcn_readfirstlane(*slot);
 }
 
 }  // namespace fds

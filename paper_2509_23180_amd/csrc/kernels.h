@@ -1,7 +1,20 @@
 // Launch wrappers of the HIP kernels (defined in kernels.hip).
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "fds_internal.h"
+
+
+// Kernel launch that carries start/stop events while a timing class is open.
+#define FDS_LAUNCH(K, GRID, BLOCK, SMEM, S, ...)                                  \
+  do {                                                                          \
+    hipEvent_t fds_e0_ = nullptr, fds_e1_ = nullptr;                            \
+    if (::fds::Timing::take_pair(&fds_e0_, &fds_e1_))                           \
+      hipExtLaunchKernelGGL(K, GRID, BLOCK, SMEM, S, fds_e0_, fds_e1_, 0u, __VA_ARGS__); \
+    else                                                                        \
+      hipLaunchKernelGGL(K, GRID, BLOCK, SMEM, S, __VA_ARGS__);                 \
+  } while (0)
 
 namespace fds {
 
@@ -12,6 +25,25 @@ enum class DstKind { D_D, D_F, F_F, F_D };
 
 void launch_dst(DstKind kind, const DstTask* tasks, int ntasks, int nblocks, size_t smem, int jidx,
                 hipStream_t s);
+// Dynamic LDS above 64 KiB must be opted into per kernel (gfx950 has 160 KiB
+// per CU).
+template <typename K>
+inline void ensure_smem(K kernel, size_t smem, size_t* granted) {
+  if (smem <= 65536 || smem <= *granted) return;
+  if (smem > 160 * 1024) throw Error(FDS_E_UNSUPPORTED, "transform too long for LDS");
+  FDS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  *granted = smem;
+}
+
+// Wave-parallel variant (one row per 16/32/64 lanes, register budget E).
+// Storage types come from DstTask::io_f32 (dst_io_flags(kind)).
+inline int dst_io_flags(DstKind k) {
+  return ((k == DstKind::F_F || k == DstKind::F_D) ? 1 : 0) |
+         ((k == DstKind::D_F || k == DstKind::F_F) ? 2 : 0);
+}
+void launch_dst_wave(DstKind kind, int E, const DstTask* tasks, int ntasks, int nblocks,
+                     int threads, size_t smem, int jidx, hipStream_t s);
 // Matrix-core variant of the row sine transform: RT*16 rows per block, each
 // of the 4 waves covers CT*16 columns (4*CT*16 >= n).
 size_t gemm_smem_bytes(int n, bool fp32, int rt);
@@ -28,6 +60,10 @@ TriConfig tri_config(bool fp32, int max_rows);
 int tri_blocks(const TriConfig& c, int modes);
 void launch_tri(const TriConfig& c, bool fp32, const TriTask* tasks, int ntasks, int nblocks,
                 int jidx, hipStream_t s);
+// Dense line operators (LineTask::mat): 64 outputs per block, lmax = the
+// longest line of the list.
+void launch_lines_dense(const LineTask* tasks, int ntasks, int nblocks, int lmax, int jidx,
+                        hipStream_t s);
 void launch_lines(const LineTask* tasks, int ntasks, size_t smem, int jidx, hipStream_t s);
 void launch_operator(int mode, const OpTask* tasks, int ntasks, int nblocks, int jidx,
                      hipStream_t s);

@@ -379,6 +379,44 @@ __global__ void __launch_bounds__(kBlock) k_schur_lines(const LineTask* __restri
   for (int k = 1 + g; k <= L; k += kBlock) tk.out[k - 1] = dst_post<double>(C, f.post64, N, k);
 }
 
+// Schur line terms as dense products with the precomputed line operator:
+// out_i = sum_k M(k, i) v_k, v the sine coefficients of the line (pre_dst)
+// or the line of z.  A block covers 64 outputs of one line; its four
+// wavefronts take quarters of k and are added in a fixed order.
+__global__ void __launch_bounds__(kBlock) k_lines_dense(const LineTask* __restrict__ tasks,
+                                                         int ntasks, int jidx) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int slot;
+  __shared__ double part[4][64];
+  const LineTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  if (tk.skip && *tk.skip) return;
+  const int L = tk.L;
+  double* v = reinterpret_cast<double*>(smem_raw);
+  const long long base = (long long)jidx * tk.z_js + tk.start;
+  for (int k = threadIdx.x; k < L; k += kBlock) {
+    const long long idx = base + (long long)k * tk.stride;
+    v[k] = tk.z_f32 ? double(static_cast<const float*>(tk.z)[idx]) : static_cast<const double*>(tk.z)[idx];
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = (blockIdx.x - tk.block_begin) * 64 + lane;
+  const int q = (L + 3) / 4;
+  const int k0 = min(L, wave * q), k1 = min(L, k0 + q);
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (i < L) {
+    const double* m = tk.mat + i;
+    int k = k0;
+    for (; k + 7 < k1; k += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = fma(m[(long long)(k + u) * L], v[k + u], a[u]);
+    }
+    for (; k < k1; ++k) a[0] = fma(m[(long long)k * L], v[k], a[0]);
+  }
+  part[wave][lane] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  __syncthreads();
+  if (wave == 0 && i < L) tk.out[i] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+}
+
 // Boundary columns of z = S y (see ColTask): one wave per row.
 __global__ void __launch_bounds__(kBlock) k_idst_cols(const ColTask* __restrict__ tasks, int ntasks) {
   __shared__ int slot;
@@ -606,13 +644,34 @@ __global__ void __launch_bounds__(kBlock) k_gram_update(const KryTask* __restric
     xj[e] = ok ? vj[idx] : 0.0;
     acc[e] = !ok ? 0.0 : (tk.implicit_w ? xj[e] - line_term(tk, idx) : w[idx]);
   }
-  for (int i = 0; i < j; ++i) {
-    const double* vi = tk.V + (long long)i * Nc;
-    const double h = hs[i];
+  // Loads are predicated by value (not by branch) so that all of them are in
+  // flight together; two basis vectors per trip.
+  int i = 0;
+  for (; i + 1 < j; i += 2) {
+    const double* va = tk.V + (long long)i * Nc;
+    const double* vb = va + Nc;
+    const double ha = hs[i], hb = hs[i + 1];
+    double a[kVecEPT], c[kVecEPT];
 #pragma unroll
     for (int e = 0; e < kVecEPT; ++e) {
       const long long idx = base + (long long)e * kBlock + threadIdx.x;
-      if (idx < Nc) acc[e] -= h * vi[idx];
+      const bool ok = idx < Nc;
+      a[e] = ok ? va[idx] : 0.0;
+      c[e] = ok ? vb[idx] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < kVecEPT; ++e) {
+      acc[e] -= ha * a[e];
+      acc[e] -= hb * c[e];
+    }
+  }
+  if (i < j) {
+    const double* va = tk.V + (long long)i * Nc;
+    const double ha = hs[i];
+#pragma unroll
+    for (int e = 0; e < kVecEPT; ++e) {
+      const long long idx = base + (long long)e * kBlock + threadIdx.x;
+      acc[e] -= ha * ((idx < Nc) ? va[idx] : 0.0);
     }
   }
 #pragma unroll
@@ -911,20 +970,10 @@ __global__ void k_count_active(const ProbState* __restrict__ st, int n, int* __r
   if (threadIdx.x == 0) *out = (int)s;
 }
 
+
 // =====================================================================
 // Launchers
 // =====================================================================
-// Dynamic LDS above 64 KiB must be opted into per kernel (gfx950 has 160 KiB
-// per CU).
-template <typename K>
-static void ensure_smem(K kernel, size_t smem, size_t* granted) {
-  if (smem <= 65536 || smem <= *granted) return;
-  if (smem > 160 * 1024) throw Error(FDS_E_UNSUPPORTED, "transform too long for LDS");
-  FDS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-  *granted = smem;
-}
-
 void launch_dst(DstKind kind, const DstTask* tasks, int ntasks, int nblocks, size_t smem, int jidx,
                 hipStream_t s) {
   if (nblocks <= 0) return;
@@ -937,19 +986,19 @@ void launch_dst(DstKind kind, const DstTask* tasks, int ntasks, int nblocks, siz
   }
   switch (kind) {
     case DstKind::D_D:
-      hipLaunchKernelGGL((k_dst_rows<double, double, double>), dim3(nblocks), dim3(kBlock), smem, s,
+      FDS_LAUNCH((k_dst_rows<double, double, double>), dim3(nblocks), dim3(kBlock), smem, s,
                          tasks, ntasks, jidx);
       break;
     case DstKind::D_F:
-      hipLaunchKernelGGL((k_dst_rows<float, double, float>), dim3(nblocks), dim3(kBlock), smem, s,
+      FDS_LAUNCH((k_dst_rows<float, double, float>), dim3(nblocks), dim3(kBlock), smem, s,
                          tasks, ntasks, jidx);
       break;
     case DstKind::F_F:
-      hipLaunchKernelGGL((k_dst_rows<float, float, float>), dim3(nblocks), dim3(kBlock), smem, s,
+      FDS_LAUNCH((k_dst_rows<float, float, float>), dim3(nblocks), dim3(kBlock), smem, s,
                          tasks, ntasks, jidx);
       break;
     case DstKind::F_D:
-      hipLaunchKernelGGL((k_dst_rows<float, float, double>), dim3(nblocks), dim3(kBlock), smem, s,
+      FDS_LAUNCH((k_dst_rows<float, float, double>), dim3(nblocks), dim3(kBlock), smem, s,
                          tasks, ntasks, jidx);
       break;
   }
@@ -967,7 +1016,7 @@ void launch_dst_gemm(DstKind kind, int rt, int ct, const DstTask* tasks, int nta
   do {                                                                                           \
     static size_t granted = 0;                                                                   \
     ensure_smem(k_dst_gemm<T, TI, TO, R, C>, smem, &granted);                                    \
-    hipLaunchKernelGGL((k_dst_gemm<T, TI, TO, R, C>), dim3(nblocks), dim3(kBlock), smem, s, tasks, \
+    FDS_LAUNCH((k_dst_gemm<T, TI, TO, R, C>), dim3(nblocks), dim3(kBlock), smem, s, tasks, \
                        ntasks, jidx);                                                            \
   } while (0)
 #define FDS_G_CT(T, TI, TO, R)                      \
@@ -994,9 +1043,9 @@ void launch_tridiag(bool fp32, const TriTask* tasks, int ntasks, int nblocks, in
                     hipStream_t s) {
   if (nblocks <= 0) return;
   if (fp32)
-    hipLaunchKernelGGL(k_tridiag<float>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
+    FDS_LAUNCH(k_tridiag<float>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
   else
-    hipLaunchKernelGGL(k_tridiag<double>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
+    FDS_LAUNCH(k_tridiag<double>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
 }
 
 TriConfig tri_config(bool fp32, int max_rows) {
@@ -1034,7 +1083,7 @@ void launch_tri(const TriConfig& c, bool fp32, const TriTask* tasks, int ntasks,
   }
   const dim3 blk(c.threads);
 #define FDS_SEG(T, L, M) \
-  hipLaunchKernelGGL((k_tridiag_seg<T, L, M>), dim3(nblocks), blk, 0, s, tasks, ntasks, jidx)
+  FDS_LAUNCH((k_tridiag_seg<T, L, M>), dim3(nblocks), blk, 0, s, tasks, ntasks, jidx)
 #define FDS_SEG_MPB(T, L)                      \
   switch (c.mpb) {                             \
     case 64: FDS_SEG(T, L, 64); break;         \
@@ -1057,82 +1106,91 @@ void launch_tri(const TriConfig& c, bool fp32, const TriTask* tasks, int ntasks,
 #undef FDS_SEG
 }
 
+void launch_lines_dense(const LineTask* tasks, int ntasks, int nblocks, int lmax, int jidx,
+                        hipStream_t s) {
+  if (ntasks <= 0) return;
+  const size_t smem = sizeof(double) * (size_t)lmax;
+  static size_t granted = 0;
+  ensure_smem(k_lines_dense, smem, &granted);
+  FDS_LAUNCH(k_lines_dense, dim3(nblocks), dim3(kBlock), smem, s, tasks, ntasks, jidx);
+}
+
 void launch_lines(const LineTask* tasks, int ntasks, size_t smem, int jidx, hipStream_t s) {
   if (ntasks <= 0) return;
   static size_t granted = 0;
   ensure_smem(k_schur_lines, smem, &granted);
-  hipLaunchKernelGGL(k_schur_lines, dim3(ntasks), dim3(kBlock), smem, s, tasks, jidx);
+  FDS_LAUNCH(k_schur_lines, dim3(ntasks), dim3(kBlock), smem, s, tasks, jidx);
 }
 
 void launch_operator(int mode, const OpTask* tasks, int ntasks, int nblocks, int jidx,
                      hipStream_t s) {
   if (nblocks <= 0) return;
   if (mode == 0)
-    hipLaunchKernelGGL(k_operator<0>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
+    FDS_LAUNCH(k_operator<0>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
   else
-    hipLaunchKernelGGL(k_operator<1>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
+    FDS_LAUNCH(k_operator<1>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
 }
 
 void launch_gram_dots(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s) {
-  hipLaunchKernelGGL(k_gram_dots, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j);
+  FDS_LAUNCH(k_gram_dots, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j);
 }
 
 void launch_gram_solve(const KryTask* tasks, int ntasks, int j, hipStream_t s) {
-  hipLaunchKernelGGL(k_gram_solve, dim3(ntasks), dim3(kBlock), 0, s, tasks, ntasks, j);
+  FDS_LAUNCH(k_gram_solve, dim3(ntasks), dim3(kBlock), 0, s, tasks, ntasks, j);
 }
 
 void launch_gram_update(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s) {
-  hipLaunchKernelGGL(k_gram_update, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j);
+  FDS_LAUNCH(k_gram_update, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j);
 }
 
 void launch_mgs_finish(const KryTask* tasks, int ntasks, int j, int* flags, int tag, hipStream_t s) {
-  hipLaunchKernelGGL(k_mgs_finish, dim3(ntasks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
+  FDS_LAUNCH(k_mgs_finish, dim3(ntasks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
 }
 
 void launch_scale_newest(const KryTask* tasks, int j, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_newest, dim3(nblocks), dim3(kBlock), 0, s, tasks, j);
+  FDS_LAUNCH(k_scale_newest, dim3(nblocks), dim3(kBlock), 0, s, tasks, j);
 }
 
 void launch_idst_cols(const ColTask* tasks, int ntasks, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return;
-  hipLaunchKernelGGL(k_idst_cols, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
+  FDS_LAUNCH(k_idst_cols, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
 }
 
 void launch_ls_solve(const KryTask* tasks, int ntasks, hipStream_t s) {
-  hipLaunchKernelGGL(k_ls_solve, dim3((ntasks + 63) / 64), dim3(64), 0, s, tasks, ntasks);
+  FDS_LAUNCH(k_ls_solve, dim3((ntasks + 63) / 64), dim3(64), 0, s, tasks, ntasks);
 }
 
 void launch_combine(bool flex, const KryTask* tasks, int ntasks, int nblocks, hipStream_t s) {
   if (flex)
-    hipLaunchKernelGGL(k_combine<1>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
+    FDS_LAUNCH(k_combine<1>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
   else
-    hipLaunchKernelGGL(k_combine<0>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
+    FDS_LAUNCH(k_combine<0>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
 }
 
 void launch_restart(const KryTask* tasks, int ntasks, int nblocks, int initial, int max_cycles,
                     hipStream_t s) {
-  hipLaunchKernelGGL(k_restart, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, initial,
+  FDS_LAUNCH(k_restart, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, initial,
                      max_cycles);
 }
 
 void launch_lift(int mode, const LiftTask* tasks, int ntasks, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return;
-  if (mode == 0) hipLaunchKernelGGL(k_lift<0>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
-  else hipLaunchKernelGGL(k_lift<1>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
+  if (mode == 0) FDS_LAUNCH(k_lift<0>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
+  else FDS_LAUNCH(k_lift<1>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
 }
 
 void launch_iface(const IfaceTask* tasks, int ntasks, hipStream_t s) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(k_iface, dim3(ntasks), dim3(kBlock), 0, s, tasks, ntasks);
+  FDS_LAUNCH(k_iface, dim3(ntasks), dim3(kBlock), 0, s, tasks, ntasks);
 }
 
 void launch_residual(const ResTask* tasks, int ntasks, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return;
-  hipLaunchKernelGGL(k_residual, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
+  FDS_LAUNCH(k_residual, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
 }
 
 void launch_count_active(const ProbState* st, int n, int* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_count_active, dim3(1), dim3(kBlock), 0, s, st, n, out);
+  FDS_LAUNCH(k_count_active, dim3(1), dim3(kBlock), 0, s, st, n, out);
 }
 
 }  // namespace fds

@@ -51,6 +51,7 @@ struct FftTable {           // one transform length
   DevBuf mem;
   FftDesc host;             // with device pointers filled in
   const FftDesc* dev;       // device copy of `host`
+  WaveDesc wave64, wave32;  // wave-parallel transform descriptors
 };
 
 struct ModeTable {          // per-mode tridiagonal coefficients, FP64 and FP32
@@ -62,7 +63,16 @@ struct ModeTable {          // per-mode tridiagonal coefficients, FP64 and FP32
 struct GsTable {            // Schur line coefficients delta^2 (2/N) g_k
   DevBuf mem;
   const double* gs;
+  // Dense line operators for n <= kDenseLineMax (else null), n x n FP64,
+  // element (k, i) at k n + i:
+  //   full: delta^2 (2/N) S diag(g) S  (symmetric), applied to a line of z
+  //   pre:  (N/2) S diag(gs), transposed, applied to sine coefficients y
+  const double* mfull = nullptr;
+  const double* mpre_t = nullptr;
 };
+constexpr int kDenseLineMax = 1024;
+// Dense line operators in use (n <= kDenseLineMax unless FDS_LINES=fft).
+bool dense_lines(int n);
 
 // Process-wide cache of device tables (per device), keyed by length and by
 // (length, rows, h, kappa).  Entries live until process exit.
@@ -72,10 +82,13 @@ class TableCache {
   std::shared_ptr<FftTable> fft(int n);
   std::shared_ptr<ModeTable> modes(int n, int m, double h, double kappa);
   std::shared_ptr<GsTable> gs(int n, int m, double h, double kappa);
+  // wave-transform descriptor of the table whose device FftDesc is `dev`
+  WaveDesc wave_desc(const FftDesc* dev, bool fp32);
 
  private:
   std::mutex mu_;
   std::map<std::pair<int, int>, std::shared_ptr<FftTable>> fft_;
+  std::map<const FftDesc*, std::shared_ptr<FftTable>> by_dev_;
   std::map<std::tuple<int, int, int, double, double>, std::shared_ptr<ModeTable>> modes_;
   std::map<std::tuple<int, int, int, double, double>, std::shared_ptr<GsTable>> gs_;
 };
@@ -87,22 +100,44 @@ void mode_coefs_host(int n, int m, double h, double kappa, double scale,
 std::shared_ptr<ModeTable> upload_modes(const std::vector<ModeCoef<double>>& c64,
                                         const std::vector<ModeCoef<float>>& c32);
 
-// Radix schedule of a complex FFT of length N (4s, 2s, 3s, 5s, then other
-// primes ascending).
+// Radix schedule of a complex FFT of length N (16s, then one of 8/4/2, 3s,
+// 5s, then other primes ascending).
 std::vector<int> fft_radices(int N);
+// True when every radix of the schedule of L has a register butterfly.
+bool fixed_radices(int L);
 // Algorithm for the length-(n+1) FFT behind a DST-I of length n: kind, the
 // Stockham length L it runs, and the LDS entries per buffer.
 struct FftShape { int kind; int L; int lds_len; };
 FftShape fft_shape(int n);
-// Threads per row for a transform of length n (power of two, 32..256).
+// Threads per row for the workgroup-wide transform of length n (power of
+// two, 32..256).
 int dst_threads_per_row(int n);
 size_t dst_smem_bytes(int n, bool fp32);
 bool dst_twiddles_in_lds(int n, bool fp32);
 size_t line_smem_bytes(int n);
-// Row sine transform algorithm for length n: the LDS FFT (default) or the
-// dense sine matrix on the matrix cores (n <= 1024; FDS_DST_ALGO=gemm).
-// FDS_DST_ALGO=fft|gemm|auto selects it for measurements.
-struct DstChoice { bool gemm; int rt; int ct; int rows_per_block; size_t smem; };
+// Wave-parallel row transform: lanes per row G, register budget E (complex
+// entries per lane and pass), wavefronts per workgroup, LDS bytes.  E == 0
+// when the length needs a radix without a register butterfly or more
+// registers than allowed.
+struct WaveCfg { int E; int G; int waves; int rows_per_block; size_t smem; };
+WaveCfg dst_wave_config(int n, bool fp32);
+// Lanes per row of the wave transform of length n, and its radix schedule
+// for an inner FFT of length L (empty when L has a prime factor above 5).
+int wave_lanes(int n);
+std::vector<int> wave_radices(int L, int G);
+// Row sine transform algorithm for length n: the wave-parallel LDS FFT
+// (default where WaveCfg allows), the workgroup-wide LDS FFT, or the dense
+// sine matrix on the matrix cores (n <= 1024).  FDS_DST_ALGO=wave|fft|gemm|auto
+// selects it for measurements.
+struct DstChoice {
+  bool gemm;
+  int rt;
+  int ct;
+  int rows_per_block;
+  size_t smem;
+  int wave_e;    // > 0: wave-parallel kernel with this register budget
+  int threads;   // workgroup size
+};
 DstChoice dst_choice(int n, bool fp32);
 
 // ---------------------------------------------------------------- plan
@@ -183,16 +218,5 @@ class Engine {
 };
 
 // Process-wide timing by kernel class (see fds_timing_*).
-struct Timing {
-  static void enable(int mask);
-  static bool on();
-  static bool on(int cls);
-  static void add_bytes(int cls, double bytes);
-  static double bytes(int cls);
-  static void begin(int cls, hipStream_t s);
-  static void end(int cls, hipStream_t s);
-  static void read(int cls, long long* calls, double* ms);
-  static void reset();
-};
 
 }  // namespace fds

@@ -1,6 +1,7 @@
 // Device tables: FFT twiddles, per-mode tridiagonal coefficients and Schur
 // line coefficients.  All values are computed on the host in FP64 (long
 // double where the angle reduction benefits) and uploaded once.
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdlib>
@@ -12,10 +13,14 @@
 namespace fds {
 
 std::vector<int> fft_radices(int N) {
+  // radix-16 and radix-8 butterflies run in registers, so powers of two go
+  // out in as few passes as possible
   std::vector<int> r;
   int n = N;
-  while (n % 4 == 0) { r.push_back(4); n /= 4; }
-  while (n % 2 == 0) { r.push_back(2); n /= 2; }
+  while (n % 16 == 0) { r.push_back(16); n /= 16; }
+  if (n % 8 == 0) { r.push_back(8); n /= 8; }
+  if (n % 4 == 0) { r.push_back(4); n /= 4; }
+  if (n % 2 == 0) { r.push_back(2); n /= 2; }
   while (n % 3 == 0) { r.push_back(3); n /= 3; }
   while (n % 5 == 0) { r.push_back(5); n /= 5; }
   for (int p = 7; n > 1; p += 2) {
@@ -26,16 +31,25 @@ std::vector<int> fft_radices(int N) {
   return r;
 }
 
+bool fixed_radices(int L) {
+  for (int R : fft_radices(L))
+    if (R != 2 && R != 3 && R != 4 && R != 5 && R != 8 && R != 16) return false;
+  return true;
+}
+
 // Relative cost of one Stockham FFT of length L (per output, summed over
-// passes): fixed butterflies 2/3/4/5, direct sums for other primes.
+// passes): a pass costs one LDS round trip plus its butterfly arithmetic;
+// other primes take direct sums.
 static double stockham_cost(int L) {
   double c = 0;
   for (int R : fft_radices(L)) {
     switch (R) {
       case 2: c += 1.0; break;
-      case 3: c += 2.0; break;
-      case 4: c += 1.5; break;
-      case 5: c += 3.0; break;
+      case 3: c += 1.6; break;
+      case 4: c += 1.3; break;
+      case 5: c += 2.0; break;
+      case 8: c += 1.7; break;
+      case 16: c += 2.2; break;
       default: c += 1.5 * R; break;
     }
   }
@@ -103,27 +117,113 @@ size_t dst_smem_bytes(int n, bool fp32) {
   return row_buffers(n, fp32) + tw;
 }
 
+// Entries of the per-pass twiddle table: sum over passes of (R - 1) Ns.
+static int wave_twiddle_len(const std::vector<int>& rad) {
+  int ns = 1, t = 0;
+  for (int R : rad) {
+    t += (R - 1) * ns;
+    ns *= R;
+  }
+  return t;
+}
+
+int wave_lanes(int n) {
+  // lanes per row: as many as keep every lane of a radix-4 pass busy (one
+  // wavefront per row from L = 256 on), so short batches still spread over
+  // many wavefronts; FDS_DST_G overrides (16, 32, 64) for measurements
+  // (read once: the cached table images follow the schedule of this choice)
+  static const int forced = [] {
+    const char* e = std::getenv("FDS_DST_G");
+    const int v = e ? std::atoi(e) : 0;
+    return (v == 16 || v == 32 || v == 64) ? v : 0;
+  }();
+  if (forced) return forced;
+  const int L = fft_shape(n).L;
+  int G = 16;
+  while (G < 64 && 4 * (2 * G) <= L) G *= 2;
+  return G;
+}
+
+std::vector<int> wave_radices(int L, int G) {
+  // powers of two in passes as long as every pass keeps L/R >= G
+  // butterflies, then 3s and 5s (other primes: not a wave schedule)
+  const int rmax = std::max(2, L / G);
+  std::vector<int> r;
+  int m = L, a = 0;
+  while (m % 2 == 0) { m /= 2; ++a; }
+  for (int R : {16, 8, 4}) {
+    const int e = R == 16 ? 4 : R == 8 ? 3 : 2;
+    while (a >= e && R <= rmax) { r.push_back(R); a -= e; }
+  }
+  while (a > 0) { r.push_back(2); --a; }
+  while (m % 3 == 0) { r.push_back(3); m /= 3; }
+  while (m % 5 == 0) { r.push_back(5); m /= 5; }
+  if (m != 1 || r.size() > 12) r.clear();
+  return r;
+}
+
+WaveCfg dst_wave_config(int n, bool fp32) {
+  WaveCfg c{0, 0, 0, 0, 0};
+  const FftShape shp = fft_shape(n);
+  const int G = wave_lanes(n);
+  const std::vector<int> rad = wave_radices(shp.L, G);
+  if (rad.empty()) return c;
+  int need = (n + G - 1) / G;  // row elements per lane
+  for (int R : rad) need = std::max(need, (shp.L / R + G - 1) / G * R);
+  for (int e : {4, 8, 16, 32, 64})
+    if ((e <= 32 || fp32) && need <= e) { c.E = e; break; }
+  if (!c.E) return c;
+  c.G = G;
+  const int twl = wave_twiddle_len(rad);
+  const WaveLayout lay = fp32 ? wave_layout<float>(shp.kind, n + 1, shp.L, shp.lds_len, twl)
+                              : wave_layout<double>(shp.kind, n + 1, shp.L, shp.lds_len, twl);
+  // workgroup size with the most rows resident per CU (160 KB of LDS, at most
+  // 16 wavefronts); ties go to the larger workgroup (fewer table copies)
+  int best = -1;
+  for (int waves : {1, 2, 4}) {
+    const int rpb = waves * 64 / c.G;
+    const size_t smem = (size_t)lay.rows + (size_t)rpb * lay.row_bytes;
+    if (smem > 160u * 1024u) continue;
+    const int blocks = std::min((int)(160u * 1024u / smem), 16 / waves);
+    const int resident = blocks * rpb;
+    if (resident >= best) {
+      best = resident;
+      c.waves = waves;
+      c.rows_per_block = rpb;
+      c.smem = smem;
+    }
+  }
+  if (best <= 0) c.E = 0;
+  return c;
+}
+
 DstChoice dst_choice(int n, bool fp32) {
-  DstChoice c{false, 1, 4, 0, 0};
+  DstChoice c{false, 1, 4, 0, 0, 0, kBlock};
   const char* env = std::getenv("FDS_DST_ALGO");
   const std::string mode = env ? env : "auto";
-  bool gemm = false;
-  if (n <= kGemmMaxN) {
-    if (mode == "gemm") gemm = true;
-    else if (mode == "fft") gemm = false;
-    else gemm = false;   // measured slower than the LDS FFT at n = 256 and 1024
-  }
-  if (gemm) {
+  if (mode == "gemm" && n <= kGemmMaxN) {
     const int np = (n + 63) / 64 * 64;
     c.gemm = true;
     c.rt = np <= 256 ? 2 : 1;
     c.ct = 4;
     c.rows_per_block = c.rt * 16;
     c.smem = gemm_smem_bytes(n, fp32, c.rt);
-  } else {
-    c.rows_per_block = kBlock / dst_threads_per_row(n);
-    c.smem = dst_smem_bytes(n, fp32);
+    return c;
   }
+  // the dense-matrix variant measured slower than the LDS FFTs at n = 256
+  // and 1024, so the automatic choice never takes it
+  if (mode != "fft") {
+    const WaveCfg w = dst_wave_config(n, fp32);
+    if (w.E) {
+      c.wave_e = w.E;
+      c.threads = 64 * w.waves;
+      c.rows_per_block = w.rows_per_block;
+      c.smem = w.smem;
+      return c;
+    }
+  }
+  c.rows_per_block = kBlock / dst_threads_per_row(n);
+  c.smem = dst_smem_bytes(n, fp32);
   return c;
 }
 
@@ -232,6 +332,11 @@ std::shared_ptr<FftTable> TableCache::fft(int n) {
   const int np = n <= kGemmMaxN ? (n + 63) / 64 * 64 : 0;
   const size_t o_s64 = take(sizeof(double) * std::max((size_t)np * np, (size_t)1));
   const size_t o_s32 = take(sizeof(float) * std::max((size_t)np * np, (size_t)1));
+  const std::vector<int> wrad = wave_radices(L, wave_lanes(n));
+  const int twl = wave_twiddle_len(wrad);
+  const WaveLayout wl64 = wave_layout<double>(shp.kind, N, L, shp.lds_len, twl);
+  const WaveLayout wl32 = wave_layout<float>(shp.kind, N, L, shp.lds_len, twl);
+  const size_t o_w64 = take((size_t)wl64.rows), o_w32 = take((size_t)wl32.rows);
   const size_t total = o;
   std::vector<unsigned char> host(total, 0);
   auto* tw64 = reinterpret_cast<double2*>(host.data() + o_tw64);
@@ -301,8 +406,59 @@ std::shared_ptr<FftTable> TableCache::fft(int n) {
         s32[(size_t)j * np + c] = (float)v;
       }
   }
+  // table images in the LDS layout of the wave-parallel row transform
+  {
+    // per-pass twiddles: pass (R, Ns) holds exp(-2 pi i r k stw / L) at
+    // (r-1) Ns + k, stw = L / (Ns R)
+    std::vector<cld> ptw;
+    {
+      int ns = 1;
+      for (int R : wrad) {
+        const int stw = L / (ns * R);
+        for (int r = 1; r < R; ++r)
+          for (int k = 0; k < ns; ++k) ptw.push_back(unit_root((long long)r * k * stw, L));
+        ns *= R;
+      }
+    }
+    auto put = [&](size_t base, const WaveLayout& w, size_t cb, size_t o_tw, size_t o_p, size_t o_k,
+                   size_t o_c) {
+      (void)o_tw;
+      unsigned char* img = host.data() + base;
+      for (size_t i = 0; i < ptw.size(); ++i) {
+        if (cb == sizeof(double2)) {
+          const double2 v{(double)ptw[i].real(), (double)ptw[i].imag()};
+          std::memcpy(img + w.tw + i * cb, &v, cb);
+        } else {
+          const float2 v{(float)ptw[i].real(), (float)ptw[i].imag()};
+          std::memcpy(img + w.tw + i * cb, &v, cb);
+        }
+      }
+      std::memcpy(img + w.post, host.data() + o_p, cb * (N + 1));
+      if (rader || blue) std::memcpy(img + w.kern, host.data() + o_k, cb * L);
+      if (blue) std::memcpy(img + w.chirp, host.data() + o_c, cb * N);
+      if (rader) {
+        std::memcpy(img + w.pin, host.data() + o_pin, sizeof(int) * L);
+        std::memcpy(img + w.pout, host.data() + o_pout, sizeof(int) * L);
+      }
+    };
+    put(o_w64, wl64, sizeof(double2), o_tw64, o_p64, o_k64, o_c64);
+    put(o_w32, wl32, sizeof(float2), o_tw32, o_p32, o_k32, o_c32);
+  }
   t->mem.alloc(total);
   FftDesc d{};
+  for (int prec = 0; prec < 2; ++prec) {
+    WaveDesc& w = prec ? t->wave32 : t->wave64;
+    w = WaveDesc{};
+    w.N = N;
+    w.L = L;
+    w.W = shp.lds_len;
+    w.kind = shp.kind;
+    w.npass = (int)wrad.size();
+    w.twlen = twl;
+    w.img_chunks = (prec ? wl32.rows : wl64.rows) / 16;
+    w.img = t->mem.as<uint4>(prec ? o_w32 : o_w64);
+    for (size_t i = 0; i < wrad.size(); ++i) w.radices |= (unsigned long long)wrad[i] << (5 * i);
+  }
   d.N = N;
   d.np = np;
   d.smat64 = np ? t->mem.as<double>(o_s64) : nullptr;
@@ -327,7 +483,15 @@ std::shared_ptr<FftTable> TableCache::fft(int n) {
   t->host = d;
   t->dev = t->mem.as<FftDesc>(0);
   fft_[key] = t;
+  by_dev_[t->dev] = t;
   return t;
+}
+
+WaveDesc TableCache::wave_desc(const FftDesc* dev, bool fp32) {
+  std::lock_guard<std::mutex> lk(mu_);
+  auto it = by_dev_.find(dev);
+  if (it == by_dev_.end()) throw Error(FDS_E_INVALID_ARG, "unknown transform table");
+  return fp32 ? it->second->wave32 : it->second->wave64;
 }
 
 // theta_k with cosh(theta_k) = -a_k/(2 delta),
@@ -429,11 +593,50 @@ std::shared_ptr<GsTable> TableCache::gs(int n, int m, double h, double kappa) {
     v[k - 1] = delta * delta * (2.0 / N) * g;
   }
   auto t = std::make_shared<GsTable>();
-  t->mem.alloc(sizeof(double) * n);
-  FDS_HIP(hipMemcpy(t->mem.get(), v.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+  const bool dense = n <= kDenseLineMax;
+  const size_t nn = (size_t)n * n;
+  std::vector<double> host(n + (dense ? 2 * nn : 0));
+  std::copy(v.begin(), v.end(), host.begin());
+  if (dense) {
+    // S diag(gs) S by product to sum: sin(a) sin(b) = (cos(a-b) - cos(a+b))/2,
+    // so M_ik = (c(|i-k|) - c(i+k))/2 with c(t) = sum_l gs_l cos(pi l t/N)
+    // (i, k, l = 1..n; angles reduced modulo 2N before the cosine).
+    std::vector<long double> cs(2 * N), sn(2 * N);  // cos / sin(pi r/N), r < 2N
+    for (int r = 0; r < 2 * N; ++r) {
+      cs[r] = cosl(kPi * (long double)r / (long double)N);
+      sn[r] = sinl(kPi * (long double)r / (long double)N);
+    }
+    std::vector<long double> c(2 * N + 1);
+    for (int tt = 0; tt <= 2 * N; ++tt) {
+      long double acc = 0;
+      for (int l = 1; l <= n; ++l) acc += (long double)v[l - 1] * cs[(long long)l * tt % (2LL * N)];
+      c[tt] = acc;
+    }
+    double* mf = host.data() + n;
+    double* mp = mf + nn;
+    for (int i = 1; i <= n; ++i)
+      for (int k = 1; k <= n; ++k) {
+        mf[(size_t)(k - 1) * n + (i - 1)] = (double)(0.5L * (c[std::abs(i - k)] - c[i + k]));
+        // (N/2) S_ik gs_k stored at (k, i)
+        mp[(size_t)(k - 1) * n + (i - 1)] =
+            (double)(0.5L * N * sn[(long long)i * k % (2LL * N)] * (long double)v[k - 1]);
+      }
+  }
+  t->mem.alloc(sizeof(double) * host.size());
+  FDS_HIP(hipMemcpy(t->mem.get(), host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice));
   t->gs = t->mem.as<double>(0);
+  if (dense) {
+    t->mfull = t->gs + n;
+    t->mpre_t = t->mfull + nn;
+  }
   gs_[key] = t;
   return t;
+}
+
+bool dense_lines(int n) {
+  const char* e = std::getenv("FDS_LINES");
+  const bool fft = e && std::string(e) == "fft";
+  return !fft && n <= kDenseLineMax;
 }
 
 }  // namespace fds

@@ -38,9 +38,11 @@ DST_SIZES = [1, 2, 3, 4, 5, 7, 10, 16, 31, 32, 33, 63, 64, 65, 96, 100, 127, 128
              300, 511, 512, 1000, 1023, 1024, 1025, 1200, 1500, 2047, 2048]
 
 
-@pytest.fixture(params=["fft", "gemm"])
+@pytest.fixture(params=["wave", "fft", "gemm"])
 def dst_algo(request, monkeypatch):
-    """Both row-transform algorithms (the matrix-core one exists for n <= 1024)."""
+    """Every row-transform algorithm: wave-parallel LDS FFT (where its radices
+    and register budget allow, else the workgroup FFT), workgroup-wide LDS FFT,
+    and the matrix-core product (n <= 1024)."""
     monkeypatch.setenv("FDS_DST_ALGO", request.param)
     return request.param
 

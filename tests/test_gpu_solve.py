@@ -42,7 +42,11 @@ def _problem(shape, n, kappa, kind, seed=0):
 
 @pytest.fixture(params=["fft", "auto"])
 def dst_algo(request, monkeypatch):
+    """Workgroup-wide row FFT with the FFT line kernel, and the automatic
+    choice (wave-parallel row FFT, dense line operators)."""
     monkeypatch.setenv("FDS_DST_ALGO", request.param)
+    if request.param == "fft":
+        monkeypatch.setenv("FDS_LINES", "fft")
     return request.param
 
 
