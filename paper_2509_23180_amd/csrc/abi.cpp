@@ -204,8 +204,7 @@ fds_status fds_solve_batch(fds_plan* const* plans, int32_t count, const double* 
       max_cycles = std::max(max_cycles, plans[i]->opt.max_cycles);
       reqs[i] = SolveRequest{plans[i], rhs[i], bc ? bc[i] : nullptr, x[i], tol[i]};
     }
-    Engine eng(reqs, m, prec, max_cycles, as_stream(stream));
-    std::vector<SolveOutcome> out = eng.run();
+    std::vector<SolveOutcome> out = Engine::run_batch(reqs, m, prec, max_cycles, as_stream(stream));
     fds_status first = FDS_OK;
     for (int i = 0; i < count; ++i) {
       if (res) res[i] = out[i].res;

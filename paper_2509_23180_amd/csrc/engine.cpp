@@ -5,11 +5,17 @@
 // L_c x_c = f'_c with restarted right-preconditioned GMRES(m) (plain FP64) or
 // flexible GMRES(m) with an FP32 preconditioner; back-substitute the arms
 // A_a p_a = b_a - R_ac x_c.  Every kernel launch serves all problems of the
-// batch; problems that finished (or whose cycle ended) skip their work.
+// current set; problems whose cycle ended skip their work.  Problems join
+// (admit: set-up phase) and leave (retire: back substitution and output) at
+// cycle boundaries, so a request stream is served by continuous batching.
+// Every kernel works on one problem's data with fixed-order reductions and a
+// per-problem kernel configuration, so a problem's result does not depend on
+// which other problems share its launches.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 
 #include "runtime.h"
 
@@ -19,19 +25,17 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// Task records of one launch; the device copy lives in the owning set's blob.
 template <typename T>
 struct TaskList {
   std::vector<T> h;
-  DevBuf d;
+  const T* dptr = nullptr;
   int nblocks = 0;
   size_t smem = 0;
-  const T* dev() const { return d.as<T>(); }
+  const T* dev() const { return dptr; }
   int n() const { return (int)h.size(); }
-  void upload() {
-    if (h.empty()) return;
-    d.alloc(sizeof(T) * h.size());
-    FDS_HIP(hipMemcpy(d.get(), h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
-  }
 };
 
 template <typename T>
@@ -41,10 +45,30 @@ void add_block_task(TaskList<T>& tl, T t, int nblocks) {
   tl.nblocks += nblocks;
 }
 
-int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
+// All task lists of a set in one device allocation, written by one copy.
+struct Blob {
+  std::vector<unsigned char> host;
+  DevBuf dev;
+  std::vector<std::function<void(const unsigned char*)>> fix;
+  template <typename T>
+  void add(TaskList<T>& tl) {
+    if (tl.h.empty()) return;
+    const size_t off = align256(host.size());
+    host.resize(off + sizeof(T) * tl.h.size());
+    std::memcpy(host.data() + off, tl.h.data(), sizeof(T) * tl.h.size());
+    TaskList<T>* p = &tl;
+    fix.push_back([p, off](const unsigned char* base) { p->dptr = reinterpret_cast<const T*>(base + off); });
+  }
+  void upload(hipStream_t s) {
+    if (host.empty()) return;
+    dev.alloc(host.size());
+    FDS_HIP(hipMemcpyAsync(dev.get(), host.data(), host.size(), hipMemcpyHostToDevice, s));
+    for (auto& f : fix) f(dev.as<unsigned char>());
+  }
+};
 
-// Row sine transforms of one stage, grouped by kernel configuration (LDS FFT,
-// or matrix-core product with a given tile shape) so every launch runs one
+// Row sine transforms of one stage, grouped by kernel configuration (wave
+// FFT, workgroup FFT, or matrix-core product) so every launch runs one
 // instantiation.
 struct DstStage {
   DstKind kind = DstKind::D_D;
@@ -80,8 +104,8 @@ struct DstStage {
     for (const Sub& s : subs) c += s.tl.n();
     return c;
   }
-  void upload() {
-    for (Sub& s : subs) s.tl.upload();
+  void stage(Blob& b) {
+    for (Sub& s : subs) b.add(s.tl);
   }
   void launch(int jidx, hipStream_t st) const {
     for (const Sub& s : subs) {
@@ -96,18 +120,37 @@ struct DstStage {
   }
 };
 
-struct Slot {
-  SolveRequest req;
-  fds_plan* plan = nullptr;
-  DevBuf mem;
-  double *b_int = nullptr, *x_int = nullptr, *tmpd = nullptr, *fp = nullptr, *V = nullptr,
-         *u = nullptr, *zbuf = nullptr, *lines = nullptr, *H = nullptr, *cs = nullptr,
-         *sn = nullptr, *g = nullptr, *y = nullptr, *partials = nullptr, *respart = nullptr,
-         *G = nullptr, *hv = nullptr, *zcols = nullptr;
-  float *Z = nullptr, *tmpf = nullptr;
-  ProbState* st = nullptr;
-  long long Nc = 0, Nint = 0;
-  int P = 0, Lmax = 0, res_blocks = 0;
+// Tridiagonal solves of one stage, grouped by the configuration each task's
+// own row count selects.
+struct TriStage {
+  bool fp32 = false;
+  struct Sub {
+    TriConfig c;
+    TaskList<TriTask> tl;
+  };
+  std::vector<Sub> subs;
+  void add(TriTask t) {
+    const TriConfig c = tri_config(fp32, t.rows);
+    Sub* sub = nullptr;
+    for (Sub& s : subs)
+      if (s.c.seg == c.seg && s.c.ls == c.ls && s.c.mpb == c.mpb && s.c.threads == c.threads) sub = &s;
+    if (!sub) {
+      subs.push_back(Sub{c, TaskList<TriTask>{}});
+      sub = &subs.back();
+    }
+    add_block_task(sub->tl, t, tri_blocks(c, t.modes));
+  }
+  int n() const {
+    int c = 0;
+    for (const Sub& s : subs) c += s.tl.n();
+    return c;
+  }
+  void stage(Blob& b) {
+    for (Sub& s : subs) b.add(s.tl);
+  }
+  void launch(hipStream_t st) const {
+    for (const Sub& s : subs) launch_tri(s.c, fp32, s.tl.dev(), s.tl.n(), s.tl.nblocks, 0, st);
+  }
 };
 
 // Buffer layout of one problem, shared by allocation and footprint queries.
@@ -152,319 +195,274 @@ SlotLayout layout_of(const fds_plan* p, int m, int precision) {
 
 }  // namespace
 
-struct Engine::Impl {
-  std::vector<Slot> slots;
-  int m, precision, max_cycles;
-  bool flex;
-  hipStream_t s;
-  DevBuf states;
-  std::vector<ProbState> host_states;
+// One solve: its device memory and its slot in the engine's state pool.
+struct Problem {
+  SolveRequest req;
+  fds_plan* plan = nullptr;
+  int id = 0;                     // caller's id (returned by retire)
+  int idx = 0;                    // index in the state pool / flag array
+  DevBuf mem;
+  double *b_int = nullptr, *x_int = nullptr, *tmpd = nullptr, *fp = nullptr, *V = nullptr,
+         *u = nullptr, *zbuf = nullptr, *lines = nullptr, *H = nullptr, *cs = nullptr,
+         *sn = nullptr, *g = nullptr, *y = nullptr, *partials = nullptr, *respart = nullptr,
+         *G = nullptr, *hv = nullptr, *zcols = nullptr;
+  float *Z = nullptr, *tmpf = nullptr;
+  ProbState* st = nullptr;
+  long long Nc = 0, Nint = 0;
+  int P = 0, Lmax = 0, res_blocks = 0;
+};
+
+namespace {
+
+// Task lists of every phase for one set of problems.
+struct TaskSet {
+  int m = 0;
+  bool flex = false;
   DstStage it_fwd, it_inv{DstKind::F_F}, cyc_fwd, cyc_inv, arm_fwd, arm_inv, bs_fwd;
-  TaskList<TriTask> it_tri, cyc_tri, arm_tri;
-  TriConfig it_tc{}, cyc_tc{}, arm_tc{};
+  TriStage it_tri, cyc_tri, arm_tri;
   TaskList<LineTask> it_lines, x_lines;      // FFT line kernel (one block per line)
   TaskList<LineTask> it_lines_d, x_lines_d;  // dense line operators
   int lmax_dense = 0;
+  size_t smem_lines = 0;
   TaskList<ColTask> it_cols;
   TaskList<OpTask> it_op, res_op;
   TaskList<KryTask> kry;
   TaskList<LiftTask> lift, gather;
   TaskList<IfaceTask> iface_fp, iface_bs;
   TaskList<ResTask> resid;
-  size_t smem_lines = 0;
-  int* flags_host = nullptr;      // per problem: serial of the last cycle that ended (mapped)
-  int* flags_dev = nullptr;
-  int cycle_serial = 0;
-  bool set_up = false;
-  std::vector<int> prev_its;
+  std::vector<Problem*> probs;
+  Blob blob;
 
-  // Algorithmic bytes (each operand read once, each result written once) of
-  // the work every problem did in the cycle that just ended, by kernel class.
-  void account_cycle(const std::vector<ProbState>& before);
-  void account_arms(bool setup_phase);
-
-  ~Impl() {
-    if (flags_host) (void)hipHostFree(flags_host);
+  TaskSet(int m_, bool flex_) : m(m_), flex(flex_) {
+    it_fwd.kind = flex ? DstKind::D_F : DstKind::D_D;
+    it_tri.fp32 = flex;
   }
-
-  void build();
-  void iteration(int j, int tag);
-  void end_of_cycle();
-  void read_states();
+  void add_problem(Problem& sl);
+  void upload(hipStream_t s) {
+    for (DstStage* d : {&it_fwd, &it_inv, &cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd}) d->stage(blob);
+    for (TriStage* t : {&it_tri, &cyc_tri, &arm_tri}) t->stage(blob);
+    blob.add(it_lines);
+    blob.add(x_lines);
+    blob.add(it_lines_d);
+    blob.add(x_lines_d);
+    blob.add(it_cols);
+    blob.add(it_op);
+    blob.add(res_op);
+    blob.add(kry);
+    blob.add(lift);
+    blob.add(gather);
+    blob.add(iface_fp);
+    blob.add(iface_bs);
+    blob.add(resid);
+    blob.upload(s);
+  }
+  void launch_x_lines(hipStream_t s) const {
+    launch_lines_dense(x_lines_d.dev(), x_lines_d.n(), x_lines_d.nblocks, lmax_dense, 0, s);
+    launch_lines(x_lines.dev(), x_lines.n(), smem_lines, 0, s);
+  }
+  void iteration(int j, int* flags_dev, int tag, hipStream_t s) const;
+  void end_of_cycle(int max_cycles, hipStream_t s) const;
 };
 
-void Engine::Impl::build() {
-  const int n = (int)slots.size();
-  states.alloc(sizeof(ProbState) * n);
-  host_states.assign(n, ProbState{});
-  for (int i = 0; i < n; ++i) {
-    Slot& sl = slots[i];
-    fds_plan* p = sl.plan;
-    const SlotLayout L = layout_of(p, m, precision);
-    sl.mem.alloc(L.total);
-    sl.Nc = (long long)p->nx * p->ny;
-    sl.Nint = p->n_internal;
-    sl.P = std::max(1, div_up(sl.Nc, kVecPerBlock));
-    sl.Lmax = std::max(p->nx, p->ny);
-    sl.b_int = sl.mem.as<double>(L.b_int);
-    sl.x_int = sl.mem.as<double>(L.x_int);
-    sl.tmpd = sl.mem.as<double>(L.tmpd);
-    sl.fp = sl.mem.as<double>(L.fp);
-    sl.V = sl.mem.as<double>(L.V);
-    sl.u = sl.mem.as<double>(L.u);
-    sl.zbuf = flex ? nullptr : sl.mem.as<double>(L.zbuf);
-    sl.lines = sl.mem.as<double>(L.lines);
-    double* small = sl.mem.as<double>(L.small);
-    sl.H = small;
-    sl.cs = sl.H + (size_t)(m + 1) * m;
-    sl.sn = sl.cs + m;
-    sl.g = sl.sn + m;
-    sl.y = sl.g + (m + 1);
-    sl.partials = sl.mem.as<double>(L.partials);
-    sl.respart = sl.mem.as<double>(L.respart);
-    sl.G = sl.mem.as<double>(L.gram);
-    sl.hv = sl.G + (size_t)(m + 1) * (m + 1);
-    sl.zcols = sl.mem.as<double>(L.zcols);
-    sl.Z = flex ? sl.mem.as<float>(L.Z) : nullptr;
-    sl.tmpf = flex ? sl.mem.as<float>(L.tmpf) : nullptr;
-    sl.st = states.as<ProbState>() + i;
-    ProbState& hs = host_states[i];
-    hs = ProbState{};
-    hs.tol = sl.req.tol;
-    hs.tol_eff = sl.req.tol;
-    hs.floor_coef = p->floor_coef;
-    hs.vscale = 1.0;
+void TaskSet::add_problem(Problem& sl) {
+  probs.push_back(&sl);
+  fds_plan* p = sl.plan;
+  const RectDev& cd = p->rd[p->centre];
+  const int nx = p->nx, ny = p->ny;
+  const long long Nc = sl.Nc;
+  const int* skip_it = &sl.st->cycle_done;
+  const int* skip_fin = &sl.st->finished;
+  const FftDesc* fftc = p->fft_c->dev;
+  const int rpb_c = kBlock / dst_threads_per_row(nx);
 
-    const RectDev& cd = p->rd[p->centre];
-    const int nx = p->nx, ny = p->ny;
-    const long long Nc = sl.Nc;
-    const int* skip_it = &sl.st->cycle_done;
-    const int* skip_fin = &sl.st->finished;
-    const FftDesc* fftc = p->fft_c->dev;
-    const int rpb_c = kBlock / dst_threads_per_row(nx);
+  // ---- per-iteration transforms of the centre.  The forward transform
+  // also normalises v_j (ProbState::vscale).  Plain variant: the Schur
+  // lines need z = A_c^{-1} v_j only on the centre's boundary lines, taken
+  // from the sine coefficients (rows 0 / ny-1 by a line transform, columns
+  // 0 / nx-1 by row sums).  Flexible variant: z_j = M^{-1} v_j is stored in
+  // FP32 (Z) and the operator is applied to it in full.
+  {
+    DstTask t{};
+    t.in = sl.V; t.in_js = Nc; t.in_rs = nx; t.in_cs = 1; t.in_scale = &sl.st->vscale;
+    t.out = flex ? (void*)sl.tmpf : (void*)sl.tmpd; t.out_js = 0; t.out_rs = nx; t.out_cs = 1;
+    t.rows = ny; t.n = nx; t.rpb = rpb_c; t.scale = 1.0; t.fft = fftc; t.skip = skip_it;
+    t.tw_lds = dst_twiddles_in_lds(nx, flex);
+    it_fwd.add(t);
 
-    // ---- per-iteration transforms of the centre.  The forward transform
-    // also normalises v_j (ProbState::vscale).  Plain variant: the Schur
-    // lines need z = A_c^{-1} v_j only on the centre's boundary lines, taken
-    // from the sine coefficients (rows 0 / ny-1 by a line transform, columns
-    // 0 / nx-1 by row sums).  Flexible variant: z_j = M^{-1} v_j is stored in
-    // FP32 (Z) and the operator is applied to it in full.
-    {
-      DstTask t{};
-      t.in = sl.V; t.in_js = Nc; t.in_rs = nx; t.in_cs = 1; t.in_scale = &sl.st->vscale;
-      t.out = flex ? (void*)sl.tmpf : (void*)sl.tmpd; t.out_js = 0; t.out_rs = nx; t.out_cs = 1;
-      t.rows = ny; t.n = nx; t.rpb = rpb_c; t.scale = 1.0; t.fft = fftc; t.skip = skip_it;
-      t.tw_lds = dst_twiddles_in_lds(nx, flex);
-      it_fwd.add(t);
+    TriTask tt{};
+    tt.data = t.out; tt.rs = nx; tt.js = 0; tt.rows = ny; tt.modes = nx;
+    tt.coef = flex ? (const void*)p->modes_c->c32 : (const void*)p->modes_c->c64;
+    tt.skip = skip_it;
+    it_tri.add(tt);
 
-      TriTask tt{};
-      tt.data = t.out; tt.rs = nx; tt.js = 0; tt.rows = ny; tt.modes = nx;
-      tt.coef = flex ? (const void*)p->modes_c->c32 : (const void*)p->modes_c->c64;
-      tt.skip = skip_it;
-      add_block_task(it_tri, tt, div_up(nx, kBlock));
-
-      if (flex) {
-        DstTask v{};
-        v.in = t.out; v.in_js = 0; v.in_rs = nx; v.in_cs = 1;
-        v.out = sl.Z; v.out_js = Nc;
-        v.out_rs = nx; v.out_cs = 1;
-        v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = 1.0; v.fft = fftc; v.skip = skip_it;
-        v.tw_lds = dst_twiddles_in_lds(nx, true);
-        it_inv.add(v);
-      } else {
-        bool west = false, east = false;
-        for (const ArmInfo& a : p->arms) { west |= a.line == 2; east |= a.line == 3; }
-        if (west || east) {
-          ColTask ct{};
-          ct.y = sl.tmpd; ct.zw = west ? sl.zcols : nullptr; ct.ze = east ? sl.zcols + ny : nullptr;
-          ct.fft = fftc; ct.nx = nx; ct.ny = ny; ct.skip = skip_it;
-          add_block_task(it_cols, ct, div_up(ny, kBlock / 64));
-        }
-      }
-    }
-    // ---- end-of-cycle preconditioner apply (plain variant): u -> x_c += A_c^{-1} u
-    if (!flex) {
-      DstTask t{};
-      t.in = sl.u; t.in_rs = nx; t.in_cs = 1; t.out = sl.tmpd; t.out_rs = nx; t.out_cs = 1;
-      t.rows = ny; t.n = nx; t.rpb = rpb_c; t.scale = 1.0; t.fft = fftc; t.skip = skip_fin;
-      t.tw_lds = dst_twiddles_in_lds(nx, false);
-      cyc_fwd.add(t);
-      TriTask tt{};
-      tt.data = sl.tmpd; tt.rs = nx; tt.rows = ny; tt.modes = nx; tt.coef = p->modes_c->c64;
-      tt.skip = skip_fin;
-      add_block_task(cyc_tri, tt, div_up(nx, kBlock));
-      DstTask v{};
-      v.in = sl.tmpd; v.in_rs = nx; v.in_cs = 1; v.out = sl.x_int + cd.off; v.out_rs = nx;
-      v.out_cs = 1; v.accumulate = 1;
-      v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = 1.0; v.fft = fftc; v.skip = skip_fin;
-      v.tw_lds = dst_twiddles_in_lds(nx, false);
-      cyc_inv.add(v);
-    }
-    // ---- Schur lines and operators
-    OpTask ot{};
-    ot.nx = nx; ot.ny = ny; ot.nblocks = sl.P; ot.delta = p->delta; ot.kappa = p->kappa;
-    for (int q = 0; q < 4; ++q) ot.line[q] = nullptr;
-    IfaceTask fi{}, bi{};
-    fi.delta = bi.delta = p->delta;
-    for (const ArmInfo& a : p->arms) {
-      LineTask lt{};
-      lt.L = a.L;
-      lt.fft = a.fft->dev;
-      lt.gs = a.gs->gs;
-      lt.out = sl.lines + (size_t)a.line * sl.Lmax;
-      switch (a.line) {
-        case 0: lt.start = 0; lt.stride = 1; break;
-        case 1: lt.start = (long long)(ny - 1) * nx; lt.stride = 1; break;
-        case 2: lt.start = 0; lt.stride = nx; break;
-        case 3: lt.start = nx - 1; lt.stride = nx; break;
-      }
-      ot.line[a.line] = lt.out;
-      smem_lines = std::max(smem_lines, line_smem_bytes(a.L));
-      LineTask li = lt;
-      li.skip = skip_it;
-      if (flex) {
-        li.z = sl.Z; li.z_js = Nc; li.z_f32 = 1;
-      } else if (a.line < 2) {
-        li.z = sl.tmpd; li.z_js = 0; li.z_f32 = 0; li.pre_dst = 1;   // sine coefficients of row 0 / ny-1
-      } else {
-        li.z = sl.zcols + (a.line == 3 ? ny : 0); li.z_js = 0; li.z_f32 = 0;
-        li.start = 0; li.stride = 1;
-      }
-      LineTask lx = lt;
-      lx.z = sl.x_int + cd.off; lx.z_js = 0; lx.z_f32 = 0; lx.skip = skip_fin;
-      if (dense_lines(a.L) && a.gs->mfull) {
-        li.mat = li.pre_dst ? a.gs->mpre_t : a.gs->mfull;
-        lx.mat = a.gs->mfull;
-        add_block_task(it_lines_d, li, div_up(a.L, 64));
-        add_block_task(x_lines_d, lx, div_up(a.L, 64));
-        lmax_dense = std::max(lmax_dense, a.L);
-      } else {
-        it_lines.h.push_back(li);
-        x_lines.h.push_back(lx);
-      }
-
-      // f'_c formation and back substitution
-      const RectDev& ad = p->rd[a.rect];
-      const int q = fi.nlines++;
-      fi.dst[q] = sl.fp; fi.dst_start[q] = lt.start; fi.dst_stride[q] = lt.stride;
-      fi.src[q] = sl.x_int; fi.src_start[q] = ad.off; fi.src_stride[q] = 1; fi.L[q] = a.L;
-      bi.dst[q] = sl.x_int; bi.dst_start[q] = ad.off; bi.dst_stride[q] = 1;
-      bi.src[q] = sl.x_int; bi.src_start[q] = cd.off + lt.start; bi.src_stride[q] = lt.stride;
-      bi.L[q] = a.L;
-      bi.nlines = fi.nlines;
-
-      // arm solves (FP64): b_int -> tmpd -> x_int, and x_int -> tmpd -> x_int
-      const int rpb = kBlock / dst_threads_per_row(a.L);
-      DstTask f{};
-      f.in = sl.b_int + ad.off; f.in_rs = a.L; f.in_cs = 1;
-      f.out = sl.tmpd + ad.off; f.out_rs = a.L; f.out_cs = 1;
-      f.rows = a.rows; f.n = a.L; f.rpb = rpb; f.scale = 1.0; f.fft = a.fft->dev; f.skip = nullptr;
-      f.tw_lds = dst_twiddles_in_lds(a.L, false);
-      arm_fwd.add(f);
-      DstTask fb = f;
-      fb.in = sl.x_int + ad.off;
-      bs_fwd.add(fb);
-      TriTask at{};
-      at.data = sl.tmpd + ad.off; at.rs = a.L; at.rows = a.rows; at.modes = a.L;
-      at.coef = a.modes->c64; at.skip = nullptr;
-      add_block_task(arm_tri, at, div_up(a.L, kBlock));
-      DstTask iv = f;
-      iv.in = sl.tmpd + ad.off; iv.out = sl.x_int + ad.off;
-      arm_inv.add(iv);
-    }
-    iface_fp.h.push_back(fi);
-    iface_bs.h.push_back(bi);
     if (flex) {
-      OpTask o = ot;
-      o.z = sl.Z; o.z_js = Nc; o.z_f32 = 1;
-      o.out = sl.V + Nc; o.out_js = Nc; o.skip = skip_it;
-      add_block_task(it_op, o, sl.P);
-    }
-    {
-      OpTask r = ot;
-      r.z = sl.x_int + cd.off; r.z_js = 0; r.z_f32 = 0;
-      r.out = sl.V; r.out_js = 0; r.fp = sl.fp; r.partials = sl.partials + (size_t)kPartRes * sl.P;
-      r.skip = skip_fin;
-      add_block_task(res_op, r, sl.P);
-    }
-    {
-      KryTask k{};
-      k.V = sl.V; k.Z = sl.Z; k.x = sl.x_int + cd.off; k.u = sl.u; k.H = sl.H; k.cs = sl.cs;
-      k.sn = sl.sn; k.g = sl.g; k.y = sl.y; k.partials = sl.partials; k.st = sl.st; k.Nc = Nc;
-      k.P = sl.P; k.m = m; k.G = sl.G; k.hv = sl.hv; k.nx = nx; k.ny = ny;
-      k.implicit_w = flex ? 0 : 1;
-      for (int q = 0; q < 4; ++q) k.line[q] = ot.line[q];
-      add_block_task(kry, k, sl.P);
-    }
-    // ---- layout conversion and composite residual
-    for (size_t r = 0; r < p->rd.size(); ++r) {
-      const RectDev& d = p->rd[r];
-      const long long tot = (long long)d.rows * d.cols;
-      LiftTask lt{};
-      lt.rd = d; lt.rhs = sl.req.rhs; lt.bc = sl.req.bc; lt.out = sl.b_int; lt.xuser = sl.req.x;
-      lt.xint = sl.x_int; lt.delta = p->delta; lt.kappa = p->kappa;
-      const int nb = std::max(1, div_up(tot, (long long)kBlock * 4));
-      lt.nblocks = nb;
-      add_block_task(lift, lt, nb);
-      add_block_task(gather, lt, nb);
-    }
-    {
-      int off = 0;
-      for (size_t r = 0; r < p->rd.size(); ++r) {
-        const RectDev& d = p->rd[r];
-        ResTask rt{};
-        rt.rd = d; rt.p = sl.x_int; rt.b = sl.b_int; rt.delta = p->delta; rt.kappa = p->kappa;
-        const int nb = std::max(1, div_up((long long)d.rows * d.cols, (long long)kBlock * 8));
-        rt.nblocks = nb;
-        rt.partials = sl.respart + 2 * off;
-        off += nb;
-        add_block_task(resid, rt, nb);
+      DstTask v{};
+      v.in = t.out; v.in_js = 0; v.in_rs = nx; v.in_cs = 1;
+      v.out = sl.Z; v.out_js = Nc;
+      v.out_rs = nx; v.out_cs = 1;
+      v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = 1.0; v.fft = fftc; v.skip = skip_it;
+      v.tw_lds = dst_twiddles_in_lds(nx, true);
+      it_inv.add(v);
+    } else {
+      bool west = false, east = false;
+      for (const ArmInfo& a : p->arms) { west |= a.line == 2; east |= a.line == 3; }
+      if (west || east) {
+        ColTask ct{};
+        ct.y = sl.tmpd; ct.zw = west ? sl.zcols : nullptr; ct.ze = east ? sl.zcols + ny : nullptr;
+        ct.fft = fftc; ct.nx = nx; ct.ny = ny; ct.skip = skip_it;
+        add_block_task(it_cols, ct, div_up(ny, kBlock / 64));
       }
-      sl.res_blocks = off;
     }
   }
-  for (auto* tl : {&it_fwd, &it_inv, &cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd}) tl->upload();
-  auto config_tri = [](TaskList<TriTask>& tl, bool fp32) {
-    int mmax = 1;
-    for (const TriTask& t : tl.h) mmax = std::max(mmax, t.rows);
-    const TriConfig c = tri_config(fp32, mmax);
-    int nb = 0;
-    for (TriTask& t : tl.h) {
-      t.block_begin = nb;
-      nb += tri_blocks(c, t.modes);
+  // ---- end-of-cycle preconditioner apply (plain variant): u -> x_c += A_c^{-1} u
+  if (!flex) {
+    DstTask t{};
+    t.in = sl.u; t.in_rs = nx; t.in_cs = 1; t.out = sl.tmpd; t.out_rs = nx; t.out_cs = 1;
+    t.rows = ny; t.n = nx; t.rpb = rpb_c; t.scale = 1.0; t.fft = fftc; t.skip = skip_fin;
+    t.tw_lds = dst_twiddles_in_lds(nx, false);
+    cyc_fwd.add(t);
+    TriTask tt{};
+    tt.data = sl.tmpd; tt.rs = nx; tt.rows = ny; tt.modes = nx; tt.coef = p->modes_c->c64;
+    tt.skip = skip_fin;
+    cyc_tri.add(tt);
+    DstTask v{};
+    v.in = sl.tmpd; v.in_rs = nx; v.in_cs = 1; v.out = sl.x_int + cd.off; v.out_rs = nx;
+    v.out_cs = 1; v.accumulate = 1;
+    v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = 1.0; v.fft = fftc; v.skip = skip_fin;
+    v.tw_lds = dst_twiddles_in_lds(nx, false);
+    cyc_inv.add(v);
+  }
+  // ---- Schur lines and operators
+  OpTask ot{};
+  ot.nx = nx; ot.ny = ny; ot.nblocks = sl.P; ot.delta = p->delta; ot.kappa = p->kappa;
+  for (int q = 0; q < 4; ++q) ot.line[q] = nullptr;
+  IfaceTask fi{}, bi{};
+  fi.delta = bi.delta = p->delta;
+  for (const ArmInfo& a : p->arms) {
+    LineTask lt{};
+    lt.L = a.L;
+    lt.fft = a.fft->dev;
+    lt.gs = a.gs->gs;
+    lt.out = sl.lines + (size_t)a.line * sl.Lmax;
+    switch (a.line) {
+      case 0: lt.start = 0; lt.stride = 1; break;
+      case 1: lt.start = (long long)(ny - 1) * nx; lt.stride = 1; break;
+      case 2: lt.start = 0; lt.stride = nx; break;
+      case 3: lt.start = nx - 1; lt.stride = nx; break;
     }
-    tl.nblocks = nb;
-    return c;
-  };
-  it_tc = config_tri(it_tri, flex);
-  cyc_tc = config_tri(cyc_tri, false);
-  arm_tc = config_tri(arm_tri, false);
-  for (auto* tl : {&it_tri, &cyc_tri, &arm_tri}) tl->upload();
-  it_lines.upload();
-  x_lines.upload();
-  it_lines_d.upload();
-  x_lines_d.upload();
-  it_cols.upload();
-  it_op.upload();
-  res_op.upload();
-  kry.upload();
-  lift.upload();
-  gather.upload();
-  iface_fp.upload();
-  iface_bs.upload();
-  resid.upload();
-  FDS_HIP(hipHostMalloc((void**)&flags_host, sizeof(int) * n, hipHostMallocMapped | hipHostMallocCoherent));
-  std::memset(flags_host, 0, sizeof(int) * n);
-  FDS_HIP(hipHostGetDevicePointer((void**)&flags_dev, flags_host, 0));
+    ot.line[a.line] = lt.out;
+    smem_lines = std::max(smem_lines, line_smem_bytes(a.L));
+    LineTask li = lt;
+    li.skip = skip_it;
+    if (flex) {
+      li.z = sl.Z; li.z_js = Nc; li.z_f32 = 1;
+    } else if (a.line < 2) {
+      li.z = sl.tmpd; li.z_js = 0; li.z_f32 = 0; li.pre_dst = 1;   // sine coefficients of row 0 / ny-1
+    } else {
+      li.z = sl.zcols + (a.line == 3 ? ny : 0); li.z_js = 0; li.z_f32 = 0;
+      li.start = 0; li.stride = 1;
+    }
+    LineTask lx = lt;
+    lx.z = sl.x_int + cd.off; lx.z_js = 0; lx.z_f32 = 0; lx.skip = skip_fin;
+    if (dense_lines(a.L) && a.gs->mfull) {
+      li.mat = li.pre_dst ? a.gs->mpre_t : a.gs->mfull;
+      lx.mat = a.gs->mfull;
+      add_block_task(it_lines_d, li, div_up(a.L, 64));
+      add_block_task(x_lines_d, lx, div_up(a.L, 64));
+      lmax_dense = std::max(lmax_dense, a.L);
+    } else {
+      it_lines.h.push_back(li);
+      x_lines.h.push_back(lx);
+    }
+
+    // f'_c formation and back substitution
+    const RectDev& ad = p->rd[a.rect];
+    const int q = fi.nlines++;
+    fi.dst[q] = sl.fp; fi.dst_start[q] = lt.start; fi.dst_stride[q] = lt.stride;
+    fi.src[q] = sl.x_int; fi.src_start[q] = ad.off; fi.src_stride[q] = 1; fi.L[q] = a.L;
+    bi.dst[q] = sl.x_int; bi.dst_start[q] = ad.off; bi.dst_stride[q] = 1;
+    bi.src[q] = sl.x_int; bi.src_start[q] = cd.off + lt.start; bi.src_stride[q] = lt.stride;
+    bi.L[q] = a.L;
+    bi.nlines = fi.nlines;
+
+    // arm solves (FP64): b_int -> tmpd -> x_int, and x_int -> tmpd -> x_int
+    const int rpb = kBlock / dst_threads_per_row(a.L);
+    DstTask f{};
+    f.in = sl.b_int + ad.off; f.in_rs = a.L; f.in_cs = 1;
+    f.out = sl.tmpd + ad.off; f.out_rs = a.L; f.out_cs = 1;
+    f.rows = a.rows; f.n = a.L; f.rpb = rpb; f.scale = 1.0; f.fft = a.fft->dev; f.skip = nullptr;
+    f.tw_lds = dst_twiddles_in_lds(a.L, false);
+    arm_fwd.add(f);
+    DstTask fb = f;
+    fb.in = sl.x_int + ad.off;
+    bs_fwd.add(fb);
+    TriTask at{};
+    at.data = sl.tmpd + ad.off; at.rs = a.L; at.rows = a.rows; at.modes = a.L;
+    at.coef = a.modes->c64; at.skip = nullptr;
+    arm_tri.add(at);
+    DstTask iv = f;
+    iv.in = sl.tmpd + ad.off; iv.out = sl.x_int + ad.off;
+    arm_inv.add(iv);
+  }
+  iface_fp.h.push_back(fi);
+  iface_bs.h.push_back(bi);
+  if (flex) {
+    OpTask o = ot;
+    o.z = sl.Z; o.z_js = Nc; o.z_f32 = 1;
+    o.out = sl.V + Nc; o.out_js = Nc; o.skip = skip_it;
+    add_block_task(it_op, o, sl.P);
+  }
+  {
+    OpTask r = ot;
+    r.z = sl.x_int + cd.off; r.z_js = 0; r.z_f32 = 0;
+    r.out = sl.V; r.out_js = 0; r.fp = sl.fp; r.partials = sl.partials + (size_t)kPartRes * sl.P;
+    r.skip = skip_fin;
+    add_block_task(res_op, r, sl.P);
+  }
+  {
+    KryTask k{};
+    k.V = sl.V; k.Z = sl.Z; k.x = sl.x_int + cd.off; k.u = sl.u; k.H = sl.H; k.cs = sl.cs;
+    k.sn = sl.sn; k.g = sl.g; k.y = sl.y; k.partials = sl.partials; k.st = sl.st; k.Nc = Nc;
+    k.P = sl.P; k.m = m; k.G = sl.G; k.hv = sl.hv; k.nx = nx; k.ny = ny;
+    k.implicit_w = flex ? 0 : 1;
+    for (int q = 0; q < 4; ++q) k.line[q] = ot.line[q];
+    add_block_task(kry, k, sl.P);
+  }
+  // ---- layout conversion and composite residual
+  for (size_t r = 0; r < p->rd.size(); ++r) {
+    const RectDev& d = p->rd[r];
+    const long long tot = (long long)d.rows * d.cols;
+    LiftTask lt{};
+    lt.rd = d; lt.rhs = sl.req.rhs; lt.bc = sl.req.bc; lt.out = sl.b_int; lt.xuser = sl.req.x;
+    lt.xint = sl.x_int; lt.delta = p->delta; lt.kappa = p->kappa;
+    const int nb = std::max(1, div_up(tot, (long long)kBlock * 4));
+    lt.nblocks = nb;
+    add_block_task(lift, lt, nb);
+    add_block_task(gather, lt, nb);
+  }
+  {
+    int off = 0;
+    for (size_t r = 0; r < p->rd.size(); ++r) {
+      const RectDev& d = p->rd[r];
+      ResTask rt{};
+      rt.rd = d; rt.p = sl.x_int; rt.b = sl.b_int; rt.delta = p->delta; rt.kappa = p->kappa;
+      const int nb = std::max(1, div_up((long long)d.rows * d.cols, (long long)kBlock * 8));
+      rt.nblocks = nb;
+      rt.partials = sl.respart + 2 * off;
+      off += nb;
+      add_block_task(resid, rt, nb);
+    }
+    sl.res_blocks = off;
+  }
 }
 
-// One Arnoldi step j of every unfinished problem.
-void Engine::Impl::iteration(int j, int tag) {
+// One Arnoldi step j of every problem of the set whose cycle is running.
+void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
   Timing::begin(0, s);
   it_fwd.launch(j, s);
   Timing::end(0, s);
   Timing::begin(1, s);
-  launch_tri(it_tc, flex, it_tri.dev(), it_tri.n(), it_tri.nblocks, 0, s);
+  it_tri.launch(s);
   Timing::end(1, s);
   if (flex) {
     Timing::begin(0, s);
@@ -501,7 +499,7 @@ void Engine::Impl::iteration(int j, int tag) {
   FDS_HIP(hipGetLastError());
 }
 
-void Engine::Impl::end_of_cycle() {
+void TaskSet::end_of_cycle(int max_cycles, hipStream_t s) const {
   Timing::begin(5, s);
   launch_ls_solve(kry.dev(), kry.n(), s);
   launch_combine(flex, kry.dev(), kry.n(), kry.nblocks, s);
@@ -511,7 +509,7 @@ void Engine::Impl::end_of_cycle() {
     cyc_fwd.launch(0, s);
     Timing::end(0, s);
     Timing::begin(1, s);
-    launch_tri(cyc_tc, false, cyc_tri.dev(), cyc_tri.n(), cyc_tri.nblocks, 0, s);
+    cyc_tri.launch(s);
     Timing::end(1, s);
     Timing::begin(0, s);
     cyc_inv.launch(0, s);
@@ -519,8 +517,7 @@ void Engine::Impl::end_of_cycle() {
   }
   if (x_lines.n() || x_lines_d.n()) {
     Timing::begin(4, s);
-    launch_lines_dense(x_lines_d.dev(), x_lines_d.n(), x_lines_d.nblocks, lmax_dense, 0, s);
-    launch_lines(x_lines.dev(), x_lines.n(), smem_lines, 0, s);
+    launch_x_lines(s);
     Timing::end(4, s);
   }
   Timing::begin(2, s);
@@ -532,28 +529,80 @@ void Engine::Impl::end_of_cycle() {
   FDS_HIP(hipGetLastError());
 }
 
+// Line term of one arm: the line in and out, plus the dense operator when
+// the term is a dense product.
+double line_bytes(const ArmInfo& a) {
+  const double mat = (dense_lines(a.L) && a.gs->mfull) ? 8.0 * a.L * a.L : 0.0;
+  return 16.0 * a.L + mat;
+}
+
+}  // namespace
+
+struct Engine::Impl {
+  int m, precision, max_cycles;
+  bool flex;
+  hipStream_t s;
+  int capacity = 0;
+  DevBuf states;                      // state pool (capacity entries)
+  std::vector<ProbState> host_states;
+  int* flags_host = nullptr;          // per pool index: serial of the last cycle that ended (mapped)
+  int* flags_dev = nullptr;
+  std::vector<int> free_idx;
+  std::vector<std::unique_ptr<Problem>> active;
+  std::unique_ptr<TaskSet> cur;       // task lists of `active` (null when stale)
+  int cycle_serial = 0;
+
+  ~Impl() {
+    if (flags_host) (void)hipHostFree(flags_host);
+  }
+  void read_states();
+  void upload_state(const Problem& p);
+  TaskSet& current();
+  void setup_phase(TaskSet& ts);
+  std::vector<SolveOutcome> finalize_phase(TaskSet& ts);
+  // Algorithmic bytes (each operand read once, each result written once) of
+  // the work every problem did in the cycle that just ended, by kernel class.
+  void account_cycle(const std::vector<ProbState>& before);
+  void account_arms(const std::vector<Problem*>& probs, bool setup_phase);
+};
+
 void Engine::Impl::read_states() {
-  FDS_HIP(hipMemcpyAsync(host_states.data(), states.get(), sizeof(ProbState) * slots.size(),
+  FDS_HIP(hipMemcpyAsync(host_states.data(), states.get(), sizeof(ProbState) * capacity,
                          hipMemcpyDeviceToHost, s));
   FDS_HIP(hipStreamSynchronize(s));
 }
 
-Engine::Engine(const std::vector<SolveRequest>& reqs, int m, int precision, int max_cycles,
-               hipStream_t stream)
+void Engine::Impl::upload_state(const Problem& p) {
+  FDS_HIP(hipMemcpyAsync(states.as<ProbState>() + p.idx, &host_states[p.idx], sizeof(ProbState),
+                         hipMemcpyHostToDevice, s));
+}
+
+TaskSet& Engine::Impl::current() {
+  if (!cur) {
+    cur.reset(new TaskSet(m, flex));
+    for (auto& p : active) cur->add_problem(*p);
+    cur->upload(s);
+  }
+  return *cur;
+}
+
+Engine::Engine(int m, int precision, int max_cycles, int capacity, hipStream_t stream)
     : impl_(new Impl()) {
   Impl& I = *impl_;
+  if (capacity < 1) throw Error(FDS_E_INVALID_ARG, "engine capacity must be positive");
   I.m = m;
   I.precision = precision;
   I.flex = precision == FDS_FP32_PRECOND;
   I.max_cycles = max_cycles;
   I.s = stream;
-  I.it_fwd.kind = I.flex ? DstKind::D_F : DstKind::D_D;
-  I.slots.resize(reqs.size());
-  for (size_t i = 0; i < reqs.size(); ++i) {
-    I.slots[i].req = reqs[i];
-    I.slots[i].plan = reqs[i].plan;
-  }
-  I.build();
+  I.capacity = capacity;
+  I.states.alloc(sizeof(ProbState) * capacity);
+  I.host_states.assign(capacity, ProbState{});
+  FDS_HIP(hipHostMalloc((void**)&I.flags_host, sizeof(int) * capacity,
+                        hipHostMallocMapped | hipHostMallocCoherent));
+  std::memset(I.flags_host, 0, sizeof(int) * capacity);
+  FDS_HIP(hipHostGetDevicePointer((void**)&I.flags_dev, I.flags_host, 0));
+  for (int i = capacity - 1; i >= 0; --i) I.free_idx.push_back(i);
 }
 
 Engine::~Engine() = default;
@@ -562,58 +611,229 @@ size_t Engine::bytes_per_problem(const fds_plan* p, int m, int precision) {
   return layout_of(p, m, precision).total + sizeof(ProbState);
 }
 
-void Engine::setup() {
+int Engine::free_slots() const { return (int)impl_->free_idx.size(); }
+int Engine::active() const { return (int)impl_->active.size(); }
+
+void Engine::admit(const std::vector<SolveRequest>& reqs, const std::vector<int>& ids) {
   Impl& I = *impl_;
-  hipStream_t s = I.s;
-  FDS_HIP(hipMemcpyAsync(I.states.get(), I.host_states.data(), sizeof(ProbState) * I.slots.size(),
-                         hipMemcpyHostToDevice, s));
-  Timing::begin(5, s);
-  launch_lift(0, I.lift.dev(), I.lift.n(), I.lift.nblocks, s);
-  Timing::end(5, s);
-  if (I.arm_fwd.n()) {
-    Timing::begin(0, s);
-    I.arm_fwd.launch(0, s);
-    Timing::end(0, s);
-    Timing::begin(1, s);
-    launch_tri(I.arm_tc, false, I.arm_tri.dev(), I.arm_tri.n(), I.arm_tri.nblocks, 0, s);
-    Timing::end(1, s);
-    Timing::begin(0, s);
-    I.arm_inv.launch(0, s);
-    Timing::end(0, s);
+  if (reqs.empty()) return;
+  if ((int)reqs.size() > (int)I.free_idx.size()) throw Error(FDS_E_NOMEM, "engine has no free slot");
+  const int m = I.m;
+  const bool flex = I.flex;
+  std::vector<Problem*> fresh;
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    std::unique_ptr<Problem> up(new Problem());
+    Problem& sl = *up;
+    sl.req = reqs[r];
+    sl.plan = reqs[r].plan;
+    sl.id = ids.empty() ? (int)r : ids[r];
+    sl.idx = I.free_idx.back();
+    fds_plan* p = sl.plan;
+    const SlotLayout L = layout_of(p, m, I.precision);
+    sl.mem.alloc(L.total);
+    I.free_idx.pop_back();
+    sl.Nc = (long long)p->nx * p->ny;
+    sl.Nint = p->n_internal;
+    sl.P = std::max(1, div_up(sl.Nc, kVecPerBlock));
+    sl.Lmax = std::max(p->nx, p->ny);
+    sl.b_int = sl.mem.as<double>(L.b_int);
+    sl.x_int = sl.mem.as<double>(L.x_int);
+    sl.tmpd = sl.mem.as<double>(L.tmpd);
+    sl.fp = sl.mem.as<double>(L.fp);
+    sl.V = sl.mem.as<double>(L.V);
+    sl.u = sl.mem.as<double>(L.u);
+    sl.zbuf = flex ? nullptr : sl.mem.as<double>(L.zbuf);
+    sl.lines = sl.mem.as<double>(L.lines);
+    double* small = sl.mem.as<double>(L.small);
+    sl.H = small;
+    sl.cs = sl.H + (size_t)(m + 1) * m;
+    sl.sn = sl.cs + m;
+    sl.g = sl.sn + m;
+    sl.y = sl.g + (m + 1);
+    sl.partials = sl.mem.as<double>(L.partials);
+    sl.respart = sl.mem.as<double>(L.respart);
+    sl.G = sl.mem.as<double>(L.gram);
+    sl.hv = sl.G + (size_t)(m + 1) * (m + 1);
+    sl.zcols = sl.mem.as<double>(L.zcols);
+    sl.Z = flex ? sl.mem.as<float>(L.Z) : nullptr;
+    sl.tmpf = flex ? sl.mem.as<float>(L.tmpf) : nullptr;
+    sl.st = I.states.as<ProbState>() + sl.idx;
+    ProbState& hs = I.host_states[sl.idx];
+    hs = ProbState{};
+    hs.tol = sl.req.tol;
+    hs.tol_eff = sl.req.tol;
+    hs.floor_coef = p->floor_coef;
+    hs.vscale = 1.0;
+    I.flags_host[sl.idx] = 0;
+    I.upload_state(sl);
+    fresh.push_back(up.get());
+    I.active.push_back(std::move(up));
   }
-  for (Slot& sl : I.slots) {
-    const long long coff = sl.plan->rd[sl.plan->centre].off;
-    FDS_HIP(hipMemcpyAsync(sl.fp, sl.b_int + coff, 8 * sl.Nc, hipMemcpyDeviceToDevice, s));
-  }
-  launch_iface(I.iface_fp.dev(), I.iface_fp.n(), s);
-  for (Slot& sl : I.slots) {
-    const long long coff = sl.plan->rd[sl.plan->centre].off;
-    FDS_HIP(hipMemsetAsync(sl.x_int + coff, 0, 8 * sl.Nc, s));
-  }
-  launch_lines_dense(I.x_lines_d.dev(), I.x_lines_d.n(), I.x_lines_d.nblocks, I.lmax_dense, 0, s);
-  if (I.x_lines.n()) launch_lines(I.x_lines.dev(), I.x_lines.n(), I.smem_lines, 0, s);
-  launch_operator(1, I.res_op.dev(), I.res_op.n(), I.res_op.nblocks, 0, s);
-  launch_restart(I.kry.dev(), I.kry.n(), I.kry.nblocks, 1, I.max_cycles, s);
-  FDS_HIP(hipGetLastError());
-  I.read_states();
-  I.set_up = true;
-  if (Timing::on()) I.account_arms(true);
+  TaskSet ts(m, flex);
+  for (Problem* p : fresh) ts.add_problem(*p);
+  ts.upload(I.s);
+  I.setup_phase(ts);
+  I.cur.reset();
 }
 
-// Line term of one arm: the line in and out, plus the dense operator when
-// the term is a dense product.
-static double line_bytes(const ArmInfo& a) {
-  const double mat = (dense_lines(a.L) && a.gs->mfull) ? 8.0 * a.L * a.L : 0.0;
-  return 16.0 * a.L + mat;
+void Engine::Impl::setup_phase(TaskSet& ts) {
+  Timing::begin(5, s);
+  launch_lift(0, ts.lift.dev(), ts.lift.n(), ts.lift.nblocks, s);
+  Timing::end(5, s);
+  if (ts.arm_fwd.n()) {
+    Timing::begin(0, s);
+    ts.arm_fwd.launch(0, s);
+    Timing::end(0, s);
+    Timing::begin(1, s);
+    ts.arm_tri.launch(s);
+    Timing::end(1, s);
+    Timing::begin(0, s);
+    ts.arm_inv.launch(0, s);
+    Timing::end(0, s);
+  }
+  for (Problem* sl : ts.probs) {
+    const long long coff = sl->plan->rd[sl->plan->centre].off;
+    FDS_HIP(hipMemcpyAsync(sl->fp, sl->b_int + coff, 8 * sl->Nc, hipMemcpyDeviceToDevice, s));
+  }
+  launch_iface(ts.iface_fp.dev(), ts.iface_fp.n(), s);
+  for (Problem* sl : ts.probs) {
+    const long long coff = sl->plan->rd[sl->plan->centre].off;
+    FDS_HIP(hipMemsetAsync(sl->x_int + coff, 0, 8 * sl->Nc, s));
+  }
+  ts.launch_x_lines(s);
+  launch_operator(1, ts.res_op.dev(), ts.res_op.n(), ts.res_op.nblocks, 0, s);
+  launch_restart(ts.kry.dev(), ts.kry.n(), ts.kry.nblocks, 1, max_cycles, s);
+  FDS_HIP(hipGetLastError());
+  read_states();
+  if (Timing::on()) account_arms(ts.probs, true);
+}
+
+bool Engine::step_cycle() {
+  Impl& I = *impl_;
+  bool any = false;
+  for (auto& p : I.active) any |= !I.host_states[p->idx].finished;
+  if (!any) return false;
+  TaskSet& ts = I.current();
+  const std::vector<ProbState> before = I.host_states;
+  const int tag = ++I.cycle_serial;
+  for (int j = 0; j < I.m; ++j) {
+    if (j >= 2) {
+      // stop launching once every running problem reported the end of this
+      // cycle (the finish kernel writes the tag to mapped host memory)
+      bool all = true;
+      const volatile int* fl = I.flags_host;
+      for (auto& p : I.active)
+        if (!before[p->idx].finished && fl[p->idx] != tag) { all = false; break; }
+      if (all) break;
+    }
+    ts.iteration(j, I.flags_dev, tag, I.s);
+  }
+  ts.end_of_cycle(I.max_cycles, I.s);
+  I.read_states();
+  if (Timing::on()) I.account_cycle(before);
+  for (auto& p : I.active) if (!I.host_states[p->idx].finished) return true;
+  return false;
+}
+
+std::vector<int> Engine::finished_ids() const {
+  std::vector<int> out;
+  for (auto& p : impl_->active)
+    if (impl_->host_states[p->idx].finished) out.push_back(p->id);
+  return out;
+}
+
+std::vector<std::pair<int, SolveOutcome>> Engine::retire(const std::vector<int>& ids) {
+  Impl& I = *impl_;
+  std::vector<std::pair<int, SolveOutcome>> res;
+  if (ids.empty()) return res;
+  TaskSet ts(I.m, I.flex);
+  for (auto& p : I.active)
+    if (std::find(ids.begin(), ids.end(), p->id) != ids.end()) ts.add_problem(*p);
+  if (ts.probs.empty()) return res;
+  ts.upload(I.s);
+  std::vector<SolveOutcome> out = I.finalize_phase(ts);
+  for (size_t i = 0; i < ts.probs.size(); ++i) res.emplace_back(ts.probs[i]->id, out[i]);
+  // release: the stream is idle after finalize_phase
+  std::vector<std::unique_ptr<Problem>> keep;
+  for (auto& p : I.active) {
+    if (std::find(ids.begin(), ids.end(), p->id) != ids.end()) I.free_idx.push_back(p->idx);
+    else keep.push_back(std::move(p));
+  }
+  I.active = std::move(keep);
+  I.cur.reset();
+  return res;
+}
+
+std::vector<SolveOutcome> Engine::Impl::finalize_phase(TaskSet& ts) {
+  for (Problem* sl : ts.probs) {
+    const long long coff = sl->plan->rd[sl->plan->centre].off;
+    const long long rest = sl->Nint - sl->Nc;
+    if (rest > 0) {
+      // arms follow the centre in the internal layout
+      FDS_HIP(hipMemcpyAsync(sl->x_int + coff + sl->Nc, sl->b_int + coff + sl->Nc, 8 * rest,
+                             hipMemcpyDeviceToDevice, s));
+    }
+  }
+  launch_iface(ts.iface_bs.dev(), ts.iface_bs.n(), s);
+  if (ts.bs_fwd.n()) {
+    Timing::begin(0, s);
+    ts.bs_fwd.launch(0, s);
+    Timing::end(0, s);
+    Timing::begin(1, s);
+    ts.arm_tri.launch(s);
+    Timing::end(1, s);
+    Timing::begin(0, s);
+    ts.arm_inv.launch(0, s);
+    Timing::end(0, s);
+  }
+  launch_lift(1, ts.gather.dev(), ts.gather.n(), ts.gather.nblocks, s);
+  launch_residual(ts.resid.dev(), ts.resid.n(), ts.resid.nblocks, s);
+  FDS_HIP(hipGetLastError());
+  std::vector<std::vector<double>> parts(ts.probs.size());
+  for (size_t i = 0; i < ts.probs.size(); ++i) {
+    parts[i].resize(2 * ts.probs[i]->res_blocks);
+    FDS_HIP(hipMemcpyAsync(parts[i].data(), ts.probs[i]->respart, 8 * parts[i].size(),
+                           hipMemcpyDeviceToHost, s));
+  }
+  read_states();
+  if (Timing::on()) account_arms(ts.probs, false);
+  std::vector<SolveOutcome> out(ts.probs.size());
+  for (size_t i = 0; i < ts.probs.size(); ++i) {
+    const Problem& sl = *ts.probs[i];
+    const ProbState& st = host_states[sl.idx];
+    double rr = 0, bb = 0;
+    int off = 0;
+    // partials are laid out rectangle by rectangle: [r^2 (nb) | b^2 (nb)]
+    for (size_t r = 0; r < sl.plan->rd.size(); ++r) {
+      const RectDev& d = sl.plan->rd[r];
+      const int nb = std::max(1, div_up((long long)d.rows * d.cols, (long long)kBlock * 8));
+      for (int b = 0; b < nb; ++b) rr += parts[i][2 * off + b];
+      for (int b = 0; b < nb; ++b) bb += parts[i][2 * off + nb + b];
+      off += nb;
+    }
+    SolveOutcome& o = out[i];
+    o.res.iterations = st.iterations;
+    o.res.cycles = st.cycles;
+    o.res.stop_reason = st.stop_reason;
+    o.res.relres_schur = st.fnorm > 0 ? st.beta / st.fnorm : 0.0;
+    o.res.relres_global = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+    o.res.seconds = 0;
+    if (st.nonfinite) o.status = FDS_E_NONFINITE;
+    else if (!st.finished) { o.status = FDS_E_NOT_CONVERGED; o.res.stop_reason = FDS_STOP_MAX_CYCLES; }
+    else if (st.stop_reason == FDS_STOP_TOL || st.stop_reason == FDS_STOP_AT_FLOOR) o.status = FDS_OK;
+    else o.status = FDS_E_NOT_CONVERGED;
+    o.res.status = o.status;
+  }
+  return out;
 }
 
 void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
   const double wz = flex ? 4.0 : 8.0;     // storage of z and of the transform scratch
-  for (size_t i = 0; i < slots.size(); ++i) {
-    if (before[i].finished) continue;
-    const Slot& sl = slots[i];
+  for (auto& up : active) {
+    const Problem& sl = *up;
+    if (before[sl.idx].finished) continue;
     const double Nc = (double)sl.Nc;
-    const int its = host_states[i].iterations - before[i].iterations;
+    const int its = host_states[sl.idx].iterations - before[sl.idx].iterations;
     double lines = 0;
     for (const ArmInfo& a : sl.plan->arms) lines += line_bytes(a);
     // per Arnoldi step: the forward transform reads v_j, writes it back
@@ -650,122 +870,36 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
   }
 }
 
-void Engine::Impl::account_arms(bool setup_phase) {
-  for (const Slot& sl : slots) {
-    for (const ArmInfo& a : sl.plan->arms) {
+void Engine::Impl::account_arms(const std::vector<Problem*>& probs, bool setup_phase) {
+  for (const Problem* sl : probs) {
+    for (const ArmInfo& a : sl->plan->arms) {
       const double na = (double)a.L * a.rows;
       Timing::add_bytes(0, 2.0 * 16.0 * na);
       Timing::add_bytes(1, 16.0 * na);
     }
-    const double Nc = (double)sl.Nc;
+    const double Nc = (double)sl->Nc;
     if (setup_phase) {
       double lines = 0;
-      for (const ArmInfo& a : sl.plan->arms) lines += line_bytes(a);
+      for (const ArmInfo& a : sl->plan->arms) lines += line_bytes(a);
       Timing::add_bytes(2, Nc * 24.0);
       Timing::add_bytes(4, lines);
     }
   }
 }
 
-bool Engine::step_cycle() {
-  Impl& I = *impl_;
-  bool any = false;
-  for (const ProbState& st : I.host_states) any |= !st.finished;
-  if (!any) return false;
-  const std::vector<ProbState> before = I.host_states;
-  const int tag = ++I.cycle_serial;
-  for (int j = 0; j < I.m; ++j) {
-    if (j >= 2) {
-      // stop launching once every running problem reported the end of this
-      // cycle (the finish kernel writes the tag to mapped host memory)
-      bool all = true;
-      const volatile int* fl = I.flags_host;
-      for (size_t p = 0; p < I.slots.size() && all; ++p)
-        if (!before[p].finished && fl[p] != tag) all = false;
-      if (all) break;
-    }
-    I.iteration(j, tag);
-  }
-  I.end_of_cycle();
-  I.read_states();
-  if (Timing::on()) I.account_cycle(before);
-  for (const ProbState& st : I.host_states) if (!st.finished) return true;
-  return false;
-}
-
-std::vector<SolveOutcome> Engine::finalize() {
-  Impl& I = *impl_;
-  hipStream_t s = I.s;
-  for (Slot& sl : I.slots) {
-    const long long coff = sl.plan->rd[sl.plan->centre].off;
-    const long long rest = sl.Nint - sl.Nc;
-    if (rest > 0) {
-      // arms follow the centre in the internal layout
-      FDS_HIP(hipMemcpyAsync(sl.x_int + coff + sl.Nc, sl.b_int + coff + sl.Nc, 8 * rest,
-                             hipMemcpyDeviceToDevice, s));
-    }
-  }
-  launch_iface(I.iface_bs.dev(), I.iface_bs.n(), s);
-  if (I.bs_fwd.n()) {
-    Timing::begin(0, s);
-    I.bs_fwd.launch(0, s);
-    Timing::end(0, s);
-    Timing::begin(1, s);
-    launch_tri(I.arm_tc, false, I.arm_tri.dev(), I.arm_tri.n(), I.arm_tri.nblocks, 0, s);
-    Timing::end(1, s);
-    Timing::begin(0, s);
-    I.arm_inv.launch(0, s);
-    Timing::end(0, s);
-  }
-  launch_lift(1, I.gather.dev(), I.gather.n(), I.gather.nblocks, s);
-  launch_residual(I.resid.dev(), I.resid.n(), I.resid.nblocks, s);
-  FDS_HIP(hipGetLastError());
-  std::vector<std::vector<double>> parts(I.slots.size());
-  for (size_t i = 0; i < I.slots.size(); ++i) {
-    parts[i].resize(2 * I.slots[i].res_blocks);
-    FDS_HIP(hipMemcpyAsync(parts[i].data(), I.slots[i].respart, 8 * parts[i].size(),
-                           hipMemcpyDeviceToHost, s));
-  }
-  I.read_states();
-  if (Timing::on()) I.account_arms(false);
-  std::vector<SolveOutcome> out(I.slots.size());
-  for (size_t i = 0; i < I.slots.size(); ++i) {
-    const ProbState& st = I.host_states[i];
-    const Slot& sl = I.slots[i];
-    double rr = 0, bb = 0;
-    int off = 0;
-    // partials are laid out rectangle by rectangle: [r^2 (nb) | b^2 (nb)]
-    for (size_t r = 0; r < sl.plan->rd.size(); ++r) {
-      const RectDev& d = sl.plan->rd[r];
-      const int nb = std::max(1, div_up((long long)d.rows * d.cols, (long long)kBlock * 8));
-      for (int b = 0; b < nb; ++b) rr += parts[i][2 * off + b];
-      for (int b = 0; b < nb; ++b) bb += parts[i][2 * off + nb + b];
-      off += nb;
-    }
-    SolveOutcome& o = out[i];
-    o.res.iterations = st.iterations;
-    o.res.cycles = st.cycles;
-    o.res.stop_reason = st.stop_reason;
-    o.res.relres_schur = st.fnorm > 0 ? st.beta / st.fnorm : 0.0;
-    o.res.relres_global = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
-    o.res.seconds = 0;
-    if (st.nonfinite) o.status = FDS_E_NONFINITE;
-    else if (!st.finished) { o.status = FDS_E_NOT_CONVERGED; o.res.stop_reason = FDS_STOP_MAX_CYCLES; }
-    else if (st.stop_reason == FDS_STOP_TOL || st.stop_reason == FDS_STOP_AT_FLOOR) o.status = FDS_OK;
-    else o.status = FDS_E_NOT_CONVERGED;
-    o.res.status = o.status;
-  }
-  return out;
-}
-
-std::vector<SolveOutcome> Engine::run() {
+std::vector<SolveOutcome> Engine::run_batch(const std::vector<SolveRequest>& reqs, int m,
+                                            int precision, int max_cycles, hipStream_t stream) {
   auto t0 = std::chrono::steady_clock::now();
-  setup();
+  Engine e(m, precision, max_cycles, (int)reqs.size(), stream);
+  std::vector<int> ids(reqs.size());
+  for (size_t i = 0; i < reqs.size(); ++i) ids[i] = (int)i;
+  e.admit(reqs, ids);
   int cyc = 0;
-  while (step_cycle()) {
-    if (++cyc > impl_->max_cycles + 2) break;
+  while (e.step_cycle()) {
+    if (++cyc > max_cycles + 2) break;
   }
-  std::vector<SolveOutcome> out = finalize();
+  std::vector<SolveOutcome> out(reqs.size());
+  for (auto& pr : e.retire(ids)) out[pr.first] = pr.second;
   const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   for (auto& o : out) o.res.seconds = sec;
   return out;

@@ -1132,18 +1132,22 @@ void launch_operator(int mode, const OpTask* tasks, int ntasks, int nblocks, int
 }
 
 void launch_gram_dots(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s) {
+  if (nblocks <= 0) return;
   FDS_LAUNCH(k_gram_dots, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j);
 }
 
 void launch_gram_solve(const KryTask* tasks, int ntasks, int j, hipStream_t s) {
+  if (ntasks <= 0) return;
   FDS_LAUNCH(k_gram_solve, dim3(ntasks), dim3(kBlock), 0, s, tasks, ntasks, j);
 }
 
 void launch_gram_update(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s) {
+  if (nblocks <= 0) return;
   FDS_LAUNCH(k_gram_update, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j);
 }
 
 void launch_mgs_finish(const KryTask* tasks, int ntasks, int j, int* flags, int tag, hipStream_t s) {
+  if (ntasks <= 0) return;
   FDS_LAUNCH(k_mgs_finish, dim3(ntasks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
 }
 
@@ -1157,10 +1161,12 @@ void launch_idst_cols(const ColTask* tasks, int ntasks, int nblocks, hipStream_t
 }
 
 void launch_ls_solve(const KryTask* tasks, int ntasks, hipStream_t s) {
+  if (ntasks <= 0) return;
   FDS_LAUNCH(k_ls_solve, dim3((ntasks + 63) / 64), dim3(64), 0, s, tasks, ntasks);
 }
 
 void launch_combine(bool flex, const KryTask* tasks, int ntasks, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return;
   if (flex)
     FDS_LAUNCH(k_combine<1>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
   else
@@ -1169,6 +1175,7 @@ void launch_combine(bool flex, const KryTask* tasks, int ntasks, int nblocks, hi
 
 void launch_restart(const KryTask* tasks, int ntasks, int nblocks, int initial, int max_cycles,
                     hipStream_t s) {
+  if (nblocks <= 0) return;
   FDS_LAUNCH(k_restart, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, initial,
                      max_cycles);
 }

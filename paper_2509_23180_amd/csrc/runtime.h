@@ -196,21 +196,29 @@ struct SolveOutcome {
 };
 
 // Batched right-preconditioned GMRES(m) / FGMRES(m): every kernel of an
-// Arnoldi step serves all unfinished problems of the batch in one launch.
+// Arnoldi step serves all running problems of the engine in one launch.
+// Problems are admitted (set-up phase: lift, arm pre-solves, f', initial
+// residual) and retired (back substitution, output, global residual) between
+// cycles, which is what the request server uses for continuous batching.
 class Engine {
  public:
-  Engine(const std::vector<SolveRequest>& reqs, int m, int precision, int max_cycles,
-         hipStream_t stream);
+  // capacity: most problems held at once (state pool and flag array size).
+  Engine(int m, int precision, int max_cycles, int capacity, hipStream_t stream);
   ~Engine();
-  // Runs setup, cycles and finalisation; blocks until done.
-  std::vector<SolveOutcome> run();
-
-  // Incremental interface used by the server: setup() then step_cycle()
-  // until done(), then finalize().
-  void setup();
-  bool step_cycle();                 // false once every problem finished
-  std::vector<SolveOutcome> finalize();
+  // Allocates the problems and runs their set-up phase (blocks until done).
+  void admit(const std::vector<SolveRequest>& reqs, const std::vector<int>& ids);
+  // One GMRES cycle of every unfinished problem; false once none is running.
+  bool step_cycle();
+  // Problems that finished (converged, stalled, failed or out of cycles).
+  std::vector<int> finished_ids() const;
+  // Back substitution and output of the given problems; frees their memory.
+  std::vector<std::pair<int, SolveOutcome>> retire(const std::vector<int>& ids);
+  int free_slots() const;
+  int active() const;
   static size_t bytes_per_problem(const fds_plan* p, int m, int precision);
+  // Whole batch: admit all, cycle until done, retire all (request order).
+  static std::vector<SolveOutcome> run_batch(const std::vector<SolveRequest>& reqs, int m,
+                                             int precision, int max_cycles, hipStream_t stream);
 
  private:
   struct Impl;

@@ -177,6 +177,74 @@ def test_batch_matches_standalone(precision):
         assert compare(p, it[3], oracle_solution(p)) <= 1e-9
 
 
+def _drain(srv, tickets, timeout=90.0):
+    import time
+    results = {}
+    t0 = time.time()
+    while len(results) < len(tickets) and time.time() - t0 < timeout:
+        for t in tickets:
+            if t not in results:
+                r = srv.poll(t)
+                if r is not None:
+                    results[t] = r
+        time.sleep(0.002)
+    return results
+
+
+def test_server_continuous_batching_matches_alone():
+    """Requests that arrive while others run join the running batch at a cycle
+    boundary (mixed shapes, sizes and both precisions); every result is
+    bitwise the result of the same solve alone."""
+    import time
+    fds = _fds()
+    first = [_problem("cross", 48, 0.0, "gauss", 1), _problem("T", 40, -20.0, "gauss", 2)]
+    later = [_problem("L", 33, -10.0, "gauss", 5), _problem("cross", 20, 0.0, "shifted", 0),
+             _problem("T", 24, -50.0, "gauss", 3)]
+    srv = fds.Server(hbm_budget_bytes=1 << 30, max_slots=4)
+    items, precs = [], []
+    tickets = []
+    for k, p in enumerate(first + later):
+        prec = k % 2
+        plan, rhs, bc, x = device_problem(p, precision=prec)
+        items.append((plan, rhs, bc, x))
+        precs.append(prec)
+    torch.cuda.synchronize()
+    for it in items[:2]:
+        tickets.append(srv.submit(it[0], it[1], it[3], 1e-11, bc=it[2]))
+    time.sleep(0.05)
+    for it in items[2:]:
+        tickets.append(srv.submit(it[0], it[1], it[3], 1e-11, bc=it[2]))
+    results = _drain(srv, tickets)
+    srv.close()
+    assert len(results) == len(tickets)
+    for k, (p, it, t) in enumerate(zip(first + later, items, tickets)):
+        log(f"server mix item {k}: {p.label}")
+        assert results[t].status == 0
+        assert results[t].seconds > 0
+        plan, rhs, bc, x = device_problem(p, precision=precs[k])
+        fds.solve(plan, rhs, x, 1e-11, bc=bc)
+        assert torch.equal(x, it[3]), k
+
+
+def test_server_admission_by_footprint():
+    """A budget that holds one problem runs the stream one at a time."""
+    fds = _fds()
+    probs = [_problem("cross", 24, 0.0, "gauss", s) for s in range(3)]
+    items = [device_problem(p) for p in probs]
+    one = items[0][0].footprint
+    srv = fds.Server(hbm_budget_bytes=int(one * 1.5), max_slots=8)
+    torch.cuda.synchronize()
+    tickets = [srv.submit(it[0], it[1], it[3], 1e-11, bc=it[2]) for it in items]
+    results = _drain(srv, tickets)
+    srv.close()
+    assert len(results) == len(tickets)
+    for p, it, t in zip(probs, items, tickets):
+        assert results[t].status == 0
+        plan, rhs, bc, x = device_problem(p)
+        fds.solve(plan, rhs, x, 1e-11, bc=bc)
+        assert torch.equal(x, it[3])
+
+
 def test_server_results_match_direct():
     fds = _fds()
     probs = [_problem("cross", 20, 0.0, "gauss", s) for s in range(3)] + \
