@@ -12,7 +12,10 @@ kernel class, CPU oracle baseline).  Diagnostics go to stderr.
 
 Other workloads (--workload): "precision" (cross 1024x1024 per square,
 FGMRES(40) with an FP32 preconditioner), "batching" (64 composite problems x
-8 right-hand sides, sizes 64..512, FGMRES(40)).
+8 right-hand sides, sizes 64..512, FGMRES(40)), "serving" (a Poisson request
+stream replayed open-loop against the continuous-batching server, once with
+the mixed-precision FGMRES(40) path and once with the plain FP64 GMRES(30)
+path; p50/p99 latency from submission to completion and throughput).
 """
 
 from __future__ import annotations
@@ -120,6 +123,126 @@ def to_device(items, opts, device):
     return plans, out
 
 
+# --------------------------------------------------------------------------- serving
+
+def serving_inputs(reqs, device):
+    """Device right-hand sides of the requested solves: the seeded Gaussian
+    source evaluated on the device grid, packed into the ABI layout through
+    index arrays (Dirichlet data zero)."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2509_23180_amd import layout as playout
+    out = []
+    for rq in reqs:
+        sp = rq.spec
+        n = sp.n
+        N = n + 1
+        h = 1.0 / N
+        rects = workloads.shape_rects(sp.shape, n)
+        side = 3 * N + 1
+        c = torch.arange(side, dtype=torch.float64, device=device) * h
+        Y, X = torch.meshgrid(c, c, indexing="ij")
+        src = workloads.gaussian_source(sp.shape, sp.config_id, sp.problem_id, sp.rhs_id)
+        f = src(X, Y, xp=torch).reshape(-1)
+        idx = playout.pack_unknowns(rects, np.arange(side * side, dtype=np.float64).reshape(side, side))
+        rhs = f[torch.tensor(idx.astype(np.int64), device=device)].contiguous()
+        nbc = int(playout.pack_boxes(rects, np.zeros((side, side))).size)
+        bc = torch.zeros(nbc, dtype=torch.float64, device=device)
+        out.append((rects, h, sp.kappa, rhs, bc))
+    return out
+
+
+def replay(fds, torch, srv, reqs, inputs, plans, tol):
+    """Open-loop replay: a submitter thread submits each request at its
+    arrival time; the caller polls.  Returns per-request (latency s, status,
+    iterations) and the makespan (first arrival to last completion)."""
+    import threading
+    xs = [torch.zeros(p.n_unknowns, dtype=torch.float64, device=rhs.device)
+          for p, (_, _, _, rhs, _) in zip(plans, inputs)]
+    torch.cuda.synchronize()
+    tickets = [None] * len(reqs)
+    t0 = time.perf_counter()
+
+    def submitter():
+        for k, rq in enumerate(reqs):
+            delay = t0 + rq.arrival_s - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            _, _, _, rhs, bc = inputs[k]
+            tickets[k] = srv.submit(plans[k], rhs, xs[k], tol, bc=bc)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    done = {}
+    last = t0
+    while len(done) < len(reqs):
+        for k in range(len(reqs)):
+            if k in done or tickets[k] is None:
+                continue
+            r = srv.poll(tickets[k])
+            if r is not None:
+                done[k] = r
+                last = time.perf_counter()
+        time.sleep(0.0005)
+    th.join()
+    res = [(done[k].seconds, done[k].status, done[k].iterations, done[k].relres_schur,
+            done[k].stop_reason, done[k].cycles) for k in range(len(reqs))]
+    return res, last - t0
+
+
+def run_serving(args, device):
+    import torch
+    import paper_2509_23180_amd as fds
+    import workloads
+    tol = 1e-10
+    reqs = workloads.request_stream(args.serving_rate, args.serving_seconds, n_min=64,
+                                    n_max=args.serving_nmax)
+    log(f"serving: {len(reqs)} requests over {args.serving_seconds} s, n in [64, {args.serving_nmax}]")
+    inputs = serving_inputs(reqs, device)
+    paths = {"mixed_fgmres40_fp32_precond": dict(restart_m=40, precision=1),
+             "plain_gmres30_fp64": dict(restart_m=30, precision=0)}
+    out = {}
+    for name, opt in paths.items():
+        t_plan = time.perf_counter()
+        plans = [fds.Plan(rects, h, kappa, max_cycles=400, **opt) for (rects, h, kappa, _, _) in inputs]
+        log(f"{name}: {len(plans)} plans in {time.perf_counter() - t_plan:.1f} s")
+        srv = fds.Server(hbm_budget_bytes=int(args.serving_budget_gb * (1 << 30)),
+                         max_slots=args.serving_slots)
+        # warm-up: the first few requests alone (kernel code, table caches)
+        warm = min(4, len(reqs))
+        replay(fds, torch, srv, reqs[:warm], inputs[:warm], plans[:warm], tol)
+        res, makespan = replay(fds, torch, srv, reqs, inputs, plans, tol)
+        srv.close()
+        lat = [r[0] * 1e3 for r in res]
+        ok = sum(1 for r in res if r[1] == 0)
+        out[name] = {"requests": len(res), "converged": ok, "throughput_solves_per_s": round(len(res) / makespan, 3),
+                     "makespan_s": round(makespan, 3), "latency_ms_p50": _r(pct(lat, 50)),
+                     "latency_ms_p99": _r(pct(lat, 99)), "latency_ms_max": _r(max(lat)),
+                     "max_relres_schur": max(r[3] for r in res),
+                     "not_converged": [{"k": k, "shape": reqs[k].spec.shape, "n": reqs[k].spec.n,
+                                        "kappa": round(reqs[k].spec.kappa, 3), "status": r[1],
+                                        "stop": r[4], "iterations": r[2], "cycles": r[5],
+                                        "relres": r[3]} for k, r in enumerate(res) if r[1] != 0]}
+        log(f"{name}: {out[name]}")
+        del plans
+        torch.cuda.empty_cache()
+    mixed = out["mixed_fgmres40_fp32_precond"]
+    return {
+        "metric": "solves/s & p50/p99 latency at rel-res 1e-10; DST/Thomas GB/s vs HBM peak",
+        "value": mixed["throughput_solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": round(mixed["makespan_s"] * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"Poisson request stream {args.serving_rate:g}/s for "
+                               f"{args.serving_seconds:g} s, shape U{{cross,L,T}}, n log-uniform "
+                               f"[64,{args.serving_nmax}], kappa 0 w.p. 1/2 else U[-100,0], seeded "
+                               f"Gaussian RHS, rel-res 1e-10, continuous-batching server "
+                               f"({args.serving_slots} slots, {args.serving_budget_gb:g} GB)",
+                   "paths": out},
+        "roofline": None, "cpu_baseline": None,
+    }
+
+
 # --------------------------------------------------------------------------- CPU baseline
 
 def cpu_baseline(items, sample):
@@ -152,7 +275,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="plain", choices=["plain", "precision", "batching"])
+    ap.add_argument("--workload", default="plain", choices=["plain", "precision", "batching", "serving"])
+    ap.add_argument("--serving-rate", type=float, default=200.0, help="requests per second")
+    ap.add_argument("--serving-seconds", type=float, default=1.0, help="length of the arrival trace")
+    ap.add_argument("--serving-nmax", type=int, default=2048)
+    ap.add_argument("--serving-budget-gb", type=float, default=160.0)
+    ap.add_argument("--serving-slots", type=int, default=64)
     ap.add_argument("--cpu-sample", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-solves", type=int, default=10)
@@ -189,6 +317,10 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         print(json.dumps({"copy_bytes_per_launch": 2 * n * 8, "GB/s": 2 * n * 8 * reps / dt / 1e9}))
+        return
+
+    if args.workload == "serving":
+        print(json.dumps(run_serving(args, device)), flush=True)
         return
 
     desc, items, opts = build_workload(args.workload, device)

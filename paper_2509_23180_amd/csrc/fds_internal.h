@@ -163,7 +163,7 @@ struct ProbState {
   double floor_coef;   // unit roundoff times a bound of ||L_c||_inf
   double last_hn;      // h_{j+1,j} of the latest Arnoldi step
   double vscale;       // factor that normalises the newest basis vector V[j]
-  double pad3;
+  double rscale;     // restart: scale of the new V[0] (0 when the problem stopped)
 };
 
 // ---------------------------------------------------------------- task records

@@ -801,18 +801,20 @@ __global__ void __launch_bounds__(kBlock) k_combine(const KryTask* __restrict__ 
   }
 }
 
-// After the residual operator (mode 1 writes r into V[0] and the partials):
-// beta = ||r||, convergence / floor / stagnation tests, normalise v_0.
+// After the residual operator (mode 1 writes r into V[0] and the partials).
+// Restart decision, one block per problem: beta = ||r||, the stopping tests
+// (tolerance with the rounding floor, cycle cap, stagnation) and the state
+// for the next cycle.  The decision is taken here, before any block scales
+// V[0], because the tests read state that this kernel updates.
 __global__ void __launch_bounds__(kBlock) k_restart(const KryTask* __restrict__ tasks, int ntasks,
                                                      int initial, int max_cycles) {
-  __shared__ int slot;
   __shared__ double red[4];
-  const KryTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  const KryTask& tk = tasks[blockIdx.x];
   ProbState* st = tk.st;
   if (st->finished) return;
-  const int b = blockIdx.x - tk.block_begin;
   const double r2 = sum_partials(tk.partials + (size_t)kPartRes * tk.P, tk.P, red);
   const double x2 = sum_partials(tk.partials + (size_t)(kPartRes + 1) * tk.P, tk.P, red);
+  if (threadIdx.x != 0) return;
   const double beta = sqrt(r2);
   const double fnorm = initial ? beta : st->fnorm;
   bool done = false;
@@ -834,33 +836,40 @@ __global__ void __launch_bounds__(kBlock) k_restart(const KryTask* __restrict__ 
     done = true;
     reason = FDS_STOP_STAGNATION;
   }
-  if (!done) {
-    const double inv = 1.0 / beta;
-    const long long base = (long long)b * kVecPerBlock;
-#pragma unroll
-    for (int e = 0; e < kVecEPT; ++e) {
-      const long long idx = base + (long long)e * kBlock + threadIdx.x;
-      if (idx < tk.Nc) tk.V[idx] *= inv;
-    }
+  if (initial) st->fnorm = fnorm;
+  else st->cycles += 1;
+  st->beta = beta;
+  st->xnorm = sqrt(x2);
+  st->tol_eff = tol_eff;
+  st->prev_rel = rel;
+  if (!finite) st->nonfinite = 1;
+  if (done) {
+    st->finished = 1;
+    st->cycle_done = 1;
+    st->stop_reason = reason;
+    st->rscale = 0.0;
+  } else {
+    st->cycle_done = 0;
+    st->j_done = 0;
+    st->vscale = 1.0;
+    st->rscale = 1.0 / beta;
+    tk.g[0] = beta;
   }
-  if (b == 0 && threadIdx.x == 0) {
-    if (initial) st->fnorm = fnorm;
-    else st->cycles += 1;
-    st->beta = beta;
-    st->xnorm = sqrt(x2);
-    st->tol_eff = tol_eff;
-    st->prev_rel = rel;
-    if (!finite) st->nonfinite = 1;
-    if (done) {
-      st->finished = 1;
-      st->cycle_done = 1;
-      st->stop_reason = reason;
-    } else {
-      st->cycle_done = 0;
-      st->j_done = 0;
-      st->vscale = 1.0;
-      tk.g[0] = beta;
-    }
+}
+
+// V[0] = r / beta for the problems that continue (after k_restart).
+__global__ void __launch_bounds__(kBlock) k_restart_scale(const KryTask* __restrict__ tasks,
+                                                           int ntasks) {
+  __shared__ int slot;
+  const KryTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  const ProbState* st = tk.st;
+  if (st->finished) return;
+  const double inv = st->rscale;
+  const long long base = (long long)(blockIdx.x - tk.block_begin) * kVecPerBlock;
+#pragma unroll
+  for (int e = 0; e < kVecEPT; ++e) {
+    const long long idx = base + (long long)e * kBlock + threadIdx.x;
+    if (idx < tk.Nc) tk.V[idx] *= inv;
   }
 }
 
@@ -1176,8 +1185,8 @@ void launch_combine(bool flex, const KryTask* tasks, int ntasks, int nblocks, hi
 void launch_restart(const KryTask* tasks, int ntasks, int nblocks, int initial, int max_cycles,
                     hipStream_t s) {
   if (nblocks <= 0) return;
-  FDS_LAUNCH(k_restart, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, initial,
-                     max_cycles);
+  FDS_LAUNCH(k_restart, dim3(ntasks), dim3(kBlock), 0, s, tasks, ntasks, initial, max_cycles);
+  FDS_LAUNCH(k_restart_scale, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
 }
 
 void launch_lift(int mode, const LiftTask* tasks, int ntasks, int nblocks, hipStream_t s) {

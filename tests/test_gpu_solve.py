@@ -177,6 +177,26 @@ def test_batch_matches_standalone(precision):
         assert compare(p, it[3], oracle_solution(p)) <= 1e-9
 
 
+def test_restart_many_cycles_batch_matches_alone():
+    """Short restarts (many cycles) on large centres, second in a batch: the
+    restart decision is taken once per problem before V[0] is scaled, so the
+    result equals the solve alone bitwise.  (Every block deciding for itself
+    while one block updated the cycle count and the previous residual let
+    late blocks skip the scaling from the third cycle on.)"""
+    fds = _fds()
+    first = _problem("L", 640, -30.0, "gauss", 7)
+    second = _problem("T", 600, 0.0, "gauss", 8)
+    a = device_problem(second, restart_m=6)
+    ra = fds.solve(a[0], a[1], a[3], 1e-10, bc=a[2])
+    assert ra.cycles >= 4
+    items = [device_problem(first, restart_m=6), device_problem(second, restart_m=6)]
+    rs = fds.solve_batch([i[0] for i in items], [i[1] for i in items], [i[3] for i in items],
+                         [1e-10, 1e-10], bcs=[i[2] for i in items])
+    log(f"restart batch: alone {ra.iterations} its / {ra.cycles} cycles, batch {rs[1].iterations}")
+    assert rs[1].iterations == ra.iterations
+    assert torch.equal(items[1][3], a[3])
+
+
 def _drain(srv, tickets, timeout=90.0):
     import time
     results = {}
