@@ -230,6 +230,8 @@ struct TaskSet {
   TaskList<LiftTask> lift, gather;
   TaskList<IfaceTask> iface_fp, iface_bs;
   TaskList<ResTask> resid;
+  TaskList<ResSumTask> res_sum;
+  TaskList<CopyTask> setup_copy, fin_copy;
   std::vector<Problem*> probs;
   Blob blob;
 
@@ -254,6 +256,9 @@ struct TaskSet {
     blob.add(iface_fp);
     blob.add(iface_bs);
     blob.add(resid);
+    blob.add(res_sum);
+    blob.add(setup_copy);
+    blob.add(fin_copy);
     blob.upload(s);
   }
   void launch_x_lines(hipStream_t s) const {
@@ -441,6 +446,7 @@ void TaskSet::add_problem(Problem& sl) {
     add_block_task(gather, lt, nb);
   }
   {
+    const int total = res_blocks_of(p);
     int off = 0;
     for (size_t r = 0; r < p->rd.size(); ++r) {
       const RectDev& d = p->rd[r];
@@ -448,12 +454,26 @@ void TaskSet::add_problem(Problem& sl) {
       rt.rd = d; rt.p = sl.x_int; rt.b = sl.b_int; rt.delta = p->delta; rt.kappa = p->kappa;
       const int nb = std::max(1, div_up((long long)d.rows * d.cols, (long long)kBlock * 8));
       rt.nblocks = nb;
-      rt.partials = sl.respart + 2 * off;
+      rt.partials = sl.respart + off;
+      rt.pstride = total;
       off += nb;
       add_block_task(resid, rt, nb);
     }
     sl.res_blocks = off;
+    res_sum.h.push_back(ResSumTask{sl.respart, total, 0, sl.st});
   }
+  // set-up copies: f'_c starts as b_c and x_c at zero; the back substitution
+  // starts the arms from b_a
+  const long long coff = p->rd[p->centre].off;
+  auto copy = [&](TaskList<CopyTask>& tl, double* dst, const double* src, long long count) {
+    if (count <= 0) return;
+    const int nb = std::max(1, div_up(count, (long long)kBlock * 8));
+    CopyTask c{dst, src, count, 0, nb};
+    add_block_task(tl, c, nb);
+  };
+  copy(setup_copy, sl.fp, sl.b_int + coff, sl.Nc);
+  copy(setup_copy, sl.x_int + coff, nullptr, sl.Nc);
+  copy(fin_copy, sl.x_int + coff + sl.Nc, sl.b_int + coff + sl.Nc, sl.Nint - sl.Nc);
 }
 
 // One Arnoldi step j of every problem of the set whose cycle is running.
@@ -553,10 +573,11 @@ struct Engine::Impl {
   int cycle_serial = 0;
 
   ~Impl() {
-    if (flags_host) (void)hipHostFree(flags_host);
+    // the device buffers go back to the cache: nothing queued may still use them
+    if (s) (void)hipStreamSynchronize(s);
+    if (flags_host) host_mapped_free(flags_host, sizeof(int) * capacity);
   }
   void read_states();
-  void upload_state(const Problem& p);
   TaskSet& current();
   void setup_phase(TaskSet& ts);
   std::vector<SolveOutcome> finalize_phase(TaskSet& ts);
@@ -570,11 +591,6 @@ void Engine::Impl::read_states() {
   FDS_HIP(hipMemcpyAsync(host_states.data(), states.get(), sizeof(ProbState) * capacity,
                          hipMemcpyDeviceToHost, s));
   FDS_HIP(hipStreamSynchronize(s));
-}
-
-void Engine::Impl::upload_state(const Problem& p) {
-  FDS_HIP(hipMemcpyAsync(states.as<ProbState>() + p.idx, &host_states[p.idx], sizeof(ProbState),
-                         hipMemcpyHostToDevice, s));
 }
 
 TaskSet& Engine::Impl::current() {
@@ -598,10 +614,10 @@ Engine::Engine(int m, int precision, int max_cycles, int capacity, hipStream_t s
   I.capacity = capacity;
   I.states.alloc(sizeof(ProbState) * capacity);
   I.host_states.assign(capacity, ProbState{});
-  FDS_HIP(hipHostMalloc((void**)&I.flags_host, sizeof(int) * capacity,
-                        hipHostMallocMapped | hipHostMallocCoherent));
+  void* fd = nullptr;
+  I.flags_host = static_cast<int*>(host_mapped_alloc(sizeof(int) * capacity, &fd));
+  I.flags_dev = static_cast<int*>(fd);
   std::memset(I.flags_host, 0, sizeof(int) * capacity);
-  FDS_HIP(hipHostGetDevicePointer((void**)&I.flags_dev, I.flags_host, 0));
   for (int i = capacity - 1; i >= 0; --i) I.free_idx.push_back(i);
 }
 
@@ -665,15 +681,27 @@ void Engine::admit(const std::vector<SolveRequest>& reqs, const std::vector<int>
     hs.floor_coef = p->floor_coef;
     hs.vscale = 1.0;
     I.flags_host[sl.idx] = 0;
-    I.upload_state(sl);
     fresh.push_back(up.get());
     I.active.push_back(std::move(up));
   }
-  TaskSet ts(m, flex);
-  for (Problem* p : fresh) ts.add_problem(*p);
-  ts.upload(I.s);
-  I.setup_phase(ts);
-  I.cur.reset();
+  // initial states: one copy per run of consecutive pool indices
+  std::vector<int> idx;
+  for (Problem* p : fresh) idx.push_back(p->idx);
+  std::sort(idx.begin(), idx.end());
+  for (size_t a = 0; a < idx.size();) {
+    size_t b = a + 1;
+    while (b < idx.size() && idx[b] == idx[b - 1] + 1) ++b;
+    FDS_HIP(hipMemcpyAsync(I.states.as<ProbState>() + idx[a], &I.host_states[idx[a]],
+                           sizeof(ProbState) * (b - a), hipMemcpyHostToDevice, I.s));
+    a = b;
+  }
+  std::unique_ptr<TaskSet> ts(new TaskSet(m, flex));
+  for (Problem* p : fresh) ts->add_problem(*p);
+  ts->upload(I.s);
+  I.setup_phase(*ts);
+  // when the new problems are the whole set, their task lists serve the cycles
+  if (fresh.size() == I.active.size()) I.cur = std::move(ts);
+  else I.cur.reset();
 }
 
 void Engine::Impl::setup_phase(TaskSet& ts) {
@@ -691,15 +719,8 @@ void Engine::Impl::setup_phase(TaskSet& ts) {
     ts.arm_inv.launch(0, s);
     Timing::end(0, s);
   }
-  for (Problem* sl : ts.probs) {
-    const long long coff = sl->plan->rd[sl->plan->centre].off;
-    FDS_HIP(hipMemcpyAsync(sl->fp, sl->b_int + coff, 8 * sl->Nc, hipMemcpyDeviceToDevice, s));
-  }
+  launch_copy(ts.setup_copy.dev(), ts.setup_copy.n(), ts.setup_copy.nblocks, s);
   launch_iface(ts.iface_fp.dev(), ts.iface_fp.n(), s);
-  for (Problem* sl : ts.probs) {
-    const long long coff = sl->plan->rd[sl->plan->centre].off;
-    FDS_HIP(hipMemsetAsync(sl->x_int + coff, 0, 8 * sl->Nc, s));
-  }
   ts.launch_x_lines(s);
   launch_operator(1, ts.res_op.dev(), ts.res_op.n(), ts.res_op.nblocks, 0, s);
   launch_restart(ts.kry.dev(), ts.kry.n(), ts.kry.nblocks, 1, max_cycles, s);
@@ -746,13 +767,23 @@ std::vector<std::pair<int, SolveOutcome>> Engine::retire(const std::vector<int>&
   Impl& I = *impl_;
   std::vector<std::pair<int, SolveOutcome>> res;
   if (ids.empty()) return res;
-  TaskSet ts(I.m, I.flex);
+  size_t hit = 0;
   for (auto& p : I.active)
-    if (std::find(ids.begin(), ids.end(), p->id) != ids.end()) ts.add_problem(*p);
-  if (ts.probs.empty()) return res;
-  ts.upload(I.s);
-  std::vector<SolveOutcome> out = I.finalize_phase(ts);
-  for (size_t i = 0; i < ts.probs.size(); ++i) res.emplace_back(ts.probs[i]->id, out[i]);
+    if (std::find(ids.begin(), ids.end(), p->id) != ids.end()) ++hit;
+  if (hit == 0) return res;
+  std::unique_ptr<TaskSet> own;
+  TaskSet* ts = nullptr;
+  if (hit == I.active.size() && I.cur) {
+    ts = I.cur.get();   // retiring everything: the cycle task lists cover it
+  } else {
+    own.reset(new TaskSet(I.m, I.flex));
+    for (auto& p : I.active)
+      if (std::find(ids.begin(), ids.end(), p->id) != ids.end()) own->add_problem(*p);
+    own->upload(I.s);
+    ts = own.get();
+  }
+  std::vector<SolveOutcome> out = I.finalize_phase(*ts);
+  for (size_t i = 0; i < ts->probs.size(); ++i) res.emplace_back(ts->probs[i]->id, out[i]);
   // release: the stream is idle after finalize_phase
   std::vector<std::unique_ptr<Problem>> keep;
   for (auto& p : I.active) {
@@ -765,15 +796,8 @@ std::vector<std::pair<int, SolveOutcome>> Engine::retire(const std::vector<int>&
 }
 
 std::vector<SolveOutcome> Engine::Impl::finalize_phase(TaskSet& ts) {
-  for (Problem* sl : ts.probs) {
-    const long long coff = sl->plan->rd[sl->plan->centre].off;
-    const long long rest = sl->Nint - sl->Nc;
-    if (rest > 0) {
-      // arms follow the centre in the internal layout
-      FDS_HIP(hipMemcpyAsync(sl->x_int + coff + sl->Nc, sl->b_int + coff + sl->Nc, 8 * rest,
-                             hipMemcpyDeviceToDevice, s));
-    }
-  }
+  // arms follow the centre in the internal layout: they start from b_a
+  launch_copy(ts.fin_copy.dev(), ts.fin_copy.n(), ts.fin_copy.nblocks, s);
   launch_iface(ts.iface_bs.dev(), ts.iface_bs.n(), s);
   if (ts.bs_fwd.n()) {
     Timing::begin(0, s);
@@ -788,29 +812,15 @@ std::vector<SolveOutcome> Engine::Impl::finalize_phase(TaskSet& ts) {
   }
   launch_lift(1, ts.gather.dev(), ts.gather.n(), ts.gather.nblocks, s);
   launch_residual(ts.resid.dev(), ts.resid.n(), ts.resid.nblocks, s);
+  launch_res_sum(ts.res_sum.dev(), ts.res_sum.n(), s);
   FDS_HIP(hipGetLastError());
-  std::vector<std::vector<double>> parts(ts.probs.size());
-  for (size_t i = 0; i < ts.probs.size(); ++i) {
-    parts[i].resize(2 * ts.probs[i]->res_blocks);
-    FDS_HIP(hipMemcpyAsync(parts[i].data(), ts.probs[i]->respart, 8 * parts[i].size(),
-                           hipMemcpyDeviceToHost, s));
-  }
   read_states();
   if (Timing::on()) account_arms(ts.probs, false);
   std::vector<SolveOutcome> out(ts.probs.size());
   for (size_t i = 0; i < ts.probs.size(); ++i) {
     const Problem& sl = *ts.probs[i];
     const ProbState& st = host_states[sl.idx];
-    double rr = 0, bb = 0;
-    int off = 0;
-    // partials are laid out rectangle by rectangle: [r^2 (nb) | b^2 (nb)]
-    for (size_t r = 0; r < sl.plan->rd.size(); ++r) {
-      const RectDev& d = sl.plan->rd[r];
-      const int nb = std::max(1, div_up((long long)d.rows * d.cols, (long long)kBlock * 8));
-      for (int b = 0; b < nb; ++b) rr += parts[i][2 * off + b];
-      for (int b = 0; b < nb; ++b) bb += parts[i][2 * off + nb + b];
-      off += nb;
-    }
+    const double rr = st.res_rr, bb = st.res_bb;
     SolveOutcome& o = out[i];
     o.res.iterations = st.iterations;
     o.res.cycles = st.cycles;

@@ -164,6 +164,8 @@ struct ProbState {
   double last_hn;      // h_{j+1,j} of the latest Arnoldi step
   double vscale;       // factor that normalises the newest basis vector V[j]
   double rscale;     // restart: scale of the new V[0] (0 when the problem stopped)
+  double res_rr;     // composite residual: sum of r^2 and of b^2 (after the solve)
+  double res_bb;
 };
 
 // ---------------------------------------------------------------- task records
@@ -317,7 +319,26 @@ struct ResTask {
   const double* p;            // internal vector base
   const double* b;
   double delta, kappa;
-  double* partials;           // [2 * nblocks]: sum r^2, sum b^2
+  double* partials;           // block sums of r^2 at [b], of b^2 at [pstride + b]
+  int block_begin;
+  int nblocks;
+  int pstride;                // blocks of the whole problem (all rectangles)
+  int pad;
+};
+
+// Sum of a problem's residual block partials into its state (one block).
+struct ResSumTask {
+  const double* partials;     // [2 * n]
+  int n;
+  int pad;
+  ProbState* st;
+};
+
+// dst[0..count) = src[0..count), or 0 when src is null.
+struct CopyTask {
+  double* dst;
+  const double* src;
+  long long count;
   int block_begin;
   int nblocks;
 };

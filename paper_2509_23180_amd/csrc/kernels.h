@@ -80,6 +80,8 @@ void launch_restart(const KryTask* tasks, int ntasks, int nblocks, int initial, 
 void launch_lift(int mode, const LiftTask* tasks, int ntasks, int nblocks, hipStream_t s);
 void launch_iface(const IfaceTask* tasks, int ntasks, hipStream_t s);
 void launch_residual(const ResTask* tasks, int ntasks, int nblocks, hipStream_t s);
+void launch_res_sum(const ResSumTask* tasks, int ntasks, hipStream_t s);
+void launch_copy(const CopyTask* tasks, int ntasks, int nblocks, hipStream_t s);
 void launch_count_active(const ProbState* st, int n, int* out, hipStream_t s);
 
 }  // namespace fds

@@ -966,8 +966,30 @@ __global__ void __launch_bounds__(kBlock) k_residual(const ResTask* __restrict__
   const double s2 = block_sum(bb, red);
   if (threadIdx.x == 0) {
     tk.partials[b] = s1;
-    tk.partials[tk.nblocks + b] = s2;
+    tk.partials[tk.pstride + b] = s2;
   }
+}
+
+// Composite residual sums of each problem, fixed order (one block per problem).
+__global__ void __launch_bounds__(kBlock) k_res_sum(const ResSumTask* __restrict__ tasks) {
+  __shared__ double red[4];
+  const ResSumTask& tk = tasks[blockIdx.x];
+  const double rr = sum_partials(tk.partials, tk.n, red);
+  const double bb = sum_partials(tk.partials + tk.n, tk.n, red);
+  if (threadIdx.x == 0) {
+    tk.st->res_rr = rr;
+    tk.st->res_bb = bb;
+  }
+}
+
+// Copies and zero fills of whole vectors, batched over problems.
+__global__ void __launch_bounds__(kBlock) k_copy(const CopyTask* __restrict__ tasks, int ntasks) {
+  __shared__ int slot;
+  const CopyTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  const long long stride = (long long)tk.nblocks * kBlock;
+  for (long long e = (long long)(blockIdx.x - tk.block_begin) * kBlock + threadIdx.x; e < tk.count;
+       e += stride)
+    tk.dst[e] = tk.src ? tk.src[e] : 0.0;
 }
 
 // Number of problems whose current cycle is still running.
@@ -1198,6 +1220,16 @@ void launch_lift(int mode, const LiftTask* tasks, int ntasks, int nblocks, hipSt
 void launch_iface(const IfaceTask* tasks, int ntasks, hipStream_t s) {
   if (ntasks <= 0) return;
   FDS_LAUNCH(k_iface, dim3(ntasks), dim3(kBlock), 0, s, tasks, ntasks);
+}
+
+void launch_res_sum(const ResSumTask* tasks, int ntasks, hipStream_t s) {
+  if (ntasks <= 0) return;
+  FDS_LAUNCH(k_res_sum, dim3(ntasks), dim3(kBlock), 0, s, tasks);
+}
+
+void launch_copy(const CopyTask* tasks, int ntasks, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return;
+  FDS_LAUNCH(k_copy, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
 }
 
 void launch_residual(const ResTask* tasks, int ntasks, int nblocks, hipStream_t s) {

@@ -13,6 +13,16 @@
 namespace fds {
 
 // ---------------------------------------------------------------- device buffer
+// Device memory cache (alloc.cpp): blocks are kept per device and size class
+// after release and handed out again, so repeated solves allocate nothing
+// from the runtime.  Cached bytes above FDS_CACHE_BYTES (default 64 GiB) are
+// returned to the runtime.
+void* device_cache_alloc(size_t bytes, size_t* capacity);
+void device_cache_free(void* p, size_t capacity);
+// Mapped, coherent host memory (flags the kernels write), cached the same way.
+void* host_mapped_alloc(size_t bytes, void** device_ptr);
+void host_mapped_free(void* p, size_t bytes);
+
 class DevBuf {
  public:
   DevBuf() = default;
@@ -20,20 +30,28 @@ class DevBuf {
   ~DevBuf() { release(); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_), cap_(o.cap_) { o.p_ = nullptr; o.n_ = 0; o.cap_ = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p_ = o.p_; n_ = o.n_; o.p_ = nullptr; o.n_ = 0; }
+    if (this != &o) {
+      release();
+      p_ = o.p_; n_ = o.n_; cap_ = o.cap_;
+      o.p_ = nullptr; o.n_ = 0; o.cap_ = 0;
+    }
     return *this;
   }
   void alloc(size_t bytes) {
     release();
-    if (bytes) FDS_HIP(hipMalloc(&p_, bytes));
+    if (bytes) p_ = device_cache_alloc(bytes, &cap_);
     n_ = bytes;
   }
+  // The caller guarantees that no queued work still uses the memory (every
+  // release in this library follows a synchronisation of the stream that
+  // used it).
   void release() {
-    if (p_) (void)hipFree(p_);
+    if (p_) device_cache_free(p_, cap_);
     p_ = nullptr;
     n_ = 0;
+    cap_ = 0;
   }
   template <typename T> T* as(size_t byte_off = 0) const {
     return reinterpret_cast<T*>(static_cast<char*>(p_) + byte_off);
@@ -44,6 +62,7 @@ class DevBuf {
  private:
   void* p_ = nullptr;
   size_t n_ = 0;
+  size_t cap_ = 0;
 };
 
 // ---------------------------------------------------------------- shared tables

@@ -3,6 +3,9 @@
 // double where the angle reduction benefits) and uploaded once.
 #include <algorithm>
 #include <cmath>
+#include <tuple>
+#include <mutex>
+#include <map>
 #include <complex>
 #include <cstdlib>
 #include <cstring>
@@ -197,10 +200,26 @@ WaveCfg dst_wave_config(int n, bool fp32) {
   return c;
 }
 
+static DstChoice dst_choice_compute(int n, bool fp32, const std::string& mode);
+
 DstChoice dst_choice(int n, bool fp32) {
-  DstChoice c{false, 1, 4, 0, 0, 0, kBlock};
+  // memoised per (algorithm setting, n, precision): task-list construction
+  // asks for every transform of every problem
+  static std::mutex mu;
+  static std::map<std::tuple<std::string, int, bool>, DstChoice> memo;
   const char* env = std::getenv("FDS_DST_ALGO");
   const std::string mode = env ? env : "auto";
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_tuple(mode, n, fp32);
+  auto it = memo.find(key);
+  if (it != memo.end()) return it->second;
+  const DstChoice c = dst_choice_compute(n, fp32, mode);
+  memo[key] = c;
+  return c;
+}
+
+static DstChoice dst_choice_compute(int n, bool fp32, const std::string& mode) {
+  DstChoice c{false, 1, 4, 0, 0, 0, kBlock};
   if (mode == "gemm" && n <= kGemmMaxN) {
     const int np = (n + 63) / 64 * 64;
     c.gemm = true;
@@ -233,8 +252,8 @@ size_t line_smem_bytes(int n) {
 }
 
 TableCache& TableCache::get() {
-  static TableCache c;
-  return c;
+  static TableCache* c = new TableCache();   // never destroyed (see alloc.cpp)
+  return *c;
 }
 
 static int current_device() {
