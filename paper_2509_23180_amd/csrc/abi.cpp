@@ -227,27 +227,6 @@ fds_status fds_solve(fds_plan* plan, const double* rhs, const double* bc, double
 
 // ---------------------------------------------------------------- kernel-level entry points
 
-static void launch_one_dst(DstKind kind, const DstTask& t0, hipStream_t s, DevBuf& keep) {
-  const bool fp32 = kind != DstKind::D_D;
-  const DstChoice ch = dst_choice(t0.n, fp32);
-  DstTask t = t0;
-  t.rpb = ch.gemm ? 1 : ch.rows_per_block;
-  t.tw_lds = (ch.gemm || ch.wave_e) ? 0 : (dst_twiddles_in_lds(t.n, fp32) ? 1 : 0);
-  if (ch.wave_e) {
-    t.wd = TableCache::get().wave_desc(t.fft, fp32);
-    t.io_f32 = dst_io_flags(kind);
-  }
-  t.block_begin = 0;
-  keep.alloc(sizeof(DstTask));
-  FDS_HIP(hipMemcpyAsync(keep.get(), &t, sizeof(t), hipMemcpyHostToDevice, s));
-  const int nb = (t.rows + ch.rows_per_block - 1) / ch.rows_per_block;
-  Timing::begin(0, s);
-  if (ch.gemm) launch_dst_gemm(kind, ch.rt, ch.ct, keep.as<DstTask>(), 1, nb, ch.smem, 0, s);
-  else if (ch.wave_e)
-    launch_dst_wave(kind, ch.wave_e, keep.as<DstTask>(), 1, nb, ch.threads, ch.smem, 0, s);
-  else launch_dst(kind, keep.as<DstTask>(), 1, nb, ch.smem, 0, s);
-  Timing::end(0, s);
-}
 
 static fds_status dst_rows_impl(const void* in, void* out, int rows, int n, double scale,
                                 bool fp32, hipStream_t s) {
@@ -258,7 +237,7 @@ static fds_status dst_rows_impl(const void* in, void* out, int rows, int n, doub
   t.in = in; t.out = out; t.in_rs = n; t.out_rs = n; t.in_cs = 1; t.out_cs = 1;
   t.rows = rows; t.n = n; t.scale = scale; t.fft = fft->dev;
   DevBuf keep;
-  launch_one_dst(fp32 ? DstKind::F_F : DstKind::D_D, t, s, keep);
+  launch_one_dst(fp32 ? DstKind::F_F : DstKind::D_D, dst_choice(n, fp32), t, s, keep);
   FDS_HIP(hipGetLastError());
   FDS_HIP(hipStreamSynchronize(s));
   return FDS_OK;
@@ -323,11 +302,11 @@ fds_status fds_k_rect_solve(const double* f, double* z, int32_t rows, int32_t co
     tt.data = tmp.get(); tt.rs = cols; tt.rows = rows; tt.modes = cols;
     tt.coef = fp32 ? (const void*)modes->c32 : (const void*)modes->c64;
     DevBuf keep1, keep2, keep3(sizeof(TriTask));
-    launch_one_dst(fp32 ? DstKind::D_F : DstKind::D_D, t, s, keep1);
+    launch_one_dst(fp32 ? DstKind::D_F : DstKind::D_D, dst_choice(cols, fp32), t, s, keep1);
     FDS_HIP(hipMemcpyAsync(keep3.get(), &tt, sizeof(tt), hipMemcpyHostToDevice, s));
     const TriConfig tc = tri_config(fp32, rows);
     launch_tri(tc, fp32, keep3.as<TriTask>(), 1, tri_blocks(tc, cols), 0, s);
-    launch_one_dst(fp32 ? DstKind::F_D : DstKind::D_D, v, s, keep2);
+    launch_one_dst(fp32 ? DstKind::F_D : DstKind::D_D, dst_choice(cols, fp32), v, s, keep2);
     FDS_HIP(hipGetLastError());
     FDS_HIP(hipStreamSynchronize(s));
     return FDS_OK;
@@ -411,20 +390,15 @@ fds_status fds_k_arnoldi_mgs(double* V, int32_t k, int64_t len, double* h, void*
     auto* dt = reinterpret_cast<KryTask*>(reinterpret_cast<char*>(st) + 512);
     FDS_HIP(hipMemcpyAsync(dt, &t, sizeof(t), hipMemcpyHostToDevice, s));
     FDS_HIP(hipMemcpyAsync(dt + 1, &gt, sizeof(gt), hipMemcpyHostToDevice, s));
-    for (int c = 0; c < j; ++c) {
-      launch_gram_dots(dt + 1, 1, P, c, s);
-      launch_gram_solve(dt + 1, 1, c, s);
-    }
+    for (int c = 0; c < j; ++c) launch_gram_dots(dt + 1, 1, P, c, s);
     Timing::begin(3, s);
     launch_gram_dots(dt, 1, P, j, s);
     Timing::end(3, s);
-    launch_gram_solve(dt, 1, j, s);
     Timing::begin(6, s);
-    launch_gram_update(dt, 1, P, j, s);
+    launch_gram_update(dt, 1, P, j, nullptr, 0, s);
     Timing::end(6, s);
-    // H column j holds h_{0..j, j} before the Givens rotations of the finish step
-    FDS_HIP(hipMemcpyAsync(h, H + (size_t)j * (m + 1), 8 * (size_t)k, hipMemcpyDeviceToDevice, s));
-    launch_mgs_finish(dt, 1, j, nullptr, 0, s);
+    // hv holds h_{0..j, j} (column j of H has the Givens rotations applied)
+    FDS_HIP(hipMemcpyAsync(h, t.hv, 8 * (size_t)k, hipMemcpyDeviceToDevice, s));
     launch_scale_newest(dt, j, std::max(1, std::min(P * kVecEPT, 1024)), s);
     FDS_HIP(hipMemcpyAsync(h + k, &st->last_hn, 8, hipMemcpyDeviceToDevice, s));
     FDS_HIP(hipGetLastError());

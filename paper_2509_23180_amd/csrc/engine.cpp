@@ -429,6 +429,7 @@ void TaskSet::add_problem(Problem& sl) {
     k.V = sl.V; k.Z = sl.Z; k.x = sl.x_int + cd.off; k.u = sl.u; k.H = sl.H; k.cs = sl.cs;
     k.sn = sl.sn; k.g = sl.g; k.y = sl.y; k.partials = sl.partials; k.st = sl.st; k.Nc = Nc;
     k.P = sl.P; k.m = m; k.G = sl.G; k.hv = sl.hv; k.nx = nx; k.ny = ny;
+    k.flag_idx = sl.idx;
     k.implicit_w = flex ? 0 : 1;
     for (int q = 0; q < 4; ++q) k.line[q] = ot.line[q];
     add_block_task(kry, k, sl.P);
@@ -507,15 +508,9 @@ void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
   Timing::begin(3, s);
   launch_gram_dots(kry.dev(), kry.n(), kry.nblocks, j, s);
   Timing::end(3, s);
-  Timing::begin(5, s);
-  launch_gram_solve(kry.dev(), kry.n(), j, s);
-  Timing::end(5, s);
   Timing::begin(6, s);
-  launch_gram_update(kry.dev(), kry.n(), kry.nblocks, j, s);
+  launch_gram_update(kry.dev(), kry.n(), kry.nblocks, j, flags_dev, tag, s);
   Timing::end(6, s);
-  Timing::begin(5, s);
-  launch_mgs_finish(kry.dev(), kry.n(), j, flags_dev, tag, s);
-  Timing::end(5, s);
   FDS_HIP(hipGetLastError());
 }
 

@@ -153,7 +153,9 @@ struct ProbState {
   int iterations;
   int cycles;
   int nonfinite;
-  int pad;
+  int ctr_dots;     // blocks of the current Gram-dot launch that finished
+  int ctr_upd;      // blocks of the current update launch that finished
+  int pad_ctr;
   double beta;      // true residual norm at the start of the current cycle
   double fnorm;     // ||f'_c||_2
   double tol;
@@ -262,6 +264,8 @@ struct KryTask {
   int implicit_w;             // 1: w = v_j - s (exact preconditioner), 0: w stored in V[j+1]
   int block_begin;
   const double* line[4];      // Schur line terms s on the centre's boundary lines (or NULL)
+  int flag_idx;               // slot of this problem in the host-visible flag array
+  int pad_k;
 };
 
 // partial-sum slots (each P wide) inside KryTask::partials

@@ -67,10 +67,14 @@ void launch_lines_dense(const LineTask* tasks, int ntasks, int nblocks, int lmax
 void launch_lines(const LineTask* tasks, int ntasks, size_t smem, int jidx, hipStream_t s);
 void launch_operator(int mode, const OpTask* tasks, int ntasks, int nblocks, int jidx,
                      hipStream_t s);
+// Dot partials of step j; each problem's last block forms the Gram column and
+// the coefficients h_{0..j} (written to KryTask::hv and column j of H).
 void launch_gram_dots(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s);
-void launch_gram_solve(const KryTask* tasks, int ntasks, int j, hipStream_t s);
-void launch_gram_update(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s);
-void launch_mgs_finish(const KryTask* tasks, int ntasks, int j, int* flags, int tag, hipStream_t s);
+// w - sum h_i v_i into V[j+1]; each problem's last block then takes the norm,
+// applies the Givens rotations and tests convergence, and on the end of the
+// cycle writes `tag` to flags[KryTask::flag_idx] (flags may be null).
+void launch_gram_update(const KryTask* tasks, int ntasks, int nblocks, int j, int* flags, int tag,
+                        hipStream_t s);
 void launch_scale_newest(const KryTask* tasks, int j, int nblocks, hipStream_t s);
 void launch_idst_cols(const ColTask* tasks, int ntasks, int nblocks, hipStream_t s);
 void launch_ls_solve(const KryTask* tasks, int ntasks, hipStream_t s);

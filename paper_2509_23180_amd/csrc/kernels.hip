@@ -523,11 +523,86 @@ __device__ __forceinline__ double line_term(const KryTask& tk, long long idx) {
   return s;
 }
 
+// The last block of a problem to finish a launch does the problem's serial
+// work (partials are added in a fixed order, so the result does not depend
+// on which block is last).  Partials that another block of the same launch
+// reads are stored and loaded as agent-scope relaxed atomics, which the
+// memory model keeps coherent across the XCDs' L2 caches; a device-wide fence
+// would instead write back and invalidate the whole L2 in every block.  Each
+// block waits for its stores to complete, then counts itself in; the last
+// block resets the counter for the next launch.
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool last_block_of_problem(int* ctr, int nblocks, int* sflag) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int old = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int last = (old == nblocks - 1) ? 1 : 0;
+    if (last) __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *sflag = last;
+  }
+  __syncthreads();
+  return *sflag != 0;
+}
+
+// Gram column and MGS coefficients of step j from the dot partials:
+// G[:, j] = <v_i, v_j>, a_i = <w, v_i>, h_i = a_i - sum_{l<i} h_l G_li.
+// The recurrence runs in LDS: after h_l is final every i > l subtracts
+// h_l G_li in parallel.  lds: 3 (j+1) + j (j+1)/2 doubles.
+__device__ void gram_solve_block(const KryTask& tk, int j, double* lds) {
+  const int nd = j + 1;
+  const int P = tk.P;
+  const int m1 = tk.m + 1;
+  double* dots = lds;                 // 2 nd
+  double* a = dots + 2 * nd;          // nd
+  double* Gt = a + nd;                // column i of the strict upper triangle at i (i - 1) / 2
+  for (int t = threadIdx.x; t < 2 * nd; t += blockDim.x) {
+    const double* p = tk.partials + (size_t)(kPartDots + t) * P;
+    double s = 0.0;
+    for (int q = 0; q < P; ++q) s += ld_agent(p + q);
+    dots[t] = s;
+  }
+  const int ntri = nd * (nd - 1) / 2;
+  for (int e = threadIdx.x; e < ntri; e += blockDim.x) {
+    int i = (int)((1.0 + sqrt(1.0 + 8.0 * e)) * 0.5);
+    while (i * (i - 1) / 2 > e) --i;
+    while ((i + 1) * i / 2 <= e) ++i;
+    const int l = e - i * (i - 1) / 2;
+    Gt[e] = (i < j) ? tk.G[l + i * m1] : -1.0;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+    tk.G[t + j * m1] = dots[t];
+    a[t] = tk.implicit_w ? dots[t] - dots[nd + t] : dots[nd + t];
+  }
+  for (int l = threadIdx.x; l < j; l += blockDim.x) Gt[j * (j - 1) / 2 + l] = dots[l];
+  __syncthreads();
+  for (int l = 0; l < nd; ++l) {
+    const double hl = a[l];
+    __syncthreads();
+    for (int i = l + 1 + threadIdx.x; i < nd; i += blockDim.x) a[i] -= hl * Gt[i * (i - 1) / 2 + l];
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < nd; i += blockDim.x) {
+    tk.hv[i] = a[i];
+    tk.H[i + j * m1] = a[i];
+  }
+}
+
 // Block partials of <v_i, v_j> (i <= j) and of <v_i, u> with u = w when w is
-// stored, u = s (the Schur line terms, zero off the boundary) otherwise.
+// stored, u = s (the Schur line terms, zero off the boundary) otherwise; the
+// problem's last block then forms the Gram column and the coefficients.
 __global__ void __launch_bounds__(kBlock) k_gram_dots(const KryTask* __restrict__ tasks, int ntasks,
                                                        int j) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int slot;
+  __shared__ int lastf;
   __shared__ double red[2 * 121][4];
   const KryTask& tk = tasks[find_task(tasks, ntasks, &slot)];
   if (tk.st->cycle_done) return;
@@ -568,65 +643,76 @@ __global__ void __launch_bounds__(kBlock) k_gram_dots(const KryTask* __restrict_
   for (int t = threadIdx.x; t < 2 * nd; t += kBlock) {
     const int row = t < nd ? t : 121 + (t - nd);
     const double s = (red[row][0] + red[row][1]) + (red[row][2] + red[row][3]);
-    tk.partials[(size_t)(kPartDots + t) * tk.P + b] = s;
+    st_agent(tk.partials + (size_t)(kPartDots + t) * tk.P + b, s);
   }
+  if (last_block_of_problem(&tk.st->ctr_dots, tk.P, &lastf))
+    gram_solve_block(tk, j, reinterpret_cast<double*>(smem_raw));
 }
 
-// One block per problem: reduce the dot partials, store the Gram column,
-// form <w, v_i>, run the MGS recurrence for h and store column j of H.
-// The recurrence h_i = a_i - sum_{l<i} h_l G_li runs in LDS: after h_l is
-// final every i > l subtracts h_l G_li in parallel.
-__global__ void __launch_bounds__(kBlock) k_gram_solve(const KryTask* __restrict__ tasks, int ntasks,
-                                                        int j) {
-  __shared__ double dots[2 * 121];
-  __shared__ double a[121];
-  __shared__ double Gt[121 * 121 / 2 + 121];
-  const KryTask& tk = tasks[blockIdx.x];
-  if (tk.st->cycle_done) return;
-  const int nd = j + 1;
-  const int P = tk.P;
+// h_{j+1,j} = ||w||, Givens update of column j and the convergence test on
+// |g_{j+1}| (thread 0 of one block of the problem).  V[j+1] is normalised by
+// the next step's sine transform (ProbState::vscale).  When the problem's
+// cycle ends, its host-visible flag receives `tag`.
+__device__ void mgs_finish_block(const KryTask& tk, int j, int* flags, int tag, double* red,
+                                 double* col, double* cs, double* sn) {
+  ProbState* st = tk.st;
   const int m1 = tk.m + 1;
-  for (int t = threadIdx.x; t < 2 * nd; t += kBlock) {
-    const double* p = tk.partials + (size_t)(kPartDots + t) * P;
-    double s = 0.0;
-    for (int q = 0; q < P; ++q) s += p[q];
-    dots[t] = s;
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = tk.H[i + j * m1];
+  for (int i = threadIdx.x; i < j; i += blockDim.x) {
+    cs[i] = tk.cs[i];
+    sn[i] = tk.sn[i];
   }
-  // strictly upper triangle G_li (l < i <= j), column i at offset i(i-1)/2;
-  // column j is this step's dots
-  const int ntri = nd * (nd - 1) / 2;
-  for (int e = threadIdx.x; e < ntri; e += kBlock) {
-    int i = (int)((1.0 + sqrt(1.0 + 8.0 * e)) * 0.5);
-    while (i * (i - 1) / 2 > e) --i;
-    while ((i + 1) * i / 2 <= e) ++i;
-    const int l = e - i * (i - 1) / 2;
-    Gt[e] = (i < j) ? tk.G[l + i * m1] : -1.0;
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < tk.P; q += blockDim.x) acc += ld_agent(tk.partials + (size_t)kPartNorm * tk.P + q);
+  const double nrm2 = block_sum(acc, red);
+  if (threadIdx.x != 0) return;
+  const double hn = sqrt(nrm2);
+  const bool breakdown = !(hn > 1e-14 * st->beta);
+  col[j + 1] = hn;
+  st->last_hn = hn;
+  st->vscale = breakdown ? 1.0 : 1.0 / hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = col[i], c2 = col[i + 1];
+    col[i] = cs[i] * a + sn[i] * c2;
+    col[i + 1] = -sn[i] * a + cs[i] * c2;
   }
-  __syncthreads();
-  for (int t = threadIdx.x; t < nd; t += kBlock) {
-    tk.G[t + j * m1] = dots[t];
-    a[t] = tk.implicit_w ? dots[t] - dots[nd + t] : dots[nd + t];
+  const double a = col[j];
+  const double rho = hypot(a, hn);
+  double c = 1.0, s = 0.0;
+  if (rho > 0.0) {
+    c = a / rho;
+    s = hn / rho;
   }
-  for (int l = threadIdx.x; l < j; l += kBlock) Gt[j * (j - 1) / 2 + l] = dots[l];
-  __syncthreads();
-  for (int l = 0; l < nd; ++l) {
-    const double hl = a[l];
-    __syncthreads();
-    for (int i = l + 1 + threadIdx.x; i < nd; i += kBlock) a[i] -= hl * Gt[i * (i - 1) / 2 + l];
-    __syncthreads();
-  }
-  for (int i = threadIdx.x; i < nd; i += kBlock) {
-    tk.hv[i] = a[i];
-    tk.H[i + j * m1] = a[i];
+  tk.cs[j] = c;
+  tk.sn[j] = s;
+  col[j] = rho;
+  col[j + 1] = 0.0;
+  for (int i = 0; i <= j + 1; ++i) tk.H[i + j * m1] = col[i];
+  const double gj = tk.g[j];
+  tk.g[j + 1] = -s * gj;
+  tk.g[j] = c * gj;
+  st->j_done = j + 1;
+  st->iterations += 1;
+  const double est = fabs(tk.g[j + 1]);
+  if (!(est > st->tol_eff * st->fnorm) || breakdown || j + 1 == tk.m) {
+    st->cycle_done = 1;
+    if (flags) {
+      flags[tk.flag_idx] = tag;
+      __threadfence_system();
+    }
   }
 }
 
-// w_new = w - sum_i h_i v_i  -> V[j+1], with block partials of ||w_new||^2.
+// w_new = w - sum_i h_i v_i  -> V[j+1], with block partials of ||w_new||^2;
+// the problem's last block then finishes the step (mgs_finish_block).
 __global__ void __launch_bounds__(kBlock) k_gram_update(const KryTask* __restrict__ tasks, int ntasks,
-                                                         int j) {
+                                                         int j, int* flags, int tag) {
   __shared__ int slot;
+  __shared__ int lastf;
   __shared__ double red[4];
   __shared__ double hs[121];
+  __shared__ double col[122];
+  __shared__ double cs[121], sn[121];
   const KryTask& tk = tasks[find_task(tasks, ntasks, &slot)];
   if (tk.st->cycle_done) return;
   for (int i = threadIdx.x; i <= j; i += kBlock) hs[i] = tk.hv[i];
@@ -686,64 +772,9 @@ __global__ void __launch_bounds__(kBlock) k_gram_update(const KryTask* __restric
     }
   }
   const double s = block_sum(nrm, red);
-  if (threadIdx.x == 0) tk.partials[(size_t)kPartNorm * tk.P + b] = s;
-}
-
-// One block per problem: h_{j+1,j} = ||w||, Givens update of column j and
-// the convergence test on |g_{j+1}|.  V[j+1] is normalised by the next
-// step's sine transform (ProbState::vscale).  When the problem's cycle ends,
-// `flag` (host-visible) receives `tag`.
-__global__ void __launch_bounds__(kBlock) k_mgs_finish(const KryTask* __restrict__ tasks, int ntasks,
-                                                        int j, int* flags, int tag) {
-  __shared__ double red[4];
-  __shared__ double col[122];
-  __shared__ double cs[121], sn[121];
-  const KryTask& tk = tasks[blockIdx.x];
-  ProbState* st = tk.st;
-  if (st->cycle_done) return;
-  const int m1 = tk.m + 1;
-  for (int i = threadIdx.x; i <= j; i += kBlock) col[i] = tk.H[i + j * m1];
-  for (int i = threadIdx.x; i < j; i += kBlock) {
-    cs[i] = tk.cs[i];
-    sn[i] = tk.sn[i];
-  }
-  const double nrm2 = sum_partials(tk.partials + (size_t)kPartNorm * tk.P, tk.P, red);
-  if (threadIdx.x != 0) return;
-  const double hn = sqrt(nrm2);
-  const bool breakdown = !(hn > 1e-14 * st->beta);
-  col[j + 1] = hn;
-  st->last_hn = hn;
-  st->vscale = breakdown ? 1.0 : 1.0 / hn;
-  for (int i = 0; i < j; ++i) {
-    const double a = col[i], c2 = col[i + 1];
-    col[i] = cs[i] * a + sn[i] * c2;
-    col[i + 1] = -sn[i] * a + cs[i] * c2;
-  }
-  const double a = col[j];
-  const double rho = hypot(a, hn);
-  double c = 1.0, s = 0.0;
-  if (rho > 0.0) {
-    c = a / rho;
-    s = hn / rho;
-  }
-  tk.cs[j] = c;
-  tk.sn[j] = s;
-  col[j] = rho;
-  col[j + 1] = 0.0;
-  for (int i = 0; i <= j + 1; ++i) tk.H[i + j * m1] = col[i];
-  const double gj = tk.g[j];
-  tk.g[j + 1] = -s * gj;
-  tk.g[j] = c * gj;
-  st->j_done = j + 1;
-  st->iterations += 1;
-  const double est = fabs(tk.g[j + 1]);
-  if (!(est > st->tol_eff * st->fnorm) || breakdown || j + 1 == tk.m) {
-    st->cycle_done = 1;
-    if (flags) {
-      flags[blockIdx.x] = tag;
-      __threadfence_system();
-    }
-  }
+  if (threadIdx.x == 0) st_agent(tk.partials + (size_t)kPartNorm * tk.P + b, s);
+  if (last_block_of_problem(&tk.st->ctr_upd, tk.P, &lastf))
+    mgs_finish_block(tk, j, flags, tag, red, col, cs, sn);
 }
 
 // v *= 1 / h_{j+1,j} for the kernel-level Arnoldi entry point.
@@ -1081,10 +1112,12 @@ void launch_tridiag(bool fp32, const TriTask* tasks, int ntasks, int nblocks, in
 
 TriConfig tri_config(bool fp32, int max_rows) {
   // register segments of at most 16 (FP64) or 32 (FP32) rows; up to 1024
-  // threads per block: 64 modes x 16 segments, 32 x 32 or 16 x 64
+  // threads per block: 16 modes x 64 segments, 32 x 32 or 64 x 16.  Fewest
+  // modes per block first: a problem's modes then spread over more blocks
+  // (16 modes x 8 bytes still read whole 128-byte lines per row).
   TriConfig c{false, 0, 0, 0};
   const int lsmax = fp32 ? 32 : 16;
-  for (int mpb : {64, 32, 16}) {
+  for (int mpb : {16, 32, 64}) {
     const int segmax = 1024 / mpb;
     for (int ls = 8; ls <= lsmax; ls *= 2) {
       const int S = (max_rows + ls - 1) / ls;
@@ -1162,24 +1195,22 @@ void launch_operator(int mode, const OpTask* tasks, int ntasks, int nblocks, int
     FDS_LAUNCH(k_operator<1>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
 }
 
+// LDS of the Gram step of column j: dots (2 (j+1)), coefficients (j+1) and
+// the strict upper triangle of the old Gram columns (j (j+1) / 2).
+static size_t gram_solve_smem(int j) {
+  return sizeof(double) * (3 * (size_t)(j + 1) + (size_t)j * (j + 1) / 2);
+}
+
+// (at most 60000 bytes for j < 120, below the 64 KiB default limit)
 void launch_gram_dots(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s) {
   if (nblocks <= 0) return;
-  FDS_LAUNCH(k_gram_dots, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j);
+  FDS_LAUNCH(k_gram_dots, dim3(nblocks), dim3(kBlock), gram_solve_smem(j), s, tasks, ntasks, j);
 }
 
-void launch_gram_solve(const KryTask* tasks, int ntasks, int j, hipStream_t s) {
-  if (ntasks <= 0) return;
-  FDS_LAUNCH(k_gram_solve, dim3(ntasks), dim3(kBlock), 0, s, tasks, ntasks, j);
-}
-
-void launch_gram_update(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s) {
+void launch_gram_update(const KryTask* tasks, int ntasks, int nblocks, int j, int* flags, int tag,
+                        hipStream_t s) {
   if (nblocks <= 0) return;
-  FDS_LAUNCH(k_gram_update, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j);
-}
-
-void launch_mgs_finish(const KryTask* tasks, int ntasks, int j, int* flags, int tag, hipStream_t s) {
-  if (ntasks <= 0) return;
-  FDS_LAUNCH(k_mgs_finish, dim3(ntasks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
+  FDS_LAUNCH(k_gram_update, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
 }
 
 void launch_scale_newest(const KryTask* tasks, int j, int nblocks, hipStream_t s) {

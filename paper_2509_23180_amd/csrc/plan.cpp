@@ -195,6 +195,11 @@ fds_plan* create_plan(const fds_rect* rects, int nrect, double h, double kappa,
 
     TableCache& tc = TableCache::get();
     p->fft_c = tc.fft(p->nx);
+    // settle the transform variants now (the autotuner measures on first use)
+    for (int len : {p->nx, p->ny}) {
+      (void)dst_choice(len, false);
+      (void)dst_choice(len, true);
+    }
     p->modes_c = tc.modes(p->nx, p->ny, h, kappa);
     for (int r = 0; r < nrect; ++r) {
       if (r == c) continue;

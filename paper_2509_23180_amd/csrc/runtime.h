@@ -158,6 +158,16 @@ struct DstChoice {
   int threads;   // workgroup size
 };
 DstChoice dst_choice(int n, bool fp32);
+// One variant ("wave": the wave FFT where its schedule allows, else the
+// workgroup FFT; "fft": the workgroup FFT; "gemm": the matrix-core product
+// for n <= 1024, else as "wave").
+DstChoice dst_choice_variant(int n, bool fp32, const std::string& mode);
+// Autotuner (tune.cpp): on the first request for (device, n, precision) every
+// variant runs on a batch of synthetic rows and the fastest is kept.
+DstChoice dst_tuned_choice(int n, bool fp32);
+// One launch of the row transform of a single task record (copied to `keep`).
+void launch_one_dst(DstKind kind, const DstChoice& ch, const DstTask& t0, hipStream_t s,
+                    DevBuf& keep);
 
 // ---------------------------------------------------------------- plan
 enum RectKind { RK_CENTRE = 0, RK_N = 1, RK_S = 2, RK_E = 3, RK_W = 4 };

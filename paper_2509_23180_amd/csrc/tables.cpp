@@ -200,25 +200,30 @@ WaveCfg dst_wave_config(int n, bool fp32) {
   return c;
 }
 
-static DstChoice dst_choice_compute(int n, bool fp32, const std::string& mode);
-
 DstChoice dst_choice(int n, bool fp32) {
-  // memoised per (algorithm setting, n, precision): task-list construction
-  // asks for every transform of every problem
+  // FDS_DST_ALGO=wave|fft|gemm pins a variant; otherwise the autotuner's
+  // measured choice (FDS_DST_TUNE=0: the static preference, wave where
+  // possible).  Memoised per (setting, n, precision): task-list construction
+  // asks for every transform of every problem.
   static std::mutex mu;
   static std::map<std::tuple<std::string, int, bool>, DstChoice> memo;
   const char* env = std::getenv("FDS_DST_ALGO");
-  const std::string mode = env ? env : "auto";
+  std::string mode = env ? env : "auto";
+  if (mode == "auto") {
+    const char* t = std::getenv("FDS_DST_TUNE");
+    if (!(t && std::string(t) == "0")) return dst_tuned_choice(n, fp32);
+    mode = "wave";
+  }
   std::lock_guard<std::mutex> lk(mu);
   auto key = std::make_tuple(mode, n, fp32);
   auto it = memo.find(key);
   if (it != memo.end()) return it->second;
-  const DstChoice c = dst_choice_compute(n, fp32, mode);
+  const DstChoice c = dst_choice_variant(n, fp32, mode);
   memo[key] = c;
   return c;
 }
 
-static DstChoice dst_choice_compute(int n, bool fp32, const std::string& mode) {
+DstChoice dst_choice_variant(int n, bool fp32, const std::string& mode) {
   DstChoice c{false, 1, 4, 0, 0, 0, kBlock};
   if (mode == "gemm" && n <= kGemmMaxN) {
     const int np = (n + 63) / 64 * 64;
@@ -229,8 +234,6 @@ static DstChoice dst_choice_compute(int n, bool fp32, const std::string& mode) {
     c.smem = gemm_smem_bytes(n, fp32, c.rt);
     return c;
   }
-  // the dense-matrix variant measured slower than the LDS FFTs at n = 256
-  // and 1024, so the automatic choice never takes it
   if (mode != "fft") {
     const WaveCfg w = dst_wave_config(n, fp32);
     if (w.E) {

@@ -1,0 +1,136 @@
+// Autotuner for the row sine transform.
+//
+// Which implementation of the DST-I is fastest depends on the length (the
+// factorisation of n + 1 decides between mixed-radix, Rader and Bluestein
+// FFTs and their LDS traffic; short rows favour the dense product on the
+// matrix cores) and on the precision.  On the first request for a (device,
+// n, precision) each available variant transforms a synthetic batch of rows
+// (about 8 MB of data) a few times, timed with HIP events on a private
+// stream, and the fastest is kept for the rest of the process.  Plans ask at
+// creation time, so a solve never waits for tuning.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "runtime.h"
+
+namespace fds {
+
+void launch_one_dst(DstKind kind, const DstChoice& ch, const DstTask& t0, hipStream_t s,
+                    DevBuf& keep) {
+  const bool fp32 = kind != DstKind::D_D;
+  DstTask t = t0;
+  t.rpb = ch.gemm ? 1 : ch.rows_per_block;
+  t.tw_lds = (ch.gemm || ch.wave_e) ? 0 : (dst_twiddles_in_lds(t.n, fp32) ? 1 : 0);
+  if (ch.wave_e) {
+    t.wd = TableCache::get().wave_desc(t.fft, fp32);
+    t.io_f32 = dst_io_flags(kind);
+  }
+  t.block_begin = 0;
+  keep.alloc(sizeof(DstTask));
+  FDS_HIP(hipMemcpyAsync(keep.get(), &t, sizeof(t), hipMemcpyHostToDevice, s));
+  const int nb = (t.rows + ch.rows_per_block - 1) / ch.rows_per_block;
+  Timing::begin(0, s);
+  if (ch.gemm) launch_dst_gemm(kind, ch.rt, ch.ct, keep.as<DstTask>(), 1, nb, ch.smem, 0, s);
+  else if (ch.wave_e)
+    launch_dst_wave(kind, ch.wave_e, keep.as<DstTask>(), 1, nb, ch.threads, ch.smem, 0, s);
+  else launch_dst(kind, keep.as<DstTask>(), 1, nb, ch.smem, 0, s);
+  Timing::end(0, s);
+}
+
+namespace {
+
+bool same(const DstChoice& a, const DstChoice& b) {
+  return a.gemm == b.gemm && a.wave_e == b.wave_e && a.rt == b.rt && a.ct == b.ct &&
+         a.threads == b.threads && a.rows_per_block == b.rows_per_block;
+}
+
+// Milliseconds per launch of one variant over `rows` rows of length n.
+double time_variant(const DstChoice& ch, int n, bool fp32, int rows, void* in, void* out,
+                    hipStream_t s) {
+  DstTask t{};
+  t.in = in; t.out = out; t.in_rs = n; t.out_rs = n; t.in_cs = 1; t.out_cs = 1;
+  t.rows = rows; t.n = n; t.scale = 1.0; t.fft = TableCache::get().fft(n)->dev;
+  const DstKind kind = fp32 ? DstKind::F_F : DstKind::D_D;
+  DevBuf keep;
+  launch_one_dst(kind, ch, t, s, keep);   // warm-up (code load, LDS opt-in)
+  hipEvent_t a, b;
+  FDS_HIP(hipEventCreate(&a));
+  FDS_HIP(hipEventCreate(&b));
+  const int reps = 3;
+  FDS_HIP(hipEventRecord(a, s));
+  for (int r = 0; r < reps; ++r) {
+    DevBuf k;
+    launch_one_dst(kind, ch, t, s, k);
+    FDS_HIP(hipStreamSynchronize(s));   // k is released after its launch finished
+  }
+  FDS_HIP(hipEventRecord(b, s));
+  FDS_HIP(hipEventSynchronize(b));
+  float ms = 0;
+  FDS_HIP(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  FDS_HIP(hipGetLastError());
+  return ms / reps;
+}
+
+}  // namespace
+
+DstChoice dst_tuned_choice(int n, bool fp32) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, bool>, DstChoice> tuned;
+  int dev = 0;
+  FDS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_tuple(dev, n, fp32);
+  auto it = tuned.find(key);
+  if (it != tuned.end()) return it->second;
+
+  std::vector<DstChoice> cand;
+  for (const char* mode : {"wave", "fft", "gemm"}) {
+    const DstChoice c = dst_choice_variant(n, fp32, mode);
+    bool dup = false;
+    for (const DstChoice& o : cand) dup |= same(o, c);
+    if (!dup) cand.push_back(c);
+  }
+  DstChoice best = cand[0];
+  if (cand.size() > 1) {
+    const size_t w = fp32 ? 4 : 8;
+    // batched use: several thousand rows per launch (about 32 MB of data)
+    const int rows = std::max(256, std::min(65536, (1 << 23) / std::max(n, 1)));
+    hipStream_t s;
+    FDS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    {
+      DevBuf in((size_t)rows * n * w), out((size_t)rows * n * w);
+      FDS_HIP(hipMemsetAsync(in.get(), 0, in.size(), s));
+      double tbest = -1;
+      const bool log = std::getenv("FDS_TUNE_LOG") != nullptr;
+      for (size_t i = 0; i < cand.size(); ++i) {
+        double ms;
+        try {
+          ms = time_variant(cand[i], n, fp32, rows, in.get(), out.get(), s);
+        } catch (const Error&) {
+          continue;   // e.g. a variant whose LDS need exceeds the CU
+        }
+        if (log)
+          std::fprintf(stderr, "[fds tune] n=%d %s rows=%d %s: %.1f us\n", n, fp32 ? "fp32" : "fp64",
+                       rows, cand[i].gemm ? "gemm" : cand[i].wave_e ? "wave" : "fft", ms * 1e3);
+        if (tbest < 0 || ms < tbest) {
+          tbest = ms;
+          best = cand[i];
+        }
+      }
+      FDS_HIP(hipStreamSynchronize(s));
+    }
+    (void)hipStreamDestroy(s);
+  }
+  tuned[key] = best;
+  return best;
+}
+
+}  // namespace fds
