@@ -367,7 +367,7 @@ fds_status fds_k_arnoldi_mgs(double* V, int32_t k, int64_t len, double* h, void*
     const int P = (int)((len + kVecPerBlock - 1) / kVecPerBlock);
     const size_t small = (size_t)(m + 1) * m + 4 * (size_t)m + 2;
     const size_t gram = (size_t)(m + 1) * (m + 1) + (m + 1);
-    const size_t parts = (size_t)(2 * (m + 1) + 4) * P;
+    const size_t parts = kry_partials_len(m, P);
     DevBuf mem(8 * (small + gram + parts) + 1024 + 2 * sizeof(KryTask));
     FDS_HIP(hipMemsetAsync(mem.get(), 0, mem.size(), s));
     double* H = mem.as<double>(0);

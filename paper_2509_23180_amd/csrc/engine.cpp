@@ -183,7 +183,7 @@ SlotLayout layout_of(const fds_plan* p, int m, int precision) {
   L.zbuf = flex ? 0 : take(8 * Nc);
   L.lines = take(8 * 4 * (size_t)Lmax);
   L.small = take(8 * ((size_t)(m + 1) * m + 4 * (size_t)m + 2));
-  L.partials = take(8 * (size_t)(2 * (m + 1) + 4) * P);
+  L.partials = take(8 * kry_partials_len(m, P));
   L.gram = take(8 * ((size_t)(m + 1) * (m + 1) + (m + 1)));
   L.zcols = take(8 * 2 * (size_t)p->ny);
   L.respart = take(8 * 2 * (size_t)res_blocks_of(p));

@@ -538,6 +538,45 @@ __device__ __forceinline__ double ld_agent(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Row sums out[d] = sum_{q < ncols} src[d * ld + q] for d < D <= blockDim.x,
+// with the whole block: each row is cut into C = blockDim.x / D contiguous
+// chunks whose loads are issued eight at a time, and the chunk sums are added
+// in chunk order (a fixed order).  scratch holds blockDim.x doubles; out is
+// in LDS and is complete when the function returns.
+__device__ void reduce_rows(const double* src, long long ld, int D, int ncols, double* scratch,
+                            double* out) {
+  const int T = blockDim.x;
+  int C = T / D;
+  if (C > ncols) C = ncols;
+  if (C < 1) C = 1;
+  const int chunk = (ncols + C - 1) / C;
+  const int e = threadIdx.x;
+  double s = 0.0;
+  if (e < D * C) {
+    const int d = e / C, c = e - d * C;
+    const int q0 = c * chunk;
+    const int q1 = min(ncols, q0 + chunk);
+    const double* p = src + (long long)d * ld;
+    int q = q0;
+    for (; q + 8 <= q1; q += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = ld_agent(p + q + u);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; q < q1; ++q) s += ld_agent(p + q);
+  }
+  scratch[e] = s;
+  __syncthreads();
+  if (e < D) {
+    double t = 0.0;
+    for (int c = 0; c < C; ++c) t += scratch[e * C + c];
+    out[e] = t;
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ bool last_block_of_problem(int* ctr, int nblocks, int* sflag) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
@@ -551,23 +590,19 @@ __device__ __forceinline__ bool last_block_of_problem(int* ctr, int nblocks, int
   return *sflag != 0;
 }
 
-// Gram column and MGS coefficients of step j from the dot partials:
-// G[:, j] = <v_i, v_j>, a_i = <w, v_i>, h_i = a_i - sum_{l<i} h_l G_li.
-// The recurrence runs in LDS: after h_l is final every i > l subtracts
-// h_l G_li in parallel.  lds: 3 (j+1) + j (j+1)/2 doubles.
-__device__ void gram_solve_block(const KryTask& tk, int j, double* lds) {
+// Gram column and MGS coefficients of step j from the dot sums (row t of
+// `src`, ncols entries at src + t ld): G[:, j] = <v_i, v_j>, a_i = <w, v_i>,
+// h_i = a_i - sum_{l<i} h_l G_li.  The recurrence runs in LDS: after h_l is
+// final every i > l subtracts h_l G_li in parallel.
+// lds: 3 (j+1) + j (j+1)/2 doubles; scratch: blockDim.x doubles.
+__device__ void gram_solve_block(const KryTask& tk, int j, double* lds, const double* src, long long ld,
+                                 int ncols, double* scratch) {
   const int nd = j + 1;
-  const int P = tk.P;
   const int m1 = tk.m + 1;
   double* dots = lds;                 // 2 nd
   double* a = dots + 2 * nd;          // nd
   double* Gt = a + nd;                // column i of the strict upper triangle at i (i - 1) / 2
-  for (int t = threadIdx.x; t < 2 * nd; t += blockDim.x) {
-    const double* p = tk.partials + (size_t)(kPartDots + t) * P;
-    double s = 0.0;
-    for (int q = 0; q < P; ++q) s += ld_agent(p + q);
-    dots[t] = s;
-  }
+  reduce_rows(src, ld, 2 * nd, ncols, scratch, dots);
   const int ntri = nd * (nd - 1) / 2;
   for (int e = threadIdx.x; e < ntri; e += blockDim.x) {
     int i = (int)((1.0 + sqrt(1.0 + 8.0 * e)) * 0.5);
@@ -645,8 +680,26 @@ __global__ void __launch_bounds__(kBlock) k_gram_dots(const KryTask* __restrict_
     const double s = (red[row][0] + red[row][1]) + (red[row][2] + red[row][3]);
     st_agent(tk.partials + (size_t)(kPartDots + t) * tk.P + b, s);
   }
-  if (last_block_of_problem(&tk.st->ctr_dots, tk.P, &lastf))
-    gram_solve_block(tk, j, reinterpret_cast<double*>(smem_raw));
+  // Two-level fixed-order reduction: the last block of each group of
+  // kGramGroup blocks sums the group's partials; the last group to finish
+  // sums the group sums and solves.  One group: the partials directly.
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  double* scratch = &red[0][0];
+  const int P = tk.P;
+  const double* part = tk.partials + (size_t)kPartDots * P;
+  const int ng = gram_groups(P);
+  if (ng == 1) {
+    if (last_block_of_problem(&tk.st->ctr_dots, P, &lastf)) gram_solve_block(tk, j, lds, part, P, P, scratch);
+    return;
+  }
+  double* gsum = tk.partials + (size_t)(2 * (tk.m + 1) + 4) * P;
+  int* gctr = reinterpret_cast<int*>(gsum + (size_t)2 * (tk.m + 1) * ng);
+  const int g = b / kGramGroup;
+  const int gb = min(kGramGroup, P - g * kGramGroup);
+  if (!last_block_of_problem(gctr + g, gb, &lastf)) return;
+  reduce_rows(part + g * kGramGroup, P, 2 * nd, gb, scratch, lds);
+  for (int t = threadIdx.x; t < 2 * nd; t += kBlock) st_agent(gsum + (size_t)t * ng + g, lds[t]);
+  if (last_block_of_problem(&tk.st->ctr_dots, ng, &lastf)) gram_solve_block(tk, j, lds, gsum, ng, ng, scratch);
 }
 
 // h_{j+1,j} = ||w||, Givens update of column j and the convergence test on
@@ -654,7 +707,7 @@ __global__ void __launch_bounds__(kBlock) k_gram_dots(const KryTask* __restrict_
 // the next step's sine transform (ProbState::vscale).  When the problem's
 // cycle ends, its host-visible flag receives `tag`.
 __device__ void mgs_finish_block(const KryTask& tk, int j, int* flags, int tag, double* red,
-                                 double* col, double* cs, double* sn) {
+                                 double* col, double* cs, double* sn, double* scratch) {
   ProbState* st = tk.st;
   const int m1 = tk.m + 1;
   for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = tk.H[i + j * m1];
@@ -662,9 +715,8 @@ __device__ void mgs_finish_block(const KryTask& tk, int j, int* flags, int tag, 
     cs[i] = tk.cs[i];
     sn[i] = tk.sn[i];
   }
-  double acc = 0.0;
-  for (int q = threadIdx.x; q < tk.P; q += blockDim.x) acc += ld_agent(tk.partials + (size_t)kPartNorm * tk.P + q);
-  const double nrm2 = block_sum(acc, red);
+  reduce_rows(tk.partials + (size_t)kPartNorm * tk.P, tk.P, 1, tk.P, scratch, red);
+  const double nrm2 = red[0];
   if (threadIdx.x != 0) return;
   const double hn = sqrt(nrm2);
   const bool breakdown = !(hn > 1e-14 * st->beta);
@@ -713,6 +765,7 @@ __global__ void __launch_bounds__(kBlock) k_gram_update(const KryTask* __restric
   __shared__ double hs[121];
   __shared__ double col[122];
   __shared__ double cs[121], sn[121];
+  __shared__ double scratch[kBlock];
   const KryTask& tk = tasks[find_task(tasks, ntasks, &slot)];
   if (tk.st->cycle_done) return;
   for (int i = threadIdx.x; i <= j; i += kBlock) hs[i] = tk.hv[i];
@@ -774,7 +827,7 @@ __global__ void __launch_bounds__(kBlock) k_gram_update(const KryTask* __restric
   const double s = block_sum(nrm, red);
   if (threadIdx.x == 0) st_agent(tk.partials + (size_t)kPartNorm * tk.P + b, s);
   if (last_block_of_problem(&tk.st->ctr_upd, tk.P, &lastf))
-    mgs_finish_block(tk, j, flags, tag, red, col, cs, sn);
+    mgs_finish_block(tk, j, flags, tag, red, col, cs, sn, scratch);
 }
 
 // v *= 1 / h_{j+1,j} for the kernel-level Arnoldi entry point.
@@ -843,6 +896,13 @@ __global__ void __launch_bounds__(kBlock) k_restart(const KryTask* __restrict__ 
   const KryTask& tk = tasks[blockIdx.x];
   ProbState* st = tk.st;
   if (st->finished) return;
+  if (initial) {   // the Gram reduction's group counters start at zero
+    const int ng = gram_groups(tk.P);
+    if (ng > 1) {
+      int* gctr = reinterpret_cast<int*>(tk.partials + kry_partials_len(tk.m, tk.P) - ng);
+      for (int g = threadIdx.x; g < ng; g += kBlock) gctr[g] = 0;
+    }
+  }
   const double r2 = sum_partials(tk.partials + (size_t)kPartRes * tk.P, tk.P, red);
   const double x2 = sum_partials(tk.partials + (size_t)(kPartRes + 1) * tk.P, tk.P, red);
   if (threadIdx.x != 0) return;

@@ -128,6 +128,9 @@ bool fixed_radices(int L);
 // Stockham length L it runs, and the LDS entries per buffer.
 struct FftShape { int kind; int L; int lds_len; };
 FftShape fft_shape(int n);
+// Schedule of the wave-parallel transform (fft_shape when it has register
+// butterflies only, else a Rader or Bluestein schedule that has).
+FftShape wave_shape(int n);
 // Threads per row for the workgroup-wide transform of length n (power of
 // two, 32..256).
 int dst_threads_per_row(int n);

@@ -130,7 +130,7 @@ static int wave_twiddle_len(const std::vector<int>& rad) {
   return t;
 }
 
-int wave_lanes(int n) {
+static int lanes_for(int L) {
   // lanes per row: as many as keep every lane of a radix-4 pass busy (one
   // wavefront per row from L = 256 on), so short batches still spread over
   // many wavefronts; FDS_DST_G overrides (16, 32, 64) for measurements
@@ -141,11 +141,52 @@ int wave_lanes(int n) {
     return (v == 16 || v == 32 || v == 64) ? v : 0;
   }();
   if (forced) return forced;
-  const int L = fft_shape(n).L;
   int G = 16;
   while (G < 64 && 4 * (2 * G) <= L) G *= 2;
   return G;
 }
+
+// Register budget (complex entries per lane) of a wave schedule, or 0.
+static int wave_need(int n, int L, int G, const std::vector<int>& rad) {
+  if (rad.empty()) return 0;
+  int need = (n + G - 1) / G;  // row elements per lane
+  for (int R : rad) need = std::max(need, (L / R + G - 1) / G * R);
+  return need;
+}
+
+FftShape wave_shape(int n) {
+  // The workgroup schedule when its radices have register butterflies;
+  // otherwise Rader (N prime, N - 1 5-smooth) or Bluestein over the smallest
+  // 5-smooth length >= 2N - 1, whichever is wave-schedulable and cheaper.
+  const int N = n + 1;
+  const FftShape s0 = fft_shape(n);
+  auto ok = [&](const FftShape& s) {
+    const int G = lanes_for(s.L);
+    const int need = wave_need(n, s.L, G, wave_radices(s.L, G));
+    return need > 0 && need <= 32;
+  };
+  if (ok(s0)) return s0;
+  FftShape best{FFT_MIXED, 0, 0};
+  double cost = 0.0;
+  if (N > 7 && is_prime(N)) {
+    const FftShape r{FFT_RADER, N - 1, N};
+    if (ok(r)) { best = r; cost = 2.0 * stockham_cost(N - 1) + 3.0 * N; }
+  }
+  int M = 2 * N - 1;
+  auto smooth = [](int v) {
+    for (int p : {2, 3, 5}) while (v % p == 0) v /= p;
+    return v == 1;
+  };
+  while (!smooth(M)) ++M;
+  const FftShape b{FFT_BLUESTEIN, M, M};
+  if (N > 8 && ok(b)) {
+    const double c = 2.0 * stockham_cost(M) + 4.0 * M;
+    if (best.L == 0 || c < cost) best = b;
+  }
+  return best.L ? best : s0;
+}
+
+int wave_lanes(int n) { return lanes_for(wave_shape(n).L); }
 
 std::vector<int> wave_radices(int L, int G) {
   // powers of two in passes as long as every pass keeps L/R >= G
@@ -167,12 +208,11 @@ std::vector<int> wave_radices(int L, int G) {
 
 WaveCfg dst_wave_config(int n, bool fp32) {
   WaveCfg c{0, 0, 0, 0, 0};
-  const FftShape shp = fft_shape(n);
-  const int G = wave_lanes(n);
+  const FftShape shp = wave_shape(n);
+  const int G = lanes_for(shp.L);
   const std::vector<int> rad = wave_radices(shp.L, G);
-  if (rad.empty()) return c;
-  int need = (n + G - 1) / G;  // row elements per lane
-  for (int R : rad) need = std::max(need, (shp.L / R + G - 1) / G * R);
+  const int need = wave_need(n, shp.L, G, rad);
+  if (need == 0) return c;
   for (int e : {4, 8, 16, 32, 64})
     if ((e <= 32 || fp32) && need <= e) { c.E = e; break; }
   if (!c.E) return c;
@@ -330,6 +370,49 @@ static int primitive_root(int p) {
   throw Error(FDS_E_UNSUPPORTED, "no primitive root");
 }
 
+// Convolution kernel (DFT of the Rader sequence or of the Bluestein chirp,
+// scaled by 1/L), chirp and Rader permutations of one FFT schedule.
+struct ShapeTables {
+  std::vector<cld> kern, chirp;
+  std::vector<int> pin, pout;
+};
+
+static ShapeTables shape_tables(const FftShape& shp, int N) {
+  ShapeTables st;
+  const int L = shp.L;
+  std::vector<cld> kern;
+  if (shp.kind == FFT_RADER) {
+    const int g = primitive_root(N);
+    long long gp = 1, gi = 1;
+    long long ginv = 1;
+    for (int e = 0; e < N - 2; ++e) ginv = ginv * g % N;  // g^{N-2} = g^{-1}
+    std::vector<cld> b(L);
+    st.pin.resize(L);
+    st.pout.resize(L);
+    for (int q = 0; q < L; ++q) {
+      st.pin[q] = (int)gi;
+      st.pout[q] = (int)gp;
+      b[q] = unit_root(gp, N);
+      gi = gi * ginv % N;
+      gp = gp * g % N;
+    }
+    kern = host_dft(b);
+  } else if (shp.kind == FFT_BLUESTEIN) {
+    std::vector<cld> h(L, cld(0, 0));
+    st.chirp.resize(N);
+    for (int j = 0; j < N; ++j) {
+      // exp(-i pi j^2/N) = exp(-2 pi i (j^2 mod 2N) / (2N))
+      const cld c = unit_root((long long)j * j % (2LL * N), 2LL * N);
+      st.chirp[j] = c;
+      h[j] = std::conj(c);
+      if (j > 0) h[L - j] = std::conj(c);
+    }
+    kern = host_dft(h);
+  }
+  for (const cld& v : kern) st.kern.push_back(v / (long double)L);
+  return st;
+}
+
 std::shared_ptr<FftTable> TableCache::fft(int n) {
   const int dev = current_device();
   std::lock_guard<std::mutex> lk(mu_);
@@ -354,10 +437,13 @@ std::shared_ptr<FftTable> TableCache::fft(int n) {
   const int np = n <= kGemmMaxN ? (n + 63) / 64 * 64 : 0;
   const size_t o_s64 = take(sizeof(double) * std::max((size_t)np * np, (size_t)1));
   const size_t o_s32 = take(sizeof(float) * std::max((size_t)np * np, (size_t)1));
-  const std::vector<int> wrad = wave_radices(L, wave_lanes(n));
+  // the wave-parallel transform may run another schedule (wave_shape)
+  const FftShape wshp = wave_shape(n);
+  const int wL = wshp.L;
+  const std::vector<int> wrad = wave_radices(wL, lanes_for(wL));
   const int twl = wave_twiddle_len(wrad);
-  const WaveLayout wl64 = wave_layout<double>(shp.kind, N, L, shp.lds_len, twl);
-  const WaveLayout wl32 = wave_layout<float>(shp.kind, N, L, shp.lds_len, twl);
+  const WaveLayout wl64 = wave_layout<double>(wshp.kind, N, wL, wshp.lds_len, twl);
+  const WaveLayout wl32 = wave_layout<float>(wshp.kind, N, wL, wshp.lds_len, twl);
   const size_t o_w64 = take((size_t)wl64.rows), o_w32 = take((size_t)wl32.rows);
   const size_t total = o;
   std::vector<unsigned char> host(total, 0);
@@ -376,42 +462,24 @@ std::shared_ptr<FftTable> TableCache::fft(int n) {
     p64[k] = double2{c, s};
     p32[k] = float2{(float)c, (float)s};
   }
-  std::vector<cld> kern;
+  const ShapeTables stab = shape_tables(shp, N);
   if (rader) {
-    const int g = primitive_root(N);
-    long long gp = 1, gi = 1;
-    long long ginv = 1;
-    for (int e = 0; e < N - 2; ++e) ginv = ginv * g % N;  // g^{N-2} = g^{-1}
-    auto* pin = reinterpret_cast<int*>(host.data() + o_pin);
-    auto* pout = reinterpret_cast<int*>(host.data() + o_pout);
-    std::vector<cld> b(L);
-    for (int q = 0; q < L; ++q) {
-      pin[q] = (int)gi;
-      pout[q] = (int)gp;
-      b[q] = unit_root(gp, N);
-      gi = gi * ginv % N;
-      gp = gp * g % N;
-    }
-    kern = host_dft(b);
-  } else if (blue) {
+    std::memcpy(host.data() + o_pin, stab.pin.data(), sizeof(int) * L);
+    std::memcpy(host.data() + o_pout, stab.pout.data(), sizeof(int) * L);
+  }
+  if (blue) {
     auto* c64 = reinterpret_cast<double2*>(host.data() + o_c64);
     auto* c32 = reinterpret_cast<float2*>(host.data() + o_c32);
-    std::vector<cld> h(L, cld(0, 0));
     for (int j = 0; j < N; ++j) {
-      // exp(-i pi j^2/N) = exp(-2 pi i (j^2 mod 2N) / (2N))
-      const cld c = unit_root((long long)j * j % (2LL * N), 2LL * N);
-      c64[j] = double2{(double)c.real(), (double)c.imag()};
-      c32[j] = float2{(float)c.real(), (float)c.imag()};
-      h[j] = std::conj(c);
-      if (j > 0) h[L - j] = std::conj(c);
+      c64[j] = double2{(double)stab.chirp[j].real(), (double)stab.chirp[j].imag()};
+      c32[j] = float2{(float)stab.chirp[j].real(), (float)stab.chirp[j].imag()};
     }
-    kern = host_dft(h);
   }
-  if (!kern.empty()) {
+  if (!stab.kern.empty()) {
     auto* k64 = reinterpret_cast<double2*>(host.data() + o_k64);
     auto* k32 = reinterpret_cast<float2*>(host.data() + o_k32);
     for (int q = 0; q < L; ++q) {
-      const cld v = kern[q] / (long double)L;
+      const cld v = stab.kern[q];
       k64[q] = double2{(double)v.real(), (double)v.imag()};
       k32[q] = float2{(float)v.real(), (float)v.imag()};
     }
@@ -430,41 +498,48 @@ std::shared_ptr<FftTable> TableCache::fft(int n) {
   }
   // table images in the LDS layout of the wave-parallel row transform
   {
-    // per-pass twiddles: pass (R, Ns) holds exp(-2 pi i r k stw / L) at
-    // (r-1) Ns + k, stw = L / (Ns R)
+    const ShapeTables wtab = (wshp.kind == shp.kind && wL == L) ? stab : shape_tables(wshp, N);
+    // per-pass twiddles: pass (R, Ns) holds exp(-2 pi i r k stw / wL) at
+    // (r-1) Ns + k, stw = wL / (Ns R)
     std::vector<cld> ptw;
     {
       int ns = 1;
       for (int R : wrad) {
-        const int stw = L / (ns * R);
+        const int stw = wL / (ns * R);
         for (int r = 1; r < R; ++r)
-          for (int k = 0; k < ns; ++k) ptw.push_back(unit_root((long long)r * k * stw, L));
+          for (int k = 0; k < ns; ++k) ptw.push_back(unit_root((long long)r * k * stw, wL));
         ns *= R;
       }
     }
-    auto put = [&](size_t base, const WaveLayout& w, size_t cb, size_t o_tw, size_t o_p, size_t o_k,
-                   size_t o_c) {
-      (void)o_tw;
-      unsigned char* img = host.data() + base;
-      for (size_t i = 0; i < ptw.size(); ++i) {
-        if (cb == sizeof(double2)) {
-          const double2 v{(double)ptw[i].real(), (double)ptw[i].imag()};
-          std::memcpy(img + w.tw + i * cb, &v, cb);
+    std::vector<cld> post(N + 1);
+    for (int k = 0; k <= N; ++k) {
+      const long double a = kPi * (long double)k / (long double)N;
+      post[k] = cld(cosl(a), sinl(a));
+    }
+    auto put_c = [](unsigned char* dst, const std::vector<cld>& v, bool f32) {
+      for (size_t i = 0; i < v.size(); ++i) {
+        if (f32) {
+          const float2 x{(float)v[i].real(), (float)v[i].imag()};
+          std::memcpy(dst + i * sizeof(x), &x, sizeof(x));
         } else {
-          const float2 v{(float)ptw[i].real(), (float)ptw[i].imag()};
-          std::memcpy(img + w.tw + i * cb, &v, cb);
+          const double2 x{(double)v[i].real(), (double)v[i].imag()};
+          std::memcpy(dst + i * sizeof(x), &x, sizeof(x));
         }
       }
-      std::memcpy(img + w.post, host.data() + o_p, cb * (N + 1));
-      if (rader || blue) std::memcpy(img + w.kern, host.data() + o_k, cb * L);
-      if (blue) std::memcpy(img + w.chirp, host.data() + o_c, cb * N);
-      if (rader) {
-        std::memcpy(img + w.pin, host.data() + o_pin, sizeof(int) * L);
-        std::memcpy(img + w.pout, host.data() + o_pout, sizeof(int) * L);
+    };
+    auto put = [&](size_t base, const WaveLayout& w, bool f32) {
+      unsigned char* img = host.data() + base;
+      put_c(img + w.tw, ptw, f32);
+      put_c(img + w.post, post, f32);
+      if (wshp.kind != FFT_MIXED) put_c(img + w.kern, wtab.kern, f32);
+      if (wshp.kind == FFT_BLUESTEIN) put_c(img + w.chirp, wtab.chirp, f32);
+      if (wshp.kind == FFT_RADER) {
+        std::memcpy(img + w.pin, wtab.pin.data(), sizeof(int) * wL);
+        std::memcpy(img + w.pout, wtab.pout.data(), sizeof(int) * wL);
       }
     };
-    put(o_w64, wl64, sizeof(double2), o_tw64, o_p64, o_k64, o_c64);
-    put(o_w32, wl32, sizeof(float2), o_tw32, o_p32, o_k32, o_c32);
+    put(o_w64, wl64, false);
+    put(o_w32, wl32, true);
   }
   t->mem.alloc(total);
   FftDesc d{};
@@ -472,9 +547,9 @@ std::shared_ptr<FftTable> TableCache::fft(int n) {
     WaveDesc& w = prec ? t->wave32 : t->wave64;
     w = WaveDesc{};
     w.N = N;
-    w.L = L;
-    w.W = shp.lds_len;
-    w.kind = shp.kind;
+    w.L = wL;
+    w.W = wshp.lds_len;
+    w.kind = wshp.kind;
     w.npass = (int)wrad.size();
     w.twlen = twl;
     w.img_chunks = (prec ? wl32.rows : wl64.rows) / 16;
