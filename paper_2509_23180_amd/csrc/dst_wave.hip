@@ -25,8 +25,13 @@ __device__ __forceinline__ void io_store(void* p, bool f32, long long i, T v) {
   else static_cast<double*>(p)[i] = double(v);
 }
 
-template <typename T, int E>
-__global__ void __launch_bounds__(256) k_dst_wave(const DstTask* __restrict__ tasks, int ntasks,
+//
+// BIG: one row per workgroup (G = blockDim.x = 128, 256 or 512 lanes) for rows
+// whose buffer and tables do not fit LDS together.  The passes are separated
+// by workgroup barriers, and the tables are read from the global image (it
+// stays resident in L2); LDS holds the row only.
+template <typename T, int E, bool BIG>
+__global__ void __launch_bounds__(BIG ? 512 : 256) k_dst_wave(const DstTask* __restrict__ tasks, int ntasks,
                                                   int jidx) {
   using C = C2<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -35,15 +40,16 @@ __global__ void __launch_bounds__(256) k_dst_wave(const DstTask* __restrict__ ta
   if (tk.skip && *tk.skip) return;
   const WaveDesc& d = tk.wd;
   const int N = d.N, n = tk.n;
-  const int rpb = tk.rpb;
+  const int rpb = BIG ? 1 : tk.rpb;
   const int G = (int)blockDim.x / rpb;
-  const int grp = (int)threadIdx.x / G;
+  const int grp = BIG ? 0 : (int)threadIdx.x / G;
   const int g = (int)threadIdx.x - grp * G;
   const int row = (blockIdx.x - tk.block_begin) * rpb + grp;
   const bool valid = row < tk.rows;
   const bool in32 = (tk.io_f32 & 1) != 0, out32 = (tk.io_f32 & 2) != 0;
   const WaveLayout lay = wave_layout<T>(d.kind, N, d.L, d.W, d.twlen);
-  C* buf = reinterpret_cast<C*>(smem_raw + lay.rows + grp * lay.row_bytes);
+  const unsigned char* tabs = BIG ? reinterpret_cast<const unsigned char*>(d.img) : smem_raw;
+  C* buf = reinterpret_cast<C*>(smem_raw + (BIG ? 0 : lay.rows + grp * lay.row_bytes));
   T* bz = reinterpret_cast<T*>(buf);
 
   // ---- issue the row loads, the normalisation factor and the table image
@@ -58,7 +64,7 @@ __global__ void __launch_bounds__(256) k_dst_wave(const DstTask* __restrict__ ta
     const int j = 1 + g + i * G;
     x[i] = io_load<T>(tk.in, in32, ioff + (long long)((j <= n ? j : 1) - 1) * ics);
   }
-  {
+  if constexpr (!BIG) {
     const uint4* img = d.img;
     const int nch = d.img_chunks, last = nch - 1;
     uint4* dst = reinterpret_cast<uint4*>(smem_raw);
@@ -103,11 +109,11 @@ __global__ void __launch_bounds__(256) k_dst_wave(const DstTask* __restrict__ ta
   __syncthreads();
   if (!valid) return;
 
-  wave_row_fft<T, E>(buf, d, smem_raw, lay, g, G);
+  wave_row_fft<T, E, BIG>(buf, d, tabs, lay, g, G);
 
   // ---- X_k = -(1/4)[Im(A+B) - (cos(pi k/N) Re(A-B) + sin(pi k/N) Im(A-B))],
   // A = C_k, B = conj(C_{N-k}); all LDS reads first, then the stores
-  const C* post = reinterpret_cast<const C*>(smem_raw + lay.post);
+  const auto post = tab_at<BIG, C>(tabs, lay.post);
   const long long ooff = (long long)jidx * tk.out_js + (long long)row * tk.out_rs;
   const T scale = T(tk.scale);
   const long long ocs = tk.out_cs;
@@ -138,38 +144,49 @@ __global__ void __launch_bounds__(256) k_dst_wave(const DstTask* __restrict__ ta
   }
 }
 
-template <typename T, int E>
+template <typename T, int E, bool BIG>
 static void launch_wave_e(const DstTask* tasks, int ntasks, int nblocks, int threads, size_t smem,
                           int jidx, hipStream_t s) {
   static size_t granted = 0;
-  ensure_smem(k_dst_wave<T, E>, smem, &granted);
-  FDS_LAUNCH((k_dst_wave<T, E>), dim3(nblocks), dim3(threads), smem, s, tasks, ntasks,
-                     jidx);
+  ensure_smem(k_dst_wave<T, E, BIG>, smem, &granted);
+  FDS_LAUNCH((k_dst_wave<T, E, BIG>), dim3(nblocks), dim3(threads), smem, s, tasks, ntasks, jidx);
 }
 
-void launch_dst_wave(DstKind kind, int E, const DstTask* tasks, int ntasks, int nblocks,
+template <typename T>
+static void launch_wave_t(int E, bool big, const DstTask* tasks, int ntasks, int nblocks, int threads,
+                          size_t smem, int jidx, hipStream_t s) {
+  if (big) {
+    switch (E) {
+      case 8: launch_wave_e<T, 8, true>(tasks, ntasks, nblocks, threads, smem, jidx, s); return;
+      case 16: launch_wave_e<T, 16, true>(tasks, ntasks, nblocks, threads, smem, jidx, s); return;
+      case 32: launch_wave_e<T, 32, true>(tasks, ntasks, nblocks, threads, smem, jidx, s); return;
+      default: break;
+    }
+  } else {
+    switch (E) {
+      case 4: launch_wave_e<T, 4, false>(tasks, ntasks, nblocks, threads, smem, jidx, s); return;
+      case 8: launch_wave_e<T, 8, false>(tasks, ntasks, nblocks, threads, smem, jidx, s); return;
+      case 16: launch_wave_e<T, 16, false>(tasks, ntasks, nblocks, threads, smem, jidx, s); return;
+      case 32: launch_wave_e<T, 32, false>(tasks, ntasks, nblocks, threads, smem, jidx, s); return;
+      case 64:
+        if constexpr (sizeof(T) == 4) {
+          launch_wave_e<T, 64, false>(tasks, ntasks, nblocks, threads, smem, jidx, s);
+          return;
+        }
+        break;
+      default: break;
+    }
+  }
+  throw Error(FDS_E_UNSUPPORTED, "wave transform: register budget out of range");
+}
+
+void launch_dst_wave(DstKind kind, int E, bool big, const DstTask* tasks, int ntasks, int nblocks,
                      int threads, size_t smem, int jidx, hipStream_t s) {
   if (nblocks <= 0) return;
-  if (threads != 64 && threads != 128 && threads != 256)
+  if (threads != 64 && threads != 128 && threads != 256 && !(big && threads == 512))
     throw Error(FDS_E_INVALID_ARG, "wave transform: bad workgroup size");
-  if (kind == DstKind::D_D) {
-    switch (E) {
-      case 4: launch_wave_e<double, 4>(tasks, ntasks, nblocks, threads, smem, jidx, s); break;
-      case 8: launch_wave_e<double, 8>(tasks, ntasks, nblocks, threads, smem, jidx, s); break;
-      case 16: launch_wave_e<double, 16>(tasks, ntasks, nblocks, threads, smem, jidx, s); break;
-      case 32: launch_wave_e<double, 32>(tasks, ntasks, nblocks, threads, smem, jidx, s); break;
-      default: throw Error(FDS_E_UNSUPPORTED, "wave transform: register budget out of range");
-    }
-    return;
-  }
-  switch (E) {
-    case 4: launch_wave_e<float, 4>(tasks, ntasks, nblocks, threads, smem, jidx, s); break;
-    case 8: launch_wave_e<float, 8>(tasks, ntasks, nblocks, threads, smem, jidx, s); break;
-    case 16: launch_wave_e<float, 16>(tasks, ntasks, nblocks, threads, smem, jidx, s); break;
-    case 32: launch_wave_e<float, 32>(tasks, ntasks, nblocks, threads, smem, jidx, s); break;
-    case 64: launch_wave_e<float, 64>(tasks, ntasks, nblocks, threads, smem, jidx, s); break;
-    default: throw Error(FDS_E_UNSUPPORTED, "wave transform: register budget out of range");
-  }
+  if (kind == DstKind::D_D) launch_wave_t<double>(E, big, tasks, ntasks, nblocks, threads, smem, jidx, s);
+  else launch_wave_t<float>(E, big, tasks, ntasks, nblocks, threads, smem, jidx, s);
 }
 
 }  // namespace fds

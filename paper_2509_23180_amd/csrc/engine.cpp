@@ -84,7 +84,7 @@ struct DstStage {
     Sub* sub = nullptr;
     for (Sub& s : subs)
       if (s.ch.gemm == ch.gemm && s.ch.rt == ch.rt && s.ch.ct == ch.ct &&
-          s.ch.wave_e == ch.wave_e && s.ch.threads == ch.threads)
+          s.ch.wave_e == ch.wave_e && s.ch.wave_big == ch.wave_big && s.ch.threads == ch.threads)
         sub = &s;
     if (!sub) {
       subs.push_back(Sub{ch, TaskList<DstTask>{}});
@@ -112,7 +112,7 @@ struct DstStage {
       if (s.ch.gemm)
         launch_dst_gemm(kind, s.ch.rt, s.ch.ct, s.tl.dev(), s.tl.n(), s.tl.nblocks, s.tl.smem, jidx, st);
       else if (s.ch.wave_e)
-        launch_dst_wave(kind, s.ch.wave_e, s.tl.dev(), s.tl.n(), s.tl.nblocks, s.ch.threads,
+        launch_dst_wave(kind, s.ch.wave_e, s.ch.wave_big != 0, s.tl.dev(), s.tl.n(), s.tl.nblocks, s.ch.threads,
                         s.tl.smem, jidx, st);
       else
         launch_dst(kind, s.tl.dev(), s.tl.n(), s.tl.nblocks, s.tl.smem, jidx, st);

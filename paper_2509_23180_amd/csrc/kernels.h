@@ -42,7 +42,7 @@ inline int dst_io_flags(DstKind k) {
   return ((k == DstKind::F_F || k == DstKind::F_D) ? 1 : 0) |
          ((k == DstKind::D_F || k == DstKind::F_F) ? 2 : 0);
 }
-void launch_dst_wave(DstKind kind, int E, const DstTask* tasks, int ntasks, int nblocks,
+void launch_dst_wave(DstKind kind, int E, bool big, const DstTask* tasks, int ntasks, int nblocks,
                      int threads, size_t smem, int jidx, hipStream_t s);
 // Matrix-core variant of the row sine transform: RT*16 rows per block, each
 // of the 4 waves covers CT*16 columns (4*CT*16 >= n).

@@ -142,7 +142,8 @@ size_t line_smem_bytes(int n);
 // when the length needs a radix without a register butterfly or more
 // registers than allowed.
 struct WaveCfg { int E; int G; int waves; int rows_per_block; size_t smem; };
-WaveCfg dst_wave_config(int n, bool fp32);
+// big: one row per workgroup of 128/256/512 lanes, tables read from global memory.
+WaveCfg dst_wave_config(int n, bool fp32, bool big);
 // Lanes per row of the wave transform of length n, and its radix schedule
 // for an inner FFT of length L (empty when L has a prime factor above 5).
 int wave_lanes(int n);
@@ -159,11 +160,13 @@ struct DstChoice {
   size_t smem;
   int wave_e;    // > 0: wave-parallel kernel with this register budget
   int threads;   // workgroup size
+  int wave_big;  // wave kernel with one row per workgroup
 };
 DstChoice dst_choice(int n, bool fp32);
-// One variant ("wave": the wave FFT where its schedule allows, else the
-// workgroup FFT; "fft": the workgroup FFT; "gemm": the matrix-core product
-// for n <= 1024, else as "wave").
+// One variant ("wave": the wave FFT where its schedule allows, a row per
+// wavefront if possible, else the workgroup FFT; "wavebig": the wave FFT with
+// a row per workgroup, else the workgroup FFT; "fft": the workgroup FFT;
+// "gemm": the matrix-core product for n <= 512, else as "wave").
 DstChoice dst_choice_variant(int n, bool fp32, const std::string& mode);
 // Autotuner (tune.cpp): on the first request for (device, n, precision) every
 // variant runs on a batch of synthetic rows and the fastest is kept.

@@ -154,39 +154,62 @@ static int wave_need(int n, int L, int G, const std::vector<int>& rad) {
   return need;
 }
 
-FftShape wave_shape(int n) {
-  // The workgroup schedule when its radices have register butterflies;
-  // otherwise Rader (N prime, N - 1 5-smooth) or Bluestein over the smallest
-  // 5-smooth length >= 2N - 1, whichever is wave-schedulable and cheaper.
+// Lanes per row of the one-row-per-workgroup ("big") wave transform.
+static int big_lanes(int L) { return L >= 3072 ? 512 : L >= 1024 ? 256 : 128; }
+
+// FFT schedule of the wave-parallel transform and the lane count its radices
+// are built for.  The workgroup schedule when its radices have register
+// butterflies only; otherwise Rader (N prime, N - 1 5-smooth) or Bluestein
+// over the smallest 5-smooth length >= 2N - 1, whichever is wave-schedulable
+// and cheaper.  When no schedule fits one wavefront per row (at most 32
+// entries per lane), the same candidates are tried with a workgroup per row
+// (big_lanes lanes, the FP64 row alone in LDS).  G == 0: no wave schedule.
+struct WaveSched {
+  FftShape shp;
+  int G;
+};
+
+static WaveSched wave_sched(int n) {
   const int N = n + 1;
   const FftShape s0 = fft_shape(n);
-  auto ok = [&](const FftShape& s) {
-    const int G = lanes_for(s.L);
-    const int need = wave_need(n, s.L, G, wave_radices(s.L, G));
-    return need > 0 && need <= 32;
-  };
-  if (ok(s0)) return s0;
-  FftShape best{FFT_MIXED, 0, 0};
-  double cost = 0.0;
-  if (N > 7 && is_prime(N)) {
-    const FftShape r{FFT_RADER, N - 1, N};
-    if (ok(r)) { best = r; cost = 2.0 * stockham_cost(N - 1) + 3.0 * N; }
-  }
+  struct Cand { FftShape s; double cost; bool own; };
+  std::vector<Cand> cand;
+  if (fixed_radices(s0.L)) cand.push_back({s0, 0.0, true});
+  if (N > 7 && is_prime(N) && s0.kind != FFT_RADER)
+    cand.push_back({FftShape{FFT_RADER, N - 1, N}, 2.0 * stockham_cost(N - 1) + 3.0 * N, false});
   int M = 2 * N - 1;
   auto smooth = [](int v) {
     for (int p : {2, 3, 5}) while (v % p == 0) v /= p;
     return v == 1;
   };
   while (!smooth(M)) ++M;
-  const FftShape b{FFT_BLUESTEIN, M, M};
-  if (N > 8 && ok(b)) {
-    const double c = 2.0 * stockham_cost(M) + 4.0 * M;
-    if (best.L == 0 || c < cost) best = b;
+  if (N > 8 && !(s0.kind == FFT_BLUESTEIN && s0.L == M))
+    cand.push_back({FftShape{FFT_BLUESTEIN, M, M}, 2.0 * stockham_cost(M) + 4.0 * M, false});
+  for (int big = 0; big < 2; ++big) {
+    int bi = -1;
+    for (size_t i = 0; i < cand.size(); ++i) {
+      const FftShape& s = cand[i].s;
+      const int G = big ? big_lanes(s.L) : lanes_for(s.L);
+      const int need = wave_need(n, s.L, G, wave_radices(s.L, G));
+      if (need <= 0 || need > 32) continue;
+      if (big && wave_layout<double>(s.kind, N, s.L, s.lds_len, s.L).row_bytes > 160 * 1024) continue;
+      if (cand[i].own) { bi = (int)i; break; }   // the workgroup schedule is kept when it qualifies
+      if (bi < 0 || cand[i].cost < cand[bi].cost) bi = (int)i;
+    }
+    if (bi >= 0) {
+      const FftShape& s = cand[bi].s;
+      return WaveSched{s, big ? big_lanes(s.L) : lanes_for(s.L)};
+    }
   }
-  return best.L ? best : s0;
+  return WaveSched{s0, 0};
 }
 
-int wave_lanes(int n) { return lanes_for(wave_shape(n).L); }
+FftShape wave_shape(int n) { return wave_sched(n).shp; }
+
+int wave_lanes(int n) {
+  const WaveSched w = wave_sched(n);
+  return w.G ? w.G : lanes_for(w.shp.L);
+}
 
 std::vector<int> wave_radices(int L, int G) {
   // powers of two in passes as long as every pass keeps L/R >= G
@@ -206,20 +229,37 @@ std::vector<int> wave_radices(int L, int G) {
   return r;
 }
 
-WaveCfg dst_wave_config(int n, bool fp32) {
+WaveCfg dst_wave_config(int n, bool fp32, bool big) {
   WaveCfg c{0, 0, 0, 0, 0};
-  const FftShape shp = wave_shape(n);
-  const int G = lanes_for(shp.L);
-  const std::vector<int> rad = wave_radices(shp.L, G);
+  const WaveSched ws = wave_sched(n);
+  if (ws.G == 0) return c;
+  const FftShape shp = ws.shp;
+  const std::vector<int> rad = wave_radices(shp.L, ws.G);
+  const int twl = wave_twiddle_len(rad);
+  const WaveLayout lay = fp32 ? wave_layout<float>(shp.kind, n + 1, shp.L, shp.lds_len, twl)
+                              : wave_layout<double>(shp.kind, n + 1, shp.L, shp.lds_len, twl);
+  if (big) {
+    // one row per workgroup; the tables stay in global memory
+    const int G = big_lanes(shp.L);
+    const int need = wave_need(n, shp.L, G, rad);
+    if (need == 0) return c;
+    for (int e : {8, 16, 32})
+      if (need <= e) { c.E = e; break; }
+    if (!c.E || (size_t)lay.row_bytes > 160u * 1024u) return WaveCfg{0, 0, 0, 0, 0};
+    c.G = G;
+    c.waves = G / 64;
+    c.rows_per_block = 1;
+    c.smem = (size_t)lay.row_bytes;
+    return c;
+  }
+  if (ws.G > 64) return c;   // only the workgroup-per-row form fits
+  const int G = ws.G;
   const int need = wave_need(n, shp.L, G, rad);
   if (need == 0) return c;
   for (int e : {4, 8, 16, 32, 64})
     if ((e <= 32 || fp32) && need <= e) { c.E = e; break; }
   if (!c.E) return c;
   c.G = G;
-  const int twl = wave_twiddle_len(rad);
-  const WaveLayout lay = fp32 ? wave_layout<float>(shp.kind, n + 1, shp.L, shp.lds_len, twl)
-                              : wave_layout<double>(shp.kind, n + 1, shp.L, shp.lds_len, twl);
   // workgroup size with the most rows resident per CU (160 KB of LDS, at most
   // 16 wavefronts); ties go to the larger workgroup (fewer table copies)
   int best = -1;
@@ -275,13 +315,18 @@ DstChoice dst_choice_variant(int n, bool fp32, const std::string& mode) {
     return c;
   }
   if (mode != "fft") {
-    const WaveCfg w = dst_wave_config(n, fp32);
-    if (w.E) {
-      c.wave_e = w.E;
-      c.threads = 64 * w.waves;
-      c.rows_per_block = w.rows_per_block;
-      c.smem = w.smem;
-      return c;
+    // "wave": a row per wavefront where possible, else a row per workgroup;
+    // "wavebig": a row per workgroup
+    for (int big = mode == "wavebig" ? 1 : 0; big < 2; ++big) {
+      const WaveCfg w = dst_wave_config(n, fp32, big != 0);
+      if (w.E) {
+        c.wave_e = w.E;
+        c.wave_big = big;
+        c.threads = 64 * w.waves;
+        c.rows_per_block = w.rows_per_block;
+        c.smem = w.smem;
+        return c;
+      }
     }
   }
   c.rows_per_block = kBlock / dst_threads_per_row(n);
@@ -438,9 +483,10 @@ std::shared_ptr<FftTable> TableCache::fft(int n) {
   const size_t o_s64 = take(sizeof(double) * std::max((size_t)np * np, (size_t)1));
   const size_t o_s32 = take(sizeof(float) * std::max((size_t)np * np, (size_t)1));
   // the wave-parallel transform may run another schedule (wave_shape)
-  const FftShape wshp = wave_shape(n);
+  const WaveSched wsch = wave_sched(n);
+  const FftShape wshp = wsch.shp;
   const int wL = wshp.L;
-  const std::vector<int> wrad = wave_radices(wL, lanes_for(wL));
+  const std::vector<int> wrad = wsch.G ? wave_radices(wL, wsch.G) : std::vector<int>{};
   const int twl = wave_twiddle_len(wrad);
   const WaveLayout wl64 = wave_layout<double>(wshp.kind, N, wL, wshp.lds_len, twl);
   const WaveLayout wl32 = wave_layout<float>(wshp.kind, N, wL, wshp.lds_len, twl);

@@ -38,7 +38,7 @@ void launch_one_dst(DstKind kind, const DstChoice& ch, const DstTask& t0, hipStr
   Timing::begin(0, s);
   if (ch.gemm) launch_dst_gemm(kind, ch.rt, ch.ct, keep.as<DstTask>(), 1, nb, ch.smem, 0, s);
   else if (ch.wave_e)
-    launch_dst_wave(kind, ch.wave_e, keep.as<DstTask>(), 1, nb, ch.threads, ch.smem, 0, s);
+    launch_dst_wave(kind, ch.wave_e, ch.wave_big != 0, keep.as<DstTask>(), 1, nb, ch.threads, ch.smem, 0, s);
   else launch_dst(kind, keep.as<DstTask>(), 1, nb, ch.smem, 0, s);
   Timing::end(0, s);
 }
@@ -46,7 +46,7 @@ void launch_one_dst(DstKind kind, const DstChoice& ch, const DstTask& t0, hipStr
 namespace {
 
 bool same(const DstChoice& a, const DstChoice& b) {
-  return a.gemm == b.gemm && a.wave_e == b.wave_e && a.rt == b.rt && a.ct == b.ct &&
+  return a.gemm == b.gemm && a.wave_e == b.wave_e && a.wave_big == b.wave_big && a.rt == b.rt && a.ct == b.ct &&
          a.threads == b.threads && a.rows_per_block == b.rows_per_block;
 }
 
@@ -92,7 +92,7 @@ DstChoice dst_tuned_choice(int n, bool fp32) {
   if (it != tuned.end()) return it->second;
 
   std::vector<DstChoice> cand;
-  for (const char* mode : {"wave", "fft", "gemm"}) {
+  for (const char* mode : {"wave", "wavebig", "fft", "gemm"}) {
     const DstChoice c = dst_choice_variant(n, fp32, mode);
     bool dup = false;
     for (const DstChoice& o : cand) dup |= same(o, c);
@@ -119,7 +119,7 @@ DstChoice dst_tuned_choice(int n, bool fp32) {
         }
         if (log)
           std::fprintf(stderr, "[fds tune] n=%d %s rows=%d %s: %.1f us\n", n, fp32 ? "fp32" : "fp64",
-                       rows, cand[i].gemm ? "gemm" : cand[i].wave_e ? "wave" : "fft", ms * 1e3);
+                       rows, cand[i].gemm ? "gemm" : cand[i].wave_big ? "wavebig" : cand[i].wave_e ? "wave" : "fft", ms * 1e3);
         if (tbest < 0 || ms < tbest) {
           tbest = ms;
           best = cand[i];

@@ -38,11 +38,13 @@ DST_SIZES = [1, 2, 3, 4, 5, 7, 10, 16, 31, 32, 33, 63, 64, 65, 96, 100, 127, 128
              300, 511, 512, 1000, 1023, 1024, 1025, 1200, 1500, 2047, 2048]
 
 
-@pytest.fixture(params=["wave", "fft", "gemm"])
+@pytest.fixture(params=["wave", "wavebig", "fft", "gemm"])
 def dst_algo(request, monkeypatch):
-    """Every row-transform algorithm: wave-parallel LDS FFT (where its radices
-    and register budget allow, else the workgroup FFT), workgroup-wide LDS FFT,
-    and the matrix-core product (n <= 1024)."""
+    """Every row-transform algorithm: wave-parallel LDS FFT with a row per
+    wavefront ("wave", where its radices and register budget allow) or a row
+    per workgroup with the tables in global memory ("wavebig"), else the
+    workgroup FFT; the workgroup-wide LDS FFT; and the matrix-core product
+    (n <= 512)."""
     monkeypatch.setenv("FDS_DST_ALGO", request.param)
     return request.param
 
