@@ -37,8 +37,91 @@ KERNEL_SOURCES = ("paper_2509_23180_amd/csrc/kernels.hip", "paper_2509_23180_amd
                   "paper_2509_23180_amd/csrc/fds_internal.h")
 # kernel class -> name of the HIP kernel that implements it (rocprofv3 summaries)
 CLASS_KERNEL = {"dst": "k_dst_wave", "tridiag": "k_tridiag_seg", "operator": "k_operator",
-                "gram_dots": "k_gram_dots", "gram_update": "k_gram_update", "lines": "k_schur_lines",
+                "gram_dots": "k_gram_dots", "gram_update": "k_gram_update", "lines": "k_lines_dense",
                 "cols": "k_idst_cols"}
+
+
+def class_kernel(cls: str, opts: dict) -> str:
+    """Kernel of a timing class for a solver configuration: the plain method
+    with restart length <= 32 takes its Gram columns from the update pass
+    (boundary dots + k_gram_update_lag) unless FDS_GRAM_LAG=0."""
+    lag = (opts.get("precision", 0) == 0 and opts.get("restart_m", 30) <= 32
+           and os.environ.get("FDS_GRAM_LAG", "1") != "0")
+    if lag and cls == "gram_dots":
+        return "k_gram_bdots"
+    if lag and cls == "gram_update":
+        return "k_gram_update_lag"
+    return CLASS_KERNEL.get(cls, cls)
+
+
+def traffic_summary(args) -> None:
+    """Per-dispatch HBM bytes of every kernel from two rocprofv3 --pmc runs of
+    the workload (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by the same
+    counters on a 1 GiB device copy; writes profiles/traffic_<kernel>_<workload>.json
+    for the named kernel (all of its template instantiations) and prints a
+    markdown table.  Runs on the host only."""
+    import csv
+    fetch_dir, write_dir, cfetch_dir, cwrite_dir = args.traffic_summary
+
+    def per_kernel(d, counter):
+        out = {}
+        with open(os.path.join(d, "run_counter_collection.csv")) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] != counter:
+                    continue
+                k = row["Kernel_Name"]
+                c = out.setdefault(k, [0, 0.0])
+                c[0] += 1
+                c[1] += float(row["Counter_Value"])
+        return out
+
+    def copy_kib(d, counter):
+        # the 1 GiB copy: the largest dispatch of __amd_rocclr_copyBuffer
+        best = 0.0
+        with open(os.path.join(d, "run_counter_collection.csv")) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] == counter and "copyBuffer" in row["Kernel_Name"]:
+                    best = max(best, float(row["Counter_Value"]))
+        return best
+
+    gib = float(1 << 30)
+    cf, cw = copy_kib(cfetch_dir, "FETCH_SIZE"), copy_kib(cwrite_dir, "WRITE_SIZE")
+    fscale, wscale = gib / (cf * 1024.0), gib / (cw * 1024.0)
+    fe, wr = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+
+    def short(k):
+        k = k.replace("void ", "").replace("fds::", "")
+        return k.split("(")[0]
+
+    rows = []
+    for k in sorted(fe, key=lambda k: -fe[k][1]):
+        n, f = fe[k]
+        wn, w = wr.get(k, [n, 0.0])
+        rows.append((short(k), n, f / n * 1024 * fscale / 1e6, w / max(wn, 1) * 1024 * wscale / 1e6))
+    print(f"calibration: 1 GiB copy reads FETCH_SIZE {cf:.1f} KiB, writes WRITE_SIZE {cw:.1f} KiB "
+          f"per dispatch: scales {fscale:.4f} / {wscale:.4f}")
+    print("| kernel | dispatches | HBM read MB / dispatch | HBM write MB / dispatch |")
+    print("|---|---:|---:|---:|")
+    for name, n, f, w in rows[:12]:
+        print(f"| {name} | {n} | {f:.2f} | {w:.2f} |")
+    sel = [k for k in fe if short(k).startswith(args.traffic_kernel + "<") or short(k) == args.traffic_kernel]
+    if not sel:
+        print(f"no dispatches of {args.traffic_kernel}", file=sys.stderr)
+        sys.exit(1)
+    n = sum(fe[k][0] for k in sel)
+    fb = sum(fe[k][1] for k in sel) * 1024 * fscale / n
+    wn = sum(wr.get(k, [0, 0.0])[0] for k in sel)
+    wb = sum(wr.get(k, [0, 0.0])[1] for k in sel) * 1024 * wscale / max(wn, 1)
+    rec = {"kernel": args.traffic_kernel, "workload": args.workload,
+           "kernel_source_hash": kernel_source_hash(),
+           "hbm_bytes_per_launch": round(fb + wb, 1), "fetch_bytes_per_launch": round(fb, 1),
+           "write_bytes_per_launch": round(wb, 1), "launches": n,
+           "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4),
+           "calibration": f"1 GiB device copy: FETCH_SIZE {cf:.1f} KiB, WRITE_SIZE {cw:.1f} KiB per dispatch"}
+    path = os.path.join(ROOT, "profiles", f"traffic_{args.traffic_kernel}_{args.workload}.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
 
 
 def log(*a):
@@ -286,13 +369,20 @@ def main():
     ap.add_argument("--latency-solves", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (HBM counter calibration)")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                            "COPY_WRITE_DIR"),
+                    help="host only: turn rocprofv3 --pmc output directories into the traffic record")
+    ap.add_argument("--traffic-kernel", default="k_gram_update_lag")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(args)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: every solve of this method fits one MI355X, and "
-              "multi-GPU runs are outside this build (see DESIGN.md for how the path would shard).",
-              file=sys.stderr)
+              "runs on several GPUs are not implemented (independent problems would shard across "
+              "GPUs with no communication).", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -384,7 +474,8 @@ def main():
 
     achieved = (algo_bytes / calls) / ((ms / calls) * 1e-3) / 1e9 if calls and ms > 0 else None
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_{CLASS_KERNEL.get(dominant, dominant)}_{args.workload}.json")
+    kname = class_kernel(dominant, opts)
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{kname}_{args.workload}.json")
     if os.path.exists(tfile):
         with open(tfile) as fh:
             tr = json.load(fh)
@@ -394,7 +485,7 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
                 "traffic": traffic,
-                "kernel": CLASS_KERNEL.get(dominant, dominant),
+                "kernel": kname,
                 "launches": calls, "avg_launch_us": round(ms / calls * 1e3, 3) if calls else None,
                 "algorithmic_bytes_per_launch": round(algo_bytes / calls, 1) if calls else None}
 

@@ -15,7 +15,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
 #include <functional>
+#include <string>
 
 #include "runtime.h"
 
@@ -214,6 +216,15 @@ struct Problem {
 
 namespace {
 
+// The plain variant keeps the Gram columns from the update pass (one pass over
+// the basis per step instead of two) when the restart length allows;
+// FDS_GRAM_LAG=0 turns this off (measurements, A/B tests).
+bool gram_lag_enabled(int m, bool flex) {
+  if (flex || m > kLagMaxJ) return false;
+  const char* v = std::getenv("FDS_GRAM_LAG");
+  return !(v && std::string(v) == "0");
+}
+
 // Task lists of every phase for one set of problems.
 struct TaskSet {
   int m = 0;
@@ -235,9 +246,12 @@ struct TaskSet {
   std::vector<Problem*> probs;
   Blob blob;
 
+  bool lag = false;   // lagged Gram columns (exact preconditioner, m <= kLagMaxJ)
+
   TaskSet(int m_, bool flex_) : m(m_), flex(flex_) {
     it_fwd.kind = flex ? DstKind::D_F : DstKind::D_D;
     it_tri.fp32 = flex;
+    lag = gram_lag_enabled(m_, flex_);
   }
   void add_problem(Problem& sl);
   void upload(hipStream_t s) {
@@ -430,6 +444,7 @@ void TaskSet::add_problem(Problem& sl) {
     k.sn = sl.sn; k.g = sl.g; k.y = sl.y; k.partials = sl.partials; k.st = sl.st; k.Nc = Nc;
     k.P = sl.P; k.m = m; k.G = sl.G; k.hv = sl.hv; k.nx = nx; k.ny = ny;
     k.flag_idx = sl.idx;
+    k.gram_lag = lag ? 1 : 0;
     k.implicit_w = flex ? 0 : 1;
     for (int q = 0; q < 4; ++q) k.line[q] = ot.line[q];
     add_block_task(kry, k, sl.P);
@@ -506,10 +521,12 @@ void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
     Timing::end(2, s);
   }
   Timing::begin(3, s);
-  launch_gram_dots(kry.dev(), kry.n(), kry.nblocks, j, s);
+  if (lag) launch_gram_bdots(kry.dev(), kry.n(), j, s);
+  else launch_gram_dots(kry.dev(), kry.n(), kry.nblocks, j, s);
   Timing::end(3, s);
   Timing::begin(6, s);
-  launch_gram_update(kry.dev(), kry.n(), kry.nblocks, j, flags_dev, tag, s);
+  if (lag) launch_gram_update_lag(kry.dev(), kry.n(), kry.nblocks, m, j, flags_dev, tag, s);
+  else launch_gram_update(kry.dev(), kry.n(), kry.nblocks, j, flags_dev, tag, s);
   Timing::end(6, s);
   FDS_HIP(hipGetLastError());
 }
@@ -857,12 +874,21 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
     }
     Timing::add_bytes(4, its * lines);
     double dots = 0, upd = 0;
+    const bool lagged = gram_lag_enabled(m, flex);
+    const double bnd = 2.0 * (sl.plan->nx + sl.plan->ny);   // boundary-line points
     for (int j = 0; j < its; ++j) {
-      dots += 8.0 * (j + 1) + (flex ? 8.0 : 0.0);
-      upd += 8.0 * (j + 1) + 8.0 + (flex ? 8.0 : 0.0);
+      if (lagged) {
+        // boundary dots read v_0..v_j and s on the lines; the update reads
+        // v_0..v_j (s on the lines) and writes w
+        dots += 16.0 * (j + 1) * bnd;
+        upd += (8.0 * (j + 1) + 8.0) * Nc;
+      } else {
+        dots += (8.0 * (j + 1) + (flex ? 8.0 : 0.0)) * Nc;
+        upd += (8.0 * (j + 1) + 8.0 + (flex ? 8.0 : 0.0)) * Nc;
+      }
     }
-    Timing::add_bytes(3, dots * Nc);
-    Timing::add_bytes(6, upd * Nc);
+    Timing::add_bytes(3, dots);
+    Timing::add_bytes(6, upd);
     // end of cycle: plain variant applies A_c^{-1} to V y (transforms and
     // tridiagonal solve in FP64, accumulate into x); residual operator reads
     // x and f', writes r; line terms of x

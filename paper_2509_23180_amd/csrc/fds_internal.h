@@ -265,8 +265,14 @@ struct KryTask {
   int block_begin;
   const double* line[4];      // Schur line terms s on the centre's boundary lines (or NULL)
   int flag_idx;               // slot of this problem in the host-visible flag array
-  int pad_k;
+  int gram_lag;               // 1: Gram columns come from the update pass (see kLagMaxJ)
 };
+
+// Lagged Gram columns (exact preconditioner, restart length <= kLagMaxJ):
+// the update pass of step j also forms <v_i, v_{j+1}> from the values it
+// holds, so the dot pass of step j+1 reduces to <v_i, s> over the boundary
+// lines where the Schur terms s live.
+constexpr int kLagMaxJ = 32;
 
 // partial-sum slots (each P wide) inside KryTask::partials
 constexpr int kPartRes = 0;   // residual r^2 (P) and x^2 (P)

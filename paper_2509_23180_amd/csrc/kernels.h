@@ -75,6 +75,12 @@ void launch_gram_dots(const KryTask* tasks, int ntasks, int nblocks, int j, hipS
 // cycle writes `tag` to flags[KryTask::flag_idx] (flags may be null).
 void launch_gram_update(const KryTask* tasks, int ntasks, int nblocks, int j, int* flags, int tag,
                         hipStream_t s);
+// Lagged Gram columns (exact preconditioner, restart length m <= kLagMaxJ):
+// boundary dots <v_i, s> and the MGS recurrence; the update pass that also
+// stores the next Gram column.
+void launch_gram_bdots(const KryTask* tasks, int ntasks, int j, hipStream_t s);
+void launch_gram_update_lag(const KryTask* tasks, int ntasks, int nblocks, int m, int j, int* flags,
+                            int tag, hipStream_t s);
 void launch_scale_newest(const KryTask* tasks, int j, int nblocks, hipStream_t s);
 void launch_idst_cols(const ColTask* tasks, int ntasks, int nblocks, hipStream_t s);
 void launch_ls_solve(const KryTask* tasks, int ntasks, hipStream_t s);

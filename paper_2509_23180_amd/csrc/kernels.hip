@@ -590,6 +590,8 @@ __device__ __forceinline__ bool last_block_of_problem(int* ctr, int nblocks, int
   return *sflag != 0;
 }
 
+__device__ void gram_recur(const KryTask& tk, int j, double* lds);
+
 // Gram column and MGS coefficients of step j from the dot sums (row t of
 // `src`, ncols entries at src + t ld): G[:, j] = <v_i, v_j>, a_i = <w, v_i>,
 // h_i = a_i - sum_{l<i} h_l G_li.  The recurrence runs in LDS: after h_l is
@@ -603,6 +605,18 @@ __device__ void gram_solve_block(const KryTask& tk, int j, double* lds, const do
   double* a = dots + 2 * nd;          // nd
   double* Gt = a + nd;                // column i of the strict upper triangle at i (i - 1) / 2
   reduce_rows(src, ld, 2 * nd, ncols, scratch, dots);
+  gram_recur(tk, j, lds);
+}
+
+// The MGS recurrence of step j from dots[0, nd) = G[:, j] and dots[nd, 2 nd)
+// = <v_i, u> in LDS (layout as in gram_solve_block); writes G[:, j], hv and
+// column j of H.
+__device__ void gram_recur(const KryTask& tk, int j, double* lds) {
+  const int nd = j + 1;
+  const int m1 = tk.m + 1;
+  double* dots = lds;
+  double* a = dots + 2 * nd;
+  double* Gt = a + nd;
   const int ntri = nd * (nd - 1) / 2;
   for (int e = threadIdx.x; e < ntri; e += blockDim.x) {
     int i = (int)((1.0 + sqrt(1.0 + 8.0 * e)) * 0.5);
@@ -830,6 +844,169 @@ __global__ void __launch_bounds__(kBlock) k_gram_update(const KryTask* __restric
     mgs_finish_block(tk, j, flags, tag, red, col, cs, sn, scratch);
 }
 
+// ---- lagged Gram columns (exact preconditioner) ----------------------
+// Boundary dots of step j: block i (< kLagMaxJ) of a problem forms
+// <v_i, s> with one wavefront per boundary line (s is zero elsewhere; a
+// corner takes both of its lines' terms, as in line_term).  The problem's
+// last block then runs the MGS recurrence with a_i = G_ij - <v_i, s>, the
+// Gram column G[:, j] having been stored by the previous update pass (or set
+// to e_0 at the start of the cycle).
+__global__ void __launch_bounds__(kBlock) k_gram_bdots(const KryTask* __restrict__ tasks, int ntasks,
+                                                        int j) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int lastf;
+  __shared__ double wred[4];
+  const int t = blockIdx.x / kLagMaxJ;
+  const int i = blockIdx.x - t * kLagMaxJ;
+  if (t >= ntasks) return;
+  const KryTask& tk = tasks[t];
+  if (tk.st->cycle_done) return;
+  const int nd = j + 1;
+  const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double* s = tk.line[q];
+  double acc = 0.0;
+  if (i <= j && s) {
+    const double* vi = tk.V + (long long)i * tk.Nc;
+    const int len = q < 2 ? tk.nx : tk.ny;
+    for (int p = lane; p < len; p += 64) {
+      const long long idx = q == 0 ? (long long)p
+                          : q == 1 ? (long long)(tk.ny - 1) * tk.nx + p
+                          : q == 2 ? (long long)p * tk.nx
+                                   : (long long)p * tk.nx + (tk.nx - 1);
+      acc += vi[idx] * s[p];
+    }
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) wred[q] = acc;
+  __syncthreads();
+  double* u = tk.partials + (size_t)(kPartDots + nd) * tk.P;   // u_i at row kPartDots + nd + i
+  if (threadIdx.x == 0 && i <= j) st_agent(u + (size_t)i * tk.P, (wred[0] + wred[1]) + (wred[2] + wred[3]));
+  if (!last_block_of_problem(&tk.st->ctr_dots, kLagMaxJ, &lastf)) return;
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  const int m1 = tk.m + 1;
+  for (int e = threadIdx.x; e < nd; e += kBlock) {
+    lds[e] = tk.G[e + j * m1];
+    lds[nd + e] = ld_agent(u + (size_t)e * tk.P);
+  }
+  __syncthreads();
+  gram_recur(tk, j, lds);
+}
+
+// Update of step j with the next Gram column: w = v_j - s - sum h_i v_i is
+// stored in V[j+1] (unnormalised, as in k_gram_update), and the same pass
+// accumulates <v_i, w> (i <= j) and ||w||^2 from the values it holds in
+// registers.  The last block finishes the step (mgs_finish_block) and stores
+// G[i, j+1] = <v_i, w> / h_{j+1,j}, G[j+1, j+1] = ||w||^2 / h_{j+1,j}^2.
+// MJ >= j + 1 basis vectors; each round a thread loads EU elements of each
+// of them (vector min(i, j) for i > j, so every load is in bounds and none
+// is behind a branch; those values are then cleared).  The dots use the
+// two-level reduction of k_gram_dots.
+template <int MJ, int EU>
+__global__ void __launch_bounds__(kBlock) k_gram_update_lag(const KryTask* __restrict__ tasks, int ntasks,
+                                                             int j, int* flags, int tag) {
+  static_assert(kVecEPT % EU == 0, "rounds must cover the block");
+  __shared__ int slot;
+  __shared__ int lastf;
+  __shared__ double red[4];
+  __shared__ double hs[MJ];
+  __shared__ double col[122];
+  __shared__ double cs[121], sn[121];
+  __shared__ double scratch[kBlock];
+  __shared__ double dred[MJ + 1][4];
+  __shared__ double gcol[MJ];
+  const KryTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  if (tk.st->cycle_done) return;
+  for (int i = threadIdx.x; i < MJ; i += kBlock) hs[i] = i <= j ? tk.hv[i] : 0.0;
+  __syncthreads();
+  const int b = blockIdx.x - tk.block_begin;
+  const long long Nc = tk.Nc;
+  const long long base = (long long)b * kVecPerBlock;
+  double* w = tk.V + (long long)(j + 1) * Nc;
+  // the basis through global-address-space pointers: one uniform base per
+  // vector and one 32-bit lane offset shared by all of its loads
+  using GD = const double __attribute__((address_space(1)));
+  GD* Vg = (GD*)(tk.V);
+  double d[MJ + 1];
+#pragma unroll
+  for (int i = 0; i <= MJ; ++i) d[i] = 0.0;
+#pragma unroll 1
+  for (int r = 0; r < kVecEPT / EU; ++r) {
+    unsigned off[EU];
+    bool ok[EU];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+      const long long idx = base + (long long)(r * EU + u) * kBlock + threadIdx.x;
+      ok[u] = idx < Nc;
+      off[u] = (unsigned)(ok[u] ? idx : Nc - 1);
+    }
+    double vv[EU][MJ];
+#pragma unroll
+    for (int i = 0; i < MJ; ++i) {
+      GD* vi = Vg + (long long)min(i, j) * Nc;
+#pragma unroll
+      for (int u = 0; u < EU; ++u) vv[u][i] = vi[off[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+      double xj = 0.0;
+#pragma unroll
+      for (int i = 0; i < MJ; ++i) {
+        xj = (i == j) ? vv[u][i] : xj;
+        vv[u][i] = (ok[u] && i <= j) ? vv[u][i] : 0.0;
+      }
+      const long long idx = base + (long long)(r * EU + u) * kBlock + threadIdx.x;
+      double acc = ok[u] ? xj - line_term(tk, idx) : 0.0;
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i < j) acc -= hs[i] * vv[u][i];
+      acc -= hs[j] * (ok[u] ? xj : 0.0);
+      if (ok[u]) w[idx] = acc;
+      d[MJ] += acc * acc;
+#pragma unroll
+      for (int i = 0; i < MJ; ++i) d[i] += vv[u][i] * acc;
+    }
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nd = j + 1;
+#pragma unroll
+  for (int i = 0; i <= MJ; ++i) {
+    if (i <= j || i == MJ) {
+      const double v = wave_sum(d[i]);
+      if (lane == 0) dred[i][wave] = v;
+    }
+  }
+  __syncthreads();
+  const int P = tk.P;
+  double* part = tk.partials + (size_t)kPartDots * P;
+  for (int t = threadIdx.x; t < nd; t += kBlock)
+    st_agent(part + (size_t)t * P + b, (dred[t][0] + dred[t][1]) + (dred[t][2] + dred[t][3]));
+  if (threadIdx.x == 0)
+    st_agent(tk.partials + (size_t)kPartNorm * P + b, (dred[MJ][0] + dred[MJ][1]) + (dred[MJ][2] + dred[MJ][3]));
+  const int ng = gram_groups(P);
+  if (ng == 1) {
+    if (!last_block_of_problem(&tk.st->ctr_upd, P, &lastf)) return;
+    reduce_rows(part, P, nd, P, scratch, gcol);
+  } else {
+    double* gsum = tk.partials + (size_t)(2 * (tk.m + 1) + 4) * P;
+    int* gctr = reinterpret_cast<int*>(gsum + (size_t)2 * (tk.m + 1) * ng);
+    const int g = b / kGramGroup;
+    const int gb = min(kGramGroup, P - g * kGramGroup);
+    if (!last_block_of_problem(gctr + g, gb, &lastf)) return;
+    reduce_rows(part + g * kGramGroup, P, nd, gb, scratch, gcol);
+    for (int t = threadIdx.x; t < nd; t += kBlock) st_agent(gsum + (size_t)t * ng + g, gcol[t]);
+    if (!last_block_of_problem(&tk.st->ctr_upd, ng, &lastf)) return;
+    reduce_rows(gsum, ng, nd, ng, scratch, gcol);
+  }
+  mgs_finish_block(tk, j, flags, tag, red, col, cs, sn, scratch);
+  if (threadIdx.x == 0) {
+    // red[0] holds ||w||^2, ProbState::vscale = 1 / h_{j+1,j}
+    const double vs = tk.st->vscale;
+    const int m1 = tk.m + 1;
+    for (int t = 0; t < nd; ++t) tk.G[t + (j + 1) * m1] = gcol[t] * vs;
+    tk.G[(j + 1) + (j + 1) * m1] = red[0] * vs * vs;
+  }
+}
+
 // v *= 1 / h_{j+1,j} for the kernel-level Arnoldi entry point.
 __global__ void k_scale_newest(const KryTask* __restrict__ tasks, int j) {
   const KryTask& tk = tasks[0];
@@ -945,6 +1122,7 @@ __global__ void __launch_bounds__(kBlock) k_restart(const KryTask* __restrict__ 
     st->vscale = 1.0;
     st->rscale = 1.0 / beta;
     tk.g[0] = beta;
+    tk.G[0] = 1.0;   // <v_0, v_0> (the lagged Gram columns start here)
   }
 }
 
@@ -1265,6 +1443,23 @@ static size_t gram_solve_smem(int j) {
 void launch_gram_dots(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s) {
   if (nblocks <= 0) return;
   FDS_LAUNCH(k_gram_dots, dim3(nblocks), dim3(kBlock), gram_solve_smem(j), s, tasks, ntasks, j);
+}
+
+void launch_gram_bdots(const KryTask* tasks, int ntasks, int j, hipStream_t s) {
+  if (ntasks <= 0) return;
+  FDS_LAUNCH(k_gram_bdots, dim3(ntasks * kLagMaxJ), dim3(kBlock), gram_solve_smem(j), s, tasks, ntasks, j);
+}
+
+void launch_gram_update_lag(const KryTask* tasks, int ntasks, int nblocks, int m, int j, int* flags,
+                            int tag, hipStream_t s) {
+  if (nblocks <= 0) return;
+  if (m > kLagMaxJ || j >= m) throw Error(FDS_E_INVALID_ARG, "lagged Gram columns need j < m <= 32");
+  // basis vectors held per round: the smallest MJ >= j + 1; about 32 loads
+  // in flight per thread and round
+  if (j < 4) FDS_LAUNCH((k_gram_update_lag<4, 8>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
+  else if (j < 8) FDS_LAUNCH((k_gram_update_lag<8, 4>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
+  else if (j < 16) FDS_LAUNCH((k_gram_update_lag<16, 2>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
+  else FDS_LAUNCH((k_gram_update_lag<32, 2>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
 }
 
 void launch_gram_update(const KryTask* tasks, int ntasks, int nblocks, int j, int* flags, int tag,

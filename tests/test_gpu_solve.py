@@ -83,6 +83,30 @@ def test_full_size_plain_fp64(kappa, kind):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("restart_m", [6, 16, 30, 40])
+@pytest.mark.parametrize("shape,n,kappa,kind", [("cross", 64, 0.0, "shifted"), ("T", 45, -50.0, "gauss"),
+                                                ("L", 1, 0.0, "shifted")])
+def test_lagged_gram_columns(shape, n, kappa, kind, restart_m, monkeypatch):
+    """Plain method with the Gram columns taken from the update pass
+    (restart length <= 32) and with the two-pass Gram-Schmidt: both reach the
+    oracle, with the same iteration counts up to rounding effects."""
+    fds = _fds()
+    prob = _problem(shape, n, kappa, kind)
+    ref = oracle_solution(prob)
+    out = {}
+    for lag in ("1", "0"):
+        monkeypatch.setenv("FDS_GRAM_LAG", lag)
+        log(f"lagged Gram {lag}: {shape} n={n} kappa={kappa} {kind} m={restart_m}")
+        plan, rhs, bc, x = device_problem(prob, restart_m=restart_m)
+        res = fds.solve(plan, rhs, x, 1e-12, bc=bc)
+        err = compare(prob, x, ref)
+        log(f"  its={res.iterations} cycles={res.cycles} err={err:.3e} relres={res.relres_schur:.2e}")
+        assert res.status == 0, res
+        assert err <= 1e-10
+        out[lag] = res.iterations
+    assert abs(out["1"] - out["0"]) <= max(2, out["0"] // 20), out
+
+
 def test_solution_is_second_order():
     """Manufactured solution through the whole GPU path: error falls 4x per
     halving of h."""
