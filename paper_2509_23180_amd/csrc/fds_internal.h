@@ -281,7 +281,8 @@ constexpr int kPartDots = 3;  // 2(m+1) dot products
 // Behind the 2(m+1)+4 slots: the Gram reduction's first level, 2(m+1) rows of
 // ng group sums (one per kGramGroup blocks), then ng int group counters.
 constexpr int kGramGroup = 16;
-__host__ __device__ inline int gram_groups(int P) { return (P + kGramGroup - 1) / kGramGroup; }
+// (one level, ng = 1, up to 64 blocks: the partials are summed directly)
+__host__ __device__ inline int gram_groups(int P) { return P <= 64 ? 1 : (P + kGramGroup - 1) / kGramGroup; }
 __host__ __device__ inline size_t kry_partials_len(int m, int P) {
   const size_t ng = (size_t)gram_groups(P);
   return (size_t)(2 * (m + 1) + 4) * P + (size_t)2 * (m + 1) * ng + ng;

@@ -632,6 +632,24 @@ __device__ void gram_recur(const KryTask& tk, int j, double* lds) {
   }
   for (int l = threadIdx.x; l < j; l += blockDim.x) Gt[j * (j - 1) / 2 + l] = dots[l];
   __syncthreads();
+  if (nd <= 64) {
+    // one wavefront, lane i holding a_i: after step l, h_l is final and is
+    // broadcast by a lane shuffle (no workgroup barriers); the subtractions
+    // run in the same order as below
+    if (threadIdx.x < 64) {
+      const int i = threadIdx.x;
+      double ai = i < nd ? a[i] : 0.0;
+      for (int l = 0; l + 1 < nd; ++l) {
+        const double hl = __shfl(ai, l, 64);
+        if (i > l && i < nd) ai -= hl * Gt[i * (i - 1) / 2 + l];
+      }
+      if (i < nd) {
+        tk.hv[i] = ai;
+        tk.H[i + j * m1] = ai;
+      }
+    }
+    return;
+  }
   for (int l = 0; l < nd; ++l) {
     const double hl = a[l];
     __syncthreads();
@@ -716,12 +734,13 @@ __global__ void __launch_bounds__(kBlock) k_gram_dots(const KryTask* __restrict_
   if (last_block_of_problem(&tk.st->ctr_dots, ng, &lastf)) gram_solve_block(tk, j, lds, gsum, ng, ng, scratch);
 }
 
-// h_{j+1,j} = ||w||, Givens update of column j and the convergence test on
+// h_{j+1,j} = ||w|| (nrm2 = ||w||^2, summed by the caller), Givens update of
+// column j and the convergence test on
 // |g_{j+1}| (thread 0 of one block of the problem).  V[j+1] is normalised by
 // the next step's sine transform (ProbState::vscale).  When the problem's
 // cycle ends, its host-visible flag receives `tag`.
-__device__ void mgs_finish_block(const KryTask& tk, int j, int* flags, int tag, double* red,
-                                 double* col, double* cs, double* sn, double* scratch) {
+__device__ void mgs_finish_block(const KryTask& tk, int j, int* flags, int tag, double nrm2,
+                                 double* col, double* cs, double* sn) {
   ProbState* st = tk.st;
   const int m1 = tk.m + 1;
   for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = tk.H[i + j * m1];
@@ -729,8 +748,7 @@ __device__ void mgs_finish_block(const KryTask& tk, int j, int* flags, int tag, 
     cs[i] = tk.cs[i];
     sn[i] = tk.sn[i];
   }
-  reduce_rows(tk.partials + (size_t)kPartNorm * tk.P, tk.P, 1, tk.P, scratch, red);
-  const double nrm2 = red[0];
+  __syncthreads();
   if (threadIdx.x != 0) return;
   const double hn = sqrt(nrm2);
   const bool breakdown = !(hn > 1e-14 * st->beta);
@@ -840,8 +858,10 @@ __global__ void __launch_bounds__(kBlock) k_gram_update(const KryTask* __restric
   }
   const double s = block_sum(nrm, red);
   if (threadIdx.x == 0) st_agent(tk.partials + (size_t)kPartNorm * tk.P + b, s);
-  if (last_block_of_problem(&tk.st->ctr_upd, tk.P, &lastf))
-    mgs_finish_block(tk, j, flags, tag, red, col, cs, sn, scratch);
+  if (last_block_of_problem(&tk.st->ctr_upd, tk.P, &lastf)) {
+    reduce_rows(tk.partials + (size_t)kPartNorm * tk.P, tk.P, 1, tk.P, scratch, red);
+    mgs_finish_block(tk, j, flags, tag, red[0], col, cs, sn);
+  }
 }
 
 // ---- lagged Gram columns (exact preconditioner) ----------------------
@@ -907,13 +927,12 @@ __global__ void __launch_bounds__(kBlock) k_gram_update_lag(const KryTask* __res
   static_assert(kVecEPT % EU == 0, "rounds must cover the block");
   __shared__ int slot;
   __shared__ int lastf;
-  __shared__ double red[4];
   __shared__ double hs[MJ];
   __shared__ double col[122];
   __shared__ double cs[121], sn[121];
   __shared__ double scratch[kBlock];
   __shared__ double dred[MJ + 1][4];
-  __shared__ double gcol[MJ];
+  __shared__ double gcol[MJ + 1];
   const KryTask& tk = tasks[find_task(tasks, ntasks, &slot)];
   if (tk.st->cycle_done) return;
   for (int i = threadIdx.x; i < MJ; i += kBlock) hs[i] = i <= j ? tk.hv[i] : 0.0;
@@ -976,34 +995,36 @@ __global__ void __launch_bounds__(kBlock) k_gram_update_lag(const KryTask* __res
     }
   }
   __syncthreads();
+  // rows 0..j: <v_i, w>; row nd: ||w||^2 (all reduced together)
   const int P = tk.P;
   double* part = tk.partials + (size_t)kPartDots * P;
-  for (int t = threadIdx.x; t < nd; t += kBlock)
-    st_agent(part + (size_t)t * P + b, (dred[t][0] + dred[t][1]) + (dred[t][2] + dred[t][3]));
-  if (threadIdx.x == 0)
-    st_agent(tk.partials + (size_t)kPartNorm * P + b, (dred[MJ][0] + dred[MJ][1]) + (dred[MJ][2] + dred[MJ][3]));
+  for (int t = threadIdx.x; t <= nd; t += kBlock) {
+    const int r = t < nd ? t : MJ;
+    st_agent(part + (size_t)t * P + b, (dred[r][0] + dred[r][1]) + (dred[r][2] + dred[r][3]));
+  }
   const int ng = gram_groups(P);
   if (ng == 1) {
     if (!last_block_of_problem(&tk.st->ctr_upd, P, &lastf)) return;
-    reduce_rows(part, P, nd, P, scratch, gcol);
+    reduce_rows(part, P, nd + 1, P, scratch, gcol);
   } else {
     double* gsum = tk.partials + (size_t)(2 * (tk.m + 1) + 4) * P;
     int* gctr = reinterpret_cast<int*>(gsum + (size_t)2 * (tk.m + 1) * ng);
     const int g = b / kGramGroup;
     const int gb = min(kGramGroup, P - g * kGramGroup);
     if (!last_block_of_problem(gctr + g, gb, &lastf)) return;
-    reduce_rows(part + g * kGramGroup, P, nd, gb, scratch, gcol);
-    for (int t = threadIdx.x; t < nd; t += kBlock) st_agent(gsum + (size_t)t * ng + g, gcol[t]);
+    reduce_rows(part + g * kGramGroup, P, nd + 1, gb, scratch, gcol);
+    for (int t = threadIdx.x; t <= nd; t += kBlock) st_agent(gsum + (size_t)t * ng + g, gcol[t]);
     if (!last_block_of_problem(&tk.st->ctr_upd, ng, &lastf)) return;
-    reduce_rows(gsum, ng, nd, ng, scratch, gcol);
+    reduce_rows(gsum, ng, nd + 1, ng, scratch, gcol);
   }
-  mgs_finish_block(tk, j, flags, tag, red, col, cs, sn, scratch);
+  const double nrm2 = gcol[nd];
+  mgs_finish_block(tk, j, flags, tag, nrm2, col, cs, sn);
   if (threadIdx.x == 0) {
-    // red[0] holds ||w||^2, ProbState::vscale = 1 / h_{j+1,j}
+    // ProbState::vscale = 1 / h_{j+1,j}
     const double vs = tk.st->vscale;
     const int m1 = tk.m + 1;
     for (int t = 0; t < nd; ++t) tk.G[t + (j + 1) * m1] = gcol[t] * vs;
-    tk.G[(j + 1) + (j + 1) * m1] = red[0] * vs * vs;
+    tk.G[(j + 1) + (j + 1) * m1] = nrm2 * vs * vs;
   }
 }
 
