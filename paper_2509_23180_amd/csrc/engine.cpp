@@ -150,8 +150,8 @@ struct TriStage {
   void stage(Blob& b) {
     for (Sub& s : subs) b.add(s.tl);
   }
-  void launch(hipStream_t st) const {
-    for (const Sub& s : subs) launch_tri(s.c, fp32, s.tl.dev(), s.tl.n(), s.tl.nblocks, 0, st);
+  void launch(hipStream_t st, int jidx = 0) const {
+    for (const Sub& s : subs) launch_tri(s.c, fp32, s.tl.dev(), s.tl.n(), s.tl.nblocks, jidx, st);
   }
 };
 
@@ -229,14 +229,16 @@ bool gram_lag_enabled(int m, bool flex) {
 struct TaskSet {
   int m = 0;
   bool flex = false;
-  DstStage it_fwd, it_inv{DstKind::F_F}, cyc_fwd, cyc_inv, arm_fwd, arm_inv, bs_fwd;
+  DstStage it_fwd, cyc_fwd, cyc_inv, arm_fwd, arm_inv, bs_fwd;
   TriStage it_tri, cyc_tri, arm_tri;
   TaskList<LineTask> it_lines, x_lines;      // FFT line kernel (one block per line)
   TaskList<LineTask> it_lines_d, x_lines_d;  // dense line operators
   int lmax_dense = 0;
   size_t smem_lines = 0;
   TaskList<ColTask> it_cols;
-  TaskList<OpTask> it_op, res_op;
+  TaskList<OpTask> res_op;
+  TaskList<PrepTask> it_prep;        // flexible variant (sine basis of the centre)
+  TaskList<SpecOpTask> it_spec;
   TaskList<KryTask> kry;
   TaskList<LiftTask> lift, gather;
   TaskList<IfaceTask> iface_fp, iface_bs;
@@ -255,14 +257,15 @@ struct TaskSet {
   }
   void add_problem(Problem& sl);
   void upload(hipStream_t s) {
-    for (DstStage* d : {&it_fwd, &it_inv, &cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd}) d->stage(blob);
+    for (DstStage* d : {&it_fwd, &cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd}) d->stage(blob);
     for (TriStage* t : {&it_tri, &cyc_tri, &arm_tri}) t->stage(blob);
     blob.add(it_lines);
     blob.add(x_lines);
     blob.add(it_lines_d);
     blob.add(x_lines_d);
     blob.add(it_cols);
-    blob.add(it_op);
+    blob.add(it_prep);
+    blob.add(it_spec);
     blob.add(res_op);
     blob.add(kry);
     blob.add(lift);
@@ -294,46 +297,54 @@ void TaskSet::add_problem(Problem& sl) {
   const FftDesc* fftc = p->fft_c->dev;
   const int rpb_c = kBlock / dst_threads_per_row(nx);
 
-  // ---- per-iteration transforms of the centre.  The forward transform
-  // also normalises v_j (ProbState::vscale).  Plain variant: the Schur
-  // lines need z = A_c^{-1} v_j only on the centre's boundary lines, taken
-  // from the sine coefficients (rows 0 / ny-1 by a line transform, columns
-  // 0 / nx-1 by row sums).  Flexible variant: z_j = M^{-1} v_j is stored in
-  // FP32 (Z) and the operator is applied to it in full.
-  {
+  // ---- per-iteration work on the centre.  Plain variant: the forward
+  // transform normalises v_j (ProbState::vscale), the tridiagonal solve gives
+  // the sine coefficients of z = A_c^{-1} v_j, and the Schur lines need z only
+  // on the centre's boundary lines (rows 0 / ny-1 by a line transform, columns
+  // 0 / nx-1 by row sums).  Flexible variant: the Krylov basis lives in the
+  // orthonormal sine basis of the centre (Q = sqrt(2/N) S along x), so the
+  // preconditioner is the FP32 tridiagonal solve alone, z^_j is stored in
+  // FP32 (Z) and the operator is applied in that basis (k_spec_op).
+  bool west = false, east = false;
+  for (const ArmInfo& a : p->arms) { west |= a.line == 2; east |= a.line == 3; }
+  const double qscale = std::sqrt(2.0 / (nx + 1));
+  if (!flex) {
     DstTask t{};
     t.in = sl.V; t.in_js = Nc; t.in_rs = nx; t.in_cs = 1; t.in_scale = &sl.st->vscale;
-    t.out = flex ? (void*)sl.tmpf : (void*)sl.tmpd; t.out_js = 0; t.out_rs = nx; t.out_cs = 1;
+    t.out = sl.tmpd; t.out_js = 0; t.out_rs = nx; t.out_cs = 1;
     t.rows = ny; t.n = nx; t.rpb = rpb_c; t.scale = 1.0; t.fft = fftc; t.skip = skip_it;
-    t.tw_lds = dst_twiddles_in_lds(nx, flex);
+    t.tw_lds = dst_twiddles_in_lds(nx, false);
     it_fwd.add(t);
-
     TriTask tt{};
     tt.data = t.out; tt.rs = nx; tt.js = 0; tt.rows = ny; tt.modes = nx;
-    tt.coef = flex ? (const void*)p->modes_c->c32 : (const void*)p->modes_c->c64;
+    tt.coef = p->modes_c->c64;
     tt.skip = skip_it;
     it_tri.add(tt);
-
-    if (flex) {
-      DstTask v{};
-      v.in = t.out; v.in_js = 0; v.in_rs = nx; v.in_cs = 1;
-      v.out = sl.Z; v.out_js = Nc;
-      v.out_rs = nx; v.out_cs = 1;
-      v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = 1.0; v.fft = fftc; v.skip = skip_it;
-      v.tw_lds = dst_twiddles_in_lds(nx, true);
-      it_inv.add(v);
-    } else {
-      bool west = false, east = false;
-      for (const ArmInfo& a : p->arms) { west |= a.line == 2; east |= a.line == 3; }
-      if (west || east) {
-        ColTask ct{};
-        ct.y = sl.tmpd; ct.zw = west ? sl.zcols : nullptr; ct.ze = east ? sl.zcols + ny : nullptr;
-        ct.fft = fftc; ct.nx = nx; ct.ny = ny; ct.skip = skip_it;
-        add_block_task(it_cols, ct, div_up(ny, kBlock / 64));
-      }
+    if (west || east) {
+      ColTask ct{};
+      ct.y = sl.tmpd; ct.zw = west ? sl.zcols : nullptr; ct.ze = east ? sl.zcols + ny : nullptr;
+      ct.fft = fftc; ct.nx = nx; ct.ny = ny; ct.skip = skip_it; ct.scale = 1.0;
+      add_block_task(it_cols, ct, div_up(ny, kBlock / 64));
+    }
+  } else {
+    PrepTask pt{};
+    pt.v = sl.V; pt.z = sl.Z; pt.vscale = &sl.st->vscale; pt.Nc = Nc; pt.skip = skip_it;
+    add_block_task(it_prep, pt, sl.P);
+    TriTask tt{};
+    tt.data = sl.Z; tt.rs = nx; tt.js = Nc; tt.rows = ny; tt.modes = nx;
+    tt.coef = p->modes_cu->c32;
+    tt.skip = skip_it;
+    it_tri.add(tt);
+    if (west || east) {
+      ColTask ct{};
+      ct.y32 = sl.Z; ct.y_js = Nc; ct.scale = qscale;
+      ct.zw = west ? sl.zcols : nullptr; ct.ze = east ? sl.zcols + ny : nullptr;
+      ct.fft = fftc; ct.nx = nx; ct.ny = ny; ct.skip = skip_it;
+      add_block_task(it_cols, ct, div_up(ny, kBlock / 64));
     }
   }
-  // ---- end-of-cycle preconditioner apply (plain variant): u -> x_c += A_c^{-1} u
+  // ---- end of cycle.  Plain: u = V y -> x_c += A_c^{-1} u.  Flexible: u = Z y
+  // (sine coefficients) -> x_c += Q^T u; the true residual r -> v_0 = Q r.
   if (!flex) {
     DstTask t{};
     t.in = sl.u; t.in_rs = nx; t.in_cs = 1; t.out = sl.tmpd; t.out_rs = nx; t.out_cs = 1;
@@ -350,6 +361,18 @@ void TaskSet::add_problem(Problem& sl) {
     v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = 1.0; v.fft = fftc; v.skip = skip_fin;
     v.tw_lds = dst_twiddles_in_lds(nx, false);
     cyc_inv.add(v);
+  } else {
+    DstTask v{};
+    v.in = sl.u; v.in_rs = nx; v.in_cs = 1; v.out = sl.x_int + cd.off; v.out_rs = nx;
+    v.out_cs = 1; v.accumulate = 1;
+    v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = qscale; v.fft = fftc; v.skip = skip_fin;
+    v.tw_lds = dst_twiddles_in_lds(nx, false);
+    cyc_inv.add(v);
+    DstTask f{};
+    f.in = sl.u; f.in_rs = nx; f.in_cs = 1; f.out = sl.V; f.out_rs = nx; f.out_cs = 1;
+    f.rows = ny; f.n = nx; f.rpb = rpb_c; f.scale = qscale; f.fft = fftc; f.skip = skip_fin;
+    f.tw_lds = dst_twiddles_in_lds(nx, false);
+    cyc_fwd.add(f);
   }
   // ---- Schur lines and operators
   OpTask ot{};
@@ -373,24 +396,25 @@ void TaskSet::add_problem(Problem& sl) {
     smem_lines = std::max(smem_lines, line_smem_bytes(a.L));
     LineTask li = lt;
     li.skip = skip_it;
-    if (flex) {
-      li.z = sl.Z; li.z_js = Nc; li.z_f32 = 1;
-    } else if (a.line < 2) {
-      li.z = sl.tmpd; li.z_js = 0; li.z_f32 = 0; li.pre_dst = 1;   // sine coefficients of row 0 / ny-1
-    } else {
+    bool it_line = true;
+    if (flex && a.line < 2) {
+      it_line = false;   // diagonal in the centre's sine basis (k_spec_op)
+    } else if (flex || a.line >= 2) {
       li.z = sl.zcols + (a.line == 3 ? ny : 0); li.z_js = 0; li.z_f32 = 0;
       li.start = 0; li.stride = 1;
+    } else {
+      li.z = sl.tmpd; li.z_js = 0; li.z_f32 = 0; li.pre_dst = 1;   // sine coefficients of row 0 / ny-1
     }
     LineTask lx = lt;
     lx.z = sl.x_int + cd.off; lx.z_js = 0; lx.z_f32 = 0; lx.skip = skip_fin;
     if (dense_lines(a.L) && a.gs->mfull) {
       li.mat = li.pre_dst ? a.gs->mpre_t : a.gs->mfull;
       lx.mat = a.gs->mfull;
-      add_block_task(it_lines_d, li, div_up(a.L, 64));
+      if (it_line) add_block_task(it_lines_d, li, div_up(a.L, 64));
       add_block_task(x_lines_d, lx, div_up(a.L, 64));
       lmax_dense = std::max(lmax_dense, a.L);
     } else {
-      it_lines.h.push_back(li);
+      if (it_line) it_lines.h.push_back(li);
       x_lines.h.push_back(lx);
     }
 
@@ -426,15 +450,23 @@ void TaskSet::add_problem(Problem& sl) {
   iface_fp.h.push_back(fi);
   iface_bs.h.push_back(bi);
   if (flex) {
-    OpTask o = ot;
-    o.z = sl.Z; o.z_js = Nc; o.z_f32 = 1;
-    o.out = sl.V + Nc; o.out_js = Nc; o.skip = skip_it;
-    add_block_task(it_op, o, sl.P);
+    SpecOpTask so{};
+    so.z = sl.Z; so.z_js = Nc; so.out = sl.V + Nc; so.out_js = Nc;
+    for (const ArmInfo& a : p->arms) {
+      if (a.line == 0) so.gsS = a.gs->gs;
+      if (a.line == 1) so.gsN = a.gs->gs;
+    }
+    so.sW = ot.line[2];
+    so.sE = ot.line[3];
+    so.fft = fftc; so.delta = p->delta; so.kappa = p->kappa; so.nx = nx; so.ny = ny;
+    so.skip = skip_it;
+    add_block_task(it_spec, so, sl.P);
   }
   {
     OpTask r = ot;
     r.z = sl.x_int + cd.off; r.z_js = 0; r.z_f32 = 0;
-    r.out = sl.V; r.out_js = 0; r.fp = sl.fp; r.partials = sl.partials + (size_t)kPartRes * sl.P;
+    r.out = flex ? sl.u : sl.V; r.out_js = 0; r.fp = sl.fp;
+    r.partials = sl.partials + (size_t)kPartRes * sl.P;
     r.skip = skip_fin;
     add_block_task(res_op, r, sl.P);
   }
@@ -494,19 +526,21 @@ void TaskSet::add_problem(Problem& sl) {
 
 // One Arnoldi step j of every problem of the set whose cycle is running.
 void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
-  Timing::begin(0, s);
-  it_fwd.launch(j, s);
-  Timing::end(0, s);
-  Timing::begin(1, s);
-  it_tri.launch(s);
-  Timing::end(1, s);
   if (flex) {
+    Timing::begin(5, s);
+    launch_spec_prep(it_prep.dev(), it_prep.n(), it_prep.nblocks, j, s);
+    Timing::end(5, s);
+  } else {
     Timing::begin(0, s);
-    it_inv.launch(j, s);
+    it_fwd.launch(j, s);
     Timing::end(0, s);
-  } else if (it_cols.n()) {
+  }
+  Timing::begin(1, s);
+  it_tri.launch(s, flex ? j : 0);
+  Timing::end(1, s);
+  if (it_cols.n()) {
     Timing::begin(7, s);
-    launch_idst_cols(it_cols.dev(), it_cols.n(), it_cols.nblocks, s);
+    launch_idst_cols(it_cols.dev(), it_cols.n(), it_cols.nblocks, j, s);
     Timing::end(7, s);
   }
   if (it_lines.n() || it_lines_d.n()) {
@@ -517,7 +551,7 @@ void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
   }
   if (flex) {
     Timing::begin(2, s);
-    launch_operator(0, it_op.dev(), it_op.n(), it_op.nblocks, j, s);
+    launch_spec_op(it_spec.dev(), it_spec.n(), it_spec.nblocks, j, s);
     Timing::end(2, s);
   }
   Timing::begin(3, s);
@@ -533,7 +567,7 @@ void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
 
 void TaskSet::end_of_cycle(int max_cycles, hipStream_t s) const {
   Timing::begin(5, s);
-  launch_ls_solve(kry.dev(), kry.n(), s);
+  launch_ls_solve(kry.dev(), kry.n(), m, s);
   launch_combine(flex, kry.dev(), kry.n(), kry.nblocks, s);
   Timing::end(5, s);
   if (!flex) {
@@ -543,10 +577,10 @@ void TaskSet::end_of_cycle(int max_cycles, hipStream_t s) const {
     Timing::begin(1, s);
     cyc_tri.launch(s);
     Timing::end(1, s);
-    Timing::begin(0, s);
-    cyc_inv.launch(0, s);
-    Timing::end(0, s);
   }
+  Timing::begin(0, s);
+  cyc_inv.launch(0, s);
+  Timing::end(0, s);
   if (x_lines.n() || x_lines_d.n()) {
     Timing::begin(4, s);
     launch_x_lines(s);
@@ -555,6 +589,11 @@ void TaskSet::end_of_cycle(int max_cycles, hipStream_t s) const {
   Timing::begin(2, s);
   launch_operator(1, res_op.dev(), res_op.n(), res_op.nblocks, 0, s);
   Timing::end(2, s);
+  if (flex) {   // v_0 = Q r (before the restart kernels scale it)
+    Timing::begin(0, s);
+    cyc_fwd.launch(0, s);
+    Timing::end(0, s);
+  }
   Timing::begin(5, s);
   launch_restart(kry.dev(), kry.n(), kry.nblocks, 0, max_cycles, s);
   Timing::end(5, s);
@@ -735,6 +774,7 @@ void Engine::Impl::setup_phase(TaskSet& ts) {
   launch_iface(ts.iface_fp.dev(), ts.iface_fp.n(), s);
   ts.launch_x_lines(s);
   launch_operator(1, ts.res_op.dev(), ts.res_op.n(), ts.res_op.nblocks, 0, s);
+  if (flex) ts.cyc_fwd.launch(0, s);   // v_0 = Q r (sine basis of the centre)
   launch_restart(ts.kry.dev(), ts.kry.n(), ts.kry.nblocks, 1, max_cycles, s);
   FDS_HIP(hipGetLastError());
   read_states();
@@ -858,18 +898,22 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
     const int its = host_states[sl.idx].iterations - before[sl.idx].iterations;
     double lines = 0;
     for (const ArmInfo& a : sl.plan->arms) lines += line_bytes(a);
-    // per Arnoldi step: the forward transform reads v_j, writes it back
-    // normalised and writes the scratch; the tridiagonal solve reads and
-    // writes the scratch.  Flexible: the inverse transform writes z_j and
-    // the operator reads z_j and writes w.  Plain: the boundary columns read
-    // the scratch once.  Gram dots read v_0..v_j (and w if stored), the
-    // update reads v_0..v_j (and w if stored) and writes w.
-    Timing::add_bytes(0, its * Nc * (8.0 + 8.0 + wz));
-    Timing::add_bytes(1, its * Nc * 2.0 * wz);
+    // per Arnoldi step.  Plain: the forward transform reads v_j, writes it
+    // back normalised and writes the scratch; the tridiagonal solve reads and
+    // writes the scratch; the boundary columns read it once.  Flexible (sine
+    // basis): the preparation reads v_j, writes it back normalised and writes
+    // z^_j (FP32); the tridiagonal solve reads and writes z^_j; the boundary
+    // columns read it; the operator reads z^_j and writes w.  Gram dots read
+    // v_0..v_j (and w if stored), the update reads v_0..v_j (and w if
+    // stored) and writes w.
     if (flex) {
-      Timing::add_bytes(0, its * Nc * (wz + wz));
+      Timing::add_bytes(5, its * Nc * (8.0 + 8.0 + wz));
+      Timing::add_bytes(1, its * Nc * 2.0 * wz);
+      Timing::add_bytes(7, its * Nc * wz);
       Timing::add_bytes(2, its * Nc * (wz + 8.0));
     } else {
+      Timing::add_bytes(0, its * Nc * (8.0 + 8.0 + wz));
+      Timing::add_bytes(1, its * Nc * 2.0 * wz);
       Timing::add_bytes(7, its * Nc * 8.0);
     }
     Timing::add_bytes(4, its * lines);
@@ -895,6 +939,10 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
     if (!flex) {
       Timing::add_bytes(0, Nc * (16.0 + 24.0));
       Timing::add_bytes(1, Nc * 16.0);
+    } else {
+      // inverse transform of u into x (read u, read and write x); forward
+      // transform of the residual into v_0
+      Timing::add_bytes(0, Nc * (24.0 + 16.0));
     }
     Timing::add_bytes(2, Nc * 24.0);
     Timing::add_bytes(4, lines);

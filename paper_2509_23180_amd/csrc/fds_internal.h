@@ -317,6 +317,46 @@ struct ColTask {
   const int* skip;
   int block_begin;
   int pad;
+  const float* y32;           // FP32 coefficients (used instead of y when set)
+  long long y_js;             // y32 stride per Arnoldi step
+  double scale;               // factor on the sums (1: z = S y)
+};
+
+// Spectral centre operator of the flexible variant, in the orthonormal sine
+// basis of the centre's x-direction (coefficients of row r at r nx + k - 1):
+//   w^[r][k] = d (z^[r-1][k] + z^[r+1][k]) + (kappa - 4 d + 2 d cos(pi k/N)) z^[r][k]
+//             - [r = 0] (N/2) gsS[k-1] z^[0][k] - [r = ny-1] (N/2) gsN[k-1] z^[ny-1][k]
+//             - sqrt(2/N) sin(pi k/N) sW[r] - sqrt(2/N) sin(pi k nx/N) sE[r],
+// i.e. Q L_c Q^T z^ with the S/N Schur blocks diagonal in this basis and the
+// W/E line terms (physical, from the dense line operators) transformed as
+// rank-one terms per row.
+struct SpecOpTask {
+  const float* z;             // z^_j (FP32), step stride z_js
+  long long z_js;
+  double* out;                // w^ (FP64), step stride out_js
+  long long out_js;
+  const double* gsS;          // delta^2 (2/N) g_k of the S / N arm, or NULL
+  const double* gsN;
+  const double* sW;           // line terms on column 0 / nx-1 (ny values), or NULL
+  const double* sE;
+  const FftDesc* fft;         // post64[k] = (cos, sin)(pi k / N)
+  double delta, kappa;
+  int nx, ny;
+  const int* skip;
+  int block_begin;
+  int pad;
+};
+
+// z^_j = FP32(v_j * vscale) and v_j *= vscale (the basis vector is
+// normalised in place, as the forward transform of the plain variant does).
+struct PrepTask {
+  double* v;                  // V base, step stride Nc
+  float* z;                   // Z base, step stride Nc
+  const double* vscale;
+  long long Nc;
+  const int* skip;
+  int block_begin;
+  int pad;
 };
 
 struct LiftTask {

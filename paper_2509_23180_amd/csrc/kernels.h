@@ -82,8 +82,13 @@ void launch_gram_bdots(const KryTask* tasks, int ntasks, int j, hipStream_t s);
 void launch_gram_update_lag(const KryTask* tasks, int ntasks, int nblocks, int m, int j, int* flags,
                             int tag, hipStream_t s);
 void launch_scale_newest(const KryTask* tasks, int j, int nblocks, hipStream_t s);
-void launch_idst_cols(const ColTask* tasks, int ntasks, int nblocks, hipStream_t s);
-void launch_ls_solve(const KryTask* tasks, int ntasks, hipStream_t s);
+void launch_idst_cols(const ColTask* tasks, int ntasks, int nblocks, int jidx, hipStream_t s);
+// Flexible variant in the centre's sine basis: operator and basis preparation.
+void launch_spec_op(const SpecOpTask* tasks, int ntasks, int nblocks, int jidx, hipStream_t s);
+void launch_spec_prep(const PrepTask* tasks, int ntasks, int nblocks, int jidx, hipStream_t s);
+// Hessenberg least squares (back substitution), one workgroup per problem;
+// m is the restart length of every task.
+void launch_ls_solve(const KryTask* tasks, int ntasks, int m, hipStream_t s);
 void launch_combine(bool flex, const KryTask* tasks, int ntasks, int nblocks, hipStream_t s);
 void launch_restart(const KryTask* tasks, int ntasks, int nblocks, int initial, int max_cycles,
                     hipStream_t s);

@@ -418,26 +418,94 @@ __global__ void __launch_bounds__(kBlock) k_lines_dense(const LineTask* __restri
 }
 
 // Boundary columns of z = S y (see ColTask): one wave per row.
-__global__ void __launch_bounds__(kBlock) k_idst_cols(const ColTask* __restrict__ tasks, int ntasks) {
+__global__ void __launch_bounds__(kBlock) k_idst_cols(const ColTask* __restrict__ tasks, int ntasks,
+                                                       int jidx) {
   __shared__ int slot;
   const ColTask& tk = tasks[find_task(tasks, ntasks, &slot)];
   if (tk.skip && *tk.skip) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = (blockIdx.x - tk.block_begin) * (kBlock / 64) + wave;
   if (r >= tk.ny) return;
-  const double* y = tk.y + (long long)r * tk.nx;
   const double2* post = tk.fft->post64;
   double odd = 0.0, even = 0.0;   // k odd / k even (k = 1..nx)
-  for (int k = 1 + lane; k <= tk.nx; k += 64) {
-    const double v = y[k - 1] * post[k].y;
-    if (k & 1) odd += v;
-    else even += v;
+  if (tk.y32) {
+    const float* y = tk.y32 + (long long)jidx * tk.y_js + (long long)r * tk.nx;
+    for (int k = 1 + lane; k <= tk.nx; k += 64) {
+      const double v = double(y[k - 1]) * post[k].y;
+      if (k & 1) odd += v;
+      else even += v;
+    }
+  } else {
+    const double* y = tk.y + (long long)r * tk.nx;
+    for (int k = 1 + lane; k <= tk.nx; k += 64) {
+      const double v = y[k - 1] * post[k].y;
+      if (k & 1) odd += v;
+      else even += v;
+    }
   }
   odd = wave_sum(odd);
   even = wave_sum(even);
   if (lane == 0) {
-    if (tk.zw) tk.zw[r] = odd + even;
-    if (tk.ze) tk.ze[r] = odd - even;
+    if (tk.zw) tk.zw[r] = tk.scale * (odd + even);
+    if (tk.ze) tk.ze[r] = tk.scale * (odd - even);
+  }
+}
+
+// Spectral centre operator of the flexible variant (see SpecOpTask).
+__global__ void __launch_bounds__(kBlock) k_spec_op(const SpecOpTask* __restrict__ tasks, int ntasks,
+                                                     int jidx) {
+  __shared__ int slot;
+  const SpecOpTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  if (tk.skip && *tk.skip) return;
+  const int b = blockIdx.x - tk.block_begin;
+  const int nx = tk.nx, ny = tk.ny;
+  const long long Nc = (long long)nx * ny;
+  const int N = nx + 1;
+  const double d = tk.delta;
+  const double qs = sqrt(2.0 / N), half = 0.5 * N;
+  const float* z = tk.z + (long long)jidx * tk.z_js;
+  double* out = tk.out + (long long)jidx * tk.out_js;
+  const double2* post = tk.fft->post64;
+  const long long base = (long long)b * kVecPerBlock;
+#pragma unroll
+  for (int e = 0; e < kVecEPT; ++e) {
+    const long long idx = base + (long long)e * kBlock + threadIdx.x;
+    if (idx >= Nc) break;
+    const int r = (int)(idx / nx);
+    const int c = (int)(idx - (long long)r * nx);
+    const int kk = c + 1;
+    const double2 cs = post[kk];
+    const double zc = double(z[idx]);
+    double nb = 0.0;
+    if (r > 0) nb += double(z[idx - nx]);
+    if (r < ny - 1) nb += double(z[idx + nx]);
+    double w = d * nb + (tk.kappa - 4.0 * d + 2.0 * d * cs.x) * zc;
+    if (r == 0 && tk.gsS) w -= half * tk.gsS[c] * zc;
+    if (r == ny - 1 && tk.gsN) w -= half * tk.gsN[c] * zc;
+    if (tk.sW) w -= qs * cs.y * tk.sW[r];
+    if (tk.sE) w -= qs * ((kk & 1) ? cs.y : -cs.y) * tk.sE[r];
+    out[idx] = w;
+  }
+}
+
+// z^_j = FP32(v_j vscale), v_j *= vscale (see PrepTask).
+__global__ void __launch_bounds__(kBlock) k_spec_prep(const PrepTask* __restrict__ tasks, int ntasks,
+                                                       int jidx) {
+  __shared__ int slot;
+  const PrepTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  if (tk.skip && *tk.skip) return;
+  const double sc = *tk.vscale;
+  double* v = tk.v + (long long)jidx * tk.Nc;
+  float* z = tk.z + (long long)jidx * tk.Nc;
+  const long long base = (long long)(blockIdx.x - tk.block_begin) * kVecPerBlock;
+#pragma unroll
+  for (int e = 0; e < kVecEPT; ++e) {
+    const long long idx = base + (long long)e * kBlock + threadIdx.x;
+    if (idx < tk.Nc) {
+      const double x = v[idx] * sc;
+      v[idx] = x;
+      z[idx] = float(x);
+    }
   }
 }
 
@@ -1038,23 +1106,40 @@ __global__ void k_scale_newest(const KryTask* __restrict__ tasks, int j) {
     w[i] *= s;
 }
 
-// Back substitution R y = g over the j_done columns (one thread per problem).
-__global__ void k_ls_solve(const KryTask* __restrict__ tasks, int ntasks) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntasks) return;
-  const KryTask& tk = tasks[t];
+// Back substitution R y = g over the j_done columns.
+__global__ void __launch_bounds__(kBlock) k_ls_solve(const KryTask* __restrict__ tasks, int ntasks) {
+  // one workgroup per problem: the triangle of H is staged in LDS with every
+  // thread (column l at l k), then one wavefront back-substitutes; lane i
+  // (and i + 64) holds the running right-hand side s_i, and y_i, once
+  // final, is broadcast by a lane shuffle
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Hs = reinterpret_cast<double*>(smem_raw);
+  const KryTask& tk = tasks[blockIdx.x];
   if (tk.st->finished) return;
   const int k = tk.st->j_done;
   const int m1 = tk.m + 1;
+  for (int e = threadIdx.x; e < k * k; e += kBlock) {
+    const int l = e / k, i = e - l * k;
+    Hs[e] = i <= l ? tk.H[i + l * m1] : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  const int i0 = lane, i1 = lane + 64;
+  double s0 = i0 < k ? tk.g[i0] : 0.0;
+  double s1 = i1 < k ? tk.g[i1] : 0.0;
   for (int i = k - 1; i >= 0; --i) {
-    double s = tk.g[i];
-    for (int l = i + 1; l < k; ++l) s -= tk.H[i + l * m1] * tk.y[l];
-    const double d = tk.H[i + i * m1];
-    tk.y[i] = (d != 0.0) ? s / d : 0.0;
+    const double d = Hs[i + i * k];
+    const double si = __shfl(i < 64 ? s0 : s1, i & 63, 64);
+    const double yi = (d != 0.0) ? si / d : 0.0;
+    if (lane == (i & 63)) tk.y[i] = yi;
+    if (i0 < i) s0 -= Hs[i0 + i * k] * yi;
+    if (i1 < i) s1 -= Hs[i1 + i * k] * yi;
   }
 }
 
-// u = V y (plain variant) or x += Z y (flexible variant).
+// u = V y (plain variant) or u = Z y (flexible variant, sine coefficients);
+// the preconditioner / inverse transform then adds it to x.
 template <int FLEX>
 __global__ void __launch_bounds__(kBlock) k_combine(const KryTask* __restrict__ tasks, int ntasks) {
   __shared__ int slot;
@@ -1074,7 +1159,7 @@ __global__ void __launch_bounds__(kBlock) k_combine(const KryTask* __restrict__ 
       double acc = 0.0;
       if (FLEX) {
         for (int i = 0; i < k; ++i) acc += ys[i] * double(tk.Z[(long long)i * Nc + idx]);
-        tk.x[idx] += acc;
+        tk.u[idx] = acc;
       } else {
         for (int i = 0; i < k; ++i) acc += ys[i] * tk.V[(long long)i * Nc + idx];
         tk.u[idx] = acc;
@@ -1493,14 +1578,29 @@ void launch_scale_newest(const KryTask* tasks, int j, int nblocks, hipStream_t s
   FDS_LAUNCH(k_scale_newest, dim3(nblocks), dim3(kBlock), 0, s, tasks, j);
 }
 
-void launch_idst_cols(const ColTask* tasks, int ntasks, int nblocks, hipStream_t s) {
+void launch_idst_cols(const ColTask* tasks, int ntasks, int nblocks, int jidx, hipStream_t s) {
   if (nblocks <= 0) return;
-  FDS_LAUNCH(k_idst_cols, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
+  FDS_LAUNCH(k_idst_cols, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
 }
 
-void launch_ls_solve(const KryTask* tasks, int ntasks, hipStream_t s) {
+void launch_spec_op(const SpecOpTask* tasks, int ntasks, int nblocks, int jidx, hipStream_t s) {
+  if (nblocks <= 0) return;
+  FDS_LAUNCH(k_spec_op, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
+}
+
+void launch_spec_prep(const PrepTask* tasks, int ntasks, int nblocks, int jidx, hipStream_t s) {
+  if (nblocks <= 0) return;
+  FDS_LAUNCH(k_spec_prep, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
+}
+
+void launch_ls_solve(const KryTask* tasks, int ntasks, int m, hipStream_t s) {
   if (ntasks <= 0) return;
-  FDS_LAUNCH(k_ls_solve, dim3((ntasks + 63) / 64), dim3(64), 0, s, tasks, ntasks);
+  if (m < 1 || m > 120) throw Error(FDS_E_INVALID_ARG, "restart length out of range");
+  // LDS: the k x k triangle of H, k <= m <= 120 (opt-in above 64 KiB)
+  const size_t smem = sizeof(double) * (size_t)m * m;
+  static size_t granted = 0;
+  ensure_smem(k_ls_solve, smem, &granted);
+  FDS_LAUNCH(k_ls_solve, dim3(ntasks), dim3(kBlock), smem, s, tasks, ntasks);
 }
 
 void launch_combine(bool flex, const KryTask* tasks, int ntasks, int nblocks, hipStream_t s) {

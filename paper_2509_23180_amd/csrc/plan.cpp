@@ -201,6 +201,7 @@ fds_plan* create_plan(const fds_rect* rects, int nrect, double h, double kappa,
       (void)dst_choice(len, true);
     }
     p->modes_c = tc.modes(p->nx, p->ny, h, kappa);
+    p->modes_cu = tc.modes(p->nx, p->ny, h, kappa, true);
     for (int r = 0; r < nrect; ++r) {
       if (r == c) continue;
       ArmInfo ai{};

@@ -99,7 +99,9 @@ class TableCache {
  public:
   static TableCache& get();
   std::shared_ptr<FftTable> fft(int n);
-  std::shared_ptr<ModeTable> modes(int n, int m, double h, double kappa);
+  // unit: solve T_k y = r exactly (coefficients in the orthonormal sine
+  // basis); otherwise the DST normalisation 2/(n+1) is folded in.
+  std::shared_ptr<ModeTable> modes(int n, int m, double h, double kappa, bool unit = false);
   std::shared_ptr<GsTable> gs(int n, int m, double h, double kappa);
   // wave-transform descriptor of the table whose device FftDesc is `dev`
   WaveDesc wave_desc(const FftDesc* dev, bool fp32);
@@ -108,7 +110,7 @@ class TableCache {
   std::mutex mu_;
   std::map<std::pair<int, int>, std::shared_ptr<FftTable>> fft_;
   std::map<const FftDesc*, std::shared_ptr<FftTable>> by_dev_;
-  std::map<std::tuple<int, int, int, double, double>, std::shared_ptr<ModeTable>> modes_;
+  std::map<std::tuple<int, int, int, double, double, bool>, std::shared_ptr<ModeTable>> modes_;
   std::map<std::tuple<int, int, int, double, double>, std::shared_ptr<GsTable>> gs_;
 };
 
@@ -207,6 +209,7 @@ struct fds_plan {
   std::vector<long long> user_off, bc_off;
   std::shared_ptr<fds::FftTable> fft_c;
   std::shared_ptr<fds::ModeTable> modes_c;
+  std::shared_ptr<fds::ModeTable> modes_cu;   // centre, unit scale (flexible variant)
   double floor_coef = 0;
   size_t footprint(int m, int precision) const;
 };

@@ -700,15 +700,15 @@ std::shared_ptr<ModeTable> upload_modes(const std::vector<ModeCoef<double>>& c64
   return t;
 }
 
-std::shared_ptr<ModeTable> TableCache::modes(int n, int m, double h, double kappa) {
+std::shared_ptr<ModeTable> TableCache::modes(int n, int m, double h, double kappa, bool unit) {
   const int dev = current_device();
   std::lock_guard<std::mutex> lk(mu_);
-  auto key = std::make_tuple(dev, n, m, h, kappa);
+  auto key = std::make_tuple(dev, n, m, h, kappa, unit);
   auto it = modes_.find(key);
   if (it != modes_.end()) return it->second;
   std::vector<ModeCoef<double>> c64;
   std::vector<ModeCoef<float>> c32;
-  mode_coefs_host(n, m, h, kappa, 2.0 / (n + 1), c64, c32);
+  mode_coefs_host(n, m, h, kappa, unit ? 1.0 : 2.0 / (n + 1), c64, c32);
   auto t = upload_modes(c64, c32);
   modes_[key] = t;
   return t;
