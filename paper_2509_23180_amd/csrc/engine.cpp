@@ -158,7 +158,7 @@ struct TriStage {
 // Buffer layout of one problem, shared by allocation and footprint queries.
 struct SlotLayout {
   size_t b_int, x_int, tmpd, fp, V, u, zbuf, lines, small, partials, respart, Z, tmpf, gram, zcols,
-      total;
+      bc, total;
 };
 
 int res_blocks_of(const fds_plan* p) {
@@ -188,6 +188,7 @@ SlotLayout layout_of(const fds_plan* p, int m, int precision) {
   L.partials = take(8 * kry_partials_len(m, P));
   L.gram = take(8 * ((size_t)(m + 1) * (m + 1) + (m + 1)));
   L.zcols = take(8 * 2 * (size_t)p->ny);
+  L.bc = flex ? 0 : take(8 * 2 * (size_t)p->ny * (m + 1));
   L.respart = take(8 * 2 * (size_t)res_blocks_of(p));
   L.Z = flex ? take(4 * (size_t)m * Nc) : 0;
   L.tmpf = flex ? take(4 * Nc) : 0;
@@ -207,7 +208,7 @@ struct Problem {
   double *b_int = nullptr, *x_int = nullptr, *tmpd = nullptr, *fp = nullptr, *V = nullptr,
          *u = nullptr, *zbuf = nullptr, *lines = nullptr, *H = nullptr, *cs = nullptr,
          *sn = nullptr, *g = nullptr, *y = nullptr, *partials = nullptr, *respart = nullptr,
-         *G = nullptr, *hv = nullptr, *zcols = nullptr;
+         *G = nullptr, *hv = nullptr, *zcols = nullptr, *bc = nullptr;
   float *Z = nullptr, *tmpf = nullptr;
   ProbState* st = nullptr;
   long long Nc = 0, Nint = 0;
@@ -229,7 +230,7 @@ bool gram_lag_enabled(int m, bool flex) {
 struct TaskSet {
   int m = 0;
   bool flex = false;
-  DstStage it_fwd, cyc_fwd, cyc_inv, arm_fwd, arm_inv, bs_fwd;
+  DstStage cyc_fwd, cyc_inv, arm_fwd, arm_inv, bs_fwd;
   TriStage it_tri, cyc_tri, arm_tri;
   TaskList<LineTask> it_lines, x_lines;      // FFT line kernel (one block per line)
   TaskList<LineTask> it_lines_d, x_lines_d;  // dense line operators
@@ -251,13 +252,12 @@ struct TaskSet {
   bool lag = false;   // lagged Gram columns (exact preconditioner, m <= kLagMaxJ)
 
   TaskSet(int m_, bool flex_) : m(m_), flex(flex_) {
-    it_fwd.kind = flex ? DstKind::D_F : DstKind::D_D;
     it_tri.fp32 = flex;
     lag = gram_lag_enabled(m_, flex_);
   }
   void add_problem(Problem& sl);
   void upload(hipStream_t s) {
-    for (DstStage* d : {&it_fwd, &cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd}) d->stage(blob);
+    for (DstStage* d : {&cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd}) d->stage(blob);
     for (TriStage* t : {&it_tri, &cyc_tri, &arm_tri}) t->stage(blob);
     blob.add(it_lines);
     blob.add(x_lines);
@@ -297,71 +297,49 @@ void TaskSet::add_problem(Problem& sl) {
   const FftDesc* fftc = p->fft_c->dev;
   const int rpb_c = kBlock / dst_threads_per_row(nx);
 
-  // ---- per-iteration work on the centre.  Plain variant: the forward
-  // transform normalises v_j (ProbState::vscale), the tridiagonal solve gives
-  // the sine coefficients of z = A_c^{-1} v_j, and the Schur lines need z only
-  // on the centre's boundary lines (rows 0 / ny-1 by a line transform, columns
-  // 0 / nx-1 by row sums).  Flexible variant: the Krylov basis lives in the
-  // orthonormal sine basis of the centre (Q = sqrt(2/N) S along x), so the
-  // preconditioner is the FP32 tridiagonal solve alone, z^_j is stored in
-  // FP32 (Z) and the operator is applied in that basis (k_spec_op).
+  // ---- per-iteration work on the centre.  The Krylov basis of both variants
+  // lives in the orthonormal sine basis of the centre (Q = sqrt(2/N) S along
+  // x), so the preconditioner A_c^{-1} = Q^T T^{-1} Q reduces to the
+  // tridiagonal solve per mode.  The preparation normalises v_j in place
+  // (ProbState::vscale) and copies it to the solve's buffer: FP64 scratch
+  // (plain) or z^_j in FP32 (flexible, Z).  The W/E Schur lines need z on
+  // the centre's columns 0 / nx-1 (row sums of z^); the plain variant also
+  // keeps the physical boundary columns of v_j for <v_i, s>.
   bool west = false, east = false;
   for (const ArmInfo& a : p->arms) { west |= a.line == 2; east |= a.line == 3; }
   const double qscale = std::sqrt(2.0 / (nx + 1));
-  if (!flex) {
-    DstTask t{};
-    t.in = sl.V; t.in_js = Nc; t.in_rs = nx; t.in_cs = 1; t.in_scale = &sl.st->vscale;
-    t.out = sl.tmpd; t.out_js = 0; t.out_rs = nx; t.out_cs = 1;
-    t.rows = ny; t.n = nx; t.rpb = rpb_c; t.scale = 1.0; t.fft = fftc; t.skip = skip_it;
-    t.tw_lds = dst_twiddles_in_lds(nx, false);
-    it_fwd.add(t);
-    TriTask tt{};
-    tt.data = t.out; tt.rs = nx; tt.js = 0; tt.rows = ny; tt.modes = nx;
-    tt.coef = p->modes_c->c64;
-    tt.skip = skip_it;
-    it_tri.add(tt);
-    if (west || east) {
-      ColTask ct{};
-      ct.y = sl.tmpd; ct.zw = west ? sl.zcols : nullptr; ct.ze = east ? sl.zcols + ny : nullptr;
-      ct.fft = fftc; ct.nx = nx; ct.ny = ny; ct.skip = skip_it; ct.scale = 1.0;
-      add_block_task(it_cols, ct, div_up(ny, kBlock / 64));
-    }
-  } else {
+  {
     PrepTask pt{};
-    pt.v = sl.V; pt.z = sl.Z; pt.vscale = &sl.st->vscale; pt.Nc = Nc; pt.skip = skip_it;
+    pt.v = sl.V; pt.vscale = &sl.st->vscale; pt.Nc = Nc; pt.skip = skip_it;
+    if (flex) pt.z = sl.Z;
+    else pt.zd = sl.tmpd;
     add_block_task(it_prep, pt, sl.P);
     TriTask tt{};
-    tt.data = sl.Z; tt.rs = nx; tt.js = Nc; tt.rows = ny; tt.modes = nx;
-    tt.coef = p->modes_cu->c32;
+    tt.data = flex ? (void*)sl.Z : (void*)sl.tmpd; tt.rs = nx; tt.js = flex ? Nc : 0;
+    tt.rows = ny; tt.modes = nx;
+    tt.coef = flex ? (const void*)p->modes_cu->c32 : (const void*)p->modes_cu->c64;
     tt.skip = skip_it;
     it_tri.add(tt);
     if (west || east) {
       ColTask ct{};
-      ct.y32 = sl.Z; ct.y_js = Nc; ct.scale = qscale;
+      if (flex) { ct.y32 = sl.Z; ct.y_js = Nc; }
+      else { ct.y = sl.tmpd; ct.v = sl.V; ct.bc = sl.bc; ct.Nc = Nc; }
+      ct.scale = qscale;
       ct.zw = west ? sl.zcols : nullptr; ct.ze = east ? sl.zcols + ny : nullptr;
       ct.fft = fftc; ct.nx = nx; ct.ny = ny; ct.skip = skip_it;
       add_block_task(it_cols, ct, div_up(ny, kBlock / 64));
     }
   }
-  // ---- end of cycle.  Plain: u = V y -> x_c += A_c^{-1} u.  Flexible: u = Z y
-  // (sine coefficients) -> x_c += Q^T u; the true residual r -> v_0 = Q r.
-  if (!flex) {
-    DstTask t{};
-    t.in = sl.u; t.in_rs = nx; t.in_cs = 1; t.out = sl.tmpd; t.out_rs = nx; t.out_cs = 1;
-    t.rows = ny; t.n = nx; t.rpb = rpb_c; t.scale = 1.0; t.fft = fftc; t.skip = skip_fin;
-    t.tw_lds = dst_twiddles_in_lds(nx, false);
-    cyc_fwd.add(t);
-    TriTask tt{};
-    tt.data = sl.tmpd; tt.rs = nx; tt.rows = ny; tt.modes = nx; tt.coef = p->modes_c->c64;
-    tt.skip = skip_fin;
-    cyc_tri.add(tt);
-    DstTask v{};
-    v.in = sl.tmpd; v.in_rs = nx; v.in_cs = 1; v.out = sl.x_int + cd.off; v.out_rs = nx;
-    v.out_cs = 1; v.accumulate = 1;
-    v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = 1.0; v.fft = fftc; v.skip = skip_fin;
-    v.tw_lds = dst_twiddles_in_lds(nx, false);
-    cyc_inv.add(v);
-  } else {
+  // ---- end of cycle: u = V y (plain) or Z y (flexible), sine coefficients;
+  // plain: u = T^{-1} u; then x_c += Q^T u.  The true residual r (in u) then
+  // becomes v_0 = Q r.
+  {
+    if (!flex) {
+      TriTask tt{};
+      tt.data = sl.u; tt.rs = nx; tt.rows = ny; tt.modes = nx; tt.coef = p->modes_cu->c64;
+      tt.skip = skip_fin;
+      cyc_tri.add(tt);
+    }
     DstTask v{};
     v.in = sl.u; v.in_rs = nx; v.in_cs = 1; v.out = sl.x_int + cd.off; v.out_rs = nx;
     v.out_cs = 1; v.accumulate = 1;
@@ -396,15 +374,11 @@ void TaskSet::add_problem(Problem& sl) {
     smem_lines = std::max(smem_lines, line_smem_bytes(a.L));
     LineTask li = lt;
     li.skip = skip_it;
-    bool it_line = true;
-    if (flex && a.line < 2) {
-      it_line = false;   // diagonal in the centre's sine basis (k_spec_op)
-    } else if (flex || a.line >= 2) {
-      li.z = sl.zcols + (a.line == 3 ? ny : 0); li.z_js = 0; li.z_f32 = 0;
-      li.start = 0; li.stride = 1;
-    } else {
-      li.z = sl.tmpd; li.z_js = 0; li.z_f32 = 0; li.pre_dst = 1;   // sine coefficients of row 0 / ny-1
-    }
+    // S/N blocks are diagonal in the centre's sine basis (k_spec_op, and
+    // qs terms in the plain Arnoldi step): no line term per step
+    const bool it_line = a.line >= 2;
+    li.z = sl.zcols + (a.line == 3 ? ny : 0); li.z_js = 0; li.z_f32 = 0;
+    li.start = 0; li.stride = 1;
     LineTask lx = lt;
     lx.z = sl.x_int + cd.off; lx.z_js = 0; lx.z_f32 = 0; lx.skip = skip_fin;
     if (dense_lines(a.L) && a.gs->mfull) {
@@ -465,7 +439,7 @@ void TaskSet::add_problem(Problem& sl) {
   {
     OpTask r = ot;
     r.z = sl.x_int + cd.off; r.z_js = 0; r.z_f32 = 0;
-    r.out = flex ? sl.u : sl.V; r.out_js = 0; r.fp = sl.fp;
+    r.out = sl.u; r.out_js = 0; r.fp = sl.fp;
     r.partials = sl.partials + (size_t)kPartRes * sl.P;
     r.skip = skip_fin;
     add_block_task(res_op, r, sl.P);
@@ -478,7 +452,16 @@ void TaskSet::add_problem(Problem& sl) {
     k.flag_idx = sl.idx;
     k.gram_lag = lag ? 1 : 0;
     k.implicit_w = flex ? 0 : 1;
-    for (int q = 0; q < 4; ++q) k.line[q] = ot.line[q];
+    for (int q = 0; q < 4; ++q) k.line[q] = (q >= 2 && !flex) ? ot.line[q] : nullptr;
+    if (!flex) {
+      for (const ArmInfo& a : p->arms)
+        if (a.line < 2) k.gs[a.line] = a.gs->gs;
+      k.zhat = sl.tmpd;
+      k.post = p->fft_c->host.post64;
+      k.bc = sl.bc;
+      k.qscale = qscale;
+      k.half_n = 0.5 * (nx + 1);
+    }
     add_block_task(kry, k, sl.P);
   }
   // ---- layout conversion and composite residual
@@ -526,15 +509,9 @@ void TaskSet::add_problem(Problem& sl) {
 
 // One Arnoldi step j of every problem of the set whose cycle is running.
 void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
-  if (flex) {
-    Timing::begin(5, s);
-    launch_spec_prep(it_prep.dev(), it_prep.n(), it_prep.nblocks, j, s);
-    Timing::end(5, s);
-  } else {
-    Timing::begin(0, s);
-    it_fwd.launch(j, s);
-    Timing::end(0, s);
-  }
+  Timing::begin(5, s);
+  launch_spec_prep(it_prep.dev(), it_prep.n(), it_prep.nblocks, j, s);
+  Timing::end(5, s);
   Timing::begin(1, s);
   it_tri.launch(s, flex ? j : 0);
   Timing::end(1, s);
@@ -571,9 +548,6 @@ void TaskSet::end_of_cycle(int max_cycles, hipStream_t s) const {
   launch_combine(flex, kry.dev(), kry.n(), kry.nblocks, s);
   Timing::end(5, s);
   if (!flex) {
-    Timing::begin(0, s);
-    cyc_fwd.launch(0, s);
-    Timing::end(0, s);
     Timing::begin(1, s);
     cyc_tri.launch(s);
     Timing::end(1, s);
@@ -589,11 +563,9 @@ void TaskSet::end_of_cycle(int max_cycles, hipStream_t s) const {
   Timing::begin(2, s);
   launch_operator(1, res_op.dev(), res_op.n(), res_op.nblocks, 0, s);
   Timing::end(2, s);
-  if (flex) {   // v_0 = Q r (before the restart kernels scale it)
-    Timing::begin(0, s);
-    cyc_fwd.launch(0, s);
-    Timing::end(0, s);
-  }
+  Timing::begin(0, s);   // v_0 = Q r (before the restart kernels scale it)
+  cyc_fwd.launch(0, s);
+  Timing::end(0, s);
   Timing::begin(5, s);
   launch_restart(kry.dev(), kry.n(), kry.nblocks, 0, max_cycles, s);
   Timing::end(5, s);
@@ -722,6 +694,7 @@ void Engine::admit(const std::vector<SolveRequest>& reqs, const std::vector<int>
     sl.G = sl.mem.as<double>(L.gram);
     sl.hv = sl.G + (size_t)(m + 1) * (m + 1);
     sl.zcols = sl.mem.as<double>(L.zcols);
+    sl.bc = flex ? nullptr : sl.mem.as<double>(L.bc);
     sl.Z = flex ? sl.mem.as<float>(L.Z) : nullptr;
     sl.tmpf = flex ? sl.mem.as<float>(L.tmpf) : nullptr;
     sl.st = I.states.as<ProbState>() + sl.idx;
@@ -774,7 +747,7 @@ void Engine::Impl::setup_phase(TaskSet& ts) {
   launch_iface(ts.iface_fp.dev(), ts.iface_fp.n(), s);
   ts.launch_x_lines(s);
   launch_operator(1, ts.res_op.dev(), ts.res_op.n(), ts.res_op.nblocks, 0, s);
-  if (flex) ts.cyc_fwd.launch(0, s);   // v_0 = Q r (sine basis of the centre)
+  ts.cyc_fwd.launch(0, s);   // v_0 = Q r (sine basis of the centre)
   launch_restart(ts.kry.dev(), ts.kry.n(), ts.kry.nblocks, 1, max_cycles, s);
   FDS_HIP(hipGetLastError());
   read_states();
@@ -898,23 +871,20 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
     const int its = host_states[sl.idx].iterations - before[sl.idx].iterations;
     double lines = 0;
     for (const ArmInfo& a : sl.plan->arms) lines += line_bytes(a);
-    // per Arnoldi step.  Plain: the forward transform reads v_j, writes it
-    // back normalised and writes the scratch; the tridiagonal solve reads and
-    // writes the scratch; the boundary columns read it once.  Flexible (sine
-    // basis): the preparation reads v_j, writes it back normalised and writes
-    // z^_j (FP32); the tridiagonal solve reads and writes z^_j; the boundary
-    // columns read it; the operator reads z^_j and writes w.  Gram dots read
+    // per Arnoldi step (sine basis): the preparation reads v_j, writes it
+    // back normalised and writes the solve buffer (FP64 plain, FP32 z^_j
+    // flexible); the tridiagonal solve reads and writes it; the boundary
+    // columns read it (plain: and v_j); flexible: the operator reads z^_j and
+    // writes w.  Gram dots read
     // v_0..v_j (and w if stored), the update reads v_0..v_j (and w if
     // stored) and writes w.
+    Timing::add_bytes(5, its * Nc * (8.0 + 8.0 + wz));
+    Timing::add_bytes(1, its * Nc * 2.0 * wz);
     if (flex) {
-      Timing::add_bytes(5, its * Nc * (8.0 + 8.0 + wz));
-      Timing::add_bytes(1, its * Nc * 2.0 * wz);
       Timing::add_bytes(7, its * Nc * wz);
       Timing::add_bytes(2, its * Nc * (wz + 8.0));
     } else {
-      Timing::add_bytes(0, its * Nc * (8.0 + 8.0 + wz));
-      Timing::add_bytes(1, its * Nc * 2.0 * wz);
-      Timing::add_bytes(7, its * Nc * 8.0);
+      Timing::add_bytes(7, its * Nc * 16.0);   // z^ and v_j row sums
     }
     Timing::add_bytes(4, its * lines);
     double dots = 0, upd = 0;
@@ -936,14 +906,10 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
     // end of cycle: plain variant applies A_c^{-1} to V y (transforms and
     // tridiagonal solve in FP64, accumulate into x); residual operator reads
     // x and f', writes r; line terms of x
-    if (!flex) {
-      Timing::add_bytes(0, Nc * (16.0 + 24.0));
-      Timing::add_bytes(1, Nc * 16.0);
-    } else {
-      // inverse transform of u into x (read u, read and write x); forward
-      // transform of the residual into v_0
-      Timing::add_bytes(0, Nc * (24.0 + 16.0));
-    }
+    // inverse transform of u into x (read u, read and write x), forward
+    // transform of the residual into v_0; plain: the solve on u
+    Timing::add_bytes(0, Nc * (24.0 + 16.0));
+    if (!flex) Timing::add_bytes(1, Nc * 16.0);
     Timing::add_bytes(2, Nc * 24.0);
     Timing::add_bytes(4, lines);
   }

@@ -266,6 +266,18 @@ struct KryTask {
   const double* line[4];      // Schur line terms s on the centre's boundary lines (or NULL)
   int flag_idx;               // slot of this problem in the host-visible flag array
   int gram_lag;               // 1: Gram columns come from the update pass (see kLagMaxJ)
+  // Plain variant in the centre's orthonormal sine basis: the Schur term of
+  // w = v_j - Q s (see qs_term) takes the S/N blocks as per-mode scalings of
+  // the solve's sine coefficients z^ (rows 0 and ny-1) and the W/E line
+  // terms line[2] / line[3] as rank-one terms per row; line[0] / line[1] are
+  // then NULL.  bc holds the physical values of every basis vector on
+  // columns 0 and nx-1 (vector i at bc + 2 ny i, W then E) for <v_i, s>.
+  const double* gs[2];        // delta^2 (2/N) g_k of the S / N arm, or NULL
+  const double* zhat;         // z^ (ny x nx)
+  const double2* post;        // (cos, sin)(pi k / N), k = 0..N
+  double* bc;
+  double qscale;              // sqrt(2/N)
+  double half_n;              // N/2
 };
 
 // Lagged Gram columns (exact preconditioner, restart length <= kLagMaxJ):
@@ -320,6 +332,9 @@ struct ColTask {
   const float* y32;           // FP32 coefficients (used instead of y when set)
   long long y_js;             // y32 stride per Arnoldi step
   double scale;               // factor on the sums (1: z = S y)
+  const double* v;            // also: basis vector v_j (step stride Nc) ...
+  double* bc;                 // ... whose boundary columns go to bc + 2 ny j (W, E), or NULL
+  long long Nc;
 };
 
 // Spectral centre operator of the flexible variant, in the orthonormal sine
@@ -351,7 +366,8 @@ struct SpecOpTask {
 // normalised in place, as the forward transform of the plain variant does).
 struct PrepTask {
   double* v;                  // V base, step stride Nc
-  float* z;                   // Z base, step stride Nc
+  float* z;                   // Z base, step stride Nc (FP32 copy), or NULL
+  double* zd;                 // FP64 copy (one buffer, no step stride), or NULL
   const double* vscale;
   long long Nc;
   const int* skip;

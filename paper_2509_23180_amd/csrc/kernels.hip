@@ -449,6 +449,22 @@ __global__ void __launch_bounds__(kBlock) k_idst_cols(const ColTask* __restrict_
     if (tk.zw) tk.zw[r] = tk.scale * (odd + even);
     if (tk.ze) tk.ze[r] = tk.scale * (odd - even);
   }
+  if (tk.bc) {
+    const double* v = tk.v + (long long)jidx * tk.Nc + (long long)r * tk.nx;
+    double vo = 0.0, ve = 0.0;
+    for (int k = 1 + lane; k <= tk.nx; k += 64) {
+      const double x = v[k - 1] * post[k].y;
+      if (k & 1) vo += x;
+      else ve += x;
+    }
+    vo = wave_sum(vo);
+    ve = wave_sum(ve);
+    if (lane == 0) {
+      double* bc = tk.bc + (long long)2 * tk.ny * jidx;
+      bc[r] = tk.scale * (vo + ve);
+      bc[tk.ny + r] = tk.scale * (vo - ve);
+    }
+  }
 }
 
 // Spectral centre operator of the flexible variant (see SpecOpTask).
@@ -488,7 +504,7 @@ __global__ void __launch_bounds__(kBlock) k_spec_op(const SpecOpTask* __restrict
   }
 }
 
-// z^_j = FP32(v_j vscale), v_j *= vscale (see PrepTask).
+// v_j *= vscale, with an FP32 copy into Z or an FP64 copy (see PrepTask).
 __global__ void __launch_bounds__(kBlock) k_spec_prep(const PrepTask* __restrict__ tasks, int ntasks,
                                                        int jidx) {
   __shared__ int slot;
@@ -496,7 +512,7 @@ __global__ void __launch_bounds__(kBlock) k_spec_prep(const PrepTask* __restrict
   if (tk.skip && *tk.skip) return;
   const double sc = *tk.vscale;
   double* v = tk.v + (long long)jidx * tk.Nc;
-  float* z = tk.z + (long long)jidx * tk.Nc;
+  float* z = tk.z ? tk.z + (long long)jidx * tk.Nc : nullptr;
   const long long base = (long long)(blockIdx.x - tk.block_begin) * kVecPerBlock;
 #pragma unroll
   for (int e = 0; e < kVecEPT; ++e) {
@@ -504,7 +520,8 @@ __global__ void __launch_bounds__(kBlock) k_spec_prep(const PrepTask* __restrict
     if (idx < tk.Nc) {
       const double x = v[idx] * sc;
       v[idx] = x;
-      z[idx] = float(x);
+      if (tk.z) z[idx] = float(x);
+      if (tk.zd) tk.zd[idx] = x;
     }
   }
 }
@@ -581,9 +598,24 @@ __global__ void __launch_bounds__(kBlock) k_operator(const OpTask* __restrict__ 
 // variant: L_c A_c^{-1} v = v - S A_c^{-1} v).
 // =====================================================================
 __device__ __forceinline__ double line_term(const KryTask& tk, long long idx) {
-  const int r = (int)(idx / tk.nx);
-  const int c = (int)(idx - (long long)r * tk.nx);
+  // (the centre has fewer than 2^32 nodes)
+  const unsigned ui = (unsigned)idx, unx = (unsigned)tk.nx;
+  const int r = (int)(ui / unx);
+  const int c = (int)(ui - (unsigned)r * unx);
   double s = 0.0;
+  if (tk.post) {
+    // sine basis of the centre: (Q s)[r][k] with the S/N blocks diagonal,
+    // (N/2) gs_k z^[r][k], and the W/E terms spread along the row by
+    // Q e_1 = sqrt(2/N) sin(pi k/N), Q e_nx = (-1)^(k+1) sqrt(2/N) sin(pi k/N)
+    if (r == 0 && tk.gs[0]) s += tk.half_n * tk.gs[0][c] * tk.zhat[c];
+    if (r == tk.ny - 1 && tk.gs[1]) s += tk.half_n * tk.gs[1][c] * tk.zhat[idx];
+    if (tk.line[2] || tk.line[3]) {
+      const double q = tk.qscale * tk.post[c + 1].y;
+      if (tk.line[2]) s += q * tk.line[2][r];
+      if (tk.line[3]) s += ((c & 1) ? -q : q) * tk.line[3][r];
+    }
+    return s;
+  }
   if (r == 0 && tk.line[0]) s += tk.line[0][c];
   if (r == tk.ny - 1 && tk.line[1]) s += tk.line[1][c];
   if (c == 0 && tk.line[2]) s += tk.line[2][r];
@@ -951,9 +983,24 @@ __global__ void __launch_bounds__(kBlock) k_gram_bdots(const KryTask* __restrict
   if (tk.st->cycle_done) return;
   const int nd = j + 1;
   const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const double* s = tk.line[q];
   double acc = 0.0;
-  if (i <= j && s) {
+  if (tk.post) {
+    // sine basis of the centre: rows 0 / ny-1 pair v^_i with the diagonal
+    // S/N terms (N/2) gs_k z^; columns pair the physical boundary values of
+    // v_i (bc) with the W/E line terms
+    if (i <= j) {
+      const double* vi = tk.V + (long long)i * tk.Nc;
+      if (q < 2 && tk.gs[q]) {
+        const long long row = q == 0 ? 0 : (long long)(tk.ny - 1) * tk.nx;
+        for (int p = lane; p < tk.nx; p += 64)
+          acc += vi[row + p] * (tk.half_n * tk.gs[q][p] * tk.zhat[row + p]);
+      } else if (q >= 2 && tk.line[q]) {
+        const double* b = tk.bc + (long long)2 * tk.ny * i + (q == 3 ? tk.ny : 0);
+        for (int p = lane; p < tk.ny; p += 64) acc += b[p] * tk.line[q][p];
+      }
+    }
+  } else if (i <= j && tk.line[q]) {
+    const double* s = tk.line[q];
     const double* vi = tk.V + (long long)i * tk.Nc;
     const int len = q < 2 ? tk.nx : tk.ny;
     for (int p = lane; p < len; p += 64) {
