@@ -238,8 +238,7 @@ struct TaskSet {
   size_t smem_lines = 0;
   TaskList<ColTask> it_cols;
   TaskList<OpTask> res_op;
-  TaskList<PrepTask> it_prep;        // flexible variant (sine basis of the centre)
-  TaskList<SpecOpTask> it_spec;
+  TaskList<SpecOpTask> it_spec;      // flexible variant (sine basis of the centre)
   TaskList<KryTask> kry;
   TaskList<LiftTask> lift, gather;
   TaskList<IfaceTask> iface_fp, iface_bs;
@@ -264,7 +263,6 @@ struct TaskSet {
     blob.add(it_lines_d);
     blob.add(x_lines_d);
     blob.add(it_cols);
-    blob.add(it_prep);
     blob.add(it_spec);
     blob.add(res_op);
     blob.add(kry);
@@ -300,25 +298,21 @@ void TaskSet::add_problem(Problem& sl) {
   // ---- per-iteration work on the centre.  The Krylov basis of both variants
   // lives in the orthonormal sine basis of the centre (Q = sqrt(2/N) S along
   // x), so the preconditioner A_c^{-1} = Q^T T^{-1} Q reduces to the
-  // tridiagonal solve per mode.  The preparation normalises v_j in place
-  // (ProbState::vscale) and copies it to the solve's buffer: FP64 scratch
-  // (plain) or z^_j in FP32 (flexible, Z).  The W/E Schur lines need z on
+  // tridiagonal solve per mode.  The solve reads v_j times ProbState::vscale,
+  // writes v_j back normalised, and writes z^ to FP64 scratch (plain) or to
+  // z^_j in FP32 (flexible, Z).  The W/E Schur lines need z on
   // the centre's columns 0 / nx-1 (row sums of z^); the plain variant also
   // keeps the physical boundary columns of v_j for <v_i, s>.
   bool west = false, east = false;
   for (const ArmInfo& a : p->arms) { west |= a.line == 2; east |= a.line == 3; }
   const double qscale = std::sqrt(2.0 / (nx + 1));
   {
-    PrepTask pt{};
-    pt.v = sl.V; pt.vscale = &sl.st->vscale; pt.Nc = Nc; pt.skip = skip_it;
-    if (flex) pt.z = sl.Z;
-    else pt.zd = sl.tmpd;
-    add_block_task(it_prep, pt, sl.P);
     TriTask tt{};
     tt.data = flex ? (void*)sl.Z : (void*)sl.tmpd; tt.rs = nx; tt.js = flex ? Nc : 0;
     tt.rows = ny; tt.modes = nx;
     tt.coef = flex ? (const void*)p->modes_cu->c32 : (const void*)p->modes_cu->c64;
     tt.skip = skip_it;
+    tt.vin = sl.V; tt.vjs = Nc; tt.vscale = &sl.st->vscale;
     it_tri.add(tt);
     if (west || east) {
       ColTask ct{};
@@ -509,11 +503,8 @@ void TaskSet::add_problem(Problem& sl) {
 
 // One Arnoldi step j of every problem of the set whose cycle is running.
 void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
-  Timing::begin(5, s);
-  launch_spec_prep(it_prep.dev(), it_prep.n(), it_prep.nblocks, j, s);
-  Timing::end(5, s);
   Timing::begin(1, s);
-  it_tri.launch(s, flex ? j : 0);
+  it_tri.launch(s, j);
   Timing::end(1, s);
   if (it_cols.n()) {
     Timing::begin(7, s);
@@ -871,15 +862,13 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
     const int its = host_states[sl.idx].iterations - before[sl.idx].iterations;
     double lines = 0;
     for (const ArmInfo& a : sl.plan->arms) lines += line_bytes(a);
-    // per Arnoldi step (sine basis): the preparation reads v_j, writes it
-    // back normalised and writes the solve buffer (FP64 plain, FP32 z^_j
-    // flexible); the tridiagonal solve reads and writes it; the boundary
-    // columns read it (plain: and v_j); flexible: the operator reads z^_j and
-    // writes w.  Gram dots read
+    // per Arnoldi step (sine basis): the tridiagonal solve reads v_j, writes
+    // it back normalised and writes z^ (FP64 plain, FP32 z^_j flexible); the
+    // boundary columns read z^ (plain: and v_j); flexible: the operator reads
+    // z^_j and writes w.  Gram dots read
     // v_0..v_j (and w if stored), the update reads v_0..v_j (and w if
     // stored) and writes w.
-    Timing::add_bytes(5, its * Nc * (8.0 + 8.0 + wz));
-    Timing::add_bytes(1, its * Nc * 2.0 * wz);
+    Timing::add_bytes(1, its * Nc * (8.0 + 8.0 + wz));
     if (flex) {
       Timing::add_bytes(7, its * Nc * wz);
       Timing::add_bytes(2, its * Nc * (wz + 8.0));

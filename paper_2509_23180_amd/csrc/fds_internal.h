@@ -201,6 +201,13 @@ struct TriTask {
   const int* skip;
   int block_begin;
   int pad;
+  // Optional source: the right-hand side is read from vin (FP64, layout of
+  // data, step stride vjs) times *vscale, and vin is written back scaled
+  // (the Krylov basis vector is normalised in the same pass); the solution
+  // goes to data.
+  double* vin;
+  long long vjs;
+  const double* vscale;
 };
 
 // Schur line term: out[k] = sum_l Sline(k,l) z_line[l] with
@@ -357,19 +364,6 @@ struct SpecOpTask {
   const FftDesc* fft;         // post64[k] = (cos, sin)(pi k / N)
   double delta, kappa;
   int nx, ny;
-  const int* skip;
-  int block_begin;
-  int pad;
-};
-
-// z^_j = FP32(v_j * vscale) and v_j *= vscale (the basis vector is
-// normalised in place, as the forward transform of the plain variant does).
-struct PrepTask {
-  double* v;                  // V base, step stride Nc
-  float* z;                   // Z base, step stride Nc (FP32 copy), or NULL
-  double* zd;                 // FP64 copy (one buffer, no step stride), or NULL
-  const double* vscale;
-  long long Nc;
   const int* skip;
   int block_begin;
   int pad;

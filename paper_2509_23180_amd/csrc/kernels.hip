@@ -183,10 +183,20 @@ __global__ void __launch_bounds__(kBlock) k_tridiag(const TriTask* __restrict__ 
   T* d = static_cast<T*>(tk.data) + (long long)jidx * tk.js + k;
   const long long rs = tk.rs;
   const int m = tk.rows;
+  double* v = tk.vin ? tk.vin + (long long)jidx * tk.vjs + k : nullptr;
+  const double sc = tk.vin ? *tk.vscale : 1.0;
   T w = T(0), s = T(0), p = T(1);
 #pragma unroll 4
   for (int i = 0; i < m; ++i) {
-    w = c.sc * d[i * rs] + c.q * w;
+    T r;
+    if (v) {
+      const double a = v[i * rs] * sc;
+      v[i * rs] = a;
+      r = T(a);
+    } else {
+      r = d[i * rs];
+    }
+    w = c.sc * r + c.q * w;
     d[i * rs] = w;
     s += p * w;
     p *= c.q;
@@ -235,8 +245,23 @@ __global__ void __launch_bounds__(1024) k_tridiag_seg(const TriTask* __restrict_
   const int rs = (int)tk.rs;
   T* d = static_cast<T*>(tk.data) + (long long)jidx * tk.js + (long long)i0 * rs + (k < tk.modes ? k : 0);
   T x[LS];
+  if (tk.vin) {
+    double* v = tk.vin + (long long)jidx * tk.vjs + (long long)i0 * rs + (k < tk.modes ? k : 0);
+    const double sc = *tk.vscale;
 #pragma unroll
-  for (int t = 0; t < LS; ++t) x[t] = (t < L) ? d[t * rs] : T(0);
+    for (int t = 0; t < LS; ++t) {
+      if (t < L) {
+        const double a = v[t * rs] * sc;
+        v[t * rs] = a;
+        x[t] = T(a);
+      } else {
+        x[t] = T(0);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < LS; ++t) x[t] = (t < L) ? d[t * rs] : T(0);
+  }
   // local forward sweep
   T w = T(0), A = T(0), p = T(1);
 #pragma unroll
@@ -504,27 +529,6 @@ __global__ void __launch_bounds__(kBlock) k_spec_op(const SpecOpTask* __restrict
   }
 }
 
-// v_j *= vscale, with an FP32 copy into Z or an FP64 copy (see PrepTask).
-__global__ void __launch_bounds__(kBlock) k_spec_prep(const PrepTask* __restrict__ tasks, int ntasks,
-                                                       int jidx) {
-  __shared__ int slot;
-  const PrepTask& tk = tasks[find_task(tasks, ntasks, &slot)];
-  if (tk.skip && *tk.skip) return;
-  const double sc = *tk.vscale;
-  double* v = tk.v + (long long)jidx * tk.Nc;
-  float* z = tk.z ? tk.z + (long long)jidx * tk.Nc : nullptr;
-  const long long base = (long long)(blockIdx.x - tk.block_begin) * kVecPerBlock;
-#pragma unroll
-  for (int e = 0; e < kVecEPT; ++e) {
-    const long long idx = base + (long long)e * kBlock + threadIdx.x;
-    if (idx < tk.Nc) {
-      const double x = v[idx] * sc;
-      v[idx] = x;
-      if (tk.z) z[idx] = float(x);
-      if (tk.zd) tk.zd[idx] = x;
-    }
-  }
-}
 
 // =====================================================================
 // Centre operator (5-point stencil with zero data outside the centre, minus
@@ -1635,10 +1639,6 @@ void launch_spec_op(const SpecOpTask* tasks, int ntasks, int nblocks, int jidx, 
   FDS_LAUNCH(k_spec_op, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
 }
 
-void launch_spec_prep(const PrepTask* tasks, int ntasks, int nblocks, int jidx, hipStream_t s) {
-  if (nblocks <= 0) return;
-  FDS_LAUNCH(k_spec_prep, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
-}
 
 void launch_ls_solve(const KryTask* tasks, int ntasks, int m, hipStream_t s) {
   if (ntasks <= 0) return;
