@@ -334,6 +334,26 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Wavefront sum with DPP lane moves (register to register, no LDS crossbar):
+// quad swaps, half-row and row mirrors, then the row broadcasts of lanes 15
+// and 31.  The full sum is valid in lane 63 only.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return v + __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum_last(double v) {
+  v = dpp_add<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xf>(v);   // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);   // row_mirror: every lane holds its row's sum
+  v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 // Sum over a block of kBlock threads; every thread receives the same bits.
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);

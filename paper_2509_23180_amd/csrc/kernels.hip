@@ -802,9 +802,9 @@ __global__ void __launch_bounds__(kBlock) k_gram_dots(const KryTask* __restrict_
       a += v * xj[e];
       c += v * uv[e];
     }
-    a = wave_sum(a);
-    c = wave_sum(c);
-    if (lane == 0) {
+    a = wave_sum_last(a);
+    c = wave_sum_last(c);
+    if (lane == 63) {
       red[i][wave] = a;
       red[121 + i][wave] = c;
     }
@@ -1054,8 +1054,11 @@ __global__ void __launch_bounds__(kBlock) k_gram_update_lag(const KryTask* __res
   __shared__ double gcol[MJ + 1];
   const KryTask& tk = tasks[find_task(tasks, ntasks, &slot)];
   if (tk.st->cycle_done) return;
-  for (int i = threadIdx.x; i < MJ; i += kBlock) hs[i] = i <= j ? tk.hv[i] : 0.0;
+  // hs: coefficients of v_0..v_{j-1} (zero from j on); v_j's is taken apart
+  // so that it is subtracted last, as in k_gram_update
+  for (int i = threadIdx.x; i < MJ; i += kBlock) hs[i] = i < j ? tk.hv[i] : 0.0;
   __syncthreads();
+  const double hj = tk.hv[j];
   const int b = blockIdx.x - tk.block_begin;
   const long long Nc = tk.Nc;
   const long long base = (long long)b * kVecPerBlock;
@@ -1063,41 +1066,43 @@ __global__ void __launch_bounds__(kBlock) k_gram_update_lag(const KryTask* __res
   // the basis through global-address-space pointers: one uniform base per
   // vector and one 32-bit lane offset shared by all of its loads
   using GD = const double __attribute__((address_space(1)));
+  using GB = const unsigned char __attribute__((address_space(1)));
   GD* Vg = (GD*)(tk.V);
   double d[MJ + 1];
 #pragma unroll
   for (int i = 0; i <= MJ; ++i) d[i] = 0.0;
 #pragma unroll 1
   for (int r = 0; r < kVecEPT / EU; ++r) {
-    unsigned off[EU];
+    unsigned off[EU], boff[EU];
     bool ok[EU];
 #pragma unroll
     for (int u = 0; u < EU; ++u) {
       const long long idx = base + (long long)(r * EU + u) * kBlock + threadIdx.x;
       ok[u] = idx < Nc;
       off[u] = (unsigned)(ok[u] ? idx : Nc - 1);
+      boff[u] = off[u] * 8u;   // byte offset (a centre vector is below 4 GiB)
     }
-    double vv[EU][MJ];
+    // vectors beyond j load v_j again (in bounds, cached); their
+    // coefficients are zero and their dot sums are never reduced, so no
+    // selects are needed
+    double vv[EU][MJ], xj[EU];
+    GD* vj = Vg + (long long)j * Nc;
+#pragma unroll
+    for (int u = 0; u < EU; ++u) xj[u] = vj[off[u]];
 #pragma unroll
     for (int i = 0; i < MJ; ++i) {
-      GD* vi = Vg + (long long)min(i, j) * Nc;
+      GB* vi = (GB*)(Vg + (long long)min(i, j) * Nc);
 #pragma unroll
-      for (int u = 0; u < EU; ++u) vv[u][i] = vi[off[u]];
+      for (int u = 0; u < EU; ++u) vv[u][i] = *(GD*)(vi + boff[u]);
     }
 #pragma unroll
     for (int u = 0; u < EU; ++u) {
-      double xj = 0.0;
-#pragma unroll
-      for (int i = 0; i < MJ; ++i) {
-        xj = (i == j) ? vv[u][i] : xj;
-        vv[u][i] = (ok[u] && i <= j) ? vv[u][i] : 0.0;
-      }
       const long long idx = base + (long long)(r * EU + u) * kBlock + threadIdx.x;
-      double acc = ok[u] ? xj - line_term(tk, idx) : 0.0;
+      double acc = xj[u] - (ok[u] ? line_term(tk, idx) : 0.0);
 #pragma unroll
-      for (int i = 0; i < MJ; ++i)
-        if (i < j) acc -= hs[i] * vv[u][i];
-      acc -= hs[j] * (ok[u] ? xj : 0.0);
+      for (int i = 0; i < MJ; ++i) acc -= hs[i] * vv[u][i];   // hs[i] = 0 for i >= j
+      acc -= hj * xj[u];
+      acc = ok[u] ? acc : 0.0;
       if (ok[u]) w[idx] = acc;
       d[MJ] += acc * acc;
 #pragma unroll
@@ -1109,8 +1114,8 @@ __global__ void __launch_bounds__(kBlock) k_gram_update_lag(const KryTask* __res
 #pragma unroll
   for (int i = 0; i <= MJ; ++i) {
     if (i <= j || i == MJ) {
-      const double v = wave_sum(d[i]);
-      if (lane == 0) dred[i][wave] = v;
+      const double v = wave_sum_last(d[i]);
+      if (lane == 63) dred[i][wave] = v;
     }
   }
   __syncthreads();
@@ -1613,8 +1618,9 @@ void launch_gram_update_lag(const KryTask* tasks, int ntasks, int nblocks, int m
   if (m > kLagMaxJ || j >= m) throw Error(FDS_E_INVALID_ARG, "lagged Gram columns need j < m <= 32");
   // basis vectors held per round: the smallest MJ >= j + 1; about 32 loads
   // in flight per thread and round
-  if (j < 4) FDS_LAUNCH((k_gram_update_lag<4, 8>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
-  else if (j < 8) FDS_LAUNCH((k_gram_update_lag<8, 4>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
+  constexpr int eu8 = kVecEPT < 8 ? kVecEPT : 8, eu4 = kVecEPT < 4 ? kVecEPT : 4;
+  if (j < 4) FDS_LAUNCH((k_gram_update_lag<4, eu8>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
+  else if (j < 8) FDS_LAUNCH((k_gram_update_lag<8, eu4>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
   else if (j < 16) FDS_LAUNCH((k_gram_update_lag<16, 2>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
   else FDS_LAUNCH((k_gram_update_lag<32, 2>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
 }
