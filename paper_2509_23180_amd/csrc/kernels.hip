@@ -1616,13 +1616,13 @@ void launch_gram_update_lag(const KryTask* tasks, int ntasks, int nblocks, int m
                             int tag, hipStream_t s) {
   if (nblocks <= 0) return;
   if (m > kLagMaxJ || j >= m) throw Error(FDS_E_INVALID_ARG, "lagged Gram columns need j < m <= 32");
-  // basis vectors held per round: the smallest MJ >= j + 1; about 32 loads
-  // in flight per thread and round
-  constexpr int eu8 = kVecEPT < 8 ? kVecEPT : 8, eu4 = kVecEPT < 4 ? kVecEPT : 4;
-  if (j < 4) FDS_LAUNCH((k_gram_update_lag<4, eu8>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
-  else if (j < 8) FDS_LAUNCH((k_gram_update_lag<8, eu4>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
-  else if (j < 16) FDS_LAUNCH((k_gram_update_lag<16, 2>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
-  else FDS_LAUNCH((k_gram_update_lag<32, 2>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
+  // basis vectors held per round: the smallest MJ >= j + 1; at most 16 (or
+  // 32 for j >= 16) loads per thread and round, which keeps three
+  // wavefronts per SIMD resident (measured best)
+  if (j < 4) FDS_LAUNCH((k_gram_update_lag<4, 4>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
+  else if (j < 8) FDS_LAUNCH((k_gram_update_lag<8, 2>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
+  else if (j < 16) FDS_LAUNCH((k_gram_update_lag<16, 1>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
+  else FDS_LAUNCH((k_gram_update_lag<32, 1>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
 }
 
 void launch_gram_update(const KryTask* tasks, int ntasks, int nblocks, int j, int* flags, int tag,
