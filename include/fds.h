@@ -212,11 +212,13 @@ fds_status fds_k_arnoldi_mgs(double* V, int32_t k, int64_t len, double* h, void*
 const char* fds_status_str(fds_status s);
 const char* fds_last_error(void);
 /* Per-kernel-class timing with HIP events recorded on the launching stream
- * (off by default).  Classes (one kernel each unless noted): 0 sine
- * transforms (k_dst_rows), 1 tridiagonal solves (k_tridiag_seg or
- * k_tridiag), 2 centre operator (k_operator), 3 Gram-Schmidt dot products
- * (k_gram_dots), 4 Schur line terms (k_schur_lines), 5 other small kernels,
- * 6 Gram-Schmidt update (k_gram_update), 7 boundary columns (k_idst_cols).
+ * (off by default).  Classes: 0 sine transforms (k_dst_wave, k_dst_rows or
+ * k_dst_gemm, whichever the tuner picked per length), 1 tridiagonal solves
+ * (k_tridiag_seg or k_tridiag), 2 centre operator (k_operator, k_spec_op),
+ * 3 Gram-Schmidt dot products (k_gram_dots or k_gram_bdots), 4 Schur line
+ * terms (k_lines_dense or k_schur_lines), 5 other small kernels, 6
+ * Gram-Schmidt update (k_gram_update or k_gram_update_lag), 7 boundary
+ * columns (k_idst_cols).
  * `mask` selects the classes to time (bit c = class c; 0 = off).
  * fds_timing_read returns, per class, the launches timed, their summed
  * duration and the algorithmic bytes (minimal HBM traffic: every operand
