@@ -376,7 +376,7 @@ void TaskSet::add_problem(Problem& sl) {
     LineTask lx = lt;
     lx.z = sl.x_int + cd.off; lx.z_js = 0; lx.z_f32 = 0; lx.skip = skip_fin;
     if (dense_lines(a.L) && a.gs->mfull) {
-      li.mat = li.pre_dst ? a.gs->mpre_t : a.gs->mfull;
+      li.mat = a.gs->mfull;
       lx.mat = a.gs->mfull;
       if (it_line) add_block_task(it_lines_d, li, div_up(a.L, 64));
       add_block_task(x_lines_d, lx, div_up(a.L, 64));

@@ -219,7 +219,7 @@ struct LineTask {
   long long stride;           // element stride along the line
   int L;
   int z_f32;
-  int pre_dst;                // 1: the line holds sine coefficients; transform them first
+  int pad_l;
   int pad;
   const FftDesc* fft;
   const double* gs;           // delta^2 (2/N) g_k, k = 1..L

@@ -355,10 +355,6 @@ __global__ void __launch_bounds__(1024) k_tridiag_seg(const TriTask* __restrict_
   }
 }
 
-__device__ __forceinline__ double A_line(const LineTask& tk, int jidx, int k) {
-  const double* z = static_cast<const double*>(tk.z) + (long long)jidx * tk.z_js + tk.start;
-  return z[(long long)(k - 1) * tk.stride];
-}
 
 // =====================================================================
 // Schur line terms: out = delta^2 (2/N) S diag(g) S z_line (FP64).
@@ -378,9 +374,7 @@ __global__ void __launch_bounds__(kBlock) k_schur_lines(const LineTask* __restri
   const double2* tw = stage_twiddles<double>(f, twl, true);
   const int g = threadIdx.x;
   const long long st = tk.stride;
-  if (tk.pre_dst) {
-    // nothing to transform before the diagonal scaling
-  } else if (tk.z_f32) {
+  if (tk.z_f32) {
     const float* z = static_cast<const float*>(tk.z) + (long long)jidx * tk.z_js + tk.start;
     dst_pack<double>(A, N, g, kBlock, [&](int j) { return double(z[(long long)(j - 1) * st]); });
   } else {
@@ -388,15 +382,8 @@ __global__ void __launch_bounds__(kBlock) k_schur_lines(const LineTask* __restri
     dst_pack<double>(A, N, g, kBlock, [&](int j) { return z[(long long)(j - 1) * st]; });
   }
   __syncthreads();
-  const double2* C = tk.pre_dst ? A : fft_lds<double>(A, B, f, tw, g, kBlock);
-  if (tk.pre_dst) {
-    // the line holds the sine coefficients y of z (z = S y); since
-    // S S = (N/2) I the term is delta^2 (2/N) S diag(g) S S y = (N/2) S (gs o y)
-    const double half = 0.5 * N;
-    for (int k = 1 + g; k <= L; k += kBlock) mid[k - 1] = half * tk.gs[k - 1] * A_line(tk, jidx, k);
-  } else {
-    for (int k = 1 + g; k <= L; k += kBlock) mid[k - 1] = tk.gs[k - 1] * dst_post<double>(C, f.post64, N, k);
-  }
+  const double2* C = fft_lds<double>(A, B, f, tw, g, kBlock);
+  for (int k = 1 + g; k <= L; k += kBlock) mid[k - 1] = tk.gs[k - 1] * dst_post<double>(C, f.post64, N, k);
   __syncthreads();
   dst_pack<double>(A, N, g, kBlock, [&](int j) { return mid[j - 1]; });
   __syncthreads();
@@ -405,8 +392,7 @@ __global__ void __launch_bounds__(kBlock) k_schur_lines(const LineTask* __restri
 }
 
 // Schur line terms as dense products with the precomputed line operator:
-// out_i = sum_k M(k, i) v_k, v the sine coefficients of the line (pre_dst)
-// or the line of z.  A block covers 64 outputs of one line; its four
+// out_i = sum_k M(k, i) v_k, v the line of z.  A block covers 64 outputs of one line; its four
 // wavefronts take quarters of k and are added in a fixed order.
 __global__ void __launch_bounds__(kBlock) k_lines_dense(const LineTask* __restrict__ tasks,
                                                          int ntasks, int jidx) {
@@ -839,10 +825,10 @@ __global__ void __launch_bounds__(kBlock) k_gram_dots(const KryTask* __restrict_
 }
 
 // h_{j+1,j} = ||w|| (nrm2 = ||w||^2, summed by the caller), Givens update of
-// column j and the convergence test on
-// |g_{j+1}| (thread 0 of one block of the problem).  V[j+1] is normalised by
-// the next step's sine transform (ProbState::vscale).  When the problem's
-// cycle ends, its host-visible flag receives `tag`.
+// column j and the convergence test on |g_{j+1}| (thread 0 of one block of
+// the problem).  V[j+1] is normalised by the next step's tridiagonal solve
+// (ProbState::vscale).  When the problem's cycle ends, its host-visible flag
+// receives `tag`.
 __device__ void mgs_finish_block(const KryTask& tk, int j, int* flags, int tag, double nrm2,
                                  double* col, double* cs, double* sn) {
   ProbState* st = tk.st;

@@ -82,12 +82,10 @@ struct ModeTable {          // per-mode tridiagonal coefficients, FP64 and FP32
 struct GsTable {            // Schur line coefficients delta^2 (2/N) g_k
   DevBuf mem;
   const double* gs;
-  // Dense line operators for n <= kDenseLineMax (else null), n x n FP64,
-  // element (k, i) at k n + i:
-  //   full: delta^2 (2/N) S diag(g) S  (symmetric), applied to a line of z
-  //   pre:  (N/2) S diag(gs), transposed, applied to sine coefficients y
+  // Dense line operator for n <= kDenseLineMax (else null), n x n FP64,
+  // element (k, i) at k n + i: delta^2 (2/N) S diag(g) S (symmetric),
+  // applied to a line of z
   const double* mfull = nullptr;
-  const double* mpre_t = nullptr;
 };
 constexpr int kDenseLineMax = 1024;
 // Dense line operators in use (n <= kDenseLineMax unless FDS_LINES=fft).

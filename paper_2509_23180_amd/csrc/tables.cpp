@@ -738,17 +738,14 @@ std::shared_ptr<GsTable> TableCache::gs(int n, int m, double h, double kappa) {
   auto t = std::make_shared<GsTable>();
   const bool dense = n <= kDenseLineMax;
   const size_t nn = (size_t)n * n;
-  std::vector<double> host(n + (dense ? 2 * nn : 0));
+  std::vector<double> host(n + (dense ? nn : 0));
   std::copy(v.begin(), v.end(), host.begin());
   if (dense) {
     // S diag(gs) S by product to sum: sin(a) sin(b) = (cos(a-b) - cos(a+b))/2,
     // so M_ik = (c(|i-k|) - c(i+k))/2 with c(t) = sum_l gs_l cos(pi l t/N)
     // (i, k, l = 1..n; angles reduced modulo 2N before the cosine).
-    std::vector<long double> cs(2 * N), sn(2 * N);  // cos / sin(pi r/N), r < 2N
-    for (int r = 0; r < 2 * N; ++r) {
-      cs[r] = cosl(kPi * (long double)r / (long double)N);
-      sn[r] = sinl(kPi * (long double)r / (long double)N);
-    }
+    std::vector<long double> cs(2 * N);  // cos(pi r/N), r < 2N
+    for (int r = 0; r < 2 * N; ++r) cs[r] = cosl(kPi * (long double)r / (long double)N);
     std::vector<long double> c(2 * N + 1);
     for (int tt = 0; tt <= 2 * N; ++tt) {
       long double acc = 0;
@@ -756,21 +753,15 @@ std::shared_ptr<GsTable> TableCache::gs(int n, int m, double h, double kappa) {
       c[tt] = acc;
     }
     double* mf = host.data() + n;
-    double* mp = mf + nn;
     for (int i = 1; i <= n; ++i)
-      for (int k = 1; k <= n; ++k) {
+      for (int k = 1; k <= n; ++k)
         mf[(size_t)(k - 1) * n + (i - 1)] = (double)(0.5L * (c[std::abs(i - k)] - c[i + k]));
-        // (N/2) S_ik gs_k stored at (k, i)
-        mp[(size_t)(k - 1) * n + (i - 1)] =
-            (double)(0.5L * N * sn[(long long)i * k % (2LL * N)] * (long double)v[k - 1]);
-      }
   }
   t->mem.alloc(sizeof(double) * host.size());
   FDS_HIP(hipMemcpy(t->mem.get(), host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice));
   t->gs = t->mem.as<double>(0);
   if (dense) {
     t->mfull = t->gs + n;
-    t->mpre_t = t->mfull + nn;
   }
   gs_[key] = t;
   return t;
