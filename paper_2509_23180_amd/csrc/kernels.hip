@@ -1043,8 +1043,7 @@ __global__ void __launch_bounds__(kBlock) k_gram_update_lag(const KryTask* __res
   // hs: coefficients of v_0..v_{j-1} (zero from j on); v_j's is taken apart
   // so that it is subtracted last, as in k_gram_update
   for (int i = threadIdx.x; i < MJ; i += kBlock) hs[i] = i < j ? tk.hv[i] : 0.0;
-  __syncthreads();
-  const double hj = tk.hv[j];
+  const double hj = tk.hv[j];   // (hs is published after round 0's loads are issued)
   const int b = blockIdx.x - tk.block_begin;
   const long long Nc = tk.Nc;
   const long long base = (long long)b * kVecPerBlock;
@@ -1081,6 +1080,7 @@ __global__ void __launch_bounds__(kBlock) k_gram_update_lag(const KryTask* __res
 #pragma unroll
       for (int u = 0; u < EU; ++u) vv[u][i] = *(GD*)(vi + boff[u]);
     }
+    if (r == 0) __syncthreads();
 #pragma unroll
     for (int u = 0; u < EU; ++u) {
       const long long idx = base + (long long)(r * EU + u) * kBlock + threadIdx.x;
