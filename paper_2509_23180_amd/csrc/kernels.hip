@@ -441,6 +441,7 @@ __global__ void __launch_bounds__(kBlock) k_idst_cols(const ColTask* __restrict_
   double odd = 0.0, even = 0.0;   // k odd / k even (k = 1..nx)
   if (tk.y32) {
     const float* y = tk.y32 + (long long)jidx * tk.y_js + (long long)r * tk.nx;
+    #pragma unroll 4
     for (int k = 1 + lane; k <= tk.nx; k += 64) {
       const double v = double(y[k - 1]) * post[k].y;
       if (k & 1) odd += v;
@@ -448,6 +449,7 @@ __global__ void __launch_bounds__(kBlock) k_idst_cols(const ColTask* __restrict_
     }
   } else {
     const double* y = tk.y + (long long)r * tk.nx;
+    #pragma unroll 4
     for (int k = 1 + lane; k <= tk.nx; k += 64) {
       const double v = y[k - 1] * post[k].y;
       if (k & 1) odd += v;
@@ -463,6 +465,7 @@ __global__ void __launch_bounds__(kBlock) k_idst_cols(const ColTask* __restrict_
   if (tk.bc) {
     const double* v = tk.v + (long long)jidx * tk.Nc + (long long)r * tk.nx;
     double vo = 0.0, ve = 0.0;
+    #pragma unroll 4
     for (int k = 1 + lane; k <= tk.nx; k += 64) {
       const double x = v[k - 1] * post[k].y;
       if (k & 1) vo += x;
@@ -982,10 +985,12 @@ __global__ void __launch_bounds__(kBlock) k_gram_bdots(const KryTask* __restrict
       const double* vi = tk.V + (long long)i * tk.Nc;
       if (q < 2 && tk.gs[q]) {
         const long long row = q == 0 ? 0 : (long long)(tk.ny - 1) * tk.nx;
+        #pragma unroll 4
         for (int p = lane; p < tk.nx; p += 64)
           acc += vi[row + p] * (tk.half_n * tk.gs[q][p] * tk.zhat[row + p]);
       } else if (q >= 2 && tk.line[q]) {
         const double* b = tk.bc + (long long)2 * tk.ny * i + (q == 3 ? tk.ny : 0);
+        #pragma unroll 4
         for (int p = lane; p < tk.ny; p += 64) acc += b[p] * tk.line[q][p];
       }
     }
