@@ -832,16 +832,23 @@ __global__ void __launch_bounds__(kBlock) k_gram_dots(const KryTask* __restrict_
 // the problem).  V[j+1] is normalised by the next step's tridiagonal solve
 // (ProbState::vscale).  When the problem's cycle ends, its host-visible flag
 // receives `tag`.
-__device__ void mgs_finish_block(const KryTask& tk, int j, int* flags, int tag, double nrm2,
-                                 double* col, double* cs, double* sn) {
-  ProbState* st = tk.st;
+// Column j of H and the stored rotations into LDS (every block of the pass
+// does this at its start, so the finishing block does not wait for them).
+__device__ __forceinline__ void mgs_finish_preload(const KryTask& tk, int j, double* col, double* cs,
+                                                   double* sn) {
   const int m1 = tk.m + 1;
   for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = tk.H[i + j * m1];
   for (int i = threadIdx.x; i < j; i += blockDim.x) {
     cs[i] = tk.cs[i];
     sn[i] = tk.sn[i];
   }
-  __syncthreads();
+}
+
+// (col, cs, sn filled by mgs_finish_preload and published by a barrier)
+__device__ void mgs_finish_block(const KryTask& tk, int j, int* flags, int tag, double nrm2,
+                                 double* col, double* cs, double* sn) {
+  ProbState* st = tk.st;
+  const int m1 = tk.m + 1;
   if (threadIdx.x != 0) return;
   const double hn = sqrt(nrm2);
   const bool breakdown = !(hn > 1e-14 * st->beta);
@@ -894,6 +901,7 @@ __global__ void __launch_bounds__(kBlock) k_gram_update(const KryTask* __restric
   const KryTask& tk = tasks[find_task(tasks, ntasks, &slot)];
   if (tk.st->cycle_done) return;
   for (int i = threadIdx.x; i <= j; i += kBlock) hs[i] = tk.hv[i];
+  mgs_finish_preload(tk, j, col, cs, sn);
   __syncthreads();
   const int b = blockIdx.x - tk.block_begin;
   const long long Nc = tk.Nc;
@@ -1048,7 +1056,8 @@ __global__ void __launch_bounds__(kBlock) k_gram_update_lag(const KryTask* __res
   // hs: coefficients of v_0..v_{j-1} (zero from j on); v_j's is taken apart
   // so that it is subtracted last, as in k_gram_update
   for (int i = threadIdx.x; i < MJ; i += kBlock) hs[i] = i < j ? tk.hv[i] : 0.0;
-  const double hj = tk.hv[j];   // (hs is published after round 0's loads are issued)
+  mgs_finish_preload(tk, j, col, cs, sn);
+  const double hj = tk.hv[j];   // (hs, col, cs, sn are published after round 0's loads are issued)
   const int b = blockIdx.x - tk.block_begin;
   const long long Nc = tk.Nc;
   const long long base = (long long)b * kVecPerBlock;
