@@ -15,7 +15,9 @@ FGMRES(40) with an FP32 preconditioner), "batching" (64 composite problems x
 8 right-hand sides, sizes 64..512, FGMRES(40)), "serving" (a Poisson request
 stream replayed open-loop against the continuous-batching server, once with
 the mixed-precision FGMRES(40) path and once with the plain FP64 GMRES(30)
-path; p50/p99 latency from submission to completion and throughput).
+path; p50/p99 latency from submission to completion and throughput),
+"convergence" (iteration counts without preconditioner and with A_c^-1, the
+iteration count against n, a restart sweep).
 """
 
 from __future__ import annotations
@@ -206,6 +208,67 @@ def to_device(items, opts, device):
     return plans, out
 
 
+# --------------------------------------------------------------------------- convergence
+
+def run_convergence(args, device):
+    """The paper's convergence comparison on these kernels (Section 3.2): GMRES
+    iterations to rel-res 1e-10 without preconditioner (P = I) and with A_c^-1,
+    at two n and two restart lengths; the iteration count of the
+    preconditioned method against n (power-law fit); and a restart sweep at
+    n = 256.  Manufactured solution on the cross, kappa = 0.  One solve per
+    case, timed with the device synchronised around it."""
+    import math
+    import torch
+    import workloads
+    import paper_2509_23180_amd as fds
+
+    tol = 1e-10
+
+    def one(n, m, precision, max_cycles=200):
+        prob = workloads.manufactured_problem("cross", n, 0.0, shifted=True)
+        _, dev = to_device([prob], dict(restart_m=m, precision=precision, max_cycles=max_cycles), device)
+        plan, rhs, bc, x = dev[0]
+        fds.solve(plan, rhs, x, tol, bc=bc)          # tables, tuning, code load
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fds.solve(plan, rhs, x, tol, bc=bc)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        stop = r.stop_reason
+        log(f"n={n} m={m} precision={precision}: its={r.iterations} cycles={r.cycles} "
+            f"relres={r.relres_schur:.2e} stop={stop} {ms:.1f} ms")
+        return {"n": n, "m": m, "iterations": r.iterations, "cycles": r.cycles, "status": r.status,
+                "stop": stop, "relres": r.relres_schur, "ms": round(ms, 3)}
+
+    compare = []
+    for n in (32, 64):
+        for m in (30, 80):
+            a = one(n, m, fds.NO_PRECOND, max_cycles=400)
+            b = one(n, m, fds.FP64)
+            compare.append({"n": n, "m": m, "none": a, "A_c_inv": b,
+                            "ratio": round(a["iterations"] / max(1, b["iterations"]), 2)})
+    vs_n = [one(n, 30, fds.FP64) for n in (32, 64, 128, 256, 512, 1024)]
+    xs = [math.log(r["n"]) for r in vs_n]
+    ys = [math.log(max(1, r["iterations"])) for r in vs_n]
+    xm, ym = sum(xs) / len(xs), sum(ys) / len(ys)
+    slope = sum((x - xm) * (y - ym) for x, y in zip(xs, ys)) / sum((x - xm) ** 2 for x in xs)
+    sweep = [one(256, m, fds.FP64) for m in (20, 40, 60, 80, 100, 120)]
+    ratios = [c["ratio"] for c in compare if c["none"]["status"] == 0]
+    return {
+        "metric": "GMRES iterations to rel-res 1e-10: no preconditioner over A_c^-1 (cross, kappa=0)",
+        "value": min(ratios) if ratios else None, "unit": "x (smallest ratio over converged cases)",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "convergence: cross, manufactured solution, kappa 0, rel-res 1e-10",
+                   "compare_P_I_vs_A_c_inv": compare,
+                   "iterations_vs_n": {"restart_m": 30, "cases": vs_n,
+                                       "fit": f"iterations ~ n^{slope:.3f}"},
+                   "restart_sweep_n256": sweep},
+        "roofline": None, "cpu_baseline": None,
+    }
+
+
 # --------------------------------------------------------------------------- serving
 
 def serving_inputs(reqs, device):
@@ -358,7 +421,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="plain", choices=["plain", "precision", "batching", "serving"])
+    ap.add_argument("--workload", default="plain",
+                    choices=["plain", "precision", "batching", "serving", "convergence"])
     ap.add_argument("--serving-rate", type=float, default=200.0, help="requests per second")
     ap.add_argument("--serving-seconds", type=float, default=1.0, help="length of the arrival trace")
     ap.add_argument("--serving-nmax", type=int, default=2048)
@@ -407,6 +471,10 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         print(json.dumps({"copy_bytes_per_launch": 2 * n * 8, "GB/s": 2 * n * 8 * reps / dt / 1e9}))
+        return
+
+    if args.workload == "convergence":
+        print(json.dumps(run_convergence(args, device)), flush=True)
         return
 
     if args.workload == "serving":

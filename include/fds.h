@@ -70,9 +70,12 @@ typedef struct { int32_t i0, j0, i1, j1; } fds_rect;
 
 typedef enum {
   FDS_FP64 = 0,               /* plain method: everything in FP64 (GMRES)   */
-  FDS_FP32_PRECOND = 1        /* FP32 sine transforms + tridiagonal solves  */
+  FDS_FP32_PRECOND = 1,       /* FP32 sine transforms + tridiagonal solves  */
                               /* inside flexible GMRES; FP64 Gram-Schmidt,  */
                               /* Givens, operator, true residual, update    */
+  FDS_NO_PRECOND = 2          /* no preconditioner (P = I, Section 3.2's    */
+                              /* baseline): flexible GMRES with z = v       */
+                              /* stored in FP32; for convergence studies    */
 } fds_precision;
 
 typedef enum {

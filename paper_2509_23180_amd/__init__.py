@@ -23,6 +23,7 @@ STATUS = {0: "ok", 1: "pending", -1: "invalid argument", -2: "unsupported geomet
           -7: "non-finite input", -8: "device error"}
 FP64 = 0
 FP32_PRECOND = 1
+NO_PRECOND = 2       # P = I: the convergence baseline (flexible GMRES, z = v in FP32)
 STOP = {0: "none", 1: "tol", 2: "at_floor", 3: "max_cycles", 4: "stagnation"}
 
 TIMING_CLASSES = {"dst": 0, "tridiag": 1, "operator": 2, "gram_dots": 3, "lines": 4, "other": 5,

@@ -172,7 +172,7 @@ SlotLayout layout_of(const fds_plan* p, int m, int precision) {
   const long long Nint = p->n_internal;
   const int P = std::max(1, div_up(Nc, kVecPerBlock));
   const int Lmax = std::max(p->nx, p->ny);
-  const bool flex = precision == FDS_FP32_PRECOND;
+  const bool flex = precision != FDS_FP64;
   SlotLayout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
@@ -313,6 +313,7 @@ void TaskSet::add_problem(Problem& sl) {
     tt.coef = flex ? (const void*)p->modes_cu->c32 : (const void*)p->modes_cu->c64;
     tt.skip = skip_it;
     tt.vin = sl.V; tt.vjs = Nc; tt.vscale = &sl.st->vscale;
+    tt.identity = p->opt.precision == FDS_NO_PRECOND ? 1 : 0;   // z^ = v^ (P = I)
     it_tri.add(tt);
     if (west || east) {
       ColTask ct{};
@@ -622,7 +623,7 @@ Engine::Engine(int m, int precision, int max_cycles, int capacity, hipStream_t s
   if (capacity < 1) throw Error(FDS_E_INVALID_ARG, "engine capacity must be positive");
   I.m = m;
   I.precision = precision;
-  I.flex = precision == FDS_FP32_PRECOND;
+  I.flex = precision != FDS_FP64;   // FP32 preconditioner or none: flexible GMRES
   I.max_cycles = max_cycles;
   I.s = stream;
   I.capacity = capacity;

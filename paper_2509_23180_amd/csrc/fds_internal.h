@@ -208,6 +208,8 @@ struct TriTask {
   double* vin;
   long long vjs;
   const double* vscale;
+  int identity;               // 1: no solve, data = the scaled right-hand side (P = I)
+  int pad_t;
 };
 
 // Schur line term: out[k] = sum_l Sline(k,l) z_line[l] with

@@ -196,11 +196,16 @@ __global__ void __launch_bounds__(kBlock) k_tridiag(const TriTask* __restrict__ 
     } else {
       r = d[i * rs];
     }
+    if (tk.identity) {   // no preconditioner: z^ = v^
+      d[i * rs] = r;
+      continue;
+    }
     w = c.sc * r + c.q * w;
     d[i * rs] = w;
     s += p * w;
     p *= c.q;
   }
+  if (tk.identity) return;
   const T gam = c.beta * s;
   T y = T(0);
   p = T(0);
@@ -261,6 +266,12 @@ __global__ void __launch_bounds__(1024) k_tridiag_seg(const TriTask* __restrict_
   } else {
 #pragma unroll
     for (int t = 0; t < LS; ++t) x[t] = (t < L) ? d[t * rs] : T(0);
+  }
+  if (tk.identity) {   // no preconditioner: z^ = v^
+#pragma unroll
+    for (int t = 0; t < LS; ++t)
+      if (t < L) d[t * rs] = x[t];
+    return;
   }
   // local forward sweep
   T w = T(0), A = T(0), p = T(1);

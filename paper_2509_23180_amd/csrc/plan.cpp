@@ -38,7 +38,7 @@ fds_plan* create_plan(const fds_rect* rects, int nrect, double h, double kappa,
   if (opt) o = *opt;
   if (o.restart_m < 1 || o.restart_m > 120) throw Error(FDS_E_INVALID_ARG, "restart_m must be in 1..120");
   if (o.max_cycles < 1) throw Error(FDS_E_INVALID_ARG, "max_cycles must be >= 1");
-  if (o.precision != FDS_FP64 && o.precision != FDS_FP32_PRECOND)
+  if (o.precision != FDS_FP64 && o.precision != FDS_FP32_PRECOND && o.precision != FDS_NO_PRECOND)
     throw Error(FDS_E_INVALID_ARG, "unknown precision");
   for (int r = 0; r < nrect; ++r) {
     const fds_rect& a = rects[r];
