@@ -238,7 +238,6 @@ struct TaskSet {
   size_t smem_lines = 0;
   TaskList<ColTask> it_cols;
   TaskList<OpTask> res_op;
-  TaskList<SpecOpTask> it_spec;      // flexible variant (sine basis of the centre)
   TaskList<KryTask> kry;
   TaskList<LiftTask> lift, gather;
   TaskList<IfaceTask> iface_fp, iface_bs;
@@ -263,7 +262,6 @@ struct TaskSet {
     blob.add(it_lines_d);
     blob.add(x_lines_d);
     blob.add(it_cols);
-    blob.add(it_spec);
     blob.add(res_op);
     blob.add(kry);
     blob.add(lift);
@@ -369,7 +367,7 @@ void TaskSet::add_problem(Problem& sl) {
     smem_lines = std::max(smem_lines, line_smem_bytes(a.L));
     LineTask li = lt;
     li.skip = skip_it;
-    // S/N blocks are diagonal in the centre's sine basis (k_spec_op, and
+    // S/N blocks are diagonal in the centre's sine basis (spec_w, and
     // qs terms in the plain Arnoldi step): no line term per step
     const bool it_line = a.line >= 2;
     li.z = sl.zcols + (a.line == 3 ? ny : 0); li.z_js = 0; li.z_f32 = 0;
@@ -418,19 +416,6 @@ void TaskSet::add_problem(Problem& sl) {
   }
   iface_fp.h.push_back(fi);
   iface_bs.h.push_back(bi);
-  if (flex) {
-    SpecOpTask so{};
-    so.z = sl.Z; so.z_js = Nc; so.out = sl.V + Nc; so.out_js = Nc;
-    for (const ArmInfo& a : p->arms) {
-      if (a.line == 0) so.gsS = a.gs->gs;
-      if (a.line == 1) so.gsN = a.gs->gs;
-    }
-    so.sW = ot.line[2];
-    so.sE = ot.line[3];
-    so.fft = fftc; so.delta = p->delta; so.kappa = p->kappa; so.nx = nx; so.ny = ny;
-    so.skip = skip_it;
-    add_block_task(it_spec, so, sl.P);
-  }
   {
     OpTask r = ot;
     r.z = sl.x_int + cd.off; r.z_js = 0; r.z_f32 = 0;
@@ -448,14 +433,21 @@ void TaskSet::add_problem(Problem& sl) {
     k.gram_lag = lag ? 1 : 0;
     k.implicit_w = flex ? 0 : 1;
     for (int q = 0; q < 4; ++q) k.line[q] = (q >= 2 && !flex) ? ot.line[q] : nullptr;
+    for (const ArmInfo& a : p->arms)
+      if (a.line < 2) k.gs[a.line] = a.gs->gs;
+    k.post = p->fft_c->host.post64;
+    k.qscale = qscale;
+    k.half_n = 0.5 * (nx + 1);
     if (!flex) {
-      for (const ArmInfo& a : p->arms)
-        if (a.line < 2) k.gs[a.line] = a.gs->gs;
       k.zhat = sl.tmpd;
-      k.post = p->fft_c->host.post64;
       k.bc = sl.bc;
-      k.qscale = qscale;
-      k.half_n = 0.5 * (nx + 1);
+    } else {
+      // the dot pass applies the operator itself (spec_w)
+      k.fuse_op = 1;
+      k.delta = p->delta;
+      k.kappa = p->kappa;
+      k.line[2] = ot.line[2];
+      k.line[3] = ot.line[3];
     }
     add_block_task(kry, k, sl.P);
   }
@@ -517,11 +509,6 @@ void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
     launch_lines_dense(it_lines_d.dev(), it_lines_d.n(), it_lines_d.nblocks, lmax_dense, j, s);
     launch_lines(it_lines.dev(), it_lines.n(), smem_lines, j, s);
     Timing::end(4, s);
-  }
-  if (flex) {
-    Timing::begin(2, s);
-    launch_spec_op(it_spec.dev(), it_spec.n(), it_spec.nblocks, j, s);
-    Timing::end(2, s);
   }
   Timing::begin(3, s);
   if (lag) launch_gram_bdots(kry.dev(), kry.n(), j, s);
@@ -865,14 +852,16 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
     for (const ArmInfo& a : sl.plan->arms) lines += line_bytes(a);
     // per Arnoldi step (sine basis): the tridiagonal solve reads v_j, writes
     // it back normalised and writes z^ (FP64 plain, FP32 z^_j flexible); the
-    // boundary columns read z^ (plain: and v_j); flexible: the operator reads
-    // z^_j and writes w.  Gram dots read
+    // boundary columns read z^ (plain: and v_j); flexible: the dot pass also
+    // applies the operator (reads z^_j, writes w).  Gram dots read
     // v_0..v_j (and w if stored), the update reads v_0..v_j (and w if
     // stored) and writes w.
     Timing::add_bytes(1, its * Nc * (8.0 + 8.0 + wz));
     if (flex) {
       Timing::add_bytes(7, its * Nc * wz);
-      Timing::add_bytes(2, its * Nc * (wz + 8.0));
+      // the dot pass also reads z^_j (4) and writes w (8); the w it no
+      // longer reads (8) is counted with the dots below
+      Timing::add_bytes(3, its * Nc * 4.0);
     } else {
       Timing::add_bytes(7, its * Nc * 16.0);   // z^ and v_j row sums
     }

@@ -287,6 +287,12 @@ struct KryTask {
   double* bc;
   double qscale;              // sqrt(2/N)
   double half_n;              // N/2
+  // Flexible variant: the dot pass forms w = Q L_c Q^T z^_j itself (see
+  // spec_w; gs, line[2..3], post, qscale, half_n as above) and stores it in
+  // V[j+1].
+  int fuse_op;
+  int pad_f;
+  double delta, kappa;
 };
 
 // Lagged Gram columns (exact preconditioner, restart length <= kLagMaxJ):
@@ -344,31 +350,6 @@ struct ColTask {
   const double* v;            // also: basis vector v_j (step stride Nc) ...
   double* bc;                 // ... whose boundary columns go to bc + 2 ny j (W, E), or NULL
   long long Nc;
-};
-
-// Spectral centre operator of the flexible variant, in the orthonormal sine
-// basis of the centre's x-direction (coefficients of row r at r nx + k - 1):
-//   w^[r][k] = d (z^[r-1][k] + z^[r+1][k]) + (kappa - 4 d + 2 d cos(pi k/N)) z^[r][k]
-//             - [r = 0] (N/2) gsS[k-1] z^[0][k] - [r = ny-1] (N/2) gsN[k-1] z^[ny-1][k]
-//             - sqrt(2/N) sin(pi k/N) sW[r] - sqrt(2/N) sin(pi k nx/N) sE[r],
-// i.e. Q L_c Q^T z^ with the S/N Schur blocks diagonal in this basis and the
-// W/E line terms (physical, from the dense line operators) transformed as
-// rank-one terms per row.
-struct SpecOpTask {
-  const float* z;             // z^_j (FP32), step stride z_js
-  long long z_js;
-  double* out;                // w^ (FP64), step stride out_js
-  long long out_js;
-  const double* gsS;          // delta^2 (2/N) g_k of the S / N arm, or NULL
-  const double* gsN;
-  const double* sW;           // line terms on column 0 / nx-1 (ny values), or NULL
-  const double* sE;
-  const FftDesc* fft;         // post64[k] = (cos, sin)(pi k / N)
-  double delta, kappa;
-  int nx, ny;
-  const int* skip;
-  int block_begin;
-  int pad;
 };
 
 struct LiftTask {

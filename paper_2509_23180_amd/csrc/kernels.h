@@ -83,8 +83,6 @@ void launch_gram_update_lag(const KryTask* tasks, int ntasks, int nblocks, int m
                             int tag, hipStream_t s);
 void launch_scale_newest(const KryTask* tasks, int j, int nblocks, hipStream_t s);
 void launch_idst_cols(const ColTask* tasks, int ntasks, int nblocks, int jidx, hipStream_t s);
-// Flexible variant in the centre's sine basis: the operator.
-void launch_spec_op(const SpecOpTask* tasks, int ntasks, int nblocks, int jidx, hipStream_t s);
 // Hessenberg least squares (back substitution), one workgroup per problem;
 // m is the restart length of every task.
 void launch_ls_solve(const KryTask* tasks, int ntasks, int m, hipStream_t s);

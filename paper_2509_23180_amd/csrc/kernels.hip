@@ -492,44 +492,6 @@ __global__ void __launch_bounds__(kBlock) k_idst_cols(const ColTask* __restrict_
   }
 }
 
-// Spectral centre operator of the flexible variant (see SpecOpTask).
-__global__ void __launch_bounds__(kBlock) k_spec_op(const SpecOpTask* __restrict__ tasks, int ntasks,
-                                                     int jidx) {
-  __shared__ int slot;
-  const SpecOpTask& tk = tasks[find_task(tasks, ntasks, &slot)];
-  if (tk.skip && *tk.skip) return;
-  const int b = blockIdx.x - tk.block_begin;
-  const int nx = tk.nx, ny = tk.ny;
-  const long long Nc = (long long)nx * ny;
-  const int N = nx + 1;
-  const double d = tk.delta;
-  const double qs = sqrt(2.0 / N), half = 0.5 * N;
-  const float* z = tk.z + (long long)jidx * tk.z_js;
-  double* out = tk.out + (long long)jidx * tk.out_js;
-  const double2* post = tk.fft->post64;
-  const long long base = (long long)b * kVecPerBlock;
-#pragma unroll
-  for (int e = 0; e < kVecEPT; ++e) {
-    const long long idx = base + (long long)e * kBlock + threadIdx.x;
-    if (idx >= Nc) break;
-    const int r = (int)(idx / nx);
-    const int c = (int)(idx - (long long)r * nx);
-    const int kk = c + 1;
-    const double2 cs = post[kk];
-    const double zc = double(z[idx]);
-    double nb = 0.0;
-    if (r > 0) nb += double(z[idx - nx]);
-    if (r < ny - 1) nb += double(z[idx + nx]);
-    double w = d * nb + (tk.kappa - 4.0 * d + 2.0 * d * cs.x) * zc;
-    if (r == 0 && tk.gsS) w -= half * tk.gsS[c] * zc;
-    if (r == ny - 1 && tk.gsN) w -= half * tk.gsN[c] * zc;
-    if (tk.sW) w -= qs * cs.y * tk.sW[r];
-    if (tk.sE) w -= qs * ((kk & 1) ? cs.y : -cs.y) * tk.sE[r];
-    out[idx] = w;
-  }
-}
-
-
 // =====================================================================
 // Centre operator (5-point stencil with zero data outside the centre, minus
 // the Schur line terms).  mode 0: out = L_c z.  mode 1: out = f' - L_c z,
@@ -625,6 +587,33 @@ __device__ __forceinline__ double line_term(const KryTask& tk, long long idx) {
   if (c == 0 && tk.line[2]) s += tk.line[2][r];
   if (c == tk.nx - 1 && tk.line[3]) s += tk.line[3][r];
   return s;
+}
+
+// w^[r][k] of the flexible variant's operator Q L_c Q^T z^_j at element idx,
+// in the orthonormal sine basis of the centre's x direction (coefficients of
+// row r at r nx + k - 1):
+//   w^[r][k] = d (z^[r-1][k] + z^[r+1][k]) + (kappa - 4 d + 2 d cos(pi k/N)) z^[r][k]
+//             - [r = 0] (N/2) gsS[k-1] z^[0][k] - [r = ny-1] (N/2) gsN[k-1] z^[ny-1][k]
+//             - sqrt(2/N) sin(pi k/N) sW[r] - sqrt(2/N) sin(pi k nx/N) sE[r]:
+// the S/N Schur blocks are diagonal in this basis and the W/E line terms
+// (physical, from the dense line operators) enter as rank-one terms per row.
+__device__ __forceinline__ double spec_w(const KryTask& tk, int j, long long idx) {
+  const unsigned ui = (unsigned)idx, unx = (unsigned)tk.nx;
+  const int r = (int)(ui / unx);
+  const int c = (int)(ui - (unsigned)r * unx);
+  const float* z = tk.Z + (long long)j * tk.Nc;
+  const double2 cs = tk.post[c + 1];
+  const double zc = double(z[idx]);
+  double nb = 0.0;
+  if (r > 0) nb += double(z[idx - tk.nx]);
+  if (r < tk.ny - 1) nb += double(z[idx + tk.nx]);
+  const double d = tk.delta;
+  double w = d * nb + (tk.kappa - 4.0 * d + 2.0 * d * cs.x) * zc;
+  if (r == 0 && tk.gs[0]) w -= tk.half_n * tk.gs[0][c] * zc;
+  if (r == tk.ny - 1 && tk.gs[1]) w -= tk.half_n * tk.gs[1][c] * zc;
+  if (tk.line[2]) w -= tk.qscale * cs.y * tk.line[2][r];
+  if (tk.line[3]) w -= tk.qscale * ((c & 1) ? -cs.y : cs.y) * tk.line[3][r];
+  return w;
 }
 
 // The last block of a problem to finish a launch does the problem's serial
@@ -783,13 +772,25 @@ __global__ void __launch_bounds__(kBlock) k_gram_dots(const KryTask* __restrict_
   const bool stored = !tk.implicit_w;
   double xj[kVecEPT], uv[kVecEPT];
   const double* vj = tk.V + (long long)j * Nc;
-  const double* w = tk.V + (long long)(j + 1) * Nc;
+  double* w = tk.V + (long long)(j + 1) * Nc;
+  if (tk.fuse_op) {
+    // flexible variant: w = Q L_c Q^T z^_j formed and stored here
 #pragma unroll
-  for (int e = 0; e < kVecEPT; ++e) {
-    const long long idx = base + (long long)e * kBlock + threadIdx.x;
-    const bool ok = idx < Nc;
-    xj[e] = ok ? vj[idx] : 0.0;
-    uv[e] = !ok ? 0.0 : (stored ? w[idx] : line_term(tk, idx));
+    for (int e = 0; e < kVecEPT; ++e) {
+      const long long idx = base + (long long)e * kBlock + threadIdx.x;
+      const bool ok = idx < Nc;
+      xj[e] = ok ? vj[idx] : 0.0;
+      uv[e] = ok ? spec_w(tk, j, idx) : 0.0;
+      if (ok) w[idx] = uv[e];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < kVecEPT; ++e) {
+      const long long idx = base + (long long)e * kBlock + threadIdx.x;
+      const bool ok = idx < Nc;
+      xj[e] = ok ? vj[idx] : 0.0;
+      uv[e] = !ok ? 0.0 : (stored ? w[idx] : line_term(tk, idx));
+    }
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i = 0; i <= j; ++i) {
@@ -1650,12 +1651,6 @@ void launch_idst_cols(const ColTask* tasks, int ntasks, int nblocks, int jidx, h
   if (nblocks <= 0) return;
   FDS_LAUNCH(k_idst_cols, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
 }
-
-void launch_spec_op(const SpecOpTask* tasks, int ntasks, int nblocks, int jidx, hipStream_t s) {
-  if (nblocks <= 0) return;
-  FDS_LAUNCH(k_spec_op, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
-}
-
 
 void launch_ls_solve(const KryTask* tasks, int ntasks, int m, hipStream_t s) {
   if (ntasks <= 0) return;
