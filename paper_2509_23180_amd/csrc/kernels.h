@@ -54,7 +54,9 @@ void launch_tridiag(bool fp32, const TriTask* tasks, int ntasks, int nblocks, in
 // Choice of tridiagonal kernel for a launch whose longest system has
 // max_rows rows: the segmented kernel (register segments of `ls` rows, `mpb`
 // modes per block, `threads` per block) when the rows fit, else one lane per
-// mode sweeping the rows.
+// mode sweeping the rows.  FDS_TRI_SEG="mpb,ls" forces a segmented
+// configuration (mpb in {8,16,32,64}, ls in {4,8,16}, or 32 for FP32) when
+// the rows fit; other values are ignored.
 struct TriConfig { bool seg; int ls; int mpb; int threads; };
 TriConfig tri_config(bool fp32, int max_rows);
 int tri_blocks(const TriConfig& c, int modes);

@@ -1,6 +1,8 @@
 // HIP kernels of the hot path (gfx950).  Every kernel works on a list of
 // task records so one launch serves all rectangles / problems of a batch.
 #include "kernels.h"
+#include <cstdio>
+#include <cstdlib>
 
 #include "fft_device.h"
 
@@ -250,19 +252,37 @@ __global__ void __launch_bounds__(1024) k_tridiag_seg(const TriTask* __restrict_
   const int rs = (int)tk.rs;
   T* d = static_cast<T*>(tk.data) + (long long)jidx * tk.js + (long long)i0 * rs + (k < tk.modes ? k : 0);
   T x[LS];
+  // a full segment loads (and stores) without per-row guards, so all LS
+  // loads of a thread are in flight together
+  const bool full = L == LS;
   if (tk.vin) {
     double* v = tk.vin + (long long)jidx * tk.vjs + (long long)i0 * rs + (k < tk.modes ? k : 0);
     const double sc = *tk.vscale;
+    double a[LS];
+    if (full) {
 #pragma unroll
-    for (int t = 0; t < LS; ++t) {
-      if (t < L) {
-        const double a = v[t * rs] * sc;
-        v[t * rs] = a;
-        x[t] = T(a);
-      } else {
-        x[t] = T(0);
+      for (int t = 0; t < LS; ++t) a[t] = v[t * rs];
+#pragma unroll
+      for (int t = 0; t < LS; ++t) {
+        a[t] *= sc;
+        v[t * rs] = a[t];
+        x[t] = T(a[t]);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < LS; ++t) {
+        if (t < L) {
+          a[t] = v[t * rs] * sc;
+          v[t * rs] = a[t];
+          x[t] = T(a[t]);
+        } else {
+          x[t] = T(0);
+        }
       }
     }
+  } else if (full) {
+#pragma unroll
+    for (int t = 0; t < LS; ++t) x[t] = d[t * rs];
   } else {
 #pragma unroll
     for (int t = 0; t < LS; ++t) x[t] = (t < L) ? d[t * rs] : T(0);
@@ -270,14 +290,14 @@ __global__ void __launch_bounds__(1024) k_tridiag_seg(const TriTask* __restrict_
   if (tk.identity) {   // no preconditioner: z^ = v^
 #pragma unroll
     for (int t = 0; t < LS; ++t)
-      if (t < L) d[t * rs] = x[t];
+      if (full || t < L) d[t * rs] = x[t];
     return;
   }
   // local forward sweep
   T w = T(0), A = T(0), p = T(1);
 #pragma unroll
   for (int t = 0; t < LS; ++t) {
-    if (t < L) {
+    if (full || t < L) {
       w = c.sc * x[t] + c.q * w;
       x[t] = w;
       A += p * w;
@@ -289,24 +309,40 @@ __global__ void __launch_bounds__(1024) k_tridiag_seg(const TriTask* __restrict_
     sb[s][lane] = A;
   }
   __syncthreads();
+  // The carries run serially over the S segments of a mode.  Their LDS inputs
+  // do not depend on the carry, so they are read eight segments at a time
+  // (SEGMAX is a multiple of 8: the reads past S stay inside the arrays and
+  // go unused); only the last segment can be shorter than LS.
+  static_assert(SEGMAX % 8 == 0, "segment chunks of 8");
+  const int Llast = m - (S - 1) * LS;
   if (s == 0 && k < tk.modes) {
     // forward carries, the first-row weight sum and gamma
-    T carry = T(0), qi0 = T(1), stot = T(0);
     T qLf = T(1), Bf = T(0), q2 = c.q;
     for (int t = 0; t < LS; ++t) { Bf += q2; q2 *= c.q * c.q; qLf *= c.q; }
-    for (int ss = 0; ss < S; ++ss) {
-      const int Ls = min(LS, m - ss * LS);
-      T qL = qLf, B = Bf;
-      if (Ls != LS) {
-        qL = T(1); B = T(0); q2 = c.q;
-        for (int t = 0; t < Ls; ++t) { B += q2; q2 *= c.q * c.q; qL *= c.q; }
+    T qLl = T(1), Bl = T(0);
+    q2 = c.q;
+    for (int t = 0; t < Llast; ++t) { Bl += q2; q2 *= c.q * c.q; qLl *= c.q; }
+    T carry = T(0), qi0 = T(1), stot = T(0);
+    for (int s0 = 0; s0 < S; s0 += 8) {
+      T E[8], As[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        E[u] = sa[s0 + u][lane];
+        As[u] = sb[s0 + u][lane];
       }
-      const T E = sa[ss][lane], As = sb[ss][lane];
-      stot += qi0 * (As + carry * B);
-      sa[ss][lane] = carry;
-      sb[ss][lane] = qi0;
-      carry = E + qL * carry;
-      qi0 *= qL;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int ss = s0 + u;
+        if (ss < S) {
+          const bool last = ss == S - 1;
+          const T qL = last ? qLl : qLf, B = last ? Bl : Bf;
+          stot += qi0 * (As[u] + carry * B);
+          sa[ss][lane] = carry;
+          sb[ss][lane] = qi0;
+          carry = E[u] + qL * carry;
+          qi0 *= qL;
+        }
+      }
     }
     sg[lane] = c.beta * stot;
   }
@@ -317,7 +353,7 @@ __global__ void __launch_bounds__(1024) k_tridiag_seg(const TriTask* __restrict_
     T pc = c.q, pg = qi0;
 #pragma unroll
     for (int t = 0; t < LS; ++t) {
-      if (t < L) {
+      if (full || t < L) {
         x[t] = x[t] + pc * cin - gam * pg;
         pc *= c.q;
         pg *= c.q;
@@ -325,7 +361,7 @@ __global__ void __launch_bounds__(1024) k_tridiag_seg(const TriTask* __restrict_
     }
 #pragma unroll
     for (int t = LS - 1; t >= 0; --t) {
-      if (t < L) {
+      if (full || t < L) {
         y = x[t] + c.q * y;
         x[t] = y;
       }
@@ -334,19 +370,23 @@ __global__ void __launch_bounds__(1024) k_tridiag_seg(const TriTask* __restrict_
   }
   __syncthreads();
   if (s == 0 && k < tk.modes) {
-    T qLf = T(1);
+    T qLf = T(1), qLl = T(1);
     for (int t = 0; t < LS; ++t) qLf *= c.q;
+    for (int t = 0; t < Llast; ++t) qLl *= c.q;
     T dc = T(0);
-    for (int ss = S - 1; ss >= 0; --ss) {
-      const int Ls = min(LS, m - ss * LS);
-      T qL = qLf;
-      if (Ls != LS) {
-        qL = T(1);
-        for (int t = 0; t < Ls; ++t) qL *= c.q;
+    for (int s0 = ((S - 1) / 8) * 8; s0 >= 0; s0 -= 8) {
+      T D[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) D[u] = sa[s0 + u][lane];
+#pragma unroll
+      for (int u = 7; u >= 0; --u) {
+        const int ss = s0 + u;
+        if (ss < S) {
+          const T qL = ss == S - 1 ? qLl : qLf;
+          sb[ss][lane] = dc;
+          dc = D[u] + qL * dc;
+        }
       }
-      const T D = sa[ss][lane];
-      sb[ss][lane] = dc;
-      dc = D + qL * dc;
     }
   }
   __syncthreads();
@@ -355,14 +395,14 @@ __global__ void __launch_bounds__(1024) k_tridiag_seg(const TriTask* __restrict_
     T pw = c.q;
 #pragma unroll
     for (int t = LS - 1; t >= 0; --t) {
-      if (t < L) {
+      if (full || t < L) {
         x[t] += pw * din;
         pw *= c.q;
       }
     }
 #pragma unroll
     for (int t = 0; t < LS; ++t)
-      if (t < L) d[t * rs] = x[t];
+      if (full || t < L) d[t * rs] = x[t];
   }
 }
 
@@ -1529,6 +1569,22 @@ TriConfig tri_config(bool fp32, int max_rows) {
   // (16 modes x 8 bytes still read whole 128-byte lines per row).
   TriConfig c{false, 0, 0, 0};
   const int lsmax = fp32 ? 32 : 16;
+  // tuning override "mpb,ls": taken when the pair is instantiated and fits
+  if (const char* e = std::getenv("FDS_TRI_SEG")) {
+    int mpb = 0, ls = 0;
+    if (std::sscanf(e, "%d,%d", &mpb, &ls) == 2 && (mpb == 8 || mpb == 16 || mpb == 32 || mpb == 64) &&
+        (ls == 4 || ls == 8 || ls == 16 || (fp32 && ls == 32))) {
+      const int S = (max_rows + ls - 1) / ls;
+      if (S <= 1024 / mpb) {
+        c.seg = true;
+        c.ls = ls;
+        c.mpb = mpb;
+        c.threads = mpb * (S < 1 ? 1 : S);
+        if (c.threads < 64) c.threads = 64;
+        return c;
+      }
+    }
+  }
   for (int mpb : {16, 32, 64}) {
     const int segmax = 1024 / mpb;
     for (int ls = 8; ls <= lsmax; ls *= 2) {
@@ -1564,16 +1620,19 @@ void launch_tri(const TriConfig& c, bool fp32, const TriTask* tasks, int ntasks,
   switch (c.mpb) {                             \
     case 64: FDS_SEG(T, L, 64); break;         \
     case 32: FDS_SEG(T, L, 32); break;         \
+    case 8: FDS_SEG(T, L, 8); break;           \
     default: FDS_SEG(T, L, 16); break;         \
   }
   if (fp32) {
     switch (c.ls) {
+      case 4: FDS_SEG_MPB(float, 4); break;
       case 8: FDS_SEG_MPB(float, 8); break;
       case 16: FDS_SEG_MPB(float, 16); break;
       default: FDS_SEG_MPB(float, 32); break;
     }
   } else {
     switch (c.ls) {
+      case 4: FDS_SEG_MPB(double, 4); break;
       case 8: FDS_SEG_MPB(double, 8); break;
       default: FDS_SEG_MPB(double, 16); break;
     }

@@ -107,6 +107,27 @@ def test_lagged_gram_columns(shape, n, kappa, kind, restart_m, monkeypatch):
     assert abs(out["1"] - out["0"]) <= max(2, out["0"] // 20), out
 
 
+@pytest.mark.parametrize("seg", ["8,4", "8,8", "8,16", "16,4", "16,16", "32,4", "32,8", "64,4", "16,32"])
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("shape,n,kappa,kind", [("cross", 64, 0.0, "shifted"), ("T", 45, -50.0, "gauss")])
+def test_tridiag_segment_configs(shape, n, kappa, kind, precision, seg, monkeypatch):
+    """Every instantiated (modes per block, rows per segment) pair of the
+    segmented tridiagonal solve, forced through its tuning override: full and
+    ragged last segments (45 rows), both precisions (32-row segments exist
+    for FP32 only; FP64 then keeps the automatic choice)."""
+    fds = _fds()
+    monkeypatch.setenv("FDS_TRI_SEG", seg)
+    log(f"tridiag segments {seg}: {shape} n={n} kappa={kappa} {kind} prec={precision}")
+    prob = _problem(shape, n, kappa, kind)
+    ref = oracle_solution(prob)
+    plan, rhs, bc, x = device_problem(prob, restart_m=30, precision=precision)
+    res = fds.solve(plan, rhs, x, 1e-12, bc=bc)
+    err = compare(prob, x, ref)
+    log(f"  its={res.iterations} cycles={res.cycles} err={err:.3e} relres={res.relres_schur:.2e}")
+    assert res.status == 0, res
+    assert err <= 1e-10
+
+
 @pytest.mark.parametrize("shape,n", [("cross", 16), ("L", 20)])
 def test_no_preconditioner_baseline(shape, n):
     """P = I (flexible GMRES with z = v) reaches the oracle too, and the
