@@ -131,10 +131,17 @@ def band_solve(A: sp.spmatrix, b: np.ndarray, spd_negative: bool) -> np.ndarray:
     return scipy.linalg.solve_banded((bw, bw), ab, b, check_finite=False)
 
 
+def sparse_lu(A: sp.spmatrix):
+    """SuperLU factorisation of the assembled matrix.  The column order is a
+    minimum-degree order of the pattern of A + A^T, which suits the symmetric
+    5-point matrix (about half the fill of the default column order)."""
+    return spla.splu(A.tocsc(), permc_spec="MMD_AT_PLUS_A")
+
+
 def sparse_lu_solve(A: sp.spmatrix, b: np.ndarray) -> np.ndarray:
     """SuperLU on the same assembled matrix (used where a dense band would not
     fit in host memory)."""
-    return spla.splu(A.tocsc()).solve(b)
+    return sparse_lu(A).solve(b)
 
 
 BAND_BYTES_LIMIT = int(os.environ.get("FDS_ORACLE_BAND_BYTES", str(6 << 30)))
@@ -174,6 +181,32 @@ def solve(rects: Sequence[Rect], h: float, kappa: float, f_grid, g_grid,
     r = b - A @ p
     nb = np.linalg.norm(b)
     return Solution(p, grid, float(np.linalg.norm(r) / nb) if nb > 0 else 0.0, method)
+
+
+def solve_many(rects: Sequence[Rect], h: float, kappa: float, fg: Sequence[Tuple[np.ndarray, np.ndarray]],
+               method: str = "auto") -> List[Solution]:
+    """solve() for several (f_grid, g_grid) pairs on one domain: the matrix is
+    assembled and factorised once (the right-hand sides differ)."""
+    if not fg:
+        return []
+    A, b0, grid = assemble(rects, h, kappa, fg[0][0], fg[0][1])
+    bs = [b0] + [assemble(rects, h, kappa, f, g)[1] for (f, g) in fg[1:]]
+    n = A.shape[0]
+    bw = half_bandwidth(A)
+    if method == "auto":
+        method = "band" if (bw + 1) * n * 8 <= BAND_BYTES_LIMIT else "splu"
+    out = []
+    if method == "splu":
+        lu = sparse_lu(A)
+        ps = [lu.solve(b) for b in bs]
+    elif method == "band":
+        ps = [band_solve(A, b, spd_negative=(kappa <= 0.0)) for b in bs]
+    else:
+        raise ValueError(method)
+    for p, b in zip(ps, bs):
+        nb = np.linalg.norm(b)
+        out.append(Solution(p, grid, float(np.linalg.norm(b - A @ p) / nb) if nb > 0 else 0.0, method))
+    return out
 
 
 def residual(rects: Sequence[Rect], h: float, kappa: float, f_grid, g_grid,

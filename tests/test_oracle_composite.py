@@ -85,6 +85,20 @@ def test_band_solvers_agree_with_dense(shape):
         assert s.relres < 1e-13
 
 
+@pytest.mark.parametrize("method", ["band", "splu"])
+def test_solve_many_matches_dense_per_rhs(method):
+    """One factorisation for several right-hand sides gives each dense solve."""
+    probs = [workloads.gaussian_problem("T", 6, -4.0, 98, 0, r) for r in range(3)]
+    probs.append(workloads.manufactured_problem("T", 6, -4.0, shifted=True))
+    p0 = probs[0]
+    sols = composite.solve_many(p0.rects, p0.h, p0.kappa, [(q.f_grid, q.g_grid) for q in probs],
+                                method=method)
+    for q, s in zip(probs, sols):
+        ref = composite.solve(q.rects, q.h, q.kappa, q.f_grid, q.g_grid, method="dense")
+        assert np.max(np.abs(s.p - ref.p)) <= 1e-13 * np.max(np.abs(ref.p))
+        assert s.relres < 1e-13
+
+
 def test_matrix_symmetric():
     """R_ij = R_ji^T for the self-adjoint operator (Section 2.3)."""
     prob = workloads.manufactured_problem("T", 9, -3.0)

@@ -110,3 +110,45 @@ def test_dst_matrix_entries_exact_for_large_n():
     for j, k in rng.integers(1, n + 1, size=(300, 2)):
         ref = float(mpmath.sin(mpmath.pi * int(j) * int(k) / (n + 1)))
         assert abs(S[j - 1, k - 1] - ref) <= 1e-15
+
+
+@pytest.mark.parametrize("n,h,kappa", [(1, 0.5, 0.0), (6, 1.0 / 7, -50.0), (17, 1.0 / 18, 3.0),
+                                       (40, 0.01, -100.0)])
+def test_mode_diagonal_is_shifted_line_spectrum(n, h, kappa):
+    """mode_diagonal is the spectrum of the x-direction line operator of the
+    5-point scheme plus the y-direction centre weight and kappa (Section 2.1):
+    eigenvalues of delta*tridiag(1, -2, 1) (built here from the stencil, not
+    from the oracle), shifted by -2 delta + kappa, sorted alike."""
+    d = 1.0 / (h * h)
+    T = np.zeros((n, n))
+    for i in range(n):
+        T[i, i] = -2.0 * d
+        if i > 0:
+            T[i, i - 1] = d
+        if i + 1 < n:
+            T[i, i + 1] = d
+    ref = np.sort(np.linalg.eigvalsh(T + (kappa - 2.0 * d) * np.eye(n)))
+    got = np.sort(rect.mode_diagonal(n, h, kappa))
+    assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("rows,cols,kappa", [(5, 4, 0.0), (3, 7, -30.0), (6, 6, 2.5)])
+def test_mode_diagonal_block_diagonalises_rectangle(rows, cols, kappa):
+    """Transforming the rectangle operator along x with the orthonormal sine
+    basis (written out here) leaves, for every mode k, the tridiagonal system
+    tridiag(delta, mode_diagonal[k], delta) along y: the per-mode systems the
+    fast solver runs (Section 2.1)."""
+    h = 1.0 / (max(rows, cols) + 1)
+    d = 1.0 / (h * h)
+    j = np.arange(1, cols + 1)
+    Q = np.sqrt(2.0 / (cols + 1)) * np.sin(np.pi * np.outer(j, j) / (cols + 1))
+    A = rect.rect_matrix(rows, cols, h, kappa).toarray()
+    B = np.kron(np.eye(rows), Q) @ A @ np.kron(np.eye(rows), Q.T)
+    diag = rect.mode_diagonal(cols, h, kappa)
+    for k in range(cols):
+        idx = np.arange(rows) * cols + k
+        blk = B[np.ix_(idx, idx)]
+        ref = np.diag(np.full(rows, diag[k])) + d * (np.eye(rows, k=1) + np.eye(rows, k=-1))
+        assert np.abs(blk - ref).max() <= 1e-10 * d
+        off = B[idx][:, np.setdiff1d(np.arange(rows * cols), idx)]
+        assert np.abs(off).max() <= 1e-10 * d
