@@ -389,6 +389,33 @@ def run_serving(args, device):
     }
 
 
+# --------------------------------------------------------------------------- reduced precision vs FP64
+
+def precision_error(items, xs):
+    """max|x - p*| / max|p*| of every solution of the precision workload
+    against the FP64 oracle (sparse direct solve of the global system, one
+    factorisation for both right-hand sides of the domain), computed after
+    the timed region."""
+    import numpy as np
+    from oracle import composite, layout as olayout
+    prob0 = items[0]
+    log(f"error vs the FP64 oracle: SuperLU on {prob0.shape} n={prob0.n} ...")
+    t0 = time.perf_counter()
+    sols = composite.solve_many(prob0.rects, prob0.h, prob0.kappa,
+                                [(p.f_grid, p.g_grid) for p in items], method="splu")
+    dt = time.perf_counter() - t0
+    out = {}
+    for prob, sol, x in zip(items, sols, xs):
+        H, W = sol.grid.height, sol.grid.width
+        G = olayout.from_user(prob.rects, x.detach().cpu().numpy(), (H, W))
+        ref = sol.on_grid()
+        m = sol.grid.unknown
+        out[prob.label] = float(np.max(np.abs(G[m] - ref[m])) / np.max(np.abs(ref[m])))
+    log(f"error vs oracle: {out} ({dt:.1f} s)")
+    return {"max_rel_err": out, "oracle": "global composite system, SuperLU (scipy splu), FP64",
+            "oracle_seconds": round(dt, 1)}
+
+
 # --------------------------------------------------------------------------- CPU baseline
 
 def cpu_baseline(items, sample):
@@ -430,6 +457,8 @@ def main():
     ap.add_argument("--serving-slots", type=int, default=64)
     ap.add_argument("--cpu-sample", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-error", action="store_true",
+                    help="precision workload: skip the error against the FP64 oracle")
     ap.add_argument("--latency-solves", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (HBM counter calibration)")
@@ -547,6 +576,10 @@ def main():
         fds.solve(P[0], R[0], X[0], tol, bc=B[0])
         lat.append((time.perf_counter() - t0) * 1e3)
 
+    error_vs_oracle = None
+    if args.workload == "precision" and not args.no_oracle_error:
+        error_vs_oracle = precision_error(items, X)
+
     achieved = (algo_bytes / calls) / ((ms / calls) * 1e-3) / 1e9 if calls and ms > 0 else None
     traffic = None
     kname = class_kernel(dominant, opts)
@@ -584,6 +617,8 @@ def main():
         "cpu_baseline": cpu,
         "kernel_source_hash": kernel_source_hash(),
     }
+    if error_vs_oracle is not None:
+        line["error_vs_oracle"] = error_vs_oracle
     if args.workload != "plain":
         line["dtype"] = "f64+f32"
     print(json.dumps(line), flush=True)

@@ -63,10 +63,31 @@ typedef enum {
   FDS_E_NOMEM = -5,           /* device allocation failed / over budget     */
   FDS_E_NOT_CONVERGED = -6,   /* cycle cap or stagnation; best x returned   */
   FDS_E_NONFINITE = -7,       /* NaN/Inf in the right-hand side             */
-  FDS_E_DEVICE = -8           /* HIP runtime error                          */
+  FDS_E_DEVICE = -8,          /* HIP runtime error                          */
+  FDS_E_UNSUPPORTED_BC = -9   /* a boundary-condition kind this build does  */
+                              /* not solve (see fds_bc)                     */
 } fds_status;
 
 typedef struct { int32_t i0, j0, i1, j1; } fds_rect;
+
+/* Boundary-condition kinds of the paper's Section 2.2 (Dirichlet, Neumann,
+ * periodic).  The kind selects the transform of each rectangle (sine
+ * transform for Dirichlet), so it is fixed when the plan is made; the
+ * Dirichlet VALUES are per-solve data and go to fds_solve / fds_batch_submit
+ * with the right-hand side, so one plan serves any number of boundary data. */
+typedef enum {
+  FDS_BC_DIRICHLET = 0,
+  FDS_BC_NEUMANN = 1,         /* reserved: FDS_E_UNSUPPORTED_BC             */
+  FDS_BC_PERIODIC = 2         /* reserved: FDS_E_UNSUPPORTED_BC             */
+} fds_bc_kind;
+
+typedef struct {
+  int32_t kind;               /* fds_bc_kind on every outer edge            */
+  const int32_t* edge_kinds;  /* optional host array of 4 kinds per         */
+                              /* rectangle (sides j=j0, i=i1, j=j1, i=i0),  */
+                              /* overriding `kind`; entries on shared edges */
+                              /* are ignored.  NULL: `kind` everywhere      */
+} fds_bc;
 
 typedef enum {
   FDS_FP64 = 0,               /* plain method: everything in FP64 (GMRES)   */
@@ -115,10 +136,12 @@ typedef struct fds_server fds_server;
  * line coefficients) on the current device.  h > 0; kappa <= 0 is always
  * accepted; kappa > 0 is accepted only if every mode stays diagonally
  * dominant, else FDS_E_UNSUPPORTED (FDS_E_SINGULAR if a subdomain operator
- * has a zero eigenvalue).  opt may be NULL (defaults).  On success *out owns
- * the tables until fds_plan_destroy. */
+ * has a zero eigenvalue).  bc (host struct) may be NULL (Dirichlet on every
+ * outer edge); a Neumann or periodic edge gives FDS_E_UNSUPPORTED_BC, an
+ * unknown kind FDS_E_INVALID_ARG.  opt may be NULL (defaults).  On success
+ * *out owns the tables until fds_plan_destroy. */
 fds_status fds_plan_create(const fds_rect* rects, int32_t nrect, double h, double kappa,
-                           const fds_options* opt, fds_plan** out);
+                           const fds_bc* bc, const fds_options* opt, fds_plan** out);
 void fds_plan_destroy(fds_plan* plan);
 
 /* Offsets (in doubles) of each rectangle's block in the unknown vector and in
@@ -161,14 +184,36 @@ fds_status fds_server_create(size_t hbm_budget_bytes, int32_t max_slots, fds_ser
 void fds_server_destroy(fds_server* server);
 
 /* Queue one solve; rhs/bc/x must stay valid until poll returns non-PENDING.
- * FDS_E_NOMEM if the request could never fit the budget. */
+ * The solve reads rhs/bc only after all work queued on `stream` before this
+ * call has completed (an event recorded on `stream`; NULL = the null stream),
+ * so inputs produced asynchronously on the caller's stream are safe to
+ * submit.  x is complete when poll returns non-PENDING.  FDS_E_NOMEM if the
+ * request could never fit the budget. */
 fds_status fds_batch_submit(fds_server* server, fds_plan* plan, const double* rhs,
-                            const double* bc, double* x, double tol, uint64_t* ticket);
+                            const double* bc, double* x, double tol, void* stream,
+                            uint64_t* ticket);
 
 /* FDS_PENDING while the request is queued or running; otherwise its final
- * status, with *res filled (may be NULL).  A finished ticket is forgotten
- * after the first non-PENDING poll. */
+ * status, with *res filled (may be NULL).  res->seconds is the request's
+ * latency: submission to publication of the result.  A finished ticket is
+ * forgotten after the first non-PENDING poll. */
 fds_status fds_batch_poll(fds_server* server, uint64_t ticket, fds_result* res);
+
+/* Counters of a server since it was created (a consistent snapshot). */
+typedef struct {
+  uint64_t submitted;         /* requests accepted by fds_batch_submit      */
+  uint64_t admitted;          /* requests that started their set-up phase   */
+  uint64_t completed;         /* results published                          */
+  uint64_t admitted_mid_flight; /* admissions at a cycle boundary while     */
+                              /* problems admitted earlier were still       */
+                              /* iterating on the device                    */
+  uint64_t cycles;            /* GMRES cycles stepped (all engine groups)   */
+  int32_t queued;             /* waiting for a slot or for memory now       */
+  int32_t running;            /* admitted and not yet retired now           */
+  uint64_t bytes_in_use;      /* footprint of the running requests now      */
+  uint64_t peak_bytes_in_use;
+} fds_server_stats;
+fds_status fds_server_stats_get(fds_server* server, fds_server_stats* out);
 
 /* ------------------------------------------------ kernel-level entry points
  * Single hot-path steps on raw device arrays, for verification and for

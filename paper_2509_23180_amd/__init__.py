@@ -20,7 +20,10 @@ FDS_OK = 0
 FDS_PENDING = 1
 STATUS = {0: "ok", 1: "pending", -1: "invalid argument", -2: "unsupported geometry",
           -3: "unsupported", -4: "singular", -5: "out of memory", -6: "not converged",
-          -7: "non-finite input", -8: "device error"}
+          -7: "non-finite input", -8: "device error", -9: "unsupported boundary condition"}
+BC_DIRICHLET = 0
+BC_NEUMANN = 1
+BC_PERIODIC = 2
 FP64 = 0
 FP32_PRECOND = 1
 NO_PRECOND = 2       # P = I: the convergence baseline (flexible GMRES, z = v in FP32)
@@ -39,6 +42,17 @@ class FdsError(RuntimeError):
 class _Rect(ctypes.Structure):
     _fields_ = [("i0", ctypes.c_int32), ("j0", ctypes.c_int32), ("i1", ctypes.c_int32),
                 ("j1", ctypes.c_int32)]
+
+
+class _Bc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("edge_kinds", ctypes.POINTER(ctypes.c_int32))]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("admitted_mid_flight", ctypes.c_uint64),
+                ("cycles", ctypes.c_uint64), ("queued", ctypes.c_int32), ("running", ctypes.c_int32),
+                ("bytes_in_use", ctypes.c_uint64), ("peak_bytes_in_use", ctypes.c_uint64)]
 
 
 class _Options(ctypes.Structure):
@@ -75,7 +89,7 @@ _lib = None
 SYMBOLS = (
     "fds_plan_create", "fds_plan_destroy", "fds_plan_layout", "fds_plan_footprint", "fds_solve",
     "fds_solve_batch", "fds_server_create", "fds_server_destroy", "fds_batch_submit",
-    "fds_batch_poll", "fds_k_dst_rows", "fds_k_dst_rows_f32", "fds_k_tridiag_modes",
+    "fds_batch_poll", "fds_server_stats_get", "fds_k_dst_rows", "fds_k_dst_rows_f32", "fds_k_tridiag_modes",
     "fds_k_tridiag_modes_f32", "fds_k_rect_solve", "fds_k_centre_operator", "fds_k_arnoldi_mgs",
     "fds_status_str", "fds_last_error", "fds_timing_enable", "fds_timing_read", "fds_timing_bytes",
     "fds_timing_reset",
@@ -94,8 +108,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     P = ctypes.c_void_p
     I32, I64, D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {
-        "fds_plan_create": ([ctypes.POINTER(_Rect), I32, D, D, ctypes.POINTER(_Options),
-                             ctypes.POINTER(P)], I32),
+        "fds_plan_create": ([ctypes.POINTER(_Rect), I32, D, D, ctypes.POINTER(_Bc),
+                             ctypes.POINTER(_Options), ctypes.POINTER(P)], I32),
         "fds_plan_destroy": ([P], None),
         "fds_plan_layout": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
         "fds_plan_footprint": ([P, ctypes.POINTER(ctypes.c_size_t)], I32),
@@ -104,8 +118,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                              ctypes.POINTER(P), ctypes.POINTER(D), P, ctypes.POINTER(_Result)], I32),
         "fds_server_create": ([ctypes.c_size_t, I32, ctypes.POINTER(P)], I32),
         "fds_server_destroy": ([P], None),
-        "fds_batch_submit": ([P, P, P, P, P, D, ctypes.POINTER(ctypes.c_uint64)], I32),
+        "fds_batch_submit": ([P, P, P, P, P, D, P, ctypes.POINTER(ctypes.c_uint64)], I32),
         "fds_batch_poll": ([P, ctypes.c_uint64, ctypes.POINTER(_Result)], I32),
+        "fds_server_stats_get": ([P, ctypes.POINTER(_ServerStats)], I32),
         "fds_k_dst_rows": ([P, P, I32, I32, D, P], I32),
         "fds_k_dst_rows_f32": ([P, P, I32, I32, ctypes.c_float, P], I32),
         "fds_k_tridiag_modes": ([P, I32, I32, D, D, D, P], I32),
@@ -164,18 +179,31 @@ def _stream(stream) -> Optional[int]:
 
 # --------------------------------------------------------------------------- plans
 
+def _bc_struct(bc_kind: int, edge_kinds: Optional[Sequence[int]], nrect: int):
+    if edge_kinds is None:
+        return _Bc(int(bc_kind), None), None
+    if len(edge_kinds) != 4 * nrect:
+        raise ValueError("edge_kinds needs 4 entries per rectangle")
+    arr = (ctypes.c_int32 * len(edge_kinds))(*map(int, edge_kinds))
+    return _Bc(int(bc_kind), ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))), arr
+
+
 class Plan:
-    """fds_plan_create wrapper.  rects: closed node boxes (i0, j0, i1, j1)."""
+    """fds_plan_create wrapper.  rects: closed node boxes (i0, j0, i1, j1).
+    bc_kind / edge_kinds: boundary-condition kinds (BC_*; edge_kinds has four
+    per rectangle, sides j=j0, i=i1, j=j1, i=i0)."""
 
     def __init__(self, rects: Sequence[Tuple[int, int, int, int]], h: float, kappa: float,
-                 restart_m: int = 30, max_cycles: int = 200, precision: int = FP64):
+                 restart_m: int = 30, max_cycles: int = 200, precision: int = FP64,
+                 bc_kind: int = BC_DIRICHLET, edge_kinds: Optional[Sequence[int]] = None):
         _require_gpu()
         lib = load_library()
         arr = (_Rect * len(rects))(*[_Rect(*map(int, r)) for r in rects])
         opt = _Options(restart_m, max_cycles, precision, 0)
+        bc, _keep = _bc_struct(bc_kind, edge_kinds, len(rects))
         out = ctypes.c_void_p()
-        _check(lib.fds_plan_create(arr, len(rects), float(h), float(kappa), ctypes.byref(opt),
-                                   ctypes.byref(out)))
+        _check(lib.fds_plan_create(arr, len(rects), float(h), float(kappa), ctypes.byref(bc),
+                                   ctypes.byref(opt), ctypes.byref(out)))
         self._h = out
         self.rects = [tuple(map(int, r)) for r in rects]
         self.h = float(h)
@@ -248,11 +276,15 @@ class Server:
         out = ctypes.c_void_p()
         _check(lib.fds_server_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(out)))
         self._h = out
+        self._held = {}   # ticket -> (plan, rhs, bc, x): alive until the result is polled
 
-    def submit(self, plan: Plan, rhs, x, tol: float, bc=None) -> int:
+    def submit(self, plan: Plan, rhs, x, tol: float, bc=None, stream=None) -> int:
+        """Queue a solve.  The server reads rhs/bc after the work queued on
+        `stream` (default: the current torch stream) up to this call."""
         t = ctypes.c_uint64()
         _check(load_library().fds_batch_submit(self._h, plan._h, _ptr(rhs), _ptr(bc), _ptr(x),
-                                               float(tol), ctypes.byref(t)))
+                                               float(tol), _stream(stream), ctypes.byref(t)))
+        self._held[t.value] = (plan, rhs, bc, x)
         return t.value
 
     def poll(self, ticket: int) -> Optional[Result]:
@@ -260,8 +292,14 @@ class Server:
         st = load_library().fds_batch_poll(self._h, int(ticket), ctypes.byref(res))
         if st == FDS_PENDING:
             return None
+        self._held.pop(int(ticket), None)
         _check(st, allow=(FDS_OK, -6, -7))
         return Result.from_c(res)
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        _check(load_library().fds_server_stats_get(self._h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in _ServerStats._fields_}
 
     def close(self):
         if getattr(self, "_h", None):

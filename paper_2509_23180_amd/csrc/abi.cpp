@@ -149,17 +149,56 @@ const char* fds_status_str(fds_status s) {
     case FDS_E_NOT_CONVERGED: return "not converged";
     case FDS_E_NONFINITE: return "non-finite input";
     case FDS_E_DEVICE: return "device error";
+    case FDS_E_UNSUPPORTED_BC: return "unsupported boundary-condition kind";
   }
   return "unknown status";
 }
 
 const char* fds_last_error(void) { return g_last_error.c_str(); }
 
+// Boundary-condition kinds of the plan: every outer edge must be Dirichlet
+// (the sine transforms); Neumann and periodic edges are recognised and
+// refused with their own status.  Shared (interface) edges carry no kind.
+static void check_bc(const fds_rect* rects, int32_t nrect, const fds_bc* bc) {
+  if (!bc) return;
+  auto check_kind = [](int32_t k) {
+    if (k == FDS_BC_DIRICHLET) return;
+    if (k == FDS_BC_NEUMANN || k == FDS_BC_PERIODIC)
+      throw Error(FDS_E_UNSUPPORTED_BC, k == FDS_BC_NEUMANN ? "Neumann edges are not supported (Dirichlet only)"
+                                                            : "periodic edges are not supported (Dirichlet only)");
+    throw Error(FDS_E_INVALID_ARG, "unknown boundary-condition kind " + std::to_string(k));
+  };
+  if (!bc->edge_kinds) {
+    check_kind(bc->kind);
+    return;
+  }
+  if (!rects || nrect < 1) return;   // the geometry check reports it
+  for (int32_t r = 0; r < nrect; ++r)
+    for (int side = 0; side < 4; ++side) {
+      const int32_t k = bc->edge_kinds[4 * r + side];
+      if (k == FDS_BC_DIRICHLET) continue;
+      const fds_rect& a = rects[r];
+      bool shared = false;
+      for (int32_t q = 0; q < nrect && !shared; ++q) {
+        if (q == r) continue;
+        const fds_rect& b = rects[q];
+        switch (side) {
+          case 0: shared = b.j1 == a.j0 && b.i0 == a.i0 && b.i1 == a.i1; break;
+          case 1: shared = b.i0 == a.i1 && b.j0 == a.j0 && b.j1 == a.j1; break;
+          case 2: shared = b.j0 == a.j1 && b.i0 == a.i0 && b.i1 == a.i1; break;
+          case 3: shared = b.i1 == a.i0 && b.j0 == a.j0 && b.j1 == a.j1; break;
+        }
+      }
+      if (!shared) check_kind(k);
+    }
+}
+
 fds_status fds_plan_create(const fds_rect* rects, int32_t nrect, double h, double kappa,
-                           const fds_options* opt, fds_plan** out) {
+                           const fds_bc* bc, const fds_options* opt, fds_plan** out) {
   return guarded([&] {
     if (!out) throw Error(FDS_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
+    check_bc(rects, nrect, bc);
     *out = create_plan(rects, nrect, h, kappa, opt);
     return FDS_OK;
   });
@@ -450,8 +489,16 @@ fds_status fds_server_create(size_t hbm_budget_bytes, int32_t max_slots, fds_ser
 void fds_server_destroy(fds_server* server) { server_destroy(server); }
 
 fds_status fds_batch_submit(fds_server* server, fds_plan* plan, const double* rhs,
-                            const double* bc, double* x, double tol, uint64_t* ticket) {
-  return guarded([&] { return server_submit(server, plan, rhs, bc, x, tol, ticket); });
+                            const double* bc, double* x, double tol, void* stream,
+                            uint64_t* ticket) {
+  return guarded([&] { return server_submit(server, plan, rhs, bc, x, tol, as_stream(stream), ticket); });
+}
+
+fds_status fds_server_stats_get(fds_server* server, fds_server_stats* out) {
+  return guarded([&] {
+    server_stats(server, out);
+    return FDS_OK;
+  });
 }
 
 fds_status fds_batch_poll(fds_server* server, uint64_t ticket, fds_result* res) {

@@ -573,12 +573,31 @@ struct Engine::Impl {
   std::vector<std::unique_ptr<Problem>> active;
   std::unique_ptr<TaskSet> cur;       // task lists of `active` (null when stale)
   int cycle_serial = 0;
+  // cycle in flight (between cycle_launch and cycle_finish)
+  bool in_flight = false;
+  std::vector<ProbState> before;
+  // captured cycle of the current task set
+  bool graphs = true;
+  long long ts_gen = 0;               // bumped whenever `cur` is replaced
+  long long cycles_on_gen = 0;        // cycles run with the current task set
+  long long graph_gen = -1;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;   // capture only (nothing runs on it)
+  int replays = 0;
 
   ~Impl() {
     // the device buffers go back to the cache: nothing queued may still use them
     if (s) (void)hipStreamSynchronize(s);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (flags_host) host_mapped_free(flags_host, sizeof(int) * capacity);
   }
+  void set_cur(std::unique_ptr<TaskSet> ts) {
+    cur = std::move(ts);
+    ++ts_gen;
+    cycles_on_gen = 0;
+  }
+  void launch_graph_cycle(TaskSet& ts);
   void read_states();
   TaskSet& current();
   void setup_phase(TaskSet& ts);
@@ -597,17 +616,52 @@ void Engine::Impl::read_states() {
 
 TaskSet& Engine::Impl::current() {
   if (!cur) {
-    cur.reset(new TaskSet(m, flex));
-    for (auto& p : active) cur->add_problem(*p);
-    cur->upload(s);
+    std::unique_ptr<TaskSet> ts(new TaskSet(m, flex));
+    for (auto& p : active) ts->add_problem(*p);
+    ts->upload(s);
+    set_cur(std::move(ts));
   }
   return *cur;
+}
+
+// Every Arnoldi step of a cycle and the cycle's end, captured once per task
+// set and replayed: the kernels of a step take their step index as a launch
+// argument and find everything else through the task lists, which stay put
+// while the set is unchanged.  All m steps are in the graph; a problem whose
+// cycle ended early skips its blocks (its cycle_done flag), as it does in
+// kernel-by-kernel mode while other problems still iterate.
+void Engine::Impl::launch_graph_cycle(TaskSet& ts) {
+  if (graph_gen != ts_gen) {
+    if (gexec) {
+      FDS_HIP(hipGraphExecDestroy(gexec));
+      gexec = nullptr;
+    }
+    if (!cap_stream) FDS_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+    FDS_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+    hipGraph_t g = nullptr;
+    try {
+      for (int j = 0; j < m; ++j) ts.iteration(j, flags_dev, 0, cap_stream);
+      ts.end_of_cycle(max_cycles, cap_stream);
+    } catch (...) {
+      (void)hipStreamEndCapture(cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    FDS_HIP(hipStreamEndCapture(cap_stream, &g));
+    const hipError_t e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    FDS_HIP(e);
+    graph_gen = ts_gen;
+  }
+  FDS_HIP(hipGraphLaunch(gexec, s));
+  ++replays;
 }
 
 Engine::Engine(int m, int precision, int max_cycles, int capacity, hipStream_t stream)
     : impl_(new Impl()) {
   Impl& I = *impl_;
   if (capacity < 1) throw Error(FDS_E_INVALID_ARG, "engine capacity must be positive");
+  if (const char* g = std::getenv("FDS_GRAPH")) I.graphs = std::string(g) != "0";
   I.m = m;
   I.precision = precision;
   I.flex = precision != FDS_FP64;   // FP32 preconditioner or none: flexible GMRES
@@ -631,10 +685,16 @@ size_t Engine::bytes_per_problem(const fds_plan* p, int m, int precision) {
 
 int Engine::free_slots() const { return (int)impl_->free_idx.size(); }
 int Engine::active() const { return (int)impl_->active.size(); }
+void Engine::set_graphs(bool on) { impl_->graphs = on; }
+int Engine::graph_replays() const { return impl_->replays; }
 
-void Engine::admit(const std::vector<SolveRequest>& reqs, const std::vector<int>& ids) {
+void Engine::admit(const std::vector<SolveRequest>& reqs, const std::vector<int>& ids,
+                   const std::vector<hipEvent_t>& wait_events) {
   Impl& I = *impl_;
   if (reqs.empty()) return;
+  if (I.in_flight) throw Error(FDS_E_INVALID_ARG, "admit while a cycle is in flight");
+  for (hipEvent_t e : wait_events)
+    if (e) FDS_HIP(hipStreamWaitEvent(I.s, e, 0));
   if ((int)reqs.size() > (int)I.free_idx.size()) throw Error(FDS_E_NOMEM, "engine has no free slot");
   const int m = I.m;
   const bool flex = I.flex;
@@ -703,7 +763,7 @@ void Engine::admit(const std::vector<SolveRequest>& reqs, const std::vector<int>
   ts->upload(I.s);
   I.setup_phase(*ts);
   // when the new problems are the whole set, their task lists serve the cycles
-  if (fresh.size() == I.active.size()) I.cur = std::move(ts);
+  if (fresh.size() == I.active.size()) I.set_cur(std::move(ts));
   else I.cur.reset();
 }
 
@@ -734,28 +794,50 @@ void Engine::Impl::setup_phase(TaskSet& ts) {
 }
 
 bool Engine::step_cycle() {
+  if (!cycle_launch()) return false;
+  return cycle_finish();
+}
+
+bool Engine::cycle_launch() {
   Impl& I = *impl_;
+  if (I.in_flight) throw Error(FDS_E_INVALID_ARG, "a cycle is already in flight");
   bool any = false;
   for (auto& p : I.active) any |= !I.host_states[p->idx].finished;
   if (!any) return false;
   TaskSet& ts = I.current();
-  const std::vector<ProbState> before = I.host_states;
-  const int tag = ++I.cycle_serial;
-  for (int j = 0; j < I.m; ++j) {
-    if (j >= 2) {
-      // stop launching once every running problem reported the end of this
-      // cycle (the finish kernel writes the tag to mapped host memory)
-      bool all = true;
-      const volatile int* fl = I.flags_host;
-      for (auto& p : I.active)
-        if (!before[p->idx].finished && fl[p->idx] != tag) { all = false; break; }
-      if (all) break;
+  I.before = I.host_states;
+  // per-kernel events cannot be captured: timed cycles launch kernel by kernel
+  if (I.graphs && I.cycles_on_gen >= 1 && !Timing::on()) {
+    I.launch_graph_cycle(ts);
+  } else {
+    const int tag = ++I.cycle_serial;
+    for (int j = 0; j < I.m; ++j) {
+      if (j >= 2) {
+        // stop launching once every running problem reported the end of this
+        // cycle (the finish kernel writes the tag to mapped host memory)
+        bool all = true;
+        const volatile int* fl = I.flags_host;
+        for (auto& p : I.active)
+          if (!I.before[p->idx].finished && fl[p->idx] != tag) { all = false; break; }
+        if (all) break;
+      }
+      ts.iteration(j, I.flags_dev, tag, I.s);
     }
-    ts.iteration(j, I.flags_dev, tag, I.s);
+    ts.end_of_cycle(I.max_cycles, I.s);
   }
-  ts.end_of_cycle(I.max_cycles, I.s);
-  I.read_states();
-  if (Timing::on()) I.account_cycle(before);
+  ++I.cycles_on_gen;
+  FDS_HIP(hipMemcpyAsync(I.host_states.data(), I.states.get(), sizeof(ProbState) * I.capacity,
+                         hipMemcpyDeviceToHost, I.s));
+  I.in_flight = true;
+  return true;
+}
+
+bool Engine::cycle_finish() {
+  Impl& I = *impl_;
+  if (!I.in_flight) throw Error(FDS_E_INVALID_ARG, "no cycle in flight");
+  FDS_HIP(hipStreamSynchronize(I.s));
+  I.in_flight = false;
+  if (Timing::on()) I.account_cycle(I.before);
   for (auto& p : I.active) if (!I.host_states[p->idx].finished) return true;
   return false;
 }
@@ -771,6 +853,7 @@ std::vector<std::pair<int, SolveOutcome>> Engine::retire(const std::vector<int>&
   Impl& I = *impl_;
   std::vector<std::pair<int, SolveOutcome>> res;
   if (ids.empty()) return res;
+  if (I.in_flight) throw Error(FDS_E_INVALID_ARG, "retire while a cycle is in flight");
   size_t hit = 0;
   for (auto& p : I.active)
     if (std::find(ids.begin(), ids.end(), p->id) != ids.end()) ++hit;

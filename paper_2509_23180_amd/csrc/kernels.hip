@@ -1672,10 +1672,17 @@ static size_t gram_solve_smem(int j) {
   return sizeof(double) * (3 * (size_t)(j + 1) + (size_t)j * (j + 1) / 2);
 }
 
-// (at most 60000 bytes for j < 120, below the 64 KiB default limit)
+// Static LDS of k_gram_dots (its per-wavefront dot table).
+constexpr size_t kGramDotsStatic = sizeof(double) * 2 * 121 * 4;
+
+// The dynamic part reaches 60000 bytes at j = 119; with the static table the
+// kernel then needs more than the 64 KiB granted by default.
 void launch_gram_dots(const KryTask* tasks, int ntasks, int nblocks, int j, hipStream_t s) {
   if (nblocks <= 0) return;
-  FDS_LAUNCH(k_gram_dots, dim3(nblocks), dim3(kBlock), gram_solve_smem(j), s, tasks, ntasks, j);
+  const size_t smem = gram_solve_smem(j);
+  static size_t granted = 0;
+  ensure_smem(k_gram_dots, smem + kGramDotsStatic, &granted);
+  FDS_LAUNCH(k_gram_dots, dim3(nblocks), dim3(kBlock), smem, s, tasks, ntasks, j);
 }
 
 void launch_gram_bdots(const KryTask* tasks, int ntasks, int j, hipStream_t s) {

@@ -242,9 +242,23 @@ class Engine {
   Engine(int m, int precision, int max_cycles, int capacity, hipStream_t stream);
   ~Engine();
   // Allocates the problems and runs their set-up phase (blocks until done).
-  void admit(const std::vector<SolveRequest>& reqs, const std::vector<int>& ids);
+  // wait_events (may be empty, else one per request, entries may be null):
+  // the set-up reads the request's inputs only after the event completed.
+  void admit(const std::vector<SolveRequest>& reqs, const std::vector<int>& ids,
+             const std::vector<hipEvent_t>& wait_events = {});
   // One GMRES cycle of every unfinished problem; false once none is running.
   bool step_cycle();
+  // The same cycle in three parts, so that the host can queue the cycles of
+  // several engines (on their own streams) before waiting for any of them:
+  // cycle_launch() queues the cycle (false: nothing to run), cycle_finish()
+  // waits for it and returns whether a problem is still running.
+  bool cycle_launch();
+  bool cycle_finish();
+  // Cycles of a fixed set of problems (from the second cycle on the same
+  // set) are replayed from one captured HIP graph instead of being launched
+  // kernel by kernel.  On by default; FDS_GRAPH=0 turns it off.
+  void set_graphs(bool on);
+  int graph_replays() const;
   // Problems that finished (converged, stalled, failed or out of cycles).
   std::vector<int> finished_ids() const;
   // Back substitution and output of the given problems; frees their memory.

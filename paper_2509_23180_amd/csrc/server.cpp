@@ -1,13 +1,16 @@
 // Request server with continuous batching at GMRES-cycle granularity.
 //
-// A host thread owns one HIP stream and one batch engine per (restart length,
-// precision, cycle cap).  Between cycles it retires every finished problem
-// (back substitution and output, result published to the ticket) and admits
-// queued requests in arrival order while their device footprint fits the
-// budget and a slot is free; admitted requests run their set-up phase and
-// join the next cycle of the running batch.  A request's arithmetic does not
-// depend on the other problems in the batch (per-problem kernels and
-// reductions), so its result is the same alone and in the mix.
+// A host thread owns one batch engine, on a HIP stream of its own, per
+// (restart length, precision, cycle cap).  Between cycles it retires every
+// finished problem (back substitution and output, result published to the
+// ticket) and admits queued requests in arrival order while their device
+// footprint fits the budget and a slot is free; admitted requests run their
+// set-up phase and join the next cycle of the running batch.  The cycles of
+// all engines are queued before the thread waits for any of them, so groups
+// of different precision or restart length overlap on the device.  A
+// request's arithmetic does not depend on the other problems in the batch
+// (per-problem kernels and reductions), so its result is the same alone and
+// in the mix.
 #include "server.h"
 
 #include <chrono>
@@ -29,6 +32,7 @@ struct Pending {
   SolveRequest req;
   size_t bytes;
   Clock::time_point submitted;
+  hipEvent_t ready;   // recorded on the submitter's stream (inputs written)
 };
 
 using Key = std::tuple<int, int, int>;   // restart_m, precision, max_cycles
@@ -36,8 +40,10 @@ using Key = std::tuple<int, int, int>;   // restart_m, precision, max_cycles
 Key key_of(const fds_plan* p) { return Key{p->opt.restart_m, p->opt.precision, p->opt.max_cycles}; }
 
 struct Group {
+  hipStream_t stream = nullptr;
   std::unique_ptr<Engine> eng;
   std::map<int, Pending> running;   // engine id -> request
+  bool launched = false;
 };
 
 }  // namespace
@@ -56,7 +62,8 @@ struct fds_server {
   uint64_t next_ticket = 1;
   bool stop = false;
   std::thread worker;
-  hipStream_t stream = nullptr;
+  std::vector<hipEvent_t> event_pool;   // guarded by mu
+  fds_server_stats stats{};             // guarded by mu
   // worker-thread state
   std::map<fds::Key, fds::Group> groups;
   size_t used = 0;
@@ -66,7 +73,23 @@ struct fds_server {
   void run();
   void admit_from_queue();
   void publish(const fds::Pending& p, const fds_result& r);
+  void fail_group(fds::Group& g, fds_status st);
+  hipEvent_t take_event();
 };
+
+hipEvent_t fds_server::take_event() {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!event_pool.empty()) {
+      hipEvent_t e = event_pool.back();
+      event_pool.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  FDS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return e;
+}
 
 void fds_server::publish(const fds::Pending& p, const fds_result& r0) {
   fds_result r = r0;
@@ -74,6 +97,22 @@ void fds_server::publish(const fds::Pending& p, const fds_result& r0) {
   std::lock_guard<std::mutex> lk(mu);
   done[p.ticket] = r;
   state[p.ticket] = 2;
+  stats.completed += 1;
+  // the event's wait was queued before the set-up phase, which has finished
+  if (p.ready) event_pool.push_back(p.ready);
+}
+
+void fds_server::fail_group(fds::Group& g, fds_status st) {
+  fds_result r{};
+  r.status = st;
+  for (auto& pr : g.running) {
+    publish(pr.second, r);
+    used -= pr.second.bytes;
+    --running;
+  }
+  g.running.clear();
+  g.eng.reset();   // its state is unknown after a failure
+  g.launched = false;
 }
 
 // Move queued requests into their engines while the footprint fits the
@@ -81,6 +120,7 @@ void fds_server::publish(const fds::Pending& p, const fds_result& r0) {
 // the rest so that a large request is not starved).
 void fds_server::admit_from_queue() {
   std::map<fds::Key, std::vector<fds::Pending>> take;
+  const bool mid_flight = running > 0;   // problems admitted earlier still iterate
   {
     std::lock_guard<std::mutex> lk(mu);
     size_t u = used;
@@ -97,30 +137,39 @@ void fds_server::admit_from_queue() {
   }
   for (auto& kv : take) {
     fds::Group& g = groups[kv.first];
-    if (!g.eng)
-      g.eng.reset(new fds::Engine(std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                                  max_slots, stream));
     std::vector<fds::SolveRequest> reqs;
     std::vector<int> ids;
+    std::vector<hipEvent_t> evs;
     for (const fds::Pending& p : kv.second) {
       reqs.push_back(p.req);
       ids.push_back(next_id++);
+      evs.push_back(p.ready);
     }
     try {
-      g.eng->admit(reqs, ids);
+      if (!g.stream) FDS_HIP(hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking));
+      if (!g.eng)
+        g.eng.reset(new fds::Engine(std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                                    max_slots, g.stream));
+      g.eng->admit(reqs, ids, evs);
       for (size_t i = 0; i < ids.size(); ++i) {
         g.running[ids[i]] = kv.second[i];
         used += kv.second[i].bytes;
         ++running;
       }
+      std::lock_guard<std::mutex> lk(mu);
+      stats.admitted += ids.size();
+      if (mid_flight) stats.admitted_mid_flight += ids.size();
+      stats.bytes_in_use = used;
+      stats.peak_bytes_in_use = std::max<uint64_t>(stats.peak_bytes_in_use, used);
     } catch (const fds::Error& e) {
       fds_result r{};
       r.status = e.status;
-      for (const fds::Pending& p : kv.second) publish(p, r);
-      g.eng.reset();   // its state is unknown after a failed set-up
-      for (auto& pr : g.running) publish(pr.second, r);
-      for (auto& pr : g.running) { used -= pr.second.bytes; --running; }
-      g.running.clear();
+      for (const fds::Pending& p : kv.second) {
+        bool admitted = false;
+        for (auto& pr : g.running) admitted |= pr.second.ticket == p.ticket;
+        if (!admitted) publish(p, r);
+      }
+      fail_group(g, e.status);
     }
   }
 }
@@ -134,11 +183,25 @@ void fds_server::run() {
       if (stop && queue.empty() && running == 0) return;
     }
     admit_from_queue();
+    // queue one cycle of every group, then wait for each in turn
     for (auto& kv : groups) {
       fds::Group& g = kv.second;
+      g.launched = false;
       if (!g.eng || g.running.empty()) continue;
       try {
-        g.eng->step_cycle();
+        g.launched = g.eng->cycle_launch();
+      } catch (const fds::Error& e) {
+        fail_group(g, e.status);
+      }
+    }
+    uint64_t cycles = 0;
+    for (auto& kv : groups) {
+      fds::Group& g = kv.second;
+      if (!g.eng || !g.launched) continue;
+      try {
+        g.eng->cycle_finish();
+        g.launched = false;
+        ++cycles;
         const std::vector<int> fin = g.eng->finished_ids();
         if (fin.empty()) continue;
         for (auto& pr : g.eng->retire(fin)) {
@@ -150,17 +213,12 @@ void fds_server::run() {
           g.running.erase(it);
         }
       } catch (const fds::Error& e) {
-        fds_result r{};
-        r.status = e.status;
-        for (auto& pr : g.running) {
-          publish(pr.second, r);
-          used -= pr.second.bytes;
-          --running;
-        }
-        g.running.clear();
-        g.eng.reset();
+        fail_group(g, e.status);
       }
     }
+    std::lock_guard<std::mutex> lk(mu);
+    stats.cycles += cycles;
+    stats.bytes_in_use = used;
   }
 }
 
@@ -172,7 +230,6 @@ fds_server* server_create(size_t budget, int max_slots) {
   s->budget = budget;
   s->max_slots = max_slots;
   FDS_HIP(hipGetDevice(&s->device));
-  FDS_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
   s->worker = std::thread([s] { s->run(); });
   return s;
 }
@@ -185,20 +242,34 @@ void server_destroy(fds_server* s) {
   }
   s->cv.notify_all();
   if (s->worker.joinable()) s->worker.join();
+  for (auto& kv : s->groups) {
+    kv.second.eng.reset();
+    if (kv.second.stream) (void)hipStreamDestroy(kv.second.stream);
+  }
   s->groups.clear();
-  if (s->stream) (void)hipStreamDestroy(s->stream);
+  for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+  for (auto& p : s->queue)
+    if (p.ready) (void)hipEventDestroy(p.ready);
   delete s;
 }
 
 fds_status server_submit(fds_server* s, fds_plan* plan, const double* rhs, const double* bc,
-                         double* x, double tol, uint64_t* ticket) {
+                         double* x, double tol, hipStream_t stream, uint64_t* ticket) {
   if (!s || !plan || !rhs || !x || !ticket || !(tol >= 0.0)) throw Error(FDS_E_INVALID_ARG, "bad submit arguments");
   const size_t bytes = Engine::bytes_per_problem(plan, plan->opt.restart_m, plan->opt.precision);
   if (bytes > s->budget) throw Error(FDS_E_NOMEM, "request footprint exceeds the server budget");
+  hipEvent_t ev = s->take_event();
+  const hipError_t e = hipEventRecord(ev, stream);
+  if (e != hipSuccess) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->event_pool.push_back(ev);
+    FDS_HIP(e);
+  }
   std::lock_guard<std::mutex> lk(s->mu);
   const uint64_t t = s->next_ticket++;
-  s->queue.push_back(Pending{t, SolveRequest{plan, rhs, bc, x, tol}, bytes, Clock::now()});
+  s->queue.push_back(Pending{t, SolveRequest{plan, rhs, bc, x, tol}, bytes, Clock::now(), ev});
   s->state[t] = 0;
+  s->stats.submitted += 1;
   *ticket = t;
   s->cv.notify_one();
   return FDS_OK;
@@ -215,6 +286,20 @@ fds_status server_poll(fds_server* s, uint64_t ticket, fds_result* res) {
   s->state.erase(it);
   if (res) *res = r;
   return (fds_status)r.status;
+}
+
+void server_stats(fds_server* s, fds_server_stats* out) {
+  if (!s || !out) throw Error(FDS_E_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  fds_server_stats st = s->stats;
+  int q = 0, r = 0;
+  for (auto& kv : s->state) {
+    if (kv.second == 0) ++q;
+    if (kv.second == 1) ++r;
+  }
+  st.queued = q;
+  st.running = r;
+  *out = st;
 }
 
 }  // namespace fds

@@ -60,3 +60,34 @@ def test_host_layout_packing_matches_oracle_layout():
         g = np.random.default_rng(1).normal(size=(19, 19))
         assert np.array_equal(playout.pack_unknowns(rects, g), olayout.to_user(rects, g))
         assert np.array_equal(playout.pack_boxes(rects, g), olayout.bc_boxes(rects, g))
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_boundary_condition_kinds_are_checked_before_any_device_work():
+    """Neumann and periodic edges are refused with their own status, an unknown
+    kind as an invalid argument; the check runs on the host before the plan
+    touches a device (so it runs here without a GPU)."""
+    import paper_2509_23180_amd as fds
+    lib = fds.load_library()
+    assert lib.fds_status_str(-9) == b"unsupported boundary-condition kind"
+    rects = (fds._Rect * 1)(fds._Rect(0, 0, 10, 10))
+    out = ctypes.c_void_p()
+    for kind, want in ((fds.BC_NEUMANN, -9), (fds.BC_PERIODIC, -9), (7, -1)):
+        bc, _ = fds._bc_struct(kind, None, 1)
+        st = lib.fds_plan_create(rects, 1, 0.1, 0.0, ctypes.byref(bc), None, ctypes.byref(out))
+        assert st == want, (kind, st)
+        assert out.value is None
+    # per-edge kinds: a Neumann side of a lone square is an outer edge
+    bc, keep = fds._bc_struct(fds.BC_DIRICHLET, [0, 0, fds.BC_NEUMANN, 0], 1)
+    assert lib.fds_plan_create(rects, 1, 0.1, 0.0, ctypes.byref(bc), None, ctypes.byref(out)) == -9
+    # a Neumann kind on the shared side of two squares is ignored by the check
+    # (the plan then needs a device, so only the host check is exercised here)
+    two = (fds._Rect * 2)(fds._Rect(0, 0, 10, 10), fds._Rect(10, 0, 20, 10))
+    bc, keep = fds._bc_struct(fds.BC_DIRICHLET, [0, 0, 0, fds.BC_NEUMANN, 0, fds.BC_NEUMANN, 0, 0], 2)
+    st = lib.fds_plan_create(two, 2, 0.1, 0.0, ctypes.byref(bc), None, ctypes.byref(out))
+    assert st == -9   # outer sides of both squares
+    bc, keep = fds._bc_struct(fds.BC_DIRICHLET, [0, fds.BC_NEUMANN, 0, 0, 0, 0, 0, fds.BC_NEUMANN], 2)
+    st = lib.fds_plan_create(two, 2, 0.1, 0.0, ctypes.byref(bc), None, ctypes.byref(out))
+    assert st != -9   # both Neumann entries sit on the shared edge
+    if st == 0:
+        lib.fds_plan_destroy(out)
