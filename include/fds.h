@@ -256,6 +256,21 @@ fds_status fds_k_centre_operator(const fds_plan* plan, const double* z, double* 
  * h (device, k+1 doubles) holds <w_i, v_i> for i < k and the norm. */
 fds_status fds_k_arnoldi_mgs(double* V, int32_t k, int64_t len, double* h, void* stream);
 
+/* The same Arnoldi step for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): its working memory (Hessenberg column, Gram matrix, block
+ * partials and counters, state, task records) lives in a fixed array of 8 MiB
+ * that each device holds from its first use until the process ends, and the
+ * call allocates nothing.  V and h are as for fds_k_arnoldi_mgs and results
+ * are identical.  Working memory grows with k and len (about
+ * 8 (2k + 6) ceil(len / 2048) bytes of partials); a call that would need
+ * more than the array holds fails with FDS_E_NOMEM before launching
+ * anything.  All calls on one device share the array, which keeps the
+ * previous call's contents (the call clears what must start at zero): calls
+ * that overlap on one device race, so serialise them (one stream, or host
+ * ordering). */
+fds_status fds_k_arnoldi_mgs_noalloc(double* V, int32_t k, int64_t len, double* h, void* stream);
+
 /* ---------------------------------------------------------------- misc */
 const char* fds_status_str(fds_status s);
 const char* fds_last_error(void);

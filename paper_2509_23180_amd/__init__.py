@@ -91,6 +91,7 @@ SYMBOLS = (
     "fds_solve_batch", "fds_server_create", "fds_server_destroy", "fds_batch_submit",
     "fds_batch_poll", "fds_server_stats_get", "fds_k_dst_rows", "fds_k_dst_rows_f32", "fds_k_tridiag_modes",
     "fds_k_tridiag_modes_f32", "fds_k_rect_solve", "fds_k_centre_operator", "fds_k_arnoldi_mgs",
+    "fds_k_arnoldi_mgs_noalloc",
     "fds_status_str", "fds_last_error", "fds_timing_enable", "fds_timing_read", "fds_timing_bytes",
     "fds_timing_reset",
 )
@@ -128,6 +129,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "fds_k_rect_solve": ([P, P, I32, I32, D, D, I32, P], I32),
         "fds_k_centre_operator": ([P, P, P, P], I32),
         "fds_k_arnoldi_mgs": ([P, I32, I64, P, P], I32),
+        "fds_k_arnoldi_mgs_noalloc": ([P, I32, I64, P, P], I32),
         "fds_status_str": ([I32], ctypes.c_char_p),
         "fds_last_error": ([], ctypes.c_char_p),
         "fds_timing_enable": ([I32], I32),
@@ -346,6 +348,13 @@ def centre_operator(plan: Plan, z, w, stream=None):
 def arnoldi_mgs(V, k: int, h, stream=None):
     _check(load_library().fds_k_arnoldi_mgs(_ptr(V), int(k), int(V.shape[1]), _ptr(h),
                                             _stream(stream)))
+
+
+def arnoldi_mgs_noalloc(V, k: int, h, stream=None):
+    """fds_k_arnoldi_mgs_noalloc: the same step with the library's fixed
+    per-device working memory (no device allocation)."""
+    _check(load_library().fds_k_arnoldi_mgs_noalloc(_ptr(V), int(k), int(V.shape[1]), _ptr(h),
+                                                    _stream(stream)))
 
 
 def timing_enable(classes=None):

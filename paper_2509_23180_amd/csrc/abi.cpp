@@ -446,6 +446,57 @@ fds_status fds_k_arnoldi_mgs(double* V, int32_t k, int64_t len, double* h, void*
   });
 }
 
+fds_status fds_k_arnoldi_mgs_noalloc(double* V, int32_t k, int64_t len, double* h, void* stream) {
+  return guarded([&] {
+    hipStream_t s = as_stream(stream);
+    if (!V || !h || k < 1 || len < 1 || k > 120) throw Error(FDS_E_INVALID_ARG, "bad Arnoldi arguments");
+    const int m = k;
+    const int j = k - 1;
+    const int P = (int)((len + kVecPerBlock - 1) / kVecPerBlock);
+    // the working memory of fds_k_arnoldi_mgs, laid out in the scratch array
+    const size_t small = (size_t)(m + 1) * m + 4 * (size_t)m + 2;
+    const size_t gram = (size_t)(m + 1) * (m + 1) + (m + 1);
+    const size_t parts = kry_partials_len(m, P);
+    const size_t n_zero = small + gram + parts;
+    const size_t st_off = (8 * n_zero + 255) / 256 * 256;
+    const size_t dt_off = st_off + 512;
+    const size_t need = dt_off + 2 * sizeof(KryTask);
+    if (need > kNoAllocScratchBytes)
+      throw Error(FDS_E_NOMEM, "Arnoldi step of k = " + std::to_string(k) + " vectors of length " +
+                                   std::to_string(len) + " needs " + std::to_string(need) +
+                                   " bytes of working memory; the allocation-free entry point has " +
+                                   std::to_string(kNoAllocScratchBytes));
+    char* base = static_cast<char*>(noalloc_scratch());
+    double* H = reinterpret_cast<double*>(base);
+    double* G = H + small;
+    double* partials = G + gram;
+    auto* st = reinterpret_cast<ProbState*>(base + st_off);
+    auto* dt = reinterpret_cast<KryTask*>(base + dt_off);
+    ProbState hs{};
+    hs.beta = 1.0;
+    hs.fnorm = 1.0;
+    hs.tol_eff = 0.0;
+    hs.vscale = 1.0;
+    KryTask t{};
+    t.V = V; t.H = H; t.cs = H + (size_t)(m + 1) * m; t.sn = t.cs + m; t.g = t.sn + m; t.y = t.g + m + 1;
+    t.partials = partials; t.st = st; t.Nc = len; t.P = P; t.m = m; t.G = G; t.hv = G + (size_t)(m + 1) * (m + 1);
+    t.nx = (int)std::min<int64_t>(len, 1 << 30); t.ny = 1;
+    KryTask gt = t;   // Gram columns of the existing basis (w implicit, no line terms)
+    gt.implicit_w = 1;
+    t.implicit_w = 0;
+    launch_noalloc_setup(H, (long long)n_zero, st, hs, dt, t, gt, s);
+    for (int c = 0; c < j; ++c) launch_gram_dots(dt + 1, 1, P, c, s);
+    launch_gram_dots(dt, 1, P, j, s);
+    launch_gram_update(dt, 1, P, j, nullptr, 0, s);
+    FDS_HIP(hipMemcpyAsync(h, t.hv, 8 * (size_t)k, hipMemcpyDeviceToDevice, s));
+    launch_scale_newest(dt, j, std::max(1, std::min(P * kVecEPT, 1024)), s);
+    FDS_HIP(hipMemcpyAsync(h + k, &st->last_hn, 8, hipMemcpyDeviceToDevice, s));
+    FDS_HIP(hipGetLastError());
+    FDS_HIP(hipStreamSynchronize(s));
+    return FDS_OK;
+  });
+}
+
 fds_status fds_timing_enable(int32_t mask) {
   return guarded([&] { Timing::enable(mask); return FDS_OK; });
 }

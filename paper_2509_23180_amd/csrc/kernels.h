@@ -98,4 +98,12 @@ void launch_res_sum(const ResSumTask* tasks, int ntasks, hipStream_t s);
 void launch_copy(const CopyTask* tasks, int ntasks, int nblocks, hipStream_t s);
 void launch_count_active(const ProbState* st, int n, int* out, hipStream_t s);
 
+// Allocation-free Arnoldi step: size of the per-device scratch array, its
+// device address on the current device (looked up once per device), and the
+// kernel that clears its partials and writes the state and task records.
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+void* noalloc_scratch();
+void launch_noalloc_setup(double* zero, long long n_zero, ProbState* st, const ProbState& hs,
+                          KryTask* dt, const KryTask& t0, const KryTask& t1, hipStream_t s);
+
 }  // namespace fds

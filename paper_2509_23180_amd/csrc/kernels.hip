@@ -1,8 +1,11 @@
 // HIP kernels of the hot path (gfx950).  Every kernel works on a list of
 // task records so one launch serves all rectangles / problems of a batch.
 #include "kernels.h"
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 
 #include "fft_device.h"
 
@@ -1771,6 +1774,54 @@ void launch_residual(const ResTask* tasks, int ntasks, int nblocks, hipStream_t 
 
 void launch_count_active(const ProbState* st, int n, int* out, hipStream_t s) {
   FDS_LAUNCH(k_count_active, dim3(1), dim3(kBlock), 0, s, st, n, out);
+}
+
+// ------------------------------------------------ allocation-free Arnoldi step
+// Working memory of fds_k_arnoldi_mgs_noalloc: Hessenberg column, Givens
+// arrays, Gram matrix, block partials and hand-off counters, the problem
+// state and the two task records, in one array of fixed size that each
+// device holds for the life of the process.  Host code never names the
+// array: it uses the device address looked up once per device below.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+}  // namespace
+
+void* noalloc_scratch() {
+  int dev = 0;
+  FDS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  FDS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) throw Error(FDS_E_DEVICE, "no device address for the scratch array");
+  g_scratch_ptr[dev] = ptr;
+  return ptr;
+}
+
+// Zero the first n_zero doubles (partials and counters must start at zero)
+// and write the state and the task records behind them; the records arrive
+// as kernel arguments, so nothing is copied from host memory.
+__global__ void k_noalloc_setup(double* __restrict__ zero, long long n_zero, ProbState* st,
+                                ProbState hs, KryTask* dt, KryTask t0, KryTask t1) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_zero;
+       i += (long long)gridDim.x * blockDim.x)
+    zero[i] = 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *st = hs;
+    dt[0] = t0;
+    dt[1] = t1;
+  }
+}
+
+void launch_noalloc_setup(double* zero, long long n_zero, ProbState* st, const ProbState& hs,
+                          KryTask* dt, const KryTask& t0, const KryTask& t1, hipStream_t s) {
+  const long long per = (long long)kBlock * 8;
+  const int nb = (int)std::max(1LL, std::min(1024LL, (n_zero + per - 1) / per));
+  FDS_LAUNCH(k_noalloc_setup, dim3(nb), dim3(kBlock), 0, s, zero, n_zero, st, hs, dt, t0, t1);
 }
 
 }  // namespace fds
