@@ -108,11 +108,28 @@ typedef enum {
   FDS_STOP_STAGNATION = 4
 } fds_stop_reason;
 
+/* fds_options.flags */
+enum {
+  /* Interface Krylov iteration (FDS_FP64 only): the same right-preconditioned
+   * GMRES(m), with its basis stored on the coupled rectangle's interface
+   * lines.  The preconditioned operator I - S A_c^{-1} changes a vector only
+   * on the lines that border an independent subdomain (S is zero elsewhere),
+   * so every basis vector is a multiple of the cycle's interior residual plus
+   * a vector on those lines; the Arnoldi step then costs O(line length)
+   * memory traffic (plus O(nx ny) arithmetic for the coupling between the two
+   * axes) instead of O(m nx ny), and the transforms and per-mode solves run
+   * once per cycle.  Iterates equal those of the full-vector iteration up to
+   * rounding.  Centres narrower than 2 nodes, or whose lines together exceed
+   * 9215 nodes, use the full-vector iteration (the flag is then cleared in
+   * the plan). */
+  FDS_FLAG_INTERFACE_KRYLOV = 1u
+};
+
 typedef struct {
   int32_t restart_m;          /* Krylov dimension per cycle (default 30)    */
   int32_t max_cycles;         /* restart cap (default 200)                  */
   int32_t precision;          /* fds_precision                              */
-  uint32_t flags;             /* reserved, must be 0                        */
+  uint32_t flags;             /* FDS_FLAG_* (0: the full-vector iteration)  */
 } fds_options;
 
 typedef struct {

@@ -21,6 +21,7 @@ FDS_PENDING = 1
 STATUS = {0: "ok", 1: "pending", -1: "invalid argument", -2: "unsupported geometry",
           -3: "unsupported", -4: "singular", -5: "out of memory", -6: "not converged",
           -7: "non-finite input", -8: "device error", -9: "unsupported boundary condition"}
+FLAG_INTERFACE_KRYLOV = 1   # fds_options.flags: Krylov basis on the centre's interface lines
 BC_DIRICHLET = 0
 BC_NEUMANN = 1
 BC_PERIODIC = 2
@@ -197,11 +198,12 @@ class Plan:
 
     def __init__(self, rects: Sequence[Tuple[int, int, int, int]], h: float, kappa: float,
                  restart_m: int = 30, max_cycles: int = 200, precision: int = FP64,
-                 bc_kind: int = BC_DIRICHLET, edge_kinds: Optional[Sequence[int]] = None):
+                 bc_kind: int = BC_DIRICHLET, edge_kinds: Optional[Sequence[int]] = None,
+                 flags: int = 0):
         _require_gpu()
         lib = load_library()
         arr = (_Rect * len(rects))(*[_Rect(*map(int, r)) for r in rects])
-        opt = _Options(restart_m, max_cycles, precision, 0)
+        opt = _Options(restart_m, max_cycles, precision, int(flags))
         bc, _keep = _bc_struct(bc_kind, edge_kinds, len(rects))
         out = ctypes.c_void_p()
         _check(lib.fds_plan_create(arr, len(rects), float(h), float(kappa), ctypes.byref(bc),
@@ -212,6 +214,7 @@ class Plan:
         self.kappa = float(kappa)
         self.restart_m = restart_m
         self.precision = precision
+        self.flags = int(flags)
         n = len(rects)
         uo = (ctypes.c_int64 * (n + 1))()
         bo = (ctypes.c_int64 * (n + 1))()

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libfds.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "dst_wave.hip", "alloc.cpp", "tune.cpp", "tables.cpp", "plan.cpp", "engine.cpp", "server.cpp", "abi.cpp"]
+SOURCES = ["kernels.hip", "dst_wave.hip", "ik_kernels.hip", "alloc.cpp", "tune.cpp", "tables.cpp", "plan.cpp", "engine.cpp", "server.cpp", "abi.cpp"]
 ARCH = os.environ.get("FDS_OFFLOAD_ARCH", "gfx950")
 
 

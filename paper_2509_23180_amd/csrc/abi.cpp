@@ -234,16 +234,19 @@ fds_status fds_solve_batch(fds_plan* const* plans, int32_t count, const double* 
     std::vector<SolveRequest> reqs(count);
     const int m = plans[0] ? plans[0]->opt.restart_m : 0;
     const int prec = plans[0] ? plans[0]->opt.precision : 0;
+    const uint32_t flags = plans[0] ? plans[0]->opt.flags : 0;
     int max_cycles = 1;
     for (int i = 0; i < count; ++i) {
       if (!plans[i] || !rhs[i] || !x[i]) throw Error(FDS_E_INVALID_ARG, "NULL plan/rhs/x in batch");
       if (plans[i]->opt.restart_m != m || plans[i]->opt.precision != prec)
         throw Error(FDS_E_INVALID_ARG, "batched plans must share restart_m and precision");
+      if (plans[i]->opt.flags != flags)
+        throw Error(FDS_E_INVALID_ARG, "batched plans must share the Krylov iteration (option flags)");
       if (!(tol[i] >= 0.0)) throw Error(FDS_E_INVALID_ARG, "tol must be >= 0");
       max_cycles = std::max(max_cycles, plans[i]->opt.max_cycles);
       reqs[i] = SolveRequest{plans[i], rhs[i], bc ? bc[i] : nullptr, x[i], tol[i]};
     }
-    std::vector<SolveOutcome> out = Engine::run_batch(reqs, m, prec, max_cycles, as_stream(stream));
+    std::vector<SolveOutcome> out = Engine::run_batch(reqs, m, prec, max_cycles, as_stream(stream), flags);
     fds_status first = FDS_OK;
     for (int i = 0; i < count; ++i) {
       if (res) res[i] = out[i].res;

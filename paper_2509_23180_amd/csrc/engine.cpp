@@ -159,7 +159,34 @@ struct TriStage {
 struct SlotLayout {
   size_t b_int, x_int, tmpd, fp, V, u, zbuf, lines, small, partials, respart, Z, tmpf, gram, zcols,
       bc, total;
+  // interface Krylov iteration
+  size_t V0, Vb, rline, rho, zcol, zc, ucoef, uphys, dhat, xpart, scal;
 };
+
+// Interface Krylov iteration: coordinates of the lines that carry an arm.
+struct IkGeom {
+  int nb = 0, ldv = 0, off[4] = {-1, -1, -1, -1};
+  int nxa = 0, nya = 0;   // cross-sum blocks of the two directions
+};
+
+IkGeom ik_geom(const fds_plan* p) {
+  IkGeom g;
+  for (const ArmInfo& a : p->arms) {
+    g.off[a.line] = 0;
+  }
+  for (int a = 0; a < 4; ++a)
+    if (g.off[a] == 0) {
+      g.off[a] = g.nb;
+      g.nb += a < 2 ? p->nx : p->ny;
+    }
+  g.ldv = (1 + g.nb + 31) / 32 * 32;
+  const bool xl = g.off[0] >= 0 || g.off[1] >= 0, yl = g.off[2] >= 0 || g.off[3] >= 0;
+  if (xl && yl) {
+    g.nxa = div_up(p->ny, kIkXTile);   // x -> y: targets along y
+    g.nya = div_up(p->nx, kIkXTile);
+  }
+  return g;
+}
 
 int res_blocks_of(const fds_plan* p) {
   int nb = 0;
@@ -180,6 +207,28 @@ SlotLayout layout_of(const fds_plan* p, int m, int precision) {
   L.x_int = take(8 * Nint);
   L.tmpd = take(8 * Nint);
   L.fp = take(8 * Nc);
+  if (p->interface_krylov()) {
+    const IkGeom g = ik_geom(p);
+    L.u = take(8 * Nc);
+    L.V0 = take(8 * Nc);
+    L.lines = take(8 * 4 * (size_t)Lmax);
+    L.small = take(8 * ((size_t)(m + 1) * m + 4 * (size_t)m + 2));
+    L.partials = take(8 * kry_partials_len(m, P));
+    L.gram = take(8 * ((size_t)(m + 1) * (m + 1) + (m + 1)));
+    L.respart = take(8 * 2 * (size_t)res_blocks_of(p));
+    L.Vb = take(8 * (size_t)(m + 1) * g.ldv);
+    L.rline = take(8 * 4 * (size_t)Lmax);
+    L.rho = take(8 * (size_t)std::max(1, g.nb));
+    L.zcol = take(8 * 2 * (size_t)p->ny);
+    L.zc = take(8 * 2 * (size_t)p->ny);
+    L.ucoef = take(8 * (size_t)(1 + g.nb));
+    L.uphys = take(8 * 2 * (size_t)p->ny);
+    L.dhat = take(8 * (size_t)std::max(1, g.nb));
+    L.xpart = take(8 * 8 * (size_t)Lmax);
+    L.scal = take(8 * 8);
+    L.total = o;
+    return L;
+  }
   L.V = take(8 * (size_t)(m + 1) * Nc);
   L.u = take(8 * Nc);
   L.zbuf = flex ? 0 : take(8 * Nc);
@@ -210,6 +259,10 @@ struct Problem {
          *sn = nullptr, *g = nullptr, *y = nullptr, *partials = nullptr, *respart = nullptr,
          *G = nullptr, *hv = nullptr, *zcols = nullptr, *bc = nullptr;
   float *Z = nullptr, *tmpf = nullptr;
+  // interface Krylov iteration
+  double *V0 = nullptr, *Vb = nullptr, *rline = nullptr, *rho = nullptr, *zcol = nullptr, *zc = nullptr,
+         *ucoef = nullptr, *uphys = nullptr, *dhat = nullptr, *xpart = nullptr, *scal = nullptr;
+  double scal_init[8] = {0, 0, 0, 1.0, 0, 0, 0, 0};   // scal[3] = 1 (unit scale of a solve's input)
   ProbState* st = nullptr;
   long long Nc = 0, Nint = 0;
   int P = 0, Lmax = 0, res_blocks = 0;
@@ -248,15 +301,28 @@ struct TaskSet {
   Blob blob;
 
   bool lag = false;   // lagged Gram columns (exact preconditioner, m <= kLagMaxJ)
+  // interface Krylov iteration
+  bool ik = false;
+  TaskList<IkTask> ik_p, ik_x, ik_1;   // blocks over the centre / cross sums / one per problem
+  DstStage ik_lfwd, ik_linv;           // line transforms at the cycle start / end
+  TriStage ik_tri0;                    // T^{-1} of the interior residual's coefficients
+  TaskList<ColTask> ik_cols;           // its values on columns 0 and nx-1
+  int ik_max_coords = 1;               // longest coordinate vector (1 + nb) of the set
 
-  TaskSet(int m_, bool flex_) : m(m_), flex(flex_) {
+  TaskSet(int m_, bool flex_, bool ik_ = false) : m(m_), flex(flex_), ik(ik_) {
     it_tri.fp32 = flex;
-    lag = gram_lag_enabled(m_, flex_);
+    lag = !ik && gram_lag_enabled(m_, flex_);
   }
+  void add_problem_ik(Problem& sl);
+  void ik_cycle_start(hipStream_t s) const;
   void add_problem(Problem& sl);
   void upload(hipStream_t s) {
-    for (DstStage* d : {&cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd}) d->stage(blob);
-    for (TriStage* t : {&it_tri, &cyc_tri, &arm_tri}) t->stage(blob);
+    for (DstStage* d : {&cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd, &ik_lfwd, &ik_linv}) d->stage(blob);
+    for (TriStage* t : {&it_tri, &cyc_tri, &arm_tri, &ik_tri0}) t->stage(blob);
+    blob.add(ik_p);
+    blob.add(ik_x);
+    blob.add(ik_1);
+    blob.add(ik_cols);
     blob.add(it_lines);
     blob.add(x_lines);
     blob.add(it_lines_d);
@@ -304,7 +370,8 @@ void TaskSet::add_problem(Problem& sl) {
   bool west = false, east = false;
   for (const ArmInfo& a : p->arms) { west |= a.line == 2; east |= a.line == 3; }
   const double qscale = std::sqrt(2.0 / (nx + 1));
-  {
+  if (ik) add_problem_ik(sl);
+  if (!ik) {
     TriTask tt{};
     tt.data = flex ? (void*)sl.Z : (void*)sl.tmpd; tt.rs = nx; tt.js = flex ? Nc : 0;
     tt.rows = ny; tt.modes = nx;
@@ -329,18 +396,18 @@ void TaskSet::add_problem(Problem& sl) {
   {
     if (!flex) {
       TriTask tt{};
-      tt.data = sl.u; tt.rs = nx; tt.rows = ny; tt.modes = nx; tt.coef = p->modes_cu->c64;
+      tt.data = ik ? sl.tmpd : sl.u; tt.rs = nx; tt.rows = ny; tt.modes = nx; tt.coef = p->modes_cu->c64;
       tt.skip = skip_fin;
       cyc_tri.add(tt);
     }
     DstTask v{};
-    v.in = sl.u; v.in_rs = nx; v.in_cs = 1; v.out = sl.x_int + cd.off; v.out_rs = nx;
+    v.in = ik ? sl.tmpd : sl.u; v.in_rs = nx; v.in_cs = 1; v.out = sl.x_int + cd.off; v.out_rs = nx;
     v.out_cs = 1; v.accumulate = 1;
     v.rows = ny; v.n = nx; v.rpb = rpb_c; v.scale = qscale; v.fft = fftc; v.skip = skip_fin;
     v.tw_lds = dst_twiddles_in_lds(nx, false);
     cyc_inv.add(v);
     DstTask f{};
-    f.in = sl.u; f.in_rs = nx; f.in_cs = 1; f.out = sl.V; f.out_rs = nx; f.out_cs = 1;
+    f.in = sl.u; f.in_rs = nx; f.in_cs = 1; f.out = ik ? sl.V0 : sl.V; f.out_rs = nx; f.out_cs = 1;
     f.rows = ny; f.n = nx; f.rpb = rpb_c; f.scale = qscale; f.fft = fftc; f.skip = skip_fin;
     f.tw_lds = dst_twiddles_in_lds(nx, false);
     cyc_fwd.add(f);
@@ -368,8 +435,9 @@ void TaskSet::add_problem(Problem& sl) {
     LineTask li = lt;
     li.skip = skip_it;
     // S/N blocks are diagonal in the centre's sine basis (spec_w, and
-    // qs terms in the plain Arnoldi step): no line term per step
-    const bool it_line = a.line >= 2;
+    // qs terms in the plain Arnoldi step): no line term per step; the
+    // interface iteration forms its own
+    const bool it_line = a.line >= 2 && !ik;
     li.z = sl.zcols + (a.line == 3 ? ny : 0); li.z_js = 0; li.z_f32 = 0;
     li.start = 0; li.stride = 1;
     LineTask lx = lt;
@@ -424,7 +492,14 @@ void TaskSet::add_problem(Problem& sl) {
     r.skip = skip_fin;
     add_block_task(res_op, r, sl.P);
   }
-  {
+  if (ik) {
+    // restart decision and least squares only (no stored centre basis)
+    KryTask k{};
+    k.x = sl.x_int + cd.off; k.u = sl.u; k.H = sl.H; k.cs = sl.cs; k.sn = sl.sn; k.g = sl.g;
+    k.y = sl.y; k.partials = sl.partials; k.st = sl.st; k.Nc = Nc; k.P = sl.P; k.m = m; k.G = sl.G;
+    k.hv = sl.hv; k.nx = nx; k.ny = ny; k.flag_idx = sl.idx;
+    add_block_task(kry, k, sl.P);
+  } else {
     KryTask k{};
     k.V = sl.V; k.Z = sl.Z; k.x = sl.x_int + cd.off; k.u = sl.u; k.H = sl.H; k.cs = sl.cs;
     k.sn = sl.sn; k.g = sl.g; k.y = sl.y; k.partials = sl.partials; k.st = sl.st; k.Nc = Nc;
@@ -494,8 +569,111 @@ void TaskSet::add_problem(Problem& sl) {
   copy(fin_copy, sl.x_int + coff + sl.Nc, sl.b_int + coff + sl.Nc, sl.Nint - sl.Nc);
 }
 
+// Task records of the interface Krylov iteration for one problem.
+void TaskSet::add_problem_ik(Problem& sl) {
+  fds_plan* p = sl.plan;
+  const int nx = p->nx, ny = p->ny;
+  const IkGeom g = ik_geom(p);
+  const int* skip_fin = &sl.st->finished;
+  IkTask t{};
+  t.st = sl.st; t.H = sl.H; t.cs = sl.cs; t.sn = sl.sn; t.g = sl.g; t.y = sl.y; t.G = sl.G;
+  t.Vb = sl.Vb; t.ldv = g.ldv; t.nb = g.nb; t.m = m; t.flag_idx = sl.idx;
+  t.nx = nx; t.ny = ny; t.Nc = sl.Nc; t.P = sl.P;
+  for (int a = 0; a < 4; ++a) {
+    t.off[a] = g.off[a];
+    t.gd[a] = nullptr;
+    t.gscale[a] = 0.0;
+  }
+  for (const ArmInfo& a : p->arms) {
+    t.gd[a.line] = a.gs->gs;
+    t.gscale[a.line] = 0.5 * (a.L + 1);
+    t.present |= 1 << a.line;
+  }
+  t.nxa = g.nxa; t.nya = g.nya;
+  t.lamx = p->ik->lamx; t.lamy = p->ik->lamy; t.qx = p->ik->qx; t.qy = p->ik->qy;
+  t.t00 = p->ik->t00; t.t0n = p->ik->t0n; t.s00 = p->ik->s00; t.s0n = p->ik->s0n;
+  t.kappa = p->kappa;
+  t.u = sl.u; t.V0 = sl.V0; t.tz = sl.tmpd; t.rline = sl.rline; t.rho = sl.rho; t.zcol = sl.zcol;
+  t.zc = sl.zc; t.ucoef = sl.ucoef; t.uphys = sl.uphys; t.dhat = sl.dhat; t.xpart = sl.xpart;
+  t.scal = sl.scal; t.partials = sl.partials + (size_t)kPartNorm * sl.P; t.lmax = sl.Lmax;
+  ik_max_coords = std::max(ik_max_coords, 1 + g.nb);
+  add_block_task(ik_p, t, sl.P);
+  if (g.nxa + g.nya > 0) add_block_task(ik_x, t, g.nxa + g.nya);
+  add_block_task(ik_1, t, 1);
+  // cycle start: T^{-1} of the interior residual's coefficients (read from
+  // V0, which is written back unchanged: scale scal[3] = 1) into tz, its
+  // values on columns 0 / nx-1, and the line transforms
+  TriTask tt{};
+  tt.data = sl.tmpd; tt.rs = nx; tt.rows = ny; tt.modes = nx; tt.coef = p->modes_cu->c64;
+  tt.skip = skip_fin; tt.vin = sl.V0; tt.vjs = 0; tt.vscale = sl.scal + 3;
+  ik_tri0.add(tt);
+  if (g.off[2] >= 0 || g.off[3] >= 0) {
+    ColTask ct{};
+    ct.y = sl.tmpd; ct.zw = g.off[2] >= 0 ? sl.zcol : nullptr; ct.ze = g.off[3] >= 0 ? sl.zcol + ny : nullptr;
+    ct.fft = p->fft_c->dev; ct.nx = nx; ct.ny = ny; ct.skip = skip_fin; ct.scale = std::sqrt(2.0 / (nx + 1));
+    add_block_task(ik_cols, ct, div_up(ny, kBlock / 64));
+  }
+  auto line_dst = [&](DstStage& st, const double* in, double* out, int L) {
+    DstTask d{};
+    d.in = in; d.out = out; d.in_rs = L; d.out_rs = L; d.in_cs = 1; d.out_cs = 1;
+    d.rows = 1; d.n = L; d.scale = std::sqrt(2.0 / (L + 1)); d.skip = skip_fin;
+    d.fft = TableCache::get().fft(L)->dev;
+    d.tw_lds = dst_twiddles_in_lds(L, false);
+    st.add(d);
+  };
+  for (int a = 0; a < 4; ++a) {
+    if (g.off[a] < 0) continue;
+    const int L = a < 2 ? nx : ny;
+    line_dst(ik_lfwd, sl.rline + (size_t)a * sl.Lmax, sl.rho + g.off[a], L);
+    if (a >= 2) {
+      line_dst(ik_lfwd, sl.zcol + (size_t)(a - 2) * ny, sl.zc + (size_t)(a - 2) * ny, ny);
+      line_dst(ik_linv, sl.ucoef + 1 + g.off[a], sl.uphys + (size_t)(a - 2) * ny, ny);
+    }
+  }
+}
+
+// Cycle start of the interface iteration (after the residual r is in u and
+// the restart decision is taken): split r into its interior part and its
+// lines, transform the interior part along x, solve per mode, read the
+// solution's values on the lines, transform the lines, then v_0 and
+// S A^{-1} of the unit interior residual.
+void TaskSet::ik_cycle_start(hipStream_t s) const {
+  Timing::begin(2, s);
+  launch_ik_extract(ik_p.dev(), ik_p.n(), ik_p.nblocks, s);
+  Timing::end(2, s);
+  Timing::begin(0, s);
+  cyc_fwd.launch(0, s);
+  Timing::end(0, s);
+  Timing::begin(1, s);
+  ik_tri0.launch(s);
+  Timing::end(1, s);
+  if (ik_cols.n()) {
+    Timing::begin(7, s);
+    launch_idst_cols(ik_cols.dev(), ik_cols.n(), ik_cols.nblocks, 0, s);
+    Timing::end(7, s);
+  }
+  Timing::begin(0, s);
+  ik_lfwd.launch(0, s);
+  Timing::end(0, s);
+  Timing::begin(5, s);
+  launch_ik_start(ik_1.dev(), ik_1.n(), ik_max_coords, s);
+  Timing::end(5, s);
+}
+
 // One Arnoldi step j of every problem of the set whose cycle is running.
 void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
+  if (ik) {
+    if (ik_x.n()) {
+      Timing::begin(4, s);
+      launch_ik_cross(ik_x.dev(), ik_x.n(), ik_x.nblocks, j, s);
+      Timing::end(4, s);
+    }
+    Timing::begin(6, s);
+    launch_ik_step(ik_1.dev(), ik_1.n(), ik_max_coords, j, flags_dev, tag, s);
+    Timing::end(6, s);
+    FDS_HIP(hipGetLastError());
+    return;
+  }
   Timing::begin(1, s);
   it_tri.launch(s, j);
   Timing::end(1, s);
@@ -522,6 +700,42 @@ void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
 }
 
 void TaskSet::end_of_cycle(int max_cycles, hipStream_t s) const {
+  if (ik) {
+    // x += A^{-1} (V y): coordinates of the update, its W/E lines in physical
+    // values, its sine coefficients along x, the per-mode solve and the
+    // inverse transform; then the true residual, the restart decision and
+    // the next cycle's start
+    Timing::begin(5, s);
+    launch_ls_solve(kry.dev(), kry.n(), m, s);
+    launch_ik_combine(ik_1.dev(), ik_1.n(), s);
+    Timing::end(5, s);
+    Timing::begin(0, s);
+    ik_linv.launch(0, s);
+    Timing::end(0, s);
+    Timing::begin(2, s);
+    launch_ik_compose(ik_p.dev(), ik_p.n(), ik_p.nblocks, s);
+    Timing::end(2, s);
+    Timing::begin(1, s);
+    cyc_tri.launch(s);
+    Timing::end(1, s);
+    Timing::begin(0, s);
+    cyc_inv.launch(0, s);
+    Timing::end(0, s);
+    if (x_lines.n() || x_lines_d.n()) {
+      Timing::begin(4, s);
+      launch_x_lines(s);
+      Timing::end(4, s);
+    }
+    Timing::begin(2, s);
+    launch_operator(1, res_op.dev(), res_op.n(), res_op.nblocks, 0, s);
+    Timing::end(2, s);
+    Timing::begin(5, s);
+    launch_restart_decide(kry.dev(), kry.n(), 0, max_cycles, s);
+    Timing::end(5, s);
+    ik_cycle_start(s);
+    FDS_HIP(hipGetLastError());
+    return;
+  }
   Timing::begin(5, s);
   launch_ls_solve(kry.dev(), kry.n(), m, s);
   launch_combine(flex, kry.dev(), kry.n(), kry.nblocks, s);
@@ -563,6 +777,7 @@ double line_bytes(const ArmInfo& a) {
 struct Engine::Impl {
   int m, precision, max_cycles;
   bool flex;
+  bool ik = false;                    // interface Krylov iteration
   hipStream_t s;
   int capacity = 0;
   DevBuf states;                      // state pool (capacity entries)
@@ -616,7 +831,7 @@ void Engine::Impl::read_states() {
 
 TaskSet& Engine::Impl::current() {
   if (!cur) {
-    std::unique_ptr<TaskSet> ts(new TaskSet(m, flex));
+    std::unique_ptr<TaskSet> ts(new TaskSet(m, flex, ik));
     for (auto& p : active) ts->add_problem(*p);
     ts->upload(s);
     set_cur(std::move(ts));
@@ -657,10 +872,11 @@ void Engine::Impl::launch_graph_cycle(TaskSet& ts) {
   ++replays;
 }
 
-Engine::Engine(int m, int precision, int max_cycles, int capacity, hipStream_t stream)
+Engine::Engine(int m, int precision, int max_cycles, int capacity, hipStream_t stream, uint32_t flags)
     : impl_(new Impl()) {
   Impl& I = *impl_;
   if (capacity < 1) throw Error(FDS_E_INVALID_ARG, "engine capacity must be positive");
+  I.ik = (flags & FDS_FLAG_INTERFACE_KRYLOV) != 0;
   if (const char* g = std::getenv("FDS_GRAPH")) I.graphs = std::string(g) != "0";
   I.m = m;
   I.precision = precision;
@@ -707,6 +923,8 @@ void Engine::admit(const std::vector<SolveRequest>& reqs, const std::vector<int>
     sl.id = ids.empty() ? (int)r : ids[r];
     sl.idx = I.free_idx.back();
     fds_plan* p = sl.plan;
+    if (p->interface_krylov() != I.ik)
+      throw Error(FDS_E_INVALID_ARG, "the plans of one engine must share the Krylov iteration");
     const SlotLayout L = layout_of(p, m, I.precision);
     sl.mem.alloc(L.total);
     I.free_idx.pop_back();
@@ -736,6 +954,24 @@ void Engine::admit(const std::vector<SolveRequest>& reqs, const std::vector<int>
     sl.bc = flex ? nullptr : sl.mem.as<double>(L.bc);
     sl.Z = flex ? sl.mem.as<float>(L.Z) : nullptr;
     sl.tmpf = flex ? sl.mem.as<float>(L.tmpf) : nullptr;
+    if (I.ik) {
+      sl.zbuf = nullptr;
+      sl.bc = nullptr;
+      sl.zcols = nullptr;
+      sl.V = nullptr;
+      sl.V0 = sl.mem.as<double>(L.V0);
+      sl.Vb = sl.mem.as<double>(L.Vb);
+      sl.rline = sl.mem.as<double>(L.rline);
+      sl.rho = sl.mem.as<double>(L.rho);
+      sl.zcol = sl.mem.as<double>(L.zcol);
+      sl.zc = sl.mem.as<double>(L.zc);
+      sl.ucoef = sl.mem.as<double>(L.ucoef);
+      sl.uphys = sl.mem.as<double>(L.uphys);
+      sl.dhat = sl.mem.as<double>(L.dhat);
+      sl.xpart = sl.mem.as<double>(L.xpart);
+      sl.scal = sl.mem.as<double>(L.scal);
+      FDS_HIP(hipMemcpyAsync(sl.scal, sl.scal_init, sizeof(sl.scal_init), hipMemcpyHostToDevice, I.s));
+    }
     sl.st = I.states.as<ProbState>() + sl.idx;
     ProbState& hs = I.host_states[sl.idx];
     hs = ProbState{};
@@ -758,7 +994,7 @@ void Engine::admit(const std::vector<SolveRequest>& reqs, const std::vector<int>
                            sizeof(ProbState) * (b - a), hipMemcpyHostToDevice, I.s));
     a = b;
   }
-  std::unique_ptr<TaskSet> ts(new TaskSet(m, flex));
+  std::unique_ptr<TaskSet> ts(new TaskSet(m, flex, I.ik));
   for (Problem* p : fresh) ts->add_problem(*p);
   ts->upload(I.s);
   I.setup_phase(*ts);
@@ -786,8 +1022,13 @@ void Engine::Impl::setup_phase(TaskSet& ts) {
   launch_iface(ts.iface_fp.dev(), ts.iface_fp.n(), s);
   ts.launch_x_lines(s);
   launch_operator(1, ts.res_op.dev(), ts.res_op.n(), ts.res_op.nblocks, 0, s);
-  ts.cyc_fwd.launch(0, s);   // v_0 = Q r (sine basis of the centre)
-  launch_restart(ts.kry.dev(), ts.kry.n(), ts.kry.nblocks, 1, max_cycles, s);
+  if (ik) {
+    launch_restart_decide(ts.kry.dev(), ts.kry.n(), 1, max_cycles, s);
+    ts.ik_cycle_start(s);
+  } else {
+    ts.cyc_fwd.launch(0, s);   // v_0 = Q r (sine basis of the centre)
+    launch_restart(ts.kry.dev(), ts.kry.n(), ts.kry.nblocks, 1, max_cycles, s);
+  }
   FDS_HIP(hipGetLastError());
   read_states();
   if (Timing::on()) account_arms(ts.probs, true);
@@ -863,7 +1104,7 @@ std::vector<std::pair<int, SolveOutcome>> Engine::retire(const std::vector<int>&
   if (hit == I.active.size() && I.cur) {
     ts = I.cur.get();   // retiring everything: the cycle task lists cover it
   } else {
-    own.reset(new TaskSet(I.m, I.flex));
+    own.reset(new TaskSet(I.m, I.flex, I.ik));
     for (auto& p : I.active)
       if (std::find(ids.begin(), ids.end(), p->id) != ids.end()) own->add_problem(*p);
     own->upload(I.s);
@@ -931,6 +1172,30 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
     if (before[sl.idx].finished) continue;
     const double Nc = (double)sl.Nc;
     const int its = host_states[sl.idx].iterations - before[sl.idx].iterations;
+    if (ik) {
+      // per step: the cross sums read two source lines per axis and write
+      // their sums; the step reads v_0..v_j (the coordinates) and the line
+      // tables and writes v_{j+1}
+      const IkGeom g = ik_geom(sl.plan);
+      const double nco = 1.0 + g.nb;
+      double step = 0;
+      for (int j = 0; j < its; ++j) step += 8.0 * (j + 2) * nco;
+      Timing::add_bytes(4, its * 8.0 * (2.0 * g.nb + 4.0 * (sl.plan->nx + sl.plan->ny)));
+      Timing::add_bytes(6, step);
+      // cycle end: compose (read V0, write tz), solve (read, write), inverse
+      // transform into x (read tz, read and write x), residual (read x and
+      // f', write r); cycle start: extract (read r, write the interior
+      // part), forward transform (read, write V0), solve (read V0, write it
+      // back and tz)
+      Timing::add_bytes(2, Nc * (16.0 + 24.0 + 16.0));
+      Timing::add_bytes(1, Nc * (16.0 + 24.0));
+      Timing::add_bytes(0, Nc * (24.0 + 16.0));
+      Timing::add_bytes(7, Nc * 8.0);
+      double lines = 0;
+      for (const ArmInfo& a : sl.plan->arms) lines += line_bytes(a);
+      Timing::add_bytes(4, lines);
+      continue;
+    }
     double lines = 0;
     for (const ArmInfo& a : sl.plan->arms) lines += line_bytes(a);
     // per Arnoldi step (sine basis): the tridiagonal solve reads v_j, writes
@@ -995,9 +1260,10 @@ void Engine::Impl::account_arms(const std::vector<Problem*>& probs, bool setup_p
 }
 
 std::vector<SolveOutcome> Engine::run_batch(const std::vector<SolveRequest>& reqs, int m,
-                                            int precision, int max_cycles, hipStream_t stream) {
+                                            int precision, int max_cycles, hipStream_t stream,
+                                            uint32_t flags) {
   auto t0 = std::chrono::steady_clock::now();
-  Engine e(m, precision, max_cycles, (int)reqs.size(), stream);
+  Engine e(m, precision, max_cycles, (int)reqs.size(), stream, flags);
   std::vector<int> ids(reqs.size());
   for (size_t i = 0; i < reqs.size(); ++i) ids[i] = (int)i;
   e.admit(reqs, ids);

@@ -411,4 +411,76 @@ struct IfaceTask {
   double delta;
 };
 
+// ---------------------------------------------------------------- interface Krylov
+// Krylov iteration on the coupled rectangle's interface lines.  With the
+// exact preconditioner the operator of right-preconditioned GMRES is
+// I - S A_c^{-1}, and S (the Schur terms of the independent subdomains) only
+// reads and writes the centre's boundary lines that carry an arm.  Every
+// basis vector is therefore the interior part of the cycle's residual times a
+// scalar plus a vector supported on those lines.  A vector is stored by its
+// coordinates in an orthonormal system: [0] the coefficient of the unit
+// interior residual, then for each line that carries an arm its orthonormal
+// sine coefficients along the line (x lines S/N own the corner nodes they
+// share with W/E lines).  Inner products of coordinates equal those of the
+// centre vectors, so Gram-Schmidt and Givens run on vectors of length
+// 1 + (sum of line lengths).  The operator needs (A_c^{-1} b) on the lines for
+// a line-supported b: its blocks between lines of one axis are diagonal in
+// the sine basis (corner entries of the per-mode tridiagonal inverses), and
+// between the two axes they are sums of 1/(lambda_x + lambda_y + kappa)
+// (the eigenvalues of A_c) against the sine values at the line positions.
+constexpr int kIkThreads = 1024;  // threads of the per-problem step kernels
+constexpr int kIkEPT = 9;         // coordinates per thread: 1 + lines <= 9216
+constexpr int kIkMaxCoords = kIkThreads * kIkEPT;
+constexpr int kIkGroup = 8;       // basis vectors per block reduction of the step's dots
+constexpr int kIkXThreads = 512;  // cross-axis sums: threads per block (8 wavefronts)
+constexpr int kIkXTile = 64;      // cross-axis sums: target modes per block (one per lane)
+constexpr int kIkXStage = 1024;   // cross-axis sums: source modes staged in LDS at a time
+
+struct IkTask {
+  ProbState* st;
+  double* H;                  // Hessenberg, rotations, g, y: as in KryTask
+  double* cs;
+  double* sn;
+  double* g;
+  double* y;
+  double* G;                  // Gram columns <v_l, v_i>, column-major (m+1)^2
+  double* Vb;                 // (m+1) x ldv coordinates
+  int ldv, nb;                // row stride; sum of the present line lengths
+  int m, flag_idx;
+  int nx, ny;
+  long long Nc;
+  int P;                      // blocks of kVecPerBlock over the centre
+  int present;                // bit a: line a carries an arm (0 S, 1 N, 2 W, 3 E)
+  int off[4];                 // coordinate offset of line a (after the [0] entry), -1 if absent
+  int nxa, nya;               // cross blocks of direction x->y and y->x (0 if unused)
+  // plan tables
+  const double* lamx;         // eigenvalues 2 delta (cos(k pi/(nx+1)) - 1)
+  const double* lamy;
+  const double* qx;           // orthonormal sine vector value at the first node
+  const double* qy;
+  const double* t00;          // [T_k^{-1}]_{00} and [T_k^{-1}]_{0,ny-1} of x mode k (x lines)
+  const double* t0n;
+  const double* s00;          // the same for y mode l (y lines)
+  const double* s0n;
+  const double* gd[4];        // Schur term of the arm on line a: delta^2 (2/N) g_k (line sine basis x N/2)
+  double gscale[4];           // N/2 of line a (gd holds the S-matrix form's coefficients)
+  double kappa;
+  // per-problem work arrays
+  double* u;                  // residual, then its interior part (Nc)
+  double* V0;                 // sine coefficients along x of the interior residual (Nc)
+  double* tz;                 // T^{-1} V0 at the cycle start, the update at the cycle end (Nc)
+  double* rline;              // 4 x lmax: residual on each line's owned nodes
+  double* rho;                // nb: line sine coefficients of rline
+  double* zcol;               // 2 x ny: A^{-1} r_int on columns 0 and nx-1
+  double* zc;                 // 2 x ny: their sine coefficients
+  double* ucoef;              // 1 + nb: coordinates of the cycle's update V y
+  double* uphys;              // 2 x ny: W/E lines of the update, physical values
+  double* dhat;               // nb: S A^{-1} of the unit interior residual
+  double* xpart;              // cross sums: [dir 2][acc 4][lmax]
+  double* scal;               // [0] eta, [1] 1/eta (0 if eta = 0), [2] beta, [3] 1.0
+  double* partials;           // >= P doubles: block sums of the interior residual
+  int lmax;
+  int block_begin;
+};
+
 }  // namespace fds

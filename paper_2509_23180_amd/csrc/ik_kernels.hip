@@ -1,0 +1,605 @@
+// Kernels of the interface Krylov iteration (see IkTask in fds_internal.h).
+//
+// Right-preconditioned GMRES on L_c p_c = f'_c (paper Section 2.4) with the
+// basis kept in coordinates: the unit interior residual of the cycle plus
+// orthonormal sine coefficients on the lines that carry an arm.  One Arnoldi
+// step is two launches: the cross-axis sums of A_c^{-1} between x lines and
+// y lines (k_ik_cross, many blocks per problem for long lines), then one
+// workgroup per problem that forms w = v_j - S A_c^{-1} v_j, runs modified
+// Gram-Schmidt in its one-reduction form and the Givens update (k_ik_step).
+// The cycle start and end touch the whole centre: the interior residual is
+// split from the lines (k_ik_extract), sine-transformed and solved per mode
+// by the existing kernels, and k_ik_start turns the results into the first
+// basis vector and S A_c^{-1} of the interior residual; at the end the
+// update's coordinates (k_ik_combine) become sine coefficients along x
+// (k_ik_compose) for the per-mode solve and the inverse transform into x.
+#include "kernels.h"
+
+#include <algorithm>
+
+#include "fft_device.h"
+
+namespace fds {
+
+namespace {
+
+constexpr int kIkWaves = kIkThreads / 64;
+
+// Block sum over kIkThreads threads: wavefront sums (wave_sum, every lane
+// gets its wavefront's sum), then the wavefronts in order.  `red` holds kIkWaves doubles; every thread gets the result.
+__device__ __forceinline__ double ik_block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < kIkWaves; ++i) s += red[i];
+  return s;
+}
+
+// Line and position of coordinate e >= 1 (line -1 past the end).
+__device__ __forceinline__ int ik_line_of(const IkTask& tk, int e, int* pos) {
+  const int c = e - 1;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int o = tk.off[a];
+    const int L = a < 2 ? tk.nx : tk.ny;
+    if (o >= 0 && c >= o && c < o + L) {
+      *pos = c - o;
+      return a;
+    }
+  }
+  *pos = 0;
+  return -1;
+}
+
+__device__ __forceinline__ double sgn(int k) { return (k & 1) ? -1.0 : 1.0; }
+
+// 1/d to full double precision: the hardware reciprocal estimate refined by
+// two steps of Newton's iteration r <- r + r (1 - d r) (each step squares the
+// relative error).  d is a sum of the operator's eigenvalues: finite,
+// nonzero and far from the denormal range.
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Moves the corner values of the W/E lines' terms onto the S/N lines that own
+// those corners.  sh[q] holds the term of this thread's coordinate q (line
+// lines[q], position pos[q]); the four corner values are reduced over the
+// block first.  red: 4 x kIkWaves doubles.
+template <int EPT>
+__device__ void ik_corner_fix(const IkTask& tk, double* sh, const int* line, const int* pos,
+                              double* red) {
+  const bool hasS = tk.off[0] >= 0, hasN = tk.off[1] >= 0;
+  const bool hasW = tk.off[2] >= 0, hasE = tk.off[3] >= 0;
+  if (!(hasW || hasE) || !(hasS || hasN)) return;
+  double p[4] = {0.0, 0.0, 0.0, 0.0};   // W . qy, W . sigma qy, E . qy, E . sigma qy
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    if (line[q] >= 2) {
+      const double v = sh[q] * tk.qy[pos[q]];
+      const int b = (line[q] - 2) * 2;
+      p[b] += v;
+      p[b + 1] += sgn(pos[q]) * v;
+    }
+  }
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) p[b] = wave_sum(p[b]);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+    for (int b = 0; b < 4; ++b) red[b * kIkWaves + w] = p[b];
+  __syncthreads();
+  double c[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    double s = 0.0;
+    for (int i = 0; i < kIkWaves; ++i) s += red[b * kIkWaves + i];
+    c[b] = s;
+  }
+  const double w0 = hasS ? 1.0 : 0.0, w1 = hasN ? 1.0 : 0.0;
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int a = line[q];
+    if (a < 0) continue;
+    const int i = pos[q];
+    if (a >= 2) {
+      const int b = (a - 2) * 2;
+      sh[q] -= w0 * c[b] * tk.qy[i] + w1 * c[b + 1] * sgn(i) * tk.qy[i];
+    } else {
+      const double qx = tk.qx[i];
+      const int b = a;   // S takes the y = 0 corners (sums 0 / 2), N the y = ny-1 ones (1 / 3)
+      sh[q] += c[b] * qx + c[2 + b] * sgn(i) * qx;
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- cycle start
+
+// Residual r (in u) -> its values on the owned line nodes (rline, y-line
+// corners owned by an x line set to zero), u = r with those nodes zeroed
+// (the interior part), and block sums of the interior part's squares.
+__global__ void __launch_bounds__(kBlock) k_ik_extract(const IkTask* __restrict__ tasks, int ntasks) {
+  __shared__ int slot;
+  __shared__ double red[4];
+  const IkTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  if (tk.st->finished) return;
+  const int b = blockIdx.x - tk.block_begin;
+  const long long base = (long long)b * kVecPerBlock;
+  const int nx = tk.nx, ny = tk.ny;
+  const bool hasS = tk.off[0] >= 0, hasN = tk.off[1] >= 0;
+  const bool hasW = tk.off[2] >= 0, hasE = tk.off[3] >= 0;
+  double r2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < kVecEPT; ++e) {
+    const long long idx = base + (long long)e * kBlock + threadIdx.x;
+    if (idx >= tk.Nc) continue;
+    const int y = (int)(idx / nx);
+    const int x = (int)(idx - (long long)y * nx);
+    const double r = tk.u[idx];
+    int a = -1, p = 0;
+    if (y == 0 && hasS) { a = 0; p = x; }
+    else if (y == ny - 1 && hasN) { a = 1; p = x; }
+    else if (x == 0 && hasW) { a = 2; p = y; }
+    else if (x == nx - 1 && hasE) { a = 3; p = y; }
+    if (a < 0) {
+      r2 += r * r;
+      continue;
+    }
+    tk.rline[(long long)a * tk.lmax + p] = r;
+    tk.u[idx] = 0.0;
+    if (a < 2) {   // a corner owned by this x line: the y line's slot is empty
+      if (x == 0 && hasW) tk.rline[(long long)2 * tk.lmax + y] = 0.0;
+      if (x == nx - 1 && hasE) tk.rline[(long long)3 * tk.lmax + y] = 0.0;
+    }
+  }
+  const double s = block_sum(r2, red);
+  if (threadIdx.x == 0) tk.partials[b] = s;
+}
+
+// After the interior residual's sine transform, per-mode solve, boundary
+// columns and line transforms: eta = ||r_int||, dhat = S A^{-1} r_int / eta,
+// v_0 = (eta, line coefficients of r) / beta and g_0 = beta.
+template <int EPT>
+__global__ void __launch_bounds__(kIkThreads) k_ik_start(const IkTask* __restrict__ tasks, int ntasks) {
+  __shared__ double red[4 * kIkWaves];
+  const IkTask& tk = tasks[blockIdx.x];
+  if (tk.st->finished) return;
+  double e2 = 0.0;
+  for (int b = threadIdx.x; b < tk.P; b += kIkThreads) e2 += tk.partials[b];
+  const double eta2 = ik_block_sum(e2, red);
+  const double eta = sqrt(eta2);
+  const double inv_eta = eta > 0.0 ? 1.0 / eta : 0.0;
+  const int nco = 1 + tk.nb;
+  const int nx = tk.nx, ny = tk.ny;
+  double sh[EPT];
+  int line[EPT], pos[EPT];
+  double rr = 0.0;
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = threadIdx.x + q * kIkThreads;
+    sh[q] = 0.0;
+    line[q] = -1;
+    pos[q] = 0;
+    if (e < 1 || e >= nco) continue;
+    const int a = ik_line_of(tk, e, &pos[q]);
+    line[q] = a;
+    const int i = pos[q];
+    double ahat;
+    if (a == 0) ahat = tk.tz[i];
+    else if (a == 1) ahat = tk.tz[(long long)(ny - 1) * nx + i];
+    else ahat = tk.zc[(a - 2) * ny + i];
+    sh[q] = tk.gd[a][i] * tk.gscale[a] * ahat * inv_eta;
+    const double rv = tk.rho[e - 1];
+    rr += rv * rv;
+  }
+  ik_corner_fix<EPT>(tk, sh, line, pos, red);
+  const double rho2 = ik_block_sum(rr, red);
+  const double beta = sqrt(eta2 + rho2);
+  const double ib = beta > 0.0 ? 1.0 / beta : 0.0;
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = threadIdx.x + q * kIkThreads;
+    if (e >= nco) continue;
+    if (e == 0) {
+      tk.Vb[0] = eta * ib;
+    } else {
+      tk.dhat[e - 1] = sh[q];
+      tk.Vb[e] = tk.rho[e - 1] * ib;
+    }
+  }
+  if (threadIdx.x == 0) {
+    tk.g[0] = beta;
+    tk.G[0] = 1.0;
+    tk.scal[0] = eta;
+    tk.scal[1] = inv_eta;
+    tk.scal[2] = beta;
+  }
+}
+
+// ---------------------------------------------------------------- Arnoldi step
+
+// Cross-axis sums of step j.  Direction x->y (sources on the S/N lines, x
+// modes k; targets on the W/E lines, y modes l):
+//   acc0[l] = sum_k R_lk qx_k b^S_k,          acc1[l] = sum_k R_lk qx_k b^N_k,
+//   acc2[l] = sum_k R_lk (-1)^k qx_k b^S_k,   acc3[l] = sum_k R_lk (-1)^k qx_k b^N_k,
+// R_lk = 1/(lamx_k + lamy_l + kappa); direction y->x the same with the roles
+// of the axes (and of S/N, W/E) exchanged.  A block covers kIkXTile targets,
+// one per lane; its wavefronts take the sources in turn (source s goes to
+// wavefront s mod 8, so each wavefront's sources share one parity and the
+// alternating sums follow from the per-wavefront sums), staged in LDS
+// kIkXStage at a time.  The eight partial sums are added in wavefront order.
+__global__ void __launch_bounds__(kIkXThreads) k_ik_cross(const IkTask* __restrict__ tasks, int ntasks, int j) {
+  __shared__ int slot;
+  __shared__ double lam_s[kIkXStage], w0[kIkXStage], w1[kIkXStage];
+  __shared__ double red[2][kIkXThreads / 64][64];
+  const IkTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  if (tk.st->cycle_done) return;
+  int b = blockIdx.x - tk.block_begin;
+  const bool xy = b < tk.nxa;
+  if (!xy) b -= tk.nxa;
+  const int ns = xy ? tk.nx : tk.ny;
+  const int nt = xy ? tk.ny : tk.nx;
+  const double* lams = xy ? tk.lamx : tk.lamy;
+  const double* lamt = xy ? tk.lamy : tk.lamx;
+  const double* qs = xy ? tk.qx : tk.qy;
+  const int oa = tk.off[xy ? 0 : 2], ob = tk.off[xy ? 1 : 3];
+  const double* v = tk.Vb + (long long)j * tk.ldv + 1;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int kW = kIkXThreads / 64;
+  const int t = b * kIkXTile + lane;
+  const bool live = t < nt;
+  const double lt = live ? lamt[t] : 0.0;
+  double a0 = 0.0, a1 = 0.0;
+  for (int c0 = 0; c0 < ns; c0 += kIkXStage) {
+    const int n = min(ns - c0, kIkXStage);
+    __syncthreads();
+    for (int s = threadIdx.x; s < n; s += kIkXThreads) {
+      const int g = c0 + s;
+      lam_s[s] = lams[g] + tk.kappa;
+      w0[s] = oa >= 0 ? qs[g] * v[oa + g] : 0.0;
+      w1[s] = ob >= 0 ? qs[g] * v[ob + g] : 0.0;
+    }
+    __syncthreads();
+    if (live) {
+      // c0 is a multiple of kIkXStage (even): source c0 + s has the parity of s
+      for (int s = wv; s < n; s += kW) {
+        const double r = recip(lt + lam_s[s]);
+        a0 += r * w0[s];
+        a1 += r * w1[s];
+      }
+    }
+  }
+  red[0][wv][lane] = a0;
+  red[1][wv][lane] = a1;
+  __syncthreads();
+  if (wv != 0 || !live) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+  for (int w = 0; w < kW; ++w) {
+    const double x = red[0][w][lane], y = red[1][w][lane];
+    s0 += x;
+    s1 += y;
+    if (w & 1) {
+      s2 -= x;
+      s3 -= y;
+    } else {
+      s2 += x;
+      s3 += y;
+    }
+  }
+  double* out = tk.xpart + (xy ? 0LL : 4LL * tk.lmax);
+  out[t] = s0;
+  out[tk.lmax + t] = s1;
+  out[2LL * tk.lmax + t] = s2;
+  out[3LL * tk.lmax + t] = s3;
+}
+
+// One Arnoldi step of one problem (one workgroup): w = v_j - c0 dhat - S
+// A^{-1} b_j from the same-axis diagonal terms and the cross sums, the dots
+// <w, v_i> and the Gram column <v_j, v_i> in one pass, the MGS coefficients by
+// the recurrence h_i = <w, v_i> - sum_{l<i} h_l <v_l, v_i>, the update, the
+// norm, v_{j+1}, and the Givens update with the convergence test.
+template <int EPT, int GRP>
+__global__ void __launch_bounds__(kIkThreads) k_ik_step(const IkTask* __restrict__ tasks, int ntasks,
+                                                         int j, int* flags, int tag) {
+  __shared__ double gred[2 * GRP * kIkWaves];
+  __shared__ double cred[4 * kIkWaves];
+  __shared__ double av[122], gv[122], hv[122];
+  __shared__ double nred[kIkWaves];
+  const IkTask& tk = tasks[blockIdx.x];
+  ProbState* st = tk.st;
+  if (st->cycle_done) return;
+  const int nco = 1 + tk.nb;
+  const int nx = tk.nx, ny = tk.ny;
+  const int m1 = tk.m + 1;
+  const double* vj = tk.Vb + (long long)j * tk.ldv;
+  const double c0 = vj[0];
+  (void)ntasks;
+  const long long lm = tk.lmax;
+  const double* px = tk.xpart;            // direction x->y: sums for the W/E lines
+  const double* py = tk.xpart + 4 * lm;   // direction y->x: sums for the S/N lines
+  double vr[EPT], sh[EPT];
+  int line[EPT], pos[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = threadIdx.x + q * kIkThreads;
+    vr[q] = e < nco ? vj[e] : 0.0;
+    sh[q] = 0.0;
+    line[q] = -1;
+    pos[q] = 0;
+    if (e < 1 || e >= nco) continue;
+    const int a = ik_line_of(tk, e, &pos[q]);
+    line[q] = a;
+    const int i = pos[q];
+    double ahat;
+    if (a < 2) {   // x line: same-axis diagonal + sums from the y lines (direction y->x)
+      const double bS = tk.off[0] >= 0 ? vj[1 + tk.off[0] + i] : 0.0;
+      const double bN = tk.off[1] >= 0 ? vj[1 + tk.off[1] + i] : 0.0;
+      ahat = a == 0 ? tk.t00[i] * bS + tk.t0n[i] * bN : tk.t0n[i] * bS + tk.t00[i] * bN;
+      if (tk.nya) {
+        const int k0 = a == 0 ? 0 : 2;
+        ahat += tk.qx[i] * (py[k0 * lm + i] + sgn(i) * py[(k0 + 1) * lm + i]);
+      }
+    } else {       // y line
+      const double bW = tk.off[2] >= 0 ? vj[1 + tk.off[2] + i] : 0.0;
+      const double bE = tk.off[3] >= 0 ? vj[1 + tk.off[3] + i] : 0.0;
+      ahat = a == 2 ? tk.s00[i] * bW + tk.s0n[i] * bE : tk.s0n[i] * bW + tk.s00[i] * bE;
+      if (tk.nxa) {
+        const int k0 = a == 2 ? 0 : 2;
+        ahat += tk.qy[i] * (px[k0 * lm + i] + sgn(i) * px[(k0 + 1) * lm + i]);
+      }
+    }
+    sh[q] = tk.gd[a][i] * tk.gscale[a] * ahat;
+  }
+  ik_corner_fix<EPT>(tk, sh, line, pos, cred);
+  double w[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = threadIdx.x + q * kIkThreads;
+    w[q] = e == 0 ? c0 : (e < nco ? vr[q] - c0 * tk.dhat[e - 1] - sh[q] : 0.0);
+  }
+  // dots <w, v_i> (i <= j) and <v_j, v_i> (i < j), GRP basis vectors at
+  // a time: every thread accumulates the group's dots over its coordinates
+  // (all loads of a group independent), then one block reduction per group
+  // (wavefront sums, then the wavefronts in order)
+  const int wv = threadIdx.x >> 6;
+  for (int i0 = 0; i0 <= j; i0 += GRP) {
+    double pa[GRP], pg[GRP];
+#pragma unroll
+    for (int g = 0; g < GRP; ++g) pa[g] = pg[g] = 0.0;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = threadIdx.x + q * kIkThreads;
+#pragma unroll
+      for (int g = 0; g < GRP; ++g) {
+        const int i = i0 + g;
+        const double x = (i <= j && e < nco) ? tk.Vb[(long long)i * tk.ldv + e] : 0.0;
+        pa[g] += w[q] * x;
+        pg[g] += vr[q] * x;
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < GRP; ++g) {
+      pa[g] = wave_sum_last(pa[g]);
+      pg[g] = wave_sum_last(pg[g]);
+    }
+    if ((threadIdx.x & 63) == 63) {
+#pragma unroll
+      for (int g = 0; g < GRP; ++g) {
+        gred[g * kIkWaves + wv] = pa[g];
+        gred[(GRP + g) * kIkWaves + wv] = pg[g];
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * GRP) {
+      const int g = threadIdx.x % GRP;
+      const int i = i0 + g;
+      double sum = 0.0;
+      for (int k = 0; k < kIkWaves; ++k) sum += gred[threadIdx.x * kIkWaves + k];
+      if (i <= j) {
+        if (threadIdx.x < GRP) av[i] = sum;
+        else gv[i] = sum;
+      }
+    }
+    __syncthreads();
+  }
+  for (int l = threadIdx.x; l < j; l += kIkThreads) tk.G[l + (long long)j * m1] = gv[l];
+  // MGS recurrence: h_i = a_i - sum_{l<i} h_l G_li, G_li = <v_l, v_i>
+  if (j + 1 <= 64) {
+    if (threadIdx.x < 64) {
+      const int i = threadIdx.x;
+      double ai = i <= j ? av[i] : 0.0;
+      for (int l = 0; l < j; ++l) {
+        const double hl = __shfl(ai, l, 64);
+        if (i > l && i <= j) ai -= hl * (i < j ? tk.G[l + (long long)i * m1] : gv[l]);
+      }
+      if (i <= j) hv[i] = ai;
+    }
+  } else {
+    for (int l = 0; l <= j; ++l) {
+      __syncthreads();
+      const double hl = av[l];
+      for (int i = l + 1 + (int)threadIdx.x; i <= j; i += kIkThreads)
+        av[i] -= hl * (i < j ? tk.G[l + (long long)i * m1] : gv[l]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j; i += kIkThreads) hv[i] = av[i];
+  }
+  __syncthreads();
+  // w -= sum_i h_i v_i, ||w||
+#pragma unroll 4
+  for (int i = 0; i <= j; ++i) {
+    const double* vi = tk.Vb + (long long)i * tk.ldv;
+    const double hi = hv[i];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = threadIdx.x + q * kIkThreads;
+      if (e < nco) w[q] -= hi * vi[e];
+    }
+  }
+  double nn = 0.0;
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) nn += w[q] * w[q];
+  const double hn = sqrt(ik_block_sum(nn, nred));
+  const bool breakdown = !(hn > 1e-14 * st->beta);
+  const double inv = breakdown ? 1.0 : 1.0 / hn;
+  if (j + 1 <= tk.m) {
+    double* vn = tk.Vb + (long long)(j + 1) * tk.ldv;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = threadIdx.x + q * kIkThreads;
+      if (e < nco) vn[e] = w[q] * inv;
+    }
+  }
+  if (threadIdx.x != 0) return;
+  // Givens update of column j (rotations of the previous columns, then a new
+  // one), in place in hv
+  double* col = hv;
+  col[j + 1] = hn;
+  st->last_hn = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = col[i], c2 = col[i + 1];
+    col[i] = tk.cs[i] * a + tk.sn[i] * c2;
+    col[i + 1] = -tk.sn[i] * a + tk.cs[i] * c2;
+  }
+  const double a = col[j];
+  const double rho = hypot(a, hn);
+  double c = 1.0, s = 0.0;
+  if (rho > 0.0) {
+    c = a / rho;
+    s = hn / rho;
+  }
+  tk.cs[j] = c;
+  tk.sn[j] = s;
+  col[j] = rho;
+  col[j + 1] = 0.0;
+  for (int i = 0; i <= j + 1; ++i) tk.H[i + (long long)j * m1] = col[i];
+  const double gj = tk.g[j];
+  tk.g[j + 1] = -s * gj;
+  tk.g[j] = c * gj;
+  st->j_done = j + 1;
+  st->iterations += 1;
+  const double est = fabs(tk.g[j + 1]);
+  if (!(est > st->tol_eff * st->fnorm) || breakdown || j + 1 == tk.m) {
+    st->cycle_done = 1;
+    if (flags) {
+      flags[tk.flag_idx] = tag;
+      __threadfence_system();
+    }
+  }
+  (void)nx;
+  (void)ny;
+}
+
+// ---------------------------------------------------------------- cycle end
+
+// Coordinates of the update V y (k = steps of the cycle) and the factor of
+// the interior residual's sine coefficients in it (scal[4] = u_0 / eta).
+__global__ void __launch_bounds__(kIkThreads) k_ik_combine(const IkTask* __restrict__ tasks, int ntasks) {
+  __shared__ double ys[128];
+  const IkTask& tk = tasks[blockIdx.x];
+  if (tk.st->finished) return;
+  const int k = tk.st->j_done;
+  for (int i = threadIdx.x; i < k; i += kIkThreads) ys[i] = tk.y[i];
+  __syncthreads();
+  const int nco = 1 + tk.nb;
+  for (int e = threadIdx.x; e < nco; e += kIkThreads) {
+    double acc = 0.0;
+    for (int i = 0; i < k; ++i) acc += ys[i] * tk.Vb[(long long)i * tk.ldv + e];
+    tk.ucoef[e] = acc;
+    if (e == 0) tk.scal[4] = acc * tk.scal[1];
+  }
+}
+
+// Sine coefficients along x of the update: scal[4] V0 plus the S/N line
+// coefficients on rows 0 / ny-1 plus the W/E lines' physical values times the
+// sine vectors' first / last node values; written to tz for the per-mode
+// solve and the inverse transform.
+__global__ void __launch_bounds__(kBlock) k_ik_compose(const IkTask* __restrict__ tasks, int ntasks) {
+  __shared__ int slot;
+  const IkTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  if (tk.st->finished) return;
+  const int b = blockIdx.x - tk.block_begin;
+  const long long base = (long long)b * kVecPerBlock;
+  const int nx = tk.nx, ny = tk.ny;
+  const double s0 = tk.scal[4];
+  const double* us = tk.off[0] >= 0 ? tk.ucoef + 1 + tk.off[0] : nullptr;
+  const double* un = tk.off[1] >= 0 ? tk.ucoef + 1 + tk.off[1] : nullptr;
+  const double* pw = tk.off[2] >= 0 ? tk.uphys : nullptr;
+  const double* pe = tk.off[3] >= 0 ? tk.uphys + ny : nullptr;
+#pragma unroll
+  for (int e = 0; e < kVecEPT; ++e) {
+    const long long idx = base + (long long)e * kBlock + threadIdx.x;
+    if (idx >= tk.Nc) continue;
+    const int y = (int)(idx / nx);
+    const int k = (int)(idx - (long long)y * nx);
+    double v = s0 * tk.V0[idx];
+    if (y == 0 && us) v += us[k];
+    if (y == ny - 1 && un) v += un[k];
+    const double qk = tk.qx[k];
+    if (pw) v += qk * pw[y];
+    if (pe) v += sgn(k) * qk * pe[y];
+    tk.tz[idx] = v;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+void launch_ik_extract(const IkTask* tasks, int ntasks, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return;
+  FDS_LAUNCH(k_ik_extract, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
+}
+
+// Coordinates per thread of the per-problem kernels: the smallest
+// instantiation that holds the launch's longest coordinate vector.
+static int ik_ept(int max_coords) {
+  if (max_coords <= 2 * kIkThreads) return 2;
+  if (max_coords <= 4 * kIkThreads) return 4;
+  if (max_coords <= kIkMaxCoords) return kIkEPT;
+  throw Error(FDS_E_INVALID_ARG, "interface Krylov vector longer than the step kernel holds");
+}
+
+void launch_ik_start(const IkTask* tasks, int ntasks, int max_coords, hipStream_t s) {
+  if (ntasks <= 0) return;
+  switch (ik_ept(max_coords)) {
+    case 2: FDS_LAUNCH(k_ik_start<2>, dim3(ntasks), dim3(kIkThreads), 0, s, tasks, ntasks); break;
+    case 4: FDS_LAUNCH(k_ik_start<4>, dim3(ntasks), dim3(kIkThreads), 0, s, tasks, ntasks); break;
+    default: FDS_LAUNCH(k_ik_start<kIkEPT>, dim3(ntasks), dim3(kIkThreads), 0, s, tasks, ntasks); break;
+  }
+}
+
+void launch_ik_cross(const IkTask* tasks, int ntasks, int nblocks, int j, hipStream_t s) {
+  if (nblocks <= 0) return;
+  FDS_LAUNCH(k_ik_cross, dim3(nblocks), dim3(kIkXThreads), 0, s, tasks, ntasks, j);
+}
+
+void launch_ik_step(const IkTask* tasks, int ntasks, int max_coords, int j, int* flags, int tag,
+                    hipStream_t s) {
+  if (ntasks <= 0) return;
+  switch (ik_ept(max_coords)) {
+    case 2: FDS_LAUNCH((k_ik_step<2, 8>), dim3(ntasks), dim3(kIkThreads), 0, s, tasks, ntasks, j, flags, tag); break;
+    case 4: FDS_LAUNCH((k_ik_step<4, 8>), dim3(ntasks), dim3(kIkThreads), 0, s, tasks, ntasks, j, flags, tag); break;
+    default: FDS_LAUNCH((k_ik_step<kIkEPT, 4>), dim3(ntasks), dim3(kIkThreads), 0, s, tasks, ntasks, j, flags, tag); break;
+  }
+}
+
+void launch_ik_combine(const IkTask* tasks, int ntasks, hipStream_t s) {
+  if (ntasks <= 0) return;
+  FDS_LAUNCH(k_ik_combine, dim3(ntasks), dim3(kIkThreads), 0, s, tasks, ntasks);
+}
+
+void launch_ik_compose(const IkTask* tasks, int ntasks, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return;
+  FDS_LAUNCH(k_ik_compose, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
+}
+
+}  // namespace fds

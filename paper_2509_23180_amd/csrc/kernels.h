@@ -98,6 +98,18 @@ void launch_res_sum(const ResSumTask* tasks, int ntasks, hipStream_t s);
 void launch_copy(const CopyTask* tasks, int ntasks, int nblocks, hipStream_t s);
 void launch_count_active(const ProbState* st, int n, int* out, hipStream_t s);
 
+// Interface Krylov iteration (ik_kernels.hip).
+void launch_ik_extract(const IkTask* tasks, int ntasks, int nblocks, hipStream_t s);
+// max_coords: the largest 1 + nb of the launch's problems
+void launch_ik_start(const IkTask* tasks, int ntasks, int max_coords, hipStream_t s);
+void launch_ik_cross(const IkTask* tasks, int ntasks, int nblocks, int j, hipStream_t s);
+void launch_ik_step(const IkTask* tasks, int ntasks, int max_coords, int j, int* flags, int tag,
+                    hipStream_t s);
+void launch_ik_combine(const IkTask* tasks, int ntasks, hipStream_t s);
+void launch_ik_compose(const IkTask* tasks, int ntasks, int nblocks, hipStream_t s);
+// k_restart alone: the restart decision without scaling a stored V[0].
+void launch_restart_decide(const KryTask* tasks, int ntasks, int initial, int max_cycles, hipStream_t s);
+
 // Allocation-free Arnoldi step: size of the per-device scratch array, its
 // device address on the current device (looked up once per device), and the
 // kernel that clears its partials and writes the state and task records.

@@ -1746,6 +1746,11 @@ void launch_restart(const KryTask* tasks, int ntasks, int nblocks, int initial, 
   FDS_LAUNCH(k_restart_scale, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
 }
 
+void launch_restart_decide(const KryTask* tasks, int ntasks, int initial, int max_cycles, hipStream_t s) {
+  if (ntasks <= 0) return;
+  FDS_LAUNCH(k_restart, dim3(ntasks), dim3(kBlock), 0, s, tasks, ntasks, initial, max_cycles);
+}
+
 void launch_lift(int mode, const LiftTask* tasks, int ntasks, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return;
   if (mode == 0) FDS_LAUNCH(k_lift<0>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);

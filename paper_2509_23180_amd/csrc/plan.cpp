@@ -40,6 +40,9 @@ fds_plan* create_plan(const fds_rect* rects, int nrect, double h, double kappa,
   if (o.max_cycles < 1) throw Error(FDS_E_INVALID_ARG, "max_cycles must be >= 1");
   if (o.precision != FDS_FP64 && o.precision != FDS_FP32_PRECOND && o.precision != FDS_NO_PRECOND)
     throw Error(FDS_E_INVALID_ARG, "unknown precision");
+  if (o.flags & ~(uint32_t)FDS_FLAG_INTERFACE_KRYLOV) throw Error(FDS_E_INVALID_ARG, "unknown option flags");
+  if ((o.flags & FDS_FLAG_INTERFACE_KRYLOV) && o.precision != FDS_FP64)
+    throw Error(FDS_E_INVALID_ARG, "the interface Krylov iteration is an FP64 method");
   for (int r = 0; r < nrect; ++r) {
     const fds_rect& a = rects[r];
     if (a.i0 < 0 || a.j0 < 0 || a.i1 - a.i0 < 2 || a.j1 - a.j0 < 2)
@@ -202,6 +205,15 @@ fds_plan* create_plan(const fds_rect* rects, int nrect, double h, double kappa,
     }
     p->modes_c = tc.modes(p->nx, p->ny, h, kappa);
     p->modes_cu = tc.modes(p->nx, p->ny, h, kappa, true);
+    if (p->opt.flags & FDS_FLAG_INTERFACE_KRYLOV) {
+      // lines of the arms present (x lines S/N have nx nodes, y lines ny)
+      long long lines = 0;
+      for (int r = 0; r < nrect; ++r)
+        if (r != c) lines += line_of_kind(p->kind[r]) < 2 ? p->nx : p->ny;
+      if (p->nx < 2 || p->ny < 2 || 1 + lines > kIkMaxCoords) p->opt.flags &= ~(uint32_t)FDS_FLAG_INTERFACE_KRYLOV;
+      else p->ik = build_ik_table(p->nx, p->ny, h, kappa);
+    }
+    const bool dense_ops = !p->interface_krylov();   // the line operators of the other paths
     for (int r = 0; r < nrect; ++r) {
       if (r == c) continue;
       ArmInfo ai{};
@@ -212,7 +224,7 @@ fds_plan* create_plan(const fds_rect* rects, int nrect, double h, double kappa,
       ai.rows = p->rd[r].rows;
       ai.fft = tc.fft(ai.L);
       ai.modes = tc.modes(ai.L, ai.rows, h, kappa);
-      ai.gs = tc.gs(ai.L, ai.rows, h, kappa);
+      ai.gs = tc.gs(ai.L, ai.rows, h, kappa, dense_ops);
       p->arms.push_back(ai);
     }
     p->floor_coef = 1.1102230246251565e-16 * (9.0 * p->delta + std::fabs(kappa));

@@ -100,7 +100,8 @@ class TableCache {
   // unit: solve T_k y = r exactly (coefficients in the orthonormal sine
   // basis); otherwise the DST normalisation 2/(n+1) is folded in.
   std::shared_ptr<ModeTable> modes(int n, int m, double h, double kappa, bool unit = false);
-  std::shared_ptr<GsTable> gs(int n, int m, double h, double kappa);
+  // dense: also form the n x n line operator (n <= kDenseLineMax)
+  std::shared_ptr<GsTable> gs(int n, int m, double h, double kappa, bool dense = true);
   // wave-transform descriptor of the table whose device FftDesc is `dev`
   WaveDesc wave_desc(const FftDesc* dev, bool fp32);
 
@@ -109,8 +110,17 @@ class TableCache {
   std::map<std::pair<int, int>, std::shared_ptr<FftTable>> fft_;
   std::map<const FftDesc*, std::shared_ptr<FftTable>> by_dev_;
   std::map<std::tuple<int, int, int, double, double, bool>, std::shared_ptr<ModeTable>> modes_;
-  std::map<std::tuple<int, int, int, double, double>, std::shared_ptr<GsTable>> gs_;
+  std::map<std::tuple<int, int, int, double, double, bool>, std::shared_ptr<GsTable>> gs_;
 };
+
+// Tables of the interface Krylov iteration for an nx x ny centre (IkTask):
+// eigenvalues along each axis, the orthonormal sine vectors' first-node
+// values, and the corner entries of the per-mode tridiagonal inverses.
+struct IkPlanTable {
+  DevBuf mem;
+  const double *lamx, *lamy, *qx, *qy, *t00, *t0n, *s00, *s0n;
+};
+std::shared_ptr<IkPlanTable> build_ik_table(int nx, int ny, double h, double kappa);
 
 // Per-mode coefficients for `n` modes of an m-row tridiagonal system whose
 // right-hand side is multiplied by `scale`.
@@ -208,7 +218,9 @@ struct fds_plan {
   std::shared_ptr<fds::FftTable> fft_c;
   std::shared_ptr<fds::ModeTable> modes_c;
   std::shared_ptr<fds::ModeTable> modes_cu;   // centre, unit scale (flexible variant)
+  std::shared_ptr<fds::IkPlanTable> ik;       // interface Krylov iteration (or null)
   double floor_coef = 0;
+  bool interface_krylov() const { return (opt.flags & FDS_FLAG_INTERFACE_KRYLOV) != 0; }
   size_t footprint(int m, int precision) const;
 };
 
@@ -239,7 +251,7 @@ struct SolveOutcome {
 class Engine {
  public:
   // capacity: most problems held at once (state pool and flag array size).
-  Engine(int m, int precision, int max_cycles, int capacity, hipStream_t stream);
+  Engine(int m, int precision, int max_cycles, int capacity, hipStream_t stream, uint32_t flags = 0);
   ~Engine();
   // Allocates the problems and runs their set-up phase (blocks until done).
   // wait_events (may be empty, else one per request, entries may be null):
@@ -268,7 +280,8 @@ class Engine {
   static size_t bytes_per_problem(const fds_plan* p, int m, int precision);
   // Whole batch: admit all, cycle until done, retire all (request order).
   static std::vector<SolveOutcome> run_batch(const std::vector<SolveRequest>& reqs, int m,
-                                             int precision, int max_cycles, hipStream_t stream);
+                                             int precision, int max_cycles, hipStream_t stream,
+                                             uint32_t flags = 0);
 
  private:
   struct Impl;

@@ -1,7 +1,7 @@
 // Request server with continuous batching at GMRES-cycle granularity.
 //
 // A host thread owns one batch engine, on a HIP stream of its own, per
-// (restart length, precision, cycle cap).  Between cycles it retires every
+// (restart length, precision, cycle cap, Krylov iteration).  Between cycles it retires every
 // finished problem (back substitution and output, result published to the
 // ticket) and admits queued requests in arrival order while their device
 // footprint fits the budget and a slot is free; admitted requests run their
@@ -35,9 +35,11 @@ struct Pending {
   hipEvent_t ready;   // recorded on the submitter's stream (inputs written)
 };
 
-using Key = std::tuple<int, int, int>;   // restart_m, precision, max_cycles
+using Key = std::tuple<int, int, int, unsigned>;   // restart_m, precision, max_cycles, flags
 
-Key key_of(const fds_plan* p) { return Key{p->opt.restart_m, p->opt.precision, p->opt.max_cycles}; }
+Key key_of(const fds_plan* p) {
+  return Key{p->opt.restart_m, p->opt.precision, p->opt.max_cycles, p->opt.flags};
+}
 
 struct Group {
   hipStream_t stream = nullptr;
@@ -149,7 +151,7 @@ void fds_server::admit_from_queue() {
       if (!g.stream) FDS_HIP(hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking));
       if (!g.eng)
         g.eng.reset(new fds::Engine(std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                                    max_slots, g.stream));
+                                    max_slots, g.stream, std::get<3>(kv.first)));
       g.eng->admit(reqs, ids, evs);
       for (size_t i = 0; i < ids.size(); ++i) {
         g.running[ids[i]] = kv.second[i];

@@ -718,10 +718,10 @@ std::shared_ptr<ModeTable> TableCache::modes(int n, int m, double h, double kapp
 // interface row first):  g_k = [T_k^{-1}]_{11} = -sinh(m theta)/(delta sinh((m+1) theta))
 //                           = -(q/delta) (1 - q^{2m})/(1 - q^{2m+2}),
 // stored as delta^2 (2/N) g_k.
-std::shared_ptr<GsTable> TableCache::gs(int n, int m, double h, double kappa) {
+std::shared_ptr<GsTable> TableCache::gs(int n, int m, double h, double kappa, bool want_dense) {
   const int dev = current_device();
   std::lock_guard<std::mutex> lk(mu_);
-  auto key = std::make_tuple(dev, n, m, h, kappa);
+  auto key = std::make_tuple(dev, n, m, h, kappa, want_dense);
   auto it = gs_.find(key);
   if (it != gs_.end()) return it->second;
   const int N = n + 1;
@@ -736,7 +736,7 @@ std::shared_ptr<GsTable> TableCache::gs(int n, int m, double h, double kappa) {
     v[k - 1] = delta * delta * (2.0 / N) * g;
   }
   auto t = std::make_shared<GsTable>();
-  const bool dense = n <= kDenseLineMax;
+  const bool dense = want_dense && n <= kDenseLineMax;
   const size_t nn = (size_t)n * n;
   std::vector<double> host(n + (dense ? nn : 0));
   std::copy(v.begin(), v.end(), host.begin());
@@ -764,6 +764,58 @@ std::shared_ptr<GsTable> TableCache::gs(int n, int m, double h, double kappa) {
     t->mfull = t->gs + n;
   }
   gs_[key] = t;
+  return t;
+}
+
+// Corner entries of T^{-1} for T = tridiag(delta, a, delta) of order m with
+// a = -2 delta cosh(theta) (theta from mode_theta):
+//   [T^{-1}]_{11} = -sinh(m theta) / (delta sinh((m+1) theta)),
+//   [T^{-1}]_{1m} = -sinh(theta)   / (delta sinh((m+1) theta)),
+// in the decaying form q = e^{-theta} (no overflow for long systems).
+static void corner_inverse(double theta, int m, double delta, double* t11, double* t1m) {
+  const double den = -std::expm1(-2.0 * (m + 1) * theta);
+  *t11 = -(std::exp(-theta) * -std::expm1(-2.0 * m * theta) / den) / delta;
+  *t1m = -(std::exp(-(double)m * theta) * -std::expm1(-2.0 * theta) / den) / delta;
+}
+
+std::shared_ptr<IkPlanTable> build_ik_table(int nx, int ny, double h, double kappa) {
+  const double delta = 1.0 / (h * h);
+  const long double pi = kPi;
+  std::vector<double> host(4 * (size_t)nx + 4 * (size_t)ny);
+  double* lamx = host.data();
+  double* qx = lamx + nx;
+  double* t00 = qx + nx;
+  double* t0n = t00 + nx;
+  double* lamy = t0n + nx;
+  double* qy = lamy + ny;
+  double* s00 = qy + ny;
+  double* s0n = s00 + ny;
+  auto axis = [&](int n, int m, double* lam, double* q, double* c11, double* c1m) {
+    const int N = n + 1;
+    for (int k = 1; k <= n; ++k) {
+      const long double sh = sinl(pi * (long double)k / (2.0L * N));
+      lam[k - 1] = (double)(-4.0L * (long double)delta * sh * sh);   // 2 delta (cos(k pi/N) - 1)
+      q[k - 1] = (double)(sqrtl(2.0L / N) * sinl(pi * (long double)k / N));
+      double th;
+      if (!mode_theta(k, N, delta, kappa, &th))
+        throw Error(FDS_E_UNSUPPORTED, "kappa makes a sine mode oscillatory (not diagonally dominant)");
+      corner_inverse(th, m, delta, &c11[k - 1], &c1m[k - 1]);
+    }
+  };
+  axis(nx, ny, lamx, qx, t00, t0n);   // x modes: systems of ny rows
+  axis(ny, nx, lamy, qy, s00, s0n);   // y modes: systems of nx columns
+  auto t = std::make_shared<IkPlanTable>();
+  t->mem.alloc(sizeof(double) * host.size());
+  FDS_HIP(hipMemcpy(t->mem.get(), host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice));
+  const double* b = t->mem.as<double>(0);
+  t->lamx = b;
+  t->qx = b + nx;
+  t->t00 = b + 2 * (size_t)nx;
+  t->t0n = b + 3 * (size_t)nx;
+  t->lamy = b + 4 * (size_t)nx;
+  t->qy = t->lamy + ny;
+  t->s00 = t->lamy + 2 * (size_t)ny;
+  t->s0n = t->lamy + 3 * (size_t)ny;
   return t;
 }
 
