@@ -43,10 +43,18 @@ CLASS_KERNEL = {"dst": "k_dst_wave", "tridiag": "k_tridiag_seg", "operator": "k_
                 "cols": "k_idst_cols"}
 
 
+IK_CLASS_KERNEL = {"gram_update": "k_ik_step", "lines": "k_ik_cross", "operator": "k_ik_compose",
+                   "other": "k_ik_start", "cols": "k_idst_cols", "tridiag": "k_tridiag_seg",
+                   "dst": "k_dst_wave"}
+
+
 def class_kernel(cls: str, opts: dict) -> str:
     """Kernel of a timing class for a solver configuration: the plain method
     with restart length <= 32 takes its Gram columns from the update pass
-    (boundary dots + k_gram_update_lag) unless FDS_GRAM_LAG=0."""
+    (boundary dots + k_gram_update_lag) unless FDS_GRAM_LAG=0; the interface
+    Krylov iteration has kernels of its own."""
+    if opts.get("flags", 0) & 1:
+        return IK_CLASS_KERNEL.get(cls, cls)
     lag = (opts.get("precision", 0) == 0 and opts.get("restart_m", 30) <= 32
            and os.environ.get("FDS_GRAM_LAG", "1") != "0")
     if lag and cls == "gram_dots":
@@ -271,122 +279,266 @@ def run_convergence(args, device):
 
 # --------------------------------------------------------------------------- serving
 
-def serving_inputs(reqs, device):
-    """Device right-hand sides of the requested solves: the seeded Gaussian
-    source evaluated on the device grid, packed into the ABI layout through
-    index arrays (Dirichlet data zero)."""
-    import numpy as np
+def request_rhs(spec, device):
+    """Right-hand side of one request on the device: the seeded Gaussian
+    source evaluated at the owned unknown nodes, rectangle by rectangle in
+    the ABI layout (Dirichlet data zero, passed as NULL)."""
     import torch
     import workloads
     from paper_2509_23180_amd import layout as playout
-    out = []
-    for rq in reqs:
-        sp = rq.spec
-        n = sp.n
-        N = n + 1
-        h = 1.0 / N
-        rects = workloads.shape_rects(sp.shape, n)
-        side = 3 * N + 1
-        c = torch.arange(side, dtype=torch.float64, device=device) * h
-        Y, X = torch.meshgrid(c, c, indexing="ij")
-        src = workloads.gaussian_source(sp.shape, sp.config_id, sp.problem_id, sp.rhs_id)
-        f = src(X, Y, xp=torch).reshape(-1)
-        idx = playout.pack_unknowns(rects, np.arange(side * side, dtype=np.float64).reshape(side, side))
-        rhs = f[torch.tensor(idx.astype(np.int64), device=device)].contiguous()
-        nbc = int(playout.pack_boxes(rects, np.zeros((side, side))).size)
-        bc = torch.zeros(nbc, dtype=torch.float64, device=device)
-        out.append((rects, h, sp.kappa, rhs, bc))
-    return out
+    n = spec.n
+    h = 1.0 / (n + 1)
+    rects = workloads.shape_rects(spec.shape, n)
+    src = workloads.gaussian_source(spec.shape, spec.config_id, spec.problem_id, spec.rhs_id)
+    parts = []
+    for r in range(len(rects)):
+        ilo, ihi, jlo, jhi = playout.owned_box(rects, r)
+        xs = torch.arange(ilo, ihi + 1, dtype=torch.float64, device=device) * h
+        ys = torch.arange(jlo, jhi + 1, dtype=torch.float64, device=device) * h
+        Y, X = torch.meshgrid(ys, xs, indexing="ij")
+        parts.append(src(X, Y, xp=torch).reshape(-1))
+    return rects, h, torch.cat(parts).contiguous()
 
 
-def replay(fds, torch, srv, reqs, inputs, plans, tol):
-    """Open-loop replay: a submitter thread submits each request at its
-    arrival time; the caller polls.  Returns per-request (latency s, status,
-    iterations) and the makespan (first arrival to last completion)."""
+class TimedSlice:
+    """Turns per-kernel timing of one class on for a slice of the measured
+    window (events on every launch of the class cost a few microseconds of
+    dispatch gap, so only a fifth of the window carries them)."""
+
+    def __init__(self, fds, cls, t_on, t_off):
+        import threading
+        self.fds, self.cls = fds, cls
+        self.th = threading.Thread(target=self._run, args=(t_on, t_off), daemon=True)
+
+    def _run(self, t_on, t_off):
+        time.sleep(max(0.0, t_on - time.perf_counter()))
+        self.fds.timing_enable([self.cls])
+        time.sleep(max(0.0, t_off - time.perf_counter()))
+        self.fds.timing_enable([])
+
+    def start(self):
+        self.th.start()
+
+    def join(self):
+        self.th.join()
+
+
+def replay(fds, torch, srv, reqs, opts, device, t_measure, plan_cache, timed=None):
+    """Open-loop replay of a request trace against a server.  A submitter
+    thread takes each request at its arrival time, builds its plan (or takes
+    it from the plan cache, keyed by shape, n and kappa) and its right-hand
+    side on the device, and submits it; the latency clock starts at the
+    scheduled arrival.  The main thread polls.  Returns per-request records."""
     import threading
-    xs = [torch.zeros(p.n_unknowns, dtype=torch.float64, device=rhs.device)
-          for p, (_, _, _, rhs, _) in zip(plans, inputs)]
-    torch.cuda.synchronize()
+    recs = [None] * len(reqs)
     tickets = [None] * len(reqs)
-    t0 = time.perf_counter()
+    xs = [None] * len(reqs)
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter() + 0.2
+    lock = threading.Lock()
 
     def submitter():
-        for k, rq in enumerate(reqs):
-            delay = t0 + rq.arrival_s - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            _, _, _, rhs, bc = inputs[k]
-            tickets[k] = srv.submit(plans[k], rhs, xs[k], tol, bc=bc)
+        torch.cuda.set_device(device)
+        with torch.cuda.stream(stream):
+            for k, rq in enumerate(reqs):
+                delay = t0 + rq.arrival_s - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                sp = rq.spec
+                key = (sp.shape, sp.n, sp.kappa)
+                tp = time.perf_counter()
+                plan = plan_cache.get(key)
+                hit = plan is not None
+                rects, h, rhs = request_rhs(sp, device)
+                if plan is None:
+                    plan = fds.Plan(rects, h, sp.kappa, **opts)
+                    plan_cache[key] = plan
+                x = torch.empty(plan.n_unknowns, dtype=torch.float64, device=device)
+                t = srv.submit(plan, rhs, x, 1e-10, stream=stream)
+                with lock:
+                    tickets[k] = t
+                    xs[k] = x
+                    recs[k] = {"arrival": t0 + rq.arrival_s, "prep_ms": (time.perf_counter() - tp) * 1e3,
+                               "plan_hit": hit}
 
     th = threading.Thread(target=submitter)
     th.start()
-    done = {}
-    last = t0
-    while len(done) < len(reqs):
-        for k in range(len(reqs)):
-            if k in done or tickets[k] is None:
-                continue
+    if timed is not None:
+        timed.start()
+    done = 0
+    pending = set()
+    nxt = 0
+    while done < len(reqs):
+        with lock:
+            while nxt < len(reqs) and tickets[nxt] is not None:
+                pending.add(nxt)
+                nxt += 1
+        for k in list(pending):
             r = srv.poll(tickets[k])
             if r is not None:
-                done[k] = r
-                last = time.perf_counter()
-        time.sleep(0.0005)
+                recs[k].update(done=time.perf_counter(), status=r.status, iterations=r.iterations,
+                               cycles=r.cycles, relres=r.relres_schur, stop=r.stop_reason)
+                xs[k] = None
+                pending.discard(k)
+                done += 1
+        time.sleep(0.0002)
     th.join()
-    res = [(done[k].seconds, done[k].status, done[k].iterations, done[k].relres_schur,
-            done[k].stop_reason, done[k].cycles) for k in range(len(reqs))]
-    return res, last - t0
+    if timed is not None:
+        timed.join()
+    for rq, rec in zip(reqs, recs):
+        rec["latency_ms"] = (rec["done"] - rec["arrival"]) * 1e3
+        rec["measured"] = rq.arrival_s >= t_measure
+    return recs
+
+
+def summarise(recs, reqs, srv_stats):
+    meas = [r for r in recs if r["measured"]]
+    lat = [r["latency_ms"] for r in meas]
+    first = min(r["arrival"] for r in meas)
+    last = max(r["done"] for r in meas)
+    prep = [r["prep_ms"] for r in meas]
+    return {"requests": len(meas), "converged": sum(1 for r in meas if r["status"] == 0),
+            "throughput_solves_per_s": round(len(meas) / (last - first), 3),
+            "makespan_s": round(last - first, 3),
+            "latency_ms_p50": _r(pct(lat, 50)), "latency_ms_p99": _r(pct(lat, 99)),
+            "latency_ms_max": _r(max(lat)), "latency_ms_mean": _r(sum(lat) / len(lat)),
+            "plan_cache_hit_rate": round(sum(1 for r in meas if r["plan_hit"]) / len(meas), 3),
+            "request_prep_ms_p50": _r(pct(prep, 50)), "request_prep_ms_p99": _r(pct(prep, 99)),
+            "iterations_mean": round(sum(r["iterations"] for r in meas) / len(meas), 1),
+            "max_relres_schur": max(r["relres"] for r in meas),
+            "admitted_mid_flight": srv_stats["admitted_mid_flight"],
+            "peak_hbm_gb": round(srv_stats["peak_bytes_in_use"] / 1e9, 2),
+            "not_converged": [{"shape": reqs[k].spec.shape, "n": reqs[k].spec.n,
+                               "kappa": round(reqs[k].spec.kappa, 3), "problem": reqs[k].spec.problem_id,
+                               "status": r["status"], "stop": r["stop"], "cycles": r["cycles"],
+                               "iterations": r["iterations"], "relres": r["relres"]}
+                              for k, r in enumerate(recs) if r["measured"] and r["status"] != 0][:10]}
+
+
+SERVING_PATHS = {
+    # the interface Krylov iteration (FP64, basis on the centre's interface lines)
+    "interface_gmres40_fp64": dict(restart_m=40, precision=0, flags=1),
+    # FP32 sine transforms and tridiagonal solves inside flexible GMRES(40)
+    "mixed_fgmres40_fp32_precond": dict(restart_m=40, precision=1),
+    # the plain method, full centre vectors in FP64
+    "plain_gmres30_fp64": dict(restart_m=30, precision=0),
+}
 
 
 def run_serving(args, device):
     import torch
     import paper_2509_23180_amd as fds
     import workloads
-    tol = 1e-10
-    reqs = workloads.request_stream(args.serving_rate, args.serving_seconds, n_min=64,
-                                    n_max=args.serving_nmax)
-    log(f"serving: {len(reqs)} requests over {args.serving_seconds} s, n in [64, {args.serving_nmax}]")
-    inputs = serving_inputs(reqs, device)
-    paths = {"mixed_fgmres40_fp32_precond": dict(restart_m=40, precision=1),
-             "plain_gmres30_fp64": dict(restart_m=30, precision=0)}
+    warm, meas = float(args.warmup), float(args.steps)
+    reqs = workloads.request_stream(args.serving_rate, warm + meas, n_min=64, n_max=args.serving_nmax)
+    log(f"serving: {len(reqs)} requests at {args.serving_rate:g}/s over {warm:g} s warm-up + {meas:g} s "
+        f"measured, n in [64, {args.serving_nmax}]")
     out = {}
-    for name, opt in paths.items():
-        t_plan = time.perf_counter()
-        plans = [fds.Plan(rects, h, kappa, max_cycles=400, **opt) for (rects, h, kappa, _, _) in inputs]
-        log(f"{name}: {len(plans)} plans in {time.perf_counter() - t_plan:.1f} s")
+    headline = "interface_gmres40_fp64"
+    roofline = None
+    cls_times = None
+    paths = SERVING_PATHS if not args.serving_paths else {
+        k: SERVING_PATHS[k] for k in args.serving_paths.split(",")}
+    if headline not in paths:
+        headline = next(iter(paths))
+    for name, opts in paths.items():
+        # the comparison paths replay the same trace up to the end of its
+        # first `--serving-compare-seconds` measured seconds
+        span = warm + meas if name == headline else warm + min(meas, args.serving_compare_seconds)
+        sub = [r for r in reqs if r.arrival_s <= span]
         srv = fds.Server(hbm_budget_bytes=int(args.serving_budget_gb * (1 << 30)),
                          max_slots=args.serving_slots)
-        # warm-up: the first few requests alone (kernel code, table caches)
-        warm = min(4, len(reqs))
-        replay(fds, torch, srv, reqs[:warm], inputs[:warm], plans[:warm], tol)
-        res, makespan = replay(fds, torch, srv, reqs, inputs, plans, tol)
+        plan_cache = {}
+        timed = None
+        if name == headline:
+            # warm-up pass with every class timed: which kernel dominates
+            fds.timing_reset()
+            fds.timing_enable(None)
+            replay(fds, torch, srv, [r for r in reqs if r.arrival_s < warm], opts, device, warm, {})
+            fds.timing_enable([])
+            cls_times = {}
+            for c in ("dst", "tridiag", "operator", "gram_dots", "gram_update", "lines", "cols", "other"):
+                calls, ms, by = fds.timing_read(c)
+                cls_times[c] = {"calls": calls, "ms": round(ms, 3),
+                                "GB/s": round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 and by > 0 else None}
+            dominant = max((c for c in cls_times if c != "other"), key=lambda c: cls_times[c]["ms"])
+            log(f"{name}: per-class times over the warm-up: {cls_times}; dominant {dominant}")
+            fds.timing_reset()
+            t_base = time.perf_counter() + 0.2
+            timed = TimedSlice(fds, dominant, t_base + warm + 0.4 * meas, t_base + warm + 0.6 * meas)
+        t_wall = time.perf_counter()
+        recs = replay(fds, torch, srv, sub, opts, device, warm, plan_cache, timed)
+        st = srv.stats()
         srv.close()
-        lat = [r[0] * 1e3 for r in res]
-        ok = sum(1 for r in res if r[1] == 0)
-        out[name] = {"requests": len(res), "converged": ok, "throughput_solves_per_s": round(len(res) / makespan, 3),
-                     "makespan_s": round(makespan, 3), "latency_ms_p50": _r(pct(lat, 50)),
-                     "latency_ms_p99": _r(pct(lat, 99)), "latency_ms_max": _r(max(lat)),
-                     "max_relres_schur": max(r[3] for r in res),
-                     "not_converged": [{"k": k, "shape": reqs[k].spec.shape, "n": reqs[k].spec.n,
-                                        "kappa": round(reqs[k].spec.kappa, 3), "status": r[1],
-                                        "stop": r[4], "iterations": r[2], "cycles": r[5],
-                                        "relres": r[3]} for k, r in enumerate(res) if r[1] != 0]}
+        out[name] = summarise(recs, sub, st)
+        out[name]["trace_s"] = span
+        out[name]["wall_s"] = round(time.perf_counter() - t_wall, 2)
         log(f"{name}: {out[name]}")
-        del plans
+        if name == headline:
+            calls, ms, by = fds.timing_read(dominant)
+            kname = class_kernel(dominant, opts)
+            achieved = (by / calls) / ((ms / calls) * 1e-3) / 1e9 if calls and ms > 0 else None
+            roofline = {"bound": "hbm", "achieved": _r(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                        "traffic": None, "kernel": kname, "class": dominant, "launches": calls,
+                        "avg_launch_us": round(ms / calls * 1e3, 3) if calls else None,
+                        "algorithmic_bytes_per_launch": round(by / calls, 1) if calls else None,
+                        "timed_window": "middle fifth of the measured window"}
+            tfile = os.path.join(ROOT, "profiles", f"traffic_{kname}_serving.json")
+            if os.path.exists(tfile):
+                with open(tfile) as fh:
+                    tr = json.load(fh)
+                if tr.get("kernel_source_hash") == kernel_source_hash():
+                    roofline["traffic"] = tr.get("hbm_bytes_per_launch")
+        del plan_cache
         torch.cuda.empty_cache()
-    mixed = out["mixed_fgmres40_fp32_precond"]
+    head = out[headline]
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = serving_cpu_baseline(reqs, args.cpu_seconds)
     return {
         "metric": "solves/s & p50/p99 latency at rel-res 1e-10; DST/Thomas GB/s vs HBM peak",
-        "value": mixed["throughput_solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 1,
-        "warmup": 1, "ms_per_step": round(mixed["makespan_s"] * 1e3, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
-        "config": {"workload": f"Poisson request stream {args.serving_rate:g}/s for "
-                               f"{args.serving_seconds:g} s, shape U{{cross,L,T}}, n log-uniform "
-                               f"[64,{args.serving_nmax}], kappa 0 w.p. 1/2 else U[-100,0], seeded "
-                               f"Gaussian RHS, rel-res 1e-10, continuous-batching server "
-                               f"({args.serving_slots} slots, {args.serving_budget_gb:g} GB)",
-                   "paths": out},
-        "roofline": None, "cpu_baseline": None,
+        "value": head["throughput_solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": int(meas), "warmup": int(warm),
+        "ms_per_step": round(head["makespan_s"] * 1e3 / meas, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"serving: Poisson request stream {args.serving_rate:g}/s, shape U{{cross,L,T}}, "
+                               f"n log-uniform [64,{args.serving_nmax}], kappa 0 w.p. 1/2 else U[-100,0], "
+                               f"seeded Gaussian RHS, rel-res 1e-10; continuous-batching server "
+                               f"({args.serving_slots} slots, {args.serving_budget_gb:g} GB); a step is one "
+                               f"second of arrivals ({warm:g} s warm-up, {meas:g} s measured); plans built at "
+                               f"arrival inside the latency",
+                   "headline_path": headline, "paths": out, "latency_ms": {
+                       "p50": head["latency_ms_p50"], "p99": head["latency_ms_p99"]}},
+        "kernels_warmup": cls_times, "roofline": roofline, "cpu_baseline": cpu,
+        "kernel_source_hash": kernel_source_hash(),
     }
+
+
+def serving_cpu_baseline(reqs, budget_s):
+    """The FP64 oracle on requests of the same trace, taken in arrival order
+    among those it finishes in seconds (n <= 256), until the time budget is
+    spent."""
+    from oracle import composite
+    try:
+        import threadpoolctl
+        cores = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    done, t0 = [], time.perf_counter()
+    for rq in reqs:
+        if rq.spec.n > 256:
+            continue
+        prob = rq.spec.build()
+        composite.solve(prob.rects, prob.h, prob.kappa, prob.f_grid, prob.g_grid)
+        done.append(f"{rq.spec.shape} n={rq.spec.n}")
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(len(done) / dt, 4), "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{len(done)} requests of the trace in arrival order with n <= 256 "
+                      f"({', '.join(done[:6])}{', ...' if len(done) > 6 else ''}); global composite "
+                      f"system, LAPACK banded Cholesky; {dt:.1f} s (larger requests excluded: minutes each)"}
 
 
 # --------------------------------------------------------------------------- reduced precision vs FP64
@@ -446,12 +598,18 @@ def cpu_baseline(items, sample):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="plain",
-                    choices=["plain", "precision", "batching", "serving", "convergence"])
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (serving: seconds of measured arrivals; default 10)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="warm-up steps (serving: seconds of arrivals before the measured window; default 2)")
+    ap.add_argument("--workload", default="serving",
+                    choices=["serving", "plain", "precision", "batching", "convergence"])
     ap.add_argument("--serving-rate", type=float, default=200.0, help="requests per second")
-    ap.add_argument("--serving-seconds", type=float, default=1.0, help="length of the arrival trace")
+    ap.add_argument("--serving-compare-seconds", type=float, default=5.0,
+                    help="measured seconds of the trace replayed on the comparison paths")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="serving: CPU oracle time budget")
+    ap.add_argument("--serving-paths", default="",
+                    help="comma-separated subset of the serving paths (default: all three)")
     ap.add_argument("--serving-nmax", type=int, default=2048)
     ap.add_argument("--serving-budget-gb", type=float, default=160.0)
     ap.add_argument("--serving-slots", type=int, default=64)
@@ -467,6 +625,10 @@ def main():
                     help="host only: turn rocprofv3 --pmc output directories into the traffic record")
     ap.add_argument("--traffic-kernel", default="k_gram_update_lag")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 10
+    if args.warmup is None:
+        args.warmup = 2
     if args.traffic_summary:
         traffic_summary(args)
         return
@@ -478,6 +640,11 @@ def main():
               "GPUs with no communication).", file=sys.stderr)
         sys.exit(2)
 
+    # measured transform choices of this device kind (see tune.cpp): plans
+    # built as requests arrive then cost no device measurement
+    table = os.path.join(ROOT, "paper_2509_23180_amd", "tune_gfx950.txt")
+    if "FDS_TUNE_FILE" not in os.environ and os.path.exists(table):
+        os.environ["FDS_TUNE_FILE"] = table
     import torch
     import paper_2509_23180_amd as fds
     if not torch.cuda.is_available():

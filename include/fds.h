@@ -103,7 +103,8 @@ typedef enum {
   FDS_STOP_NONE = 0,
   FDS_STOP_TOL = 1,           /* true relative residual <= tol              */
   FDS_STOP_AT_FLOOR = 2,      /* tol below the FP64 rounding floor; stopped */
-                              /* at max(tol, 2*floor estimate)              */
+                              /* at max(tol, 2*floor estimate), or a cycle  */
+                              /* without 10% gain within twice that bound   */
   FDS_STOP_MAX_CYCLES = 3,
   FDS_STOP_STAGNATION = 4
 } fds_stop_reason;

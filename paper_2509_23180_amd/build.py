@@ -45,8 +45,19 @@ def build(verbose: bool = False) -> str:
     cc = hipcc()
     objs = []
 
+    # FDS_BUILD_INCREMENTAL=1 (development only): keep objects newer than
+    # their source and every header; the default rebuilds everything
+    incremental = os.environ.get("FDS_BUILD_INCREMENTAL") == "1"
+    headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    headers.append(os.path.join(ROOT, "include", "fds.h"))
+    newest_header = max(os.path.getmtime(h) for h in headers)
+
     def compile_one(src):
         obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+        if incremental and os.path.exists(obj):
+            t = os.path.getmtime(obj)
+            if t > os.path.getmtime(os.path.join(CSRC, src)) and t > newest_header:
+                return obj
         cmd = [cc, *_flags(src), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

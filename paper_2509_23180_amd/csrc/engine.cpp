@@ -852,7 +852,7 @@ void Engine::Impl::launch_graph_cycle(TaskSet& ts) {
       gexec = nullptr;
     }
     if (!cap_stream) FDS_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
-    FDS_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+    FDS_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed));
     hipGraph_t g = nullptr;
     try {
       for (int j = 0; j < m; ++j) ts.iteration(j, flags_dev, 0, cap_stream);

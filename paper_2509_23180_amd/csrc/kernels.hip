@@ -1318,8 +1318,11 @@ __global__ void __launch_bounds__(kBlock) k_restart(const KryTask* __restrict__ 
     done = true;
     reason = FDS_STOP_MAX_CYCLES;
   } else if (!initial && st->cycles >= 2 && rel > 0.9 * st->prev_rel) {
+    // no 10% gain over a cycle: within twice the effective tolerance this is
+    // the rounding floor (the floor estimate is only an estimate), otherwise
+    // the iteration has stalled
     done = true;
-    reason = FDS_STOP_STAGNATION;
+    reason = rel <= 2.0 * tol_eff ? FDS_STOP_AT_FLOOR : FDS_STOP_STAGNATION;
   }
   if (initial) st->fnorm = fnorm;
   else st->cycles += 1;
@@ -1566,17 +1569,18 @@ void launch_tridiag(bool fp32, const TriTask* tasks, int ntasks, int nblocks, in
 }
 
 TriConfig tri_config(bool fp32, int max_rows) {
-  // register segments of at most 16 (FP64) or 32 (FP32) rows; up to 1024
-  // threads per block: 16 modes x 64 segments, 32 x 32 or 64 x 16.  Fewest
-  // modes per block first: a problem's modes then spread over more blocks
-  // (16 modes x 8 bytes still read whole 128-byte lines per row).
+  // register segments of 8 to 32 rows (the shortest that fits); up to 1024
+  // threads per block: 16 modes x 64 segments, 32 x 32, 64 x 16, or 8 x 128
+  // for the longest systems.  Fewest modes per block first: a problem's
+  // modes then spread over more blocks (16 modes x 8 bytes still read whole
+  // 128-byte lines per row).
   TriConfig c{false, 0, 0, 0};
-  const int lsmax = fp32 ? 32 : 16;
+  const int lsmax = 32;
   // tuning override "mpb,ls": taken when the pair is instantiated and fits
   if (const char* e = std::getenv("FDS_TRI_SEG")) {
     int mpb = 0, ls = 0;
     if (std::sscanf(e, "%d,%d", &mpb, &ls) == 2 && (mpb == 8 || mpb == 16 || mpb == 32 || mpb == 64) &&
-        (ls == 4 || ls == 8 || ls == 16 || (fp32 && ls == 32))) {
+        (ls == 4 || ls == 8 || ls == 16 || ls == 32)) {
       const int S = (max_rows + ls - 1) / ls;
       if (S <= 1024 / mpb) {
         c.seg = true;
@@ -1588,7 +1592,9 @@ TriConfig tri_config(bool fp32, int max_rows) {
       }
     }
   }
-  for (int mpb : {16, 32, 64}) {
+  // (8 modes per block last: up to 128 segments, for systems of more than
+  // 1024 (FP64 with 16-row segments) or 2048 rows)
+  for (int mpb : {16, 32, 64, 8}) {
     const int segmax = 1024 / mpb;
     for (int ls = 8; ls <= lsmax; ls *= 2) {
       const int S = (max_rows + ls - 1) / ls;
@@ -1637,7 +1643,8 @@ void launch_tri(const TriConfig& c, bool fp32, const TriTask* tasks, int ntasks,
     switch (c.ls) {
       case 4: FDS_SEG_MPB(double, 4); break;
       case 8: FDS_SEG_MPB(double, 8); break;
-      default: FDS_SEG_MPB(double, 16); break;
+      case 16: FDS_SEG_MPB(double, 16); break;
+      default: FDS_SEG_MPB(double, 32); break;
     }
   }
 #undef FDS_SEG_MPB

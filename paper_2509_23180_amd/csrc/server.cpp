@@ -149,9 +149,14 @@ void fds_server::admit_from_queue() {
     }
     try {
       if (!g.stream) FDS_HIP(hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking));
-      if (!g.eng)
+      if (!g.eng) {
         g.eng.reset(new fds::Engine(std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
                                     max_slots, g.stream, std::get<3>(kv.first)));
+        // the set changes at most cycle boundaries under continuous batching,
+        // so cycles are launched kernel by kernel (no graph capture while
+        // the submitting threads build plans)
+        g.eng->set_graphs(false);
+      }
       g.eng->admit(reqs, ids, evs);
       for (size_t i = 0; i < ids.size(); ++i) {
         g.running[ids[i]] = kv.second[i];

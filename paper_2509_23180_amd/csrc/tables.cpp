@@ -15,6 +15,17 @@
 
 namespace fds {
 
+// Host-to-device upload of a table, ordered on a private non-blocking stream
+// of the calling thread and waited for: no legacy-stream operation, so plans
+// can be built while another thread captures or replays a graph.
+static void upload(void* dst, const void* src, size_t bytes) {
+  thread_local hipStream_t s = nullptr;
+  if (!s) FDS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  FDS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+  FDS_HIP(hipStreamSynchronize(s));
+}
+
+
 std::vector<int> fft_radices(int N) {
   // radix-16 and radix-8 butterflies run in registers, so powers of two go
   // out in as few passes as possible
@@ -622,7 +633,7 @@ std::shared_ptr<FftTable> TableCache::fft(int n) {
   d.chirp64 = blue ? t->mem.as<double2>(o_c64) : nullptr;
   d.chirp32 = blue ? t->mem.as<float2>(o_c32) : nullptr;
   std::memcpy(host.data(), &d, sizeof(d));
-  FDS_HIP(hipMemcpy(t->mem.get(), host.data(), total, hipMemcpyHostToDevice));
+  upload(t->mem.get(), host.data(), total);
   t->host = d;
   t->dev = t->mem.as<FftDesc>(0);
   fft_[key] = t;
@@ -692,9 +703,8 @@ std::shared_ptr<ModeTable> upload_modes(const std::vector<ModeCoef<double>>& c64
   auto t = std::make_shared<ModeTable>();
   const size_t o32 = align_up(sizeof(ModeCoef<double>) * n, 256);
   t->mem.alloc(o32 + sizeof(ModeCoef<float>) * n);
-  FDS_HIP(hipMemcpy(t->mem.get(), c64.data(), sizeof(ModeCoef<double>) * n, hipMemcpyHostToDevice));
-  FDS_HIP(hipMemcpy(t->mem.as<char>(o32), c32.data(), sizeof(ModeCoef<float>) * n,
-                    hipMemcpyHostToDevice));
+  upload(t->mem.get(), c64.data(), sizeof(ModeCoef<double>) * n);
+  upload(t->mem.as<char>(o32), c32.data(), sizeof(ModeCoef<float>) * n);
   t->c64 = t->mem.as<ModeCoef<double>>(0);
   t->c32 = t->mem.as<ModeCoef<float>>(o32);
   return t;
@@ -758,7 +768,7 @@ std::shared_ptr<GsTable> TableCache::gs(int n, int m, double h, double kappa, bo
         mf[(size_t)(k - 1) * n + (i - 1)] = (double)(0.5L * (c[std::abs(i - k)] - c[i + k]));
   }
   t->mem.alloc(sizeof(double) * host.size());
-  FDS_HIP(hipMemcpy(t->mem.get(), host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice));
+  upload(t->mem.get(), host.data(), sizeof(double) * host.size());
   t->gs = t->mem.as<double>(0);
   if (dense) {
     t->mfull = t->gs + n;
@@ -806,7 +816,7 @@ std::shared_ptr<IkPlanTable> build_ik_table(int nx, int ny, double h, double kap
   axis(ny, nx, lamy, qy, s00, s0n);   // y modes: systems of nx columns
   auto t = std::make_shared<IkPlanTable>();
   t->mem.alloc(sizeof(double) * host.size());
-  FDS_HIP(hipMemcpy(t->mem.get(), host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice));
+  upload(t->mem.get(), host.data(), sizeof(double) * host.size());
   const double* b = t->mem.as<double>(0);
   t->lamx = b;
   t->qx = b + nx;

@@ -8,7 +8,15 @@
 // (about 8 MB of data) a few times, timed with HIP events on a private
 // stream, and the fastest is kept for the rest of the process.  Plans ask at
 // creation time, so a solve never waits for tuning.
+//
+// FDS_TUNE_FILE names a table of earlier measurements on this kind of device
+// ("n precision variant" per line, precision 0 FP64 / 1 FP32, variant
+// wave|wavebig|fft|gemm): a length found there is not measured again, and a
+// new measurement is appended to the file (when it is writable).  Request
+// paths that build plans as requests arrive use it so that a new length does
+// not cost a device measurement.
 #include <algorithm>
+#include <fstream>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -79,6 +87,38 @@ double time_variant(const DstChoice& ch, int n, bool fp32, int rows, void* in, v
   return ms / reps;
 }
 
+const char* variant_name(const DstChoice& c) {
+  return c.gemm ? "gemm" : c.wave_big ? "wavebig" : c.wave_e ? "wave" : "fft";
+}
+
+// The table of FDS_TUNE_FILE, read once: (n, fp32) -> variant.
+std::map<std::pair<int, bool>, std::string>& tune_table() {
+  static std::map<std::pair<int, bool>, std::string> table;
+  static bool loaded = false;
+  if (!loaded) {
+    loaded = true;
+    if (const char* path = std::getenv("FDS_TUNE_FILE")) {
+      std::ifstream in(path);
+      int n = 0, prec = 0;
+      std::string mode;
+      while (in >> n >> prec >> mode)
+        if (n > 0 && (prec == 0 || prec == 1) &&
+            (mode == "wave" || mode == "wavebig" || mode == "fft" || mode == "gemm"))
+          table[{n, prec != 0}] = mode;
+    }
+  }
+  return table;
+}
+
+void tune_table_append(int n, bool fp32, const char* mode) {
+  const char* path = std::getenv("FDS_TUNE_FILE");
+  if (!path) return;
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "%d %d %s\n", n, fp32 ? 1 : 0, mode);
+    std::fclose(f);
+  }
+}
+
 }  // namespace
 
 DstChoice dst_tuned_choice(int n, bool fp32) {
@@ -90,6 +130,15 @@ DstChoice dst_tuned_choice(int n, bool fp32) {
   auto key = std::make_tuple(dev, n, fp32);
   auto it = tuned.find(key);
   if (it != tuned.end()) return it->second;
+  {
+    auto& table = tune_table();
+    auto t = table.find({n, fp32});
+    if (t != table.end()) {
+      const DstChoice c = dst_choice_variant(n, fp32, t->second);
+      tuned[key] = c;
+      return c;
+    }
+  }
 
   std::vector<DstChoice> cand;
   for (const char* mode : {"wave", "wavebig", "fft", "gemm"}) {
@@ -119,7 +168,7 @@ DstChoice dst_tuned_choice(int n, bool fp32) {
         }
         if (log)
           std::fprintf(stderr, "[fds tune] n=%d %s rows=%d %s: %.1f us\n", n, fp32 ? "fp32" : "fp64",
-                       rows, cand[i].gemm ? "gemm" : cand[i].wave_big ? "wavebig" : cand[i].wave_e ? "wave" : "fft", ms * 1e3);
+                       rows, variant_name(cand[i]), ms * 1e3);
         if (tbest < 0 || ms < tbest) {
           tbest = ms;
           best = cand[i];
@@ -130,6 +179,7 @@ DstChoice dst_tuned_choice(int n, bool fp32) {
     (void)hipStreamDestroy(s);
   }
   tuned[key] = best;
+  if (cand.size() > 1) tune_table_append(n, fp32, variant_name(best));
   return best;
 }
 

@@ -1,0 +1,36 @@
+"""Measure the row-transform variant of every length in a range on this
+device and append the choices to the tuning table (FDS_TUNE_FILE format:
+"n precision variant").  Lengths already in the table are skipped by the
+library itself.
+
+    python -m paper_2509_23180_amd.tune_table --nmin 1 --nmax 2048 --out paper_2509_23180_amd/tune_gfx950.txt
+"""
+
+import argparse
+import os
+import sys
+import time
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--nmin", type=int, default=1)
+    ap.add_argument("--nmax", type=int, default=2048)
+    ap.add_argument("--out", required=True)
+    args = ap.parse_args()
+    os.environ["FDS_TUNE_FILE"] = os.path.abspath(args.out)
+    import torch
+    import paper_2509_23180_amd as fds
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    for n in range(args.nmin, args.nmax + 1):
+        for dtype in (torch.float64, torch.float32):
+            x = torch.zeros((1, n), dtype=dtype, device="cuda")
+            fds.dst_rows(x, x)      # first use of (n, precision): the tuner measures it
+        if n % 64 == 0:
+            print(f"n={n} ({time.time() - t0:.0f} s)", flush=True)
+    print(f"done in {time.time() - t0:.0f} s", file=sys.stderr)
+
+
+if __name__ == "__main__":
+    main()
