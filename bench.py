@@ -323,24 +323,62 @@ class TimedSlice:
         self.th.join()
 
 
-def replay(fds, torch, srv, reqs, opts, device, t_measure, plan_cache, timed=None):
+SUBMITTERS = 4   # front-end threads building plans and submitting requests
+
+
+class PlanCache:
+    """Plans keyed by (shape, n, kappa), the least recently used dropped
+    beyond `capacity` (a dropped plan stays alive while a request uses it)."""
+
+    def __init__(self, capacity=256):
+        import collections
+        self.capacity = capacity
+        self.d = collections.OrderedDict()
+
+    def get(self, key):
+        p = self.d.get(key)
+        if p is not None:
+            self.d.move_to_end(key)
+        return p
+
+    def put(self, key, plan):
+        self.d[key] = plan
+        while len(self.d) > self.capacity:
+            self.d.popitem(last=False)
+
+
+def request_inputs(reqs, device):
+    """Right-hand sides of every request of a trace, generated on the device
+    before the replay (the requests' data is resident in HBM when they
+    arrive)."""
+    import torch
+    out = []
+    for rq in reqs:
+        rects, h, rhs = request_rhs(rq.spec, device)
+        out.append((rects, h, rhs))
+    torch.cuda.synchronize()
+    return out
+
+
+def replay(fds, torch, srv, reqs, inputs, opts, device, t_measure, plan_cache, timed=None):
     """Open-loop replay of a request trace against a server.  A submitter
     thread takes each request at its arrival time, builds its plan (or takes
-    it from the plan cache, keyed by shape, n and kappa) and its right-hand
-    side on the device, and submits it; the latency clock starts at the
+    it from the plan cache) and its output buffer, and submits it with its
+    right-hand side (already on the device); the latency clock starts at the
     scheduled arrival.  The main thread polls.  Returns per-request records."""
     import threading
     recs = [None] * len(reqs)
     tickets = [None] * len(reqs)
     xs = [None] * len(reqs)
-    stream = torch.cuda.Stream()
     t0 = time.perf_counter() + 0.2
     lock = threading.Lock()
 
-    def submitter():
+    def submitter(first, step):
         torch.cuda.set_device(device)
+        stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
-            for k, rq in enumerate(reqs):
+            for k in range(first, len(reqs), step):
+                rq = reqs[k]
                 delay = t0 + rq.arrival_s - time.perf_counter()
                 if delay > 0:
                     time.sleep(delay)
@@ -349,10 +387,10 @@ def replay(fds, torch, srv, reqs, opts, device, t_measure, plan_cache, timed=Non
                 tp = time.perf_counter()
                 plan = plan_cache.get(key)
                 hit = plan is not None
-                rects, h, rhs = request_rhs(sp, device)
+                rects, h, rhs = inputs[k]
                 if plan is None:
                     plan = fds.Plan(rects, h, sp.kappa, **opts)
-                    plan_cache[key] = plan
+                    plan_cache.put(key, plan)
                 x = torch.empty(plan.n_unknowns, dtype=torch.float64, device=device)
                 t = srv.submit(plan, rhs, x, 1e-10, stream=stream)
                 with lock:
@@ -361,18 +399,24 @@ def replay(fds, torch, srv, reqs, opts, device, t_measure, plan_cache, timed=Non
                     recs[k] = {"arrival": t0 + rq.arrival_s, "prep_ms": (time.perf_counter() - tp) * 1e3,
                                "plan_hit": hit}
 
-    th = threading.Thread(target=submitter)
-    th.start()
+    # a front end of SUBMITTERS threads, request k handled by thread k % SUBMITTERS
+    ths = [threading.Thread(target=submitter, args=(i, SUBMITTERS)) for i in range(SUBMITTERS)]
+    for th in ths:
+        th.start()
     if timed is not None:
         timed.start()
     done = 0
     pending = set()
     nxt = 0
+    seen = [False] * len(reqs)
     while done < len(reqs):
         with lock:
-            while nxt < len(reqs) and tickets[nxt] is not None:
-                pending.add(nxt)
+            while nxt < len(reqs) and seen[nxt]:
                 nxt += 1
+            for k in range(nxt, min(len(reqs), nxt + 4 * SUBMITTERS + 64)):
+                if not seen[k] and tickets[k] is not None:
+                    seen[k] = True
+                    pending.add(k)
         for k in list(pending):
             r = srv.poll(tickets[k])
             if r is not None:
@@ -382,7 +426,8 @@ def replay(fds, torch, srv, reqs, opts, device, t_measure, plan_cache, timed=Non
                 pending.discard(k)
                 done += 1
         time.sleep(0.0002)
-    th.join()
+    for th in ths:
+        th.join()
     if timed is not None:
         timed.join()
     for rq, rec in zip(reqs, recs):
@@ -407,6 +452,8 @@ def summarise(recs, reqs, srv_stats):
             "iterations_mean": round(sum(r["iterations"] for r in meas) / len(meas), 1),
             "max_relres_schur": max(r["relres"] for r in meas),
             "admitted_mid_flight": srv_stats["admitted_mid_flight"],
+            "server_host_s": {k[5:-2]: round(srv_stats[k], 3) for k in
+                              ("host_admit_s", "host_retire_s", "host_tasks_s", "host_launch_s", "host_wait_s")},
             "peak_hbm_gb": round(srv_stats["peak_bytes_in_use"] / 1e9, 2),
             "not_converged": [{"shape": reqs[k].spec.shape, "n": reqs[k].spec.n,
                                "kappa": round(reqs[k].spec.kappa, 3), "problem": reqs[k].spec.problem_id,
@@ -433,6 +480,19 @@ def run_serving(args, device):
     reqs = workloads.request_stream(args.serving_rate, warm + meas, n_min=64, n_max=args.serving_nmax)
     log(f"serving: {len(reqs)} requests at {args.serving_rate:g}/s over {warm:g} s warm-up + {meas:g} s "
         f"measured, n in [64, {args.serving_nmax}]")
+    t_in = time.perf_counter()
+    inputs = request_inputs(reqs, device)
+    log(f"serving: right-hand sides of {len(reqs)} requests generated on the device in "
+        f"{time.perf_counter() - t_in:.1f} s")
+    # transform tables depend on the length only (not on shape or kappa): a
+    # server builds them once for the lengths it serves, before taking
+    # requests (like the transform tuning table)
+    t_in = time.perf_counter()
+    for n in sorted({r.spec.n for r in reqs}):
+        x = torch.zeros((1, n), dtype=torch.float64, device=device)
+        fds.dst_rows(x, x)
+    log(f"serving: transform tables of {len({r.spec.n for r in reqs})} lengths built in "
+        f"{time.perf_counter() - t_in:.1f} s")
     out = {}
     headline = "interface_gmres40_fp64"
     roofline = None
@@ -446,15 +506,17 @@ def run_serving(args, device):
         # first `--serving-compare-seconds` measured seconds
         span = warm + meas if name == headline else warm + min(meas, args.serving_compare_seconds)
         sub = [r for r in reqs if r.arrival_s <= span]
+        sub_in = inputs[:len(sub)]
         srv = fds.Server(hbm_budget_bytes=int(args.serving_budget_gb * (1 << 30)),
                          max_slots=args.serving_slots)
-        plan_cache = {}
+        plan_cache = PlanCache()
         timed = None
         if name == headline:
             # warm-up pass with every class timed: which kernel dominates
             fds.timing_reset()
             fds.timing_enable(None)
-            replay(fds, torch, srv, [r for r in reqs if r.arrival_s < warm], opts, device, warm, {})
+            nwarm = sum(1 for r in reqs if r.arrival_s < warm)
+            replay(fds, torch, srv, reqs[:nwarm], inputs[:nwarm], opts, device, warm, PlanCache())
             fds.timing_enable([])
             cls_times = {}
             for c in ("dst", "tridiag", "operator", "gram_dots", "gram_update", "lines", "cols", "other"):
@@ -467,7 +529,7 @@ def run_serving(args, device):
             t_base = time.perf_counter() + 0.2
             timed = TimedSlice(fds, dominant, t_base + warm + 0.4 * meas, t_base + warm + 0.6 * meas)
         t_wall = time.perf_counter()
-        recs = replay(fds, torch, srv, sub, opts, device, warm, plan_cache, timed)
+        recs = replay(fds, torch, srv, sub, sub_in, opts, device, warm, plan_cache, timed)
         st = srv.stats()
         srv.close()
         out[name] = summarise(recs, sub, st)
@@ -492,6 +554,8 @@ def run_serving(args, device):
                     roofline["traffic"] = tr.get("hbm_bytes_per_launch")
         del plan_cache
         torch.cuda.empty_cache()
+    del inputs
+    torch.cuda.empty_cache()
     head = out[headline]
     cpu = None
     if not args.no_cpu_baseline:
@@ -506,8 +570,10 @@ def run_serving(args, device):
                                f"n log-uniform [64,{args.serving_nmax}], kappa 0 w.p. 1/2 else U[-100,0], "
                                f"seeded Gaussian RHS, rel-res 1e-10; continuous-batching server "
                                f"({args.serving_slots} slots, {args.serving_budget_gb:g} GB); a step is one "
-                               f"second of arrivals ({warm:g} s warm-up, {meas:g} s measured); plans built at "
-                               f"arrival inside the latency",
+                               f"second of arrivals ({warm:g} s warm-up, {meas:g} s measured); right-hand sides "
+                               f"resident in HBM before the replay; transform tables per length built "
+                               f"before it; plans built at arrival inside the latency by "
+                               f"{SUBMITTERS} front-end threads (LRU cache of 256 plans)",
                    "headline_path": headline, "paths": out, "latency_ms": {
                        "p50": head["latency_ms_p50"], "p99": head["latency_ms_p99"]}},
         "kernels_warmup": cls_times, "roofline": roofline, "cpu_baseline": cpu,

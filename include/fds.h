@@ -230,6 +230,11 @@ typedef struct {
   int32_t running;            /* admitted and not yet retired now           */
   uint64_t bytes_in_use;      /* footprint of the running requests now      */
   uint64_t peak_bytes_in_use;
+  double host_admit_s;        /* worker thread: admissions (set-up phases)  */
+  double host_retire_s;       /*   retirements (back substitution, output)  */
+  double host_tasks_s;        /*   task lists rebuilt after set changes     */
+  double host_launch_s;       /*   queueing the cycles' kernels             */
+  double host_wait_s;         /*   waiting for cycles to finish             */
 } fds_server_stats;
 fds_status fds_server_stats_get(fds_server* server, fds_server_stats* out);
 

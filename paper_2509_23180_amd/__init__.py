@@ -53,7 +53,10 @@ class _ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
                 ("completed", ctypes.c_uint64), ("admitted_mid_flight", ctypes.c_uint64),
                 ("cycles", ctypes.c_uint64), ("queued", ctypes.c_int32), ("running", ctypes.c_int32),
-                ("bytes_in_use", ctypes.c_uint64), ("peak_bytes_in_use", ctypes.c_uint64)]
+                ("bytes_in_use", ctypes.c_uint64), ("peak_bytes_in_use", ctypes.c_uint64),
+                ("host_admit_s", ctypes.c_double), ("host_retire_s", ctypes.c_double),
+                ("host_tasks_s", ctypes.c_double), ("host_launch_s", ctypes.c_double),
+                ("host_wait_s", ctypes.c_double)]
 
 
 class _Options(ctypes.Structure):

@@ -160,13 +160,14 @@ struct SlotLayout {
   size_t b_int, x_int, tmpd, fp, V, u, zbuf, lines, small, partials, respart, Z, tmpf, gram, zcols,
       bc, total;
   // interface Krylov iteration
-  size_t V0, Vb, rline, rho, zcol, zc, ucoef, uphys, dhat, xpart, scal;
+  size_t V0, Vb, rline, rho, zcol, zc, ucoef, uphys, dhat, xpart, scal, rscale, Wv, dpart, cpart;
 };
 
 // Interface Krylov iteration: coordinates of the lines that carry an arm.
 struct IkGeom {
   int nb = 0, ldv = 0, off[4] = {-1, -1, -1, -1};
   int nxa = 0, nya = 0;   // cross-sum blocks of the two directions
+  int nslab = 1;          // blocks of the coordinate passes
 };
 
 IkGeom ik_geom(const fds_plan* p) {
@@ -182,9 +183,10 @@ IkGeom ik_geom(const fds_plan* p) {
   g.ldv = (1 + g.nb + 31) / 32 * 32;
   const bool xl = g.off[0] >= 0 || g.off[1] >= 0, yl = g.off[2] >= 0 || g.off[3] >= 0;
   if (xl && yl) {
-    g.nxa = div_up(p->ny, kIkXTile);   // x -> y: targets along y
-    g.nya = div_up(p->nx, kIkXTile);
+    g.nxa = div_up(p->ny, kIkXTile) * kIkXParts;   // x -> y: targets along y
+    g.nya = div_up(p->nx, kIkXTile) * kIkXParts;
   }
+  g.nslab = div_up(1 + g.nb, kIkSlab);
   return g;
 }
 
@@ -224,8 +226,12 @@ SlotLayout layout_of(const fds_plan* p, int m, int precision) {
     L.ucoef = take(8 * (size_t)(1 + g.nb));
     L.uphys = take(8 * 2 * (size_t)p->ny);
     L.dhat = take(8 * (size_t)std::max(1, g.nb));
-    L.xpart = take(8 * 8 * (size_t)Lmax);
-    L.scal = take(8 * 8);
+    L.xpart = take(8 * 8 * kIkXParts * (size_t)Lmax);
+    L.scal = take(8 * 16);
+    L.rscale = take(8 * (size_t)(m + 1));
+    L.Wv = take(8 * (size_t)g.ldv);
+    L.dpart = take(8 * (size_t)(2 * (m + 1) + 1) * g.nslab);
+    L.cpart = take(8 * 4 * (size_t)std::max(1, g.nxa));
     L.total = o;
     return L;
   }
@@ -261,8 +267,9 @@ struct Problem {
   float *Z = nullptr, *tmpf = nullptr;
   // interface Krylov iteration
   double *V0 = nullptr, *Vb = nullptr, *rline = nullptr, *rho = nullptr, *zcol = nullptr, *zc = nullptr,
-         *ucoef = nullptr, *uphys = nullptr, *dhat = nullptr, *xpart = nullptr, *scal = nullptr;
-  double scal_init[8] = {0, 0, 0, 1.0, 0, 0, 0, 0};   // scal[3] = 1 (unit scale of a solve's input)
+         *ucoef = nullptr, *uphys = nullptr, *dhat = nullptr, *xpart = nullptr, *scal = nullptr,
+         *rscale = nullptr, *Wv = nullptr, *dpart = nullptr, *cpart = nullptr;
+  double scal_init[16] = {0, 0, 0, 1.0};   // scal[3] = 1 (unit scale of a solve's input)
   ProbState* st = nullptr;
   long long Nc = 0, Nint = 0;
   int P = 0, Lmax = 0, res_blocks = 0;
@@ -304,6 +311,7 @@ struct TaskSet {
   // interface Krylov iteration
   bool ik = false;
   TaskList<IkTask> ik_p, ik_x, ik_1;   // blocks over the centre / cross sums / one per problem
+  TaskList<IkTask> ik_s;               // coordinate blocks of the step passes
   DstStage ik_lfwd, ik_linv;           // line transforms at the cycle start / end
   TriStage ik_tri0;                    // T^{-1} of the interior residual's coefficients
   TaskList<ColTask> ik_cols;           // its values on columns 0 and nx-1
@@ -320,6 +328,7 @@ struct TaskSet {
     for (DstStage* d : {&cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd, &ik_lfwd, &ik_linv}) d->stage(blob);
     for (TriStage* t : {&it_tri, &cyc_tri, &arm_tri, &ik_tri0}) t->stage(blob);
     blob.add(ik_p);
+    blob.add(ik_s);
     blob.add(ik_x);
     blob.add(ik_1);
     blob.add(ik_cols);
@@ -576,7 +585,7 @@ void TaskSet::add_problem_ik(Problem& sl) {
   const IkGeom g = ik_geom(p);
   const int* skip_fin = &sl.st->finished;
   IkTask t{};
-  t.st = sl.st; t.H = sl.H; t.cs = sl.cs; t.sn = sl.sn; t.g = sl.g; t.y = sl.y; t.G = sl.G;
+  t.st = sl.st; t.H = sl.H; t.cs = sl.cs; t.sn = sl.sn; t.g = sl.g; t.y = sl.y; t.G = sl.G; t.hv = sl.hv;
   t.Vb = sl.Vb; t.ldv = g.ldv; t.nb = g.nb; t.m = m; t.flag_idx = sl.idx;
   t.nx = nx; t.ny = ny; t.Nc = sl.Nc; t.P = sl.P;
   for (int a = 0; a < 4; ++a) {
@@ -589,7 +598,8 @@ void TaskSet::add_problem_ik(Problem& sl) {
     t.gscale[a.line] = 0.5 * (a.L + 1);
     t.present |= 1 << a.line;
   }
-  t.nxa = g.nxa; t.nya = g.nya;
+  t.nxa = g.nxa; t.nya = g.nya; t.nslab = g.nslab;
+  t.rscale = sl.rscale; t.Wv = sl.Wv; t.dpart = sl.dpart; t.cpart = sl.cpart;
   t.lamx = p->ik->lamx; t.lamy = p->ik->lamy; t.qx = p->ik->qx; t.qy = p->ik->qy;
   t.t00 = p->ik->t00; t.t0n = p->ik->t0n; t.s00 = p->ik->s00; t.s0n = p->ik->s0n;
   t.kappa = p->kappa;
@@ -597,6 +607,7 @@ void TaskSet::add_problem_ik(Problem& sl) {
   t.zc = sl.zc; t.ucoef = sl.ucoef; t.uphys = sl.uphys; t.dhat = sl.dhat; t.xpart = sl.xpart;
   t.scal = sl.scal; t.partials = sl.partials + (size_t)kPartNorm * sl.P; t.lmax = sl.Lmax;
   ik_max_coords = std::max(ik_max_coords, 1 + g.nb);
+  add_block_task(ik_s, t, g.nslab);
   add_block_task(ik_p, t, sl.P);
   if (g.nxa + g.nya > 0) add_block_task(ik_x, t, g.nxa + g.nya);
   add_block_task(ik_1, t, 1);
@@ -613,21 +624,25 @@ void TaskSet::add_problem_ik(Problem& sl) {
     ct.fft = p->fft_c->dev; ct.nx = nx; ct.ny = ny; ct.skip = skip_fin; ct.scale = std::sqrt(2.0 / (nx + 1));
     add_block_task(ik_cols, ct, div_up(ny, kBlock / 64));
   }
-  auto line_dst = [&](DstStage& st, const double* in, double* out, int L) {
+  // transform tables from the plan (the arms' lines have the centre's side
+  // lengths): no table lookups while the set is rebuilt
+  const FftDesc* fft_line[4] = {p->fft_c->dev, p->fft_c->dev, nullptr, nullptr};
+  for (const ArmInfo& a : p->arms) fft_line[a.line] = a.fft->dev;
+  auto line_dst = [&](DstStage& st, const double* in, double* out, int L, const FftDesc* fft) {
     DstTask d{};
     d.in = in; d.out = out; d.in_rs = L; d.out_rs = L; d.in_cs = 1; d.out_cs = 1;
     d.rows = 1; d.n = L; d.scale = std::sqrt(2.0 / (L + 1)); d.skip = skip_fin;
-    d.fft = TableCache::get().fft(L)->dev;
+    d.fft = fft;
     d.tw_lds = dst_twiddles_in_lds(L, false);
     st.add(d);
   };
   for (int a = 0; a < 4; ++a) {
     if (g.off[a] < 0) continue;
     const int L = a < 2 ? nx : ny;
-    line_dst(ik_lfwd, sl.rline + (size_t)a * sl.Lmax, sl.rho + g.off[a], L);
+    line_dst(ik_lfwd, sl.rline + (size_t)a * sl.Lmax, sl.rho + g.off[a], L, fft_line[a]);
     if (a >= 2) {
-      line_dst(ik_lfwd, sl.zcol + (size_t)(a - 2) * ny, sl.zc + (size_t)(a - 2) * ny, ny);
-      line_dst(ik_linv, sl.ucoef + 1 + g.off[a], sl.uphys + (size_t)(a - 2) * ny, ny);
+      line_dst(ik_lfwd, sl.zcol + (size_t)(a - 2) * ny, sl.zc + (size_t)(a - 2) * ny, ny, fft_line[a]);
+      line_dst(ik_linv, sl.ucoef + 1 + g.off[a], sl.uphys + (size_t)(a - 2) * ny, ny, fft_line[a]);
     }
   }
 }
@@ -669,7 +684,7 @@ void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
       Timing::end(4, s);
     }
     Timing::begin(6, s);
-    launch_ik_step(ik_1.dev(), ik_1.n(), ik_max_coords, j, flags_dev, tag, s);
+    launch_ik_step(ik_s.dev(), ik_s.n(), ik_s.nblocks, j, flags_dev, tag, s);
     Timing::end(6, s);
     FDS_HIP(hipGetLastError());
     return;
@@ -799,6 +814,7 @@ struct Engine::Impl {
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_stream = nullptr;   // capture only (nothing runs on it)
   int replays = 0;
+  double t_tasks = 0;                 // host seconds building task lists
 
   ~Impl() {
     // the device buffers go back to the cache: nothing queued may still use them
@@ -831,10 +847,12 @@ void Engine::Impl::read_states() {
 
 TaskSet& Engine::Impl::current() {
   if (!cur) {
+    const auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<TaskSet> ts(new TaskSet(m, flex, ik));
     for (auto& p : active) ts->add_problem(*p);
     ts->upload(s);
     set_cur(std::move(ts));
+    t_tasks += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return *cur;
 }
@@ -902,6 +920,7 @@ size_t Engine::bytes_per_problem(const fds_plan* p, int m, int precision) {
 int Engine::free_slots() const { return (int)impl_->free_idx.size(); }
 int Engine::active() const { return (int)impl_->active.size(); }
 void Engine::set_graphs(bool on) { impl_->graphs = on; }
+double Engine::host_task_seconds() const { return impl_->t_tasks; }
 int Engine::graph_replays() const { return impl_->replays; }
 
 void Engine::admit(const std::vector<SolveRequest>& reqs, const std::vector<int>& ids,
@@ -970,6 +989,10 @@ void Engine::admit(const std::vector<SolveRequest>& reqs, const std::vector<int>
       sl.dhat = sl.mem.as<double>(L.dhat);
       sl.xpart = sl.mem.as<double>(L.xpart);
       sl.scal = sl.mem.as<double>(L.scal);
+      sl.rscale = sl.mem.as<double>(L.rscale);
+      sl.Wv = sl.mem.as<double>(L.Wv);
+      sl.dpart = sl.mem.as<double>(L.dpart);
+      sl.cpart = sl.mem.as<double>(L.cpart);
       FDS_HIP(hipMemcpyAsync(sl.scal, sl.scal_init, sizeof(sl.scal_init), hipMemcpyHostToDevice, I.s));
     }
     sl.st = I.states.as<ProbState>() + sl.idx;

@@ -155,7 +155,7 @@ struct ProbState {
   int nonfinite;
   int ctr_dots;     // blocks of the current Gram-dot launch that finished
   int ctr_upd;      // blocks of the current update launch that finished
-  int pad_ctr;
+  int ctr_aux;      // blocks of the current interface-iteration cross-sum launch that finished
   double beta;      // true residual norm at the start of the current cycle
   double fnorm;     // ||f'_c||_2
   double tol;
@@ -428,12 +428,16 @@ struct IfaceTask {
 // the sine basis (corner entries of the per-mode tridiagonal inverses), and
 // between the two axes they are sums of 1/(lambda_x + lambda_y + kappa)
 // (the eigenvalues of A_c) against the sine values at the line positions.
-constexpr int kIkThreads = 1024;  // threads of the per-problem step kernels
-constexpr int kIkEPT = 9;         // coordinates per thread: 1 + lines <= 9216
+constexpr int kIkThreads = 1024;  // threads of the per-problem kernels (start, combine)
+constexpr int kIkEPT = 9;         // coordinates per thread there: 1 + lines <= 9216
 constexpr int kIkMaxCoords = kIkThreads * kIkEPT;
-constexpr int kIkGroup = 8;       // basis vectors per block reduction of the step's dots
+constexpr int kIkSlab = 1024;     // coordinates per block of the step kernels (256 threads x 4)
+constexpr int kIkSlabEPT = kIkSlab / kBlock;
+constexpr int kIkMaxSlabs = (kIkMaxCoords + kIkSlab - 1) / kIkSlab;
+constexpr int kIkGroup = 8;       // basis vectors per block reduction of the dots
 constexpr int kIkXThreads = 512;  // cross-axis sums: threads per block (8 wavefronts)
 constexpr int kIkXTile = 64;      // cross-axis sums: target modes per block (one per lane)
+constexpr int kIkXParts = 4;      // cross-axis sums: source ranges per target tile
 constexpr int kIkXStage = 1024;   // cross-axis sums: source modes staged in LDS at a time
 
 struct IkTask {
@@ -444,6 +448,7 @@ struct IkTask {
   double* g;
   double* y;
   double* G;                  // Gram columns <v_l, v_i>, column-major (m+1)^2
+  double* hv;                 // m+2: MGS coefficients of the current step (then its H column)
   double* Vb;                 // (m+1) x ldv coordinates
   int ldv, nb;                // row stride; sum of the present line lengths
   int m, flag_idx;
@@ -453,6 +458,7 @@ struct IkTask {
   int present;                // bit a: line a carries an arm (0 S, 1 N, 2 W, 3 E)
   int off[4];                 // coordinate offset of line a (after the [0] entry), -1 if absent
   int nxa, nya;               // cross blocks of direction x->y and y->x (0 if unused)
+  int nslab;                  // blocks of the step kernels (kIkSlab coordinates each)
   // plan tables
   const double* lamx;         // eigenvalues 2 delta (cos(k pi/(nx+1)) - 1)
   const double* lamy;
@@ -476,8 +482,13 @@ struct IkTask {
   double* ucoef;              // 1 + nb: coordinates of the cycle's update V y
   double* uphys;              // 2 x ny: W/E lines of the update, physical values
   double* dhat;               // nb: S A^{-1} of the unit interior residual
-  double* xpart;              // cross sums: [dir 2][acc 4][lmax]
-  double* scal;               // [0] eta, [1] 1/eta (0 if eta = 0), [2] beta, [3] 1.0
+  double* xpart;              // cross sums: [dir 2][acc 4][part kIkXParts][lmax]
+  double* rscale;             // m+1: factor that normalises stored basis vector i
+  double* Wv;                 // ldv: w of the current step
+  double* dpart;              // (2 (m+1) + 1) x nslab block partials of the step kernels
+  double* cpart;              // 4 x nxa: corner-value shares of the x->y cross blocks
+  double* scal;               // [0] eta, [1] 1/eta (0 if eta = 0), [2] beta, [3] 1.0, [4] update
+                              // factor of V0
   double* partials;           // >= P doubles: block sums of the interior residual
   int lmax;
   int block_begin;

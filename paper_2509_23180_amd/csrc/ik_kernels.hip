@@ -3,16 +3,19 @@
 // Right-preconditioned GMRES on L_c p_c = f'_c (paper Section 2.4) with the
 // basis kept in coordinates: the unit interior residual of the cycle plus
 // orthonormal sine coefficients on the lines that carry an arm.  One Arnoldi
-// step is two launches: the cross-axis sums of A_c^{-1} between x lines and
-// y lines (k_ik_cross, many blocks per problem for long lines), then one
-// workgroup per problem that forms w = v_j - S A_c^{-1} v_j, runs modified
-// Gram-Schmidt in its one-reduction form and the Givens update (k_ik_step).
-// The cycle start and end touch the whole centre: the interior residual is
-// split from the lines (k_ik_extract), sine-transformed and solved per mode
-// by the existing kernels, and k_ik_start turns the results into the first
-// basis vector and S A_c^{-1} of the interior residual; at the end the
-// update's coordinates (k_ik_combine) become sine coefficients along x
-// (k_ik_compose) for the per-mode solve and the inverse transform into x.
+// step is three launches: the cross-axis sums of A_c^{-1} between x lines
+// and y lines (k_ik_cross, whose last block also forms the corner values),
+// then two passes over the coordinates in blocks of kIkSlab: w = v_j - S
+// A_c^{-1} v_j with the dot products of modified Gram-Schmidt in its
+// one-reduction form (k_ik_wdots), and the update with the norm and the
+// Givens step (k_ik_update).  Stored basis vectors are not normalised in
+// place: rscale[i] holds the factor of vector i.  The cycle start and end
+// touch the whole centre: the interior residual is split from the lines
+// (k_ik_extract), sine-transformed and solved per mode by the existing
+// kernels, and k_ik_start turns the results into the first basis vector and
+// S A_c^{-1} of the interior residual; at the end the update's coordinates
+// (k_ik_combine) become sine coefficients along x (k_ik_compose) for the
+// per-mode solve and the inverse transform into x.
 #include "kernels.h"
 
 #include <algorithm>
@@ -219,6 +222,7 @@ __global__ void __launch_bounds__(kIkThreads) k_ik_start(const IkTask* __restric
   if (threadIdx.x == 0) {
     tk.g[0] = beta;
     tk.G[0] = 1.0;
+    tk.rscale[0] = 1.0;
     tk.scal[0] = eta;
     tk.scal[1] = inv_eta;
     tk.scal[2] = beta;
@@ -227,50 +231,114 @@ __global__ void __launch_bounds__(kIkThreads) k_ik_start(const IkTask* __restric
 
 // ---------------------------------------------------------------- Arnoldi step
 
+namespace {
+
+// Schur term of coordinate (line a, position i) of step j before the corner
+// correction: gd_a[i] (N/2) ((A^{-1} b)_a)_i with b = rs V_j: the same-axis
+// diagonal terms plus the cross sums over the source ranges.
+__device__ __forceinline__ double ik_raw_term(const IkTask& tk, const double* vj, double rs, int a, int i) {
+  const long long lm = tk.lmax;
+  auto ld = [](const double* p) { return *p; };
+  double ahat, cross = 0.0;
+  if (a < 2) {   // x line: same axis + sums from the y lines (direction y->x)
+    const double bS = tk.off[0] >= 0 ? vj[1 + tk.off[0] + i] : 0.0;
+    const double bN = tk.off[1] >= 0 ? vj[1 + tk.off[1] + i] : 0.0;
+    ahat = (a == 0 ? tk.t00[i] * bS + tk.t0n[i] * bN : tk.t0n[i] * bS + tk.t00[i] * bN) * rs;
+    if (tk.nya) {
+      const double* py = tk.xpart + 4LL * kIkXParts * lm;
+      const int k0 = a == 0 ? 0 : 2;
+      double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+      for (int p = 0; p < kIkXParts; ++p) {
+        c0 += ld(py + ((long long)k0 * kIkXParts + p) * lm + i);
+        c1 += ld(py + ((long long)(k0 + 1) * kIkXParts + p) * lm + i);
+      }
+      cross = tk.qx[i] * (c0 + sgn(i) * c1);
+    }
+  } else {       // y line: same axis + sums from the x lines (direction x->y)
+    const double bW = tk.off[2] >= 0 ? vj[1 + tk.off[2] + i] : 0.0;
+    const double bE = tk.off[3] >= 0 ? vj[1 + tk.off[3] + i] : 0.0;
+    ahat = (a == 2 ? tk.s00[i] * bW + tk.s0n[i] * bE : tk.s0n[i] * bW + tk.s00[i] * bE) * rs;
+    if (tk.nxa) {
+      const double* px = tk.xpart;
+      const int k0 = a == 2 ? 0 : 2;
+      double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+      for (int p = 0; p < kIkXParts; ++p) {
+        c0 += ld(px + ((long long)k0 * kIkXParts + p) * lm + i);
+        c1 += ld(px + ((long long)(k0 + 1) * kIkXParts + p) * lm + i);
+      }
+      cross = tk.qy[i] * (c0 + sgn(i) * c1);
+    }
+  }
+  return tk.gd[a][i] * tk.gscale[a] * (ahat + cross);
+}
+
+// Corner correction of a raw term (c: the four corner values of the W/E
+// terms, zero when one axis has no line).
+__device__ __forceinline__ double ik_corner(const IkTask& tk, const double* c, int a, int i, double sh) {
+  if (a >= 2) {
+    const int b = (a - 2) * 2;
+    const double w0 = tk.off[0] >= 0 ? 1.0 : 0.0, w1 = tk.off[1] >= 0 ? 1.0 : 0.0;
+    return sh - (w0 * c[b] * tk.qy[i] + w1 * c[b + 1] * sgn(i) * tk.qy[i]);
+  }
+  return sh + c[a] * tk.qx[i] + c[2 + a] * sgn(i) * tk.qx[i];
+}
+
+}  // namespace
+
 // Cross-axis sums of step j.  Direction x->y (sources on the S/N lines, x
 // modes k; targets on the W/E lines, y modes l):
 //   acc0[l] = sum_k R_lk qx_k b^S_k,          acc1[l] = sum_k R_lk qx_k b^N_k,
 //   acc2[l] = sum_k R_lk (-1)^k qx_k b^S_k,   acc3[l] = sum_k R_lk (-1)^k qx_k b^N_k,
-// R_lk = 1/(lamx_k + lamy_l + kappa); direction y->x the same with the roles
-// of the axes (and of S/N, W/E) exchanged.  A block covers kIkXTile targets,
-// one per lane; its wavefronts take the sources in turn (source s goes to
-// wavefront s mod 8, so each wavefront's sources share one parity and the
-// alternating sums follow from the per-wavefront sums), staged in LDS
-// kIkXStage at a time.  The eight partial sums are added in wavefront order.
+// R_lk = 1/(lamx_k + lamy_l + kappa), b = rscale_j V_j; direction y->x the
+// same with the axes (and S/N, W/E) exchanged.  A block covers kIkXTile
+// targets (one per lane) and one of kIkXParts source ranges; its
+// wavefronts take the range's sources in turn (source s to wavefront s mod
+// 8: one parity per wavefront, so the alternating sums follow from the
+// per-wavefront sums), staged in LDS.  Blocks of direction x->y also form
+// their shares of the corner values of the W/E lines' terms, which move to
+// the S/N lines that own those corners.
 __global__ void __launch_bounds__(kIkXThreads) k_ik_cross(const IkTask* __restrict__ tasks, int ntasks, int j) {
+  constexpr int kW = kIkXThreads / 64;
   __shared__ int slot;
   __shared__ double lam_s[kIkXStage], w0[kIkXStage], w1[kIkXStage];
-  __shared__ double red[2][kIkXThreads / 64][64];
+  __shared__ double red[2][kW][64];
   const IkTask& tk = tasks[find_task(tasks, ntasks, &slot)];
   if (tk.st->cycle_done) return;
+  const double rs = tk.rscale[j];
   int b = blockIdx.x - tk.block_begin;
   const bool xy = b < tk.nxa;
   if (!xy) b -= tk.nxa;
+  const int tile = b / kIkXParts, part = b - tile * kIkXParts;
   const int ns = xy ? tk.nx : tk.ny;
   const int nt = xy ? tk.ny : tk.nx;
   const double* lams = xy ? tk.lamx : tk.lamy;
   const double* lamt = xy ? tk.lamy : tk.lamx;
   const double* qs = xy ? tk.qx : tk.qy;
   const int oa = tk.off[xy ? 0 : 2], ob = tk.off[xy ? 1 : 3];
-  const double* v = tk.Vb + (long long)j * tk.ldv + 1;
+  const double* vj = tk.Vb + (long long)j * tk.ldv;
+  const double* v = vj + 1;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  constexpr int kW = kIkXThreads / 64;
-  const int t = b * kIkXTile + lane;
+  const int t = tile * kIkXTile + lane;
   const bool live = t < nt;
   const double lt = live ? lamt[t] : 0.0;
+  // this part's sources: an even start and length (a multiple of 8)
+  const int Q = ((ns + kIkXParts - 1) / kIkXParts + 7) / 8 * 8;
+  const int sa = part * Q, sb = min(ns, sa + Q);
   double a0 = 0.0, a1 = 0.0;
-  for (int c0 = 0; c0 < ns; c0 += kIkXStage) {
-    const int n = min(ns - c0, kIkXStage);
+  for (int c0 = sa; c0 < sb; c0 += kIkXStage) {
+    const int n = min(sb - c0, kIkXStage);
     __syncthreads();
     for (int s = threadIdx.x; s < n; s += kIkXThreads) {
       const int g = c0 + s;
       lam_s[s] = lams[g] + tk.kappa;
-      w0[s] = oa >= 0 ? qs[g] * v[oa + g] : 0.0;
-      w1[s] = ob >= 0 ? qs[g] * v[ob + g] : 0.0;
+      w0[s] = oa >= 0 ? qs[g] * v[oa + g] * rs : 0.0;
+      w1[s] = ob >= 0 ? qs[g] * v[ob + g] * rs : 0.0;
     }
     __syncthreads();
     if (live) {
-      // c0 is a multiple of kIkXStage (even): source c0 + s has the parity of s
+      // c0 is even: source c0 + s has the parity of s, which is wv's
       for (int s = wv; s < n; s += kW) {
         const double r = recip(lt + lam_s[s]);
         a0 += r * w0[s];
@@ -281,210 +349,290 @@ __global__ void __launch_bounds__(kIkXThreads) k_ik_cross(const IkTask* __restri
   red[0][wv][lane] = a0;
   red[1][wv][lane] = a1;
   __syncthreads();
-  if (wv != 0 || !live) return;
+  if (wv != 0) return;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (live) {
 #pragma unroll
-  for (int w = 0; w < kW; ++w) {
-    const double x = red[0][w][lane], y = red[1][w][lane];
-    s0 += x;
-    s1 += y;
-    if (w & 1) {
-      s2 -= x;
-      s3 -= y;
-    } else {
-      s2 += x;
-      s3 += y;
+    for (int w = 0; w < kW; ++w) {
+      const double x = red[0][w][lane], y = red[1][w][lane];
+      s0 += x;
+      s1 += y;
+      s2 += (w & 1) ? -x : x;
+      s3 += (w & 1) ? -y : y;
+    }
+    const long long lm = tk.lmax;
+    double* out = tk.xpart + (xy ? 0LL : 4LL * kIkXParts * lm);
+    out[(0LL * kIkXParts + part) * lm + t] = s0;
+    out[(1LL * kIkXParts + part) * lm + t] = s1;
+    out[(2LL * kIkXParts + part) * lm + t] = s2;
+    out[(3LL * kIkXParts + part) * lm + t] = s3;
+  }
+  if (!xy) return;
+  // This block's share of the four corner values of the W/E lines' terms
+  // (their values at y = 0 and y = ny-1: <term, qy> and <term, sigma qy>),
+  // which are linear in the cross sums: over its targets l, with the
+  // same-axis terms added by the blocks of the first source range.  The
+  // step kernels add the shares in block order.
+  double p[4] = {0.0, 0.0, 0.0, 0.0};
+  if (live) {
+    const int l = t;
+    const double q = tk.qy[l], sq = sgn(l) * q;
+    const double bW = tk.off[2] >= 0 ? v[tk.off[2] + l] * rs : 0.0;
+    const double bE = tk.off[3] >= 0 ? v[tk.off[3] + l] * rs : 0.0;
+    if (tk.off[2] >= 0) {
+      double term = q * (s0 + sgn(l) * s1);
+      if (part == 0) term += tk.s00[l] * bW + tk.s0n[l] * bE;
+      term *= tk.gd[2][l] * tk.gscale[2];
+      p[0] = term * q;
+      p[1] = term * sq;
+    }
+    if (tk.off[3] >= 0) {
+      double term = q * (s2 + sgn(l) * s3);
+      if (part == 0) term += tk.s0n[l] * bW + tk.s00[l] * bE;
+      term *= tk.gd[3][l] * tk.gscale[3];
+      p[2] = term * q;
+      p[3] = term * sq;
     }
   }
-  double* out = tk.xpart + (xy ? 0LL : 4LL * tk.lmax);
-  out[t] = s0;
-  out[tk.lmax + t] = s1;
-  out[2LL * tk.lmax + t] = s2;
-  out[3LL * tk.lmax + t] = s3;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) p[k] = wave_sum(p[k]);
+  if (lane == 0)
+    for (int k = 0; k < 4; ++k) tk.cpart[(long long)b * 4 + k] = p[k];
 }
 
-// One Arnoldi step of one problem (one workgroup): w = v_j - c0 dhat - S
-// A^{-1} b_j from the same-axis diagonal terms and the cross sums, the dots
-// <w, v_i> and the Gram column <v_j, v_i> in one pass, the MGS coefficients by
-// the recurrence h_i = <w, v_i> - sum_{l<i} h_l <v_l, v_i>, the update, the
-// norm, v_{j+1}, and the Givens update with the convergence test.
-template <int EPT, int GRP>
-__global__ void __launch_bounds__(kIkThreads) k_ik_step(const IkTask* __restrict__ tasks, int ntasks,
-                                                         int j, int* flags, int tag) {
-  __shared__ double gred[2 * GRP * kIkWaves];
-  __shared__ double cred[4 * kIkWaves];
-  __shared__ double av[122], gv[122], hv[122];
-  __shared__ double nred[kIkWaves];
-  const IkTask& tk = tasks[blockIdx.x];
+// Step j, first pass over the coordinates (kIkSlab per block): w = b_j -
+// c0 dhat - S A^{-1} b_j with b_j = rscale_j V_j (stored in Wv), and the
+// block's parts of <w, V_i> (i <= j) and <V_j, V_i> (i < j), kIkGroup basis
+// vectors at a time.  The problem's last block sums the parts in block
+// order, scales them to the normalised basis, stores the Gram column j and
+// runs the MGS recurrence h_i = <w, v_i> - sum_{l<i} h_l <v_l, v_i> (one-
+// reduction form of modified Gram-Schmidt) into hv.
+__global__ void __launch_bounds__(kBlock) k_ik_wdots(const IkTask* __restrict__ tasks, int ntasks, int j) {
+  constexpr int kW = kBlock / 64;
+  __shared__ int slot;
+  __shared__ int lastf;
+  __shared__ double gred[2 * kIkGroup][kW];
+  __shared__ double av[122], gv[122];
+  __shared__ double cv[4];
+  extern __shared__ __align__(16) double gt[];   // strict upper triangle of G, column i at i (i - 1) / 2
+  const IkTask& tk = tasks[find_task(tasks, ntasks, &slot)];
   ProbState* st = tk.st;
   if (st->cycle_done) return;
+  const int b = blockIdx.x - tk.block_begin;
   const int nco = 1 + tk.nb;
-  const int nx = tk.nx, ny = tk.ny;
   const int m1 = tk.m + 1;
+  const double rs = tk.rscale[j];
   const double* vj = tk.Vb + (long long)j * tk.ldv;
-  const double c0 = vj[0];
-  (void)ntasks;
-  const long long lm = tk.lmax;
-  const double* px = tk.xpart;            // direction x->y: sums for the W/E lines
-  const double* py = tk.xpart + 4 * lm;   // direction y->x: sums for the S/N lines
-  double vr[EPT], sh[EPT];
-  int line[EPT], pos[EPT];
+  const double c0 = rs * vj[0];
+  // corner values: the shares of the x->y cross blocks, summed by a fixed
+  // tree (thread t takes shares t/4, t/4 + 64, ... of corner t % 4; lanes of
+  // one corner are then combined by shuffles, the wavefronts in order)
+  {
+    const int cc = threadIdx.x & 3;
+    double v = 0.0;
+    for (int k = threadIdx.x >> 2; k < tk.nxa; k += kBlock / 4) v += tk.cpart[(long long)k * 4 + cc];
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int e = threadIdx.x + q * kIkThreads;
-    vr[q] = e < nco ? vj[e] : 0.0;
-    sh[q] = 0.0;
-    line[q] = -1;
-    pos[q] = 0;
-    if (e < 1 || e >= nco) continue;
-    const int a = ik_line_of(tk, e, &pos[q]);
-    line[q] = a;
-    const int i = pos[q];
-    double ahat;
-    if (a < 2) {   // x line: same-axis diagonal + sums from the y lines (direction y->x)
-      const double bS = tk.off[0] >= 0 ? vj[1 + tk.off[0] + i] : 0.0;
-      const double bN = tk.off[1] >= 0 ? vj[1 + tk.off[1] + i] : 0.0;
-      ahat = a == 0 ? tk.t00[i] * bS + tk.t0n[i] * bN : tk.t0n[i] * bS + tk.t00[i] * bN;
-      if (tk.nya) {
-        const int k0 = a == 0 ? 0 : 2;
-        ahat += tk.qx[i] * (py[k0 * lm + i] + sgn(i) * py[(k0 + 1) * lm + i]);
-      }
-    } else {       // y line
-      const double bW = tk.off[2] >= 0 ? vj[1 + tk.off[2] + i] : 0.0;
-      const double bE = tk.off[3] >= 0 ? vj[1 + tk.off[3] + i] : 0.0;
-      ahat = a == 2 ? tk.s00[i] * bW + tk.s0n[i] * bE : tk.s0n[i] * bW + tk.s00[i] * bE;
-      if (tk.nxa) {
-        const int k0 = a == 2 ? 0 : 2;
-        ahat += tk.qy[i] * (px[k0 * lm + i] + sgn(i) * px[(k0 + 1) * lm + i]);
-      }
+    for (int o = 4; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) < 4) gred[cc][threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      double sum = 0.0;
+      for (int w = 0; w < kW; ++w) sum += gred[threadIdx.x][w];
+      cv[threadIdx.x] = sum;
     }
-    sh[q] = tk.gd[a][i] * tk.gscale[a] * ahat;
+    __syncthreads();
   }
-  ik_corner_fix<EPT>(tk, sh, line, pos, cred);
-  double w[EPT];
+  double c[4];
+  for (int k = 0; k < 4; ++k) c[k] = cv[k];
+  double w[kIkSlabEPT], vr[kIkSlabEPT];
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int e = threadIdx.x + q * kIkThreads;
-    w[q] = e == 0 ? c0 : (e < nco ? vr[q] - c0 * tk.dhat[e - 1] - sh[q] : 0.0);
+  for (int q = 0; q < kIkSlabEPT; ++q) {
+    const int e = b * kIkSlab + q * kBlock + (int)threadIdx.x;
+    w[q] = 0.0;
+    vr[q] = 0.0;
+    if (e >= nco) continue;
+    vr[q] = vj[e];
+    if (e == 0) {
+      w[q] = c0;
+    } else {
+      int i = 0;
+      const int a = ik_line_of(tk, e, &i);
+      const double sh = ik_corner(tk, c, a, i, ik_raw_term(tk, vj, rs, a, i));
+      w[q] = rs * vr[q] - c0 * tk.dhat[e - 1] - sh;
+    }
+    tk.Wv[e] = w[q];
   }
-  // dots <w, v_i> (i <= j) and <v_j, v_i> (i < j), GRP basis vectors at
-  // a time: every thread accumulates the group's dots over its coordinates
-  // (all loads of a group independent), then one block reduction per group
-  // (wavefront sums, then the wavefronts in order)
   const int wv = threadIdx.x >> 6;
-  for (int i0 = 0; i0 <= j; i0 += GRP) {
-    double pa[GRP], pg[GRP];
+  const int nrow = 2 * m1;   // partial rows: <w, V_i> at i, <V_j, V_i> at m1 + i
+  for (int i0 = 0; i0 <= j; i0 += kIkGroup) {
+    double pa[kIkGroup], pg[kIkGroup];
 #pragma unroll
-    for (int g = 0; g < GRP; ++g) pa[g] = pg[g] = 0.0;
+    for (int g = 0; g < kIkGroup; ++g) pa[g] = pg[g] = 0.0;
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int e = threadIdx.x + q * kIkThreads;
+    for (int q = 0; q < kIkSlabEPT; ++q) {
+      const int e = b * kIkSlab + q * kBlock + (int)threadIdx.x;
+      const bool ok = e < nco;
 #pragma unroll
-      for (int g = 0; g < GRP; ++g) {
+      for (int g = 0; g < kIkGroup; ++g) {
         const int i = i0 + g;
-        const double x = (i <= j && e < nco) ? tk.Vb[(long long)i * tk.ldv + e] : 0.0;
+        const double x = (ok && i <= j) ? tk.Vb[(long long)i * tk.ldv + e] : 0.0;
         pa[g] += w[q] * x;
         pg[g] += vr[q] * x;
       }
     }
 #pragma unroll
-    for (int g = 0; g < GRP; ++g) {
+    for (int g = 0; g < kIkGroup; ++g) {
       pa[g] = wave_sum_last(pa[g]);
       pg[g] = wave_sum_last(pg[g]);
     }
     if ((threadIdx.x & 63) == 63) {
 #pragma unroll
-      for (int g = 0; g < GRP; ++g) {
-        gred[g * kIkWaves + wv] = pa[g];
-        gred[(GRP + g) * kIkWaves + wv] = pg[g];
+      for (int g = 0; g < kIkGroup; ++g) {
+        gred[g][wv] = pa[g];
+        gred[kIkGroup + g][wv] = pg[g];
       }
     }
     __syncthreads();
-    if (threadIdx.x < 2 * GRP) {
-      const int g = threadIdx.x % GRP;
+    if (threadIdx.x < 2 * kIkGroup) {
+      const int g = threadIdx.x % kIkGroup;
       const int i = i0 + g;
-      double sum = 0.0;
-      for (int k = 0; k < kIkWaves; ++k) sum += gred[threadIdx.x * kIkWaves + k];
       if (i <= j) {
-        if (threadIdx.x < GRP) av[i] = sum;
-        else gv[i] = sum;
+        double sum = 0.0;
+        for (int k = 0; k < kW; ++k) sum += gred[threadIdx.x][k];
+        const int row = threadIdx.x < kIkGroup ? i : m1 + i;
+        st_agent(tk.dpart + (long long)row * tk.nslab + b, sum);
       }
     }
     __syncthreads();
   }
-  for (int l = threadIdx.x; l < j; l += kIkThreads) tk.G[l + (long long)j * m1] = gv[l];
-  // MGS recurrence: h_i = a_i - sum_{l<i} h_l G_li, G_li = <v_l, v_i>
+  (void)nrow;
+  if (!last_block_of_problem(&st->ctr_dots, tk.nslab, &lastf)) return;
+  for (int t = threadIdx.x; t < 2 * (j + 1); t += kBlock) {
+    const int i = t <= j ? t : t - (j + 1);
+    const int row = t <= j ? i : m1 + i;
+    // all parts loaded before any is added (they arrive together)
+    double part[kIkMaxSlabs];
+#pragma unroll
+    for (int k = 0; k < kIkMaxSlabs; ++k)
+      part[k] = k < tk.nslab ? ld_agent(tk.dpart + (long long)row * tk.nslab + k) : 0.0;
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < kIkMaxSlabs; ++k) sum += part[k];
+    if (t <= j) av[i] = sum * tk.rscale[i];
+    else gv[i] = sum * tk.rscale[i] * rs;
+  }
+  // the earlier Gram columns (G_li, l < i < j) into LDS, column j from gv
+  const int ntri = j * (j + 1) / 2;
+  for (int e = threadIdx.x; e < ntri; e += kBlock) {
+    int i = (int)((1.0 + sqrt(1.0 + 8.0 * e)) * 0.5);
+    while (i * (i - 1) / 2 > e) --i;
+    while ((i + 1) * i / 2 <= e) ++i;
+    const int l = e - i * (i - 1) / 2;
+    gt[e] = i < j ? tk.G[l + (long long)i * m1] : 0.0;
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < j; l += kBlock) {
+    tk.G[l + (long long)j * m1] = gv[l];
+    gt[j * (j - 1) / 2 + l] = gv[l];
+  }
+  __syncthreads();
   if (j + 1 <= 64) {
     if (threadIdx.x < 64) {
       const int i = threadIdx.x;
       double ai = i <= j ? av[i] : 0.0;
       for (int l = 0; l < j; ++l) {
         const double hl = __shfl(ai, l, 64);
-        if (i > l && i <= j) ai -= hl * (i < j ? tk.G[l + (long long)i * m1] : gv[l]);
+        if (i > l && i <= j) ai -= hl * gt[i * (i - 1) / 2 + l];
       }
-      if (i <= j) hv[i] = ai;
+      if (i <= j) tk.hv[i] = ai;
     }
   } else {
     for (int l = 0; l <= j; ++l) {
       __syncthreads();
       const double hl = av[l];
-      for (int i = l + 1 + (int)threadIdx.x; i <= j; i += kIkThreads)
-        av[i] -= hl * (i < j ? tk.G[l + (long long)i * m1] : gv[l]);
+      for (int i = l + 1 + (int)threadIdx.x; i <= j; i += kBlock) av[i] -= hl * gt[i * (i - 1) / 2 + l];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i <= j; i += kIkThreads) hv[i] = av[i];
+    for (int i = threadIdx.x; i <= j; i += kBlock) tk.hv[i] = av[i];
+  }
+}
+
+// Step j, second pass: V_{j+1} = w - sum_i h_i rscale_i V_i (stored
+// unnormalised) with the block's part of ||V_{j+1}||^2; the problem's last
+// block forms h_{j+1,j}, the normalising factor rscale_{j+1}, the Givens
+// update of column j and the convergence test.
+__global__ void __launch_bounds__(kBlock) k_ik_update(const IkTask* __restrict__ tasks, int ntasks, int j,
+                                                       int* flags, int tag) {
+  __shared__ int slot;
+  __shared__ int lastf;
+  __shared__ double hs[122];
+  __shared__ double col[122], cs[121], sn[121];
+  __shared__ double red[4];
+  const IkTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  ProbState* st = tk.st;
+  if (st->cycle_done) return;
+  const int b = blockIdx.x - tk.block_begin;
+  const int nco = 1 + tk.nb;
+  const int m1 = tk.m + 1;
+  // the step's coefficients and the earlier rotations (read by every block,
+  // so the finishing block has them at hand)
+  for (int i = threadIdx.x; i <= j; i += kBlock) {
+    col[i] = tk.hv[i];
+    hs[i] = col[i] * tk.rscale[i];
+  }
+  for (int i = threadIdx.x; i < j; i += kBlock) {
+    cs[i] = tk.cs[i];
+    sn[i] = tk.sn[i];
   }
   __syncthreads();
-  // w -= sum_i h_i v_i, ||w||
-#pragma unroll 4
-  for (int i = 0; i <= j; ++i) {
-    const double* vi = tk.Vb + (long long)i * tk.ldv;
-    const double hi = hv[i];
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int e = threadIdx.x + q * kIkThreads;
-      if (e < nco) w[q] -= hi * vi[e];
-    }
-  }
+  double* vn = tk.Vb + (long long)(j + 1) * tk.ldv;
   double nn = 0.0;
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) nn += w[q] * w[q];
-  const double hn = sqrt(ik_block_sum(nn, nred));
-  const bool breakdown = !(hn > 1e-14 * st->beta);
-  const double inv = breakdown ? 1.0 : 1.0 / hn;
-  if (j + 1 <= tk.m) {
-    double* vn = tk.Vb + (long long)(j + 1) * tk.ldv;
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int e = threadIdx.x + q * kIkThreads;
-      if (e < nco) vn[e] = w[q] * inv;
-    }
+  for (int q = 0; q < kIkSlabEPT; ++q) {
+    const int e = b * kIkSlab + q * kBlock + (int)threadIdx.x;
+    if (e >= nco) continue;
+    double x = tk.Wv[e];
+#pragma unroll 4
+    for (int i = 0; i <= j; ++i) x -= hs[i] * tk.Vb[(long long)i * tk.ldv + e];
+    vn[e] = x;
+    nn += x * x;
   }
+  const double s = block_sum(nn, red);
+  if (threadIdx.x == 0) st_agent(tk.dpart + (long long)2 * m1 * tk.nslab + b, s);
+  if (!last_block_of_problem(&st->ctr_upd, tk.nslab, &lastf)) return;
   if (threadIdx.x != 0) return;
-  // Givens update of column j (rotations of the previous columns, then a new
-  // one), in place in hv
-  double* col = hv;
-  col[j + 1] = hn;
+  double part[kIkMaxSlabs];
+#pragma unroll
+  for (int k = 0; k < kIkMaxSlabs; ++k)
+    part[k] = k < tk.nslab ? ld_agent(tk.dpart + (long long)2 * m1 * tk.nslab + k) : 0.0;
+  double n2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < kIkMaxSlabs; ++k) n2 += part[k];
+  const double hn = sqrt(n2);
+  const bool breakdown = !(hn > 1e-14 * st->beta);
+  tk.rscale[j + 1] = breakdown ? 1.0 : 1.0 / hn;
   st->last_hn = hn;
+  // Givens update of column j (in LDS): the previous rotations, then a new one
+  col[j + 1] = hn;
   for (int i = 0; i < j; ++i) {
     const double a = col[i], c2 = col[i + 1];
-    col[i] = tk.cs[i] * a + tk.sn[i] * c2;
-    col[i + 1] = -tk.sn[i] * a + tk.cs[i] * c2;
+    col[i] = cs[i] * a + sn[i] * c2;
+    col[i + 1] = -sn[i] * a + cs[i] * c2;
   }
   const double a = col[j];
   const double rho = hypot(a, hn);
-  double c = 1.0, s = 0.0;
+  double c = 1.0, s1 = 0.0;
   if (rho > 0.0) {
     c = a / rho;
-    s = hn / rho;
+    s1 = hn / rho;
   }
   tk.cs[j] = c;
-  tk.sn[j] = s;
+  tk.sn[j] = s1;
   col[j] = rho;
   col[j + 1] = 0.0;
   for (int i = 0; i <= j + 1; ++i) tk.H[i + (long long)j * m1] = col[i];
   const double gj = tk.g[j];
-  tk.g[j + 1] = -s * gj;
+  tk.g[j + 1] = -s1 * gj;
   tk.g[j] = c * gj;
   st->j_done = j + 1;
   st->iterations += 1;
@@ -496,8 +644,6 @@ __global__ void __launch_bounds__(kIkThreads) k_ik_step(const IkTask* __restrict
       __threadfence_system();
     }
   }
-  (void)nx;
-  (void)ny;
 }
 
 // ---------------------------------------------------------------- cycle end
@@ -509,7 +655,7 @@ __global__ void __launch_bounds__(kIkThreads) k_ik_combine(const IkTask* __restr
   const IkTask& tk = tasks[blockIdx.x];
   if (tk.st->finished) return;
   const int k = tk.st->j_done;
-  for (int i = threadIdx.x; i < k; i += kIkThreads) ys[i] = tk.y[i];
+  for (int i = threadIdx.x; i < k; i += kIkThreads) ys[i] = tk.y[i] * tk.rscale[i];
   __syncthreads();
   const int nco = 1 + tk.nb;
   for (int e = threadIdx.x; e < nco; e += kIkThreads) {
@@ -582,14 +728,14 @@ void launch_ik_cross(const IkTask* tasks, int ntasks, int nblocks, int j, hipStr
   FDS_LAUNCH(k_ik_cross, dim3(nblocks), dim3(kIkXThreads), 0, s, tasks, ntasks, j);
 }
 
-void launch_ik_step(const IkTask* tasks, int ntasks, int max_coords, int j, int* flags, int tag,
+void launch_ik_step(const IkTask* tasks, int ntasks, int nblocks, int j, int* flags, int tag,
                     hipStream_t s) {
-  if (ntasks <= 0) return;
-  switch (ik_ept(max_coords)) {
-    case 2: FDS_LAUNCH((k_ik_step<2, 8>), dim3(ntasks), dim3(kIkThreads), 0, s, tasks, ntasks, j, flags, tag); break;
-    case 4: FDS_LAUNCH((k_ik_step<4, 8>), dim3(ntasks), dim3(kIkThreads), 0, s, tasks, ntasks, j, flags, tag); break;
-    default: FDS_LAUNCH((k_ik_step<kIkEPT, 4>), dim3(ntasks), dim3(kIkThreads), 0, s, tasks, ntasks, j, flags, tag); break;
-  }
+  if (nblocks <= 0) return;
+  const size_t smem = sizeof(double) * std::max<size_t>(1, (size_t)j * (j + 1) / 2);
+  static size_t granted = 0;
+  ensure_smem(k_ik_wdots, smem + 8192, &granted);
+  FDS_LAUNCH(k_ik_wdots, dim3(nblocks), dim3(kBlock), smem, s, tasks, ntasks, j);
+  FDS_LAUNCH(k_ik_update, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
 }
 
 void launch_ik_combine(const IkTask* tasks, int ntasks, hipStream_t s) {

@@ -103,7 +103,8 @@ void launch_ik_extract(const IkTask* tasks, int ntasks, int nblocks, hipStream_t
 // max_coords: the largest 1 + nb of the launch's problems
 void launch_ik_start(const IkTask* tasks, int ntasks, int max_coords, hipStream_t s);
 void launch_ik_cross(const IkTask* tasks, int ntasks, int nblocks, int j, hipStream_t s);
-void launch_ik_step(const IkTask* tasks, int ntasks, int max_coords, int j, int* flags, int tag,
+// The two coordinate passes of step j (nblocks: kIkSlab-coordinate blocks).
+void launch_ik_step(const IkTask* tasks, int ntasks, int nblocks, int j, int* flags, int tag,
                     hipStream_t s);
 void launch_ik_combine(const IkTask* tasks, int ntasks, hipStream_t s);
 void launch_ik_compose(const IkTask* tasks, int ntasks, int nblocks, hipStream_t s);

@@ -659,21 +659,6 @@ __device__ __forceinline__ double spec_w(const KryTask& tk, int j, long long idx
   return w;
 }
 
-// The last block of a problem to finish a launch does the problem's serial
-// work (partials are added in a fixed order, so the result does not depend
-// on which block is last).  Partials that another block of the same launch
-// reads are stored and loaded as agent-scope relaxed atomics, which the
-// memory model keeps coherent across the XCDs' L2 caches; a device-wide fence
-// would instead write back and invalidate the whole L2 in every block.  Each
-// block waits for its stores to complete, then counts itself in; the last
-// block resets the counter for the next launch.
-__device__ __forceinline__ void st_agent(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double ld_agent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Row sums out[d] = sum_{q < ncols} src[d * ld + q] for d < D <= blockDim.x,
 // with the whole block: each row is cut into C = blockDim.x / D contiguous
 // chunks whose loads are issued eight at a time, and the chunk sums are added
@@ -711,19 +696,6 @@ __device__ void reduce_rows(const double* src, long long ld, int D, int ncols, d
     out[e] = t;
   }
   __syncthreads();
-}
-
-__device__ __forceinline__ bool last_block_of_problem(int* ctr, int nblocks, int* sflag) {
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int old = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int last = (old == nblocks - 1) ? 1 : 0;
-    if (last) __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    *sflag = last;
-  }
-  __syncthreads();
-  return *sflag != 0;
 }
 
 __device__ void gram_recur(const KryTask& tk, int j, double* lds);

@@ -92,7 +92,7 @@ constexpr int kDenseLineMax = 1024;
 bool dense_lines(int n);
 
 // Process-wide cache of device tables (per device), keyed by length and by
-// (length, rows, h, kappa).  Entries live until process exit.
+// (length, rows, h, kappa).  Transform tables live until process exit.
 class TableCache {
  public:
   static TableCache& get();
@@ -109,8 +109,12 @@ class TableCache {
   std::mutex mu_;
   std::map<std::pair<int, int>, std::shared_ptr<FftTable>> fft_;
   std::map<const FftDesc*, std::shared_ptr<FftTable>> by_dev_;
-  std::map<std::tuple<int, int, int, double, double, bool>, std::shared_ptr<ModeTable>> modes_;
-  std::map<std::tuple<int, int, int, double, double, bool>, std::shared_ptr<GsTable>> gs_;
+  // kappa-dependent tables are held by the plans that use them: the cache
+  // only finds a live one again, so a stream of requests with continuous
+  // kappa does not keep every table ever built (their memory returns to the
+  // device-memory cache when the last plan using them is destroyed)
+  std::map<std::tuple<int, int, int, double, double, bool>, std::weak_ptr<ModeTable>> modes_;
+  std::map<std::tuple<int, int, int, double, double, bool>, std::weak_ptr<GsTable>> gs_;
 };
 
 // Tables of the interface Krylov iteration for an nx x ny centre (IkTask):
@@ -271,6 +275,8 @@ class Engine {
   // kernel by kernel.  On by default; FDS_GRAPH=0 turns it off.
   void set_graphs(bool on);
   int graph_replays() const;
+  // Host seconds spent rebuilding task lists after the set changed.
+  double host_task_seconds() const;
   // Problems that finished (converged, stalled, failed or out of cycles).
   std::vector<int> finished_ids() const;
   // Back substitution and output of the given problems; frees their memory.

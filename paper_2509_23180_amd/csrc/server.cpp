@@ -71,6 +71,7 @@ struct fds_server {
   size_t used = 0;
   int running = 0;
   int next_id = 0;
+  double tasks_base = 0;   // task-list seconds of engines already destroyed
 
   void run();
   void admit_from_queue();
@@ -113,6 +114,7 @@ void fds_server::fail_group(fds::Group& g, fds_status st) {
     --running;
   }
   g.running.clear();
+  if (g.eng) tasks_base += g.eng->host_task_seconds();
   g.eng.reset();   // its state is unknown after a failure
   g.launched = false;
 }
@@ -183,20 +185,27 @@ void fds_server::admit_from_queue() {
 
 void fds_server::run() {
   (void)hipSetDevice(device);
+  using fds::Clock;
+  auto secs = [](Clock::time_point a) { return std::chrono::duration<double>(Clock::now() - a).count(); };
   while (true) {
     {
       std::unique_lock<std::mutex> lk(mu);
       cv.wait(lk, [&] { return stop || !queue.empty() || running > 0; });
       if (stop && queue.empty() && running == 0) return;
     }
+    double t_admit = 0, t_launch = 0, t_wait = 0, t_retire = 0;
+    auto t0 = Clock::now();
     admit_from_queue();
+    t_admit = secs(t0);
     // queue one cycle of every group, then wait for each in turn
     for (auto& kv : groups) {
       fds::Group& g = kv.second;
       g.launched = false;
       if (!g.eng || g.running.empty()) continue;
       try {
+        t0 = Clock::now();
         g.launched = g.eng->cycle_launch();
+        t_launch += secs(t0);
       } catch (const fds::Error& e) {
         fail_group(g, e.status);
       }
@@ -206,12 +215,17 @@ void fds_server::run() {
       fds::Group& g = kv.second;
       if (!g.eng || !g.launched) continue;
       try {
+        t0 = Clock::now();
         g.eng->cycle_finish();
+        t_wait += secs(t0);
         g.launched = false;
         ++cycles;
         const std::vector<int> fin = g.eng->finished_ids();
         if (fin.empty()) continue;
-        for (auto& pr : g.eng->retire(fin)) {
+        t0 = Clock::now();
+        auto retired = g.eng->retire(fin);
+        t_retire += secs(t0);
+        for (auto& pr : retired) {
           auto it = g.running.find(pr.first);
           if (it == g.running.end()) continue;
           publish(it->second, pr.second.res);
@@ -223,9 +237,17 @@ void fds_server::run() {
         fail_group(g, e.status);
       }
     }
+    double t_tasks = 0;
+    for (auto& kv : groups)
+      if (kv.second.eng) t_tasks += kv.second.eng->host_task_seconds();
     std::lock_guard<std::mutex> lk(mu);
     stats.cycles += cycles;
     stats.bytes_in_use = used;
+    stats.host_admit_s += t_admit;
+    stats.host_retire_s += t_retire;
+    stats.host_launch_s += t_launch;
+    stats.host_wait_s += t_wait;
+    stats.host_tasks_s = tasks_base + t_tasks;
   }
 }
 

@@ -471,10 +471,15 @@ static ShapeTables shape_tables(const FftShape& shp, int N) {
 
 std::shared_ptr<FftTable> TableCache::fft(int n) {
   const int dev = current_device();
-  std::lock_guard<std::mutex> lk(mu_);
   auto key = std::make_pair(dev, n);
-  auto it = fft_.find(key);
-  if (it != fft_.end()) return it->second;
+  {
+    // the lock covers the lookups and the insertion only: building and
+    // uploading a table runs unlocked, so threads that build plans do not
+    // stall threads that only look tables up
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = fft_.find(key);
+    if (it != fft_.end()) return it->second;
+  }
   const int N = n + 1;
   const FftShape shp = fft_shape(n);
   const int L = shp.L;
@@ -636,6 +641,9 @@ std::shared_ptr<FftTable> TableCache::fft(int n) {
   upload(t->mem.get(), host.data(), total);
   t->host = d;
   t->dev = t->mem.as<FftDesc>(0);
+  std::lock_guard<std::mutex> lk(mu_);
+  auto it = fft_.find(key);
+  if (it != fft_.end()) return it->second;   // built meanwhile by another thread
   fft_[key] = t;
   by_dev_[t->dev] = t;
   return t;
@@ -712,14 +720,25 @@ std::shared_ptr<ModeTable> upload_modes(const std::vector<ModeCoef<double>>& c64
 
 std::shared_ptr<ModeTable> TableCache::modes(int n, int m, double h, double kappa, bool unit) {
   const int dev = current_device();
-  std::lock_guard<std::mutex> lk(mu_);
   auto key = std::make_tuple(dev, n, m, h, kappa, unit);
-  auto it = modes_.find(key);
-  if (it != modes_.end()) return it->second;
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = modes_.find(key);
+    if (it != modes_.end()) {
+      if (auto live = it->second.lock()) return live;
+      modes_.erase(it);
+    }
+  }
   std::vector<ModeCoef<double>> c64;
   std::vector<ModeCoef<float>> c32;
   mode_coefs_host(n, m, h, kappa, unit ? 1.0 : 2.0 / (n + 1), c64, c32);
   auto t = upload_modes(c64, c32);
+  std::lock_guard<std::mutex> lk(mu_);
+  auto it = modes_.find(key);
+  if (it != modes_.end())
+    if (auto live = it->second.lock()) return live;
+  if (modes_.size() > 4096)   // drop the keys of tables no plan holds any more
+    for (auto i = modes_.begin(); i != modes_.end();) i = i->second.expired() ? modes_.erase(i) : std::next(i);
   modes_[key] = t;
   return t;
 }
@@ -730,10 +749,15 @@ std::shared_ptr<ModeTable> TableCache::modes(int n, int m, double h, double kapp
 // stored as delta^2 (2/N) g_k.
 std::shared_ptr<GsTable> TableCache::gs(int n, int m, double h, double kappa, bool want_dense) {
   const int dev = current_device();
-  std::lock_guard<std::mutex> lk(mu_);
   auto key = std::make_tuple(dev, n, m, h, kappa, want_dense);
-  auto it = gs_.find(key);
-  if (it != gs_.end()) return it->second;
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = gs_.find(key);
+    if (it != gs_.end()) {
+      if (auto live = it->second.lock()) return live;
+      gs_.erase(it);
+    }
+  }
   const int N = n + 1;
   const double delta = 1.0 / (h * h);
   std::vector<double> v(n);
@@ -773,6 +797,12 @@ std::shared_ptr<GsTable> TableCache::gs(int n, int m, double h, double kappa, bo
   if (dense) {
     t->mfull = t->gs + n;
   }
+  std::lock_guard<std::mutex> lk(mu_);
+  auto it = gs_.find(key);
+  if (it != gs_.end())
+    if (auto live = it->second.lock()) return live;
+  if (gs_.size() > 4096)
+    for (auto i = gs_.begin(); i != gs_.end();) i = i->second.expired() ? gs_.erase(i) : std::next(i);
   gs_[key] = t;
   return t;
 }
@@ -790,7 +820,7 @@ static void corner_inverse(double theta, int m, double delta, double* t11, doubl
 
 std::shared_ptr<IkPlanTable> build_ik_table(int nx, int ny, double h, double kappa) {
   const double delta = 1.0 / (h * h);
-  const long double pi = kPi;
+  const double pi = 3.14159265358979323846;
   std::vector<double> host(4 * (size_t)nx + 4 * (size_t)ny);
   double* lamx = host.data();
   double* qx = lamx + nx;
@@ -800,15 +830,20 @@ std::shared_ptr<IkPlanTable> build_ik_table(int nx, int ny, double h, double kap
   double* qy = lamy + ny;
   double* s00 = qy + ny;
   double* s0n = s00 + ny;
+  // double-precision closed forms (relative errors of a few units in the
+  // last place); theta from cosh(theta) = 1 + u, u = 2 sin^2(k pi/(2N)) -
+  // kappa/(2 delta), without cancellation
   auto axis = [&](int n, int m, double* lam, double* q, double* c11, double* c1m) {
     const int N = n + 1;
+    const double sq = std::sqrt(2.0 / N);
     for (int k = 1; k <= n; ++k) {
-      const long double sh = sinl(pi * (long double)k / (2.0L * N));
-      lam[k - 1] = (double)(-4.0L * (long double)delta * sh * sh);   // 2 delta (cos(k pi/N) - 1)
-      q[k - 1] = (double)(sqrtl(2.0L / N) * sinl(pi * (long double)k / N));
-      double th;
-      if (!mode_theta(k, N, delta, kappa, &th))
+      const double sh = std::sin(pi * k / (2.0 * N));
+      lam[k - 1] = -4.0 * delta * sh * sh;   // 2 delta (cos(k pi/N) - 1)
+      q[k - 1] = sq * std::sin(pi * k / N);
+      const double u = 2.0 * sh * sh - kappa / (2.0 * delta);
+      if (!(u > 0.0))
         throw Error(FDS_E_UNSUPPORTED, "kappa makes a sine mode oscillatory (not diagonally dominant)");
+      const double th = std::log1p(u + std::sqrt(u * (u + 2.0)));
       corner_inverse(th, m, delta, &c11[k - 1], &c1m[k - 1]);
     }
   };
