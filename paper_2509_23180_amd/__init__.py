@@ -14,7 +14,8 @@ from dataclasses import dataclass
 from typing import List, Optional, Sequence, Tuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfds.so")
+# FDS_LIB selects another build of the library (e.g. a build variant)
+LIB_PATH = os.environ.get("FDS_LIB") or os.path.join(HERE, "libfds.so")
 
 FDS_OK = 0
 FDS_PENDING = 1

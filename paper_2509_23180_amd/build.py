@@ -15,8 +15,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
-OUT = os.path.join(HERE, "libfds.so")
-BUILD_DIR = os.path.join(ROOT, "_build")
+# FDS_BUILD_OUT / FDS_BUILD_DIR / FDS_BUILD_DEFINES (development only) build a
+# variant library elsewhere, e.g. with -DFDS_HANDOFF_FENCED
+OUT = os.environ.get("FDS_BUILD_OUT", os.path.join(HERE, "libfds.so"))
+BUILD_DIR = os.environ.get("FDS_BUILD_DIR", os.path.join(ROOT, "_build"))
+DEFINES = os.environ.get("FDS_BUILD_DEFINES", "").split()
 
 SOURCES = ["kernels.hip", "dst_wave.hip", "ik_kernels.hip", "alloc.cpp", "tune.cpp", "tables.cpp", "plan.cpp", "engine.cpp", "server.cpp", "abi.cpp"]
 ARCH = os.environ.get("FDS_OFFLOAD_ARCH", "gfx950")
@@ -31,7 +34,7 @@ def hipcc() -> str:
 
 def _flags(src: str):
     f = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
-         f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
+         f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}", *DEFINES]
     if src.endswith(".hip"):
         f += ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
               "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics"]

@@ -343,6 +343,34 @@ __device__ __forceinline__ double ld_agent(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+#if defined(FDS_HANDOFF_FENCED)
+// Release/acquire form (build option): the block's stores are ordered before
+// the counter increment by a workgroup barrier and an agent-scope release on
+// the increment; the last block takes an agent-scope acquire before it reads.
+// On gfx950 the release writes back the XCD's L2 and the acquire invalidates
+// it, which the relaxed form below avoids.
+__device__ __forceinline__ bool last_block_of_problem(int* ctr, int nblocks, int* sflag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int old = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const int last = (old == nblocks - 1) ? 1 : 0;
+    if (last) __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *sflag = last;
+  }
+  __syncthreads();
+  const bool last = *sflag != 0;
+  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return last;
+}
+#else
+// Relaxed form (default).  Ordering without fences: (1) every partial is an
+// agent-scope atomic store, which gfx950 writes through to the coherent level
+// past the XCD's L2; (2) `s_waitcnt vmcnt(0)` waits until those stores have
+// completed, and its "memory" clobber, like the barrier after it, keeps the
+// compiler from moving any memory access across; (3) only then does thread 0
+// increment the counter; (4) the last block issues its agent-scope atomic
+// loads of the partials after the increment has returned, behind a barrier,
+// so they cannot be hoisted above it and they bypass the non-coherent L2.
 __device__ __forceinline__ bool last_block_of_problem(int* ctr, int nblocks, int* sflag) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
@@ -355,6 +383,7 @@ __device__ __forceinline__ bool last_block_of_problem(int* ctr, int nblocks, int
   __syncthreads();
   return *sflag != 0;
 }
+#endif
 
 // ---------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
