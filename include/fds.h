@@ -94,9 +94,13 @@ typedef enum {
   FDS_FP32_PRECOND = 1,       /* FP32 sine transforms + tridiagonal solves  */
                               /* inside flexible GMRES; FP64 Gram-Schmidt,  */
                               /* Givens, operator, true residual, update    */
-  FDS_NO_PRECOND = 2          /* no preconditioner (P = I, Section 3.2's    */
+  FDS_NO_PRECOND = 2,         /* no preconditioner (P = I, Section 3.2's    */
                               /* baseline): flexible GMRES with z = v       */
                               /* stored in FP32; for convergence studies    */
+  FDS_JACOBI = 3              /* Jacobi preconditioner P = diag(L_c), the   */
+                              /* diagonal of the Schur-reduced operator     */
+                              /* (Section 3.2's second baseline): flexible  */
+                              /* GMRES with z = P^-1 v stored in FP32       */
 } fds_precision;
 
 typedef enum {

@@ -96,6 +96,27 @@ class SchurOperator:
             return np.zeros(0)
         return self.Arr_lu.solve(self.P.b[self.P.rest] - self.Arc @ pc)
 
+    def jacobi_diagonal(self):
+        """diag(L_c) = diag(A_cc) - diag(S) (Section 3.2's Jacobi
+        preconditioner), from the assembled blocks: S e_b is nonzero only for
+        the centre nodes b that couple to another subdomain, so one solve per
+        such node gives diag(S)."""
+        d = np.asarray(self.Acc.diagonal(), dtype=np.float64).copy()
+        if self.Acr is None:
+            return d
+        Arc = self.Arc.tocsc()
+        B = np.flatnonzero(np.diff(Arc.indptr))
+        if B.size:
+            X = self.Arr_lu.solve(Arc[:, B].toarray())
+            Y = self.Acr[B, :] @ X
+            d[B] -= np.diag(np.asarray(Y))
+        return d
+
+    def apply_Jinv(self, v):
+        if not hasattr(self, "_jd"):
+            self._jd = self.jacobi_diagonal()
+        return np.asarray(v, dtype=np.float64) / self._jd
+
     def dense_L(self):
         n = self.Acc.shape[0]
         return np.column_stack([self.apply_L(e) for e in np.eye(n)])

@@ -29,6 +29,7 @@ BC_PERIODIC = 2
 FP64 = 0
 FP32_PRECOND = 1
 NO_PRECOND = 2       # P = I: the convergence baseline (flexible GMRES, z = v in FP32)
+JACOBI = 3           # P = diag(L_c): the second baseline (flexible GMRES, z = P^-1 v in FP32)
 STOP = {0: "none", 1: "tol", 2: "at_floor", 3: "max_cycles", 4: "stagnation"}
 
 TIMING_CLASSES = {"dst": 0, "tridiag": 1, "operator": 2, "gram_dots": 3, "lines": 4, "other": 5,

@@ -297,6 +297,10 @@ struct TaskSet {
   int lmax_dense = 0;
   size_t smem_lines = 0;
   TaskList<ColTask> it_cols;
+  // Jacobi preconditioner: z^ = Q D^-1 Q^T v^ (inverse transform, diagonal
+  // scaling, forward transform; z^ = v^ is first written to Z_j in FP32)
+  DstStage it_jinv{DstKind::F_D}, it_jfwd{DstKind::D_F};
+  TaskList<CopyTask> it_jdiag;
   TaskList<OpTask> res_op;
   TaskList<KryTask> kry;
   TaskList<LiftTask> lift, gather;
@@ -325,7 +329,9 @@ struct TaskSet {
   void ik_cycle_start(hipStream_t s) const;
   void add_problem(Problem& sl);
   void upload(hipStream_t s) {
-    for (DstStage* d : {&cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd, &ik_lfwd, &ik_linv}) d->stage(blob);
+    for (DstStage* d : {&cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd, &ik_lfwd, &ik_linv, &it_jinv, &it_jfwd})
+      d->stage(blob);
+    blob.add(it_jdiag);
     for (TriStage* t : {&it_tri, &cyc_tri, &arm_tri, &ik_tri0}) t->stage(blob);
     blob.add(ik_p);
     blob.add(ik_s);
@@ -387,8 +393,24 @@ void TaskSet::add_problem(Problem& sl) {
     tt.coef = flex ? (const void*)p->modes_cu->c32 : (const void*)p->modes_cu->c64;
     tt.skip = skip_it;
     tt.vin = sl.V; tt.vjs = Nc; tt.vscale = &sl.st->vscale;
-    tt.identity = p->opt.precision == FDS_NO_PRECOND ? 1 : 0;   // z^ = v^ (P = I)
+    const bool jacobi = p->opt.precision == FDS_JACOBI;
+    tt.identity = (p->opt.precision == FDS_NO_PRECOND || jacobi) ? 1 : 0;   // z^ = v^ (P = I)
     it_tri.add(tt);
+    if (jacobi) {
+      DstTask a{};
+      a.in = sl.Z; a.in_rs = nx; a.in_cs = 1; a.in_js = Nc;
+      a.out = sl.tmpd; a.out_rs = nx; a.out_cs = 1;
+      a.rows = ny; a.n = nx; a.scale = qscale; a.fft = fftc; a.skip = skip_it;
+      it_jinv.add(a);
+      const int nb = std::max(1, div_up(Nc, (long long)kBlock * 8));
+      CopyTask c{sl.tmpd, sl.tmpd, Nc, 0, nb, p->jacobi->dinv, skip_it};
+      add_block_task(it_jdiag, c, nb);
+      DstTask b{};
+      b.in = sl.tmpd; b.in_rs = nx; b.in_cs = 1;
+      b.out = sl.Z; b.out_rs = nx; b.out_cs = 1; b.out_js = Nc;
+      b.rows = ny; b.n = nx; b.scale = qscale; b.fft = fftc; b.skip = skip_it;
+      it_jfwd.add(b);
+    }
     if (west || east) {
       ColTask ct{};
       if (flex) { ct.y32 = sl.Z; ct.y_js = Nc; }
@@ -692,6 +714,13 @@ void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
   Timing::begin(1, s);
   it_tri.launch(s, j);
   Timing::end(1, s);
+  if (it_jdiag.n()) {
+    Timing::begin(0, s);
+    it_jinv.launch(j, s);
+    launch_copy(it_jdiag.dev(), it_jdiag.n(), it_jdiag.nblocks, s);
+    it_jfwd.launch(j, s);
+    Timing::end(0, s);
+  }
   if (it_cols.n()) {
     Timing::begin(7, s);
     launch_idst_cols(it_cols.dev(), it_cols.n(), it_cols.nblocks, j, s);

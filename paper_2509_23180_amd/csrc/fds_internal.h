@@ -389,10 +389,12 @@ struct ResSumTask {
 // dst[0..count) = src[0..count), or 0 when src is null.
 struct CopyTask {
   double* dst;
-  const double* src;
+  const double* src;          // null: zero fill
   long long count;
   int block_begin;
   int nblocks;
+  const double* mul;          // if set: dst = src * mul, element by element
+  const int* skip;            // skip when *skip != 0
 };
 
 // Interface right-hand side updates between the centre and its arms of one

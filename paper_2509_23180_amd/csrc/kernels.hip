@@ -1443,14 +1443,17 @@ __global__ void __launch_bounds__(kBlock) k_res_sum(const ResSumTask* __restrict
   }
 }
 
-// Copies and zero fills of whole vectors, batched over problems.
+// Copies, zero fills and diagonal scalings of whole vectors, batched over
+// problems.
 __global__ void __launch_bounds__(kBlock) k_copy(const CopyTask* __restrict__ tasks, int ntasks) {
   __shared__ int slot;
   const CopyTask& tk = tasks[find_task(tasks, ntasks, &slot)];
+  if (tk.skip && *tk.skip) return;
   const long long stride = (long long)tk.nblocks * kBlock;
+  const double* mul = tk.mul;
   for (long long e = (long long)(blockIdx.x - tk.block_begin) * kBlock + threadIdx.x; e < tk.count;
        e += stride)
-    tk.dst[e] = tk.src ? tk.src[e] : 0.0;
+    tk.dst[e] = tk.src ? (mul ? tk.src[e] * mul[e] : tk.src[e]) : 0.0;
 }
 
 // Number of problems whose current cycle is still running.

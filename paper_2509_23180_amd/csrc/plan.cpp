@@ -38,7 +38,8 @@ fds_plan* create_plan(const fds_rect* rects, int nrect, double h, double kappa,
   if (opt) o = *opt;
   if (o.restart_m < 1 || o.restart_m > 120) throw Error(FDS_E_INVALID_ARG, "restart_m must be in 1..120");
   if (o.max_cycles < 1) throw Error(FDS_E_INVALID_ARG, "max_cycles must be >= 1");
-  if (o.precision != FDS_FP64 && o.precision != FDS_FP32_PRECOND && o.precision != FDS_NO_PRECOND)
+  if (o.precision != FDS_FP64 && o.precision != FDS_FP32_PRECOND && o.precision != FDS_NO_PRECOND &&
+      o.precision != FDS_JACOBI)
     throw Error(FDS_E_INVALID_ARG, "unknown precision");
   if (o.flags & ~(uint32_t)FDS_FLAG_INTERFACE_KRYLOV) throw Error(FDS_E_INVALID_ARG, "unknown option flags");
   if ((o.flags & FDS_FLAG_INTERFACE_KRYLOV) && o.precision != FDS_FP64)
@@ -228,6 +229,7 @@ fds_plan* create_plan(const fds_rect* rects, int nrect, double h, double kappa,
       p->arms.push_back(ai);
     }
     p->floor_coef = 1.1102230246251565e-16 * (9.0 * p->delta + std::fabs(kappa));
+    if (p->opt.precision == FDS_JACOBI) p->jacobi = build_jacobi_table(p);
   } catch (...) {
     delete p;
     throw;

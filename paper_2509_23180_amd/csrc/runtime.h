@@ -125,6 +125,12 @@ struct IkPlanTable {
   const double *lamx, *lamy, *qx, *qy, *t00, *t0n, *s00, *s0n;
 };
 std::shared_ptr<IkPlanTable> build_ik_table(int nx, int ny, double h, double kappa);
+// Host copy of the Schur line coefficients delta^2 (2/N) g_k of an arm.
+std::vector<double> schur_gs_host(int n, int m, double h, double kappa);
+struct DiagTable {           // reciprocal of a diagonal preconditioner, centre layout
+  DevBuf mem;
+  const double* dinv = nullptr;
+};
 
 // Per-mode coefficients for `n` modes of an m-row tridiagonal system whose
 // right-hand side is multiplied by `scale`.
@@ -223,6 +229,7 @@ struct fds_plan {
   std::shared_ptr<fds::ModeTable> modes_c;
   std::shared_ptr<fds::ModeTable> modes_cu;   // centre, unit scale (flexible variant)
   std::shared_ptr<fds::IkPlanTable> ik;       // interface Krylov iteration (or null)
+  std::shared_ptr<fds::DiagTable> jacobi;     // FDS_JACOBI: 1/diag(L_c) (or null)
   double floor_coef = 0;
   bool interface_krylov() const { return (opt.flags & FDS_FLAG_INTERFACE_KRYLOV) != 0; }
   size_t footprint(int m, int precision) const;
@@ -232,6 +239,8 @@ namespace fds {
 
 fds_plan* create_plan(const fds_rect* rects, int nrect, double h, double kappa,
                       const fds_options* opt);
+// 1 / diag(L_c) of a plan (Jacobi preconditioner).
+std::shared_ptr<DiagTable> build_jacobi_table(const fds_plan* p);
 
 // ---------------------------------------------------------------- engine
 struct SolveRequest {

@@ -747,6 +747,21 @@ std::shared_ptr<ModeTable> TableCache::modes(int n, int m, double h, double kapp
 // interface row first):  g_k = [T_k^{-1}]_{11} = -sinh(m theta)/(delta sinh((m+1) theta))
 //                           = -(q/delta) (1 - q^{2m})/(1 - q^{2m+2}),
 // stored as delta^2 (2/N) g_k.
+std::vector<double> schur_gs_host(int n, int m, double h, double kappa) {
+  const int N = n + 1;
+  const double delta = 1.0 / (h * h);
+  std::vector<double> v(n);
+  for (int k = 1; k <= n; ++k) {
+    double th;
+    if (!mode_theta(k, N, delta, kappa, &th))
+      throw Error(FDS_E_UNSUPPORTED, "kappa makes a sine mode oscillatory (not diagonally dominant)");
+    const double q = std::exp(-th);
+    const double g = -(q / delta) * (std::expm1(-2.0 * m * th) / std::expm1(-2.0 * (m + 1) * th));
+    v[k - 1] = delta * delta * (2.0 / N) * g;
+  }
+  return v;
+}
+
 std::shared_ptr<GsTable> TableCache::gs(int n, int m, double h, double kappa, bool want_dense) {
   const int dev = current_device();
   auto key = std::make_tuple(dev, n, m, h, kappa, want_dense);
@@ -759,16 +774,7 @@ std::shared_ptr<GsTable> TableCache::gs(int n, int m, double h, double kappa, bo
     }
   }
   const int N = n + 1;
-  const double delta = 1.0 / (h * h);
-  std::vector<double> v(n);
-  for (int k = 1; k <= n; ++k) {
-    double th;
-    if (!mode_theta(k, N, delta, kappa, &th))
-      throw Error(FDS_E_UNSUPPORTED, "kappa makes a sine mode oscillatory (not diagonally dominant)");
-    const double q = std::exp(-th);
-    const double g = -(q / delta) * (std::expm1(-2.0 * m * th) / std::expm1(-2.0 * (m + 1) * th));
-    v[k - 1] = delta * delta * (2.0 / N) * g;
-  }
+  const std::vector<double> v = schur_gs_host(n, m, h, kappa);
   auto t = std::make_shared<GsTable>();
   const bool dense = want_dense && n <= kDenseLineMax;
   const size_t nn = (size_t)n * n;
@@ -868,6 +874,45 @@ bool dense_lines(int n) {
   const char* e = std::getenv("FDS_LINES");
   const bool fft = e && std::string(e) == "fft";
   return !fft && n <= kDenseLineMax;
+}
+
+}  // namespace fds
+
+namespace fds {
+
+// Jacobi preconditioner of Section 3.2: D = diag(L_c) = diag(A_c) minus the
+// diagonal of every arm's Schur term.  On a boundary line of length n the arm
+// term is delta^2 [A_a^{-1}] restricted to its interface row, Q diag(g) Q in
+// the line's sine basis, whose diagonal is sum_k gs_k sin^2(pi i k/N)
+// (gs_k = delta^2 (2/N) g_k); a corner node collects the terms of both lines.
+std::shared_ptr<DiagTable> build_jacobi_table(const fds_plan* p) {
+  const int nx = p->nx, ny = p->ny;
+  std::vector<double> d((size_t)nx * ny, -4.0 * p->delta + p->kappa);
+  for (const ArmInfo& a : p->arms) {
+    const int n = a.L, N = n + 1;
+    const std::vector<double> gs = schur_gs_host(n, a.rows, p->h, p->kappa);
+    for (int i = 1; i <= n; ++i) {
+      long double acc = 0;
+      for (int k = 1; k <= n; ++k) {
+        const long double sn = sinl(kPi * (long double)((long long)i * k % (2LL * N)) / (long double)N);
+        acc += (long double)gs[k - 1] * sn * sn;
+      }
+      size_t at = 0;
+      switch (a.line) {
+        case 0: at = (size_t)(i - 1); break;
+        case 1: at = (size_t)(ny - 1) * nx + (i - 1); break;
+        case 2: at = (size_t)(i - 1) * nx; break;
+        default: at = (size_t)(i - 1) * nx + (nx - 1); break;
+      }
+      d[at] -= (double)acc;
+    }
+  }
+  for (double& v : d) v = 1.0 / v;
+  auto t = std::make_shared<DiagTable>();
+  t->mem.alloc(sizeof(double) * d.size());
+  upload(t->mem.get(), d.data(), sizeof(double) * d.size());
+  t->dinv = t->mem.as<double>(0);
+  return t;
 }
 
 }  // namespace fds

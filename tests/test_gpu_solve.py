@@ -149,6 +149,35 @@ def test_no_preconditioner_baseline(shape, n):
     assert its[fds.NO_PRECOND] >= 3 * its[fds.FP64], its
 
 
+@pytest.mark.parametrize("shape,n,kappa", [("cross", 16, 0.0), ("T", 20, -40.0), ("L", 33, 0.0)])
+def test_jacobi_preconditioner(shape, n, kappa):
+    """P = diag(L_c) (Section 3.2's Jacobi baseline) reaches the oracle's
+    solution; its iteration count matches the oracle's own Jacobi-preconditioned
+    GMRES (same restart length and stopping rule) to within the FP32 storage
+    of z, and stays several times above the A_c^-1 preconditioner's."""
+    from oracle import schur
+    fds = _fds()
+    prob = _problem(shape, n, kappa, "shifted")
+    ref = oracle_solution(prob)
+    its = {}
+    for prec in (fds.JACOBI, fds.FP64):
+        log(f"{shape} n={n} kappa={kappa} precision={prec}")
+        plan, rhs, bc, x = device_problem(prob, restart_m=30, precision=prec, max_cycles=400)
+        res = fds.solve(plan, rhs, x, 1e-12, bc=bc)
+        err = compare(prob, x, ref)
+        log(f"  its={res.iterations} cycles={res.cycles} err={err:.3e} stop={res.stop_reason}")
+        assert res.status == 0, res
+        assert err <= 1e-10
+        its[prec] = res.iterations
+    P = schur.partition(prob.rects, prob.h, kappa, prob.f_grid, prob.g_grid)
+    op = schur.SchurOperator(P)
+    o = schur.gmres_right(op.apply_L, op.apply_Jinv, op.fprime(), m=30, tol=1e-12, max_cycles=400)
+    log(f"  oracle Jacobi GMRES its={o.iterations}")
+    assert o.converged
+    assert abs(its[fds.JACOBI] - o.iterations) <= max(3, 0.1 * o.iterations), (its, o.iterations)
+    assert its[fds.JACOBI] >= 3 * its[fds.FP64], its
+
+
 def test_solution_is_second_order():
     """Manufactured solution through the whole GPU path: error falls 4x per
     halving of h."""

@@ -123,3 +123,59 @@ def test_preconditioner_cuts_iterations():
     nop = schur.gmres_right(op.apply_L, lambda v: np.array(v), f, m=40, tol=1e-8, max_cycles=50)
     assert pre.converged
     assert nop.iterations > 5 * pre.iterations
+
+
+def _corner_inverse(m, delta, a):
+    """[T^-1]_11 of the m x m tridiagonal (delta, a, delta), by a dense inverse."""
+    T = np.diag(np.full(m, a)) + delta * (np.eye(m, k=1) + np.eye(m, k=-1))
+    return np.linalg.inv(T)[0, 0]
+
+
+ARMS = {"cross": ("S", "N", "W", "E"), "L": ("N", "E"), "T": ("W", "E", "S")}
+
+
+@pytest.mark.parametrize("shape", ["cross", "L", "T"])
+@pytest.mark.parametrize("kappa", [0.0, -30.0])
+def test_jacobi_diagonal_closed_form(shape, kappa):
+    """diag(L_c) (Section 3.2's Jacobi preconditioner) from the assembled
+    blocks equals its closed form: -4 delta + kappa, minus on each boundary
+    line next to an arm delta^2 sum_k (2/N) sin^2(pi i k/N) [T_k^-1]_11, where
+    T_k = tridiag(delta, 2 delta (cos(k pi/N) - 2) + kappa, delta) is the arm's
+    mode-k system over its n+1 rows (Section 2.1's per-mode decomposition);
+    corners take both lines' terms."""
+    n = 7
+    _, P, op = _op(shape, n, kappa)
+    h = 1.0 / (n + 1)
+    delta = 1.0 / h ** 2
+    N = n + 1
+    want = np.full((n, n), -4 * delta + kappa)
+    i = np.arange(1, n + 1)
+    line = np.zeros(n)
+    for k in range(1, n + 1):
+        g = _corner_inverse(n + 1, delta, 2 * delta * (np.cos(k * np.pi / N) - 2) + kappa)
+        line += delta ** 2 * (2.0 / N) * np.sin(np.pi * i * k / N) ** 2 * g
+    for arm in ARMS[shape]:
+        if arm == "S":
+            want[0, :] -= line
+        elif arm == "N":
+            want[-1, :] -= line
+        elif arm == "W":
+            want[:, 0] -= line
+        else:
+            want[:, -1] -= line
+    got = op.jacobi_diagonal().reshape(n, n)
+    assert np.abs(got - want).max() <= 1e-12 * delta
+
+
+def test_jacobi_preconditioned_gmres_reaches_solution_slowly():
+    """GMRES preconditioned by the Jacobi diagonal reaches the direct solution
+    of the interface system, with several times the iterations of the A_c^-1
+    preconditioner (Section 3.2, Fig. 4)."""
+    prob, P, op = _op("cross", 12, 0.0)
+    f = op.fprime()
+    ref = np.linalg.solve(op.dense_L(), f)
+    jac = schur.gmres_right(op.apply_L, op.apply_Jinv, f, m=30, tol=1e-11, max_cycles=100)
+    pre = schur.gmres_right(op.apply_L, op.apply_Minv, f, m=30, tol=1e-11, max_cycles=100)
+    assert jac.converged and pre.converged
+    assert np.abs(jac.x - ref).max() <= 1e-9 * np.abs(ref).max()
+    assert jac.iterations >= 3 * pre.iterations, (jac.iterations, pre.iterations)
