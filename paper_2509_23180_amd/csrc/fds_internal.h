@@ -433,10 +433,10 @@ struct IfaceTask {
 constexpr int kIkThreads = 1024;  // threads of the per-problem kernels (start, combine)
 constexpr int kIkEPT = 9;         // coordinates per thread there: 1 + lines <= 9216
 constexpr int kIkMaxCoords = kIkThreads * kIkEPT;
-constexpr int kIkSlab = 1024;     // coordinates per block of the step kernels (256 threads x 4)
-constexpr int kIkSlabEPT = kIkSlab / kBlock;
+constexpr int kIkSlab = kBlock;   // coordinates per block of the step kernels (one per thread)
 constexpr int kIkMaxSlabs = (kIkMaxCoords + kIkSlab - 1) / kIkSlab;
-constexpr int kIkGroup = 8;       // basis vectors per block reduction of the dots
+constexpr int kIkDotChunk = 8;    // basis vectors per wavefront whose loads are in flight together
+constexpr int kIkUpdChunk = 16;   // the same in the update pass
 constexpr int kIkXThreads = 512;  // cross-axis sums: threads per block (8 wavefronts)
 constexpr int kIkXTile = 64;      // cross-axis sums: target modes per block (one per lane)
 constexpr int kIkXParts = 4;      // cross-axis sums: source ranges per target tile

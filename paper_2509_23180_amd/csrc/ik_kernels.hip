@@ -72,57 +72,6 @@ __device__ __forceinline__ double recip(double d) {
   return fma(r, e, r);
 }
 
-// Moves the corner values of the W/E lines' terms onto the S/N lines that own
-// those corners.  sh[q] holds the term of this thread's coordinate q (line
-// lines[q], position pos[q]); the four corner values are reduced over the
-// block first.  red: 4 x kIkWaves doubles.
-template <int EPT>
-__device__ void ik_corner_fix(const IkTask& tk, double* sh, const int* line, const int* pos,
-                              double* red) {
-  const bool hasS = tk.off[0] >= 0, hasN = tk.off[1] >= 0;
-  const bool hasW = tk.off[2] >= 0, hasE = tk.off[3] >= 0;
-  if (!(hasW || hasE) || !(hasS || hasN)) return;
-  double p[4] = {0.0, 0.0, 0.0, 0.0};   // W . qy, W . sigma qy, E . qy, E . sigma qy
-#pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    if (line[q] >= 2) {
-      const double v = sh[q] * tk.qy[pos[q]];
-      const int b = (line[q] - 2) * 2;
-      p[b] += v;
-      p[b + 1] += sgn(pos[q]) * v;
-    }
-  }
-  const int w = threadIdx.x >> 6;
-#pragma unroll
-  for (int b = 0; b < 4; ++b) p[b] = wave_sum(p[b]);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0)
-    for (int b = 0; b < 4; ++b) red[b * kIkWaves + w] = p[b];
-  __syncthreads();
-  double c[4];
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    double s = 0.0;
-    for (int i = 0; i < kIkWaves; ++i) s += red[b * kIkWaves + i];
-    c[b] = s;
-  }
-  const double w0 = hasS ? 1.0 : 0.0, w1 = hasN ? 1.0 : 0.0;
-#pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int a = line[q];
-    if (a < 0) continue;
-    const int i = pos[q];
-    if (a >= 2) {
-      const int b = (a - 2) * 2;
-      sh[q] -= w0 * c[b] * tk.qy[i] + w1 * c[b + 1] * sgn(i) * tk.qy[i];
-    } else {
-      const double qx = tk.qx[i];
-      const int b = a;   // S takes the y = 0 corners (sums 0 / 2), N the y = ny-1 ones (1 / 3)
-      sh[q] += c[b] * qx + c[2 + b] * sgn(i) * qx;
-    }
-  }
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------- cycle start
@@ -170,12 +119,16 @@ __global__ void __launch_bounds__(kBlock) k_ik_extract(const IkTask* __restrict_
 
 // After the interior residual's sine transform, per-mode solve, boundary
 // columns and line transforms: eta = ||r_int||, dhat = S A^{-1} r_int / eta,
-// v_0 = (eta, line coefficients of r) / beta and g_0 = beta.
-template <int EPT>
+// v_0 = (eta, line coefficients of r) / beta and g_0 = beta.  Two phases over
+// the coordinates: the raw terms go to dhat while the corner sums (the W/E
+// terms at the shared corners) and ||rho||^2 are reduced; then each thread
+// re-reads its own entries, moves the corner values onto the S/N lines that
+// own those corners, and writes v_0.
 __global__ void __launch_bounds__(kIkThreads) k_ik_start(const IkTask* __restrict__ tasks, int ntasks) {
-  __shared__ double red[4 * kIkWaves];
+  __shared__ double red[5 * kIkWaves];
   const IkTask& tk = tasks[blockIdx.x];
   if (tk.st->finished) return;
+  const int w = threadIdx.x >> 6;
   double e2 = 0.0;
   for (int b = threadIdx.x; b < tk.P; b += kIkThreads) e2 += tk.partials[b];
   const double eta2 = ik_block_sum(e2, red);
@@ -183,41 +136,66 @@ __global__ void __launch_bounds__(kIkThreads) k_ik_start(const IkTask* __restric
   const double inv_eta = eta > 0.0 ? 1.0 / eta : 0.0;
   const int nco = 1 + tk.nb;
   const int nx = tk.nx, ny = tk.ny;
-  double sh[EPT];
-  int line[EPT], pos[EPT];
-  double rr = 0.0;
-#pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int e = threadIdx.x + q * kIkThreads;
-    sh[q] = 0.0;
-    line[q] = -1;
-    pos[q] = 0;
-    if (e < 1 || e >= nco) continue;
-    const int a = ik_line_of(tk, e, &pos[q]);
-    line[q] = a;
-    const int i = pos[q];
+  const bool hasS = tk.off[0] >= 0, hasN = tk.off[1] >= 0;
+  const bool fix = (tk.off[2] >= 0 || tk.off[3] >= 0) && (hasS || hasN);
+  // phase 1: raw terms, corner sums W . qy, W . sigma qy, E . qy, E . sigma qy
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, rr = 0.0;
+  for (int e = 1 + (int)threadIdx.x; e < nco; e += kIkThreads) {
+    int i = 0;
+    const int a = ik_line_of(tk, e, &i);
     double ahat;
     if (a == 0) ahat = tk.tz[i];
     else if (a == 1) ahat = tk.tz[(long long)(ny - 1) * nx + i];
     else ahat = tk.zc[(a - 2) * ny + i];
-    sh[q] = tk.gd[a][i] * tk.gscale[a] * ahat * inv_eta;
+    const double sh = tk.gd[a][i] * tk.gscale[a] * ahat * inv_eta;
+    tk.dhat[e - 1] = sh;
+    if (a >= 2) {
+      const double v = sh * tk.qy[i];
+      if (a == 2) { p0 += v; p1 += sgn(i) * v; }
+      else { p2 += v; p3 += sgn(i) * v; }
+    }
     const double rv = tk.rho[e - 1];
     rr += rv * rv;
   }
-  ik_corner_fix<EPT>(tk, sh, line, pos, red);
-  const double rho2 = ik_block_sum(rr, red);
-  const double beta = sqrt(eta2 + rho2);
-  const double ib = beta > 0.0 ? 1.0 / beta : 0.0;
+  p0 = wave_sum(p0); p1 = wave_sum(p1); p2 = wave_sum(p2); p3 = wave_sum(p3); rr = wave_sum(rr);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[w] = p0;
+    red[kIkWaves + w] = p1;
+    red[2 * kIkWaves + w] = p2;
+    red[3 * kIkWaves + w] = p3;
+    red[4 * kIkWaves + w] = rr;
+  }
+  __syncthreads();
+  double c[5];
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int e = threadIdx.x + q * kIkThreads;
-    if (e >= nco) continue;
+  for (int k = 0; k < 5; ++k) {
+    double sum = 0.0;
+    for (int q = 0; q < kIkWaves; ++q) sum += red[k * kIkWaves + q];
+    c[k] = sum;
+  }
+  const double beta = sqrt(eta2 + c[4]);
+  const double ib = beta > 0.0 ? 1.0 / beta : 0.0;
+  const double w0 = hasS ? 1.0 : 0.0, w1 = hasN ? 1.0 : 0.0;
+  // phase 2: corner correction and v_0 (every entry was written by this thread)
+  for (int e = threadIdx.x; e < nco; e += kIkThreads) {
     if (e == 0) {
       tk.Vb[0] = eta * ib;
-    } else {
-      tk.dhat[e - 1] = sh[q];
-      tk.Vb[e] = tk.rho[e - 1] * ib;
+      continue;
     }
+    tk.Vb[e] = tk.rho[e - 1] * ib;
+    if (!fix) continue;
+    int i = 0;
+    const int a = ik_line_of(tk, e, &i);
+    double sh = tk.dhat[e - 1];
+    if (a >= 2) {
+      const int b = (a - 2) * 2;
+      sh -= w0 * c[b] * tk.qy[i] + w1 * c[b + 1] * sgn(i) * tk.qy[i];
+    } else {
+      const double qx = tk.qx[i];   // S takes the y = 0 corners (sums 0 / 2), N the y = ny-1 ones (1 / 3)
+      sh += c[a] * qx + c[2 + a] * sgn(i) * qx;
+    }
+    tk.dhat[e - 1] = sh;
   }
   if (threadIdx.x == 0) {
     tk.g[0] = beta;
@@ -402,8 +380,7 @@ __global__ void __launch_bounds__(kIkXThreads) k_ik_cross(const IkTask* __restri
 
 // Step j, first pass over the coordinates (kIkSlab per block): w = b_j -
 // c0 dhat - S A^{-1} b_j with b_j = rscale_j V_j (stored in Wv), and the
-// block's parts of <w, V_i> (i <= j) and <V_j, V_i> (i < j), kIkGroup basis
-// vectors at a time.  The problem's last block sums the parts in block
+// block's parts of <w, V_i> and <V_j, V_i> (i <= j).  The problem's last block sums the parts in block
 // order, scales them to the normalised basis, stores the Gram column j and
 // runs the MGS recurrence h_i = <w, v_i> - sum_{l<i} h_l <v_l, v_i> (one-
 // reduction form of modified Gram-Schmidt) into hv.
@@ -411,7 +388,8 @@ __global__ void __launch_bounds__(kBlock) k_ik_wdots(const IkTask* __restrict__ 
   constexpr int kW = kBlock / 64;
   __shared__ int slot;
   __shared__ int lastf;
-  __shared__ double gred[2 * kIkGroup][kW];
+  __shared__ double gred[4][kW];
+  __shared__ double ws[kIkSlab], vs[kIkSlab];
   __shared__ double av[122], gv[122];
   __shared__ double cv[4];
   extern __shared__ __align__(16) double gt[];   // strict upper triangle of G, column i at i (i - 1) / 2
@@ -444,68 +422,68 @@ __global__ void __launch_bounds__(kBlock) k_ik_wdots(const IkTask* __restrict__ 
   }
   double c[4];
   for (int k = 0; k < 4; ++k) c[k] = cv[k];
-  double w[kIkSlabEPT], vr[kIkSlabEPT];
-#pragma unroll
-  for (int q = 0; q < kIkSlabEPT; ++q) {
-    const int e = b * kIkSlab + q * kBlock + (int)threadIdx.x;
-    w[q] = 0.0;
-    vr[q] = 0.0;
-    if (e >= nco) continue;
-    vr[q] = vj[e];
-    if (e == 0) {
-      w[q] = c0;
-    } else {
-      int i = 0;
-      const int a = ik_line_of(tk, e, &i);
-      const double sh = ik_corner(tk, c, a, i, ik_raw_term(tk, vj, rs, a, i));
-      w[q] = rs * vr[q] - c0 * tk.dhat[e - 1] - sh;
+  // w and v_j of the slab (one coordinate per thread) into LDS
+  {
+    const int e = b * kIkSlab + (int)threadIdx.x;
+    double wq = 0.0, vq = 0.0;
+    if (e < nco) {
+      vq = vj[e];
+      if (e == 0) {
+        wq = c0;
+      } else {
+        int i = 0;
+        const int a = ik_line_of(tk, e, &i);
+        const double sh = ik_corner(tk, c, a, i, ik_raw_term(tk, vj, rs, a, i));
+        wq = rs * vq - c0 * tk.dhat[e - 1] - sh;
+      }
+      tk.Wv[e] = wq;
     }
-    tk.Wv[e] = w[q];
+    ws[threadIdx.x] = wq;
+    vs[threadIdx.x] = vq;
   }
-  const int wv = threadIdx.x >> 6;
-  const int nrow = 2 * m1;   // partial rows: <w, V_i> at i, <V_j, V_i> at m1 + i
-  for (int i0 = 0; i0 <= j; i0 += kIkGroup) {
-    double pa[kIkGroup], pg[kIkGroup];
+  __syncthreads();
+  // dots: wavefront wv takes basis vectors i = wv, wv + kW, ... over the whole
+  // slab (lane l: coordinates l, l + 64, ...), kIkDotChunk of them with their
+  // loads in flight together; each sum ends in lane 63, which stores it
+  {
+    constexpr int R = kIkSlab / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double wl[R], vl[R];
 #pragma unroll
-    for (int g = 0; g < kIkGroup; ++g) pa[g] = pg[g] = 0.0;
+    for (int r = 0; r < R; ++r) {
+      wl[r] = ws[lane + 64 * r];
+      vl[r] = vs[lane + 64 * r];
+    }
+    const int e0 = b * kIkSlab + lane;
+    for (int i0 = wv; i0 <= j; i0 += kW * kIkDotChunk) {
+      double x[kIkDotChunk][R];
 #pragma unroll
-    for (int q = 0; q < kIkSlabEPT; ++q) {
-      const int e = b * kIkSlab + q * kBlock + (int)threadIdx.x;
-      const bool ok = e < nco;
+      for (int q = 0; q < kIkDotChunk; ++q) {
+        const int i = i0 + q * kW;
 #pragma unroll
-      for (int g = 0; g < kIkGroup; ++g) {
-        const int i = i0 + g;
-        const double x = (ok && i <= j) ? tk.Vb[(long long)i * tk.ldv + e] : 0.0;
-        pa[g] += w[q] * x;
-        pg[g] += vr[q] * x;
+        for (int r = 0; r < R; ++r) {
+          const int e = e0 + 64 * r;
+          x[q][r] = (i <= j && e < nco) ? tk.Vb[(long long)i * tk.ldv + e] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kIkDotChunk; ++q) {
+        const int i = i0 + q * kW;
+        double pa = 0.0, pg = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          pa += wl[r] * x[q][r];
+          pg += vl[r] * x[q][r];
+        }
+        pa = wave_sum_last(pa);
+        pg = wave_sum_last(pg);
+        if (lane == 63 && i <= j) {
+          st_agent(tk.dpart + (long long)i * tk.nslab + b, pa);
+          st_agent(tk.dpart + (long long)(m1 + i) * tk.nslab + b, pg);
+        }
       }
     }
-#pragma unroll
-    for (int g = 0; g < kIkGroup; ++g) {
-      pa[g] = wave_sum_last(pa[g]);
-      pg[g] = wave_sum_last(pg[g]);
-    }
-    if ((threadIdx.x & 63) == 63) {
-#pragma unroll
-      for (int g = 0; g < kIkGroup; ++g) {
-        gred[g][wv] = pa[g];
-        gred[kIkGroup + g][wv] = pg[g];
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x < 2 * kIkGroup) {
-      const int g = threadIdx.x % kIkGroup;
-      const int i = i0 + g;
-      if (i <= j) {
-        double sum = 0.0;
-        for (int k = 0; k < kW; ++k) sum += gred[threadIdx.x][k];
-        const int row = threadIdx.x < kIkGroup ? i : m1 + i;
-        st_agent(tk.dpart + (long long)row * tk.nslab + b, sum);
-      }
-    }
-    __syncthreads();
   }
-  (void)nrow;
   if (!last_block_of_problem(&st->ctr_dots, tk.nslab, &lastf)) return;
   for (int t = threadIdx.x; t < 2 * (j + 1); t += kBlock) {
     const int i = t <= j ? t : t - (j + 1);
@@ -565,7 +543,7 @@ __global__ void __launch_bounds__(kBlock) k_ik_update(const IkTask* __restrict__
                                                        int* flags, int tag) {
   __shared__ int slot;
   __shared__ int lastf;
-  __shared__ double hs[122];
+  __shared__ double hs[122 + kIkUpdChunk];
   __shared__ double col[122], cs[121], sn[121];
   __shared__ double red[4];
   const IkTask& tk = tasks[find_task(tasks, ntasks, &slot)];
@@ -580,22 +558,31 @@ __global__ void __launch_bounds__(kBlock) k_ik_update(const IkTask* __restrict__
     col[i] = tk.hv[i];
     hs[i] = col[i] * tk.rscale[i];
   }
+  for (int i = j + 1 + (int)threadIdx.x; i < 122 + kIkUpdChunk; i += kBlock) hs[i] = 0.0;
   for (int i = threadIdx.x; i < j; i += kBlock) {
     cs[i] = tk.cs[i];
     sn[i] = tk.sn[i];
   }
   __syncthreads();
   double* vn = tk.Vb + (long long)(j + 1) * tk.ldv;
+  // one coordinate per thread; the loads of kIkUpdChunk basis vectors are in
+  // flight together (hs is zero past j)
   double nn = 0.0;
+  {
+    const int e = b * kIkSlab + (int)threadIdx.x;
+    if (e < nco) {
+      double x = tk.Wv[e];
+      for (int i0 = 0; i0 <= j; i0 += kIkUpdChunk) {
+        double xv[kIkUpdChunk];
 #pragma unroll
-  for (int q = 0; q < kIkSlabEPT; ++q) {
-    const int e = b * kIkSlab + q * kBlock + (int)threadIdx.x;
-    if (e >= nco) continue;
-    double x = tk.Wv[e];
-#pragma unroll 4
-    for (int i = 0; i <= j; ++i) x -= hs[i] * tk.Vb[(long long)i * tk.ldv + e];
-    vn[e] = x;
-    nn += x * x;
+        for (int g = 0; g < kIkUpdChunk; ++g)
+          xv[g] = i0 + g <= j ? tk.Vb[(long long)(i0 + g) * tk.ldv + e] : 0.0;
+#pragma unroll
+        for (int g = 0; g < kIkUpdChunk; ++g) x -= hs[i0 + g] * xv[g];
+      }
+      vn[e] = x;
+      nn = x * x;
+    }
   }
   const double s = block_sum(nn, red);
   if (threadIdx.x == 0) st_agent(tk.dpart + (long long)2 * m1 * tk.nslab + b, s);
@@ -705,22 +692,11 @@ void launch_ik_extract(const IkTask* tasks, int ntasks, int nblocks, hipStream_t
   FDS_LAUNCH(k_ik_extract, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks);
 }
 
-// Coordinates per thread of the per-problem kernels: the smallest
-// instantiation that holds the launch's longest coordinate vector.
-static int ik_ept(int max_coords) {
-  if (max_coords <= 2 * kIkThreads) return 2;
-  if (max_coords <= 4 * kIkThreads) return 4;
-  if (max_coords <= kIkMaxCoords) return kIkEPT;
-  throw Error(FDS_E_INVALID_ARG, "interface Krylov vector longer than the step kernel holds");
-}
-
 void launch_ik_start(const IkTask* tasks, int ntasks, int max_coords, hipStream_t s) {
   if (ntasks <= 0) return;
-  switch (ik_ept(max_coords)) {
-    case 2: FDS_LAUNCH(k_ik_start<2>, dim3(ntasks), dim3(kIkThreads), 0, s, tasks, ntasks); break;
-    case 4: FDS_LAUNCH(k_ik_start<4>, dim3(ntasks), dim3(kIkThreads), 0, s, tasks, ntasks); break;
-    default: FDS_LAUNCH(k_ik_start<kIkEPT>, dim3(ntasks), dim3(kIkThreads), 0, s, tasks, ntasks); break;
-  }
+  if (max_coords > kIkMaxCoords)
+    throw Error(FDS_E_INVALID_ARG, "interface Krylov vector longer than the step kernels hold");
+  FDS_LAUNCH(k_ik_start, dim3(ntasks), dim3(kIkThreads), 0, s, tasks, ntasks);
 }
 
 void launch_ik_cross(const IkTask* tasks, int ntasks, int nblocks, int j, hipStream_t s) {
