@@ -35,6 +35,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2509_23180_amd/csrc/kernels.hip", "paper_2509_23180_amd/csrc/dst_wave.hip",
+                  "paper_2509_23180_amd/csrc/ik_kernels.hip",
                   "paper_2509_23180_amd/csrc/fft_device.h", "paper_2509_23180_amd/csrc/fft_wave.h",
                   "paper_2509_23180_amd/csrc/fds_internal.h")
 # kernel class -> name of the HIP kernel that implements it (rocprofv3 summaries)
@@ -43,7 +44,7 @@ CLASS_KERNEL = {"dst": "k_dst_wave", "tridiag": "k_tridiag_seg", "operator": "k_
                 "cols": "k_idst_cols"}
 
 
-IK_CLASS_KERNEL = {"gram_update": "k_ik_step", "lines": "k_ik_cross", "operator": "k_ik_compose",
+IK_CLASS_KERNEL = {"gram_dots": "k_ik_wdots", "gram_update": "k_ik_update", "lines": "k_ik_cross", "operator": "k_ik_compose",
                    "other": "k_ik_start", "cols": "k_idst_cols", "tridiag": "k_tridiag_seg",
                    "dst": "k_dst_wave"}
 
@@ -285,7 +286,8 @@ def run_convergence(args, device):
 def request_rhs(spec, device):
     """Right-hand side of one request on the device: the seeded Gaussian
     source evaluated at the owned unknown nodes, rectangle by rectangle in
-    the ABI layout (Dirichlet data zero, passed as NULL)."""
+    the ABI layout (Dirichlet data zero, passed as NULL).  All nodes of the
+    request go through one broadcast sum over the Gaussians, in chunks."""
     import torch
     import workloads
     from paper_2509_23180_amd import layout as playout
@@ -293,14 +295,25 @@ def request_rhs(spec, device):
     h = 1.0 / (n + 1)
     rects = workloads.shape_rects(spec.shape, n)
     src = workloads.gaussian_source(spec.shape, spec.config_id, spec.problem_id, spec.rhs_id)
-    parts = []
+    xs, ys = [], []
     for r in range(len(rects)):
         ilo, ihi, jlo, jhi = playout.owned_box(rects, r)
-        xs = torch.arange(ilo, ihi + 1, dtype=torch.float64, device=device) * h
-        ys = torch.arange(jlo, jhi + 1, dtype=torch.float64, device=device) * h
-        Y, X = torch.meshgrid(ys, xs, indexing="ij")
-        parts.append(src(X, Y, xp=torch).reshape(-1))
-    return rects, h, torch.cat(parts).contiguous()
+        gx = torch.arange(ilo, ihi + 1, dtype=torch.float64, device=device) * h
+        gy = torch.arange(jlo, jhi + 1, dtype=torch.float64, device=device) * h
+        xs.append(gx.repeat(jhi - jlo + 1))
+        ys.append(gy.repeat_interleave(ihi - ilo + 1))
+    X, Y = torch.cat(xs), torch.cat(ys)
+    cx = torch.tensor(src.centres[:, 0], dtype=torch.float64, device=device)[:, None]
+    cy = torch.tensor(src.centres[:, 1], dtype=torch.float64, device=device)[:, None]
+    iw = torch.tensor(-0.5 / src.widths ** 2, dtype=torch.float64, device=device)[:, None]
+    amp = torch.tensor(src.amps, dtype=torch.float64, device=device)[None, :]
+    out = torch.empty_like(X)
+    chunk = 1 << 22
+    for a in range(0, X.numel(), chunk):
+        x, y = X[a:a + chunk], Y[a:a + chunk]
+        e = torch.exp(((x[None, :] - cx) ** 2 + (y[None, :] - cy) ** 2) * iw)
+        out[a:a + chunk] = (amp @ e)[0]
+    return rects, h, out
 
 
 class TimedSlice:

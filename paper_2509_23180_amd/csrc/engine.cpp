@@ -705,8 +705,11 @@ void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
       launch_ik_cross(ik_x.dev(), ik_x.n(), ik_x.nblocks, j, s);
       Timing::end(4, s);
     }
+    Timing::begin(3, s);
+    launch_ik_wdots(ik_s.dev(), ik_s.n(), ik_s.nblocks, j, s);
+    Timing::end(3, s);
     Timing::begin(6, s);
-    launch_ik_step(ik_s.dev(), ik_s.n(), ik_s.nblocks, j, flags_dev, tag, s);
+    launch_ik_update(ik_s.dev(), ik_s.n(), ik_s.nblocks, j, flags_dev, tag, s);
     Timing::end(6, s);
     FDS_HIP(hipGetLastError());
     return;
@@ -1226,14 +1229,18 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
     const int its = host_states[sl.idx].iterations - before[sl.idx].iterations;
     if (ik) {
       // per step: the cross sums read two source lines per axis and write
-      // their sums; the step reads v_0..v_j (the coordinates) and the line
-      // tables and writes v_{j+1}
+      // their sums; the dot pass reads v_0..v_j (the coordinates) and writes
+      // w; the update reads w and v_0..v_j and writes v_{j+1}
       const IkGeom g = ik_geom(sl.plan);
       const double nco = 1.0 + g.nb;
-      double step = 0;
-      for (int j = 0; j < its; ++j) step += 8.0 * (j + 2) * nco;
+      double dots = 0, upd = 0;
+      for (int j = 0; j < its; ++j) {
+        dots += 8.0 * (j + 2) * nco;
+        upd += 8.0 * (j + 3) * nco;
+      }
       Timing::add_bytes(4, its * 8.0 * (2.0 * g.nb + 4.0 * (sl.plan->nx + sl.plan->ny)));
-      Timing::add_bytes(6, step);
+      Timing::add_bytes(3, dots);
+      Timing::add_bytes(6, upd);
       // cycle end: compose (read V0, write tz), solve (read, write), inverse
       // transform into x (read tz, read and write x), residual (read x and
       // f', write r); cycle start: extract (read r, write the interior

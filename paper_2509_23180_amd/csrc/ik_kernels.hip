@@ -704,13 +704,17 @@ void launch_ik_cross(const IkTask* tasks, int ntasks, int nblocks, int j, hipStr
   FDS_LAUNCH(k_ik_cross, dim3(nblocks), dim3(kIkXThreads), 0, s, tasks, ntasks, j);
 }
 
-void launch_ik_step(const IkTask* tasks, int ntasks, int nblocks, int j, int* flags, int tag,
-                    hipStream_t s) {
+void launch_ik_wdots(const IkTask* tasks, int ntasks, int nblocks, int j, hipStream_t s) {
   if (nblocks <= 0) return;
   const size_t smem = sizeof(double) * std::max<size_t>(1, (size_t)j * (j + 1) / 2);
   static size_t granted = 0;
   ensure_smem(k_ik_wdots, smem + 8192, &granted);
   FDS_LAUNCH(k_ik_wdots, dim3(nblocks), dim3(kBlock), smem, s, tasks, ntasks, j);
+}
+
+void launch_ik_update(const IkTask* tasks, int ntasks, int nblocks, int j, int* flags, int tag,
+                      hipStream_t s) {
+  if (nblocks <= 0) return;
   FDS_LAUNCH(k_ik_update, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
 }
 

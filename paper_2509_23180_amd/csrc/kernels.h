@@ -104,8 +104,9 @@ void launch_ik_extract(const IkTask* tasks, int ntasks, int nblocks, hipStream_t
 void launch_ik_start(const IkTask* tasks, int ntasks, int max_coords, hipStream_t s);
 void launch_ik_cross(const IkTask* tasks, int ntasks, int nblocks, int j, hipStream_t s);
 // The two coordinate passes of step j (nblocks: kIkSlab-coordinate blocks).
-void launch_ik_step(const IkTask* tasks, int ntasks, int nblocks, int j, int* flags, int tag,
-                    hipStream_t s);
+void launch_ik_wdots(const IkTask* tasks, int ntasks, int nblocks, int j, hipStream_t s);
+void launch_ik_update(const IkTask* tasks, int ntasks, int nblocks, int j, int* flags, int tag,
+                      hipStream_t s);
 void launch_ik_combine(const IkTask* tasks, int ntasks, hipStream_t s);
 void launch_ik_compose(const IkTask* tasks, int ntasks, int nblocks, hipStream_t s);
 // k_restart alone: the restart decision without scaling a stored V[0].
