@@ -825,6 +825,32 @@ def main():
         fds.solve(P[0], R[0], X[0], tol, bc=B[0])
         lat.append((time.perf_counter() - t0) * 1e3)
 
+    # batching: the same steps with one hipGraph per cycle and with the static
+    # transform choice instead of the autotuner's (both are read when a batch
+    # is set up, so they apply from the next step on)
+    variants = None
+    if args.workload == "batching":
+        variants = {"default_graphs_off_tuned": round(value, 3)}
+        for label, env in (("graphs_on", {"FDS_GRAPH": "1"}),
+                           ("untuned_transforms", {"FDS_DST_TUNE": "0"}),
+                           ("graphs_on_untuned", {"FDS_GRAPH": "1", "FDS_DST_TUNE": "0"})):
+            saved = {k: os.environ.get(k) for k in env}
+            os.environ.update(env)
+            step()
+            torch.cuda.synchronize()
+            k_steps = max(1, min(args.steps, 3))
+            t0 = time.perf_counter()
+            for _ in range(k_steps):
+                step()
+            torch.cuda.synchronize()
+            variants[label] = round(len(dev) * k_steps / (time.perf_counter() - t0), 3)
+            for k, v in saved.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+            log(f"variant {label}: {variants[label]} solves/s")
+
     error_vs_oracle = None
     if args.workload == "precision" and not args.no_oracle_error:
         error_vs_oracle = precision_error(items, X)
@@ -868,6 +894,8 @@ def main():
     }
     if error_vs_oracle is not None:
         line["error_vs_oracle"] = error_vs_oracle
+    if variants is not None:
+        line["variants_solves_per_s"] = variants
     if args.workload != "plain":
         line["dtype"] = "f64+f32"
     print(json.dumps(line), flush=True)

@@ -839,9 +839,16 @@ struct Engine::Impl {
   bool in_flight = false;
   std::vector<ProbState> before;
   // captured cycle of the current task set
-  bool graphs = true;
+  // one hipGraph per GMRES cycle (FDS_GRAPH=1): off by default, since a
+  // capture and instantiation cost about 0.7 ms, more than the launches of
+  // the cycles a solve replays it for (measured on the plain and batching
+  // workloads; the host enqueues a cycle faster than the device runs it)
+  bool graphs = false;
   long long ts_gen = 0;               // bumped whenever `cur` is replaced
   long long cycles_on_gen = 0;        // cycles run with the current task set
+  // cycles of an unchanged task set launched kernel by kernel before one is
+  // captured (capture and instantiation cost about what a few cycles' launches do)
+  int graph_after = 1;
   long long graph_gen = -1;
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_stream = nullptr;   // capture only (nothing runs on it)
@@ -928,6 +935,7 @@ Engine::Engine(int m, int precision, int max_cycles, int capacity, hipStream_t s
   if (capacity < 1) throw Error(FDS_E_INVALID_ARG, "engine capacity must be positive");
   I.ik = (flags & FDS_FLAG_INTERFACE_KRYLOV) != 0;
   if (const char* g = std::getenv("FDS_GRAPH")) I.graphs = std::string(g) != "0";
+  if (const char* g = std::getenv("FDS_GRAPH_AFTER")) I.graph_after = std::max(1, std::atoi(g));
   I.m = m;
   I.precision = precision;
   I.flex = precision != FDS_FP64;   // FP32 preconditioner or none: flexible GMRES
@@ -1103,7 +1111,7 @@ bool Engine::cycle_launch() {
   TaskSet& ts = I.current();
   I.before = I.host_states;
   // per-kernel events cannot be captured: timed cycles launch kernel by kernel
-  if (I.graphs && I.cycles_on_gen >= 1 && !Timing::on()) {
+  if (I.graphs && I.cycles_on_gen >= I.graph_after && !Timing::on()) {
     I.launch_graph_cycle(ts);
   } else {
     const int tag = ++I.cycle_serial;

@@ -77,6 +77,31 @@ static bool is_prime(int p) {
   return true;
 }
 
+// Convolution length of Bluestein's algorithm for a length-N DFT: at least
+// 2N - 1, with radices that have register butterflies.  FDS_BLUE_M selects
+// the smallest 5-smooth length ("smooth", fewest points) or the smallest
+// 2^a or 3 2^a ("pow2", fewest passes).
+static int bluestein_len(int N) {
+  static const int mode = [] {
+    const char* e = std::getenv("FDS_BLUE_M");
+    return (e && std::string(e) == "pow2") ? 1 : 0;
+  }();
+  int M = 2 * N - 1;
+  if (mode == 1) {
+    int p = 1;
+    while (p < M) p *= 2;
+    int q = 3;
+    while (q < M) q *= 2;
+    return std::min(p, q);
+  }
+  auto smooth = [](int v) {
+    for (int p : {2, 3, 5}) while (v % p == 0) v /= p;
+    return v == 1;
+  };
+  while (!smooth(M)) ++M;
+  return M;
+}
+
 FftShape fft_shape(int n) {
   const int N = n + 1;
   FftShape s{FFT_MIXED, N, N};
@@ -85,13 +110,7 @@ FftShape fft_shape(int n) {
     const double c = 2.0 * stockham_cost(N - 1) + 3.0 * N;
     if (c < best) { best = c; s = FftShape{FFT_RADER, N - 1, N}; }
   }
-  // smallest 5-smooth length >= 2N-1 (fixed butterflies only)
-  int M = 2 * N - 1;
-  auto smooth = [](int v) {
-    for (int p : {2, 3, 5}) while (v % p == 0) v /= p;
-    return v == 1;
-  };
-  while (!smooth(M)) ++M;
+  const int M = bluestein_len(N);
   // both LDS buffers of an FP64 row (plus the line-kernel scratch) must fit
   const bool fits = (size_t)M * 3 * sizeof(double2) + sizeof(double) * (N + 1) <= 160u * 1024u;
   if (N > 8 && fits) {
@@ -188,12 +207,7 @@ static WaveSched wave_sched(int n) {
   if (fixed_radices(s0.L)) cand.push_back({s0, 0.0, true});
   if (N > 7 && is_prime(N) && s0.kind != FFT_RADER)
     cand.push_back({FftShape{FFT_RADER, N - 1, N}, 2.0 * stockham_cost(N - 1) + 3.0 * N, false});
-  int M = 2 * N - 1;
-  auto smooth = [](int v) {
-    for (int p : {2, 3, 5}) while (v % p == 0) v /= p;
-    return v == 1;
-  };
-  while (!smooth(M)) ++M;
+  const int M = bluestein_len(N);
   if (N > 8 && !(s0.kind == FFT_BLUESTEIN && s0.L == M))
     cand.push_back({FftShape{FFT_BLUESTEIN, M, M}, 2.0 * stockham_cost(M) + 4.0 * M, false});
   for (int big = 0; big < 2; ++big) {

@@ -297,6 +297,39 @@ def test_restart_many_cycles_batch_matches_alone():
     assert torch.equal(items[1][3], a[3])
 
 
+@pytest.mark.parametrize("flags,precision", [(0, 0), (0, 1), (1, 0)])
+def test_cycle_graphs_match_kernel_launches(monkeypatch, flags, precision):
+    """One hipGraph per GMRES cycle (FDS_GRAPH=1, captured after the first
+    cycle of a batch and replayed for every later one, with the engine's own
+    synchronisations between replays) gives bitwise the result of the cycles
+    launched kernel by kernel, and the oracle's solution.  Plain, flexible
+    and interface Krylov paths, restart length 6 so the graph is replayed
+    many times."""
+    fds = _fds()
+    probs = [_problem("cross", 40, -10.0, "gauss", 4), _problem("T", 33, 0.0, "shifted", 0)]
+    out = {}
+    for g in ("0", "1"):
+        monkeypatch.setenv("FDS_GRAPH", g)
+        items = [device_problem(p, restart_m=6, precision=precision) for p in probs]
+        if flags:
+            items = []
+            for p in probs:
+                plan0, rhs, bc, x = device_problem(p, restart_m=6, precision=precision)
+                items.append((fds.Plan(p.rects, p.h, p.kappa, restart_m=6, precision=precision,
+                                       flags=flags), rhs, bc, x))
+        res = fds.solve_batch([i[0] for i in items], [i[1] for i in items], [i[3] for i in items],
+                              [1e-11] * len(items), bcs=[i[2] for i in items])
+        assert all(r.status == 0 for r in res), res
+        assert min(r.cycles for r in res) >= 4
+        out[g] = ([i[3].clone() for i in items], [r.iterations for r in res])
+        log(f"graphs={g} flags={flags} precision={precision}: its {out[g][1]}")
+    assert out["0"][1] == out["1"][1]
+    for a, b in zip(out["0"][0], out["1"][0]):
+        assert torch.equal(a, b)
+    for p, x in zip(probs, out["1"][0]):
+        assert compare(p, x, oracle_solution(p)) <= 1e-10
+
+
 def _drain(srv, tickets, timeout=90.0):
     import time
     results = {}
