@@ -232,9 +232,17 @@ __global__ void __launch_bounds__(kBlock) k_tridiag(const TriTask* __restrict__ 
 //            sum_i q^i w_i = sum_s q^{i0}(A_s + c_s q (1-q^{2L})/(1-q^2))
 //   backward y_{i0+t} = y_loc_t + q^{L-t} d,        d = y_{i0+L}
 // so the data is read once and written once.
+// Threads per block of a segment length: 32-row segments keep up to 64
+// values per thread in registers, which needs more than the 128 VGPRs a
+// 1024-thread block leaves each thread (576 threads: 8 modes x 72 segments,
+// systems of up to 2304 rows, at three wavefronts per SIMD).
+constexpr int kTriMaxThreadsLong = 576;
+template <int LS>
+constexpr int tri_max_threads() { return LS >= 32 ? kTriMaxThreadsLong : 1024; }
+
 template <typename T, int LS, int MPB>
-__global__ void __launch_bounds__(1024) k_tridiag_seg(const TriTask* __restrict__ tasks, int ntasks,
-                                                       int jidx) {
+__global__ void __launch_bounds__(tri_max_threads<LS>()) k_tridiag_seg(const TriTask* __restrict__ tasks,
+                                                                       int ntasks, int jidx) {
   constexpr int SEGMAX = 1024 / MPB;
   __shared__ int slot;
   __shared__ T sa[SEGMAX][MPB];
@@ -1557,7 +1565,7 @@ TriConfig tri_config(bool fp32, int max_rows) {
     if (std::sscanf(e, "%d,%d", &mpb, &ls) == 2 && (mpb == 8 || mpb == 16 || mpb == 32 || mpb == 64) &&
         (ls == 4 || ls == 8 || ls == 16 || ls == 32)) {
       const int S = (max_rows + ls - 1) / ls;
-      if (S <= 1024 / mpb) {
+      if (S <= (ls >= 32 ? kTriMaxThreadsLong : 1024) / mpb) {
         c.seg = true;
         c.ls = ls;
         c.mpb = mpb;
@@ -1570,10 +1578,9 @@ TriConfig tri_config(bool fp32, int max_rows) {
   // (8 modes per block last: up to 128 segments, for systems of more than
   // 1024 (FP64 with 16-row segments) or 2048 rows)
   for (int mpb : {16, 32, 64, 8}) {
-    const int segmax = 1024 / mpb;
     for (int ls = 8; ls <= lsmax; ls *= 2) {
       const int S = (max_rows + ls - 1) / ls;
-      if (S <= segmax) {
+      if (S <= (ls >= 32 ? kTriMaxThreadsLong : 1024) / mpb) {
         c.seg = true;
         c.ls = ls;
         c.mpb = mpb;
@@ -1597,6 +1604,8 @@ void launch_tri(const TriConfig& c, bool fp32, const TriTask* tasks, int ntasks,
     launch_tridiag(fp32, tasks, ntasks, nblocks, jidx, s);
     return;
   }
+  if (c.threads > (c.ls >= 32 ? kTriMaxThreadsLong : 1024))
+    throw Error(FDS_E_INVALID_ARG, "tridiagonal launch wider than its kernel's bound");
   const dim3 blk(c.threads);
 #define FDS_SEG(T, L, M) \
   FDS_LAUNCH((k_tridiag_seg<T, L, M>), dim3(nblocks), blk, 0, s, tasks, ntasks, jidx)
