@@ -440,7 +440,8 @@ def replay(fds, torch, srv, reqs, inputs, opts, device, t_measure, plan_cache, t
             r = srv.poll(tickets[k])
             if r is not None:
                 recs[k].update(done=time.perf_counter(), status=r.status, iterations=r.iterations,
-                               cycles=r.cycles, relres=r.relres_schur, stop=r.stop_reason)
+                               cycles=r.cycles, relres=r.relres_schur, stop=r.stop_reason,
+                               server_ms=r.seconds * 1e3, n=reqs[k].spec.n)
                 xs[k] = None
                 pending.discard(k)
                 done += 1
@@ -453,6 +454,23 @@ def replay(fds, torch, srv, reqs, inputs, opts, device, t_measure, plan_cache, t
         rec["latency_ms"] = (rec["done"] - rec["arrival"]) * 1e3
         rec["measured"] = rq.arrival_s >= t_measure
     return recs
+
+
+def latency_by_n(meas):
+    """Latency percentiles per octave of n, with the part spent inside the
+    server (submission to publication of the result)."""
+    out = {}
+    for lo in (64, 128, 256, 512, 1024):
+        hi = 2 * lo if lo < 1024 else 2049
+        sel = [r for r in meas if lo <= r["n"] < hi]
+        if not sel:
+            continue
+        lat = [r["latency_ms"] for r in sel]
+        srv = [r["server_ms"] for r in sel]
+        out[f"{lo}-{hi - 1}"] = {"requests": len(sel), "p50": _r(pct(lat, 50)), "p99": _r(pct(lat, 99)),
+                                 "server_p50": _r(pct(srv, 50)), "server_p99": _r(pct(srv, 99)),
+                                 "iterations_mean": round(sum(r["iterations"] for r in sel) / len(sel), 1)}
+    return out
 
 
 def summarise(recs, reqs, srv_stats):
@@ -474,6 +492,7 @@ def summarise(recs, reqs, srv_stats):
             "server_host_s": {k[5:-2]: round(srv_stats[k], 3) for k in
                               ("host_admit_s", "host_retire_s", "host_tasks_s", "host_launch_s", "host_wait_s")},
             "peak_hbm_gb": round(srv_stats["peak_bytes_in_use"] / 1e9, 2),
+            "latency_by_n": latency_by_n(meas),
             "not_converged": [{"shape": reqs[k].spec.shape, "n": reqs[k].spec.n,
                                "kappa": round(reqs[k].spec.kappa, 3), "problem": reqs[k].spec.problem_id,
                                "status": r["status"], "stop": r["stop"], "cycles": r["cycles"],

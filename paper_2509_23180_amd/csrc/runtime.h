@@ -281,7 +281,7 @@ class Engine {
   bool cycle_finish();
   // Cycles of a fixed set of problems (from the second cycle on the same
   // set) are replayed from one captured HIP graph instead of being launched
-  // kernel by kernel.  On by default; FDS_GRAPH=0 turns it off.
+  // kernel by kernel.  Off by default; FDS_GRAPH=1 turns it on.
   void set_graphs(bool on);
   int graph_replays() const;
   // Host seconds spent rebuilding task lists after the set changed.

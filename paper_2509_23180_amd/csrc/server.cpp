@@ -1,22 +1,26 @@
 // Request server with continuous batching at GMRES-cycle granularity.
 //
-// A host thread owns one batch engine, on a HIP stream of its own, per
-// (restart length, precision, cycle cap, Krylov iteration).  Between cycles it retires every
-// finished problem (back substitution and output, result published to the
-// ticket) and admits queued requests in arrival order while their device
-// footprint fits the budget and a slot is free; admitted requests run their
-// set-up phase and join the next cycle of the running batch.  The cycles of
-// all engines are queued before the thread waits for any of them, so groups
-// of different precision or restart length overlap on the device.  A
-// request's arithmetic does not depend on the other problems in the batch
-// (per-problem kernels and reductions), so its result is the same alone and
-// in the mix.
+// Requests are grouped by (restart length, precision, cycle cap, Krylov
+// iteration, size class); each group has its own batch engine, HIP stream and
+// host thread.  A group's thread runs cycles back to back: between cycles it
+// retires every finished problem (back substitution and output, result
+// published to the ticket) and admits queued requests of its group in arrival
+// order while their device footprint fits the server's budget and a slot is
+// free; admitted requests run their set-up phase and join the next cycle.
+// Groups therefore overlap on the device and on the host, and a short
+// request does not wait for a long one's cycle: the problems of one engine
+// advance in lockstep, one step per launch at the pace of the largest, so
+// centres of very different sizes go to different groups.  A request's
+// arithmetic does not depend on the other problems in the batch (per-problem
+// kernels and reductions), so its result is the same alone and in the mix.
 #include "server.h"
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <tuple>
@@ -35,48 +39,59 @@ struct Pending {
   hipEvent_t ready;   // recorded on the submitter's stream (inputs written)
 };
 
-using Key = std::tuple<int, int, int, unsigned>;   // restart_m, precision, max_cycles, flags
+// restart_m, precision, max_cycles, flags, size class
+using Key = std::tuple<int, int, int, unsigned, int>;
 
-Key key_of(const fds_plan* p) {
-  return Key{p->opt.restart_m, p->opt.precision, p->opt.max_cycles, p->opt.flags};
+// Size class of a plan's coupled rectangle: centres up to 256, up to 1024 and
+// above 1024 nodes per side.
+int size_class(const fds_plan* p) {
+  const int n = std::max(p->nx, p->ny);
+  return n <= 256 ? 0 : n <= 1024 ? 1 : 2;
 }
 
-struct Group {
-  hipStream_t stream = nullptr;
-  std::unique_ptr<Engine> eng;
-  std::map<int, Pending> running;   // engine id -> request
-  bool launched = false;
-};
+Key key_of(const fds_plan* p) {
+  return Key{p->opt.restart_m, p->opt.precision, p->opt.max_cycles, p->opt.flags, size_class(p)};
+}
+
+double seconds_since(Clock::time_point a) { return std::chrono::duration<double>(Clock::now() - a).count(); }
 
 }  // namespace
 
 }  // namespace fds
 
 struct fds_server {
+  struct Group {
+    fds::Key key;
+    hipStream_t stream = nullptr;
+    std::unique_ptr<fds::Engine> eng;   // touched by the group's thread only
+    std::map<int, fds::Pending> running;
+    int next_id = 0;
+    double tasks_seen = 0;
+    std::thread th;
+  };
+
   size_t budget = 0;
   int max_slots = 0;
   int device = 0;
+  // everything below is guarded by mu (an engine belongs to its group's thread)
   std::mutex mu;
-  std::condition_variable cv;
+  std::condition_variable cv;   // new requests, freed memory or slots, stop
   std::deque<fds::Pending> queue;
   std::map<uint64_t, fds_result> done;
   std::map<uint64_t, int> state;   // 0 queued, 1 running, 2 done
   uint64_t next_ticket = 1;
   bool stop = false;
-  std::thread worker;
-  std::vector<hipEvent_t> event_pool;   // guarded by mu
-  fds_server_stats stats{};             // guarded by mu
-  // worker-thread state
-  std::map<fds::Key, fds::Group> groups;
-  size_t used = 0;
-  int running = 0;
-  int next_id = 0;
-  double tasks_base = 0;   // task-list seconds of engines already destroyed
+  std::vector<hipEvent_t> event_pool;
+  fds_server_stats stats{};
+  size_t used = 0;   // footprint of the admitted requests
+  int running = 0;   // admitted requests not yet published
+  std::map<fds::Key, std::unique_ptr<Group>> groups;
 
-  void run();
-  void admit_from_queue();
-  void publish(const fds::Pending& p, const fds_result& r);
-  void fail_group(fds::Group& g, fds_status st);
+  void group_loop(Group* g);
+  bool admissible_locked(const Group* g) const;
+  bool has_queued_locked(const Group* g) const;
+  void publish_locked(const fds::Pending& p, const fds_result& r);
+  void fail_group(Group* g, fds_status st);
   hipEvent_t take_event();
 };
 
@@ -94,10 +109,9 @@ hipEvent_t fds_server::take_event() {
   return e;
 }
 
-void fds_server::publish(const fds::Pending& p, const fds_result& r0) {
+void fds_server::publish_locked(const fds::Pending& p, const fds_result& r0) {
   fds_result r = r0;
-  r.seconds = std::chrono::duration<double>(fds::Clock::now() - p.submitted).count();
-  std::lock_guard<std::mutex> lk(mu);
+  r.seconds = fds::seconds_since(p.submitted);
   done[p.ticket] = r;
   state[p.ticket] = 2;
   stats.completed += 1;
@@ -105,149 +119,151 @@ void fds_server::publish(const fds::Pending& p, const fds_result& r0) {
   if (p.ready) event_pool.push_back(p.ready);
 }
 
-void fds_server::fail_group(fds::Group& g, fds_status st) {
+// Publishes a failure for every request of the group and drops its engine
+// (its state is unknown after a failure).
+void fds_server::fail_group(Group* g, fds_status st) {
   fds_result r{};
   r.status = st;
-  for (auto& pr : g.running) {
-    publish(pr.second, r);
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto& pr : g->running) {
+    publish_locked(pr.second, r);
     used -= pr.second.bytes;
     --running;
   }
-  g.running.clear();
-  if (g.eng) tasks_base += g.eng->host_task_seconds();
-  g.eng.reset();   // its state is unknown after a failure
-  g.launched = false;
+  g->running.clear();
+  if (g->eng) stats.host_tasks_s += g->eng->host_task_seconds() - g->tasks_seen;
+  g->tasks_seen = 0;
+  g->eng.reset();
+  cv.notify_all();
 }
 
-// Move queued requests into their engines while the footprint fits the
-// budget and slots are free (arrival order; the head of the queue blocks
-// the rest so that a large request is not starved).
-void fds_server::admit_from_queue() {
-  std::map<fds::Key, std::vector<fds::Pending>> take;
-  const bool mid_flight = running > 0;   // problems admitted earlier still iterate
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    size_t u = used;
-    int r = running;
-    while (!queue.empty() && r < max_slots) {
-      const fds::Pending& p = queue.front();
-      if (u + p.bytes > budget && r > 0) break;
-      u += p.bytes;
-      ++r;
-      state[p.ticket] = 1;
-      take[fds::key_of(p.req.plan)].push_back(p);
-      queue.pop_front();
-    }
-  }
-  for (auto& kv : take) {
-    fds::Group& g = groups[kv.first];
-    std::vector<fds::SolveRequest> reqs;
-    std::vector<int> ids;
-    std::vector<hipEvent_t> evs;
-    for (const fds::Pending& p : kv.second) {
-      reqs.push_back(p.req);
-      ids.push_back(next_id++);
-      evs.push_back(p.ready);
-    }
-    try {
-      if (!g.stream) FDS_HIP(hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking));
-      if (!g.eng) {
-        g.eng.reset(new fds::Engine(std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                                    max_slots, g.stream, std::get<3>(kv.first)));
-        // the set changes at most cycle boundaries under continuous batching,
-        // so cycles are launched kernel by kernel (no graph capture while
-        // the submitting threads build plans)
-        g.eng->set_graphs(false);
-      }
-      g.eng->admit(reqs, ids, evs);
-      for (size_t i = 0; i < ids.size(); ++i) {
-        g.running[ids[i]] = kv.second[i];
-        used += kv.second[i].bytes;
-        ++running;
-      }
-      std::lock_guard<std::mutex> lk(mu);
-      stats.admitted += ids.size();
-      if (mid_flight) stats.admitted_mid_flight += ids.size();
-      stats.bytes_in_use = used;
-      stats.peak_bytes_in_use = std::max<uint64_t>(stats.peak_bytes_in_use, used);
-    } catch (const fds::Error& e) {
-      fds_result r{};
-      r.status = e.status;
-      for (const fds::Pending& p : kv.second) {
-        bool admitted = false;
-        for (auto& pr : g.running) admitted |= pr.second.ticket == p.ticket;
-        if (!admitted) publish(p, r);
-      }
-      fail_group(g, e.status);
-    }
-  }
+bool fds_server::has_queued_locked(const Group* g) const {
+  for (const fds::Pending& p : queue)
+    if (fds::key_of(p.req.plan) == g->key) return true;
+  return false;
 }
 
-void fds_server::run() {
+// Whether the group's first queued request can be admitted now: a slot is
+// free and its footprint fits the budget (always, when nothing runs at all).
+bool fds_server::admissible_locked(const Group* g) const {
+  if (running >= max_slots) return false;
+  for (const fds::Pending& p : queue)
+    if (fds::key_of(p.req.plan) == g->key) return used + p.bytes <= budget || running == 0;
+  return false;
+}
+
+void fds_server::group_loop(Group* g) {
   (void)hipSetDevice(device);
   using fds::Clock;
-  auto secs = [](Clock::time_point a) { return std::chrono::duration<double>(Clock::now() - a).count(); };
   while (true) {
+    std::vector<fds::Pending> take;
+    bool mid_flight = false;
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv.wait(lk, [&] { return stop || !queue.empty() || running > 0; });
-      if (stop && queue.empty() && running == 0) return;
+      cv.wait(lk, [&] { return stop || !g->running.empty() || admissible_locked(g); });
+      if (stop && g->running.empty() && !has_queued_locked(g)) return;
+      // the group's queued requests in arrival order, while slots are free
+      // and the footprint fits (the first that does not fit blocks the rest,
+      // so that a large request is not starved)
+      mid_flight = running > 0;
+      for (auto it = queue.begin(); it != queue.end() && running < max_slots;) {
+        if (fds::key_of(it->req.plan) != g->key) {
+          ++it;
+          continue;
+        }
+        if (used + it->bytes > budget && running > 0) break;
+        used += it->bytes;
+        ++running;
+        state[it->ticket] = 1;
+        take.push_back(*it);
+        it = queue.erase(it);
+      }
     }
     double t_admit = 0, t_launch = 0, t_wait = 0, t_retire = 0;
-    auto t0 = Clock::now();
-    admit_from_queue();
-    t_admit = secs(t0);
-    // queue one cycle of every group, then wait for each in turn
-    for (auto& kv : groups) {
-      fds::Group& g = kv.second;
-      g.launched = false;
-      if (!g.eng || g.running.empty()) continue;
-      try {
-        t0 = Clock::now();
-        g.launched = g.eng->cycle_launch();
-        t_launch += secs(t0);
-      } catch (const fds::Error& e) {
-        fail_group(g, e.status);
+    if (!take.empty()) {
+      const auto t0 = Clock::now();
+      std::vector<fds::SolveRequest> reqs;
+      std::vector<int> ids;
+      std::vector<hipEvent_t> evs;
+      for (const fds::Pending& p : take) {
+        reqs.push_back(p.req);
+        ids.push_back(g->next_id++);
+        evs.push_back(p.ready);
       }
-    }
-    uint64_t cycles = 0;
-    for (auto& kv : groups) {
-      fds::Group& g = kv.second;
-      if (!g.eng || !g.launched) continue;
       try {
-        t0 = Clock::now();
-        g.eng->cycle_finish();
-        t_wait += secs(t0);
-        g.launched = false;
-        ++cycles;
-        const std::vector<int> fin = g.eng->finished_ids();
-        if (fin.empty()) continue;
-        t0 = Clock::now();
-        auto retired = g.eng->retire(fin);
-        t_retire += secs(t0);
-        for (auto& pr : retired) {
-          auto it = g.running.find(pr.first);
-          if (it == g.running.end()) continue;
-          publish(it->second, pr.second.res);
-          used -= it->second.bytes;
-          --running;
-          g.running.erase(it);
+        if (!g->stream) FDS_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+        if (!g->eng) {
+          g->eng.reset(new fds::Engine(std::get<0>(g->key), std::get<1>(g->key), std::get<2>(g->key),
+                                       max_slots, g->stream, std::get<3>(g->key)));
+          // the set changes at most cycle boundaries under continuous
+          // batching: cycles are launched kernel by kernel
+          g->eng->set_graphs(false);
         }
+        g->eng->admit(reqs, ids, evs);
+        for (size_t i = 0; i < ids.size(); ++i) g->running[ids[i]] = take[i];
+        std::lock_guard<std::mutex> lk(mu);
+        stats.admitted += ids.size();
+        if (mid_flight) stats.admitted_mid_flight += ids.size();
+        stats.bytes_in_use = used;
+        stats.peak_bytes_in_use = std::max<uint64_t>(stats.peak_bytes_in_use, used);
       } catch (const fds::Error& e) {
+        {
+          fds_result r{};
+          r.status = e.status;
+          std::lock_guard<std::mutex> lk(mu);
+          for (size_t i = 0; i < take.size(); ++i) {
+            if (g->running.count(ids[i])) continue;   // failed with the group below
+            publish_locked(take[i], r);
+            used -= take[i].bytes;
+            --running;
+          }
+        }
         fail_group(g, e.status);
+        continue;
       }
+      t_admit = fds::seconds_since(t0);
     }
-    double t_tasks = 0;
-    for (auto& kv : groups)
-      if (kv.second.eng) t_tasks += kv.second.eng->host_task_seconds();
+    if (g->running.empty()) continue;
+    std::vector<std::pair<int, fds::SolveOutcome>> retired;
+    bool cycled = false;
+    try {
+      auto t0 = Clock::now();
+      cycled = g->eng->cycle_launch();
+      t_launch = fds::seconds_since(t0);
+      if (cycled) {
+        t0 = Clock::now();
+        g->eng->cycle_finish();
+        t_wait = fds::seconds_since(t0);
+      }
+      const std::vector<int> fin = g->eng->finished_ids();
+      if (!fin.empty()) {
+        t0 = Clock::now();
+        retired = g->eng->retire(fin);
+        t_retire = fds::seconds_since(t0);
+      }
+    } catch (const fds::Error& e) {
+      fail_group(g, e.status);
+      continue;
+    }
     std::lock_guard<std::mutex> lk(mu);
-    stats.cycles += cycles;
+    for (auto& pr : retired) {
+      auto it = g->running.find(pr.first);
+      if (it == g->running.end()) continue;
+      publish_locked(it->second, pr.second.res);
+      used -= it->second.bytes;
+      --running;
+      g->running.erase(it);
+    }
+    if (cycled) stats.cycles += 1;
     stats.bytes_in_use = used;
     stats.host_admit_s += t_admit;
     stats.host_retire_s += t_retire;
     stats.host_launch_s += t_launch;
     stats.host_wait_s += t_wait;
-    stats.host_tasks_s = tasks_base + t_tasks;
+    const double tasks = g->eng->host_task_seconds();
+    stats.host_tasks_s += tasks - g->tasks_seen;
+    g->tasks_seen = tasks;
+    if (!retired.empty()) cv.notify_all();   // memory and slots were freed
   }
 }
 
@@ -259,21 +275,24 @@ fds_server* server_create(size_t budget, int max_slots) {
   s->budget = budget;
   s->max_slots = max_slots;
   FDS_HIP(hipGetDevice(&s->device));
-  s->worker = std::thread([s] { s->run(); });
   return s;
 }
 
 void server_destroy(fds_server* s) {
   if (!s) return;
+  std::vector<fds_server::Group*> gs;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
+    for (auto& kv : s->groups) gs.push_back(kv.second.get());
   }
   s->cv.notify_all();
-  if (s->worker.joinable()) s->worker.join();
-  for (auto& kv : s->groups) {
-    kv.second.eng.reset();
-    if (kv.second.stream) (void)hipStreamDestroy(kv.second.stream);
+  // every group thread drains its queued and running requests, then exits
+  for (auto* g : gs)
+    if (g->th.joinable()) g->th.join();
+  for (auto* g : gs) {
+    g->eng.reset();
+    if (g->stream) (void)hipStreamDestroy(g->stream);
   }
   s->groups.clear();
   for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
@@ -295,12 +314,25 @@ fds_status server_submit(fds_server* s, fds_plan* plan, const double* rhs, const
     FDS_HIP(e);
   }
   std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) {
+    s->event_pool.push_back(ev);
+    throw Error(FDS_E_INVALID_ARG, "server is shutting down");
+  }
   const uint64_t t = s->next_ticket++;
   s->queue.push_back(Pending{t, SolveRequest{plan, rhs, bc, x, tol}, bytes, Clock::now(), ev});
   s->state[t] = 0;
   s->stats.submitted += 1;
   *ticket = t;
-  s->cv.notify_one();
+  // the request's group, with its thread, on first use
+  const Key k = key_of(plan);
+  auto& slot = s->groups[k];
+  if (!slot) {
+    slot.reset(new fds_server::Group());
+    slot->key = k;
+    fds_server::Group* g = slot.get();
+    g->th = std::thread([s, g] { s->group_loop(g); });
+  }
+  s->cv.notify_all();
   return FDS_OK;
 }
 

@@ -344,11 +344,11 @@ def _drain(srv, tickets, timeout=90.0):
     return results
 
 
-def _server_check(prob, x_server, precision):
-    """A server result: bitwise the solve alone, and the oracle's solution at
-    the FP64 bar."""
+def _server_check(prob, x_server, precision, **opts):
+    """A server result: bitwise the solve alone (same options), and the
+    oracle's solution at the FP64 bar."""
     fds = _fds()
-    plan, rhs, bc, x = device_problem(prob, precision=precision)
+    plan, rhs, bc, x = device_problem(prob, precision=precision, **opts)
     fds.solve(plan, rhs, x, 1e-11, bc=bc)
     assert torch.equal(x, x_server)
     err = compare(prob, x_server, oracle_solution(prob))
@@ -368,11 +368,16 @@ def test_server_continuous_batching_matches_alone():
     long_req = _problem("cross", 256, 0.0, "gauss", 1)
     later = [_problem("L", 33, -10.0, "gauss", 5), _problem("cross", 20, 0.0, "shifted", 0),
              _problem("T", 24, -50.0, "gauss", 3), _problem("T", 40, -20.0, "gauss", 2)]
-    items, precs, tickets = [], [], []
+    items, precs, opts, tickets = [], [], [], []
     for k, p in enumerate(later):
         prec = k % 2
-        items.append(device_problem(p, precision=prec))
+        # the FP64 ones share the long request's options and size class, so
+        # they join its engine at a cycle boundary; the others start a group
+        # of their own beside it
+        o = dict(restart_m=6, max_cycles=400) if prec == 0 else {}
+        items.append(device_problem(p, precision=prec, **o))
         precs.append(prec)
+        opts.append(o)
     first = device_problem(long_req, restart_m=6, precision=0, max_cycles=400)
     # warm the per-length tables and kernels of the later requests
     for it in items:
@@ -411,7 +416,7 @@ def test_server_continuous_batching_matches_alone():
     for k, (p, it, t) in enumerate(zip(later, items, tickets)):
         assert results[t].status == 0
         assert results[t].seconds > 0
-        _server_check(p, it[3], precs[k])
+        _server_check(p, it[3], precs[k], **opts[k])
     assert results[t_long].status == 0
     plan, rhs, bc, x = device_problem(long_req, restart_m=6, precision=0, max_cycles=400)
     fds.solve(plan, rhs, x, 1e-11, bc=bc)
