@@ -514,24 +514,34 @@ __global__ void __launch_bounds__(kBlock) k_ik_wdots(const IkTask* __restrict__ 
     gt[j * (j - 1) / 2 + l] = gv[l];
   }
   __syncthreads();
-  if (j + 1 <= 64) {
-    if (threadIdx.x < 64) {
-      const int i = threadIdx.x;
-      double ai = i <= j ? av[i] : 0.0;
-      for (int l = 0; l < j; ++l) {
-        const double hl = __shfl(ai, l, 64);
-        if (i > l && i <= j) ai -= hl * gt[i * (i - 1) / 2 + l];
+  // h = L^{-1} a with L unit lower triangular (L_il = G_li, l < i): one
+  // wavefront, rows i = lane and lane + 64 (j < 128); each step broadcasts
+  // the finished h_l and updates the later rows, with the Gram entries of 16
+  // steps read from LDS ahead of their use
+  if (threadIdx.x < 64) {
+    const int i0 = threadIdx.x, i1 = threadIdx.x + 64;
+    double a0 = i0 <= j ? av[i0] : 0.0, a1 = i1 <= j ? av[i1] : 0.0;
+    const int b0 = i0 * (i0 - 1) / 2, b1 = i1 * (i1 - 1) / 2;
+    for (int l0 = 0; l0 < j; l0 += 16) {
+      double g0[16], g1[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int l = l0 + u;
+        g0[u] = (l < i0 && i0 <= j) ? gt[b0 + l] : 0.0;
+        g1[u] = (l < i1 && i1 <= j) ? gt[b1 + l] : 0.0;
       }
-      if (i <= j) tk.hv[i] = ai;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int l = l0 + u;
+        if (l < j) {
+          const double hl = l < 64 ? __shfl(a0, l, 64) : __shfl(a1, l - 64, 64);
+          a0 -= hl * g0[u];
+          a1 -= hl * g1[u];
+        }
+      }
     }
-  } else {
-    for (int l = 0; l <= j; ++l) {
-      __syncthreads();
-      const double hl = av[l];
-      for (int i = l + 1 + (int)threadIdx.x; i <= j; i += kBlock) av[i] -= hl * gt[i * (i - 1) / 2 + l];
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i <= j; i += kBlock) tk.hv[i] = av[i];
+    if (i0 <= j) tk.hv[i0] = a0;
+    if (i1 <= j) tk.hv[i1] = a1;
   }
 }
 

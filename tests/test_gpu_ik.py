@@ -99,6 +99,26 @@ def test_ik_large_parity(shape, n, kappa, kind, seed):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("restart_m,shape,n,kappa,kind,seed", [(80, "cross", 400, 0.0, "shifted", 0),
+                                                               (120, "L", 512, -30.0, "gauss", 4),
+                                                               (80, "T", 450, 0.0, "gauss", 2)])
+def test_ik_long_restart_parity(restart_m, shape, n, kappa, kind, seed):
+    """Restart lengths 80 (the serving path's) and 120 (the most a plan
+    takes): more than 64 steps in one cycle, which the MGS recurrence runs
+    with two rows per lane; each case is checked against a solve whose
+    first cycle runs past step 64."""
+    fds = _fds()
+    prob, ref = _large(shape, n, kappa, kind, seed)
+    ik, plan, rhs, bc, x = _ik_problem(prob, restart_m=restart_m)
+    log(f"ik {shape} n={n} m={restart_m}")
+    r = fds.solve(ik, rhs, x, 1e-12, bc=bc)
+    err = compare(prob, x, ref)
+    log(f"  its={r.iterations} cycles={r.cycles} stop={r.stop_reason} err={err:.3e}")
+    assert r.status == 0, r
+    assert min(r.iterations, restart_m) > 64, r
+    assert err <= 1e-10
+
+
 def test_ik_long_lines_parity():
     """Lines of 1100 nodes: three source chunks and five target tiles in the
     cross-axis sums (L shape keeps the oracle in seconds)."""
