@@ -384,13 +384,21 @@ def replay(fds, torch, srv, reqs, inputs, opts, device, t_measure, plan_cache, t
     thread takes each request at its arrival time, builds its plan (or takes
     it from the plan cache) and its output buffer, and submits it with its
     right-hand side (already on the device); the latency clock starts at the
-    scheduled arrival.  The main thread polls.  Returns per-request records."""
+    scheduled arrival.  The main thread collects results from the server's
+    completion queue as they are published.  Returns per-request records."""
     import threading
     recs = [None] * len(reqs)
-    tickets = [None] * len(reqs)
     xs = [None] * len(reqs)
     t0 = time.perf_counter() + 0.2
     lock = threading.Lock()
+    k_of = {}     # ticket -> request index
+    early = {}    # results collected before their submitter recorded the ticket
+
+    def record(k, t_done, r):
+        recs[k].update(done=t_done, status=r.status, iterations=r.iterations, cycles=r.cycles,
+                       relres=r.relres_schur, stop=r.stop_reason, server_ms=r.seconds * 1e3,
+                       n=reqs[k].spec.n)
+        xs[k] = None
 
     def submitter(first, step):
         torch.cuda.set_device(device)
@@ -411,12 +419,16 @@ def replay(fds, torch, srv, reqs, inputs, opts, device, t_measure, plan_cache, t
                     plan = fds.Plan(rects, h, sp.kappa, **opts)
                     plan_cache.put(key, plan)
                 x = torch.empty(plan.n_unknowns, dtype=torch.float64, device=device)
+                with lock:
+                    recs[k] = {"arrival": t0 + rq.arrival_s, "plan_hit": hit}
+                    xs[k] = x
                 t = srv.submit(plan, rhs, x, 1e-10, stream=stream)
                 with lock:
-                    tickets[k] = t
-                    xs[k] = x
-                    recs[k] = {"arrival": t0 + rq.arrival_s, "prep_ms": (time.perf_counter() - tp) * 1e3,
-                               "plan_hit": hit}
+                    recs[k]["prep_ms"] = (time.perf_counter() - tp) * 1e3
+                    k_of[t] = k
+                    got = early.pop(t, None)
+                    if got is not None:
+                        record(k, *got)
 
     # a front end of SUBMITTERS threads, request k handled by thread k % SUBMITTERS
     ths = [threading.Thread(target=submitter, args=(i, SUBMITTERS)) for i in range(SUBMITTERS)]
@@ -425,27 +437,19 @@ def replay(fds, torch, srv, reqs, inputs, opts, device, t_measure, plan_cache, t
     if timed is not None:
         timed.start()
     done = 0
-    pending = set()
-    nxt = 0
-    seen = [False] * len(reqs)
     while done < len(reqs):
+        got = srv.wait_any(0.05)
+        if got is None:
+            continue
+        t_done = time.perf_counter()
+        t, r = got
         with lock:
-            while nxt < len(reqs) and seen[nxt]:
-                nxt += 1
-            for k in range(nxt, min(len(reqs), nxt + 4 * SUBMITTERS + 64)):
-                if not seen[k] and tickets[k] is not None:
-                    seen[k] = True
-                    pending.add(k)
-        for k in list(pending):
-            r = srv.poll(tickets[k])
-            if r is not None:
-                recs[k].update(done=time.perf_counter(), status=r.status, iterations=r.iterations,
-                               cycles=r.cycles, relres=r.relres_schur, stop=r.stop_reason,
-                               server_ms=r.seconds * 1e3, n=reqs[k].spec.n)
-                xs[k] = None
-                pending.discard(k)
-                done += 1
-        time.sleep(0.0002)
+            k = k_of.get(t)
+            if k is None:
+                early[t] = (t_done, r)
+            else:
+                record(k, t_done, r)
+        done += 1
     for th in ths:
         th.join()
     if timed is not None:

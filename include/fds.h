@@ -221,6 +221,16 @@ fds_status fds_batch_submit(fds_server* server, fds_plan* plan, const double* rh
  * forgotten after the first non-PENDING poll. */
 fds_status fds_batch_poll(fds_server* server, uint64_t ticket, fds_result* res);
 
+/* Completion queue of a server: blocks until some request has finished and
+ * has not been collected yet (by this call or fds_batch_poll), for at most
+ * timeout_us microseconds (negative: no limit).  Sets *ticket and, when res
+ * is not NULL, *res, forgets the ticket, and returns that request's final
+ * status; returns FDS_PENDING (ticket untouched) on time-out.  Collects the
+ * finished request with the smallest ticket first.  Thread-safe; the server
+ * must not be destroyed while a call waits. */
+fds_status fds_batch_wait_any(fds_server* server, int64_t timeout_us, uint64_t* ticket,
+                              fds_result* res);
+
 /* Counters of a server since it was created (a consistent snapshot). */
 typedef struct {
   uint64_t submitted;         /* requests accepted by fds_batch_submit      */

@@ -95,7 +95,8 @@ _lib = None
 SYMBOLS = (
     "fds_plan_create", "fds_plan_destroy", "fds_plan_layout", "fds_plan_footprint", "fds_solve",
     "fds_solve_batch", "fds_server_create", "fds_server_destroy", "fds_batch_submit",
-    "fds_batch_poll", "fds_server_stats_get", "fds_k_dst_rows", "fds_k_dst_rows_f32", "fds_k_tridiag_modes",
+    "fds_batch_poll",
+    "fds_batch_wait_any", "fds_server_stats_get", "fds_k_dst_rows", "fds_k_dst_rows_f32", "fds_k_tridiag_modes",
     "fds_k_tridiag_modes_f32", "fds_k_rect_solve", "fds_k_centre_operator", "fds_k_arnoldi_mgs",
     "fds_k_arnoldi_mgs_noalloc",
     "fds_status_str", "fds_last_error", "fds_timing_enable", "fds_timing_read", "fds_timing_bytes",
@@ -127,6 +128,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "fds_server_destroy": ([P], None),
         "fds_batch_submit": ([P, P, P, P, P, D, P, ctypes.POINTER(ctypes.c_uint64)], I32),
         "fds_batch_poll": ([P, ctypes.c_uint64, ctypes.POINTER(_Result)], I32),
+        "fds_batch_wait_any": ([P, I64, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_Result)], I32),
         "fds_server_stats_get": ([P, ctypes.POINTER(_ServerStats)], I32),
         "fds_k_dst_rows": ([P, P, I32, I32, D, P], I32),
         "fds_k_dst_rows_f32": ([P, P, I32, I32, ctypes.c_float, P], I32),
@@ -286,15 +288,18 @@ class Server:
         out = ctypes.c_void_p()
         _check(lib.fds_server_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(out)))
         self._h = out
-        self._held = {}   # ticket -> (plan, rhs, bc, x): alive until the result is polled
+        self._held = {}   # ticket -> (plan, rhs, bc, x): alive until the result is collected
+        import threading
+        self._lock = threading.Lock()
 
     def submit(self, plan: Plan, rhs, x, tol: float, bc=None, stream=None) -> int:
         """Queue a solve.  The server reads rhs/bc after the work queued on
         `stream` (default: the current torch stream) up to this call."""
         t = ctypes.c_uint64()
-        _check(load_library().fds_batch_submit(self._h, plan._h, _ptr(rhs), _ptr(bc), _ptr(x),
-                                               float(tol), _stream(stream), ctypes.byref(t)))
-        self._held[t.value] = (plan, rhs, bc, x)
+        with self._lock:   # registered before a waiter can collect the ticket
+            _check(load_library().fds_batch_submit(self._h, plan._h, _ptr(rhs), _ptr(bc), _ptr(x),
+                                                   float(tol), _stream(stream), ctypes.byref(t)))
+            self._held[t.value] = (plan, rhs, bc, x)
         return t.value
 
     def poll(self, ticket: int) -> Optional[Result]:
@@ -302,9 +307,24 @@ class Server:
         st = load_library().fds_batch_poll(self._h, int(ticket), ctypes.byref(res))
         if st == FDS_PENDING:
             return None
-        self._held.pop(int(ticket), None)
+        with self._lock:
+            self._held.pop(int(ticket), None)
         _check(st, allow=(FDS_OK, -6, -7))
         return Result.from_c(res)
+
+    def wait_any(self, timeout_s: Optional[float] = None) -> Optional[Tuple[int, Result]]:
+        """The next finished request, (ticket, Result), waiting at most
+        timeout_s seconds (None: no limit); None on time-out."""
+        t = ctypes.c_uint64()
+        res = _Result()
+        us = -1 if timeout_s is None else int(timeout_s * 1e6)
+        st = load_library().fds_batch_wait_any(self._h, us, ctypes.byref(t), ctypes.byref(res))
+        if st == FDS_PENDING:
+            return None
+        with self._lock:
+            self._held.pop(t.value, None)
+        _check(st, allow=(FDS_OK, -6, -7))
+        return t.value, Result.from_c(res)
 
     def stats(self) -> dict:
         s = _ServerStats()

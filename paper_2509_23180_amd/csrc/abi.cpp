@@ -559,4 +559,8 @@ fds_status fds_batch_poll(fds_server* server, uint64_t ticket, fds_result* res) 
   return guarded([&] { return server_poll(server, ticket, res); });
 }
 
+fds_status fds_batch_wait_any(fds_server* server, int64_t timeout_us, uint64_t* ticket, fds_result* res) {
+  return guarded([&] { return server_wait_any(server, timeout_us, ticket, res); });
+}
+
 }  // extern "C"

@@ -76,6 +76,7 @@ struct fds_server {
   // everything below is guarded by mu (an engine belongs to its group's thread)
   std::mutex mu;
   std::condition_variable cv;   // new requests, freed memory or slots, stop
+  std::condition_variable done_cv;   // a result was published
   std::deque<fds::Pending> queue;
   std::map<uint64_t, fds_result> done;
   std::map<uint64_t, int> state;   // 0 queued, 1 running, 2 done
@@ -117,6 +118,7 @@ void fds_server::publish_locked(const fds::Pending& p, const fds_result& r0) {
   stats.completed += 1;
   // the event's wait was queued before the set-up phase, which has finished
   if (p.ready) event_pool.push_back(p.ready);
+  done_cv.notify_all();
 }
 
 // Publishes a failure for every request of the group and drops its engine
@@ -345,6 +347,25 @@ fds_status server_poll(fds_server* s, uint64_t ticket, fds_result* res) {
   fds_result r = s->done[ticket];
   s->done.erase(ticket);
   s->state.erase(it);
+  if (res) *res = r;
+  return (fds_status)r.status;
+}
+
+fds_status server_wait_any(fds_server* s, int64_t timeout_us, uint64_t* ticket, fds_result* res) {
+  if (!s || !ticket) throw Error(FDS_E_INVALID_ARG, "NULL argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto ready = [&] { return !s->done.empty(); };
+  if (timeout_us < 0) {
+    s->done_cv.wait(lk, ready);
+  } else if (!s->done_cv.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+    return FDS_PENDING;
+  }
+  auto it = s->done.begin();
+  const uint64_t t = it->first;
+  const fds_result r = it->second;
+  s->done.erase(it);
+  s->state.erase(t);
+  *ticket = t;
   if (res) *res = r;
   return (fds_status)r.status;
 }

@@ -11,5 +11,6 @@ void server_destroy(fds_server* s);
 fds_status server_submit(fds_server* s, fds_plan* plan, const double* rhs, const double* bc,
                          double* x, double tol, hipStream_t stream, uint64_t* ticket);
 fds_status server_poll(fds_server* s, uint64_t ticket, fds_result* res);
+fds_status server_wait_any(fds_server* s, int64_t timeout_us, uint64_t* ticket, fds_result* res);
 void server_stats(fds_server* s, fds_server_stats* out);
 }  // namespace fds

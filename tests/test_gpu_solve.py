@@ -446,6 +446,29 @@ def test_server_reads_inputs_after_the_submitting_stream():
     _server_check(prob, x, 0)
 
 
+def test_server_completion_queue():
+    """fds_batch_wait_any hands out every finished request exactly once, each
+    matching the oracle, and times out with nothing left."""
+    fds = _fds()
+    probs = [_problem("cross", 20, 0.0, "gauss", s) for s in range(2)] + \
+            [_problem("L", 33, -10.0, "gauss", 5), _problem("T", 120, 0.0, "shifted", 0)]
+    srv = fds.Server(hbm_budget_bytes=1 << 31, max_slots=4)
+    items = [device_problem(p) for p in probs]
+    tickets = [srv.submit(it[0], it[1], it[3], 1e-11, bc=it[2]) for it in items]
+    got = {}
+    while len(got) < len(tickets):
+        r = srv.wait_any(60.0)
+        assert r is not None
+        t, res = r
+        assert t in tickets and t not in got
+        got[t] = res
+    assert srv.wait_any(0.01) is None
+    srv.close()
+    for p, it, t in zip(probs, items, tickets):
+        assert got[t].status == 0
+        _server_check(p, it[3], 0)
+
+
 def test_server_admission_by_footprint():
     """A budget that holds one problem runs the stream one at a time."""
     fds = _fds()
