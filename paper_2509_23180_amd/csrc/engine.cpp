@@ -213,7 +213,7 @@ SlotLayout layout_of(const fds_plan* p, int m, int precision) {
     const IkGeom g = ik_geom(p);
     L.u = take(8 * Nc);
     L.V0 = take(8 * Nc);
-    L.lines = take(8 * 4 * (size_t)Lmax);
+    L.lines = take(8 * 8 * (size_t)Lmax);   // four line terms, then four lines of scratch
     L.small = take(8 * ((size_t)(m + 1) * m + 4 * (size_t)m + 2));
     L.partials = take(8 * kry_partials_len(m, P));
     L.gram = take(8 * ((size_t)(m + 1) * (m + 1) + (m + 1)));
@@ -238,7 +238,7 @@ SlotLayout layout_of(const fds_plan* p, int m, int precision) {
   L.V = take(8 * (size_t)(m + 1) * Nc);
   L.u = take(8 * Nc);
   L.zbuf = flex ? 0 : take(8 * Nc);
-  L.lines = take(8 * 4 * (size_t)Lmax);
+  L.lines = take(8 * 8 * (size_t)Lmax);   // four line terms, then four lines of scratch
   L.small = take(8 * ((size_t)(m + 1) * m + 4 * (size_t)m + 2));
   L.partials = take(8 * kry_partials_len(m, P));
   L.gram = take(8 * ((size_t)(m + 1) * (m + 1) + (m + 1)));
@@ -292,10 +292,12 @@ struct TaskSet {
   bool flex = false;
   DstStage cyc_fwd, cyc_inv, arm_fwd, arm_inv, bs_fwd;
   TriStage it_tri, cyc_tri, arm_tri;
-  TaskList<LineTask> it_lines, x_lines;      // FFT line kernel (one block per line)
   TaskList<LineTask> it_lines_d, x_lines_d;  // dense line operators
+  // line terms without a dense operator: S (gs * (S z_line)) by the batched
+  // row transforms (forward, coefficient scaling, inverse)
+  DstStage it_lnf, it_lni, x_lnf, x_lni;
+  TaskList<CopyTask> it_lnm, x_lnm;
   int lmax_dense = 0;
-  size_t smem_lines = 0;
   TaskList<ColTask> it_cols;
   // Jacobi preconditioner: z^ = Q D^-1 Q^T v^ (inverse transform, diagonal
   // scaling, forward transform; z^ = v^ is first written to Z_j in FP32)
@@ -329,17 +331,18 @@ struct TaskSet {
   void ik_cycle_start(hipStream_t s) const;
   void add_problem(Problem& sl);
   void upload(hipStream_t s) {
-    for (DstStage* d : {&cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd, &ik_lfwd, &ik_linv, &it_jinv, &it_jfwd})
+    for (DstStage* d : {&cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd, &ik_lfwd, &ik_linv, &it_jinv, &it_jfwd,
+                        &it_lnf, &it_lni, &x_lnf, &x_lni})
       d->stage(blob);
     blob.add(it_jdiag);
+    blob.add(it_lnm);
+    blob.add(x_lnm);
     for (TriStage* t : {&it_tri, &cyc_tri, &arm_tri, &ik_tri0}) t->stage(blob);
     blob.add(ik_p);
     blob.add(ik_s);
     blob.add(ik_x);
     blob.add(ik_1);
     blob.add(ik_cols);
-    blob.add(it_lines);
-    blob.add(x_lines);
     blob.add(it_lines_d);
     blob.add(x_lines_d);
     blob.add(it_cols);
@@ -357,7 +360,26 @@ struct TaskSet {
   }
   void launch_x_lines(hipStream_t s) const {
     launch_lines_dense(x_lines_d.dev(), x_lines_d.n(), x_lines_d.nblocks, lmax_dense, 0, s);
-    launch_lines(x_lines.dev(), x_lines.n(), smem_lines, 0, s);
+    if (x_lnm.n()) {
+      x_lnf.launch(0, s);
+      launch_copy(x_lnm.dev(), x_lnm.n(), x_lnm.nblocks, s);
+      x_lni.launch(0, s);
+    }
+  }
+  // S (gs * (S z)) on one line into `out`, through `tmp` (L doubles each)
+  static void add_line_stages(DstStage& fwd, TaskList<CopyTask>& mul, DstStage& inv, const double* z,
+                              long long stride, int L, const double* gs, double* tmp, double* out,
+                              const FftDesc* fft, const int* skip) {
+    DstTask f{};
+    f.in = z; f.in_cs = stride; f.out = tmp; f.out_cs = 1;
+    f.rows = 1; f.n = L; f.scale = 1.0; f.fft = fft; f.skip = skip;
+    fwd.add(f);
+    CopyTask c{tmp, tmp, L, 0, 1, gs, skip};
+    add_block_task(mul, c, 1);
+    DstTask v{};
+    v.in = tmp; v.in_cs = 1; v.out = out; v.out_cs = 1;
+    v.rows = 1; v.n = L; v.scale = 1.0; v.fft = fft; v.skip = skip;
+    inv.add(v);
   }
   void iteration(int j, int* flags_dev, int tag, hipStream_t s) const;
   void end_of_cycle(int max_cycles, hipStream_t s) const;
@@ -462,7 +484,6 @@ void TaskSet::add_problem(Problem& sl) {
       case 3: lt.start = nx - 1; lt.stride = nx; break;
     }
     ot.line[a.line] = lt.out;
-    smem_lines = std::max(smem_lines, line_smem_bytes(a.L));
     LineTask li = lt;
     li.skip = skip_it;
     // S/N blocks are diagonal in the centre's sine basis (spec_w, and
@@ -480,8 +501,12 @@ void TaskSet::add_problem(Problem& sl) {
       add_block_task(x_lines_d, lx, div_up(a.L, 64));
       lmax_dense = std::max(lmax_dense, a.L);
     } else {
-      if (it_line) it_lines.h.push_back(li);
-      x_lines.h.push_back(lx);
+      double* tmp = sl.lines + (size_t)(4 + a.line) * sl.Lmax;
+      if (it_line)
+        add_line_stages(it_lnf, it_lnm, it_lni, static_cast<const double*>(li.z), 1, a.L, a.gs->gs, tmp,
+                        lt.out, a.fft->dev, skip_it);
+      add_line_stages(x_lnf, x_lnm, x_lni, sl.x_int + cd.off + lt.start, lt.stride, a.L, a.gs->gs, tmp,
+                      lt.out, a.fft->dev, skip_fin);
     }
 
     // f'_c formation and back substitution
@@ -729,10 +754,14 @@ void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
     launch_idst_cols(it_cols.dev(), it_cols.n(), it_cols.nblocks, j, s);
     Timing::end(7, s);
   }
-  if (it_lines.n() || it_lines_d.n()) {
+  if (it_lnm.n() || it_lines_d.n()) {
     Timing::begin(4, s);
     launch_lines_dense(it_lines_d.dev(), it_lines_d.n(), it_lines_d.nblocks, lmax_dense, j, s);
-    launch_lines(it_lines.dev(), it_lines.n(), smem_lines, j, s);
+    if (it_lnm.n()) {
+      it_lnf.launch(j, s);
+      launch_copy(it_lnm.dev(), it_lnm.n(), it_lnm.nblocks, s);
+      it_lni.launch(j, s);
+    }
     Timing::end(4, s);
   }
   Timing::begin(3, s);
@@ -768,7 +797,7 @@ void TaskSet::end_of_cycle(int max_cycles, hipStream_t s) const {
     Timing::begin(0, s);
     cyc_inv.launch(0, s);
     Timing::end(0, s);
-    if (x_lines.n() || x_lines_d.n()) {
+    if (x_lnm.n() || x_lines_d.n()) {
       Timing::begin(4, s);
       launch_x_lines(s);
       Timing::end(4, s);
@@ -795,7 +824,7 @@ void TaskSet::end_of_cycle(int max_cycles, hipStream_t s) const {
   Timing::begin(0, s);
   cyc_inv.launch(0, s);
   Timing::end(0, s);
-  if (x_lines.n() || x_lines_d.n()) {
+  if (x_lnm.n() || x_lines_d.n()) {
     Timing::begin(4, s);
     launch_x_lines(s);
     Timing::end(4, s);

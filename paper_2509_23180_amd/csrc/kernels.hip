@@ -420,7 +420,10 @@ __global__ void __launch_bounds__(tri_max_threads<LS>()) k_tridiag_seg(const Tri
 
 // =====================================================================
 // Schur line terms: out = delta^2 (2/N) S diag(g) S z_line (FP64).
-// One block per line; two sine transforms in LDS.
+// One block per line; two sine transforms in LDS.  Used by the kernel-level
+// operator entry point; the solver forms these terms with the batched row
+// transforms, which spread a line over many lanes and take the autotuner's
+// schedule.
 // =====================================================================
 __global__ void __launch_bounds__(kBlock) k_schur_lines(const LineTask* __restrict__ tasks, int jidx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
