@@ -1,6 +1,8 @@
 // Launch wrappers of the HIP kernels (defined in kernels.hip).
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_ext.h>
 
 #include "fds_internal.h"
@@ -58,7 +60,14 @@ void launch_tridiag(bool fp32, const TriTask* tasks, int ntasks, int nblocks, in
 // configuration (mpb in {8,16,32,64}, ls in {4,8,16}, or 32 for FP32) when
 // the rows fit; other values are ignored.
 struct TriConfig { bool seg; int ls; int mpb; int threads; };
+// The configuration of systems of max_rows rows: FDS_TRI_SEG="mpb,ls" or
+// FDS_TRI_TUNE=0 take tri_config_static, otherwise the autotuner's measured
+// choice (tune.cpp) among tri_configs(max_rows).
 TriConfig tri_config(bool fp32, int max_rows);
+TriConfig tri_config_static(bool fp32, int max_rows);
+// Every instantiated segmented configuration that holds `rows` rows (the
+// unsegmented kernel when none does).
+std::vector<TriConfig> tri_configs(int rows);
 int tri_blocks(const TriConfig& c, int modes);
 void launch_tri(const TriConfig& c, bool fp32, const TriTask* tasks, int ntasks, int nblocks,
                 int jidx, hipStream_t s);

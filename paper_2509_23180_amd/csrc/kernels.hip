@@ -1554,7 +1554,30 @@ void launch_tridiag(bool fp32, const TriTask* tasks, int ntasks, int nblocks, in
     FDS_LAUNCH(k_tridiag<double>, dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, jidx);
 }
 
-TriConfig tri_config(bool fp32, int max_rows) {
+// A segmented configuration for systems of `rows` rows, if (mpb, ls) fits.
+static bool tri_fit(int mpb, int ls, int rows, TriConfig* c) {
+  const int S = (rows + ls - 1) / ls;
+  if (S > (ls >= 32 ? kTriMaxThreadsLong : 1024) / mpb) return false;
+  c->seg = true;
+  c->ls = ls;
+  c->mpb = mpb;
+  c->threads = std::max(64, mpb * (S < 1 ? 1 : S));
+  return true;
+}
+
+std::vector<TriConfig> tri_configs(int rows) {
+  std::vector<TriConfig> out;
+  for (int mpb : {8, 16, 32, 64})
+    for (int ls : {4, 8, 16, 32}) {
+      TriConfig c{false, 0, 0, 0};
+      if (tri_fit(mpb, ls, rows, &c)) out.push_back(c);
+    }
+  if (out.empty()) out.push_back(TriConfig{false, 0, 0, 0});
+  return out;
+}
+
+TriConfig tri_config_static(bool fp32, int max_rows) {
+  (void)fp32;
   // register segments of 8 to 32 rows (the shortest that fits); up to 1024
   // threads per block: 16 modes x 64 segments, 32 x 32, 64 x 16, or 8 x 128
   // for the longest systems.  Fewest modes per block first: a problem's
@@ -1566,33 +1589,14 @@ TriConfig tri_config(bool fp32, int max_rows) {
   if (const char* e = std::getenv("FDS_TRI_SEG")) {
     int mpb = 0, ls = 0;
     if (std::sscanf(e, "%d,%d", &mpb, &ls) == 2 && (mpb == 8 || mpb == 16 || mpb == 32 || mpb == 64) &&
-        (ls == 4 || ls == 8 || ls == 16 || ls == 32)) {
-      const int S = (max_rows + ls - 1) / ls;
-      if (S <= (ls >= 32 ? kTriMaxThreadsLong : 1024) / mpb) {
-        c.seg = true;
-        c.ls = ls;
-        c.mpb = mpb;
-        c.threads = mpb * (S < 1 ? 1 : S);
-        if (c.threads < 64) c.threads = 64;
-        return c;
-      }
-    }
+        (ls == 4 || ls == 8 || ls == 16 || ls == 32) && tri_fit(mpb, ls, max_rows, &c))
+      return c;
   }
   // (8 modes per block last: up to 128 segments, for systems of more than
   // 1024 (FP64 with 16-row segments) or 2048 rows)
-  for (int mpb : {16, 32, 64, 8}) {
-    for (int ls = 8; ls <= lsmax; ls *= 2) {
-      const int S = (max_rows + ls - 1) / ls;
-      if (S <= (ls >= 32 ? kTriMaxThreadsLong : 1024) / mpb) {
-        c.seg = true;
-        c.ls = ls;
-        c.mpb = mpb;
-        c.threads = mpb * (S < 1 ? 1 : S);
-        if (c.threads < 64) c.threads = 64;
-        return c;
-      }
-    }
-  }
+  for (int mpb : {16, 32, 64, 8})
+    for (int ls = 8; ls <= lsmax; ls *= 2)
+      if (tri_fit(mpb, ls, max_rows, &c)) return c;
   return c;
 }
 

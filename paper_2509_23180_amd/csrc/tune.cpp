@@ -1,4 +1,4 @@
-// Autotuner for the row sine transform.
+// Autotuners for the row sine transform and the segmented tridiagonal solve.
 //
 // Which implementation of the DST-I is fastest depends on the length (the
 // factorisation of n + 1 decides between mixed-radix, Rader and Bluestein
@@ -11,8 +11,9 @@
 //
 // FDS_TUNE_FILE names a table of earlier measurements on this kind of device
 // ("n precision variant" per line, precision 0 FP64 / 1 FP32, variant
-// wave|wavebig|fft|gemm): a length found there is not measured again, and a
-// new measurement is appended to the file (when it is writable).  Request
+// wave|wavebig|fft|gemm; "tri rows precision mpb ls" for the tridiagonal
+// solve): an entry found there is not measured again, and a new measurement
+// is appended to the file (when it is writable).  Request
 // paths that build plans as requests arrive use it so that a new length does
 // not cost a device measurement.
 #include <algorithm>
@@ -91,24 +92,38 @@ const char* variant_name(const DstChoice& c) {
   return c.gemm ? "gemm" : c.wave_big ? "wavebig" : c.wave_e ? "wave" : "fft";
 }
 
-// The table of FDS_TUNE_FILE, read once: (n, fp32) -> variant.
-std::map<std::pair<int, bool>, std::string>& tune_table() {
-  static std::map<std::pair<int, bool>, std::string> table;
-  static bool loaded = false;
-  if (!loaded) {
-    loaded = true;
+// The tables of FDS_TUNE_FILE, read once (under the caller's lock):
+// transforms (n, fp32) -> variant, tridiagonal solves (rows, fp32) ->
+// (modes per block, rows per segment; 0 0 for the unsegmented kernel).
+struct TuneTables {
+  std::map<std::pair<int, bool>, std::string> dst;
+  std::map<std::pair<int, bool>, std::pair<int, int>> tri;
+};
+
+TuneTables& tune_tables() {
+  static TuneTables t;
+  static std::once_flag once;
+  std::call_once(once, [] {
     if (const char* path = std::getenv("FDS_TUNE_FILE")) {
       std::ifstream in(path);
-      int n = 0, prec = 0;
-      std::string mode;
-      while (in >> n >> prec >> mode)
-        if (n > 0 && (prec == 0 || prec == 1) &&
-            (mode == "wave" || mode == "wavebig" || mode == "fft" || mode == "gemm"))
-          table[{n, prec != 0}] = mode;
+      std::string line;
+      while (std::getline(in, line)) {
+        char mode[32] = {0};
+        int n = 0, prec = 0, mpb = 0, ls = 0;
+        if (std::sscanf(line.c_str(), "tri %d %d %d %d", &n, &prec, &mpb, &ls) == 4) {
+          if (n > 0 && (prec == 0 || prec == 1)) t.tri[{n, prec != 0}] = {mpb, ls};
+        } else if (std::sscanf(line.c_str(), "%d %d %31s", &n, &prec, mode) == 3) {
+          const std::string m = mode;
+          if (n > 0 && (prec == 0 || prec == 1) && (m == "wave" || m == "wavebig" || m == "fft" || m == "gemm"))
+            t.dst[{n, prec != 0}] = m;
+        }
+      }
     }
-  }
-  return table;
+  });
+  return t;
 }
+
+std::map<std::pair<int, bool>, std::string>& tune_table() { return tune_tables().dst; }
 
 void tune_table_append(int n, bool fp32, const char* mode) {
   const char* path = std::getenv("FDS_TUNE_FILE");
@@ -117,6 +132,41 @@ void tune_table_append(int n, bool fp32, const char* mode) {
     std::fprintf(f, "%d %d %s\n", n, fp32 ? 1 : 0, mode);
     std::fclose(f);
   }
+}
+
+void tri_table_append(int rows, bool fp32, const TriConfig& c) {
+  const char* path = std::getenv("FDS_TUNE_FILE");
+  if (!path) return;
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "tri %d %d %d %d\n", rows, fp32 ? 1 : 0, c.seg ? c.mpb : 0, c.seg ? c.ls : 0);
+    std::fclose(f);
+  }
+}
+
+// Milliseconds per launch of a tridiagonal configuration on `modes` systems
+// of `rows` rows.
+double time_tri(const TriConfig& c, bool fp32, int rows, int modes, void* data, const void* coef,
+                hipStream_t s) {
+  TriTask t{};
+  t.data = data; t.rs = modes; t.js = 0; t.rows = rows; t.modes = modes; t.coef = coef;
+  DevBuf task(sizeof(TriTask));
+  FDS_HIP(hipMemcpyAsync(task.get(), &t, sizeof(t), hipMemcpyHostToDevice, s));
+  const int nb = tri_blocks(c, modes);
+  launch_tri(c, fp32, task.as<TriTask>(), 1, nb, 0, s);   // warm-up
+  hipEvent_t a, b;
+  FDS_HIP(hipEventCreate(&a));
+  FDS_HIP(hipEventCreate(&b));
+  const int reps = 4;
+  FDS_HIP(hipEventRecord(a, s));
+  for (int r = 0; r < reps; ++r) launch_tri(c, fp32, task.as<TriTask>(), 1, nb, 0, s);
+  FDS_HIP(hipEventRecord(b, s));
+  FDS_HIP(hipEventSynchronize(b));
+  float ms = 0;
+  FDS_HIP(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  FDS_HIP(hipGetLastError());
+  return ms / reps;
 }
 
 }  // namespace
@@ -180,6 +230,70 @@ DstChoice dst_tuned_choice(int n, bool fp32) {
   }
   tuned[key] = best;
   if (cand.size() > 1) tune_table_append(n, fp32, variant_name(best));
+  return best;
+}
+
+}  // namespace fds
+
+namespace fds {
+
+// Segmentation of the per-mode tridiagonal solve, measured like the
+// transforms: on the first request for (device, rows, precision) every
+// instantiated configuration that holds the rows solves a synthetic batch
+// (about 32 MB), and the fastest is kept (and appended to FDS_TUNE_FILE).
+TriConfig tri_config(bool fp32, int rows) {
+  const char* seg = std::getenv("FDS_TRI_SEG");
+  const char* tune = std::getenv("FDS_TRI_TUNE");
+  if (seg || (tune && std::string(tune) == "0")) return tri_config_static(fp32, rows);
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, bool>, TriConfig> tuned;
+  int dev = 0;
+  FDS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_tuple(dev, rows, fp32);
+  auto it = tuned.find(key);
+  if (it != tuned.end()) return it->second;
+  const std::vector<TriConfig> cand = tri_configs(rows);
+  {
+    const auto& table = tune_tables().tri;   // read-only once loaded
+    auto t = table.find({rows, fp32});
+    if (t != table.end()) {
+      for (const TriConfig& c : cand)
+        if ((!c.seg && t->second.first == 0) || (c.seg && c.mpb == t->second.first && c.ls == t->second.second)) {
+          tuned[key] = c;
+          return c;
+        }
+    }
+  }
+  TriConfig best = cand[0];
+  if (cand.size() > 1) {
+    const size_t w = fp32 ? 4 : 8;
+    const int modes = std::max(64, std::min(65536, (1 << 22) / std::max(rows, 1)));
+    hipStream_t s;
+    FDS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    {
+      DevBuf data((size_t)rows * modes * w);
+      FDS_HIP(hipMemsetAsync(data.get(), 0, data.size(), s));
+      auto tab = TableCache::get().modes(modes, rows, 1.0 / (std::max(rows, modes) + 1), 0.0, true);
+      const void* coef = fp32 ? (const void*)tab->c32 : (const void*)tab->c64;
+      double tbest = -1;
+      const bool log = std::getenv("FDS_TUNE_LOG") != nullptr;
+      for (const TriConfig& c : cand) {
+        const double ms = time_tri(c, fp32, rows, modes, data.get(), coef, s);
+        if (log)
+          std::fprintf(stderr, "[fds tune] tri rows=%d %s modes=%d mpb=%d ls=%d: %.1f us\n", rows,
+                       fp32 ? "fp32" : "fp64", modes, c.mpb, c.ls, ms * 1e3);
+        if (tbest < 0 || ms < tbest) {
+          tbest = ms;
+          best = c;
+        }
+      }
+      FDS_HIP(hipStreamSynchronize(s));
+    }
+    (void)hipStreamDestroy(s);
+  }
+  tuned[key] = best;
+  if (cand.size() > 1) tri_table_append(rows, fp32, best);
   return best;
 }
 
