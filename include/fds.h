@@ -315,15 +315,19 @@ const char* fds_last_error(void);
  * (off by default).  Classes: 0 sine transforms (k_dst_wave, k_dst_rows or
  * k_dst_gemm, whichever the tuner picked per length), 1 tridiagonal solves
  * (k_tridiag_seg or k_tridiag), 2 centre operator (k_operator, k_spec_op),
- * 3 Gram-Schmidt dot products (k_gram_dots or k_gram_bdots), 4 Schur line
- * terms (k_lines_dense or k_schur_lines), 5 other small kernels, 6
- * Gram-Schmidt update (k_gram_update or k_gram_update_lag), 7 boundary
- * columns (k_idst_cols).
- * `mask` selects the classes to time (bit c = class c; 0 = off).
+ * 3 Gram-Schmidt dot products (k_gram_dots, k_gram_bdots or k_ik_wdots),
+ * 4 Schur line terms (k_lines_dense, the line transforms, or k_ik_cross),
+ * 5 other small kernels, 6 Gram-Schmidt update (k_gram_update,
+ * k_gram_update_lag or k_ik_update), 7 boundary columns (k_idst_cols).
+ * `mask` selects the classes to time (bit c = class c; 0 = off).  Launches
+ * from several threads (a server's groups) are each attributed to their own
+ * thread's class.
  * fds_timing_read returns, per class, the launches timed, their summed
  * duration and the algorithmic bytes (minimal HBM traffic: every operand
  * read once and every result written once) the solver's work in those
- * launches required, all since the last reset. */
+ * launches required, all since the last reset.  fds_timing_read and
+ * fds_timing_reset wait for the timed launches; call them when no timed
+ * launch is being issued (e.g. between benchmark phases). */
 fds_status fds_timing_enable(int32_t mask);
 fds_status fds_timing_read(int32_t cls, int64_t* calls, double* total_ms);
 fds_status fds_timing_bytes(int32_t cls, double* algorithmic_bytes);

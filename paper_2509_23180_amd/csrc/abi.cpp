@@ -47,7 +47,6 @@ struct TimingState {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   hipEvent_t open[kClasses] = {};
-  int armed = -1;
   long long calls[kClasses] = {};
   double ms[kClasses] = {};
 
@@ -76,6 +75,10 @@ TimingState& timing() {
   return t;
 }
 
+// The class open on this thread (launches of several threads, e.g. the
+// server's groups, are attributed to their own thread's class).
+thread_local int t_armed = -1;
+
 }  // namespace
 
 namespace fds {
@@ -99,24 +102,21 @@ double Timing::bytes(int cls) {
 void Timing::begin(int cls, hipStream_t) {
   TimingState& t = timing();
   if (!((t.mask >> cls) & 1)) return;
-  std::lock_guard<std::mutex> lk(t.mu);
-  t.armed = cls;
+  t_armed = cls;
 }
 void Timing::end(int cls, hipStream_t) {
-  TimingState& t = timing();
-  if (!((t.mask >> cls) & 1)) return;
-  std::lock_guard<std::mutex> lk(t.mu);
-  if (t.armed == cls) t.armed = -1;
+  if (t_armed == cls) t_armed = -1;
 }
+// A pair handed out here is recorded by the caller's launch after the lock
+// is released, so pairs are read back (and their events reused) only by
+// read() and reset(), which must not overlap timed launches.
 bool Timing::take_pair(hipEvent_t* a, hipEvent_t* b) {
+  if (t_armed < 0) return false;
   TimingState& t = timing();
-  if (t.armed < 0) return false;
   std::lock_guard<std::mutex> lk(t.mu);
-  if (t.armed < 0) return false;
-  if (t.pending.size() >= 8192) t.flush();  // every pending pair was recorded
   *a = t.take();
   *b = t.take();
-  t.pending.push_back({t.armed, *a, *b});
+  t.pending.push_back({t_armed, *a, *b});
   return true;
 }
 void Timing::read(int cls, long long* calls, double* ms) {
