@@ -15,7 +15,8 @@ Prints ONE JSON line (solves/s, p50/p99 latency, roofline of the dominant
 kernel, CPU oracle baseline).  Diagnostics go to stderr.
 
 Other workloads (--workload): "plain" (cross of 256x256 per square, 18 solves
-per step, GMRES(30) FP64), "precision" (cross 1024x1024 per square,
+per step, GMRES(30) FP64), "interface" (cross of 1024x1024 per square, 4
+solves per step, the interface GMRES(80) path without the server), "precision" (cross 1024x1024 per square,
 FGMRES(40) with an FP32 preconditioner, error against the SuperLU oracle),
 "batching" (64 composite problems x 8 right-hand sides, sizes 64..512,
 FGMRES(40); also with cycle graphs and without the transform tuner),
@@ -188,6 +189,16 @@ def build_workload(name, device):
                 "solves_per_step": len(items), "n": 1024, "restart_m": 40, "tol": 1e-10,
                 "precision": "fp32-preconditioned"}
         opts = dict(restart_m=40, precision=1)
+    elif name == "interface":
+        for kappa in (0.0, -50.0):
+            items.append(workloads.manufactured_problem("cross", 1024, kappa))
+            items.append(workloads.gaussian_problem("cross", 1024, kappa, 2, 0, 0))
+        desc = {"workload": "cross, 1024x1024 interior nodes per square (5,246,976 unknowns per solve), "
+                            "interface Krylov GMRES(80) in FP64, rel-res 1e-10, kappa in {0,-50} x "
+                            "{manufactured, seeded Gaussian} right-hand sides, one batch of 4 solves per step",
+                "solves_per_step": len(items), "n": 1024, "restart_m": 80, "tol": 1e-10,
+                "precision": "fp64"}
+        opts = dict(restart_m=80, precision=0, flags=1)
     elif name == "batching":
         specs = workloads.batch_workload()
         items = [s.build() for s in specs]
@@ -714,7 +725,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=None,
                     help="warm-up steps (serving: seconds of arrivals before the measured window; default 2)")
     ap.add_argument("--workload", default="serving",
-                    choices=["serving", "plain", "precision", "batching", "convergence"])
+                    choices=["serving", "plain", "precision", "batching", "interface", "convergence"])
     ap.add_argument("--serving-rate", type=float, default=200.0, help="requests per second")
     ap.add_argument("--serving-compare-seconds", type=float, default=5.0,
                     help="measured seconds of the trace replayed on the comparison paths")
@@ -729,6 +740,8 @@ def main():
     ap.add_argument("--no-oracle-error", action="store_true",
                     help="precision workload: skip the error against the FP64 oracle")
     ap.add_argument("--latency-solves", type=int, default=10)
+    ap.add_argument("--roofline-class", default="auto",
+                    help="batch workloads: kernel class of the roofline line (default: the dominant one)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (HBM counter calibration)")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
@@ -817,6 +830,8 @@ def main():
                          "GB/s": round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 and by > 0 else None}
     dominant = max((k for k in classes if k != "other"), key=lambda k: classes[k]["ms"])
     log(f"per-class (one step, all classes timed): {classes}; dominant: {dominant}")
+    if args.roofline_class != "auto":
+        dominant = args.roofline_class
 
     # timed region: the dominant class carries HIP events (on the stream it is
     # launched on) in one of the timed steps, the middle one.  Every step is
@@ -925,7 +940,7 @@ def main():
         line["error_vs_oracle"] = error_vs_oracle
     if variants is not None:
         line["variants_solves_per_s"] = variants
-    if args.workload != "plain":
+    if args.workload not in ("plain", "interface"):
         line["dtype"] = "f64+f32"
     print(json.dumps(line), flush=True)
 

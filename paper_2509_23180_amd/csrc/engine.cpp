@@ -358,13 +358,25 @@ struct TaskSet {
     blob.add(fin_copy);
     blob.upload(s);
   }
+  // called with the line class open: the two transforms of the transform
+  // path are timed with the transform class
   void launch_x_lines(hipStream_t s) const {
     launch_lines_dense(x_lines_d.dev(), x_lines_d.n(), x_lines_d.nblocks, lmax_dense, 0, s);
-    if (x_lnm.n()) {
-      x_lnf.launch(0, s);
-      launch_copy(x_lnm.dev(), x_lnm.n(), x_lnm.nblocks, s);
-      x_lni.launch(0, s);
-    }
+    if (x_lnm.n()) launch_line_stages(x_lnf, x_lnm, x_lni, 0, s);
+  }
+  static void launch_line_stages(const DstStage& fwd, const TaskList<CopyTask>& mul, const DstStage& inv,
+                                 int jidx, hipStream_t s) {
+    Timing::end(4, s);
+    Timing::begin(0, s);
+    fwd.launch(jidx, s);
+    Timing::end(0, s);
+    Timing::begin(4, s);
+    launch_copy(mul.dev(), mul.n(), mul.nblocks, s);
+    Timing::end(4, s);
+    Timing::begin(0, s);
+    inv.launch(jidx, s);
+    Timing::end(0, s);
+    Timing::begin(4, s);
   }
   // S (gs * (S z)) on one line into `out`, through `tmp` (L doubles each)
   static void add_line_stages(DstStage& fwd, TaskList<CopyTask>& mul, DstStage& inv, const double* z,
@@ -757,11 +769,7 @@ void TaskSet::iteration(int j, int* flags_dev, int tag, hipStream_t s) const {
   if (it_lnm.n() || it_lines_d.n()) {
     Timing::begin(4, s);
     launch_lines_dense(it_lines_d.dev(), it_lines_d.n(), it_lines_d.nblocks, lmax_dense, j, s);
-    if (it_lnm.n()) {
-      it_lnf.launch(j, s);
-      launch_copy(it_lnm.dev(), it_lnm.n(), it_lnm.nblocks, s);
-      it_lni.launch(j, s);
-    }
+    if (it_lnm.n()) launch_line_stages(it_lnf, it_lnm, it_lni, j, s);
     Timing::end(4, s);
   }
   Timing::begin(3, s);
@@ -843,9 +851,17 @@ void TaskSet::end_of_cycle(int max_cycles, hipStream_t s) const {
 
 // Line term of one arm: the line in and out, plus the dense operator when
 // the term is a dense product.
-double line_bytes(const ArmInfo& a) {
-  const double mat = (dense_lines(a.L) && a.gs->mfull) ? 8.0 * a.L * a.L : 0.0;
-  return 16.0 * a.L + mat;
+// Algorithmic bytes of `times` Schur line terms of one arm: the dense
+// operator (line class: the line in and out, the matrix), or two line
+// transforms (transform class: in and out each) around the coefficient
+// scaling (line class: the line in and out, the coefficients).
+void add_line_bytes(const ArmInfo& a, double times) {
+  if (dense_lines(a.L) && a.gs->mfull) {
+    Timing::add_bytes(4, times * (16.0 * a.L + 8.0 * a.L * a.L));
+  } else {
+    Timing::add_bytes(0, times * 32.0 * a.L);
+    Timing::add_bytes(4, times * 24.0 * a.L);
+  }
 }
 
 }  // namespace
@@ -1112,8 +1128,12 @@ void Engine::Impl::setup_phase(TaskSet& ts) {
   }
   launch_copy(ts.setup_copy.dev(), ts.setup_copy.n(), ts.setup_copy.nblocks, s);
   launch_iface(ts.iface_fp.dev(), ts.iface_fp.n(), s);
+  Timing::begin(4, s);
   ts.launch_x_lines(s);
+  Timing::end(4, s);
+  Timing::begin(2, s);
   launch_operator(1, ts.res_op.dev(), ts.res_op.n(), ts.res_op.nblocks, 0, s);
+  Timing::end(2, s);
   if (ik) {
     launch_restart_decide(ts.kry.dev(), ts.kry.n(), 1, max_cycles, s);
     ts.ik_cycle_start(s);
@@ -1287,13 +1307,9 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
       Timing::add_bytes(1, Nc * (16.0 + 24.0));
       Timing::add_bytes(0, Nc * (24.0 + 16.0));
       Timing::add_bytes(7, Nc * 8.0);
-      double lines = 0;
-      for (const ArmInfo& a : sl.plan->arms) lines += line_bytes(a);
-      Timing::add_bytes(4, lines);
+      for (const ArmInfo& a : sl.plan->arms) add_line_bytes(a, 1.0);
       continue;
     }
-    double lines = 0;
-    for (const ArmInfo& a : sl.plan->arms) lines += line_bytes(a);
     // per Arnoldi step (sine basis): the tridiagonal solve reads v_j, writes
     // it back normalised and writes z^ (FP64 plain, FP32 z^_j flexible); the
     // boundary columns read z^ (plain: and v_j); flexible: the dot pass also
@@ -1309,7 +1325,9 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
     } else {
       Timing::add_bytes(7, its * Nc * 16.0);   // z^ and v_j row sums
     }
-    Timing::add_bytes(4, its * lines);
+    // W/E line terms per step (the S/N blocks are diagonal in the sine basis)
+    for (const ArmInfo& a : sl.plan->arms)
+      if (a.line >= 2) add_line_bytes(a, its);
     double dots = 0, upd = 0;
     const bool lagged = gram_lag_enabled(m, flex);
     const double bnd = 2.0 * (sl.plan->nx + sl.plan->ny);   // boundary-line points
@@ -1334,7 +1352,7 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
     Timing::add_bytes(0, Nc * (24.0 + 16.0));
     if (!flex) Timing::add_bytes(1, Nc * 16.0);
     Timing::add_bytes(2, Nc * 24.0);
-    Timing::add_bytes(4, lines);
+    for (const ArmInfo& a : sl.plan->arms) add_line_bytes(a, 1.0);
   }
 }
 
@@ -1347,10 +1365,8 @@ void Engine::Impl::account_arms(const std::vector<Problem*>& probs, bool setup_p
     }
     const double Nc = (double)sl->Nc;
     if (setup_phase) {
-      double lines = 0;
-      for (const ArmInfo& a : sl->plan->arms) lines += line_bytes(a);
       Timing::add_bytes(2, Nc * 24.0);
-      Timing::add_bytes(4, lines);
+      for (const ArmInfo& a : sl->plan->arms) add_line_bytes(a, 1.0);
     }
   }
 }
