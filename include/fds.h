@@ -29,12 +29,19 @@
  * Geometry and layout (fds_plan_create)
  *   Rectangles are closed boxes of grid-node indices (i0, j0, i1, j1); node
  *   (i, j) sits at (i h, j h); interior nodes are i0 < i < i1, j0 < j < j1.
- *   Exactly one rectangle is the coupled "centre": the one that shares an edge
- *   with the most others (ties: first listed).  Every other rectangle must
- *   share one FULL side of the centre (same extent) and no edge with any
- *   other rectangle.  Nodes strictly inside a shared edge are unknowns owned
- *   by the non-centre rectangle ("arms own their interface line").  Corner
- *   nodes of shared edges and all other boundary nodes are Dirichlet nodes.
+ *   Coupled subdomains are the rectangles that share an edge with two or
+ *   more others; without one, the coupled "centre" is the rectangle that
+ *   shares an edge with the most others (ties: first listed).  Several
+ *   coupled rectangles (Section 2.4, closing remark: longer concatenations)
+ *   must form a straight chain of equal width, each sharing a full side with
+ *   the next; they and the lines between them are solved as ONE coupled
+ *   block M (the union's interior).  Every other rectangle must share one
+ *   FULL side of M (same extent) and no edge with any other rectangle.
+ *   Nodes strictly inside a shared edge are unknowns: owned by the
+ *   non-coupled rectangle on an edge of M ("arms own their interface line"),
+ *   and by the rectangle listed first on an edge between two coupled ones.
+ *   Corner nodes of shared edges and all other boundary nodes are Dirichlet
+ *   nodes.  At most 64 rectangles.
  *
  *   Unknown vector (rhs, x): rectangle by rectangle in the given order, the
  *   owned nodes in row-major order (j ascending outer, i ascending inner).

@@ -2,11 +2,14 @@
 from the C header's definition.  Test infrastructure only.
 
 Definition (as documented for fds_plan_create):
-* Rectangles are closed node boxes (i0, j0, i1, j1).  The coupled subdomain
-  (the "centre") is the rectangle that shares an edge with the largest number
-  of other rectangles; ties go to the first listed.
-* A rectangle owns its interior nodes.  A rectangle other than the centre also
-  owns the nodes strictly inside the edge it shares with the centre.
+* Rectangles are closed node boxes (i0, j0, i1, j1).  The coupled subdomains
+  are the rectangles that share an edge with two or more others; when there is
+  none, the coupled subdomain (the "centre") is the rectangle that shares an
+  edge with the largest number of others, ties going to the first listed.
+* A rectangle owns its interior nodes.  The nodes strictly inside an edge
+  shared by a coupled and a non-coupled rectangle belong to the non-coupled
+  one; those strictly inside an edge shared by two coupled rectangles belong
+  to the one listed first.
 * The unknown vector lists, rectangle by rectangle in the given order, the
   owned nodes in row-major order (j ascending outer, i ascending inner).
 * The Dirichlet data vector lists, rectangle by rectangle, the values on the
@@ -33,28 +36,48 @@ def _share_edge(a: Rect, b: Rect) -> bool:
     return False
 
 
-def centre_index(rects: Sequence[Rect]) -> int:
+def coupled_indices(rects: Sequence[Rect]) -> List[int]:
     counts = [sum(_share_edge(a, b) for b in rects if b is not a) for a in rects]
-    best = max(counts)
-    return counts.index(best)
+    several = [r for r, k in enumerate(counts) if k >= 2]
+    if several:
+        return several
+    return [counts.index(max(counts))]
+
+
+def centre_index(rects: Sequence[Rect]) -> int:
+    """The single coupled rectangle (geometries with one coupled subdomain)."""
+    cs = coupled_indices(rects)
+    if len(cs) != 1:
+        raise ValueError("geometry has several coupled subdomains")
+    return cs[0]
+
+
+def _edge_owner(rects: Sequence[Rect], coupled: Sequence[int], r: int, q: int) -> int:
+    if (r in coupled) != (q in coupled):
+        return q if r in coupled else r
+    return min(r, q)
 
 
 def owned_nodes(rects: Sequence[Rect]) -> List[Tuple[np.ndarray, np.ndarray]]:
     """For each rectangle, (j, i) index arrays of its owned nodes in order."""
-    c = centre_index(rects)
+    coupled = coupled_indices(rects)
     out = []
     for r, (i0, j0, i1, j1) in enumerate(rects):
         ilo, ihi, jlo, jhi = i0 + 1, i1 - 1, j0 + 1, j1 - 1   # inclusive interior
-        if r != c:
-            ci0, cj0, ci1, cj1 = rects[c]
-            if i0 == ci1:
-                ilo = i0        # east arm owns its west edge
-            elif i1 == ci0:
-                ihi = i1        # west arm owns its east edge
-            elif j0 == cj1:
-                jlo = j0        # north arm owns its south edge
-            elif j1 == cj0:
-                jhi = j1        # south arm owns its north edge
+        for q, other in enumerate(rects):
+            if q == r or not _share_edge(rects[r], other):
+                continue
+            if _edge_owner(rects, coupled, r, q) != r:
+                continue
+            oi0, oj0, oi1, oj1 = other
+            if i0 == oi1:
+                ilo = i0        # owns its west edge
+            elif i1 == oi0:
+                ihi = i1        # owns its east edge
+            elif j0 == oj1:
+                jlo = j0        # owns its south edge
+            elif j1 == oj0:
+                jhi = j1        # owns its north edge
         jj, ii = np.meshgrid(np.arange(jlo, jhi + 1), np.arange(ilo, ihi + 1), indexing="ij")
         out.append((jj.ravel(), ii.ravel()))
     return out

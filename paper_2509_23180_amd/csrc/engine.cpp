@@ -400,7 +400,7 @@ struct TaskSet {
 void TaskSet::add_problem(Problem& sl) {
   probs.push_back(&sl);
   fds_plan* p = sl.plan;
-  const RectDev& cd = p->rd[p->centre];
+  const RectDev& cd = p->cdev;
   const int nx = p->nx, ny = p->ny;
   const long long Nc = sl.Nc;
   const int* skip_it = &sl.st->cycle_done;
@@ -625,7 +625,7 @@ void TaskSet::add_problem(Problem& sl) {
   }
   // set-up copies: f'_c starts as b_c and x_c at zero; the back substitution
   // starts the arms from b_a
-  const long long coff = p->rd[p->centre].off;
+  const long long coff = p->cdev.off;
   auto copy = [&](TaskList<CopyTask>& tl, double* dst, const double* src, long long count) {
     if (count <= 0) return;
     const int nb = std::max(1, div_up(count, (long long)kBlock * 8));

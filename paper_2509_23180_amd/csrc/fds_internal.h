@@ -14,6 +14,7 @@ namespace fds {
 constexpr int kMaxPass = 24;     // radix passes of one FFT plan
 constexpr int kBlock = 256;      // threads per block for most kernels
 constexpr int kMaxArms = 4;
+constexpr int kMaxRects = 64;     // rectangles per plan (a chain and its two end arms)
 constexpr int kVecEPT = 8;       // centre-vector elements per thread in reduction kernels
 constexpr int kVecPerBlock = kBlock * kVecEPT;
 
@@ -321,6 +322,8 @@ __host__ __device__ inline size_t kry_partials_len(int m, int P) {
 struct RectDev {
   int rows, cols;
   long long off;              // into the internal vectors
+  long long ld;               // internal row stride (cols, or the width of the
+                              // merged coupled block the rectangle is part of)
   long long user_off;         // into the user unknown vector
   long long bc_off;           // into the user Dirichlet-data vector
   int ai, ar, ac, aj, br, bcc;

@@ -1362,8 +1362,9 @@ __global__ void __launch_bounds__(kBlock) k_lift(const LiftTask* __restrict__ ta
     const int i = rd.ai + rd.ar * r + rd.ac * c;
     const int j = rd.aj + rd.br * r + rd.bcc * c;
     const long long uidx = rd.user_off + (long long)(j - rd.jlo) * rd.uwidth + (i - rd.ilo);
+    const long long iidx = rd.off + (long long)r * rd.ld + c;
     if (MODE == 1) {
-      tk.xuser[uidx] = tk.xint[rd.off + e];
+      tk.xuser[uidx] = tk.xint[iidx];
       continue;
     }
     double v = tk.rhs[uidx];
@@ -1389,7 +1390,7 @@ __global__ void __launch_bounds__(kBlock) k_lift(const LiftTask* __restrict__ ta
         v -= tk.delta * tk.bc[rd.bc_off + (long long)(bq - rd.bj0) * bw + (a - rd.bi0)];
       }
     }
-    tk.out[rd.off + e] = v;
+    tk.out[iidx] = v;
   }
 }
 
@@ -1419,17 +1420,18 @@ __global__ void __launch_bounds__(kBlock) k_residual(const ResTask* __restrict__
   for (long long e = (long long)b * kBlock + threadIdx.x; e < total; e += stride) {
     const int r = (int)(e / rd.cols);
     const int c = (int)(e - (long long)r * rd.cols);
+    const long long q = (long long)r * rd.ld + c;
     double nb = 0.0;
-    if (r > 0) nb += p[e - rd.cols];
+    if (r > 0) nb += p[q - rd.ld];
     else if (rd.halo_off[0] >= 0) nb += tk.p[rd.halo_off[0] + c * rd.halo_stride[0]];
-    if (r < rd.rows - 1) nb += p[e + rd.cols];
+    if (r < rd.rows - 1) nb += p[q + rd.ld];
     else if (rd.halo_off[1] >= 0) nb += tk.p[rd.halo_off[1] + c * rd.halo_stride[1]];
-    if (c > 0) nb += p[e - 1];
+    if (c > 0) nb += p[q - 1];
     else if (rd.halo_off[2] >= 0) nb += tk.p[rd.halo_off[2] + r * rd.halo_stride[2]];
-    if (c < rd.cols - 1) nb += p[e + 1];
+    if (c < rd.cols - 1) nb += p[q + 1];
     else if (rd.halo_off[3] >= 0) nb += tk.p[rd.halo_off[3] + r * rd.halo_stride[3]];
-    const double Ap = tk.delta * nb + (tk.kappa - 4.0 * tk.delta) * p[e];
-    const double bv = tk.b[rd.off + e];
+    const double Ap = tk.delta * nb + (tk.kappa - 4.0 * tk.delta) * p[q];
+    const double bv = tk.b[rd.off + q];
     const double res = bv - Ap;
     rr += res * res;
     bb += bv * bv;

@@ -15,32 +15,57 @@ import numpy as np
 Rect = Tuple[int, int, int, int]
 
 
-def _centre(rects: Sequence[Rect]) -> int:
-    def touches(a, b):
-        if a[2] == b[0] or a[0] == b[2]:
-            return min(a[3], b[3]) - max(a[1], b[1]) > 0
-        if a[3] == b[1] or a[1] == b[3]:
-            return min(a[2], b[2]) - max(a[0], b[0]) > 0
-        return False
-    deg = [sum(touches(a, b) for k, b in enumerate(rects) if k != r) for r, a in enumerate(rects)]
-    return int(np.argmax(deg))
+def _touches(a, b) -> bool:
+    if a[2] == b[0] or a[0] == b[2]:
+        return min(a[3], b[3]) - max(a[1], b[1]) > 0
+    if a[3] == b[1] or a[1] == b[3]:
+        return min(a[2], b[2]) - max(a[0], b[0]) > 0
+    return False
+
+
+def _coupled(rects: Sequence[Rect]) -> List[int]:
+    """Indices of the coupled rectangles: those touching two or more others,
+    else the first of those touching the most."""
+    deg = [sum(_touches(a, b) for k, b in enumerate(rects) if k != r) for r, a in enumerate(rects)]
+    out = [r for r, d in enumerate(deg) if d >= 2]
+    return out if out else [int(np.argmax(deg))]
 
 
 def owned_box(rects: Sequence[Rect], r: int) -> Tuple[int, int, int, int]:
-    """Inclusive (ilo, ihi, jlo, jhi) node ranges owned by rectangle r."""
-    c = _centre(rects)
+    """Inclusive (ilo, ihi, jlo, jhi) node ranges owned by rectangle r: its
+    interior, plus for a non-coupled rectangle the line it shares with the
+    coupled block, plus for a coupled rectangle each line it shares with a
+    coupled rectangle listed after it."""
+    coupled = _coupled(rects)
     i0, j0, i1, j1 = rects[r]
     ilo, ihi, jlo, jhi = i0 + 1, i1 - 1, j0 + 1, j1 - 1
-    if r != c:
-        ci0, cj0, ci1, cj1 = rects[c]
-        if i0 == ci1:
+    if r in coupled:
+        for q in coupled:
+            if q <= r or not _touches(rects[r], rects[q]):
+                continue
+            qi0, qj0, qi1, qj1 = rects[q]
+            if qi1 == i0:
+                ilo = i0
+            elif qi0 == i1:
+                ihi = i1
+            elif qj1 == j0:
+                jlo = j0
+            elif qj0 == j1:
+                jhi = j1
+        return ilo, ihi, jlo, jhi
+    for q in coupled:
+        if not _touches(rects[r], rects[q]):
+            continue
+        qi0, qj0, qi1, qj1 = rects[q]
+        if i0 == qi1:
             ilo = i0
-        elif i1 == ci0:
+        elif i1 == qi0:
             ihi = i1
-        elif j0 == cj1:
+        elif j0 == qj1:
             jlo = j0
-        elif j1 == cj0:
+        elif j1 == qj0:
             jhi = j1
+        break
     return ilo, ihi, jlo, jhi
 
 

@@ -1,0 +1,148 @@
+"""Several coupled subdomains: straight chains of rectangles (the closing
+remark of Section 2.4).  Every rectangle sharing edges with two others is
+coupled; the chain's coupled rectangles and the lines between them form one
+coupled block, solved by the same preconditioned iteration with the end
+rectangles eliminated by their Schur complements.  Whole solves are compared
+with the global composite direct solve of the oracle."""
+
+import numpy as np
+import pytest
+
+import workloads
+from tests.gpu_util import compare, device_problem, log, oracle_solution
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _fds():
+    import paper_2509_23180_amd as fds
+    return fds
+
+
+def _reorder(rects, order):
+    if order == "reversed":
+        return rects[::-1]
+    if order == "shuffled":
+        return [rects[k] for k in np.random.default_rng(len(rects) + 1).permutation(len(rects))]
+    return list(rects)
+
+
+def _chain_problem(n, lengths, vertical, kappa, kind, order="chain", seed=0):
+    rects = _reorder(workloads.chain_rects(n, lengths, vertical), order)
+    return workloads.rects_problem(rects, 1.0 / (n + 1), kappa, kind, seed)
+
+
+CHAINS = [
+    (24, [25, 25, 25, 25], True, 0.0, "shifted"),         # four squares stacked
+    (24, [25, 25, 25, 25], True, -50.0, "gauss"),
+    (20, [15, 30, 9, 21, 12], False, -10.0, "shifted"),   # five unequal, in a row
+    (16, [17, 17, 17, 17, 17, 17], True, 0.0, "gauss"),   # six: four coupled
+    (7, [2, 3, 2, 5], False, -3.0, "shifted"),            # one-node-long rectangles
+]
+
+
+@pytest.mark.parametrize("order", ["chain", "shuffled"])
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("n,lengths,vertical,kappa,kind", CHAINS)
+def test_chain_parity(n, lengths, vertical, kappa, kind, precision, order):
+    fds = _fds()
+    log(f"chain n={n} lengths={lengths} vertical={vertical} kappa={kappa} {kind} prec={precision} {order}")
+    prob = _chain_problem(n, lengths, vertical, kappa, kind, order)
+    ref = oracle_solution(prob)
+    plan, rhs, bc, x = device_problem(prob, restart_m=30, precision=precision)
+    res = fds.solve(plan, rhs, x, 1e-12, bc=bc)
+    assert res.status == 0, res
+    err = compare(prob, x, ref)
+    log(f"  its={res.iterations} err={err:.3e} relres={res.relres_schur:.2e} global={res.relres_global:.2e}")
+    assert err <= 1e-10
+    assert res.relres_global <= 1e-11
+
+
+@pytest.mark.parametrize("n,lengths,vertical,kappa,kind", [CHAINS[1], CHAINS[2], CHAINS[3]])
+def test_chain_interface_krylov(n, lengths, vertical, kappa, kind):
+    """The interface Krylov iteration on the merged coupled block."""
+    fds = _fds()
+    prob = _chain_problem(n, lengths, vertical, kappa, kind, "reversed")
+    ref = oracle_solution(prob)
+    _, rhs, bc, x = device_problem(prob)
+    plan = fds.Plan(prob.rects, prob.h, prob.kappa, restart_m=30, flags=fds.FLAG_INTERFACE_KRYLOV)
+    res = fds.solve(plan, rhs, x, 1e-12, bc=bc)
+    assert res.status == 0, res
+    err = compare(prob, x, ref)
+    log(f"chain IK n={n} lengths={lengths}: its={res.iterations} err={err:.3e}")
+    assert err <= 1e-10
+
+
+def test_chain_jacobi_preconditioner():
+    fds = _fds()
+    prob = _chain_problem(12, [13, 13, 13, 13], True, -20.0, "gauss")
+    ref = oracle_solution(prob)
+    plan, rhs, bc, x = device_problem(prob, restart_m=60, precision=fds.JACOBI, max_cycles=400)
+    res = fds.solve(plan, rhs, x, 1e-12, bc=bc)
+    assert res.status == 0, res
+    err = compare(prob, x, ref)
+    log(f"chain Jacobi: its={res.iterations} err={err:.3e}")
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_chain_batch_with_other_shapes(precision):
+    """Chains batched with a cross and a T: each equals its solve alone
+    bitwise and the oracle to the FP64 bar."""
+    fds = _fds()
+    probs = [_chain_problem(24, [25, 25, 25, 25], True, -50.0, "gauss", "shuffled"),
+             workloads.gaussian_problem("cross", 40, 0.0, 1, 4, 0),
+             _chain_problem(20, [15, 30, 9, 21, 12], False, -10.0, "shifted"),
+             workloads.manufactured_problem("T", 33, -5.0, shifted=True)]
+    alone = []
+    for p in probs:
+        plan, rhs, bc, x = device_problem(p, precision=precision)
+        r = fds.solve(plan, rhs, x, 1e-11, bc=bc)
+        assert r.status == 0
+        alone.append((x.clone(), r))
+    items = [device_problem(p, precision=precision) for p in probs]
+    res = fds.solve_batch([it[0] for it in items], [it[1] for it in items], [it[3] for it in items],
+                          [1e-11] * len(items), bcs=[it[2] for it in items])
+    for (x_alone, r_alone), it, r, p in zip(alone, items, res, probs):
+        assert r.status == 0
+        assert r.iterations == r_alone.iterations
+        assert torch.equal(it[3], x_alone)
+        err = compare(p, it[3], oracle_solution(p))
+        log(f"chain batch {p.label} precision={precision}: err={err:.3e}")
+        assert err <= 1e-10
+
+
+def test_chain_full_size():
+    """Four 256x256 squares stacked (262,912 unknowns): the coupled block has
+    513 rows, so the tridiagonal solves run on 513-row systems and the Gram
+    passes use the two-level reduction."""
+    fds = _fds()
+    prob = _chain_problem(256, [257] * 4, True, -50.0, "gauss", "shuffled", seed=2)
+    ref = oracle_solution(prob)
+    for precision in (0, 1):
+        plan, rhs, bc, x = device_problem(prob, restart_m=40, precision=precision)
+        res = fds.solve(plan, rhs, x, 1e-12, bc=bc)
+        assert res.status == 0, res
+        err = compare(prob, x, ref)
+        log(f"chain 4x256 precision={precision}: its={res.iterations} err={err:.3e}")
+        assert err <= 1e-10
+
+
+def test_chain_geometry_errors():
+    fds = _fds()
+    N = 9
+    bad = [
+        # a bent chain: its end rectangles do not cover a full side of the coupled block
+        [(0, 0, N, N), (0, N, N, 2 * N), (N, N, 2 * N, 2 * N), (N, 2 * N, 2 * N, 3 * N)],
+        # an arm on one side of one coupled rectangle of a chain
+        [(0, 0, N, N), (0, N, N, 2 * N), (0, 2 * N, N, 3 * N), (0, 3 * N, N, 4 * N),
+         (N, N, 2 * N, 2 * N)],
+        # coupled rectangles of different widths
+        [(0, 0, N, N), (0, N, N, 2 * N), (0, 2 * N, N + 2, 3 * N), (0, 3 * N, N + 2, 4 * N)],
+    ]
+    for rects in bad:
+        with pytest.raises(fds.FdsError) as ei:
+            fds.Plan(rects, 1.0 / N, 0.0)
+        assert ei.value.status == -2, rects

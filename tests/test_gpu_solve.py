@@ -203,7 +203,7 @@ def test_geometry_errors():
     bad = [
         [(0, 0, N, N), (N - 2, 0, 2 * N, N)],                       # overlap
         [(N, N, 2 * N, 2 * N), (2 * N, N, 3 * N, 2 * N - 1)],        # partial side
-        # two coupled subdomains: the north-east square touches both arms
+        # four coupled rectangles (a 2x2 block) that do not form a straight chain
         [(N, N, 2 * N, 2 * N), (N, 2 * N, 2 * N, 3 * N), (2 * N, N, 3 * N, 2 * N),
          (2 * N, 2 * N, 3 * N, 3 * N)],
         [(N, N, 2 * N, 2 * N), (2 * N, N, 3 * N, 2 * N), (2 * N, N - 1, 3 * N, N)],  # arm on arm
@@ -212,7 +212,7 @@ def test_geometry_errors():
     for rects in bad:
         with pytest.raises(fds.FdsError) as ei:
             fds.Plan(rects, 1.0 / N, 0.0)
-            assert ei.value.status == -2, rects
+        assert ei.value.status == -2, rects
 
 
 def test_kappa_positive_paths():

@@ -161,3 +161,84 @@ def test_layout_roundtrip_and_sizes():
         vals = np.random.default_rng(0).normal(size=g.unknown.shape)
         back = layout.from_user(rects, layout.to_user(rects, vals), vals.shape)
         assert np.array_equal(back[g.unknown], vals[g.unknown])
+
+
+# ---------------------------------------------------------------------------
+# Chains of rectangles: several coupled subdomains (closing remark of
+# Section 2.4: the method carries over to longer concatenations)
+# ---------------------------------------------------------------------------
+
+CHAINS = [
+    (6, [7, 7, 7, 7], True),          # four squares stacked
+    (5, [4, 9, 3, 6, 5], False),      # five rectangles of unequal length in a row
+    (4, [5, 5, 5], True),             # three: one coupled rectangle (the L/T case)
+]
+
+
+@pytest.mark.parametrize("n,lengths,vertical", CHAINS)
+@pytest.mark.parametrize("kappa", [0.0, -30.0])
+def test_cubic_polynomials_are_exact_on_chains(n, lengths, vertical, kappa):
+    rects = workloads.chain_rects(n, lengths, vertical)
+    h = 1.0 / (n + 1)
+    I = max(r[2] for r in rects)
+    J = max(r[3] for r in rects)
+    X, Y = np.meshgrid(np.arange(I + 1) * h, np.arange(J + 1) * h, indexing="xy")
+    p = _cubic(X, Y)
+    sol = composite.solve(rects, h, kappa, _cubic_lap(X, Y) + kappa * p, p, method="band_lu")
+    P = sol.on_grid()
+    m = sol.grid.unknown
+    assert m.sum() == sum((r[2] - r[0] - 1) * (r[3] - r[1] - 1) for r in rects) + (len(rects) - 1) * n
+    assert np.max(np.abs(P[m] - p[m])) <= 1e-11 * np.max(np.abs(p[m]))
+
+
+@pytest.mark.parametrize("n,lengths,vertical", CHAINS)
+@pytest.mark.parametrize("order", ["chain", "reversed", "shuffled"])
+def test_chain_layout_owns_every_unknown_once(n, lengths, vertical, order):
+    rects = workloads.chain_rects(n, lengths, vertical)
+    if order == "reversed":
+        rects = rects[::-1]
+    elif order == "shuffled":
+        rects = [rects[k] for k in np.random.default_rng(len(rects)).permutation(len(rects))]
+    g = composite.classify(rects)
+    own = layout.owned_nodes(rects)
+    seen = np.zeros(g.unknown.shape, dtype=int)
+    for jj, ii in own:
+        seen[jj, ii] += 1
+    assert (seen[g.unknown] == 1).all() and (seen[~g.unknown] == 0).all()
+    # the ends are the non-coupled rectangles; each owns the line it shares
+    coupled = layout.coupled_indices(rects)
+    assert len(coupled) == len(rects) - 2
+    for r, (jj, ii) in enumerate(own):
+        i0, j0, i1, j1 = rects[r]
+        if r not in coupled:
+            assert len(jj) == (i1 - i0 - 1) * (j1 - j0 - 1) + n
+    # a line between two coupled rectangles goes to the one listed first
+    for r in coupled:
+        for q in coupled:
+            a, b = rects[r], rects[q]
+            if r < q and (a[3] == b[1] or a[1] == b[3] or a[2] == b[0] or a[0] == b[2]) and \
+                    ((a[0], a[2]) == (b[0], b[2]) or (a[1], a[3]) == (b[1], b[3])):
+                jj, ii = own[r]
+                if vertical:
+                    line_j = a[3] if a[3] == b[1] else a[1]
+                    assert (jj == line_j).sum() == n
+                else:
+                    line_i = a[2] if a[2] == b[0] else a[0]
+                    assert (ii == line_i).sum() == n
+
+
+@pytest.mark.parametrize("rects", [
+    workloads.chain_rects(5, [6, 6, 6, 6], True),
+    workloads.chain_rects(4, [5, 8, 3, 5, 7], False)[::-1],
+    workloads.shape_rects("cross", 5), workloads.shape_rects("T", 4), workloads.shape_rects("pair", 3),
+])
+def test_product_layout_helper_matches_oracle_layout(rects):
+    """The package's packing helper cuts the same owned blocks as the
+    oracle's layout (two independent statements of the header's rule)."""
+    from paper_2509_23180_amd import layout as plog
+    own = layout.owned_nodes(rects)
+    for r in range(len(rects)):
+        ilo, ihi, jlo, jhi = plog.owned_box(rects, r)
+        jj, ii = own[r]
+        assert (jj.min(), jj.max(), ii.min(), ii.max()) == (jlo, jhi, ilo, ihi)
+        assert len(jj) == (jhi - jlo + 1) * (ihi - ilo + 1)

@@ -184,6 +184,57 @@ def gaussian_problem(shape: str, n: int, kappa: float, config_id: int, problem_i
 
 
 # ---------------------------------------------------------------------------
+# Chains of rectangles (several coupled subdomains)
+# ---------------------------------------------------------------------------
+
+def chain_rects(n: int, lengths: Sequence[int], vertical: bool = True) -> List[Rect]:
+    """A straight chain of rectangles, n interior nodes across; rectangle k
+    spans lengths[k] node intervals along the chain.  Listed in chain order
+    from the origin; every rectangle except the two ends shares edges with
+    two others, so those are the coupled subdomains."""
+    N = n + 1
+    out, at = [], 0
+    for L in lengths:
+        if L < 2:
+            raise ValueError("every rectangle needs an interior node")
+        out.append((0, at, N, at + L) if vertical else (at, 0, at + L, N))
+        at += L
+    return out
+
+
+def rects_problem(rects: Sequence[Rect], h: float, kappa: float, kind: str = "shifted",
+                  seed: int = 0) -> Problem:
+    """Problem on an arbitrary concatenation: the manufactured solution
+    (kind "manufactured" / "shifted") or a seeded sum of 16 Gaussians with
+    zero Dirichlet data (kind "gauss"; config id 5, centres by rejection from
+    the bounding box into the union of the closed rectangles)."""
+    I = max(r[2] for r in rects)
+    J = max(r[3] for r in rects)
+    X, Y = np.meshgrid(np.arange(I + 1) * h, np.arange(J + 1) * h, indexing="xy")
+    label = f"{kind}"
+    if kind in ("manufactured", "shifted"):
+        shift = COUPLING_SHIFT if kind == "shifted" else (0.0, 0.0)
+        pe = manufactured_p(X, Y, shift)
+        return Problem("rects", 0, float(kappa), list(rects), h, manufactured_f(X, Y, kappa, shift),
+                       pe.copy(), pe, label=label)
+    if kind != "gauss":
+        raise ValueError(f"unknown kind {kind!r}")
+    rng = rng_for(5, seed, 0)
+    boxes = [(r[0] * h, r[1] * h, r[2] * h, r[3] * h) for r in rects]
+    centres = np.empty((16, 2))
+    k = 0
+    while k < 16:
+        c = rng.uniform((0.0, 0.0), (I * h, J * h))
+        if any(b[0] <= c[0] <= b[2] and b[1] <= c[1] <= b[3] for b in boxes):
+            centres[k] = c
+            k += 1
+    src = GaussianSource(centres, rng.uniform(0.05, 0.2, size=16), rng.normal(0.0, 1.0, size=16))
+    f = src(X, Y)
+    return Problem("rects", 0, float(kappa), list(rects), h, f, np.zeros_like(f), None,
+                   label=f"gauss[5,{seed},0]")
+
+
+# ---------------------------------------------------------------------------
 # Batched and served workloads
 # ---------------------------------------------------------------------------
 
