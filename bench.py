@@ -19,7 +19,9 @@ per step, GMRES(30) FP64), "interface" (cross of 1024x1024 per square, 4
 solves per step, the interface GMRES(80) path without the server), "precision" (cross 1024x1024 per square,
 FGMRES(40) with an FP32 preconditioner, error against the SuperLU oracle),
 "batching" (64 composite problems x 8 right-hand sides, sizes 64..512,
-FGMRES(40); also with cycle graphs and without the transform tuner),
+FGMRES(40); also with cycle graphs and without the transform tuner), "chain"
+(four 512x512 squares stacked, two of them coupled, interface GMRES(80), error
+against the SuperLU oracle),
 "convergence" (iteration counts with P = I, Jacobi and A_c^-1, the iteration
 count against n, a restart sweep).
 """
@@ -197,6 +199,21 @@ def build_workload(name, device):
                             "interface Krylov GMRES(80) in FP64, rel-res 1e-10, kappa in {0,-50} x "
                             "{manufactured, seeded Gaussian} right-hand sides, one batch of 4 solves per step",
                 "solves_per_step": len(items), "n": 1024, "restart_m": 80, "tol": 1e-10,
+                "precision": "fp64"}
+        opts = dict(restart_m=80, precision=0, flags=1)
+    elif name == "chain":
+        n = 512
+        rects = workloads.chain_rects(n, [n + 1] * 4, vertical=True)
+        h = 1.0 / (n + 1)
+        for kappa in (0.0, -50.0):
+            items.append(workloads.rects_problem(rects, h, kappa, "shifted"))
+            for seed in (0, 1):
+                items.append(workloads.rects_problem(rects, h, kappa, "gauss", seed))
+        desc = {"workload": "chain of four 512x512 squares stacked (two coupled, 1,050,112 unknowns "
+                            "per solve; coupled block 512 x 1025), interface Krylov GMRES(80) in FP64, "
+                            "rel-res 1e-10, kappa in {0,-50} x {manufactured, 2 seeded Gaussian} "
+                            "right-hand sides, one batch of 6 solves per step",
+                "solves_per_step": len(items), "n": n, "restart_m": 80, "tol": 1e-10,
                 "precision": "fp64"}
         opts = dict(restart_m=80, precision=0, flags=1)
     elif name == "batching":
@@ -675,8 +692,15 @@ def precision_error(items, xs):
     prob0 = items[0]
     log(f"error vs the FP64 oracle: SuperLU on {prob0.shape} n={prob0.n} ...")
     t0 = time.perf_counter()
-    sols = composite.solve_many(prob0.rects, prob0.h, prob0.kappa,
-                                [(p.f_grid, p.g_grid) for p in items], method="splu")
+    groups = {}
+    for k, p in enumerate(items):
+        groups.setdefault((tuple(p.rects), p.h, p.kappa), []).append(k)
+    sols = [None] * len(items)
+    for (rects, h, kappa), ks in groups.items():
+        for k, sol in zip(ks, composite.solve_many(list(rects), h, kappa,
+                                                   [(items[k].f_grid, items[k].g_grid) for k in ks],
+                                                   method="splu")):
+            sols[k] = sol
     dt = time.perf_counter() - t0
     out = {}
     for prob, sol, x in zip(items, sols, xs):
@@ -684,7 +708,7 @@ def precision_error(items, xs):
         G = olayout.from_user(prob.rects, x.detach().cpu().numpy(), (H, W))
         ref = sol.on_grid()
         m = sol.grid.unknown
-        out[prob.label] = float(np.max(np.abs(G[m] - ref[m])) / np.max(np.abs(ref[m])))
+        out[f"{prob.label} kappa={prob.kappa:g}"] = float(np.max(np.abs(G[m] - ref[m])) / np.max(np.abs(ref[m])))
     log(f"error vs oracle: {out} ({dt:.1f} s)")
     return {"max_rel_err": out, "oracle": "global composite system, SuperLU (scipy splu), FP64",
             "oracle_seconds": round(dt, 1)}
@@ -725,7 +749,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=None,
                     help="warm-up steps (serving: seconds of arrivals before the measured window; default 2)")
     ap.add_argument("--workload", default="serving",
-                    choices=["serving", "plain", "precision", "batching", "interface", "convergence"])
+                    choices=["serving", "plain", "precision", "batching", "interface", "chain",
+                             "convergence"])
     ap.add_argument("--serving-rate", type=float, default=200.0, help="requests per second")
     ap.add_argument("--serving-compare-seconds", type=float, default=5.0,
                     help="measured seconds of the trace replayed on the comparison paths")
@@ -738,7 +763,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-error", action="store_true",
-                    help="precision workload: skip the error against the FP64 oracle")
+                    help="precision and chain workloads: skip the error against the FP64 oracle")
     ap.add_argument("--latency-solves", type=int, default=10)
     ap.add_argument("--roofline-class", default="auto",
                     help="batch workloads: kernel class of the roofline line (default: the dominant one)")
@@ -896,7 +921,7 @@ def main():
             log(f"variant {label}: {variants[label]} solves/s")
 
     error_vs_oracle = None
-    if args.workload == "precision" and not args.no_oracle_error:
+    if args.workload in ("precision", "chain") and not args.no_oracle_error:
         error_vs_oracle = precision_error(items, X)
 
     achieved = (algo_bytes / calls) / ((ms / calls) * 1e-3) / 1e9 if calls and ms > 0 else None
@@ -940,7 +965,7 @@ def main():
         line["error_vs_oracle"] = error_vs_oracle
     if variants is not None:
         line["variants_solves_per_s"] = variants
-    if args.workload not in ("plain", "interface"):
+    if args.workload not in ("plain", "interface", "chain"):
         line["dtype"] = "f64+f32"
     print(json.dumps(line), flush=True)
 
