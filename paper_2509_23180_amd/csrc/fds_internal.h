@@ -15,7 +15,11 @@ constexpr int kMaxPass = 24;     // radix passes of one FFT plan
 constexpr int kBlock = 256;      // threads per block for most kernels
 constexpr int kMaxArms = 4;
 constexpr int kMaxRects = 64;     // rectangles per plan (a chain and its two end arms)
+#if defined(FDS_VEC_EPT)
+constexpr int kVecEPT = FDS_VEC_EPT;   // (development builds: block size A/B)
+#else
 constexpr int kVecEPT = 8;       // centre-vector elements per thread in reduction kernels
+#endif
 constexpr int kVecPerBlock = kBlock * kVecEPT;
 
 // ---------------------------------------------------------------- errors

@@ -1697,13 +1697,22 @@ void launch_gram_update_lag(const KryTask* tasks, int ntasks, int nblocks, int m
                             int tag, hipStream_t s) {
   if (nblocks <= 0) return;
   if (m > kLagMaxJ || j >= m) throw Error(FDS_E_INVALID_ARG, "lagged Gram columns need j < m <= 32");
-  // basis vectors held per round: the smallest MJ >= j + 1; at most 16 (or
-  // 32 for j >= 16) loads per thread and round, which keeps three
-  // wavefronts per SIMD resident (measured best)
-  if (j < 4) FDS_LAUNCH((k_gram_update_lag<4, 4>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
-  else if (j < 8) FDS_LAUNCH((k_gram_update_lag<8, 2>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
-  else if (j < 16) FDS_LAUNCH((k_gram_update_lag<16, 1>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
-  else FDS_LAUNCH((k_gram_update_lag<32, 1>), dim3(nblocks), dim3(kBlock), 0, s, tasks, ntasks, j, flags, tag);
+  // basis vectors held per round: the smallest multiple of 4 >= j + 1 from
+  // 12 on (fewer redundant loads of v_j than powers of two: +1.6% on the
+  // plain workload); at most 32 loads per thread and round, which keeps
+  // three wavefronts per SIMD resident
+#define FDS_LAG(MJ, EU)                                                                         \
+  FDS_LAUNCH((k_gram_update_lag<MJ, (EU < kVecEPT ? EU : kVecEPT)>), dim3(nblocks), dim3(kBlock), 0, s, \
+             tasks, ntasks, j, flags, tag)
+  if (j < 4) FDS_LAG(4, 4);
+  else if (j < 8) FDS_LAG(8, 2);
+  else if (j < 12) FDS_LAG(12, 1);
+  else if (j < 16) FDS_LAG(16, 1);
+  else if (j < 20) FDS_LAG(20, 1);
+  else if (j < 24) FDS_LAG(24, 1);
+  else if (j < 28) FDS_LAG(28, 1);
+  else FDS_LAG(32, 1);
+#undef FDS_LAG
 }
 
 void launch_gram_update(const KryTask* tasks, int ntasks, int nblocks, int j, int* flags, int tag,
