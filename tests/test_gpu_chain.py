@@ -146,3 +146,38 @@ def test_chain_geometry_errors():
         with pytest.raises(fds.FdsError) as ei:
             fds.Plan(rects, 1.0 / N, 0.0)
         assert ei.value.status == -2, rects
+
+
+def test_chain_through_the_server():
+    """Chain requests served beside a cross and an L (interface path and the
+    plain path), each bitwise its solve alone and at the oracle's FP64 bar."""
+    import time
+    fds = _fds()
+    probs = [_chain_problem(24, [25, 25, 25, 25], True, -50.0, "gauss", "shuffled"),
+             workloads.gaussian_problem("cross", 40, 0.0, 1, 4, 0),
+             _chain_problem(20, [15, 30, 9, 21, 12], False, -10.0, "shifted"),
+             workloads.gaussian_problem("L", 33, -10.0, 1, 5, 0)]
+    for flags in (0, fds.FLAG_INTERFACE_KRYLOV):
+        srv = fds.Server(hbm_budget_bytes=1 << 30, max_slots=4)
+        items = []
+        for p in probs:
+            _, rhs, bc, x = device_problem(p)
+            plan = fds.Plan(p.rects, p.h, p.kappa, restart_m=30, flags=flags)
+            items.append((plan, rhs, bc, x))
+        torch.cuda.synchronize()
+        tickets = [srv.submit(it[0], it[1], it[3], 1e-11, bc=it[2]) for it in items]
+        results, t0 = {}, time.time()
+        while len(results) < len(tickets) and time.time() - t0 < 60:
+            got = srv.wait_any(0.1)
+            if got is not None:
+                results[got[0]] = got[1]
+        srv.close()
+        assert len(results) == len(tickets)
+        for p, it, t in zip(probs, items, tickets):
+            assert results[t].status == 0, results[t]
+            x_alone = torch.full_like(it[3], float("nan"))
+            fds.solve(it[0], it[1], x_alone, 1e-11, bc=it[2])
+            assert torch.equal(x_alone, it[3])
+            err = compare(p, it[3], oracle_solution(p))
+            log(f"server flags={flags} {p.label} {p.shape}: err vs oracle {err:.3e}")
+            assert err <= 1e-10
