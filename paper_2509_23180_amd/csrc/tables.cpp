@@ -84,15 +84,17 @@ static bool is_prime(int p) {
 static int bluestein_len(int N) {
   static const int mode = [] {
     const char* e = std::getenv("FDS_BLUE_M");
-    return (e && std::string(e) == "pow2") ? 1 : 0;
+    if (e && std::string(e) == "pow2") return 1;
+    if (e && std::string(e) == "p2") return 2;
+    return 0;
   }();
   int M = 2 * N - 1;
-  if (mode == 1) {
+  if (mode >= 1) {
     int p = 1;
     while (p < M) p *= 2;
     int q = 3;
     while (q < M) q *= 2;
-    return std::min(p, q);
+    return mode == 2 ? p : std::min(p, q);
   }
   auto smooth = [](int v) {
     for (int p : {2, 3, 5}) while (v % p == 0) v /= p;
@@ -185,7 +187,15 @@ static int wave_need(int n, int L, int G, const std::vector<int>& rad) {
 }
 
 // Lanes per row of the one-row-per-workgroup ("big") wave transform.
-static int big_lanes(int L) { return L >= 3072 ? 512 : L >= 1024 ? 256 : 128; }
+static int big_lanes(int L) {
+  static const int forced = [] {
+    const char* e = std::getenv("FDS_DST_BIGG");
+    const int v = e ? std::atoi(e) : 0;
+    return (v == 128 || v == 256 || v == 512) ? v : 0;
+  }();
+  if (forced) return forced;
+  return L >= 3072 ? 512 : L >= 1024 ? 256 : 128;
+}
 
 // FFT schedule of the wave-parallel transform and the lane count its radices
 // are built for.  The workgroup schedule when its radices have register
