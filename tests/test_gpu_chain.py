@@ -40,6 +40,7 @@ CHAINS = [
     (20, [15, 30, 9, 21, 12], False, -10.0, "shifted"),   # five unequal, in a row
     (16, [17, 17, 17, 17, 17, 17], True, 0.0, "gauss"),   # six: four coupled
     (7, [2, 3, 2, 5], False, -3.0, "shifted"),            # one-node-long rectangles
+    (10, [11, 6, 11, 9], True, 1.0, "shifted"),           # small positive kappa (accepted)
 ]
 
 
@@ -58,6 +59,24 @@ def test_chain_parity(n, lengths, vertical, kappa, kind, precision, order):
     log(f"  its={res.iterations} err={err:.3e} relres={res.relres_schur:.2e} global={res.relres_global:.2e}")
     assert err <= 1e-10
     assert res.relres_global <= 1e-11
+
+
+@pytest.mark.parametrize("algo", ["fft", "gemm"])
+def test_chain_other_transform_kernels(algo, monkeypatch):
+    """The workgroup-FFT and dense-sine-matrix transform kernels, and the W/E
+    line terms through the batched transforms, on a chain in a row."""
+    fds = _fds()
+    monkeypatch.setenv("FDS_DST_ALGO", algo)
+    monkeypatch.setenv("FDS_LINES", "fft")
+    prob = _chain_problem(20, [15, 30, 9, 21, 12], False, -10.0, "gauss", "reversed", seed=3)
+    ref = oracle_solution(prob)
+    for precision in (0, 1):
+        plan, rhs, bc, x = device_problem(prob, precision=precision)
+        res = fds.solve(plan, rhs, x, 1e-12, bc=bc)
+        assert res.status == 0, res
+        err = compare(prob, x, ref)
+        log(f"chain {algo} precision={precision}: its={res.iterations} err={err:.3e}")
+        assert err <= 1e-10
 
 
 @pytest.mark.parametrize("n,lengths,vertical,kappa,kind", [CHAINS[1], CHAINS[2], CHAINS[3]])
