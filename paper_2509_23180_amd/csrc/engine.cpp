@@ -157,7 +157,7 @@ struct TriStage {
 
 // Buffer layout of one problem, shared by allocation and footprint queries.
 struct SlotLayout {
-  size_t b_int, x_int, tmpd, fp, V, u, zbuf, lines, small, partials, respart, Z, tmpf, gram, zcols,
+  size_t b_int, x_int, tmpd, ahat, fp, V, u, zbuf, lines, small, partials, respart, Z, tmpf, gram, zcols,
       bc, total;
   // interface Krylov iteration
   size_t V0, Vb, rline, rho, zcol, zc, ucoef, uphys, dhat, xpart, scal, rscale, Wv, dpart, cpart;
@@ -208,6 +208,7 @@ SlotLayout layout_of(const fds_plan* p, int m, int precision) {
   L.b_int = take(8 * Nint);
   L.x_int = take(8 * Nint);
   L.tmpd = take(8 * Nint);
+  L.ahat = take(8 * (Nint - Nc));   // sine coefficients of the arms' right-hand sides
   L.fp = take(8 * Nc);
   if (p->interface_krylov()) {
     const IkGeom g = ik_geom(p);
@@ -260,7 +261,7 @@ struct Problem {
   int id = 0;                     // caller's id (returned by retire)
   int idx = 0;                    // index in the state pool / flag array
   DevBuf mem;
-  double *b_int = nullptr, *x_int = nullptr, *tmpd = nullptr, *fp = nullptr, *V = nullptr,
+  double *b_int = nullptr, *x_int = nullptr, *tmpd = nullptr, *ahat = nullptr, *fp = nullptr, *V = nullptr,
          *u = nullptr, *zbuf = nullptr, *lines = nullptr, *H = nullptr, *cs = nullptr,
          *sn = nullptr, *g = nullptr, *y = nullptr, *partials = nullptr, *respart = nullptr,
          *G = nullptr, *hv = nullptr, *zcols = nullptr, *bc = nullptr;
@@ -290,7 +291,11 @@ bool gram_lag_enabled(int m, bool flex) {
 struct TaskSet {
   int m = 0;
   bool flex = false;
-  DstStage cyc_fwd, cyc_inv, arm_fwd, arm_inv, bs_fwd;
+  // arms: the forward transform of b_a is kept (ahat); the set-up needs the
+  // solution's interface row only, and the back substitution changes the
+  // right-hand side in the interface row only, so each takes a one-row
+  // transform instead of a whole-arm one
+  DstStage cyc_fwd, cyc_inv, arm_fwd, arm_inv, arm_inv0, bs_fwd0;
   TriStage it_tri, cyc_tri, arm_tri;
   TaskList<LineTask> it_lines_d, x_lines_d;  // dense line operators
   // line terms without a dense operator: S (gs * (S z_line)) by the batched
@@ -309,7 +314,7 @@ struct TaskSet {
   TaskList<IfaceTask> iface_fp, iface_bs;
   TaskList<ResTask> resid;
   TaskList<ResSumTask> res_sum;
-  TaskList<CopyTask> setup_copy, fin_copy;
+  TaskList<CopyTask> setup_copy, fin_copy, arm_copy;
   std::vector<Problem*> probs;
   Blob blob;
 
@@ -331,7 +336,8 @@ struct TaskSet {
   void ik_cycle_start(hipStream_t s) const;
   void add_problem(Problem& sl);
   void upload(hipStream_t s) {
-    for (DstStage* d : {&cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &bs_fwd, &ik_lfwd, &ik_linv, &it_jinv, &it_jfwd,
+    for (DstStage* d : {&cyc_fwd, &cyc_inv, &arm_fwd, &arm_inv, &arm_inv0, &bs_fwd0, &ik_lfwd, &ik_linv, &it_jinv,
+                        &it_jfwd,
                         &it_lnf, &it_lni, &x_lnf, &x_lni})
       d->stage(blob);
     blob.add(it_jdiag);
@@ -356,6 +362,7 @@ struct TaskSet {
     blob.add(res_sum);
     blob.add(setup_copy);
     blob.add(fin_copy);
+    blob.add(arm_copy);
     blob.upload(s);
   }
   // called with the line class open: the two transforms of the transform
@@ -531,17 +538,21 @@ void TaskSet::add_problem(Problem& sl) {
     bi.L[q] = a.L;
     bi.nlines = fi.nlines;
 
-    // arm solves (FP64): b_int -> tmpd -> x_int, and x_int -> tmpd -> x_int
+    // arm solves (FP64).  Set-up: b_a -> ahat (kept), copied to tmpd, per-mode
+    // solves, interface row -> x_int.  Back substitution: ahat copied to
+    // tmpd, its interface row replaced by the transform of the updated
+    // interface row of the right-hand side, per-mode solves, tmpd -> x_int.
     const int rpb = kBlock / dst_threads_per_row(a.L);
+    double* ah = sl.ahat + (ad.off - sl.Nc);
     DstTask f{};
     f.in = sl.b_int + ad.off; f.in_rs = a.L; f.in_cs = 1;
-    f.out = sl.tmpd + ad.off; f.out_rs = a.L; f.out_cs = 1;
+    f.out = ah; f.out_rs = a.L; f.out_cs = 1;
     f.rows = a.rows; f.n = a.L; f.rpb = rpb; f.scale = 1.0; f.fft = a.fft->dev; f.skip = nullptr;
     f.tw_lds = dst_twiddles_in_lds(a.L, false);
     arm_fwd.add(f);
     DstTask fb = f;
-    fb.in = sl.x_int + ad.off;
-    bs_fwd.add(fb);
+    fb.in = sl.x_int + ad.off; fb.out = sl.tmpd + ad.off; fb.rows = 1;
+    bs_fwd0.add(fb);
     TriTask at{};
     at.data = sl.tmpd + ad.off; at.rs = a.L; at.rows = a.rows; at.modes = a.L;
     at.coef = a.modes->c64; at.skip = nullptr;
@@ -549,6 +560,9 @@ void TaskSet::add_problem(Problem& sl) {
     DstTask iv = f;
     iv.in = sl.tmpd + ad.off; iv.out = sl.x_int + ad.off;
     arm_inv.add(iv);
+    DstTask iv0 = iv;
+    iv0.rows = 1;
+    arm_inv0.add(iv0);
   }
   iface_fp.h.push_back(fi);
   iface_bs.h.push_back(bi);
@@ -624,7 +638,7 @@ void TaskSet::add_problem(Problem& sl) {
     res_sum.h.push_back(ResSumTask{sl.respart, total, 0, sl.st});
   }
   // set-up copies: f'_c starts as b_c and x_c at zero; the back substitution
-  // starts the arms from b_a
+  // starts the arms' interface rows from b_a
   const long long coff = p->cdev.off;
   auto copy = [&](TaskList<CopyTask>& tl, double* dst, const double* src, long long count) {
     if (count <= 0) return;
@@ -634,7 +648,13 @@ void TaskSet::add_problem(Problem& sl) {
   };
   copy(setup_copy, sl.fp, sl.b_int + coff, sl.Nc);
   copy(setup_copy, sl.x_int + coff, nullptr, sl.Nc);
-  copy(fin_copy, sl.x_int + coff + sl.Nc, sl.b_int + coff + sl.Nc, sl.Nint - sl.Nc);
+  // (the back substitution needs b_a's interface row only: the other rows
+  // enter through ahat)
+  for (const ArmInfo& a : p->arms) {
+    const long long o = p->rd[a.rect].off;
+    copy(fin_copy, sl.x_int + o, sl.b_int + o, a.L);
+  }
+  copy(arm_copy, sl.tmpd + coff + sl.Nc, sl.ahat, sl.Nint - sl.Nc);
 }
 
 // Task records of the interface Krylov iteration for one problem.
@@ -1039,6 +1059,7 @@ void Engine::admit(const std::vector<SolveRequest>& reqs, const std::vector<int>
     sl.b_int = sl.mem.as<double>(L.b_int);
     sl.x_int = sl.mem.as<double>(L.x_int);
     sl.tmpd = sl.mem.as<double>(L.tmpd);
+    sl.ahat = sl.mem.as<double>(L.ahat);
     sl.fp = sl.mem.as<double>(L.fp);
     sl.V = sl.mem.as<double>(L.V);
     sl.u = sl.mem.as<double>(L.u);
@@ -1119,11 +1140,12 @@ void Engine::Impl::setup_phase(TaskSet& ts) {
     Timing::begin(0, s);
     ts.arm_fwd.launch(0, s);
     Timing::end(0, s);
+    launch_copy(ts.arm_copy.dev(), ts.arm_copy.n(), ts.arm_copy.nblocks, s);
     Timing::begin(1, s);
     ts.arm_tri.launch(s);
     Timing::end(1, s);
     Timing::begin(0, s);
-    ts.arm_inv.launch(0, s);
+    ts.arm_inv0.launch(0, s);
     Timing::end(0, s);
   }
   launch_copy(ts.setup_copy.dev(), ts.setup_copy.n(), ts.setup_copy.nblocks, s);
@@ -1236,12 +1258,13 @@ std::vector<std::pair<int, SolveOutcome>> Engine::retire(const std::vector<int>&
 }
 
 std::vector<SolveOutcome> Engine::Impl::finalize_phase(TaskSet& ts) {
-  // arms follow the centre in the internal layout: they start from b_a
+  // the arms' interface rows start from b_a
   launch_copy(ts.fin_copy.dev(), ts.fin_copy.n(), ts.fin_copy.nblocks, s);
   launch_iface(ts.iface_bs.dev(), ts.iface_bs.n(), s);
-  if (ts.bs_fwd.n()) {
+  if (ts.bs_fwd0.n()) {
+    launch_copy(ts.arm_copy.dev(), ts.arm_copy.n(), ts.arm_copy.nblocks, s);
     Timing::begin(0, s);
-    ts.bs_fwd.launch(0, s);
+    ts.bs_fwd0.launch(0, s);
     Timing::end(0, s);
     Timing::begin(1, s);
     ts.arm_tri.launch(s);
@@ -1359,8 +1382,9 @@ void Engine::Impl::account_cycle(const std::vector<ProbState>& before) {
 void Engine::Impl::account_arms(const std::vector<Problem*>& probs, bool setup_phase) {
   for (const Problem* sl : probs) {
     for (const ArmInfo& a : sl->plan->arms) {
+      // one whole-arm transform and one interface-row transform per phase
       const double na = (double)a.L * a.rows;
-      Timing::add_bytes(0, 2.0 * 16.0 * na);
+      Timing::add_bytes(0, 16.0 * (na + a.L));
       Timing::add_bytes(1, 16.0 * na);
     }
     const double Nc = (double)sl->Nc;
