@@ -1,4 +1,4 @@
-// Plan creation: geometry validation, classification of the coupled centre
+// Plan creation: geometry validation, classification of the coupled block
 // and the independent arms (paper Section 2.4, last paragraph), internal
 // layout and shared tables.
 #include <algorithm>
@@ -100,9 +100,6 @@ fds_plan* create_plan(const fds_rect* rects, int nrect, double h, double kappa,
   try {
     FDS_HIP(hipGetDevice(&p->device));
     p->rects.assign(rects, rects + nrect);
-    p->centre = chain[0];
-    p->n_coupled = K;
-    p->coupled_box = M;
     p->h = h;
     p->delta = 1.0 / (h * h);
     p->kappa = kappa;

@@ -218,9 +218,6 @@ struct fds_plan {
   std::vector<fds_rect> rects;
   std::vector<fds::RectDev> rd;      // per rect (user order); off relative to a problem
   std::vector<int> kind;
-  int centre = 0;                    // first coupled rectangle along the chain
-  int n_coupled = 1;                 // coupled rectangles (merged into one block)
-  fds_rect coupled_box{};            // closed box of the coupled block M
   fds::RectDev cdev{};               // the coupled block as one rectangle (offset 0)
   std::vector<fds::ArmInfo> arms;
   double h = 0, delta = 0, kappa = 0;
