@@ -200,3 +200,25 @@ def test_chain_through_the_server():
             err = compare(p, it[3], oracle_solution(p))
             log(f"server flags={flags} {p.label} {p.shape}: err vs oracle {err:.3e}")
             assert err <= 1e-10
+
+
+def test_chain_at_the_benchmark_size():
+    """The chain workload's configuration (four 512x512 squares stacked,
+    1,050,112 unknowns, interface GMRES(80), batched) against the oracle's
+    sparse direct solve, at a tolerance where the FP64 bar applies."""
+    from oracle import composite
+    fds = _fds()
+    rects = workloads.chain_rects(512, [513] * 4, vertical=True)
+    h = 1.0 / 513
+    probs = [workloads.rects_problem(rects, h, -50.0, "shifted"),
+             workloads.rects_problem(rects, h, -50.0, "gauss", 1)]
+    sols = composite.solve_many(rects, h, -50.0, [(p.f_grid, p.g_grid) for p in probs], method="splu")
+    plan = fds.Plan(rects, h, -50.0, restart_m=80, flags=fds.FLAG_INTERFACE_KRYLOV)
+    items = [device_problem(p) for p in probs]
+    xs = [it[3] for it in items]
+    res = fds.solve_batch([plan] * 2, [it[1] for it in items], xs, [1e-12] * 2, bcs=[it[2] for it in items])
+    for p, x, r, sol in zip(probs, xs, res, sols):
+        assert r.status == 0, r
+        err = compare(p, x, sol)
+        log(f"chain 4x512 {p.label}: its={r.iterations} err={err:.3e}")
+        assert err <= 1e-10
