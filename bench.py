@@ -165,6 +165,45 @@ def pct(xs, q):
     return xs[k]
 
 
+def stream_ceiling(device):
+    """Practical HBM ceilings of this device, measured with plain device
+    kernels over 1 GiB FP64 vectors (outside the timed region): a copy, a
+    read-only sum and a triad (two reads, one write), in GB/s."""
+    import torch
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device=device)
+    b = torch.empty_like(a)
+    c = torch.ones_like(a)
+
+    def rate(f, nbytes, reps=10):
+        for _ in range(2):
+            f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        return round(nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+
+    out = {"copy": rate(lambda: b.copy_(a), 16 * n), "read": rate(lambda: a.sum(), 8 * n),
+           "triad": rate(lambda: torch.add(a, c, alpha=2.0, out=b), 24 * n)}
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
+def add_practical(roofline, ceiling):
+    """The roofline against the measured triad ceiling as well as the
+    published peak."""
+    if roofline is None or ceiling is None:
+        return
+    roofline["practical_peak"] = ceiling
+    a = roofline.get("achieved")
+    roofline["frac_practical"] = round(a / ceiling["triad"], 4) if a and ceiling.get("triad") else None
+
+
 # --------------------------------------------------------------------------- workloads
 
 def build_workload(name, device):
@@ -629,6 +668,7 @@ def run_serving(args, device):
         torch.cuda.empty_cache()
     del inputs
     torch.cuda.empty_cache()
+    add_practical(roofline, stream_ceiling(device))
     head = out[headline]
     cpu = None
     if not args.no_cpu_baseline:
@@ -942,6 +982,7 @@ def main():
                 "avg_launch_us": round(ms / calls * 1e3, 3) if calls else None,
                 "algorithmic_bytes_per_launch": round(algo_bytes / calls, 1) if calls else None}
 
+    add_practical(roofline, stream_ceiling(device))
     cpu = None
     if not args.no_cpu_baseline and args.cpu_sample > 0:
         log("timing the CPU oracle on a bounded sample ...")
