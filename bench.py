@@ -6,7 +6,10 @@ uniform over cross / L / T of unit squares, n log-uniform in [64, 2048]
 interior nodes per side, kappa 0 with probability 1/2 else U[-100, 0], seeded
 sums of 16 Gaussians as right-hand sides, relative residual 1e-10, replayed
 open-loop against the continuous-batching server.  A step is one second of
-arrivals (--warmup seconds of warm-up, --steps measured seconds).  The
+arrivals (--warmup seconds of warm-up, --steps measured seconds; the
+right-hand sides of the whole trace are generated on the device before the
+replay, about 4 GB per second of arrivals, so a 60-second window is run with
+--serving-paths limited to the headline path).  The
 headline path is the interface Krylov iteration, GMRES(80) in FP64; the
 mixed-precision FGMRES(40) path and the plain FP64 GMRES(30) path replay the
 same trace beside it.  Latency runs from the scheduled arrival to completion.

@@ -3,7 +3,12 @@
 // Solving allocates a workspace per problem (Krylov basis, scratch, task
 // records); a request stream or a benchmark loop would otherwise call
 // hipMalloc / hipFree (and hipHostMalloc for the completion flags) for every
-// solve.  Released blocks are kept per device and size class and reused.
+// solve.  Released blocks are kept per device, ordered by size, and a request
+// takes the smallest kept block that holds it with at most a quarter (and at
+// most 256 MiB) to spare: request sizes vary continuously on a served stream,
+// so exact size classes were rarely reused, and every miss cost a hipMalloc
+// and, once the cache was full, a hipFree, which waits for the whole device.
+#include <algorithm>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -29,6 +34,8 @@ size_t size_class(size_t bytes) {
 size_t cache_limit() {
   static const size_t lim = [] {
     const char* e = std::getenv("FDS_CACHE_BYTES");
+    // (a hipMalloc that runs out of memory gives the kept blocks back first;
+    // allocations of other libraries in the process do not, hence the cap)
     return e ? (size_t)std::strtoull(e, nullptr, 10) : ((size_t)64 << 30);
   }();
   return lim;
@@ -36,7 +43,7 @@ size_t cache_limit() {
 
 struct DeviceCache {
   std::mutex mu;
-  std::map<std::pair<int, size_t>, std::multimap<size_t, void*>> unused;  // unused blocks
+  std::map<int, std::multimap<size_t, void*>> unused;   // unused blocks per device, by capacity
   std::map<void*, int> owner;     // block -> device
   size_t cached = 0;
   std::multimap<size_t, void*> host_free;   // mapped host blocks by size
@@ -59,14 +66,18 @@ void* device_cache_alloc(size_t bytes, size_t* capacity) {
   DeviceCache& dc = cache();
   {
     std::lock_guard<std::mutex> lk(dc.mu);
-    auto it = dc.unused.find({dev, c});
-    if (it != dc.unused.end() && !it->second.empty()) {
-      auto b = it->second.begin();
-      void* p = b->second;
-      it->second.erase(b);
-      dc.cached -= c;
-      *capacity = c;
-      return p;
+    auto it = dc.unused.find(dev);
+    if (it != dc.unused.end()) {
+      const size_t slack = std::min(c / 4, (size_t)256 << 20);
+      auto b = it->second.lower_bound(c);
+      if (b != it->second.end() && b->first <= c + slack) {
+        void* p = b->second;
+        const size_t cap = b->first;
+        it->second.erase(b);
+        dc.cached -= cap;
+        *capacity = cap;
+        return p;
+      }
     }
   }
   void* p = nullptr;
@@ -75,14 +86,14 @@ void* device_cache_alloc(size_t bytes, size_t* capacity) {
     // give the cached blocks of this device back and retry once
     (void)hipGetLastError();
     std::lock_guard<std::mutex> lk(dc.mu);
-    for (auto& kv : dc.unused) {
-      if (kv.first.first != dev) continue;
-      for (auto& b : kv.second) {
+    auto it = dc.unused.find(dev);
+    if (it != dc.unused.end()) {
+      for (auto& b : it->second) {
         (void)hipFree(b.second);
         dc.owner.erase(b.second);
-        dc.cached -= kv.first.second;
+        dc.cached -= b.first;
       }
-      kv.second.clear();
+      it->second.clear();
     }
     e = hipMalloc(&p, c);
   }
@@ -108,7 +119,7 @@ void device_cache_free(void* p, size_t capacity) {
     if (o != dc.owner.end()) dc.owner.erase(o);
     return;
   }
-  dc.unused[{dev, capacity}].emplace(capacity, p);
+  dc.unused[dev].emplace(capacity, p);
   dc.cached += capacity;
 }
 
